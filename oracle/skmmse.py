@@ -1,0 +1,523 @@
+"""Float64 CPU oracle of K-MMSE and scalable K-MMSE concealment.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product path.
+
+Paper: Koloda, Seiler, Peinado, Kaup, "Scalable Kernel-Based Minimum Mean
+Square Error Estimator for Accelerated Image Error Concealment" (arXiv
+2205.11226).  Section names below refer to it.
+
+Geometry (block mode).  The paper estimates 2x2 patches from a 6x6 context
+(Sec. "Reconstruction framework").  Here a whole lost B x B block is x0; its
+context y0 is the ring of width r around it, restricted to available pixels
+(mask m0); candidates z_j are all displacements (dx, dy) in [-W, W]^2 \\ {0}
+whose B x B prototype lies in the frame and is fully available.  A candidate's
+ring may be partly unavailable: its distance to y0 is taken over the pixels
+known in both rings (count n_j) and normalised by n_j, the "average
+distortion per context pixel" that the IDL bandwidth sigma^2 N_y expresses
+(Sec. "Intermediate dynamic layer").  Candidates with n_j below
+ceil(min_overlap_pct * |m0| / 100) are dropped.  HQL, whose covariance needs
+every coordinate, uses only candidates whose ring covers all of m0.
+
+Layers and gate (Sec. "Scalable K-MMSE estimator", Sec. "Layer switching"):
+* BRL: mean of y0 (eq. "mean"), chosen when phi = max(y0) - min(y0) <= T_phi;
+* IDL: fixed bandwidth sigma^2 = 10 kernel regression (eq. "slpe") over the
+  candidates within Chebyshev radius rho, rho growing in steps of
+  ``expand_step`` up to W; accepted at the first rho whose
+  nu = sum of raw weights (eq. "factor", read with a negative exponent)
+  reaches T_nu;
+* HQL: full K-MMSE with covariance-scaled bandwidth (eqs. "kmmse",
+  "weights", "bandwidthScaled", "epsy", "epsx").
+
+Lost blocks are concealed in Jacobi rounds: every block whose available ring
+holds at least r*B pixels is estimated from the state at the start of the
+round, then all of them become available (the transfer of x0 into S, end of
+Sec. "K-MMSE overview").
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, replace
+
+import numpy as np
+
+LAYER_FILL = -1
+LAYER_BRL = 0
+LAYER_IDL = 1
+LAYER_HQL = 2
+
+FLAG_CTX_RELAXED = 1   # block proceeded with fewer than r*B context pixels
+FLAG_NO_HQL = 2        # HQL wanted but too few complete candidates: full IDL
+FLAG_NO_CAND = 4       # no candidate at all: BRL
+FLAG_EMPTY_CTX = 8     # forced fill with no context pixel: frame mean
+
+# Profile table of the paper (Table "Profile definitions"): (T_phi, T_nu).
+PROFILES = {
+    "express": (20.0, 0.01),
+    "efficient": (20.0, 0.1),
+    "excellent": (20.0, 100.0),
+}
+
+MODES = ("plain", "full", "profile", "brl", "idl", "cnn")
+
+
+class UnsupportedLoss(ValueError):
+    """Loss mask with lost pixels outside whole in-frame B x B cells."""
+
+
+@dataclass(frozen=True)
+class Params:
+    block: int = 16
+    ring: int = 4
+    window: int = 24
+    sigma2: float = 10.0          # IDL decay factor (Sec. IDL: set to 10)
+    t_phi: float = 20.0
+    t_nu: float = 0.1
+    expand_step: int = 4
+    min_overlap_pct: int = 50
+    min_hql_cands: int = 64
+    ridge_rel: float = 1e-3
+    mode: str = "profile"
+    max_rounds: int = 0           # 0 = until every block is concealed
+
+    def with_profile(self, name: str) -> "Params":
+        tphi, tnu = PROFILES[name]
+        return replace(self, t_phi=tphi, t_nu=tnu)
+
+
+# ------------------------------------------------------------------ geometry
+
+def ring_offsets(b: int, r: int) -> np.ndarray:
+    """(oy, ox) of the context ring around a B x B block, raster order."""
+    out = [(oy, ox) for oy in range(-r, b + r) for ox in range(-r, b + r)
+           if not (0 <= oy < b and 0 <= ox < b)]
+    return np.asarray(out, dtype=np.int64).reshape(-1, 2)
+
+
+def lost_cells(mask: np.ndarray, b: int) -> list[tuple[int, int]]:
+    """Lost cells (by, bx) in raster order; every lost pixel must lie in a
+    fully lost B x B cell that is entirely inside the frame."""
+    h, w = mask.shape
+    lost = mask != 0
+    gh, gw = h // b, w // b
+    cells = []
+    covered = np.zeros_like(lost)
+    for by in range(gh):
+        for bx in range(gw):
+            c = lost[by * b:(by + 1) * b, bx * b:(bx + 1) * b]
+            if c.all():
+                cells.append((by, bx))
+                covered[by * b:(by + 1) * b, bx * b:(bx + 1) * b] = True
+    if (lost & ~covered).any():
+        raise UnsupportedLoss("lost pixels outside whole in-frame B x B cells")
+    return cells
+
+
+def _gather(u: np.ndarray, avail: np.ndarray, ys: np.ndarray, xs: np.ndarray):
+    """Pixel values and availability at (ys, xs); out-of-frame = unavailable."""
+    h, w = u.shape
+    inside = (ys >= 0) & (ys < h) & (xs >= 0) & (xs < w)
+    yc = np.clip(ys, 0, h - 1)
+    xc = np.clip(xs, 0, w - 1)
+    m = inside & avail[yc, xc]
+    v = np.where(m, u[yc, xc], 0).astype(np.int64)
+    return v, m
+
+
+def block_context(u, avail, by, bx, p: Params):
+    """Context y0 and its mask m0 over the ring (values 0 where unknown)."""
+    off = ring_offsets(p.block, p.ring)
+    return _gather(u, avail, by * p.block + off[:, 0], bx * p.block + off[:, 1])
+
+
+@dataclass
+class Candidates:
+    dx: np.ndarray        # displacement, raster order (dy, then dx)
+    dy: np.ndarray
+    n: np.ndarray         # |m0 and m_j|
+    d: np.ndarray         # sum over m0 and m_j of (y0 - y_j)^2, exact integer
+    x: np.ndarray         # (M, B*B) prototypes
+    y: np.ndarray         # (M, N_ring) context vectors (0 where unknown)
+    m: np.ndarray         # (M, N_ring) candidate ring availability
+
+    @property
+    def size(self) -> int:
+        return int(self.dx.shape[0])
+
+    @property
+    def radius(self) -> np.ndarray:
+        return np.maximum(np.abs(self.dx), np.abs(self.dy))
+
+
+def candidate_set(u, avail, by, bx, p: Params, y0, m0) -> Candidates:
+    """All admissible candidates of block (by, bx) with their exact distances.
+
+    A displacement is admissible when its prototype is in the frame and fully
+    available and its ring shares at least ceil(min_overlap_pct |m0| / 100)
+    (and at least one) known pixels with m0.
+    """
+    b, W = p.block, p.window
+    h, w = u.shape
+    off = ring_offsets(b, p.ring)
+    n0 = int(m0.sum())
+    nmin = max(1, (p.min_overlap_pct * n0 + 99) // 100)
+    dys, dxs = np.meshgrid(np.arange(-W, W + 1), np.arange(-W, W + 1), indexing="ij")
+    dys = dys.ravel()
+    dxs = dxs.ravel()
+    keep = ~((dys == 0) & (dxs == 0))
+    dys, dxs = dys[keep], dxs[keep]
+    py = by * b + dys
+    px = bx * b + dxs
+    inside = (py >= 0) & (px >= 0) & (py + b <= h) & (px + b <= w)
+    # prototype availability from an integral image of the lost indicator
+    lost_ii = np.zeros((h + 1, w + 1), dtype=np.int64)
+    lost_ii[1:, 1:] = np.cumsum(np.cumsum(~avail, axis=0), axis=1)
+    pyc = np.clip(py, 0, h - b)
+    pxc = np.clip(px, 0, w - b)
+    nlost = (lost_ii[pyc + b, pxc + b] - lost_ii[pyc, pxc + b]
+             - lost_ii[pyc + b, pxc] + lost_ii[pyc, pxc])
+    ok = inside & (nlost == 0)
+    dys, dxs, py, px = dys[ok], dxs[ok], py[ok], px[ok]
+    ry = py[:, None] + off[None, :, 0]
+    rx = px[:, None] + off[None, :, 1]
+    yj, mj = _gather(u, avail, ry, rx)
+    both = mj & m0[None, :]
+    n = both.sum(axis=1)
+    diff = np.where(both, y0[None, :] - yj, 0)
+    d = (diff * diff).sum(axis=1)
+    sel = n >= nmin
+    ii = np.arange(b)
+    xy = py[sel][:, None, None] + ii[None, :, None]
+    xx = px[sel][:, None, None] + ii[None, None, :]
+    xproto = u[xy, xx].reshape(-1, b * b).astype(np.int64)
+    return Candidates(dx=dxs[sel], dy=dys[sel], n=n[sel], d=d[sel], x=xproto,
+                      y=yj[sel], m=mj[sel])
+
+
+def block_distances(u, avail, by, bx, p: Params):
+    """Exact integer distance table over every displacement, for parity.
+
+    Returns (d, n) of shape (2W+1, 2W+1) indexed [dy+W, dx+W]; d = -1 where
+    the displacement is not an admissible candidate.
+    """
+    y0, m0 = block_context(u, avail, by, bx, p)
+    c = candidate_set(u, avail, by, bx, p, y0, m0)
+    W = p.window
+    d = np.full((2 * W + 1, 2 * W + 1), -1, dtype=np.int64)
+    n = np.zeros((2 * W + 1, 2 * W + 1), dtype=np.int64)
+    d[c.dy + W, c.dx + W] = c.d
+    n[c.dy + W, c.dx + W] = c.n
+    return d, n
+
+
+# ---------------------------------------------------------------- IDL / nu
+
+def log_weights(c: Candidates, sigma2: float) -> np.ndarray:
+    """ell_j = -(d_j / n_j) / (2 sigma^2): log of the raw IDL weight (eq. slpe
+    with N_y replaced by the per-candidate overlap n_j)."""
+    return -(c.d.astype(np.float64) / c.n.astype(np.float64)) / (2.0 * sigma2)
+
+
+def _logsumexp(v: np.ndarray) -> float:
+    if v.size == 0:
+        return -math.inf
+    m = float(v.max())
+    return m + math.log(float(np.exp(v - m).sum()))
+
+
+def idl_radii(p: Params) -> list[int]:
+    """Expansion schedule of the support area: Chebyshev radii step, 2 step,
+    ..., W (the expansion map itself is not legible in the paper)."""
+    rs = list(range(p.expand_step, p.window, p.expand_step))
+    rs.append(p.window)
+    return rs
+
+
+def log_nu_by_radius(c: Candidates, p: Params) -> list[float]:
+    """log nu(rho) = log sum_{rho_j <= rho} exp(ell_j) for each rho (eq. factor)."""
+    ell = log_weights(c, p.sigma2)
+    rad = c.radius
+    return [_logsumexp(ell[rad <= rho]) for rho in idl_radii(p)]
+
+
+def idl_estimate(c: Candidates, sel: np.ndarray, sigma2: float) -> np.ndarray:
+    """Normalised-weight average of the selected prototypes (eq. slpe)."""
+    ell = log_weights(c, sigma2)[sel]
+    wgt = np.exp(ell - ell.max())
+    wgt /= wgt.sum()
+    return wgt @ c.x[sel].astype(np.float64)
+
+
+# ---------------------------------------------------------------------- HQL
+
+def _cov(z: np.ndarray) -> np.ndarray:
+    """Sample covariance with 1/M normalisation (eq. covariance)."""
+    zc = z - z.mean(axis=0, keepdims=True)
+    return (zc.T @ zc) / z.shape[0]
+
+
+def _softmax_rows(logits: np.ndarray) -> np.ndarray:
+    m = logits.max(axis=-1, keepdims=True)
+    e = np.exp(logits - m)
+    return e / e.sum(axis=-1, keepdims=True)
+
+
+BETA_G_LO, BETA_G_HI, GOLDEN_STEPS = -8, 24, 40
+
+
+def hql_estimate(x: np.ndarray, y: np.ndarray, y0: np.ndarray, d_euclid: np.ndarray,
+                 ridge_rel: float, return_parts: bool = False, alpha_override=None):
+    """Full-featured K-MMSE (HQL) for one block.
+
+    x: (M, Nx) prototypes, y: (M, Ny) complete contexts, y0: (Ny,) context,
+    d_euclid: (M,) exact Euclidean distances, raster-ordered candidates.
+
+    Steps (Sec. "K-MMSE overview"):
+    1. C_ZZ from z_j = (x_j, y_j), 1/M normalised; C_YY gets a ridge
+       lambda = ridge_rel tr(C_YY)/Ny + 1e-12 (the paper does not regularise;
+       C_YY is singular whenever M <= Ny or the content is flat);
+    2. A = C_XY C_YY^-1 (the correction matrix of eq. kmmse with H = beta C);
+    3. Mahalanobis distances D(u, v) = (u-v)^T C_YY^-1 (u-v), weights
+       proportional to exp(-D / (2 beta)) (eq. weights with H_YY = beta C_YY);
+    4. beta = argmin eps_y(beta) (eq. epsy): first minimiser on the grid
+       D0 2^(g/2), g = -8..24, D0 = max(min_j D(y0, y_j), 1e-9), refined by
+       40 golden-section steps on log beta between the neighbouring grid
+       points; the refined value is kept only if it is not worse;
+    5. alpha = argmin eps_x(alpha) (eq. epsx) over I0 = the Ny + 1 candidates
+       closest to y0 in Euclidean distance (ties by raster index); each x_i is
+       predicted leave-one-out from the other candidates with the same beta
+       and A.  x_i_hat is affine in alpha, so the argmin is closed form;
+    6. x0_hat = x~(beta) + alpha A (y0 - y~(beta)).
+    """
+    x = x.astype(np.float64)
+    y = y.astype(np.float64)
+    y0 = y0.astype(np.float64)
+    m, nx = x.shape
+    ny = y.shape[1]
+    z = np.concatenate([x, y], axis=1)
+    c = _cov(z)
+    cxy = c[:nx, nx:]
+    cyy = c[nx:, nx:].copy()
+    lam = ridge_rel * np.trace(cyy) / ny + 1e-12
+    cyy[np.diag_indices(ny)] += lam
+    chol = np.linalg.cholesky(cyy)
+    amat = np.linalg.solve(cyy, cxy.T).T            # C_XY C_YY^-1  (Nx x Ny)
+
+    def whiten(v):                                    # L^-1 v  (rows)
+        return np.linalg.solve(chol, v.T).T
+
+    vy = whiten(y)
+    v0 = whiten(y0[None, :])[0]
+    dmah0 = ((vy - v0[None, :]) ** 2).sum(axis=1)     # D(y0, y_j)
+
+    def weights(beta):
+        return _softmax_rows(-dmah0 / (2.0 * beta))
+
+    def eps_y(beta):
+        r = y0 - weights(beta) @ y
+        return float(r @ r)
+
+    d0 = max(float(dmah0.min()), 1e-9)
+    grid = [d0 * 2.0 ** (g / 2.0) for g in range(BETA_G_LO, BETA_G_HI + 1)]
+    eg = [eps_y(bt) for bt in grid]
+    gstar = int(np.argmin(eg))                        # first minimiser
+    a_t = math.log(grid[max(gstar - 1, 0)])
+    b_t = math.log(grid[min(gstar + 1, len(grid) - 1)])
+    invphi = (math.sqrt(5.0) - 1.0) / 2.0
+    c_t = b_t - invphi * (b_t - a_t)
+    d_t = a_t + invphi * (b_t - a_t)
+    fc = eps_y(math.exp(c_t))
+    fd = eps_y(math.exp(d_t))
+    for _ in range(GOLDEN_STEPS):
+        if fc <= fd:
+            b_t, d_t, fd = d_t, c_t, fc
+            c_t = b_t - invphi * (b_t - a_t)
+            fc = eps_y(math.exp(c_t))
+        else:
+            a_t, c_t, fc = c_t, d_t, fd
+            d_t = a_t + invphi * (b_t - a_t)
+            fd = eps_y(math.exp(d_t))
+    beta = math.exp(0.5 * (a_t + b_t))
+    if eps_y(beta) > eg[gstar]:
+        beta = grid[gstar]
+
+    w0 = weights(beta)
+    xt = w0 @ x
+    yt = w0 @ y
+
+    # I0: Ny + 1 nearest candidates in Euclidean distance, ties by index
+    k = min(ny + 1, m)
+    order = np.argsort(d_euclid, kind="stable")[:k]
+    vi = vy[order]
+    dmah = ((vi[:, None, :] - vy[None, :, :]) ** 2).sum(axis=2)   # (k, M)
+    logits = -dmah / (2.0 * beta)
+    logits[np.arange(k), order] = -np.inf                         # leave one out
+    wl = _softmax_rows(logits)
+    xt_i = wl @ x
+    yt_i = wl @ y
+    ci = (y[order] - yt_i) @ amat.T                                # A r_i
+    ei = x[order] - xt_i
+    den = float((ci * ci).sum())
+    alpha = float((ci * ei).sum()) / den if den > 0.0 else 0.0
+    if alpha_override is not None:
+        alpha = float(alpha_override)
+    xhat = xt + alpha * (amat @ (y0 - yt))
+    if return_parts:
+        return xhat, {"beta": beta, "alpha": alpha, "A": amat, "xt": xt, "yt": yt,
+                      "w": w0, "grid": grid, "eps_grid": eg, "eps_y": eps_y,
+                      "dmah0": dmah0, "I0": order, "ci": ci, "ei": ei, "lam": lam}
+    return xhat
+
+
+# ---------------------------------------------------------------- one block
+
+def estimate_block(u, avail, by, bx, p: Params, cnn_gate=None):
+    """Estimate lost block (by, bx) from the current state.
+
+    Returns (xhat (B*B,) float64, info dict).
+    """
+    b = p.block
+    y0, m0 = block_context(u, avail, by, bx, p)
+    n0 = int(m0.sum())
+    info = {"bx": bx, "by": by, "layer": LAYER_BRL, "n_cand": -1, "n_complete": -1,
+            "phi": 0, "log_nu": math.nan, "radius": 0, "flags": 0}
+    known = y0[m0]
+    phi = int(known.max() - known.min()) if n0 else 0
+    info["phi"] = phi
+    brl = np.full(b * b, float(known.mean()) if n0 else 0.0)
+
+    mode = p.mode
+    if mode == "brl":
+        return brl, info
+    want_hql = None
+    if mode == "profile" and phi <= p.t_phi:
+        return brl, info
+    if mode == "cnn":
+        if cnn_gate is None:
+            raise ValueError("cnn mode needs a gate callable")
+        g = cnn_gate(u, avail, by, bx)
+        if g == LAYER_BRL:
+            return brl, info
+        want_hql = g == LAYER_HQL
+
+    c = candidate_set(u, avail, by, bx, p, y0, m0)
+    complete = c.n == n0
+    info["n_cand"] = c.size
+    info["n_complete"] = int(complete.sum())
+    if c.size == 0:
+        info["flags"] |= FLAG_NO_CAND
+        return brl, info
+    ell = log_weights(c, p.sigma2)
+    full_sel = np.ones(c.size, dtype=bool)
+    info["log_nu"] = _logsumexp(ell)
+    info["radius"] = p.window
+
+    if mode in ("profile", "idl"):
+        log_tnu = math.log(p.t_nu) if p.t_nu > 0 else -math.inf
+        rad = c.radius
+        for rho, lnu in zip(idl_radii(p), log_nu_by_radius(c, p)):
+            sel = rad <= rho
+            if sel.any() and lnu >= log_tnu:
+                info["layer"] = LAYER_IDL
+                info["log_nu"] = lnu
+                info["radius"] = rho
+                return idl_estimate(c, sel, p.sigma2), info
+        want_hql = mode == "profile"
+    elif mode == "plain":
+        want_hql = False
+    elif mode == "full":
+        want_hql = True
+
+    if want_hql:
+        if info["n_complete"] >= max(2, p.min_hql_cands):
+            info["layer"] = LAYER_HQL
+            xs = c.x[complete]
+            ys = c.y[complete][:, m0]
+            return hql_estimate(xs, ys, y0[m0], c.d[complete], p.ridge_rel), info
+        info["flags"] |= FLAG_NO_HQL
+    info["layer"] = LAYER_IDL
+    return idl_estimate(c, full_sel, p.sigma2), info
+
+
+# -------------------------------------------------------------- frame driver
+
+def _round_pixel(v: np.ndarray) -> np.ndarray:
+    return np.clip(np.floor(v + 0.5), 0, 255).astype(np.uint8)
+
+
+def conceal(frame: np.ndarray, mask: np.ndarray, p: Params, cnn_gate=None):
+    """Conceal every lost block of ``frame`` (uint8, HxW); ``mask`` != 0 = lost.
+
+    Returns (out uint8 HxW, xhat {(by, bx): float64 (B, B)}, info list in
+    processing order).
+    """
+    if p.mode not in MODES:
+        raise ValueError(f"unknown mode {p.mode}")
+    b, r = p.block, p.ring
+    frame = np.asarray(frame, dtype=np.uint8)
+    cells = lost_cells(mask, b)
+    avail = mask == 0
+    if cells and not avail.any():
+        raise ValueError("frame has no received pixel")
+    u = np.where(avail, frame, 0).astype(np.int64)
+    out = frame.copy()
+    out[~avail] = 0
+    xhats: dict = {}
+    infos: list = []
+    pending = list(cells)
+    rnd = 0
+    while pending:
+        rnd += 1
+        if p.max_rounds and rnd > p.max_rounds:
+            fill_mean = float(u[avail].mean())
+            for (by, bx) in pending:
+                y0, m0 = block_context(u, avail, by, bx, p)
+                info = {"bx": bx, "by": by, "layer": LAYER_FILL, "n_cand": -1,
+                        "n_complete": -1, "phi": 0, "log_nu": math.nan, "radius": 0,
+                        "flags": 0, "round": rnd}
+                if m0.any():
+                    v = float(y0[m0].mean())
+                else:
+                    v = fill_mean
+                    info["flags"] |= FLAG_EMPTY_CTX
+                xh = np.full((b, b), v)
+                xhats[(by, bx)] = xh
+                out[by * b:(by + 1) * b, bx * b:(bx + 1) * b] = _round_pixel(xh)
+                infos.append(info)
+            break
+        counts = {c: int(block_context(u, avail, c[0], c[1], p)[1].sum()) for c in pending}
+        thr = r * b
+        eligible = [c for c in pending if counts[c] >= thr]
+        relaxed = False
+        if not eligible:
+            mx = max(counts.values())
+            if mx <= 0:
+                raise ValueError("no lost block touches a known pixel")
+            eligible = [c for c in pending if counts[c] == mx]
+            relaxed = True
+        results = []
+        for (by, bx) in eligible:
+            xh, info = estimate_block(u, avail, by, bx, p, cnn_gate)
+            info["round"] = rnd
+            if relaxed:
+                info["flags"] |= FLAG_CTX_RELAXED
+            results.append(((by, bx), xh.reshape(b, b), info))
+        for (by, bx), xh, info in results:
+            v = _round_pixel(xh)
+            out[by * b:(by + 1) * b, bx * b:(bx + 1) * b] = v
+            u[by * b:(by + 1) * b, bx * b:(bx + 1) * b] = v
+            avail[by * b:(by + 1) * b, bx * b:(bx + 1) * b] = True
+            xhats[(by, bx)] = xh
+            infos.append(info)
+        done = set(eligible)
+        pending = [c for c in pending if c not in done]
+    return out, xhats, infos
+
+
+def psnr(a: np.ndarray, b: np.ndarray, sel=None) -> float:
+    """Luma PSNR with peak 255 over the whole frame or the pixels in ``sel``."""
+    d = a.astype(np.float64) - b.astype(np.float64)
+    if sel is not None:
+        d = d[sel]
+    mse = float((d * d).mean())
+    return math.inf if mse == 0.0 else 10.0 * math.log10(255.0 * 255.0 / mse)
