@@ -1,0 +1,240 @@
+"""Throughput benchmark: concealed 16x16 blocks/s on a 1080p frame with 25 %
+dispersed block loss (one MI355X).
+
+One step = the whole concealment of one 1920x1080 luma frame through the C
+ABI (loss geometry, rounds, context/flatness gate, candidate distances,
+weights, weighted averages, write-back), with the frame and mask already in
+HBM.  Prints ONE JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode profile]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+METRIC = "concealed 16x16 blocks/s @1080p 25% loss, layered+CNN vs plain, ΔPSNR≤0.05dB"
+VALU_PEAK_TOPS = 78.6   # 256 CU x 64 lanes x 2 ops (mul+add) x 2.4 GHz, no packed math
+KERNEL = "k_round_main"
+
+
+# ----------------------------------------------------------- CPU baseline
+
+_CPU = {}
+
+
+def _cpu_init(frame, mask, mode, t_nu):
+    import oracle.skmmse as o
+    _CPU["f"] = frame.astype(np.int64)
+    _CPU["a"] = mask == 0
+    _CPU["p"] = o.Params(mode=mode, t_nu=t_nu)
+    _CPU["est"] = o.estimate_block
+
+
+def _cpu_work(cells):
+    for by, bx in cells:
+        _CPU["est"](_CPU["f"], _CPU["a"], by, bx, _CPU["p"])
+    return len(cells)
+
+
+def cpu_baseline(frame, mask, mode, t_nu, workers):
+    """Time the float64 oracle on every lost block of the frame (one round:
+    all blocks are independent) over a process pool of ``workers``."""
+    import multiprocessing as mp
+    from oracle.skmmse import lost_cells
+    cells = lost_cells(mask, 16)
+    chunks = [cells[i::workers * 4] for i in range(workers * 4)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers, initializer=_cpu_init, initargs=(frame, mask, mode, t_nu)) as pool:
+        pool.map(_cpu_work, chunks[:workers])           # warm the workers
+        t0 = time.perf_counter()
+        n = sum(pool.map(_cpu_work, chunks))
+        dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "blocks/s", "cores": workers, "kind": "oracle",
+            "sample": f"all {n} lost blocks of the 1080p frame, float64 NumPy oracle, "
+                      f"mode={mode}, {workers} worker processes, {dt:.2f} s wall"}
+
+
+# ------------------------------------------------------------ algorithmic
+
+def algorithmic_ops(d_tab, n_tab, info, b):
+    """Ops of one launch of the estimation kernel on this frame.
+
+    Per block that computes distances: 3 ops (difference, multiply, add) per
+    pair of ring pixels compared, summed over candidates; plus 2 ops (FMA)
+    per prototype pixel per candidate inside the accepted radius.  Context-
+    mean blocks count one add per known ring pixel."""
+    W = (d_tab.shape[1] - 1) // 2
+    yy, xx = np.mgrid[-W:W + 1, -W:W + 1]
+    rad = np.maximum(np.abs(yy), np.abs(xx))
+    total = 0
+    for k, inf in enumerate(info):
+        if inf["layer"] == 0 and inf["n_cand"] < 0:
+            total += int(inf["n_ctx"])
+            continue
+        ok = d_tab[k] >= 0
+        total += 3 * int(n_tab[k][ok].sum())
+        if inf["layer"] == 1:
+            total += 2 * b * b * int((ok & (rad <= inf["radius"])).sum())
+    return total
+
+
+def traffic_from_profile(kernel_src_hash):
+    path = os.path.join(ROOT, "profiles", "traffic_k_round_main_1080p.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha1") != kernel_src_hash:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def kernel_source_hash():
+    h = hashlib.sha1()
+    for n in ("skm_kernels.hip", "skm_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2205_11226_amd", "csrc", n), "rb").read())
+    return h.hexdigest()
+
+
+def psnr(a, b):
+    d = a.astype(np.float64) - b.astype(np.float64)
+    mse = float((d * d).mean())
+    return math.inf if mse == 0 else 10 * math.log10(255 * 255 / mse)
+
+
+# ------------------------------------------------------------------- main
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--mode", default="profile")
+    ap.add_argument("--profile", default="efficient")
+    ap.add_argument("--cpu-workers", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(blocks of a round are independent; frames or bands would shard "
+              "across GPUs).  Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    t_nu = {"express": 0.01, "efficient": 0.1, "excellent": 100.0}[args.profile]
+    frame, mask = synth.workload_layered_1080p()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        workers = args.cpu_workers or max(1, min(os.cpu_count() or 1, 16))
+        cpu = cpu_baseline(frame, mask, args.mode if args.mode != "cnn" else "profile",
+                           t_nu, workers)
+        print(f"# cpu baseline: {cpu['value']:.1f} blocks/s on {workers} cores", file=sys.stderr,
+              flush=True)
+
+    import torch
+    import paper_2205_11226_amd as skm
+
+    dev = torch.device("cuda:0")
+    fd = torch.from_numpy(frame).to(dev)
+    md = torch.from_numpy(mask).to(dev)
+    out = torch.empty_like(fd)
+    ctx = skm.Context(0)
+    p_lay = skm.default_params(mode=args.mode, profile=args.profile)
+    p_plain = skm.default_params(mode="plain")
+
+    def run(p, k):
+        for _ in range(k):
+            ctx.conceal_device(fd, md, p, out=out, want_info=False, want_xhat=False)
+
+    def timed(p):
+        run(p, args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(p, args.steps)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    sec_lay = timed(p_lay)
+    print(f"# layered: {sec_lay * 1e3:.3f} ms/frame", file=sys.stderr, flush=True)
+    sec_plain = timed(p_plain)
+    print(f"# plain: {sec_plain * 1e3:.3f} ms/frame", file=sys.stderr, flush=True)
+
+    # live kernel timing of the estimation kernel (events on its own stream)
+    ctx.profile_enable(True)
+    run(p_lay, args.steps)
+    ms_tot, launches = ctx.profile_read()
+    ctx.profile_enable(False)
+    k_ms = ms_tot / max(launches, 1)
+
+    # statistics of one layered and one plain frame (not timed)
+    o_lay, info_lay, _ = ctx.conceal_device(fd, md, p_lay, want_xhat=False)
+    o_full, _, _ = ctx.conceal_device(fd, md, skm.default_params(mode="full"), want_xhat=False)
+    d_tab, n_tab = ctx.distances_device(fd, md, p_plain)
+    d_tab, n_tab = d_tab.cpu().numpy(), n_tab.cpu().numpy()
+    n_lost = len(info_lay)
+    ops = algorithmic_ops(d_tab, n_tab, info_lay, 16)
+    achieved = ops / (k_ms * 1e-3) / 1e12
+    ps_lay = psnr(o_lay.cpu().numpy(), frame)
+    ps_full = psnr(o_full.cpu().numpy(), frame)
+    layers = np.bincount(info_lay["layer"] + 1, minlength=4)
+    traffic = traffic_from_profile(kernel_source_hash())
+
+    res = {
+        "metric": METRIC,
+        "value": n_lost / sec_lay,
+        "unit": "blocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec_lay * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32+f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "1920x1080 luma (150 bumps, 40 edges, texture), 25% dispersed "
+                        "16x16 loss (2040 blocks), single frame per step",
+            "mode": args.mode, "profile": args.profile,
+            "lost_blocks": n_lost,
+            "frames_per_s": 1.0 / sec_lay,
+            "plain_blocks_per_s": n_lost / sec_plain,
+            "plain_ms_per_frame": sec_plain * 1e3,
+            "speedup_vs_plain": sec_plain / sec_lay,
+            "psnr_layered_db": ps_lay,
+            "psnr_full_kmmse_db": ps_full,
+            "delta_psnr_db": ps_full - ps_lay,
+            "layers": {"brl": int(layers[1]), "idl": int(layers[2]), "hql": int(layers[3])},
+        },
+        "roofline": {
+            "kernel": KERNEL,
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": VALU_PEAK_TOPS,
+            "unit": "TOP/s",
+            "frac": achieved / VALU_PEAK_TOPS,
+            "traffic": traffic,
+            "ops_per_launch": ops,
+            "kernel_ms": k_ms,
+            "launches_timed": launches,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

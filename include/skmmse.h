@@ -1,0 +1,189 @@
+/*
+ * skmmse.h — C ABI of the MI355X (gfx950) scalable K-MMSE spatial error
+ * concealment library (libskmmse.so).
+ *
+ * Method: Koloda, Seiler, Peinado, Kaup, "Scalable Kernel-Based Minimum Mean
+ * Square Error Estimator for Accelerated Image Error Concealment" (arXiv
+ * 2205.11226).  Problem statement: Sec. "Reconstruction framework" — a frame
+ * region R splits into received pixels S and lost pixels L; every lost vector
+ * x0 is estimated from its received context y0 and from all vectors of S with
+ * the same spatial configuration, and each estimate is transferred into S
+ * once made.  Estimators: Sec. "K-MMSE overview" (eqs. kmmse, weights,
+ * bandwidthScaled, epsy, epsx) and Sec. "Scalable K-MMSE estimator" (HQL,
+ * IDL eq. slpe, BRL eq. mean).  Gate: Sec. "Layer switching and profile
+ * selection" (flatness phi, normalisation factor nu of eq. factor, Table
+ * "Profile definitions").
+ *
+ * Geometry (block mode): a lost B x B block is x0, its context is the ring of
+ * width `ring` around it, candidates are the displacements in
+ * [-window, window]^2 whose B x B prototype is received.  Distances run over
+ * the ring pixels known in both rings and are normalised by their count.
+ *
+ * Conventions shared by every entry point
+ *  - All pixel planes are 8-bit, row-major, `stride` bytes between rows
+ *    (stride >= width).  `loss_mask` has one byte per pixel, nonzero = lost.
+ *  - Lost pixels must form whole B x B cells of the block grid that lie fully
+ *    inside the frame; anything else returns SKM_EUNSUPPORTED.  Values at lost
+ *    pixels are never read.  Received pixels are copied unchanged.
+ *  - The caller owns every buffer; the library keeps no pointer after return.
+ *    `out` may alias `frame` (in place).
+ *  - Lost blocks are concealed in rounds: a round takes every pending block
+ *    whose known ring holds at least ring*block pixels (or, if none does, the
+ *    pending blocks with the most known ring pixels), estimates them all from
+ *    the state at the start of the round and only then marks them received.
+ *  - Output is bitwise deterministic for identical inputs and parameters.
+ *  - Errors are status codes; a thread-local message is kept for
+ *    skm_last_error().  Nothing throws across the ABI.
+ *  - A context is used by one host thread (and one stream) at a time.
+ */
+#ifndef SKMMSE_H
+#define SKMMSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum skm_status {
+  SKM_OK = 0,
+  SKM_EINVAL = -1,        /* bad argument, or a frame with no received pixel */
+  SKM_ENOMEM = -2,        /* device or host allocation failed */
+  SKM_EDEVICE = -3,       /* HIP runtime error */
+  SKM_EUNSUPPORTED = -4   /* loss mask not made of whole in-frame B x B cells */
+} skm_status;
+
+/* Estimation modes (skm_params.mode). */
+enum {
+  SKM_MODE_PROFILE = 0, /* paper's layered scheme: BRL / IDL with support-area
+                           expansion / HQL chosen by (t_phi, t_nu)            */
+  SKM_MODE_CNN = 1,     /* layer chosen by the learned gate; profile rule when
+                           no network is loaded                               */
+  SKM_MODE_BRL = 2,     /* context mean for every block (eq. mean)            */
+  SKM_MODE_IDL = 3,     /* IDL with expansion, never HQL                      */
+  SKM_MODE_FULL = 4,    /* full K-MMSE (HQL) where >= min_hql_cands complete
+                           candidates exist, else IDL over the whole window   */
+  SKM_MODE_PLAIN = 5    /* fixed-bandwidth kernel regression over the whole
+                           window (SLP-E, eq. slpe with M' = M), no gating    */
+};
+
+/* Layer codes reported in skm_block_info.layer. */
+enum { SKM_LAYER_FILL = -1, SKM_LAYER_BRL = 0, SKM_LAYER_IDL = 1, SKM_LAYER_HQL = 2 };
+
+/* skm_block_info.flags bits. */
+enum {
+  SKM_FLAG_CTX_RELAXED = 1, /* concealed with fewer than ring*block context px */
+  SKM_FLAG_NO_HQL = 2,      /* HQL wanted, too few complete candidates: IDL   */
+  SKM_FLAG_NO_CAND = 4,     /* no admissible candidate: BRL                   */
+  SKM_FLAG_EMPTY_CTX = 8    /* forced fill without context: frame mean        */
+};
+
+typedef struct skm_params {
+  int32_t block;           /* B: 4, 8 or 16                                    */
+  int32_t ring;            /* context ring width r, 1..8                      */
+  int32_t window;          /* search window half-size W, 1..32                */
+  int32_t expand_step;     /* IDL support-area growth step (Chebyshev px);
+                              radii step, 2 step, ..., window (at most 16)    */
+  int32_t min_overlap_pct; /* candidate needs >= ceil(pct*|m0|/100) common
+                              known ring pixels (and >= 1), 0..100            */
+  int32_t min_hql_cands;   /* HQL needs this many complete candidates (>= 2) */
+  int32_t mode;            /* SKM_MODE_*                                       */
+  int32_t max_rounds;      /* 0 = until every block is concealed; otherwise
+                              remaining blocks get a context-mean fill        */
+  double sigma2;           /* IDL kernel decay factor (paper: 10)             */
+  double t_phi;            /* flatness threshold T_phi (BRL iff phi <= T_phi) */
+  double t_nu;             /* normalisation threshold T_nu (IDL iff nu >= T_nu)*/
+  double ridge_rel;        /* HQL ridge: lambda = ridge_rel tr(C_YY)/N_y + 1e-12 */
+} skm_params;
+
+/* Per lost block result, in the raster order (by, then bx) of the lost cells. */
+typedef struct skm_block_info {
+  int32_t bx, by;          /* cell coordinates                                 */
+  int32_t layer;           /* SKM_LAYER_*                                      */
+  int32_t round;           /* 1-based round that concealed the block           */
+  int32_t n_cand;          /* admissible candidates (-1: not evaluated)       */
+  int32_t n_complete;      /* candidates whose ring covers all of m0 (-1: n/a)*/
+  int32_t radius;          /* accepted IDL radius, or window; 0 for BRL       */
+  int32_t flags;           /* SKM_FLAG_*                                       */
+  int32_t phi;             /* flatness max(y0) - min(y0) of the known ring    */
+  int32_t n_ctx;           /* |m0|: known ring pixels                          */
+  double log_nu;           /* log of the sum of raw IDL weights at `radius`
+                              (NaN when not evaluated)                        */
+} skm_block_info;
+
+typedef struct skm_ctx skm_ctx;
+
+/* Fill `p` with the paper's defaults: B 16, ring 4, window 24, step 4,
+ * overlap 50 %, HQL from 64 complete candidates, sigma^2 10, the "efficient"
+ * profile (T_phi 20, T_nu 0.1), ridge 1e-3, SKM_MODE_PROFILE, no round limit. */
+void skm_default_params(skm_params* p);
+
+/* Create a context bound to HIP device `hip_device`.  The context owns its
+ * device workspace (grown on demand) and, once loaded, the CNN gate weights.
+ * Returns SKM_EINVAL for a bad device or NULL `out`. */
+skm_status skm_create(int32_t hip_device, skm_ctx** out);
+
+/* Release the context and all device memory it owns.  NULL is ignored. */
+void skm_destroy(skm_ctx* ctx);
+
+/* Host-memory entry point (Sec. "Reconstruction framework" problem
+ * statement: conceal(frame, loss_mask, params) -> frame).
+ *   frame, loss_mask, out : host planes of height x stride bytes.
+ *   info      : optional host array of `info_cap` records (may be NULL).
+ *   n_lost    : optional; receives the number of lost blocks.
+ * Copies in, runs the rounds on the context's stream, copies out, and
+ * returns when the frame is complete.  If info is given and info_cap is
+ * smaller than the number of lost blocks, SKM_EINVAL is returned and `out`
+ * is left untouched. */
+skm_status skm_conceal(skm_ctx* ctx, const uint8_t* frame, const uint8_t* loss_mask,
+                       int32_t width, int32_t height, int32_t stride,
+                       const skm_params* params, uint8_t* out,
+                       skm_block_info* info, int32_t info_cap, int32_t* n_lost);
+
+/* Device-memory entry point; all pointers are device pointers owned by the
+ * caller (e.g. PyTorch tensors).  Work is enqueued on `hip_stream` (NULL =
+ * the null stream); the call returns once the stream has finished the frame
+ * (the round loop reads back one counter per batch of rounds).
+ *   d_info : optional device array of cap records (lost-cell raster order).
+ *   d_xhat : optional device float array of cap * B * B pre-rounding
+ *            estimates, block i at offset i*B*B, row-major in the block.
+ *   cap    : capacity of d_info / d_xhat in blocks; SKM_EINVAL if too small.
+ *   n_lost : optional host pointer receiving the number of lost blocks. */
+skm_status skm_conceal_device(skm_ctx* ctx, const uint8_t* d_frame, const uint8_t* d_mask,
+                              int32_t width, int32_t height, int32_t stride,
+                              const skm_params* params, uint8_t* d_out,
+                              skm_block_info* d_info, float* d_xhat, int32_t cap,
+                              int32_t* n_lost, void* hip_stream);
+
+/* Distance table of the kernel-regression core (eq. weights / eq. slpe):
+ * for each lost block i (lost-cell raster order) and each displacement
+ * (dx, dy) in [-W, W]^2 (index (dy+W)*(2W+1) + (dx+W)), the exact integer
+ * d = sum over ring pixels known in both rings of (y0 - y_j)^2 and their
+ * count n, evaluated on the received frame before any concealment.
+ * d = -1 (and n = 0) where the displacement is not an admissible candidate.
+ *   d_dist, d_cnt : device int32 arrays of cap * (2W+1)^2 entries.
+ * Mode and thresholds in `params` are ignored.  Same argument rules and
+ * return behaviour as skm_conceal_device. */
+skm_status skm_distances_device(skm_ctx* ctx, const uint8_t* d_frame, const uint8_t* d_mask,
+                                int32_t width, int32_t height, int32_t stride,
+                                const skm_params* params, int32_t* d_dist, int32_t* d_cnt,
+                                int32_t cap, int32_t* n_lost, void* hip_stream);
+
+/* Kernel timing for measurement tools (not needed for concealment).  While
+ * enabled, the context brackets every launch of its per-block estimation
+ * kernel (the kernel that stages the search window, computes the distances,
+ * weights and weighted averages) with a HIP event pair on the stream that
+ * launch uses.  skm_profile_read synchronises on those events, returns the
+ * summed elapsed time in milliseconds and the number of launches since the
+ * last read, and resets both.  Either pointer may be NULL. */
+skm_status skm_profile_enable(skm_ctx* ctx, int32_t enable);
+skm_status skm_profile_read(skm_ctx* ctx, double* total_ms, int32_t* launches);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* skm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKMMSE_H */

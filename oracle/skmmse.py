@@ -169,11 +169,15 @@ def candidate_set(u, avail, by, bx, p: Params, y0, m0) -> Candidates:
     py = by * b + dys
     px = bx * b + dxs
     inside = (py >= 0) & (px >= 0) & (py + b <= h) & (px + b <= w)
-    # prototype availability from an integral image of the lost indicator
-    lost_ii = np.zeros((h + 1, w + 1), dtype=np.int64)
-    lost_ii[1:, 1:] = np.cumsum(np.cumsum(~avail, axis=0), axis=1)
-    pyc = np.clip(py, 0, h - b)
-    pxc = np.clip(px, 0, w - b)
+    # prototype availability from an integral image of the lost indicator,
+    # taken over the part of the frame the prototypes can reach
+    y_lo, x_lo = max(0, by * b - W), max(0, bx * b - W)
+    y_hi, x_hi = min(h, by * b + b + W), min(w, bx * b + b + W)
+    lost = ~avail[y_lo:y_hi, x_lo:x_hi]
+    lost_ii = np.zeros((lost.shape[0] + 1, lost.shape[1] + 1), dtype=np.int64)
+    lost_ii[1:, 1:] = np.cumsum(np.cumsum(lost, axis=0), axis=1)
+    pyc = np.clip(py, y_lo, max(y_lo, y_hi - b)) - y_lo
+    pxc = np.clip(px, x_lo, max(x_lo, x_hi - b)) - x_lo
     nlost = (lost_ii[pyc + b, pxc + b] - lost_ii[pyc, pxc + b]
              - lost_ii[pyc + b, pxc] + lost_ii[pyc, pxc])
     ok = inside & (nlost == 0)
@@ -380,7 +384,7 @@ def estimate_block(u, avail, by, bx, p: Params, cnn_gate=None):
     y0, m0 = block_context(u, avail, by, bx, p)
     n0 = int(m0.sum())
     info = {"bx": bx, "by": by, "layer": LAYER_BRL, "n_cand": -1, "n_complete": -1,
-            "phi": 0, "log_nu": math.nan, "radius": 0, "flags": 0}
+            "phi": 0, "log_nu": math.nan, "radius": 0, "flags": 0, "n_ctx": n0}
     known = y0[m0]
     phi = int(known.max() - known.min()) if n0 else 0
     info["phi"] = phi
@@ -474,7 +478,7 @@ def conceal(frame: np.ndarray, mask: np.ndarray, p: Params, cnn_gate=None):
                 y0, m0 = block_context(u, avail, by, bx, p)
                 info = {"bx": bx, "by": by, "layer": LAYER_FILL, "n_cand": -1,
                         "n_complete": -1, "phi": 0, "log_nu": math.nan, "radius": 0,
-                        "flags": 0, "round": rnd}
+                        "flags": 0, "round": rnd, "n_ctx": int(m0.sum())}
                 if m0.any():
                     v = float(y0[m0].mean())
                 else:

@@ -1,0 +1,225 @@
+"""ctypes binding of the C ABI in include/skmmse.h (same names, same order).
+
+Host arrays are NumPy; device buffers are PyTorch tensors (``torch`` is used
+only for device memory and the current HIP stream).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libskmmse.so")
+
+MODES = {"profile": 0, "cnn": 1, "brl": 2, "idl": 3, "full": 4, "plain": 5}
+LAYER_FILL, LAYER_BRL, LAYER_IDL, LAYER_HQL = -1, 0, 1, 2
+FLAG_CTX_RELAXED, FLAG_NO_HQL, FLAG_NO_CAND, FLAG_EMPTY_CTX = 1, 2, 4, 8
+
+EXPORTS = ("skm_default_params", "skm_create", "skm_destroy", "skm_conceal",
+           "skm_conceal_device", "skm_distances_device", "skm_profile_enable",
+           "skm_profile_read", "skm_last_error")
+
+
+class SkmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"skmmse status {status}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("block", ctypes.c_int32), ("ring", ctypes.c_int32), ("window", ctypes.c_int32),
+        ("expand_step", ctypes.c_int32), ("min_overlap_pct", ctypes.c_int32),
+        ("min_hql_cands", ctypes.c_int32), ("mode", ctypes.c_int32),
+        ("max_rounds", ctypes.c_int32), ("sigma2", ctypes.c_double),
+        ("t_phi", ctypes.c_double), ("t_nu", ctypes.c_double), ("ridge_rel", ctypes.c_double),
+    ]
+
+
+class BlockInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "bx", "by", "layer", "round", "n_cand", "n_complete", "radius", "flags", "phi",
+        "n_ctx")] + [("log_nu", ctypes.c_double)]
+
+
+BLOCK_INFO_DTYPE = np.dtype([(n, "<i4") for n in (
+    "bx", "by", "layer", "round", "n_cand", "n_complete", "radius", "flags", "phi",
+    "n_ctx")] + [("log_nu", "<f8")])
+assert BLOCK_INFO_DTYPE.itemsize == ctypes.sizeof(BlockInfo) == 48
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python paper_2205_11226_amd/build.py`")
+    so = ctypes.CDLL(LIB_PATH)
+    p, i32, vp = ctypes.POINTER, ctypes.c_int32, ctypes.c_void_p
+    so.skm_default_params.argtypes = [p(Params)]
+    so.skm_default_params.restype = None
+    so.skm_create.argtypes = [i32, p(vp)]
+    so.skm_create.restype = i32
+    so.skm_destroy.argtypes = [vp]
+    so.skm_destroy.restype = None
+    so.skm_conceal.argtypes = [vp, vp, vp, i32, i32, i32, p(Params), vp, vp, i32, p(i32)]
+    so.skm_conceal.restype = i32
+    so.skm_conceal_device.argtypes = [vp, vp, vp, i32, i32, i32, p(Params), vp, vp, vp, i32,
+                                      p(i32), vp]
+    so.skm_conceal_device.restype = i32
+    so.skm_distances_device.argtypes = [vp, vp, vp, i32, i32, i32, p(Params), vp, vp, i32,
+                                        p(i32), vp]
+    so.skm_distances_device.restype = i32
+    so.skm_profile_enable.argtypes = [vp, i32]
+    so.skm_profile_enable.restype = i32
+    so.skm_profile_read.argtypes = [vp, p(ctypes.c_double), p(i32)]
+    so.skm_profile_read.restype = i32
+    so.skm_last_error.argtypes = []
+    so.skm_last_error.restype = ctypes.c_char_p
+    return so
+
+
+lib = _load()
+
+
+def exported_symbols() -> tuple:
+    return tuple(n for n in EXPORTS if hasattr(lib, n))
+
+
+def _check(status: int):
+    if status != 0:
+        raise SkmError(status, lib.skm_last_error().decode(errors="replace"))
+
+
+def default_params(**kw) -> Params:
+    """Paper defaults; keyword overrides (``mode`` may be a name)."""
+    prm = Params()
+    lib.skm_default_params(ctypes.byref(prm))
+    profile = kw.pop("profile", None)
+    if profile is not None:
+        tphi, tnu = {"express": (20.0, 0.01), "efficient": (20.0, 0.1),
+                     "excellent": (20.0, 100.0)}[profile]
+        prm.t_phi, prm.t_nu = tphi, tnu
+    for k, v in kw.items():
+        if k == "mode" and isinstance(v, str):
+            v = MODES[v]
+        if not hasattr(prm, k):
+            raise KeyError(k)
+        setattr(prm, k, v)
+    return prm
+
+
+class Context:
+    """Owns an ``skm_ctx`` on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib.skm_create(int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = int(device)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.skm_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------- timing
+    def profile_enable(self, on: bool = True):
+        _check(lib.skm_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """(summed ms, launches) of the estimation kernel since the last read."""
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int32(0)
+        _check(lib.skm_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    # ---------------------------------------------------------------- host
+    def conceal(self, frame: np.ndarray, mask: np.ndarray, params: Params,
+                want_info: bool = True):
+        """Host entry point; returns (out uint8, info structured array)."""
+        frame = np.ascontiguousarray(frame, dtype=np.uint8)
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        if frame.ndim != 2 or frame.shape != mask.shape:
+            raise ValueError("frame and mask must be 2-D of the same shape")
+        h, w = frame.shape
+        out = np.empty_like(frame)
+        cap = (h // params.block) * (w // params.block)
+        info = np.zeros(max(cap, 1), dtype=BLOCK_INFO_DTYPE) if want_info else None
+        n = ctypes.c_int32(0)
+        _check(lib.skm_conceal(self._h, frame.ctypes.data, mask.ctypes.data, w, h, w,
+                               ctypes.byref(params), out.ctypes.data,
+                               info.ctypes.data if want_info else None, cap,
+                               ctypes.byref(n)))
+        return out, (info[:n.value] if want_info else None)
+
+    # -------------------------------------------------------------- device
+    def conceal_device(self, frame, mask, params: Params, out=None, want_info=True,
+                       want_xhat=True, stream=None):
+        """Device entry point on torch uint8 CUDA tensors (H, W).
+
+        Returns (out tensor, info structured array or None, xhat float32
+        tensor (n_lost, B, B) or None).
+        """
+        import torch
+        _dev_check(frame, mask)
+        h, w = frame.shape
+        if out is None:
+            out = torch.empty_like(frame)
+        b = params.block
+        cap = (h // b) * (w // b)
+        dinfo = (torch.zeros(max(cap, 1) * BLOCK_INFO_DTYPE.itemsize, dtype=torch.uint8,
+                             device=frame.device) if want_info else None)
+        dx = (torch.zeros((max(cap, 1), b, b), dtype=torch.float32, device=frame.device)
+              if want_xhat else None)
+        n = ctypes.c_int32(0)
+        s = torch.cuda.current_stream(frame.device) if stream is None else stream
+        _check(lib.skm_conceal_device(
+            self._h, frame.data_ptr(), mask.data_ptr(), w, h, frame.stride(0),
+            ctypes.byref(params), out.data_ptr(),
+            dinfo.data_ptr() if dinfo is not None else None,
+            dx.data_ptr() if dx is not None else None, cap, ctypes.byref(n),
+            ctypes.c_void_p(s.cuda_stream)))
+        info = None
+        if dinfo is not None:
+            info = dinfo.cpu().numpy().view(BLOCK_INFO_DTYPE)[:n.value].copy()
+        return out, info, (dx[:n.value] if dx is not None else None)
+
+    def distances_device(self, frame, mask, params: Params, stream=None):
+        """Exact distance table: (d, n) int32 tensors (n_lost, 2W+1, 2W+1)."""
+        import torch
+        _dev_check(frame, mask)
+        h, w = frame.shape
+        b, W = params.block, params.window
+        cap = max((h // b) * (w // b), 1)
+        D = 2 * W + 1
+        d = torch.empty((cap, D, D), dtype=torch.int32, device=frame.device)
+        c = torch.empty((cap, D, D), dtype=torch.int32, device=frame.device)
+        n = ctypes.c_int32(0)
+        s = torch.cuda.current_stream(frame.device) if stream is None else stream
+        _check(lib.skm_distances_device(
+            self._h, frame.data_ptr(), mask.data_ptr(), w, h, frame.stride(0),
+            ctypes.byref(params), d.data_ptr(), c.data_ptr(), cap, ctypes.byref(n),
+            ctypes.c_void_p(s.cuda_stream)))
+        return d[:n.value], c[:n.value]
+
+
+def _dev_check(frame, mask):
+    import torch
+    for t in (frame, mask):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.uint8
+                and t.dim() == 2 and t.stride(1) == 1):
+            raise ValueError("frame and mask must be 2-D row-contiguous uint8 CUDA tensors")
+    if frame.shape != mask.shape or frame.stride(0) != mask.stride(0):
+        raise ValueError("frame and mask must have the same shape and stride")

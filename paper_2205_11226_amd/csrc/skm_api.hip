@@ -1,0 +1,398 @@
+// Host side of the C ABI declared in include/skmmse.h.
+//
+// A context owns a stream for the host-memory entry point and a device
+// workspace that grows on demand (never shrinks until skm_destroy).  The
+// per-frame pipeline is: loss geometry (k_init, k_cells, k_compact), then
+// rounds of (prep, main, finalize) until no block is pending.  Rounds are
+// enqueued in batches; one small counter read-back per batch decides whether
+// more are needed, and the batch size is remembered for the next frame.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "skm_internal.h"
+
+using namespace skm;
+
+struct skm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int max_lds = 65536;
+  size_t lds_limit_set = 65536;
+  // frame workspace
+  uint8_t* d_avail = nullptr;     size_t cap_px = 0;
+  uint8_t* d_cell_lost = nullptr;
+  int* d_blk = nullptr;
+  int* d_bstate = nullptr;
+  int* d_m0cnt = nullptr;         size_t cap_cells = 0;
+  RoundState* d_state = nullptr;
+  RoundState* h_state = nullptr;  // pinned
+  // staging for the host-memory entry point
+  uint8_t* d_frame = nullptr;     size_t cap_frame = 0;
+  uint8_t* d_mask = nullptr;      size_t cap_mask = 0;
+  uint8_t* d_out = nullptr;       size_t cap_out = 0;
+  skm_block_info* d_info = nullptr; size_t cap_info = 0;
+  int last_rounds = 1;
+  // kernel timing (skm_profile_*)
+  bool prof = false;
+  std::vector<hipEvent_t> ev;     // pairs: [2k] before, [2k+1] after
+  int ev_used = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+skm_status fail(skm_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+skm_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? SKM_ENOMEM : SKM_EDEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define SKM_HIP(call, what)                       \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+template <typename T>
+skm_status grow(T** ptr, size_t* cap, size_t need, const char* what) {
+  if (need <= *cap && *ptr) return SKM_OK;
+  if (*ptr) { (void)hipFree(*ptr); *ptr = nullptr; *cap = 0; }
+  size_t n = need < 1 ? 1 : need;
+  SKM_HIP(hipMalloc((void**)ptr, n * sizeof(T)), what);
+  *cap = n;
+  return SKM_OK;
+}
+
+skm_status make_params(const skm_params* in, int width, int height, int stride, DevParams* p) {
+  if (!in) return fail(SKM_EINVAL, "params is NULL");
+  if (width <= 0 || height <= 0) return fail(SKM_EINVAL, "width and height must be positive");
+  if (stride < width) return fail(SKM_EINVAL, "stride must be >= width");
+  if (!(in->block == 4 || in->block == 8 || in->block == 16))
+    return fail(SKM_EINVAL, "block must be 4, 8 or 16");
+  if (in->ring < 1 || in->ring > kMaxRing) return fail(SKM_EINVAL, "ring must be in 1..8");
+  if (in->window < 1 || in->window > kMaxWin) return fail(SKM_EINVAL, "window must be in 1..32");
+  if (in->expand_step < 1) return fail(SKM_EINVAL, "expand_step must be >= 1");
+  if (in->min_overlap_pct < 0 || in->min_overlap_pct > 100)
+    return fail(SKM_EINVAL, "min_overlap_pct must be in 0..100");
+  if (in->min_hql_cands < 2) return fail(SKM_EINVAL, "min_hql_cands must be >= 2");
+  if (in->mode < SKM_MODE_PROFILE || in->mode > SKM_MODE_PLAIN)
+    return fail(SKM_EINVAL, "unknown mode");
+  if (in->max_rounds < 0) return fail(SKM_EINVAL, "max_rounds must be >= 0");
+  if (!(in->sigma2 > 0.0) || !isfinite(in->sigma2)) return fail(SKM_EINVAL, "sigma2 must be > 0");
+  if (isnan(in->t_phi)) return fail(SKM_EINVAL, "t_phi is NaN");
+  if (isnan(in->t_nu) || in->t_nu < 0.0) return fail(SKM_EINVAL, "t_nu must be >= 0");
+  if (!(in->ridge_rel >= 0.0) || !isfinite(in->ridge_rel))
+    return fail(SKM_EINVAL, "ridge_rel must be finite and >= 0");
+  memset(p, 0, sizeof(*p));
+  p->B = in->block; p->r = in->ring; p->W = in->window;
+  p->Wd = p->B + 2 * p->r + 2 * p->W;
+  p->F = p->B + 2 * p->r;
+  p->ND = (2 * p->W + 1) * (2 * p->W + 1);
+  int n = 0;
+  for (int rho = in->expand_step; rho < p->W; rho += in->expand_step) {
+    if (n >= kMaxRadii - 1) return fail(SKM_EINVAL, "expand_step gives more than 16 radii");
+    p->radii[n++] = rho;
+  }
+  p->radii[n++] = p->W;
+  p->nrad = n;
+  p->min_pct = in->min_overlap_pct;
+  p->min_hql = in->min_hql_cands;
+  p->mode = in->mode;
+  p->width = width; p->height = height; p->stride = stride;
+  p->gh = height / p->B; p->gw = width / p->B;
+  p->sigma2 = in->sigma2;
+  p->t_phi = in->t_phi;
+  p->log_tnu = in->t_nu > 0.0 ? log(in->t_nu) : -INFINITY;
+  p->ridge_rel = in->ridge_rel;
+  return SKM_OK;
+}
+
+skm_status ensure_frame(skm_ctx* c, const DevParams& p) {
+  size_t npx = (size_t)p.width * p.height;
+  size_t ncell = (size_t)p.gh * p.gw;
+  skm_status s;
+  if ((s = grow(&c->d_avail, &c->cap_px, npx, "workspace plane")) != SKM_OK) return s;
+  if (ncell > c->cap_cells || !c->d_blk) {
+    size_t cap = 0;
+    (void)hipFree(c->d_cell_lost); c->d_cell_lost = nullptr;
+    (void)hipFree(c->d_blk); c->d_blk = nullptr;
+    (void)hipFree(c->d_bstate); c->d_bstate = nullptr;
+    (void)hipFree(c->d_m0cnt); c->d_m0cnt = nullptr;
+    c->cap_cells = 0;
+    if ((s = grow(&c->d_cell_lost, &cap, ncell, "cell table")) != SKM_OK) return s;
+    cap = 0;
+    if ((s = grow(&c->d_blk, &cap, ncell, "block list")) != SKM_OK) return s;
+    cap = 0;
+    if ((s = grow(&c->d_bstate, &cap, ncell, "block state")) != SKM_OK) return s;
+    cap = 0;
+    if ((s = grow(&c->d_m0cnt, &cap, ncell, "context counts")) != SKM_OK) return s;
+    c->cap_cells = ncell < 1 ? 1 : ncell;
+  }
+  size_t lds = main_lds_bytes(p);
+  if ((int)lds > c->max_lds)
+    return fail(SKM_EUNSUPPORTED, "window/ring/block need more LDS than the device has");
+  if (lds > c->lds_limit_set) {
+    SKM_HIP(set_main_lds_limit(lds), "hipFuncSetAttribute");
+    c->lds_limit_set = lds;
+  }
+  return SKM_OK;
+}
+
+FrameArgs frame_args(skm_ctx* c, const uint8_t* frame, const uint8_t* mask, uint8_t* out) {
+  FrameArgs a;
+  memset(&a, 0, sizeof(a));
+  a.frame = frame; a.mask = mask; a.work = out;
+  a.avail = c->d_avail; a.cell_lost = c->d_cell_lost; a.blk = c->d_blk;
+  a.bstate = c->d_bstate; a.m0cnt = c->d_m0cnt; a.st = c->d_state;
+  return a;
+}
+
+skm_status read_state(skm_ctx* c, hipStream_t s) {
+  SKM_HIP(hipMemcpyAsync(c->h_state, c->d_state, sizeof(RoundState), hipMemcpyDeviceToHost, s),
+          "state read-back");
+  SKM_HIP(hipStreamSynchronize(s), "stream synchronize");
+  return SKM_OK;
+}
+
+skm_status check_err(const RoundState& st) {
+  if (st.err & kErrPartial)
+    return fail(SKM_EUNSUPPORTED, "lost pixels must form whole B x B cells inside the frame");
+  if (st.err & kErrNoContext)
+    return fail(SKM_EINVAL, "no lost block touches a received pixel (frame with no received pixel?)");
+  if (st.err & kErrHqlPending)
+    return fail(SKM_EUNSUPPORTED, "a block needs the HQL layer, which this build does not run");
+  return SKM_OK;
+}
+
+// One round: context counts, estimation, availability update.  With timing on,
+// the estimation kernel is bracketed by an event pair on `s`.
+skm_status launch_round(skm_ctx* c, const DevParams& p, FrameArgs& a, int nb, hipStream_t s) {
+  SKM_HIP(launch_prep(a, p, nb, s), "prep kernel");
+  if (c->prof) {
+    if ((int)c->ev.size() < 2 * (c->ev_used + 1)) {
+      for (int k = 0; k < 2; ++k) {
+        hipEvent_t e;
+        SKM_HIP(hipEventCreate(&e), "hipEventCreate");
+        c->ev.push_back(e);
+      }
+    }
+    SKM_HIP(hipEventRecord(c->ev[2 * c->ev_used], s), "hipEventRecord");
+  }
+  SKM_HIP(launch_est(a, p, nb, s), "estimation kernel");
+  if (c->prof) {
+    SKM_HIP(hipEventRecord(c->ev[2 * c->ev_used + 1], s), "hipEventRecord");
+    ++c->ev_used;
+  }
+  SKM_HIP(launch_finalize(a, p, nb, s), "finalize kernel");
+  return SKM_OK;
+}
+
+// Whole-frame pipeline on `s`; the frame is complete when this returns SKM_OK.
+skm_status run_frame(skm_ctx* c, const DevParams& p, FrameArgs& a, int max_rounds,
+                     hipStream_t s, int* n_lost_out) {
+  const int ncell = p.gh * p.gw;
+  SKM_HIP(launch_init(a, p, s), "geometry kernels");
+  int done = 0;
+  int batch = c->last_rounds < 1 ? 1 : c->last_rounds;
+  for (;;) {
+    if (max_rounds && batch > max_rounds - done) batch = max_rounds - done;
+    skm_status st;
+    for (int k = 0; k < batch; ++k)
+      if ((st = launch_round(c, p, a, ncell, s)) != SKM_OK) return st;
+    done += batch;
+    st = read_state(c, s);
+    if (st != SKM_OK) return st;
+    if ((st = check_err(*c->h_state)) != SKM_OK) return st;
+    if (c->h_state->remaining == 0) break;
+    if (max_rounds && done >= max_rounds) {
+      SKM_HIP(launch_fill(a, p, ncell, s), "fill kernels");
+      if ((st = read_state(c, s)) != SKM_OK) return st;
+      break;
+    }
+    batch *= 2;
+  }
+  int used = c->h_state->round - 1;
+  c->last_rounds = used < 1 ? 1 : (used > 64 ? 64 : used);
+  if (n_lost_out) *n_lost_out = c->h_state->n_lost;
+  return SKM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void skm_default_params(skm_params* p) {
+  if (!p) return;
+  p->block = 16; p->ring = 4; p->window = 24; p->expand_step = 4;
+  p->min_overlap_pct = 50; p->min_hql_cands = 64; p->mode = SKM_MODE_PROFILE;
+  p->max_rounds = 0; p->sigma2 = 10.0; p->t_phi = 20.0; p->t_nu = 0.1; p->ridge_rel = 1e-3;
+}
+
+const char* skm_last_error(void) { return g_err.c_str(); }
+
+skm_status skm_create(int32_t hip_device, skm_ctx** out) {
+  if (!out) return fail(SKM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  SKM_HIP(hipGetDeviceCount(&n), "hipGetDeviceCount");
+  if (hip_device < 0 || hip_device >= n) return fail(SKM_EINVAL, "no such HIP device");
+  SKM_HIP(hipSetDevice(hip_device), "hipSetDevice");
+  skm_ctx* c = new (std::nothrow) skm_ctx();
+  if (!c) return fail(SKM_ENOMEM, "context allocation");
+  c->device = hip_device;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) ==
+          hipSuccess && lds > 0)
+    c->max_lds = lds;
+  hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->d_state, sizeof(RoundState));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_state, sizeof(RoundState), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    skm_destroy(c);
+    return hip_fail(e, "context setup");
+  }
+  *out = c;
+  return SKM_OK;
+}
+
+void skm_destroy(skm_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(c->d_avail);
+  (void)hipFree(c->d_cell_lost);
+  (void)hipFree(c->d_blk);
+  (void)hipFree(c->d_bstate);
+  (void)hipFree(c->d_m0cnt);
+  (void)hipFree(c->d_state);
+  (void)hipFree(c->d_frame);
+  (void)hipFree(c->d_mask);
+  (void)hipFree(c->d_out);
+  (void)hipFree(c->d_info);
+  if (c->h_state) (void)hipHostFree(c->h_state);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+skm_status skm_conceal_device(skm_ctx* c, const uint8_t* d_frame, const uint8_t* d_mask,
+                              int32_t width, int32_t height, int32_t stride,
+                              const skm_params* params, uint8_t* d_out,
+                              skm_block_info* d_info, float* d_xhat, int32_t cap,
+                              int32_t* n_lost, void* hip_stream) {
+  if (!c) return fail(SKM_EINVAL, "ctx is NULL");
+  if (!d_frame || !d_mask || !d_out) return fail(SKM_EINVAL, "frame, mask and out are required");
+  if ((d_info || d_xhat) && cap < 0) return fail(SKM_EINVAL, "cap must be >= 0");
+  DevParams p;
+  skm_status s = make_params(params, width, height, stride, &p);
+  if (s != SKM_OK) return s;
+  SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  if ((s = ensure_frame(c, p)) != SKM_OK) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  FrameArgs a = frame_args(c, d_frame, d_mask, d_out);
+  a.info = d_info; a.xhat = d_xhat; a.cap = (d_info || d_xhat) ? cap : 0;
+  int nl = 0;
+  if ((s = run_frame(c, p, a, params->max_rounds, st, &nl)) != SKM_OK) return s;
+  if (n_lost) *n_lost = nl;
+  if ((d_info || d_xhat) && nl > cap)
+    return fail(SKM_EINVAL, "info/xhat capacity smaller than the number of lost blocks");
+  return SKM_OK;
+}
+
+skm_status skm_conceal(skm_ctx* c, const uint8_t* frame, const uint8_t* loss_mask,
+                       int32_t width, int32_t height, int32_t stride,
+                       const skm_params* params, uint8_t* out,
+                       skm_block_info* info, int32_t info_cap, int32_t* n_lost) {
+  if (!c) return fail(SKM_EINVAL, "ctx is NULL");
+  if (!frame || !loss_mask || !out) return fail(SKM_EINVAL, "frame, mask and out are required");
+  if (info && info_cap < 0) return fail(SKM_EINVAL, "info_cap must be >= 0");
+  DevParams p;
+  skm_status s = make_params(params, width, height, stride, &p);
+  if (s != SKM_OK) return s;
+  SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  size_t bytes = (size_t)(height - 1) * stride + width;
+  if ((s = grow(&c->d_frame, &c->cap_frame, bytes, "staging")) != SKM_OK) return s;
+  if ((s = grow(&c->d_mask, &c->cap_mask, bytes, "staging")) != SKM_OK) return s;
+  if ((s = grow(&c->d_out, &c->cap_out, bytes, "staging")) != SKM_OK) return s;
+  int ncell = (width / params->block) * (height / params->block);
+  if (info && (s = grow(&c->d_info, &c->cap_info, (size_t)(ncell < 1 ? 1 : ncell), "info")) != SKM_OK)
+    return s;
+  if ((s = ensure_frame(c, p)) != SKM_OK) return s;
+  hipStream_t st = c->stream;
+  SKM_HIP(hipMemcpyAsync(c->d_frame, frame, bytes, hipMemcpyHostToDevice, st), "frame upload");
+  SKM_HIP(hipMemcpyAsync(c->d_mask, loss_mask, bytes, hipMemcpyHostToDevice, st), "mask upload");
+  FrameArgs a = frame_args(c, c->d_frame, c->d_mask, c->d_out);
+  a.info = info ? c->d_info : nullptr;
+  a.cap = info ? ncell : 0;
+  int nl = 0;
+  if ((s = run_frame(c, p, a, params->max_rounds, st, &nl)) != SKM_OK) return s;
+  if (n_lost) *n_lost = nl;
+  if (info && nl > info_cap)
+    return fail(SKM_EINVAL, "info_cap smaller than the number of lost blocks");
+  SKM_HIP(hipMemcpyAsync(out, c->d_out, bytes, hipMemcpyDeviceToHost, st), "frame download");
+  if (info && nl > 0)
+    SKM_HIP(hipMemcpyAsync(info, c->d_info, sizeof(skm_block_info) * nl, hipMemcpyDeviceToHost, st),
+            "info download");
+  SKM_HIP(hipStreamSynchronize(st), "stream synchronize");
+  return SKM_OK;
+}
+
+skm_status skm_distances_device(skm_ctx* c, const uint8_t* d_frame, const uint8_t* d_mask,
+                                int32_t width, int32_t height, int32_t stride,
+                                const skm_params* params, int32_t* d_dist, int32_t* d_cnt,
+                                int32_t cap, int32_t* n_lost, void* hip_stream) {
+  if (!c) return fail(SKM_EINVAL, "ctx is NULL");
+  if (!d_frame || !d_mask || !d_dist || !d_cnt) return fail(SKM_EINVAL, "NULL pointer");
+  DevParams p;
+  skm_status s = make_params(params, width, height, stride, &p);
+  if (s != SKM_OK) return s;
+  SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  if ((s = ensure_frame(c, p)) != SKM_OK) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  size_t bytes = (size_t)(height - 1) * stride + width;
+  if ((s = grow(&c->d_out, &c->cap_out, bytes, "scratch plane")) != SKM_OK) return s;
+  FrameArgs a = frame_args(c, d_frame, d_mask, c->d_out);
+  SKM_HIP(launch_init(a, p, st), "geometry kernels");
+  if ((s = read_state(c, st)) != SKM_OK) return s;
+  if ((s = check_err(*c->h_state)) != SKM_OK) return s;
+  int nl = c->h_state->n_lost;
+  if (n_lost) *n_lost = nl;
+  if (nl > cap) return fail(SKM_EINVAL, "cap smaller than the number of lost blocks");
+  a.dist = d_dist; a.cnt = d_cnt;
+  SKM_HIP(launch_dist(a, p, p.gh * p.gw, st), "distance kernel");
+  SKM_HIP(hipStreamSynchronize(st), "stream synchronize");
+  return SKM_OK;
+}
+
+skm_status skm_profile_enable(skm_ctx* c, int32_t enable) {
+  if (!c) return fail(SKM_EINVAL, "ctx is NULL");
+  c->prof = enable != 0;
+  return SKM_OK;
+}
+
+skm_status skm_profile_read(skm_ctx* c, double* total_ms, int32_t* launches) {
+  if (!c) return fail(SKM_EINVAL, "ctx is NULL");
+  SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  double tot = 0.0;
+  for (int k = 0; k < c->ev_used; ++k) {
+    SKM_HIP(hipEventSynchronize(c->ev[2 * k + 1]), "hipEventSynchronize");
+    float ms = 0.f;
+    SKM_HIP(hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]), "hipEventElapsedTime");
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = c->ev_used;
+  c->ev_used = 0;
+  return SKM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal declarations shared by the host API and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "skmmse.h"
+
+namespace skm {
+
+constexpr int kThreads = 256;        // one workgroup = 4 wave64
+constexpr int kMaxRadii = 16;
+constexpr int kMaxB = 16;
+constexpr int kMaxRing = 8;
+constexpr int kMaxWin = 32;
+constexpr int kMaxWd = kMaxB + 2 * kMaxRing + 2 * kMaxWin;   // 96 window side
+
+// device error bits (RoundState::err)
+constexpr int kErrPartial = 1;       // lost pixel outside a whole in-frame cell
+constexpr int kErrNoContext = 2;     // pending blocks, none touches a known pixel
+constexpr int kErrHqlPending = 4;    // a block needs HQL and no HQL pass ran
+
+struct DevParams {
+  int B, r, W;
+  int Wd;          // window side B + 2r + 2W
+  int F;           // footprint side B + 2r
+  int ND;          // (2W+1)^2 displacements
+  int nrad;
+  int radii[kMaxRadii];
+  int min_pct, min_hql, mode;
+  int width, height, stride;
+  int gh, gw;      // full cells
+  double sigma2, t_phi, log_tnu, ridge_rel;
+};
+
+struct RoundState {
+  int n_lost;
+  int remaining;       // pending blocks at the start of the current round
+  int remaining_acc;   // pending count accumulated by the finalize kernel
+  int nq;              // pending blocks with |m0| >= r B
+  int maxm0;           // largest |m0| among pending blocks
+  int round;           // current round, 1-based
+  int err;
+  int done_wgs;        // finalize: workgroups finished
+  unsigned long long n_avail;
+  unsigned long long sum_avail;
+};
+
+// bstate values: 0 pending, > 0 concealed in that round, kNeedHql + round:
+// waiting for the HQL kernels in that round.
+constexpr int kNeedHql = 1 << 20;
+
+struct FrameArgs {
+  const uint8_t* frame;
+  const uint8_t* mask;
+  uint8_t* work;          // output plane (caller's out), same stride
+  uint8_t* avail;         // workspace plane, pitch = width
+  uint8_t* cell_lost;     // gh * gw
+  int* blk;               // lost cell indices, raster order
+  int* bstate;
+  int* m0cnt;
+  RoundState* st;
+  skm_block_info* info;   // optional
+  float* xhat;            // optional
+  int* dist;              // optional distance table (parity entry point)
+  int* cnt;
+  int cap;                // capacity of info / xhat in blocks
+};
+
+// launchers (skm_kernels.hip)
+hipError_t launch_init(const FrameArgs& a, const DevParams& p, hipStream_t s);
+hipError_t launch_prep(const FrameArgs& a, const DevParams& p, int max_blocks,
+                       hipStream_t s);
+hipError_t launch_est(const FrameArgs& a, const DevParams& p, int max_blocks, hipStream_t s);
+hipError_t launch_finalize(const FrameArgs& a, const DevParams& p, int max_blocks,
+                           hipStream_t s);
+hipError_t launch_fill(const FrameArgs& a, const DevParams& p, int max_blocks,
+                       hipStream_t s);
+hipError_t launch_dist(const FrameArgs& a, const DevParams& p, int max_blocks,
+                       hipStream_t s);
+hipError_t set_main_lds_limit(size_t bytes);
+size_t main_lds_bytes(const DevParams& p);
+
+}  // namespace skm
