@@ -23,11 +23,12 @@ struct skm_ctx {
   int max_lds = 65536;
   size_t lds_limit_set = 65536;
   // frame workspace
-  uint8_t* d_avail = nullptr;     size_t cap_px = 0;
+  int16_t* d_val = nullptr;       size_t cap_px = 0;
   uint8_t* d_cell_lost = nullptr;
   int* d_blk = nullptr;
   int* d_bstate = nullptr;
   int* d_m0cnt = nullptr;         size_t cap_cells = 0;
+  int* d_part = nullptr;
   RoundState* d_state = nullptr;
   RoundState* h_state = nullptr;  // pinned
   // staging for the host-memory entry point
@@ -97,6 +98,12 @@ skm_status make_params(const skm_params* in, int width, int height, int stride, 
   p->Wd = p->B + 2 * p->r + 2 * p->W;
   p->F = p->B + 2 * p->r;
   p->ND = (2 * p->W + 1) * (2 * p->W + 1);
+  p->NR = p->F * p->F - p->B * p->B;
+  {
+    const int side = 2 * (p->B - 1 < p->W ? p->B - 1 : p->W) + 1;   // overlap the block itself
+    p->MC = p->ND - side * side;
+    if (p->MC < 1) p->MC = 1;
+  }
   int n = 0;
   for (int rho = in->expand_step; rho < p->W; rho += in->expand_step) {
     if (n >= kMaxRadii - 1) return fail(SKM_EINVAL, "expand_step gives more than 16 radii");
@@ -109,6 +116,7 @@ skm_status make_params(const skm_params* in, int width, int height, int stride, 
   p->mode = in->mode;
   p->width = width; p->height = height; p->stride = stride;
   p->gh = height / p->B; p->gw = width / p->B;
+  p->prep_grid = prep_grid_for(p->gh * p->gw);
   p->sigma2 = in->sigma2;
   p->t_phi = in->t_phi;
   p->log_tnu = in->t_nu > 0.0 ? log(in->t_nu) : -INFINITY;
@@ -120,7 +128,7 @@ skm_status ensure_frame(skm_ctx* c, const DevParams& p) {
   size_t npx = (size_t)p.width * p.height;
   size_t ncell = (size_t)p.gh * p.gw;
   skm_status s;
-  if ((s = grow(&c->d_avail, &c->cap_px, npx, "workspace plane")) != SKM_OK) return s;
+  if ((s = grow(&c->d_val, &c->cap_px, npx, "workspace plane")) != SKM_OK) return s;
   if (ncell > c->cap_cells || !c->d_blk) {
     size_t cap = 0;
     (void)hipFree(c->d_cell_lost); c->d_cell_lost = nullptr;
@@ -137,6 +145,7 @@ skm_status ensure_frame(skm_ctx* c, const DevParams& p) {
     if ((s = grow(&c->d_m0cnt, &cap, ncell, "context counts")) != SKM_OK) return s;
     c->cap_cells = ncell < 1 ? 1 : ncell;
   }
+  if (!c->d_part) SKM_HIP(hipMalloc((void**)&c->d_part, sizeof(int) * 2 * kPrepGridMax), "prep slots");
   size_t lds = main_lds_bytes(p);
   if ((int)lds > c->max_lds)
     return fail(SKM_EUNSUPPORTED, "window/ring/block need more LDS than the device has");
@@ -151,8 +160,8 @@ FrameArgs frame_args(skm_ctx* c, const uint8_t* frame, const uint8_t* mask, uint
   FrameArgs a;
   memset(&a, 0, sizeof(a));
   a.frame = frame; a.mask = mask; a.work = out;
-  a.avail = c->d_avail; a.cell_lost = c->d_cell_lost; a.blk = c->d_blk;
-  a.bstate = c->d_bstate; a.m0cnt = c->d_m0cnt; a.st = c->d_state;
+  a.val = c->d_val; a.cell_lost = c->d_cell_lost; a.blk = c->d_blk;
+  a.bstate = c->d_bstate; a.m0cnt = c->d_m0cnt; a.part = c->d_part; a.st = c->d_state;
   return a;
 }
 
@@ -268,11 +277,12 @@ void skm_destroy(skm_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  (void)hipFree(c->d_avail);
+  (void)hipFree(c->d_val);
   (void)hipFree(c->d_cell_lost);
   (void)hipFree(c->d_blk);
   (void)hipFree(c->d_bstate);
   (void)hipFree(c->d_m0cnt);
+  (void)hipFree(c->d_part);
   (void)hipFree(c->d_state);
   (void)hipFree(c->d_frame);
   (void)hipFree(c->d_mask);

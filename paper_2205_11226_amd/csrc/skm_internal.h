@@ -25,9 +25,12 @@ struct DevParams {
   int Wd;          // window side B + 2r + 2W
   int F;           // footprint side B + 2r
   int ND;          // (2W+1)^2 displacements
+  int NR;          // ring pixels F^2 - B^2
+  int MC;          // bound on admissible candidates
   int nrad;
   int radii[kMaxRadii];
   int min_pct, min_hql, mode;
+  int prep_grid;   // workgroups of the prep kernel
   int width, height, stride;
   int gh, gw;      // full cells
   double sigma2, t_phi, log_tnu, ridge_rel;
@@ -36,15 +39,13 @@ struct DevParams {
 struct RoundState {
   int n_lost;
   int remaining;       // pending blocks at the start of the current round
-  int remaining_acc;   // pending count accumulated by the finalize kernel
-  int nq;              // pending blocks with |m0| >= r B
-  int maxm0;           // largest |m0| among pending blocks
   int round;           // current round, 1-based
   int err;
-  int done_wgs;        // finalize: workgroups finished
-  unsigned long long n_avail;
+  unsigned long long n_avail;     // fill: known pixels and their sum
   unsigned long long sum_avail;
 };
+
+constexpr int kPrepGridMax = 512;   // workgroups of the prep kernel (slots in `part`)
 
 // bstate values: 0 pending, > 0 concealed in that round, kNeedHql + round:
 // waiting for the HQL kernels in that round.
@@ -54,11 +55,14 @@ struct FrameArgs {
   const uint8_t* frame;
   const uint8_t* mask;
   uint8_t* work;          // output plane (caller's out), same stride
-  uint8_t* avail;         // workspace plane, pitch = width
+  int16_t* val;           // workspace plane, pitch = width: pixel value where
+                          // known (received or concealed in an earlier round),
+                          // -1 where still lost
   uint8_t* cell_lost;     // gh * gw
   int* blk;               // lost cell indices, raster order
   int* bstate;
   int* m0cnt;
+  int* part;              // 2 * kPrepGridMax prep partials
   RoundState* st;
   skm_block_info* info;   // optional
   float* xhat;            // optional
@@ -79,6 +83,7 @@ hipError_t launch_fill(const FrameArgs& a, const DevParams& p, int max_blocks,
 hipError_t launch_dist(const FrameArgs& a, const DevParams& p, int max_blocks,
                        hipStream_t s);
 hipError_t set_main_lds_limit(size_t bytes);
+int prep_grid_for(int max_blocks);
 size_t main_lds_bytes(const DevParams& p);
 
 }  // namespace skm

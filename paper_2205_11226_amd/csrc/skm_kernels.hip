@@ -12,6 +12,7 @@
 //   normalisation factor nu        eq. factor (raw weight sum, negative exponent)
 //   support-area expansion         Sec. "Intermediate dynamic layer"
 //   profile gate                   Sec. "SK-MMSE profiles"
+//   transfer of estimates into S   end of Sec. "K-MMSE overview"
 #include <math.h>
 
 #include "skm_internal.h"
@@ -39,9 +40,14 @@ __device__ __forceinline__ int wave_min(int v) {
   for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
   return v;
 }
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
 
-// Merge two (max, sum of exp(x - max)) pairs.  Order-fixed callers make the
-// result deterministic.
+// Merge (m2, s2) into (m, s), both "max and sum of exp(x - max)".  Callers fix
+// the merge order, so results are deterministic.
 __device__ __forceinline__ void lse_merge(double& m, double& s, double m2, double s2) {
   if (m2 == -INFINITY) return;
   if (m == -INFINITY) { m = m2; s = s2; return; }
@@ -49,69 +55,58 @@ __device__ __forceinline__ void lse_merge(double& m, double& s, double m2, doubl
   else        { s = s + s2 * exp(m2 - m); }
 }
 
-__device__ __forceinline__ void wave_lse(double& m, double& s) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    double m2 = __shfl_xor(m, o, 64);
-    double s2 = __shfl_xor(s, o, 64);
-    // both partners must compute the same merge irrespective of role:
-    // merge in lane order (lower lane first) so that the result is symmetric.
-    bool lower = (lane_id() & o) == 0;
-    double ma = lower ? m : m2, sa = lower ? s : s2;
-    double mb = lower ? m2 : m, sb = lower ? s2 : s;
-    lse_merge(ma, sa, mb, sb);
-    m = ma; s = sa;
-  }
+// 128-bit logical right shift of (lo, hi), 0 <= s < 128
+__device__ __forceinline__ void shr128(uint64_t lo, uint64_t hi, int s, uint64_t& olo, uint64_t& ohi) {
+  if (s == 0) { olo = lo; ohi = hi; }
+  else if (s < 64) { olo = (lo >> s) | (hi << (64 - s)); ohi = hi >> s; }
+  else { olo = hi >> (s - 64); ohi = 0; }
+}
+
+__device__ __forceinline__ bool bit128(const uint64_t* w, int c) {
+  return c < 64 ? ((w[0] >> c) & 1ull) : ((w[1] >> (c - 64)) & 1ull);
 }
 
 // ---------------------------------------------------------- state / setup
 
 __global__ void k_zero_state(RoundState* st) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st->n_lost = 0; st->remaining = 0; st->remaining_acc = 0; st->nq = 0;
-    st->maxm0 = 0; st->round = 1; st->err = 0; st->done_wgs = 0;
+    st->n_lost = 0; st->remaining = 0; st->round = 1; st->err = 0;
     st->n_avail = 0; st->sum_avail = 0;
   }
 }
 
-// avail = mask == 0; work = avail ? frame : 128.  Lost pixels outside the full
-// cell grid are an error.  Counts the received pixels.
+// Loss geometry, one pass over the frame.  Grid (ceil(width/256), bands of B
+// rows); one thread per column of a band: copies received pixels to `work`
+// (lost ones become 128 and are never read), writes the value plane (-1 =
+// lost), and the B lanes of one cell vote whether the cell is wholly lost.  A
+// lost pixel outside the full-cell grid, or a partly lost cell, is an error.
 __global__ __launch_bounds__(kThreads) void k_init(FrameArgs a, DevParams p) {
-  const long long npx = (long long)p.width * p.height;
-  const int gxB = p.gw * p.B, gyB = p.gh * p.B;
-  unsigned long long cnt = 0;
-  int bad = 0;
-  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < npx;
-       idx += (long long)gridDim.x * blockDim.x) {
-    int y = (int)(idx / p.width), x = (int)(idx - (long long)y * p.width);
-    size_t off = (size_t)y * p.stride + x;
-    bool lost = a.mask[off] != 0;
-    uint8_t v = lost ? (uint8_t)128 : a.frame[off];
-    a.work[off] = v;
-    a.avail[idx] = lost ? 0 : 1;
-    cnt += lost ? 0 : 1;
-    if (lost && (x >= gxB || y >= gyB)) bad = 1;
+  const int x = blockIdx.x * kThreads + threadIdx.x;
+  const int band = blockIdx.y;
+  const int B = p.B;
+  const int y0 = band * B;
+  const int rows = min(B, p.height - y0);
+  int nl = 0;
+  if (x < p.width) {
+    for (int i = 0; i < rows; ++i) {
+      const int y = y0 + i;
+      const size_t off = (size_t)y * p.stride + x;
+      const bool lost = a.mask[off] != 0;
+      const uint8_t v = a.frame[off];
+      a.work[off] = lost ? (uint8_t)128 : v;
+      a.val[(size_t)y * p.width + x] = lost ? (int16_t)-1 : (int16_t)v;
+      nl += lost;
+    }
   }
-  cnt = wave_sum(cnt);
-  bad = wave_max(bad);
-  if (lane_id() == 0) {
-    if (cnt) atomicAdd(&a.st->n_avail, cnt);
-    if (bad) atomicOr(&a.st->err, kErrPartial);
+  const bool in_cells = band < p.gh && x < p.gw * B;
+  int bad = (nl > 0 && !in_cells) ? 1 : 0;
+  int v = nl;
+  for (int o = 1; o < B; o <<= 1) v += __shfl_xor(v, o, 64);   // cells never straddle waves
+  if (in_cells && (lane_id() & (B - 1)) == 0) {
+    a.cell_lost[band * p.gw + x / B] = (v == B * B) ? 1 : 0;
+    if (v != 0 && v != B * B) bad = 1;
   }
-}
-
-// one thread per full cell: lost iff every pixel is lost; partly lost = error
-__global__ __launch_bounds__(kThreads) void k_cells(FrameArgs a, DevParams p) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= p.gh * p.gw) return;
-  int by = c / p.gw, bx = c - by * p.gw;
-  int n = 0;
-  for (int i = 0; i < p.B; ++i) {
-    const uint8_t* row = a.mask + (size_t)(by * p.B + i) * p.stride + bx * p.B;
-    for (int j = 0; j < p.B; ++j) n += row[j] != 0;
-  }
-  a.cell_lost[c] = n == p.B * p.B;
-  if (n != 0 && n != p.B * p.B) atomicOr(&a.st->err, kErrPartial);
+  if (__ballot(bad != 0) != 0ull && lane_id() == 0) atomicOr(&a.st->err, kErrPartial);
 }
 
 // single workgroup of 1024: ordered compaction of lost cells
@@ -125,8 +120,7 @@ __global__ __launch_bounds__(1024) void k_compact(FrameArgs a, DevParams p) {
   for (int c = c0; c < c1; ++c) n += a.cell_lost[c];
   s_cnt[tid] = n;
   __syncthreads();
-  // Hillis-Steele inclusive scan
-  for (int o = 1; o < 1024; o <<= 1) {
+  for (int o = 1; o < 1024; o <<= 1) {     // Hillis-Steele inclusive scan
     int v = tid >= o ? s_cnt[tid - o] : 0;
     __syncthreads();
     s_cnt[tid] += v;
@@ -148,114 +142,143 @@ __global__ __launch_bounds__(1024) void k_compact(FrameArgs a, DevParams p) {
 }
 
 // ------------------------------------------------------------- round prep
-// one wave per pending block: |m0| = known in-frame ring pixels
+// One wave per pending block: |m0| = known in-frame ring pixels.  Each
+// workgroup publishes (blocks with |m0| >= r B, largest |m0|) in its own
+// slot of `part`; the estimation kernel reduces the slots.  No atomics.
 __global__ __launch_bounds__(kThreads) void k_round_prep(FrameArgs a, DevParams p) {
+  __shared__ int s_nq[kThreads / 64], s_mx[kThreads / 64];
   RoundState* st = a.st;
   if (st->remaining == 0) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) { st->remaining_acc = 0; st->done_wgs = 0; }
   const int n_lost = st->n_lost;
-  const int nwaves = gridDim.x * (blockDim.x / 64);
-  const int F = p.F;
-  for (int i = blockIdx.x * (blockDim.x / 64) + wave_id(); i < n_lost; i += nwaves) {
+  const int lane = lane_id(), wave = wave_id();
+  const int F = p.F, B = p.B, r = p.r;
+  int my_nq = 0, my_mx = 0;
+  for (int i = blockIdx.x * (kThreads / 64) + wave; i < n_lost; i += gridDim.x * (kThreads / 64)) {
     if (a.bstate[i] != 0) continue;
-    int cell = a.blk[i];
-    int by = cell / p.gw, bx = cell - by * p.gw;
-    int x0 = bx * p.B - p.r, y0 = by * p.B - p.r;
+    const int cell = a.blk[i];
+    const int by = cell / p.gw, bx = cell - by * p.gw;
+    const int xr = bx * B - r, yr = by * B - r;
     int c = 0;
-    for (int pos = lane_id(); pos < F * F; pos += 64) {
-      int fy = pos / F, fx = pos - fy * F;
-      bool ring = fy < p.r || fy >= p.r + p.B || fx < p.r || fx >= p.r + p.B;
-      int gy = y0 + fy, gx = x0 + fx;
-      if (ring && gy >= 0 && gy < p.height && gx >= 0 && gx < p.width)
-        c += a.avail[(size_t)gy * p.width + gx];
+#pragma unroll
+    for (int fy0 = 0; fy0 < 2 * kMaxB; fy0 += 2) {     // two footprint rows per step, F <= 32
+      const int fy = fy0 + (lane >> 5), fx = lane & 31;
+      const int gy = yr + fy, gx = xr + fx;
+      const bool use = fy < F && fx < F && (fy < r || fy >= r + B || fx < r || fx >= r + B) &&
+                       gy >= 0 && gy < p.height && gx >= 0 && gx < p.width;
+      const int cy = min(max(gy, 0), p.height - 1), cx = min(max(gx, 0), p.width - 1);
+      const int16_t v = a.val[(size_t)cy * p.width + cx];
+      c += (use && v >= 0) ? 1 : 0;
     }
     c = wave_sum(c);
-    if (lane_id() == 0) {
+    if (lane == 0) {
       a.m0cnt[i] = c;
-      if (c >= p.r * p.B) atomicAdd(&st->nq, 1);
-      atomicMax(&st->maxm0, c);
+      my_nq += c >= r * B;
+      my_mx = max(my_mx, c);
     }
+  }
+  if (lane == 0) { s_nq[wave] = my_nq; s_mx[wave] = my_mx; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int nq = 0, mx = 0;
+    for (int w = 0; w < kThreads / 64; ++w) { nq += s_nq[w]; mx = max(mx, s_mx[w]); }
+    a.part[2 * blockIdx.x] = nq;
+    a.part[2 * blockIdx.x + 1] = mx;
   }
 }
 
 // ----------------------------------------------------------- main kernel
+//
+// LDS carve-up (dynamic), for one block at a time.  MC bounds the number of
+// admissible candidates: a prototype can never overlap the block itself, so
+// MC = (2W+1)^2 - (2 min(B-1, W) + 1)^2.  NU counts ring "units": horizontally
+// adjacent pairs of ring pixels, or a single pixel with a dummy partner.
+//   ell     f64 [MC]      log raw IDL weight of each candidate, -inf if dropped
+//   cand    u32 [MC]      admissible candidates in raster order:
+//                         window offset | bucket << 16 | radius << 24
+//   selw    f32 [MC]      FP32 weights exp(ell - max) of the selected candidates
+//   selo    u16 [MC]      their window offsets
+//   qu      u32x2 [NU]    per unit: packed int16 context pair, footprint offset
+//   utab    u32 [NU]      fixed unit table: footprint offset | single << 16
+//   rowbits u64 [Wd][2]   availability bits of each window row
+//   runbits u64 [Wd][2]   bit c set iff columns c .. c+B-1 are all available
+//   cmask   u64 [D2][2]   bit dx of displacement row dy set iff the B x B
+//                         prototype at (dy, dx) is admissible
+//   winp    u32 [Wd*Wd]   window pixel pairs: int16 pixel | next pixel << 16,
+//                         -1 = unknown (lost or out of frame)
 
 struct MainLds {
-  double* ell;          // [ND] log raw weight, -inf if not admissible
-  uint64_t* rowbits;    // [Wd*2] availability bits of each window row
-  int* dval;            // [ND] distance (reused as float weights)
-  uint32_t* q;          // [F*F] query ring: offset | value << 16
-  uint16_t* list;       // [ND] admissible-prototype displacement indices
-  uint16_t* nval;       // [ND] overlap counts
-  int16_t* win;         // [Wd*Wd] window pixels, -1 = unknown
+  double* ell;
+  uint32_t* cand;
+  float* selw;
+  uint16_t* selo;
+  uint2* qu;
+  uint32_t* utab;
+  uint64_t* rowbits;
+  uint64_t* runbits;
+  uint64_t* cmask;
+  uint32_t* winp;
 };
 
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 __host__ __device__ inline size_t main_lds_layout(const DevParams& p, size_t* offs) {
+  const size_t D2 = 2 * p.W + 1;
   size_t o = 0;
-  offs[0] = o; o = align_up(o + sizeof(double) * p.ND, 16);
-  offs[1] = o; o = align_up(o + sizeof(uint64_t) * p.Wd * 2, 16);
-  offs[2] = o; o = align_up(o + sizeof(int) * p.ND, 16);
-  offs[3] = o; o = align_up(o + sizeof(uint32_t) * p.F * p.F, 16);
-  offs[4] = o; o = align_up(o + sizeof(uint16_t) * p.ND, 16);
-  offs[5] = o; o = align_up(o + sizeof(uint16_t) * p.ND, 16);
-  offs[6] = o; o = align_up(o + sizeof(int16_t) * p.Wd * p.Wd, 16);
+  offs[0] = o; o = align_up(o + sizeof(double) * p.MC, 16);
+  offs[1] = o; o = align_up(o + sizeof(uint32_t) * p.MC, 16);
+  offs[2] = o; o = align_up(o + sizeof(float) * p.MC, 16);
+  offs[3] = o; o = align_up(o + sizeof(uint16_t) * p.MC, 16);
+  offs[4] = o; o = align_up(o + sizeof(uint2) * p.NR, 16);
+  offs[5] = o; o = align_up(o + sizeof(uint32_t) * p.NR, 16);
+  offs[6] = o; o = align_up(o + sizeof(uint64_t) * 2 * p.Wd, 16);
+  offs[7] = o; o = align_up(o + sizeof(uint64_t) * 2 * p.Wd, 16);
+  offs[8] = o; o = align_up(o + sizeof(uint64_t) * 2 * D2, 16);
+  offs[9] = o; o = align_up(o + sizeof(uint32_t) * p.Wd * p.Wd, 16);
   return o;
 }
 
 size_t main_lds_bytes(const DevParams& p) {
-  size_t offs[8];
+  size_t offs[10];
   return main_lds_layout(p, offs);
 }
 
-// B consecutive availability bits of window row `row` starting at column c
-__device__ __forceinline__ bool row_run_ok(const uint64_t* rb, int row, int c, int B) {
-  uint64_t lo = rb[2 * row], hi = rb[2 * row + 1];
-  uint64_t v = c == 0 ? lo : (c < 64 ? (lo >> c) | (hi << (64 - c)) : hi >> (c - 64));
-  uint64_t m = (B >= 64) ? ~0ull : ((1ull << B) - 1ull);
-  return (v & m) == m;
-}
-
-__device__ __forceinline__ int block_sum_int(int v, int* s_red) {
-  v = wave_sum(v);
-  __syncthreads();
-  if (lane_id() == 0) s_red[wave_id()] = v;
-  __syncthreads();
-  int t = s_red[0] + s_red[1] + s_red[2] + s_red[3];
-  return t;
-}
-
-__device__ __forceinline__ double block_sum_double(double v, double* s_red) {
-  v = wave_sum(v);
-  __syncthreads();
-  if (lane_id() == 0) s_red[wave_id()] = v;
-  __syncthreads();
-  return ((s_red[0] + s_red[1]) + s_red[2]) + s_red[3];
-}
-
-__device__ __forceinline__ void block_lse(double& m, double& s, double* s_m, double* s_s) {
-  wave_lse(m, s);
-  __syncthreads();
-  if (lane_id() == 0) { s_m[wave_id()] = m; s_s[wave_id()] = s; }
-  __syncthreads();
-  m = s_m[0]; s = s_s[0];
-  for (int w = 1; w < kThreads / 64; ++w) lse_merge(m, s, s_m[w], s_s[w]);
-}
-
-// Per-block scratch shared by the whole workgroup.
 struct BlockShared {
-  int n0, phi, sum;
-  int M;                      // admissible-prototype candidates
+  int NU, M, n_sel;
   int layer, radius_idx, flags, n_cand, n_complete;
-  double lnu;
-  int red_i[4];
-  double red_d[4], red_m[4], red_s[4];
-  double lse_m[kMaxRadii], lse_s[kMaxRadii];
-  int lse_c[kMaxRadii];
-  int scan[kThreads];
+  double lnu, mstar, den;
+  int red_i[kThreads / 64][4];
+  int scan[kThreads / 64];
+  int rowbase[2 * kMaxWin + 1];
+  unsigned long long bmax[kMaxRadii];
+  int bcnt[kMaxRadii];
+  double cm[kMaxRadii];
+  double ps[kThreads / 64][kMaxRadii];
+  int bucket_of[kMaxWin + 1];
   double part[kThreads];
 };
+
+typedef short short2v __attribute__((ext_vector_type(2)));
+
+// exclusive scan of one int per thread over the workgroup (fixed order)
+__device__ __forceinline__ int block_excl_scan(int v, int* s_w, int* total) {
+  const int lane = lane_id(), wave = wave_id();
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_w[wave] = x;
+  __syncthreads();
+  int base = 0, tot = 0;
+  for (int w = 0; w < kThreads / 64; ++w) {
+    if (w < wave) base += s_w[w];
+    tot += s_w[w];
+  }
+  *total = tot;
+  __syncthreads();
+  return base + x - v;
+}
 
 __device__ void write_info(const FrameArgs& a, int i, int bx, int by, int layer, int round,
                            int n_cand, int n_complete, int radius, int flags, int phi,
@@ -268,37 +291,113 @@ __device__ void write_info(const FrameArgs& a, int i, int bx, int by, int layer,
   a.info[i] = inf;
 }
 
+__device__ void write_const_block(const FrameArgs& a, const DevParams& p, int i, int x0, int y0,
+                                  double v) {
+  const int B2 = p.B * p.B;
+  const uint8_t u = (uint8_t)fmin(fmax(floor(v + 0.5), 0.0), 255.0);
+  for (int pix = threadIdx.x; pix < B2; pix += kThreads) {
+    const int py = pix / p.B, px = pix - py * p.B;
+    a.work[(size_t)(y0 + py) * p.stride + x0 + px] = u;
+    if (a.xhat && i < a.cap) a.xhat[(size_t)i * B2 + pix] = (float)v;
+  }
+}
+
+// Sum of (q - p)^2 over both halves of two packed int16 pairs where neither
+// half is negative (unknown), and the count of such halves, accumulated.
+__device__ __forceinline__ void pair_dist(uint32_t q, uint32_t pp, int& d, uint32_t& nacc) {
+  const short2v qa = __builtin_bit_cast(short2v, q), pa = __builtin_bit_cast(short2v, pp);
+  const short2v sgn = (qa | pa) >> (short2v){15, 15};          // 0xffff where unknown
+  const uint32_t bad = __builtin_bit_cast(uint32_t, sgn);
+  const uint32_t df = __builtin_bit_cast(uint32_t, (short2v)(qa - pa)) & ~bad;
+  d = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, df), __builtin_bit_cast(short2v, df), d,
+                             false);
+  nacc += ~bad & 0x00010001u;
+}
+
 __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams p, int dist_only) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ BlockShared sh;
   RoundState* st = a.st;
   const int remaining = st->remaining;
   if (remaining == 0) return;
-  const int n_lost = st->n_lost, nq = st->nq, maxm0 = st->maxm0, round = st->round;
+  const int n_lost = st->n_lost, round = st->round;
+  // context-size gate of the round, from the prep kernel's per-workgroup partials
+  int nq = 0, maxm0 = 0;
+  for (int g = threadIdx.x; g < p.prep_grid; g += kThreads) {
+    nq += a.part[2 * g];
+    maxm0 = max(maxm0, a.part[2 * g + 1]);
+  }
+  nq = wave_sum(nq);
+  maxm0 = wave_max(maxm0);
+  if (lane_id() == 0) { sh.red_i[wave_id()][0] = nq; sh.red_i[wave_id()][1] = maxm0; }
+  __syncthreads();
+  nq = 0; maxm0 = 0;
+  for (int w = 0; w < kThreads / 64; ++w) { nq += sh.red_i[w][0]; maxm0 = max(maxm0, sh.red_i[w][1]); }
   if (!dist_only && nq == 0 && maxm0 == 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&st->err, kErrNoContext);
     return;
   }
-  size_t offs[8];
+  size_t offs[10];
   main_lds_layout(p, offs);
   MainLds L;
   L.ell = (double*)(lds_raw + offs[0]);
-  L.rowbits = (uint64_t*)(lds_raw + offs[1]);
-  L.dval = (int*)(lds_raw + offs[2]);
-  L.q = (uint32_t*)(lds_raw + offs[3]);
-  L.list = (uint16_t*)(lds_raw + offs[4]);
-  L.nval = (uint16_t*)(lds_raw + offs[5]);
-  L.win = (int16_t*)(lds_raw + offs[6]);
+  L.cand = (uint32_t*)(lds_raw + offs[1]);
+  L.selw = (float*)(lds_raw + offs[2]);
+  L.selo = (uint16_t*)(lds_raw + offs[3]);
+  L.qu = (uint2*)(lds_raw + offs[4]);
+  L.utab = (uint32_t*)(lds_raw + offs[5]);
+  L.rowbits = (uint64_t*)(lds_raw + offs[6]);
+  L.runbits = (uint64_t*)(lds_raw + offs[7]);
+  L.cmask = (uint64_t*)(lds_raw + offs[8]);
+  L.winp = (uint32_t*)(lds_raw + offs[9]);
 
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
-  const int B = p.B, r = p.r, W = p.W, Wd = p.Wd, F = p.F, ND = p.ND, D2 = 2 * W + 1;
+  const int B = p.B, r = p.r, W = p.W, Wd = p.Wd, F = p.F, D2 = 2 * W + 1;
   const int B2 = B * B;
+  const int nw = kThreads / 64;
+  const int qbase = W * Wd + W;          // footprint origin of the block itself
+
+  // Fixed tables.  bucket_of: radius -> first schedule radius >= it.  utab:
+  // the ring pixels of each footprint row taken left to right in pairs of
+  // horizontal neighbours (a lone pixel gets a dummy partner); lane fy owns
+  // footprint row fy, a wave scan orders the rows.
+  if (tid <= W) {
+    int b = p.nrad - 1;
+    for (int ri = 0; ri < p.nrad; ++ri) if (p.radii[ri] >= tid) { b = ri; break; }
+    sh.bucket_of[tid] = b;
+  }
+  if (wave == 0) {
+    const int fy = lane;
+    const bool full = fy < r || fy >= r + B;
+    int cnt = 0;
+    if (fy < F) cnt = full ? (F + 1) / 2 : 2 * ((r + 1) / 2);
+    int x = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    int pos = x - cnt;
+    if (fy < F) {
+      if (full) {
+        for (int c = 0; c < F; c += 2)
+          L.utab[pos++] = (uint32_t)(fy * Wd + c) | ((uint32_t)(c + 1 >= F) << 16);
+      } else {
+        for (int c = 0; c < r; c += 2)
+          L.utab[pos++] = (uint32_t)(fy * Wd + c) | ((uint32_t)(c + 1 >= r) << 16);
+        for (int c = r + B; c < F; c += 2)
+          L.utab[pos++] = (uint32_t)(fy * Wd + c) | ((uint32_t)(c + 1 >= F) << 16);
+      }
+    }
+    if (lane == 63) sh.NU = x;
+  }
+  __syncthreads();
+  const int NU = sh.NU;
 
   for (int i = blockIdx.x; i < n_lost; i += gridDim.x) {
     if (a.bstate[i] != 0) continue;
     if (!dist_only) {
-      int m0c = a.m0cnt[i];
-      bool elig = nq > 0 ? (m0c >= r * B) : (m0c == maxm0);
+      const int m0c = a.m0cnt[i];
+      const bool elig = nq > 0 ? (m0c >= r * B) : (m0c == maxm0);
       if (!elig) continue;
     }
     const int cell = a.blk[i];
@@ -306,59 +405,82 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
     const int x0 = bx * B, y0 = by * B;
     const int ox = x0 - r - W, oy = y0 - r - W;
 
-    // 1. stage the search window (coalesced row reads)
-    for (int idx = tid; idx < Wd * Wd; idx += kThreads) {
-      int wy = idx / Wd, wx = idx - wy * Wd;
-      int gy = oy + wy, gx = ox + wx;
-      int v = -1;
-      if (gx >= 0 && gx < p.width && gy >= 0 && gy < p.height) {
-        if (a.avail[(size_t)gy * p.width + gx]) v = a.work[(size_t)gy * p.stride + gx];
+    // 1. stage the window, one wave per row and lanes along it, six rows of
+    //    loads in flight; pixel pairs by lane shuffle; row availability bits
+    for (int wy0 = wave; wy0 < Wd; wy0 += 6 * nw) {
+      int v0[6], v1[6];
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const int wy = wy0 + t * nw;
+        const int gy = oy + wy;
+        const int cy = min(max(gy, 0), p.height - 1);
+        const bool rowok = wy < Wd && gy >= 0 && gy < p.height;
+        const int gx0 = ox + lane, gx1 = ox + 64 + lane;
+        const int16_t r0 = a.val[(size_t)cy * p.width + min(max(gx0, 0), p.width - 1)];
+        const int16_t r1 = a.val[(size_t)cy * p.width + min(max(gx1, 0), p.width - 1)];
+        v0[t] = (rowok && lane < Wd && gx0 >= 0 && gx0 < p.width) ? r0 : -1;
+        v1[t] = (rowok && 64 + lane < Wd && gx1 >= 0 && gx1 < p.width) ? r1 : -1;
       }
-      L.win[idx] = (int16_t)v;
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const int wy = wy0 + t * nw;
+        const int n0 = __shfl_down(v0[t], 1, 64);
+        const int h0 = __shfl(v1[t], 0, 64);
+        const int n1 = __shfl_down(v1[t], 1, 64);
+        const int nx0 = lane == 63 ? h0 : n0;
+        const int nx1 = (lane == 63 || 64 + lane + 1 >= Wd) ? -1 : n1;
+        const int nxa = (lane + 1 >= Wd) ? -1 : nx0;
+        const uint64_t lo = __ballot(v0[t] >= 0), hi = __ballot(v1[t] >= 0);
+        if (wy < Wd) {
+          if (lane < Wd)
+            L.winp[wy * Wd + lane] = (uint32_t)(uint16_t)v0[t] | ((uint32_t)(uint16_t)nxa << 16);
+          if (64 + lane < Wd)
+            L.winp[wy * Wd + 64 + lane] = (uint32_t)(uint16_t)v1[t] | ((uint32_t)(uint16_t)nx1 << 16);
+          if (lane == 0) { L.rowbits[2 * wy] = lo; L.rowbits[2 * wy + 1] = hi; }
+        }
+      }
     }
     __syncthreads();
 
-    // 2. availability bitmask per window row; 3. context list (wave 0)
-    for (int row = wave; row < Wd; row += kThreads / 64) {
-      bool b0 = lane < Wd && L.win[row * Wd + lane] >= 0;
-      bool b1 = 64 + lane < Wd && L.win[row * Wd + 64 + lane] >= 0;
-      uint64_t lo = __ballot(b0), hi = __ballot(b1);
-      if (lane == 0) { L.rowbits[2 * row] = lo; L.rowbits[2 * row + 1] = hi; }
-    }
-    if (wave == 0) {
-      int n = 0, vmin = 255, vmax = 0, vsum = 0;
-      for (int base = 0; base < F * F; base += 64) {
-        int pos = base + lane;
-        int fy = pos / F, fx = pos - fy * F;
-        bool ring = pos < F * F && (fy < r || fy >= r + B || fx < r || fx >= r + B);
-        int v = ring ? L.win[(W + fy) * Wd + W + fx] : -1;
-        bool ok = v >= 0;
-        uint64_t m = __ballot(ok);
-        int rank = __popcll(m & ((1ull << lane) - 1ull));
-        if (ok) {
-          L.q[n + rank] = (uint32_t)(fy * Wd + fx) | ((uint32_t)v << 16);
-          vmin = min(vmin, v); vmax = max(vmax, v); vsum += v;
-        }
-        n += __popcll(m);
+    // 2. context units and ring statistics; horizontal B-runs by doubling
+    {
+      int c = 0, vmin = 255, vmax = 0, vsum = 0;
+      for (int u = tid; u < NU; u += kThreads) {
+        const uint32_t e = L.utab[u];
+        const int off = (int)(e & 0xffffu);
+        uint32_t qp = L.winp[qbase + off];
+        if (e >> 16) qp |= 0xffff0000u;
+        L.qu[u] = make_uint2(qp, (uint32_t)off);
+        const int va = (int)(int16_t)(qp & 0xffffu), vb = (int)(int16_t)(qp >> 16);
+        if (va >= 0) { ++c; vmin = min(vmin, va); vmax = max(vmax, va); vsum += va; }
+        if (vb >= 0) { ++c; vmin = min(vmin, vb); vmax = max(vmax, vb); vsum += vb; }
       }
-      vmin = wave_min(vmin); vmax = wave_max(vmax); vsum = wave_sum(vsum);
-      if (lane == 0) { sh.n0 = n; sh.phi = n > 0 ? vmax - vmin : 0; sh.sum = vsum; }
+      c = wave_sum(c); vmin = wave_min(vmin); vmax = wave_max(vmax); vsum = wave_sum(vsum);
+      if (lane == 0) { sh.red_i[wave][0] = c; sh.red_i[wave][1] = vmin; sh.red_i[wave][2] = vmax; sh.red_i[wave][3] = vsum; }
+    }
+    for (int row = tid; row < Wd; row += kThreads) {
+      uint64_t lo = L.rowbits[2 * row], hi = L.rowbits[2 * row + 1];
+      for (int s = 1; s < B; s <<= 1) {           // B is a power of two
+        uint64_t tlo, thi;
+        shr128(lo, hi, s, tlo, thi);
+        lo &= tlo; hi &= thi;
+      }
+      L.runbits[2 * row] = lo; L.runbits[2 * row + 1] = hi;
     }
     __syncthreads();
-    const int n0 = sh.n0, phi = sh.phi;
-    const double mean = n0 > 0 ? (double)sh.sum / (double)n0 : 0.0;
+    int n0 = 0, vmin = 255, vmax = 0, vsum = 0;
+    for (int w = 0; w < nw; ++w) {
+      n0 += sh.red_i[w][0]; vmin = min(vmin, sh.red_i[w][1]);
+      vmax = max(vmax, sh.red_i[w][2]); vsum += sh.red_i[w][3];
+    }
+    const int phi = n0 > 0 ? vmax - vmin : 0;
+    const double mean = n0 > 0 ? (double)vsum / (double)n0 : 0.0;
     const int relaxed_flag = (!dist_only && nq == 0) ? SKM_FLAG_CTX_RELAXED : 0;
 
     // BRL gate: context mean for every pixel of the block
     const bool profile_like = p.mode == SKM_MODE_PROFILE || p.mode == SKM_MODE_CNN;
     if (!dist_only && (p.mode == SKM_MODE_BRL || (profile_like && (double)phi <= p.t_phi))) {
-      for (int pix = tid; pix < B2; pix += kThreads) {
-        int py = pix / B, px = pix - py * B;
-        double v = floor(mean + 0.5);
-        v = fmin(fmax(v, 0.0), 255.0);
-        a.work[(size_t)(y0 + py) * p.stride + x0 + px] = (uint8_t)v;
-        if (a.xhat && i < a.cap) a.xhat[(size_t)i * B2 + pix] = (float)mean;
-      }
+      write_const_block(a, p, i, x0, y0, mean);
       if (tid == 0) {
         write_info(a, i, bx, by, SKM_LAYER_BRL, round, -1, -1, 0, relaxed_flag, phi, n0, NAN);
         a.bstate[i] = round;
@@ -367,134 +489,180 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
       continue;
     }
 
-    // 4. admissible prototypes (in frame, fully received), raster order
-    {
-      const int center = ND / 2;
-      const int chunk = (ND + kThreads - 1) / kThreads;
-      const int t0 = min(ND, tid * chunk), t1 = min(ND, t0 + chunk);
-      int cnt = 0;
-      for (int t = t0; t < t1; ++t) {
-        if (t == center) continue;
-        int dy = t / D2 - W, dx = t - (t / D2) * D2 - W;
-        int wy = W + r + dy, wx = W + r + dx;
-        bool ok = true;
-        for (int k = 0; k < B && ok; ++k) ok = row_run_ok(L.rowbits, wy + k, wx, B);
-        cnt += ok;
-      }
-      sh.scan[tid] = cnt;
-      __syncthreads();
-      for (int o = 1; o < kThreads; o <<= 1) {
-        int v = tid >= o ? sh.scan[tid - o] : 0;
-        __syncthreads();
-        sh.scan[tid] += v;
-        __syncthreads();
-      }
-      int pos = sh.scan[tid] - cnt;
-      for (int t = t0; t < t1; ++t) {
-        if (t == center) continue;
-        int dy = t / D2 - W, dx = t - (t / D2) * D2 - W;
-        int wy = W + r + dy, wx = W + r + dx;
-        bool ok = true;
-        for (int k = 0; k < B && ok; ++k) ok = row_run_ok(L.rowbits, wy + k, wx, B);
-        if (ok) L.list[pos++] = (uint16_t)t;
-      }
-      if (tid == kThreads - 1) sh.M = sh.scan[kThreads - 1];
-      __syncthreads();
+    // 3. admissible prototypes: vertical AND of B runs per displacement row,
+    //    shifted to displacement columns; row counts; row prefix
+    int rowcnt = 0;
+    if (tid < D2) {
+      uint64_t lo = ~0ull, hi = ~0ull;
+      for (int k = 0; k < B; ++k) { lo &= L.runbits[2 * (r + tid + k)]; hi &= L.runbits[2 * (r + tid + k) + 1]; }
+      uint64_t mlo, mhi;
+      shr128(lo, hi, r, mlo, mhi);
+      if (D2 < 64) { mlo &= (1ull << D2) - 1ull; mhi = 0; }
+      else { mhi &= (D2 >= 128) ? ~0ull : ((1ull << (D2 - 64)) - 1ull); }
+      if (tid == W) mlo &= ~(1ull << W);          // W < 64: the block itself
+      L.cmask[2 * tid] = mlo; L.cmask[2 * tid + 1] = mhi;
+      rowcnt = __popcll(mlo) + __popcll(mhi);
     }
-    const int M = sh.M;
-
-    // 5. exact integer distances over the ring pixels known in both rings
-    const int nmin = max(1, (p.min_pct * n0 + 99) / 100);
-    const double inv2s = 2.0 * p.sigma2;
-    for (int j = tid; j < M; j += kThreads) {
-      int t = L.list[j];
-      int dy = t / D2 - W, dx = t - (t / D2) * D2 - W;
-      int base = (W + dy) * Wd + (W + dx);
-      int d = 0, n = 0;
-      for (int k = 0; k < n0; ++k) {
-        uint32_t qq = L.q[k];
-        int pv = L.win[base + (int)(qq & 0xffffu)];
-        if (pv >= 0) {
-          int df = (int)(qq >> 16) - pv;
-          d += df * df;
-          ++n;
+    {
+      int tot = 0;
+      const int rb = block_excl_scan(rowcnt, sh.scan, &tot);   // barriers inside
+      if (tid < D2) sh.rowbase[tid] = rb;
+      if (tid == 0) sh.M = tot;
+    }
+    if (tid < p.nrad) { sh.bmax[tid] = 0xFFF0000000000000ull; sh.bcnt[tid] = 0; }
+    __syncthreads();
+    for (int dyi = wave; dyi < D2; dyi += nw) {
+      const uint64_t mlo = L.cmask[2 * dyi], mhi = L.cmask[2 * dyi + 1];
+      const int base = sh.rowbase[dyi];
+      const int ady = abs(dyi - W);
+      for (int dxi = lane; dxi < D2; dxi += 64) {
+        const bool ok = dxi < 64 ? ((mlo >> dxi) & 1ull) : ((mhi >> (dxi - 64)) & 1ull);
+        if (ok) {
+          const int rank = dxi < 64 ? __popcll(mlo & ((1ull << dxi) - 1ull))
+                                    : __popcll(mlo) + __popcll(mhi & ((1ull << (dxi - 64)) - 1ull));
+          const int rho = max(ady, abs(dxi - W));
+          L.cand[base + rank] = (uint32_t)(dyi * Wd + dxi) | ((uint32_t)sh.bucket_of[rho] << 16) |
+                                ((uint32_t)rho << 24);
         }
       }
-      bool ok = n >= nmin;
-      L.dval[j] = ok ? d : -1;
-      L.nval[j] = (uint16_t)n;
-      L.ell[j] = ok ? -((double)d / (double)n) / inv2s : -INFINITY;
     }
     __syncthreads();
+    const int M = sh.M;
 
+    // 4. exact integer distances over the ring pixels known in both rings,
+    //    two pixels per step: packed int16 difference, masked, v_dot2
+    const int nmin = max(1, (p.min_pct * n0 + 99) / 100);
+    const double two_s2 = 2.0 * p.sigma2;
+    int nc = 0, ncomp = 0;
+    for (int j = tid; j < M; j += kThreads) {
+      const uint32_t cj = L.cand[j];
+      const int base = (int)(cj & 0xffffu);
+      int d = 0;
+      uint32_t nacc = 0;
+      int u = 0;
+      for (; u + 8 <= NU; u += 8) {
+        uint2 qq[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) qq[t] = L.qu[u + t];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) pair_dist(qq[t].x, L.winp[base + (int)qq[t].y], d, nacc);
+      }
+      for (; u < NU; ++u) {
+        const uint2 qq = L.qu[u];
+        pair_dist(qq.x, L.winp[base + (int)qq.y], d, nacc);
+      }
+      const int n = (int)(nacc & 0xffffu) + (int)(nacc >> 16);
+      const bool ok = n >= nmin;
+      nc += ok;
+      ncomp += ok && n == n0;
+      const double e = ok ? -((double)d / (double)n) / two_s2 : -INFINITY;
+      L.ell[j] = e;
+      if (ok) {
+        const int b = (int)((cj >> 16) & 0xffu);
+        atomicMin(&sh.bmax[b], (unsigned long long)__double_as_longlong(e));
+        atomicAdd(&sh.bcnt[b], 1);
+      }
+      if (dist_only) {
+        const int t = (base / Wd) * D2 + (base % Wd);
+        a.dist[(size_t)i * p.ND + t] = ok ? d : -1;
+        a.cnt[(size_t)i * p.ND + t] = ok ? n : 0;
+      }
+    }
     if (dist_only) {
-      int* drow = a.dist + (size_t)i * ND;
-      int* crow = a.cnt + (size_t)i * ND;
-      for (int t = tid; t < ND; t += kThreads) { drow[t] = -1; crow[t] = 0; }
-      __syncthreads();
-      for (int j = tid; j < M; j += kThreads) {
-        if (L.dval[j] >= 0) { drow[L.list[j]] = L.dval[j]; crow[L.list[j]] = L.nval[j]; }
+      // displacements without an admissible prototype
+      for (int t = tid; t < p.ND; t += kThreads) {
+        const int dyi = t / D2, dxi = t - dyi * D2;
+        const uint64_t w = dxi < 64 ? L.cmask[2 * dyi] : L.cmask[2 * dyi + 1];
+        const bool adm = (w >> (dxi & 63)) & 1ull;
+        if (!adm) { a.dist[(size_t)i * p.ND + t] = -1; a.cnt[(size_t)i * p.ND + t] = 0; }
       }
       __syncthreads();
       continue;
     }
+    nc = wave_sum(nc);
+    ncomp = wave_sum(ncomp);
+    if (lane == 0) { sh.red_i[wave][0] = nc; sh.red_i[wave][1] = ncomp; }
+    __syncthreads();
 
-    // 6. candidate counts and log nu(rho) for every expansion radius
-    {
-      int nc = 0, ncomp = 0;
-      for (int j = tid; j < M; j += kThreads) {
-        if (L.dval[j] >= 0) { ++nc; ncomp += (L.nval[j] == n0); }
+    // 5. log nu per expansion radius.  Bucket maxima came from order-free
+    //    atomic minima of the (negative) bit patterns; cm[b] is their running
+    //    maximum over buckets <= b.  Each candidate adds exp(ell - cm[b_j]) to
+    //    its bucket (register accumulators, then wave sums in fixed order);
+    //    lane b of wave 0 combines the buckets up to b.
+    if (wave == 0) {
+      double m = lane < p.nrad ? __longlong_as_double((long long)sh.bmax[lane]) : -INFINITY;
+#pragma unroll
+      for (int o = 1; o < kMaxRadii; o <<= 1) {
+        const double y = __shfl_up(m, o, 64);
+        if (lane >= o) m = fmax(m, y);
       }
-      nc = block_sum_int(nc, sh.red_i);
-      ncomp = block_sum_int(ncomp, sh.red_i);
-      for (int ri = 0; ri < p.nrad; ++ri) {
-        const int R = p.radii[ri];
-        double m = -INFINITY, s = 0.0;
-        int c = 0;
-        for (int j = tid; j < M; j += kThreads) {
-          double e = L.ell[j];
-          if (e == -INFINITY) continue;
-          int t = L.list[j];
-          int dy = t / D2 - W, dx = t - (t / D2) * D2 - W;
-          if (max(abs(dx), abs(dy)) > R) continue;
-          lse_merge(m, s, e, 1.0);
-          ++c;
-        }
-        c = block_sum_int(c, sh.red_i);
-        block_lse(m, s, sh.red_m, sh.red_s);
-        if (tid == 0) { sh.lse_m[ri] = m; sh.lse_s[ri] = s; sh.lse_c[ri] = c; }
-      }
-      if (tid == 0) {
-        int layer = SKM_LAYER_IDL, ridx = p.nrad - 1, flags = relaxed_flag;
-        bool want_hql = false;
-        if (nc == 0) {
-          layer = SKM_LAYER_BRL;
-          flags |= SKM_FLAG_NO_CAND;
-        } else if (p.mode == SKM_MODE_PLAIN) {
-          ridx = p.nrad - 1;
-        } else if (p.mode == SKM_MODE_FULL) {
-          want_hql = true;
-        } else {  // PROFILE, IDL, CNN without a network
-          int acc = -1;
-          for (int ri = 0; ri < p.nrad; ++ri) {
-            if (sh.lse_c[ri] > 0) {
-              double lnu = sh.lse_m[ri] + log(sh.lse_s[ri]);
-              if (lnu >= p.log_tnu) { acc = ri; break; }
-            }
-          }
-          if (acc >= 0) ridx = acc;
-          else want_hql = p.mode != SKM_MODE_IDL;
-        }
-        if (want_hql) {
-          if (ncomp >= max(2, p.min_hql)) layer = SKM_LAYER_HQL;
-          else flags |= SKM_FLAG_NO_HQL;
-        }
-        sh.layer = layer; sh.radius_idx = ridx; sh.flags = flags;
-        sh.n_cand = nc; sh.n_complete = ncomp;
-        sh.lnu = nc > 0 ? sh.lse_m[ridx] + log(sh.lse_s[ridx]) : NAN;
-      }
-      __syncthreads();
+      if (lane < p.nrad) sh.cm[lane] = m;
     }
+    __syncthreads();
+    {
+      double acc[kMaxRadii];
+#pragma unroll
+      for (int b = 0; b < kMaxRadii; ++b) acc[b] = 0.0;
+      for (int j = tid; j < M; j += kThreads) {
+        const double e = L.ell[j];
+        if (e == -INFINITY) continue;
+        const int bj = (int)((L.cand[j] >> 16) & 0xffu);
+        const double t = exp(e - sh.cm[bj]);
+#pragma unroll
+        for (int b = 0; b < kMaxRadii; ++b) acc[b] += (b == bj) ? t : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < kMaxRadii; ++b) {
+        if (b < p.nrad) {
+          const double s = wave_sum(acc[b]);
+          if (lane == 0) sh.ps[wave][b] = s;
+        }
+      }
+    }
+    __syncthreads();
+    if (wave == 0) {
+      double cs = 0.0, lnu = -INFINITY;
+      int cc = 0;
+      const int b = lane;
+      if (b < p.nrad) {
+        const double mb = sh.cm[b];
+        for (int bb = 0; bb <= b; ++bb) {
+          const double sb = ((sh.ps[0][bb] + sh.ps[1][bb]) + sh.ps[2][bb]) + sh.ps[3][bb];
+          if (sb > 0.0) cs += sb * exp(sh.cm[bb] - mb);
+          cc += sh.bcnt[bb];
+        }
+        if (cc > 0) lnu = mb + log(cs);
+      }
+      const bool acc_ok = b < p.nrad && cc > 0 && lnu >= p.log_tnu;
+      const uint64_t accm = __ballot(acc_ok);
+      const int ncand = sh.red_i[0][0] + sh.red_i[1][0] + sh.red_i[2][0] + sh.red_i[3][0];
+      const int ncom = sh.red_i[0][1] + sh.red_i[1][1] + sh.red_i[2][1] + sh.red_i[3][1];
+      int layer = SKM_LAYER_IDL, ridx = p.nrad - 1, flags = relaxed_flag;
+      bool want_hql = false;
+      if (ncand == 0) {
+        layer = SKM_LAYER_BRL;
+        flags |= SKM_FLAG_NO_CAND;
+      } else if (p.mode == SKM_MODE_FULL) {
+        want_hql = true;
+      } else if (p.mode != SKM_MODE_PLAIN) {  // PROFILE, IDL, CNN without a network
+        if (accm) ridx = __ffsll((unsigned long long)accm) - 1;
+        else want_hql = p.mode != SKM_MODE_IDL;
+      }
+      if (want_hql) {
+        if (ncom >= max(2, p.min_hql)) layer = SKM_LAYER_HQL;
+        else flags |= SKM_FLAG_NO_HQL;
+      }
+      const double lnu_r = __shfl(lnu, ridx, 64);
+      const double cs_r = __shfl(cs, ridx, 64);
+      if (lane == 0) {
+        sh.layer = layer; sh.radius_idx = ridx; sh.flags = flags;
+        sh.n_cand = ncand; sh.n_complete = ncom;
+        sh.lnu = ncand > 0 ? lnu_r : NAN;
+        sh.mstar = sh.cm[ridx];
+        sh.den = cs_r;
+      }
+    }
+    __syncthreads();
     const int layer = sh.layer;
     if (layer == SKM_LAYER_HQL) {
       // HQL runs in the dense-algebra kernels after this one
@@ -507,12 +675,7 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
       continue;
     }
     if (layer == SKM_LAYER_BRL) {
-      for (int pix = tid; pix < B2; pix += kThreads) {
-        int py = pix / B, px = pix - py * B;
-        double v = fmin(fmax(floor(mean + 0.5), 0.0), 255.0);
-        a.work[(size_t)(y0 + py) * p.stride + x0 + px] = (uint8_t)v;
-        if (a.xhat && i < a.cap) a.xhat[(size_t)i * B2 + pix] = (float)mean;
-      }
+      write_const_block(a, p, i, x0, y0, mean);
       if (tid == 0) {
         write_info(a, i, bx, by, SKM_LAYER_BRL, round, sh.n_cand, sh.n_complete, 0, sh.flags,
                    phi, n0, sh.lnu);
@@ -522,60 +685,77 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
       continue;
     }
 
-    // 7. IDL: normalised weights over the accepted support area (eq. slpe)
+    // 6. IDL weights (eq. slpe) of the candidates inside the accepted radius,
+    //    compacted in raster order: thread t owns a contiguous slice
     const int ridx = sh.radius_idx;
-    const int R = p.radii[ridx];
-    const double mstar = sh.lse_m[ridx];
-    float* wv = reinterpret_cast<float*>(L.dval);
-    double wsum = 0.0;
-    for (int j = tid; j < M; j += kThreads) {
-      double e = L.ell[j];
-      float w = 0.f;
-      if (e != -INFINITY) {
-        int t = L.list[j];
-        int dy = t / D2 - W, dx = t - (t / D2) * D2 - W;
-        if (max(abs(dx), abs(dy)) <= R) w = expf((float)(e - mstar));
-      }
-      wv[j] = w;
-      wsum += (double)w;
-    }
-    const double den = block_sum_double(wsum, sh.red_d);   // also a barrier
-
-    // 8. weighted average of the prototypes, FP32 Kahan per pixel
+    const double mstar = sh.mstar;
     {
-      const int G = kThreads / B2 > 0 ? kThreads / B2 : 1;
-      const int g = tid / B2, pix = tid - g * B2;
-      const int py = pix / B, px = pix - py * B;
-      float acc = 0.f, comp = 0.f;
-      if (g < G) {
-        for (int j = g; j < M; j += G) {
-          float w = wv[j];
-          if (w == 0.f) continue;
-          int t = L.list[j];
-          int dy = t / D2 - W, dx = t - (t / D2) * D2 - W;
-          float xv = (float)L.win[(W + r + dy + py) * Wd + (W + r + dx + px)];
-          float y = w * xv - comp;
-          float tt = acc + y;
-          comp = (tt - acc) - y;
-          acc = tt;
+      const int per = (M + kThreads - 1) / kThreads;
+      const int j0 = min(M, tid * per), j1 = min(M, j0 + per);
+      int cnt = 0;
+      for (int j = j0; j < j1; ++j)
+        cnt += L.ell[j] != -INFINITY && (int)((L.cand[j] >> 16) & 0xffu) <= ridx;
+      int tot = 0;
+      int pos = block_excl_scan(cnt, sh.scan, &tot);
+      for (int j = j0; j < j1; ++j) {
+        const double e = L.ell[j];
+        if (e != -INFINITY && (int)((L.cand[j] >> 16) & 0xffu) <= ridx) {
+          L.selo[pos] = (uint16_t)(L.cand[j] & 0xffffu);
+          L.selw[pos] = expf((float)(e - mstar));
+          ++pos;
         }
       }
-      __syncthreads();
-      double* part = sh.part;
-      if (g < G) part[tid] = (double)acc - (double)comp;
+      if (tid == 0) sh.n_sel = tot;
+    }
+    __syncthreads();
+
+    // 7. weighted average of the prototypes: FP32 products, four independent
+    //    Kahan chains per pixel; groups of B*B threads split the candidates
+    //    when the block is small
+    {
+      const int nsel = sh.n_sel;
+      const int G = kThreads / B2;
+      const int g = tid / B2, pix = tid - g * B2;
+      const int py = pix / B, px = pix - py * B;
+      const int poff = (r + py) * Wd + (r + px);
+      float acc[4] = {0.f, 0.f, 0.f, 0.f}, comp[4] = {0.f, 0.f, 0.f, 0.f};
+      int j = g;
+      for (; j + 3 * G < nsel; j += 4 * G) {
+        int o[4];
+        float w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { o[u] = L.selo[j + u * G]; w[u] = L.selw[j + u * G]; }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float xv = (float)(int)(int16_t)(L.winp[o[u] + poff] & 0xffffu);
+          const float y = w[u] * xv - comp[u];
+          const float tt = acc[u] + y;
+          comp[u] = (tt - acc[u]) - y;
+          acc[u] = tt;
+        }
+      }
+      for (int u = 0; j < nsel; j += G, ++u) {
+        const float xv = (float)(int)(int16_t)(L.winp[(int)L.selo[j] + poff] & 0xffffu);
+        const float y = L.selw[j] * xv - comp[u & 3];
+        const float tt = acc[u & 3] + y;
+        comp[u & 3] = (tt - acc[u & 3]) - y;
+        acc[u & 3] = tt;
+      }
+      sh.part[tid] = (((double)acc[0] - (double)comp[0]) + ((double)acc[1] - (double)comp[1])) +
+                     (((double)acc[2] - (double)comp[2]) + ((double)acc[3] - (double)comp[3]));
       __syncthreads();
       if (g == 0) {
         double tot = 0.0;
-        for (int gg = 0; gg < G; ++gg) tot += part[gg * B2 + pix];
-        double xh = tot / den;
-        double v = fmin(fmax(floor(xh + 0.5), 0.0), 255.0);
-        a.work[(size_t)(y0 + py) * p.stride + x0 + px] = (uint8_t)v;
+        for (int gg = 0; gg < G; ++gg) tot += sh.part[gg * B2 + pix];
+        const double xh = tot / sh.den;
+        a.work[(size_t)(y0 + py) * p.stride + x0 + px] =
+            (uint8_t)fmin(fmax(floor(xh + 0.5), 0.0), 255.0);
         if (a.xhat && i < a.cap) a.xhat[(size_t)i * B2 + pix] = (float)xh;
       }
     }
     if (tid == 0) {
-      write_info(a, i, bx, by, SKM_LAYER_IDL, round, sh.n_cand, sh.n_complete, R, sh.flags,
-                 phi, n0, sh.lnu);
+      write_info(a, i, bx, by, SKM_LAYER_IDL, round, sh.n_cand, sh.n_complete, p.radii[ridx],
+                 sh.flags, phi, n0, sh.lnu);
       a.bstate[i] = round;
     }
     __syncthreads();
@@ -583,103 +763,115 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
 }
 
 // -------------------------------------------------------------- finalize
-// blocks concealed in this round become received; count what is pending
+// Blocks concealed in this round become known: their output pixels enter
+// the value plane.
 __global__ __launch_bounds__(kThreads) void k_round_finalize(FrameArgs a, DevParams p) {
-  __shared__ int s_pend;
   RoundState* st = a.st;
   if (st->remaining == 0) return;
   const int n_lost = st->n_lost, round = st->round;
-  if (threadIdx.x == 0) s_pend = 0;
-  __syncthreads();
   const int B = p.B, B2 = B * B;
   for (int i = blockIdx.x; i < n_lost; i += gridDim.x) {
-    int bs = a.bstate[i];
-    if (bs >= kNeedHql && threadIdx.x == 0) atomicOr(&st->err, kErrHqlPending);
-    if (bs == round) {
-      int cell = a.blk[i];
-      int by = cell / p.gw, bx = cell - by * p.gw;
-      for (int pix = threadIdx.x; pix < B2; pix += blockDim.x) {
-        int py = pix / B, px = pix - py * B;
-        a.avail[(size_t)(by * B + py) * p.width + bx * B + px] = 1;
-      }
-    } else if (bs == 0 && threadIdx.x == 0) {
-      ++s_pend;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (s_pend) atomicAdd(&st->remaining_acc, s_pend);
-    __threadfence();
-    int done = atomicAdd(&st->done_wgs, 1);
-    if (done == (int)gridDim.x - 1) {
-      __threadfence();
-      int rem = atomicAdd(&st->remaining_acc, 0);
-      st->remaining = rem;
-      st->nq = 0;
-      st->maxm0 = 0;
-      st->round = round + 1;
-      st->done_wgs = 0;
+    if (a.bstate[i] != round) continue;
+    const int cell = a.blk[i];
+    const int by = cell / p.gw, bx = cell - by * p.gw;
+    for (int pix = threadIdx.x; pix < B2; pix += blockDim.x) {
+      const int py = pix / B, px = pix - py * B;
+      const int y = by * B + py, x = bx * B + px;
+      a.val[(size_t)y * p.width + x] = (int16_t)a.work[(size_t)y * p.stride + x];
     }
   }
 }
 
+// single workgroup: pending blocks after the round, next round number
+__global__ __launch_bounds__(1024) void k_round_count(FrameArgs a, DevParams p) {
+  __shared__ int s_p[1024 / 64], s_h[1024 / 64];
+  RoundState* st = a.st;
+  if (st->remaining == 0) return;
+  const int n_lost = st->n_lost, round = st->round;
+  int pend = 0, hql = 0;
+  for (int i = threadIdx.x; i < n_lost; i += 1024) {
+    const int bs = a.bstate[i];
+    pend += bs == 0;
+    hql |= bs >= kNeedHql;
+  }
+  pend = wave_sum(pend);
+  hql = wave_max(hql);
+  if (lane_id() == 0) { s_p[wave_id()] = pend; s_h[wave_id()] = hql; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0, h = 0;
+    for (int w = 0; w < 1024 / 64; ++w) { t += s_p[w]; h |= s_h[w]; }
+    st->remaining = t;
+    st->round = round + 1;
+    if (h) st->err |= kErrHqlPending;
+  }
+}
+
 // ------------------------------------------------------------------- fill
-// after the round limit: context mean (or frame mean) for pending blocks
+// After the round limit: context mean (or frame mean) for pending blocks.
 
 __global__ void k_zero_fill(RoundState* st) {
   if (threadIdx.x == 0 && blockIdx.x == 0) { st->n_avail = 0; st->sum_avail = 0; }
 }
 
 __global__ __launch_bounds__(kThreads) void k_fill_stats(FrameArgs a, DevParams p) {
+  __shared__ unsigned long long s_c[kThreads / 64], s_s[kThreads / 64];
   RoundState* st = a.st;
   if (st->remaining == 0) return;
-  const long long npx = (long long)p.width * p.height;
   unsigned long long cnt = 0, sum = 0;
-  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < npx;
-       idx += (long long)gridDim.x * blockDim.x) {
-    int y = (int)(idx / p.width), x = (int)(idx - (long long)y * p.width);
-    if (a.avail[idx]) { ++cnt; sum += a.work[(size_t)y * p.stride + x]; }
+  for (int y = blockIdx.x; y < p.height; y += gridDim.x) {
+    for (int x = threadIdx.x; x < p.width; x += kThreads) {
+      const int v = a.val[(size_t)y * p.width + x];
+      if (v >= 0) { ++cnt; sum += (unsigned)v; }
+    }
   }
   cnt = wave_sum(cnt);
   sum = wave_sum(sum);
-  if (lane_id() == 0 && cnt) {
-    atomicAdd(&st->n_avail, cnt);
-    atomicAdd(&st->sum_avail, sum);
+  if (lane_id() == 0) { s_c[wave_id()] = cnt; s_s[wave_id()] = sum; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long c = 0, s = 0;
+    for (int w = 0; w < kThreads / 64; ++w) { c += s_c[w]; s += s_s[w]; }
+    if (c) { atomicAdd(&st->n_avail, c); atomicAdd(&st->sum_avail, s); }
   }
 }
 
+__device__ __forceinline__ int block_sum_int(int v, int* s_red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane_id() == 0) s_red[wave_id()] = v;
+  __syncthreads();
+  int t = 0;
+  for (int w = 0; w < kThreads / 64; ++w) t += s_red[w];
+  return t;
+}
+
 __global__ __launch_bounds__(kThreads) void k_fill(FrameArgs a, DevParams p) {
-  __shared__ int s_red[4];
+  __shared__ int s_red[kThreads / 64];
   RoundState* st = a.st;
   if (st->remaining == 0) return;
   const int n_lost = st->n_lost, round = st->round;
-  const int B = p.B, B2 = B * B, F = p.F, r = p.r;
+  const int B = p.B, F = p.F, r = p.r;
   const double fmean = st->n_avail ? (double)st->sum_avail / (double)st->n_avail : 0.0;
   for (int i = blockIdx.x; i < n_lost; i += gridDim.x) {
     if (a.bstate[i] != 0) continue;
-    int cell = a.blk[i];
-    int by = cell / p.gw, bx = cell - by * p.gw;
-    int xr = bx * B - r, yr = by * B - r;
+    const int cell = a.blk[i];
+    const int by = cell / p.gw, bx = cell - by * p.gw;
+    const int xr = bx * B - r, yr = by * B - r;
     int c = 0, s = 0;
     for (int pos = threadIdx.x; pos < F * F; pos += blockDim.x) {
-      int fy = pos / F, fx = pos - fy * F;
-      bool ring = fy < r || fy >= r + B || fx < r || fx >= r + B;
-      int gy = yr + fy, gx = xr + fx;
-      if (ring && gy >= 0 && gy < p.height && gx >= 0 && gx < p.width &&
-          a.avail[(size_t)gy * p.width + gx]) {
-        ++c;
-        s += a.work[(size_t)gy * p.stride + gx];
+      const int fy = pos / F, fx = pos - fy * F;
+      const bool ring = fy < r || fy >= r + B || fx < r || fx >= r + B;
+      const int gy = yr + fy, gx = xr + fx;
+      if (ring && gy >= 0 && gy < p.height && gx >= 0 && gx < p.width) {
+        const int v = a.val[(size_t)gy * p.width + gx];
+        if (v >= 0) { ++c; s += v; }
       }
     }
     c = block_sum_int(c, s_red);
     s = block_sum_int(s, s_red);
-    double v = c > 0 ? (double)s / (double)c : fmean;
-    for (int pix = threadIdx.x; pix < B2; pix += blockDim.x) {
-      int py = pix / B, px = pix - py * B;
-      a.work[(size_t)(by * B + py) * p.stride + bx * B + px] =
-          (uint8_t)fmin(fmax(floor(v + 0.5), 0.0), 255.0);
-      if (a.xhat && i < a.cap) a.xhat[(size_t)i * B2 + pix] = (float)v;
-    }
+    const double v = c > 0 ? (double)s / (double)c : fmean;
+    write_const_block(a, p, i, bx * B, by * B, v);
     if (threadIdx.x == 0) {
       write_info(a, i, bx, by, SKM_LAYER_FILL, round, -1, -1, 0,
                  c > 0 ? 0 : SKM_FLAG_EMPTY_CTX, 0, c, NAN);
@@ -691,32 +883,30 @@ __global__ __launch_bounds__(kThreads) void k_fill(FrameArgs a, DevParams p) {
 
 // -------------------------------------------------------------- launchers
 
-static int grid_for(long long work, int per) {
-  long long g = (work + per - 1) / per;
-  return (int)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
+static int clamp_grid(long long g, int hi) {
+  return (int)(g < 1 ? 1 : (g > hi ? hi : g));
 }
 
 hipError_t launch_init(const FrameArgs& a, const DevParams& p, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(64), 0, s, a.st);
-  hipLaunchKernelGGL(k_init, dim3(grid_for((long long)p.width * p.height, kThreads * 8)),
-                     dim3(kThreads), 0, s, a, p);
-  int ncell = p.gh * p.gw;
-  hipLaunchKernelGGL(k_cells, dim3(grid_for(ncell, kThreads)), dim3(kThreads), 0, s, a, p);
+  dim3 g((p.width + kThreads - 1) / kThreads, (p.height + p.B - 1) / p.B);
+  hipLaunchKernelGGL(k_init, g, dim3(kThreads), 0, s, a, p);
   hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, a, p);
   return hipGetLastError();
 }
 
-hipError_t launch_main(const FrameArgs& a, const DevParams& p, int max_blocks, int dist_only,
-                       hipStream_t s) {
-  size_t lds = main_lds_bytes(p);
-  int g = max_blocks < 1 ? 1 : (max_blocks > 2048 ? 2048 : max_blocks);
-  hipLaunchKernelGGL(k_round_main, dim3(g), dim3(kThreads), lds, s, a, p, dist_only);
+static hipError_t launch_main(const FrameArgs& a, const DevParams& p, int max_blocks,
+                              int dist_only, hipStream_t s) {
+  const size_t lds = main_lds_bytes(p);
+  hipLaunchKernelGGL(k_round_main, dim3(clamp_grid(max_blocks, 2048)), dim3(kThreads), lds, s, a,
+                     p, dist_only);
   return hipGetLastError();
 }
 
+int prep_grid_for(int max_blocks) { return clamp_grid((max_blocks + 3) / 4, kPrepGridMax); }
+
 hipError_t launch_prep(const FrameArgs& a, const DevParams& p, int max_blocks, hipStream_t s) {
-  int gw = grid_for(max_blocks, kThreads / 64);
-  hipLaunchKernelGGL(k_round_prep, dim3(gw), dim3(kThreads), 0, s, a, p);
+  hipLaunchKernelGGL(k_round_prep, dim3(p.prep_grid), dim3(kThreads), 0, s, a, p);
   return hipGetLastError();
 }
 
@@ -726,8 +916,9 @@ hipError_t launch_est(const FrameArgs& a, const DevParams& p, int max_blocks, hi
 
 hipError_t launch_finalize(const FrameArgs& a, const DevParams& p, int max_blocks,
                            hipStream_t s) {
-  int gf = max_blocks < 1 ? 1 : (max_blocks > 1024 ? 1024 : max_blocks);
-  hipLaunchKernelGGL(k_round_finalize, dim3(gf), dim3(kThreads), 0, s, a, p);
+  hipLaunchKernelGGL(k_round_finalize, dim3(clamp_grid(max_blocks, 2048)), dim3(kThreads), 0, s,
+                     a, p);
+  hipLaunchKernelGGL(k_round_count, dim3(1), dim3(1024), 0, s, a, p);
   return hipGetLastError();
 }
 
@@ -737,10 +928,8 @@ hipError_t launch_dist(const FrameArgs& a, const DevParams& p, int max_blocks, h
 
 hipError_t launch_fill(const FrameArgs& a, const DevParams& p, int max_blocks, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_fill, dim3(1), dim3(64), 0, s, a.st);
-  hipLaunchKernelGGL(k_fill_stats, dim3(grid_for((long long)p.width * p.height, kThreads * 8)),
-                     dim3(kThreads), 0, s, a, p);
-  int g = max_blocks < 1 ? 1 : (max_blocks > 2048 ? 2048 : max_blocks);
-  hipLaunchKernelGGL(k_fill, dim3(g), dim3(kThreads), 0, s, a, p);
+  hipLaunchKernelGGL(k_fill_stats, dim3(clamp_grid(p.height, 1024)), dim3(kThreads), 0, s, a, p);
+  hipLaunchKernelGGL(k_fill, dim3(clamp_grid(max_blocks, 2048)), dim3(kThreads), 0, s, a, p);
   return hipGetLastError();
 }
 
