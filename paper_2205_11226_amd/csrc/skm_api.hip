@@ -29,6 +29,9 @@ struct skm_ctx {
   int* d_bstate = nullptr;
   int* d_m0cnt = nullptr;         size_t cap_cells = 0;
   int* d_part = nullptr;
+  int* d_hql_list = nullptr;
+  unsigned char* d_hql_ws = nullptr; size_t cap_hql = 0;
+  size_t hql_lds_set = 65536;
   RoundState* d_state = nullptr;
   RoundState* h_state = nullptr;  // pinned
   // staging for the host-memory entry point
@@ -71,6 +74,10 @@ skm_status grow(T** ptr, size_t* cap, size_t need, const char* what) {
   SKM_HIP(hipMalloc((void**)ptr, n * sizeof(T)), what);
   *cap = n;
   return SKM_OK;
+}
+
+bool mode_uses_hql(int mode) {
+  return mode == SKM_MODE_PROFILE || mode == SKM_MODE_FULL || mode == SKM_MODE_CNN;
 }
 
 skm_status make_params(const skm_params* in, int width, int height, int stride, DevParams* p) {
@@ -143,9 +150,23 @@ skm_status ensure_frame(skm_ctx* c, const DevParams& p) {
     if ((s = grow(&c->d_bstate, &cap, ncell, "block state")) != SKM_OK) return s;
     cap = 0;
     if ((s = grow(&c->d_m0cnt, &cap, ncell, "context counts")) != SKM_OK) return s;
+    (void)hipFree(c->d_hql_list); c->d_hql_list = nullptr;
+    cap = 0;
+    if ((s = grow(&c->d_hql_list, &cap, ncell, "HQL list")) != SKM_OK) return s;
     c->cap_cells = ncell < 1 ? 1 : ncell;
   }
   if (!c->d_part) SKM_HIP(hipMalloc((void**)&c->d_part, sizeof(int) * 2 * kPrepGridMax), "prep slots");
+  if (mode_uses_hql(p.mode)) {
+    const size_t need = hql_slot_bytes(p) * kHqlSlots;
+    if ((s = grow(&c->d_hql_ws, &c->cap_hql, need, "HQL scratch")) != SKM_OK) return s;
+    const size_t hl = hql_lds_bytes(p);
+    if ((int)hl > c->max_lds)
+      return fail(SKM_EUNSUPPORTED, "window/ring/block need more LDS than the device has");
+    if (hl > c->hql_lds_set) {
+      SKM_HIP(set_hql_lds_limit(hl), "hipFuncSetAttribute");
+      c->hql_lds_set = hl;
+    }
+  }
   size_t lds = main_lds_bytes(p);
   if ((int)lds > c->max_lds)
     return fail(SKM_EUNSUPPORTED, "window/ring/block need more LDS than the device has");
@@ -162,6 +183,7 @@ FrameArgs frame_args(skm_ctx* c, const uint8_t* frame, const uint8_t* mask, uint
   a.frame = frame; a.mask = mask; a.work = out;
   a.val = c->d_val; a.cell_lost = c->d_cell_lost; a.blk = c->d_blk;
   a.bstate = c->d_bstate; a.m0cnt = c->d_m0cnt; a.part = c->d_part; a.st = c->d_state;
+  a.hql_list = c->d_hql_list;
   return a;
 }
 
@@ -201,6 +223,8 @@ skm_status launch_round(skm_ctx* c, const DevParams& p, FrameArgs& a, int nb, hi
     SKM_HIP(hipEventRecord(c->ev[2 * c->ev_used + 1], s), "hipEventRecord");
     ++c->ev_used;
   }
+  if (mode_uses_hql(p.mode))
+    SKM_HIP(launch_hql(a, p, c->d_hql_ws, hql_slot_bytes(p), kHqlSlots, s), "HQL kernel");
   SKM_HIP(launch_finalize(a, p, nb, s), "finalize kernel");
   return SKM_OK;
 }
@@ -283,6 +307,8 @@ void skm_destroy(skm_ctx* c) {
   (void)hipFree(c->d_bstate);
   (void)hipFree(c->d_m0cnt);
   (void)hipFree(c->d_part);
+  (void)hipFree(c->d_hql_list);
+  (void)hipFree(c->d_hql_ws);
   (void)hipFree(c->d_state);
   (void)hipFree(c->d_frame);
   (void)hipFree(c->d_mask);

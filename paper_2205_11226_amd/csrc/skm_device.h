@@ -1,0 +1,382 @@
+// Device helpers shared by the estimation kernel and the HQL kernel: wave
+// reductions, the per-block LDS layout, and the phases that stage a block's
+// search window and find its admissible candidates with exact distances.
+#pragma once
+
+#include <math.h>
+
+#include "skm_internal.h"
+
+namespace skm {
+
+// ------------------------------------------------------------ wave helpers
+
+static __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+static __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+
+template <typename T>
+static __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+static __device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+static __device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+static __device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Merge (m2, s2) into (m, s), both "max and sum of exp(x - max)".  Callers fix
+// the merge order, so results are deterministic.
+static __device__ __forceinline__ void lse_merge(double& m, double& s, double m2, double s2) {
+  if (m2 == -INFINITY) return;
+  if (m == -INFINITY) { m = m2; s = s2; return; }
+  if (m2 > m) { s = s * exp(m - m2) + s2; m = m2; }
+  else        { s = s + s2 * exp(m2 - m); }
+}
+
+// 128-bit logical right shift of (lo, hi), 0 <= s < 128
+static __device__ __forceinline__ void shr128(uint64_t lo, uint64_t hi, int s, uint64_t& olo,
+                                              uint64_t& ohi) {
+  if (s == 0) { olo = lo; ohi = hi; }
+  else if (s < 64) { olo = (lo >> s) | (hi << (64 - s)); ohi = hi >> s; }
+  else { olo = hi >> (s - 64); ohi = 0; }
+}
+
+// ------------------------------------------------------------ LDS layout
+//
+// Per-block LDS carve-up (dynamic).  MC bounds the number of admissible
+// candidates: a prototype can never overlap the block itself, so
+// MC = (2W+1)^2 - (2 min(B-1, W) + 1)^2.  NU counts ring "units":
+// horizontally adjacent pairs of ring pixels, or a single pixel with a dummy
+// partner.
+//   ell     f64 [MC]      log raw IDL weight of each candidate, -inf if dropped
+//   cand    u32 [MC]      admissible candidates in raster order:
+//                         window offset | bucket << 16 | radius << 24
+//   selw    f32 [MC]      FP32 weights exp(ell - max) of the selected candidates
+//   selo    u16 [MC]      their window offsets
+//   qu      u32x2 [NU]    per unit: packed int16 context pair, footprint offset
+//   utab    u32 [NU]      fixed unit table: footprint offset | single << 16
+//   rowbits u64 [Wd][2]   availability bits of each window row
+//   runbits u64 [Wd][2]   bit c set iff columns c .. c+B-1 are all available
+//   cmask   u64 [D2][2]   bit dx of displacement row dy set iff the B x B
+//                         prototype at (dy, dx) is admissible
+//   winp    u32 [Wd*Wd]   window pixel pairs: int16 pixel | next pixel << 16,
+//                         -1 = unknown (lost or out of frame)
+
+struct MainLds {
+  double* ell;
+  uint32_t* cand;
+  float* selw;
+  uint16_t* selo;
+  uint2* qu;
+  uint32_t* utab;
+  uint64_t* rowbits;
+  uint64_t* runbits;
+  uint64_t* cmask;
+  uint32_t* winp;
+};
+
+__host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+__host__ __device__ inline size_t main_lds_layout(const DevParams& p, size_t* offs) {
+  const size_t D2 = 2 * p.W + 1;
+  size_t o = 0;
+  offs[0] = o; o = align_up(o + sizeof(double) * p.MC, 16);
+  offs[1] = o; o = align_up(o + sizeof(uint32_t) * p.MC, 16);
+  offs[2] = o; o = align_up(o + sizeof(float) * p.MC, 16);
+  offs[3] = o; o = align_up(o + sizeof(uint16_t) * p.MC, 16);
+  offs[4] = o; o = align_up(o + sizeof(uint2) * p.NR, 16);
+  offs[5] = o; o = align_up(o + sizeof(uint32_t) * p.NR, 16);
+  offs[6] = o; o = align_up(o + sizeof(uint64_t) * 2 * p.Wd, 16);
+  offs[7] = o; o = align_up(o + sizeof(uint64_t) * 2 * p.Wd, 16);
+  offs[8] = o; o = align_up(o + sizeof(uint64_t) * 2 * (2 * p.W + 1), 16);
+  offs[9] = o; o = align_up(o + sizeof(uint32_t) * p.Wd * p.Wd, 16);
+  return o;
+}
+
+static __device__ __forceinline__ MainLds carve_main_lds(unsigned char* raw, const DevParams& p) {
+  size_t offs[10];
+  main_lds_layout(p, offs);
+  MainLds L;
+  L.ell = (double*)(raw + offs[0]);
+  L.cand = (uint32_t*)(raw + offs[1]);
+  L.selw = (float*)(raw + offs[2]);
+  L.selo = (uint16_t*)(raw + offs[3]);
+  L.qu = (uint2*)(raw + offs[4]);
+  L.utab = (uint32_t*)(raw + offs[5]);
+  L.rowbits = (uint64_t*)(raw + offs[6]);
+  L.runbits = (uint64_t*)(raw + offs[7]);
+  L.cmask = (uint64_t*)(raw + offs[8]);
+  L.winp = (uint32_t*)(raw + offs[9]);
+  return L;
+}
+
+// Small per-block values shared by the workgroup.
+struct BlockShared {
+  int NU, M, n_sel;
+  int layer, radius_idx, flags, n_cand, n_complete;
+  double lnu, mstar, den;
+  int red_i[kThreads / 64][4];
+  int scan[kThreads / 64];
+  int rowbase[2 * kMaxWin + 1];
+  unsigned long long bmax[kMaxRadii];
+  int bcnt[kMaxRadii];
+  double cm[kMaxRadii];
+  double ps[kThreads / 64][kMaxRadii];
+  int bucket_of[kMaxWin + 1];
+  double part[kThreads];
+};
+
+typedef short short2v __attribute__((ext_vector_type(2)));
+
+// exclusive scan of one int per thread over the workgroup (fixed order)
+static __device__ __forceinline__ int block_excl_scan(int v, int* s_w, int* total) {
+  const int lane = lane_id(), wave = wave_id();
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_w[wave] = x;
+  __syncthreads();
+  int base = 0, tot = 0;
+  for (int w = 0; w < kThreads / 64; ++w) {
+    if (w < wave) base += s_w[w];
+    tot += s_w[w];
+  }
+  *total = tot;
+  __syncthreads();
+  return base + x - v;
+}
+
+// Sum of (q - p)^2 over both halves of two packed int16 pairs where neither
+// half is negative (unknown), and the count of such halves, accumulated.
+static __device__ __forceinline__ void pair_dist(uint32_t q, uint32_t pp, int& d, uint32_t& nacc) {
+  const short2v qa = __builtin_bit_cast(short2v, q), pa = __builtin_bit_cast(short2v, pp);
+  const short2v sgn = (qa | pa) >> (short2v){15, 15};          // 0xffff where unknown
+  const uint32_t bad = __builtin_bit_cast(uint32_t, sgn);
+  const uint32_t df = __builtin_bit_cast(uint32_t, (short2v)(qa - pa)) & ~bad;
+  d = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, df), __builtin_bit_cast(short2v, df), d,
+                             false);
+  nacc += ~bad & 0x00010001u;
+}
+
+// ---------------------------------------------------------------- phases
+// All functions below are called by every thread of the workgroup.
+
+// Fixed tables, once per workgroup.  bucket_of: radius -> first schedule
+// radius >= it.  utab: the ring pixels of each footprint row taken left to
+// right in pairs of horizontal neighbours (a lone pixel gets a dummy
+// partner); lane fy owns footprint row fy, a wave scan orders the rows.
+static __device__ __forceinline__ void phase_tables(const DevParams& p, const MainLds& L,
+                                                    BlockShared& sh) {
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  const int B = p.B, r = p.r, W = p.W, Wd = p.Wd, F = p.F;
+  if (tid <= W) {
+    int b = p.nrad - 1;
+    for (int ri = 0; ri < p.nrad; ++ri) if (p.radii[ri] >= tid) { b = ri; break; }
+    sh.bucket_of[tid] = b;
+  }
+  if (wave == 0) {
+    const int fy = lane;
+    const bool full = fy < r || fy >= r + B;
+    int cnt = 0;
+    if (fy < F) cnt = full ? (F + 1) / 2 : 2 * ((r + 1) / 2);
+    int x = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    int pos = x - cnt;
+    if (fy < F) {
+      if (full) {
+        for (int c = 0; c < F; c += 2)
+          L.utab[pos++] = (uint32_t)(fy * Wd + c) | ((uint32_t)(c + 1 >= F) << 16);
+      } else {
+        for (int c = 0; c < r; c += 2)
+          L.utab[pos++] = (uint32_t)(fy * Wd + c) | ((uint32_t)(c + 1 >= r) << 16);
+        for (int c = r + B; c < F; c += 2)
+          L.utab[pos++] = (uint32_t)(fy * Wd + c) | ((uint32_t)(c + 1 >= F) << 16);
+      }
+    }
+    if (lane == 63) sh.NU = x;
+  }
+  __syncthreads();
+}
+
+// Stage the window of the block whose window origin is (ox, oy): one wave per
+// row and lanes along it, six rows of loads in flight; pixel pairs by lane
+// shuffle; availability bits per row.  Ends with a barrier.
+static __device__ __forceinline__ void phase_stage(const FrameArgs& a, const DevParams& p,
+                                                   const MainLds& L, int ox, int oy) {
+  const int lane = lane_id(), wave = wave_id();
+  const int Wd = p.Wd, nw = kThreads / 64;
+  for (int wy0 = wave; wy0 < Wd; wy0 += 6 * nw) {
+    int v0[6], v1[6];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      const int wy = wy0 + t * nw;
+      const int gy = oy + wy;
+      const int cy = min(max(gy, 0), p.height - 1);
+      const bool rowok = wy < Wd && gy >= 0 && gy < p.height;
+      const int gx0 = ox + lane, gx1 = ox + 64 + lane;
+      const int16_t r0 = a.val[(size_t)cy * p.width + min(max(gx0, 0), p.width - 1)];
+      const int16_t r1 = a.val[(size_t)cy * p.width + min(max(gx1, 0), p.width - 1)];
+      v0[t] = (rowok && lane < Wd && gx0 >= 0 && gx0 < p.width) ? r0 : -1;
+      v1[t] = (rowok && 64 + lane < Wd && gx1 >= 0 && gx1 < p.width) ? r1 : -1;
+    }
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      const int wy = wy0 + t * nw;
+      const int n0 = __shfl_down(v0[t], 1, 64);
+      const int h0 = __shfl(v1[t], 0, 64);
+      const int n1 = __shfl_down(v1[t], 1, 64);
+      const int nx0 = lane == 63 ? h0 : n0;
+      const int nx1 = (lane == 63 || 64 + lane + 1 >= Wd) ? -1 : n1;
+      const int nxa = (lane + 1 >= Wd) ? -1 : nx0;
+      const uint64_t lo = __ballot(v0[t] >= 0), hi = __ballot(v1[t] >= 0);
+      if (wy < Wd) {
+        if (lane < Wd)
+          L.winp[wy * Wd + lane] = (uint32_t)(uint16_t)v0[t] | ((uint32_t)(uint16_t)nxa << 16);
+        if (64 + lane < Wd)
+          L.winp[wy * Wd + 64 + lane] = (uint32_t)(uint16_t)v1[t] | ((uint32_t)(uint16_t)nx1 << 16);
+        if (lane == 0) { L.rowbits[2 * wy] = lo; L.rowbits[2 * wy + 1] = hi; }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+struct RingStats { int n0, phi, sum; };
+
+// Context units of the block (footprint origin qbase in the window) and ring
+// statistics; horizontal B-runs of every window row by doubling.  Ends with a
+// barrier.
+static __device__ __forceinline__ RingStats phase_context(const DevParams& p, const MainLds& L,
+                                                          BlockShared& sh, int NU) {
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  const int qbase = p.W * p.Wd + p.W;
+  {
+    int c = 0, vmin = 255, vmax = 0, vsum = 0;
+    for (int u = tid; u < NU; u += kThreads) {
+      const uint32_t e = L.utab[u];
+      const int off = (int)(e & 0xffffu);
+      uint32_t qp = L.winp[qbase + off];
+      if (e >> 16) qp |= 0xffff0000u;
+      L.qu[u] = make_uint2(qp, (uint32_t)off);
+      const int va = (int)(int16_t)(qp & 0xffffu), vb = (int)(int16_t)(qp >> 16);
+      if (va >= 0) { ++c; vmin = min(vmin, va); vmax = max(vmax, va); vsum += va; }
+      if (vb >= 0) { ++c; vmin = min(vmin, vb); vmax = max(vmax, vb); vsum += vb; }
+    }
+    c = wave_sum(c); vmin = wave_min(vmin); vmax = wave_max(vmax); vsum = wave_sum(vsum);
+    if (lane == 0) {
+      sh.red_i[wave][0] = c; sh.red_i[wave][1] = vmin;
+      sh.red_i[wave][2] = vmax; sh.red_i[wave][3] = vsum;
+    }
+  }
+  for (int row = tid; row < p.Wd; row += kThreads) {
+    uint64_t lo = L.rowbits[2 * row], hi = L.rowbits[2 * row + 1];
+    for (int s = 1; s < p.B; s <<= 1) {           // B is a power of two
+      uint64_t tlo, thi;
+      shr128(lo, hi, s, tlo, thi);
+      lo &= tlo; hi &= thi;
+    }
+    L.runbits[2 * row] = lo; L.runbits[2 * row + 1] = hi;
+  }
+  __syncthreads();
+  RingStats rs;
+  int n0 = 0, vmin = 255, vmax = 0, vsum = 0;
+  for (int w = 0; w < kThreads / 64; ++w) {
+    n0 += sh.red_i[w][0]; vmin = min(vmin, sh.red_i[w][1]);
+    vmax = max(vmax, sh.red_i[w][2]); vsum += sh.red_i[w][3];
+  }
+  rs.n0 = n0;
+  rs.phi = n0 > 0 ? vmax - vmin : 0;
+  rs.sum = vsum;
+  return rs;
+}
+
+// Admissible prototypes: vertical AND of B runs per displacement row shifted
+// to displacement columns (cmask), row counts and prefix, then the candidate
+// list in raster order (window offset | bucket << 16 | radius << 24).
+// Also resets the per-bucket maxima and counts.  Returns M; ends with a
+// barrier.
+static __device__ __forceinline__ int phase_candidates(const DevParams& p, const MainLds& L,
+                                                       BlockShared& sh) {
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  const int B = p.B, r = p.r, W = p.W, Wd = p.Wd, D2 = 2 * W + 1, nw = kThreads / 64;
+  int rowcnt = 0;
+  if (tid < D2) {
+    uint64_t lo = ~0ull, hi = ~0ull;
+    for (int k = 0; k < B; ++k) { lo &= L.runbits[2 * (r + tid + k)]; hi &= L.runbits[2 * (r + tid + k) + 1]; }
+    uint64_t mlo, mhi;
+    shr128(lo, hi, r, mlo, mhi);
+    if (D2 < 64) { mlo &= (1ull << D2) - 1ull; mhi = 0; }
+    else { mhi &= (D2 >= 128) ? ~0ull : ((1ull << (D2 - 64)) - 1ull); }
+    if (tid == W) mlo &= ~(1ull << W);          // W < 64: the block itself
+    L.cmask[2 * tid] = mlo; L.cmask[2 * tid + 1] = mhi;
+    rowcnt = __popcll(mlo) + __popcll(mhi);
+  }
+  {
+    int tot = 0;
+    const int rb = block_excl_scan(rowcnt, sh.scan, &tot);   // barriers inside
+    if (tid < D2) sh.rowbase[tid] = rb;
+    if (tid == 0) sh.M = tot;
+  }
+  if (tid < p.nrad) { sh.bmax[tid] = 0xFFF0000000000000ull; sh.bcnt[tid] = 0; }
+  __syncthreads();
+  for (int dyi = wave; dyi < D2; dyi += nw) {
+    const uint64_t mlo = L.cmask[2 * dyi], mhi = L.cmask[2 * dyi + 1];
+    const int base = sh.rowbase[dyi];
+    const int ady = abs(dyi - W);
+    for (int dxi = lane; dxi < D2; dxi += 64) {
+      const bool ok = dxi < 64 ? ((mlo >> dxi) & 1ull) : ((mhi >> (dxi - 64)) & 1ull);
+      if (ok) {
+        const int rank = dxi < 64 ? __popcll(mlo & ((1ull << dxi) - 1ull))
+                                  : __popcll(mlo) + __popcll(mhi & ((1ull << (dxi - 64)) - 1ull));
+        const int rho = max(ady, abs(dxi - W));
+        L.cand[base + rank] = (uint32_t)(dyi * Wd + dxi) | ((uint32_t)sh.bucket_of[rho] << 16) |
+                              ((uint32_t)rho << 24);
+      }
+    }
+  }
+  __syncthreads();
+  return sh.M;
+}
+
+// Exact integer distance of the candidate whose footprint origin is `base`
+// in the window, over the ring pixels known in both rings, two pixels per
+// step (packed int16 difference, masked, v_dot2).  Returns d and the count n.
+static __device__ __forceinline__ void cand_distance(const MainLds& L, int base, int NU, int& d_out,
+                                                     int& n_out) {
+  int d = 0;
+  uint32_t nacc = 0;
+  int u = 0;
+  for (; u + 8 <= NU; u += 8) {
+    uint2 qq[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) qq[t] = L.qu[u + t];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) pair_dist(qq[t].x, L.winp[base + (int)qq[t].y], d, nacc);
+  }
+  for (; u < NU; ++u) {
+    const uint2 qq = L.qu[u];
+    pair_dist(qq.x, L.winp[base + (int)qq.y], d, nacc);
+  }
+  d_out = d;
+  n_out = (int)(nacc & 0xffffu) + (int)(nacc >> 16);
+}
+
+}  // namespace skm

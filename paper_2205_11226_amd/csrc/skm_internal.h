@@ -41,6 +41,7 @@ struct RoundState {
   int remaining;       // pending blocks at the start of the current round
   int round;           // current round, 1-based
   int err;
+  int n_hql;           // blocks of this round waiting for the HQL kernel
   unsigned long long n_avail;     // fill: known pixels and their sum
   unsigned long long sum_avail;
 };
@@ -63,6 +64,7 @@ struct FrameArgs {
   int* bstate;
   int* m0cnt;
   int* part;              // 2 * kPrepGridMax prep partials
+  int* hql_list;          // lost-block indices waiting for HQL in this round
   RoundState* st;
   skm_block_info* info;   // optional
   float* xhat;            // optional
@@ -83,6 +85,13 @@ hipError_t launch_fill(const FrameArgs& a, const DevParams& p, int max_blocks,
 hipError_t launch_dist(const FrameArgs& a, const DevParams& p, int max_blocks,
                        hipStream_t s);
 hipError_t set_main_lds_limit(size_t bytes);
+// HQL (skm_hql.hip)
+constexpr int kHqlSlots = 128;     // workgroups of the HQL kernel, one scratch slot each
+size_t hql_slot_bytes(const DevParams& p);
+size_t hql_lds_bytes(const DevParams& p);
+hipError_t launch_hql(const FrameArgs& a, const DevParams& p, unsigned char* ws, size_t slot_bytes,
+                      int slots, hipStream_t s);
+hipError_t set_hql_lds_limit(size_t bytes);
 int prep_grid_for(int max_blocks);
 size_t main_lds_bytes(const DevParams& p);
 
