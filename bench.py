@@ -121,7 +121,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", default="profile")
+    ap.add_argument("--mode", default="cnn")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2205_11226_amd", "weights",
+                                                      "gate_1080p.skm"))
     ap.add_argument("--profile", default="efficient")
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -138,8 +140,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         workers = args.cpu_workers or max(1, min(os.cpu_count() or 1, 16))
-        cpu = cpu_baseline(frame, mask, args.mode if args.mode != "cnn" else "profile",
-                           t_nu, workers)
+        cpu = cpu_baseline(frame, mask, "plain" if args.mode == "cnn" else args.mode, t_nu,
+                           workers)
         print(f"# cpu baseline: {cpu['value']:.1f} blocks/s on {workers} cores", file=sys.stderr,
               flush=True)
 
@@ -151,7 +153,10 @@ def main():
     md = torch.from_numpy(mask).to(dev)
     out = torch.empty_like(fd)
     ctx = skm.Context(0)
+    if args.mode == "cnn":
+        ctx.cnn_load(args.weights)          # fails loudly when the weights are missing
     p_lay = skm.default_params(mode=args.mode, profile=args.profile)
+    p_prof = skm.default_params(mode="profile", profile=args.profile)
     p_plain = skm.default_params(mode="plain")
 
     def run(p, k):
@@ -170,6 +175,8 @@ def main():
     print(f"# layered: {sec_lay * 1e3:.3f} ms/frame", file=sys.stderr, flush=True)
     sec_plain = timed(p_plain)
     print(f"# plain: {sec_plain * 1e3:.3f} ms/frame", file=sys.stderr, flush=True)
+    sec_prof = timed(p_prof)
+    print(f"# profile rule: {sec_prof * 1e3:.3f} ms/frame", file=sys.stderr, flush=True)
 
     # live kernel timing of the estimation kernel (events on its own stream)
     ctx.profile_enable(True)
@@ -180,6 +187,7 @@ def main():
 
     # statistics of one layered and one plain frame (not timed)
     o_lay, info_lay, _ = ctx.conceal_device(fd, md, p_lay, want_xhat=False)
+    o_prof, info_prof, _ = ctx.conceal_device(fd, md, p_prof, want_xhat=False)
     o_full, _, _ = ctx.conceal_device(fd, md, skm.default_params(mode="full"), want_xhat=False)
     d_tab, n_tab = ctx.distances_device(fd, md, p_plain)
     d_tab, n_tab = d_tab.cpu().numpy(), n_tab.cpu().numpy()
@@ -188,6 +196,8 @@ def main():
     achieved = ops / (k_ms * 1e-3) / 1e12
     ps_lay = psnr(o_lay.cpu().numpy(), frame)
     ps_full = psnr(o_full.cpu().numpy(), frame)
+    ps_prof = psnr(o_prof.cpu().numpy(), frame)
+    lay_prof = np.bincount(info_prof["layer"] + 1, minlength=4)
     layers = np.bincount(info_lay["layer"] + 1, minlength=4)
     traffic = traffic_from_profile(kernel_source_hash())
 
@@ -217,6 +227,10 @@ def main():
             "psnr_full_kmmse_db": ps_full,
             "delta_psnr_db": ps_full - ps_lay,
             "layers": {"brl": int(layers[1]), "idl": int(layers[2]), "hql": int(layers[3])},
+            "profile_rule": {"blocks_per_s": n_lost / sec_prof, "ms_per_frame": sec_prof * 1e3,
+                             "delta_psnr_db": ps_full - ps_prof,
+                             "layers": {"brl": int(lay_prof[1]), "idl": int(lay_prof[2]),
+                                        "hql": int(lay_prof[3])}},
         },
         "roofline": {
             "kernel": KERNEL,

@@ -169,6 +169,53 @@ skm_status skm_distances_device(skm_ctx* ctx, const uint8_t* d_frame, const uint
                                 const skm_params* params, int32_t* d_dist, int32_t* d_cnt,
                                 int32_t cap, int32_t* n_lost, void* hip_stream);
 
+/* ---------------------------------------------------------- learned gate
+ * A small CNN can replace the profile rule of the layer switching (Sec.
+ * "Layer switching and profile selection"): from a 48 x 48 window centred on
+ * a lost block (channels: (u - 128)/128 at known pixels and 0 elsewhere; 1 at
+ * unknown pixels) it predicts g1 = dB gain of IDL over BRL and g2 = dB gain
+ * of HQL over IDL.  In SKM_MODE_CNN a block takes BRL if g1 <= tau1, else HQL
+ * if g2 > tau2 (full-window IDL when HQL is unavailable), else IDL with the
+ * support-area expansion of t_nu.  Without a loaded network SKM_MODE_CNN
+ * applies the profile rule.  Network: three 3x3 convolutions (stride 2, zero
+ * padding 1, 32 channels, ReLU), global average pool, linear 32 -> 2;
+ * bfloat16 weights and convolution inputs, FP32 accumulation; 19170 FP32
+ * master parameters in the order w1[32][2][3][3], b1[32], w2[32][32][3][3],
+ * b2[32], w3[32][32][3][3], b3[32], wh[2][32], bh[2].
+ * Training inputs are bfloat16 bit patterns, [n][2][48][48]; targets FP32
+ * [n][2].  All device pointers belong to the caller. */
+
+/* He-uniform initialisation from `seed` (zero biases, Adam state reset). */
+skm_status skm_cnn_init(skm_ctx* ctx, uint64_t seed);
+/* Copy the 19170 master parameters in (resets Adam) or out (host arrays). */
+skm_status skm_cnn_set_weights(skm_ctx* ctx, const float* host_weights, int32_t n);
+skm_status skm_cnn_get_weights(skm_ctx* ctx, float* host_weights, int32_t n);
+/* Decision thresholds in dB (see above). */
+skm_status skm_cnn_set_thresholds(skm_ctx* ctx, double tau1, double tau2);
+/* Weight file: "SKMGATE1", uint32 version 1, uint32 19170, 2 x uint32 0,
+ * float32 tau1, tau2, 19170 float32 weights; little endian. */
+skm_status skm_save_cnn(skm_ctx* ctx, const char* path);
+skm_status skm_load_cnn(skm_ctx* ctx, const char* path);
+/* Network inputs of every lost block of a frame (received pixels only), in
+ * lost-cell raster order; SKM_EINVAL if cap < number of lost blocks. */
+skm_status skm_cnn_inputs(skm_ctx* ctx, const uint8_t* d_frame, const uint8_t* d_mask,
+                          int32_t width, int32_t height, int32_t stride, const skm_params* params,
+                          uint16_t* d_inputs, int32_t cap, int32_t* n_lost, void* hip_stream);
+/* Predictions d_out[n][2] for n inputs (training-path forward). */
+skm_status skm_cnn_forward(skm_ctx* ctx, const uint16_t* d_inputs, int32_t n, float* d_out,
+                           void* hip_stream);
+/* Mean squared error over the batch and both outputs and its gradient with
+ * respect to the master parameters (copied to host_grad[19170]). */
+skm_status skm_cnn_gradients(skm_ctx* ctx, const uint16_t* d_inputs, const float* d_targets,
+                             int32_t n, float* host_grad, float* loss, void* hip_stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) at learning rate lr on a
+ * batch; `loss` (host, optional) receives the batch loss before the step. */
+skm_status skm_cnn_train_step(skm_ctx* ctx, const uint16_t* d_inputs, const float* d_targets,
+                              int32_t n, float lr, float* loss, void* hip_stream);
+/* Gate predictions (g1, g2) of the last SKM_MODE_CNN frame, per lost block in
+ * lost-cell raster order (entries of blocks the gate did not see are stale). */
+skm_status skm_cnn_last_predictions(skm_ctx* ctx, float* host, int32_t cap);
+
 /* Kernel timing for measurement tools (not needed for concealment).  While
  * enabled, the context brackets every launch of its per-block estimation
  * kernel (the kernel that stages the search window, computes the distances,

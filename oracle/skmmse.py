@@ -396,13 +396,15 @@ def estimate_block(u, avail, by, bx, p: Params, cnn_gate=None):
     want_hql = None
     if mode == "profile" and phi <= p.t_phi:
         return brl, info
+    cnn_choice = None
     if mode == "cnn":
+        # learned gate: BRL, IDL with the support-area expansion (never
+        # escalating), or HQL (full-window IDL when HQL is not available)
         if cnn_gate is None:
             raise ValueError("cnn mode needs a gate callable")
-        g = cnn_gate(u, avail, by, bx)
-        if g == LAYER_BRL:
+        cnn_choice = cnn_gate(u, avail, by, bx)
+        if cnn_choice == LAYER_BRL:
             return brl, info
-        want_hql = g == LAYER_HQL
 
     c = candidate_set(u, avail, by, bx, p, y0, m0)
     complete = c.n == n0
@@ -416,7 +418,7 @@ def estimate_block(u, avail, by, bx, p: Params, cnn_gate=None):
     info["log_nu"] = _logsumexp(ell)
     info["radius"] = p.window
 
-    if mode in ("profile", "idl"):
+    if mode in ("profile", "idl") or cnn_choice == LAYER_IDL:
         log_tnu = math.log(p.t_nu) if p.t_nu > 0 else -math.inf
         rad = c.radius
         for rho, lnu in zip(idl_radii(p), log_nu_by_radius(c, p)):
@@ -429,7 +431,7 @@ def estimate_block(u, avail, by, bx, p: Params, cnn_gate=None):
         want_hql = mode == "profile"
     elif mode == "plain":
         want_hql = False
-    elif mode == "full":
+    elif mode == "full" or cnn_choice == LAYER_HQL:
         want_hql = True
 
     if want_hql:

@@ -17,8 +17,11 @@ LAYER_FILL, LAYER_BRL, LAYER_IDL, LAYER_HQL = -1, 0, 1, 2
 FLAG_CTX_RELAXED, FLAG_NO_HQL, FLAG_NO_CAND, FLAG_EMPTY_CTX = 1, 2, 4, 8
 
 EXPORTS = ("skm_default_params", "skm_create", "skm_destroy", "skm_conceal",
-           "skm_conceal_device", "skm_distances_device", "skm_profile_enable",
-           "skm_profile_read", "skm_last_error")
+           "skm_conceal_device", "skm_distances_device", "skm_cnn_init", "skm_cnn_set_weights",
+           "skm_cnn_get_weights", "skm_cnn_set_thresholds", "skm_save_cnn", "skm_load_cnn",
+           "skm_cnn_inputs", "skm_cnn_forward", "skm_cnn_gradients", "skm_cnn_train_step",
+           "skm_cnn_last_predictions", "skm_profile_enable", "skm_profile_read", "skm_last_error")
+CNN_PARAMS = 19170
 
 
 class SkmError(RuntimeError):
@@ -50,6 +53,13 @@ assert BLOCK_INFO_DTYPE.itemsize == ctypes.sizeof(BlockInfo) == 48
 
 
 def _load():
+    # PyTorch ships its own HIP runtime under the same soname as the system
+    # one the library links; loading torch first makes the process use one
+    # runtime for both (the other order leaves torch without devices).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python paper_2205_11226_amd/build.py`")
@@ -69,6 +79,23 @@ def _load():
     so.skm_distances_device.argtypes = [vp, vp, vp, i32, i32, i32, p(Params), vp, vp, i32,
                                         p(i32), vp]
     so.skm_distances_device.restype = i32
+    f32, f64, cp = ctypes.c_float, ctypes.c_double, ctypes.c_char_p
+    so.skm_cnn_init.argtypes = [vp, ctypes.c_uint64]
+    so.skm_cnn_set_weights.argtypes = [vp, vp, i32]
+    so.skm_cnn_get_weights.argtypes = [vp, vp, i32]
+    so.skm_cnn_set_thresholds.argtypes = [vp, f64, f64]
+    so.skm_save_cnn.argtypes = [vp, cp]
+    so.skm_load_cnn.argtypes = [vp, cp]
+    so.skm_cnn_inputs.argtypes = [vp, vp, vp, i32, i32, i32, p(Params), vp, i32, p(i32), vp]
+    so.skm_cnn_forward.argtypes = [vp, vp, i32, vp, vp]
+    so.skm_cnn_gradients.argtypes = [vp, vp, vp, i32, vp, p(f32), vp]
+    so.skm_cnn_train_step.argtypes = [vp, vp, vp, i32, f32, p(f32), vp]
+    so.skm_cnn_last_predictions.argtypes = [vp, vp, i32]
+    for n in ("skm_cnn_init", "skm_cnn_set_weights", "skm_cnn_get_weights",
+              "skm_cnn_set_thresholds", "skm_save_cnn", "skm_load_cnn", "skm_cnn_inputs",
+              "skm_cnn_forward", "skm_cnn_gradients", "skm_cnn_train_step",
+              "skm_cnn_last_predictions"):
+        getattr(so, n).restype = i32
     so.skm_profile_enable.argtypes = [vp, i32]
     so.skm_profile_enable.restype = i32
     so.skm_profile_read.argtypes = [vp, p(ctypes.c_double), p(i32)]
@@ -144,6 +171,76 @@ class Context:
         n = ctypes.c_int32(0)
         _check(lib.skm_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    # ------------------------------------------------------- learned gate
+    def cnn_init(self, seed: int = 0):
+        _check(lib.skm_cnn_init(self._h, int(seed)))
+
+    def cnn_set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _check(lib.skm_cnn_set_weights(self._h, w.ctypes.data, int(w.size)))
+
+    def cnn_get_weights(self) -> np.ndarray:
+        w = np.empty(CNN_PARAMS, dtype=np.float32)
+        _check(lib.skm_cnn_get_weights(self._h, w.ctypes.data, CNN_PARAMS))
+        return w
+
+    def cnn_set_thresholds(self, tau1: float, tau2: float):
+        _check(lib.skm_cnn_set_thresholds(self._h, float(tau1), float(tau2)))
+
+    def cnn_save(self, path: str):
+        _check(lib.skm_save_cnn(self._h, os.fsencode(path)))
+
+    def cnn_load(self, path: str):
+        _check(lib.skm_load_cnn(self._h, os.fsencode(path)))
+
+    def cnn_inputs(self, frame, mask, params: Params, stream=None):
+        """bf16 bit patterns (int16 tensor) [n_lost, 2, 48, 48] of every lost block."""
+        import torch
+        _dev_check(frame, mask)
+        h, w = frame.shape
+        cap = max((h // params.block) * (w // params.block), 1)
+        out = torch.empty((cap, 2, 48, 48), dtype=torch.int16, device=frame.device)
+        n = ctypes.c_int32(0)
+        s = torch.cuda.current_stream(frame.device) if stream is None else stream
+        _check(lib.skm_cnn_inputs(self._h, frame.data_ptr(), mask.data_ptr(), w, h,
+                                  frame.stride(0), ctypes.byref(params), out.data_ptr(), cap,
+                                  ctypes.byref(n), ctypes.c_void_p(s.cuda_stream)))
+        return out[:n.value]
+
+    def cnn_forward(self, x, stream=None):
+        import torch
+        x = x.contiguous()
+        out = torch.empty((x.shape[0], 2), dtype=torch.float32, device=x.device)
+        s = torch.cuda.current_stream(x.device) if stream is None else stream
+        _check(lib.skm_cnn_forward(self._h, x.data_ptr(), int(x.shape[0]), out.data_ptr(),
+                                   ctypes.c_void_p(s.cuda_stream)))
+        return out
+
+    def cnn_gradients(self, x, t, stream=None):
+        import torch
+        x, t = x.contiguous(), t.contiguous().float()
+        g = np.empty(CNN_PARAMS, dtype=np.float32)
+        loss = ctypes.c_float(0.0)
+        s = torch.cuda.current_stream(x.device) if stream is None else stream
+        _check(lib.skm_cnn_gradients(self._h, x.data_ptr(), t.data_ptr(), int(x.shape[0]),
+                                     g.ctypes.data, ctypes.byref(loss),
+                                     ctypes.c_void_p(s.cuda_stream)))
+        return loss.value, g
+
+    def cnn_train_step(self, x, t, lr: float, want_loss=True, stream=None):
+        import torch
+        loss = ctypes.c_float(float("nan"))
+        s = torch.cuda.current_stream(x.device) if stream is None else stream
+        _check(lib.skm_cnn_train_step(self._h, x.data_ptr(), t.data_ptr(), int(x.shape[0]),
+                                      float(lr), ctypes.byref(loss) if want_loss else None,
+                                      ctypes.c_void_p(s.cuda_stream)))
+        return loss.value
+
+    def cnn_last_predictions(self, cap: int) -> np.ndarray:
+        out = np.empty((max(cap, 1), 2), dtype=np.float32)
+        _check(lib.skm_cnn_last_predictions(self._h, out.ctypes.data, int(max(cap, 1))))
+        return out[:cap]
 
     # ---------------------------------------------------------------- host
     def conceal(self, frame: np.ndarray, mask: np.ndarray, params: Params,

@@ -40,6 +40,16 @@ struct skm_ctx {
   uint8_t* d_out = nullptr;       size_t cap_out = 0;
   skm_block_info* d_info = nullptr; size_t cap_info = 0;
   int last_rounds = 1;
+  // learned gate
+  float* d_cnn = nullptr;       // [5][kCnnParams]: master, bf16 copy, Adam m, Adam v, gradient
+  float* d_cnn_loss = nullptr;
+  bool cnn_loaded = false;
+  int cnn_step = 0;
+  float tau1 = 0.0f, tau2 = 0.0f;
+  float* d_cnn_buf = nullptr;   size_t cap_cnn_buf = 0;   // training activations
+  int8_t* d_gate = nullptr;
+  float* d_gate_pred = nullptr; size_t cap_gate = 0;
+  bool gate_lds_set = false;
   // kernel timing (skm_profile_*)
   bool prof = false;
   std::vector<hipEvent_t> ev;     // pairs: [2k] before, [2k+1] after
@@ -156,6 +166,18 @@ skm_status ensure_frame(skm_ctx* c, const DevParams& p) {
     c->cap_cells = ncell < 1 ? 1 : ncell;
   }
   if (!c->d_part) SKM_HIP(hipMalloc((void**)&c->d_part, sizeof(int) * 2 * kPrepGridMax), "prep slots");
+  if (ncell > c->cap_gate || !c->d_gate) {
+    (void)hipFree(c->d_gate); c->d_gate = nullptr;
+    (void)hipFree(c->d_gate_pred); c->d_gate_pred = nullptr;
+    const size_t n = ncell < 1 ? 1 : ncell;
+    SKM_HIP(hipMalloc((void**)&c->d_gate, n), "gate");
+    SKM_HIP(hipMalloc((void**)&c->d_gate_pred, sizeof(float) * 2 * n), "gate predictions");
+    c->cap_gate = n;
+  }
+  if (!c->gate_lds_set) {
+    SKM_HIP(set_cnn_gate_lds_limit(cnn_gate_lds_bytes()), "hipFuncSetAttribute");
+    c->gate_lds_set = true;
+  }
   if (mode_uses_hql(p.mode)) {
     const size_t need = hql_slot_bytes(p) * kHqlSlots;
     if ((s = grow(&c->d_hql_ws, &c->cap_hql, need, "HQL scratch")) != SKM_OK) return s;
@@ -184,6 +206,7 @@ FrameArgs frame_args(skm_ctx* c, const uint8_t* frame, const uint8_t* mask, uint
   a.val = c->d_val; a.cell_lost = c->d_cell_lost; a.blk = c->d_blk;
   a.bstate = c->d_bstate; a.m0cnt = c->d_m0cnt; a.part = c->d_part; a.st = c->d_state;
   a.hql_list = c->d_hql_list;
+  a.gate = c->d_gate; a.gate_pred = c->d_gate_pred;
   return a;
 }
 
@@ -208,6 +231,8 @@ skm_status check_err(const RoundState& st) {
 // the estimation kernel is bracketed by an event pair on `s`.
 skm_status launch_round(skm_ctx* c, const DevParams& p, FrameArgs& a, int nb, hipStream_t s) {
   SKM_HIP(launch_prep(a, p, nb, s), "prep kernel");
+  if (p.cnn_active)
+    SKM_HIP(launch_cnn_gate(a, p, c->d_cnn + kCnnParams, c->tau1, c->tau2, nb, s), "gate kernel");
   if (c->prof) {
     if ((int)c->ev.size() < 2 * (c->ev_used + 1)) {
       for (int k = 0; k < 2; ++k) {
@@ -307,6 +332,11 @@ void skm_destroy(skm_ctx* c) {
   (void)hipFree(c->d_bstate);
   (void)hipFree(c->d_m0cnt);
   (void)hipFree(c->d_part);
+  (void)hipFree(c->d_cnn);
+  (void)hipFree(c->d_cnn_loss);
+  (void)hipFree(c->d_cnn_buf);
+  (void)hipFree(c->d_gate);
+  (void)hipFree(c->d_gate_pred);
   (void)hipFree(c->d_hql_list);
   (void)hipFree(c->d_hql_ws);
   (void)hipFree(c->d_state);
@@ -334,6 +364,7 @@ skm_status skm_conceal_device(skm_ctx* c, const uint8_t* d_frame, const uint8_t*
   SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
   if ((s = ensure_frame(c, p)) != SKM_OK) return s;
   hipStream_t st = (hipStream_t)hip_stream;
+  p.cnn_active = p.mode == SKM_MODE_CNN && c->cnn_loaded;
   FrameArgs a = frame_args(c, d_frame, d_mask, d_out);
   a.info = d_info; a.xhat = d_xhat; a.cap = (d_info || d_xhat) ? cap : 0;
   int nl = 0;
@@ -364,6 +395,7 @@ skm_status skm_conceal(skm_ctx* c, const uint8_t* frame, const uint8_t* loss_mas
     return s;
   if ((s = ensure_frame(c, p)) != SKM_OK) return s;
   hipStream_t st = c->stream;
+  p.cnn_active = p.mode == SKM_MODE_CNN && c->cnn_loaded;
   SKM_HIP(hipMemcpyAsync(c->d_frame, frame, bytes, hipMemcpyHostToDevice, st), "frame upload");
   SKM_HIP(hipMemcpyAsync(c->d_mask, loss_mask, bytes, hipMemcpyHostToDevice, st), "mask upload");
   FrameArgs a = frame_args(c, c->d_frame, c->d_mask, c->d_out);
@@ -406,6 +438,209 @@ skm_status skm_distances_device(skm_ctx* c, const uint8_t* d_frame, const uint8_
   a.dist = d_dist; a.cnt = d_cnt;
   SKM_HIP(launch_dist(a, p, p.gh * p.gw, st), "distance kernel");
   SKM_HIP(hipStreamSynchronize(st), "stream synchronize");
+  return SKM_OK;
+}
+
+// ------------------------------------------------------------ learned gate
+
+static skm_status cnn_params_alloc(skm_ctx* c) {
+  if (c->d_cnn) return SKM_OK;
+  SKM_HIP(hipMalloc((void**)&c->d_cnn, sizeof(float) * 5 * kCnnParams), "gate parameters");
+  SKM_HIP(hipMemset(c->d_cnn, 0, sizeof(float) * 5 * kCnnParams), "gate parameters");
+  SKM_HIP(hipMalloc((void**)&c->d_cnn_loss, sizeof(float) * 4), "gate loss");
+  return SKM_OK;
+}
+
+static skm_status cnn_buffers(skm_ctx* c, int n, CnnBuffers* b) {
+  const size_t need = kCnnFloatsPerSample * (size_t)n;
+  skm_status s = grow(&c->d_cnn_buf, &c->cap_cnn_buf, need, "gate activations");
+  if (s != SKM_OK) return s;
+  float* q = c->d_cnn_buf;
+  auto take = [&](size_t per) { float* r = q; q += per * (size_t)n; return r; };
+  b->z1 = take(32 * 576); b->a1 = take(32 * 576); b->z2 = take(32 * 144); b->a2 = take(32 * 144);
+  b->z3 = take(32 * 36); b->a3 = take(32 * 36); b->g = take(32); b->y = take(2); b->gy = take(2);
+  b->gz3 = take(32 * 36); b->gz2 = take(32 * 144); b->gz1 = take(32 * 576);
+  return SKM_OK;
+}
+
+skm_status skm_cnn_init(skm_ctx* c, uint64_t seed) {
+  if (!c) return fail(SKM_EINVAL, "ctx is NULL");
+  SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  skm_status s = cnn_params_alloc(c);
+  if (s != SKM_OK) return s;
+  SKM_HIP(hipMemsetAsync(c->d_cnn + 2 * kCnnParams, 0, sizeof(float) * 2 * kCnnParams, c->stream),
+          "Adam state");
+  SKM_HIP(cnn_init(c->d_cnn, c->d_cnn + kCnnParams, seed, c->stream), "gate init");
+  SKM_HIP(hipStreamSynchronize(c->stream), "stream synchronize");
+  c->cnn_step = 0;
+  c->cnn_loaded = true;
+  return SKM_OK;
+}
+
+skm_status skm_cnn_set_weights(skm_ctx* c, const float* host, int32_t n) {
+  if (!c || !host) return fail(SKM_EINVAL, "NULL argument");
+  if (n != kCnnParams) return fail(SKM_EINVAL, "weight count must be 19170");
+  SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  skm_status s = cnn_params_alloc(c);
+  if (s != SKM_OK) return s;
+  SKM_HIP(hipMemcpyAsync(c->d_cnn, host, sizeof(float) * kCnnParams, hipMemcpyHostToDevice, c->stream),
+          "weights upload");
+  SKM_HIP(hipMemsetAsync(c->d_cnn + 2 * kCnnParams, 0, sizeof(float) * 2 * kCnnParams, c->stream),
+          "Adam state");
+  SKM_HIP(cnn_quantize(c->d_cnn, c->d_cnn + kCnnParams, c->stream), "quantize");
+  SKM_HIP(hipStreamSynchronize(c->stream), "stream synchronize");
+  c->cnn_step = 0;
+  c->cnn_loaded = true;
+  return SKM_OK;
+}
+
+skm_status skm_cnn_get_weights(skm_ctx* c, float* host, int32_t n) {
+  if (!c || !host) return fail(SKM_EINVAL, "NULL argument");
+  if (n != kCnnParams) return fail(SKM_EINVAL, "weight count must be 19170");
+  if (!c->cnn_loaded) return fail(SKM_EINVAL, "no network loaded");
+  SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  SKM_HIP(hipMemcpyAsync(host, c->d_cnn, sizeof(float) * kCnnParams, hipMemcpyDeviceToHost, c->stream),
+          "weights download");
+  SKM_HIP(hipStreamSynchronize(c->stream), "stream synchronize");
+  return SKM_OK;
+}
+
+skm_status skm_cnn_set_thresholds(skm_ctx* c, double tau1, double tau2) {
+  if (!c) return fail(SKM_EINVAL, "ctx is NULL");
+  if (isnan(tau1) || isnan(tau2)) return fail(SKM_EINVAL, "threshold is NaN");
+  c->tau1 = (float)tau1;
+  c->tau2 = (float)tau2;
+  return SKM_OK;
+}
+
+static const char kGateMagic[8] = {'S', 'K', 'M', 'G', 'A', 'T', 'E', '1'};
+
+skm_status skm_save_cnn(skm_ctx* c, const char* path) {
+  if (!c || !path) return fail(SKM_EINVAL, "NULL argument");
+  if (!c->cnn_loaded) return fail(SKM_EINVAL, "no network loaded");
+  std::vector<float> w(kCnnParams);
+  skm_status s = skm_cnn_get_weights(c, w.data(), kCnnParams);
+  if (s != SKM_OK) return s;
+  FILE* f = fopen(path, "wb");
+  if (!f) return fail(SKM_EINVAL, std::string("cannot open ") + path);
+  const uint32_t hdr[4] = {1u, (uint32_t)kCnnParams, 0u, 0u};
+  const float tau[2] = {c->tau1, c->tau2};
+  bool ok = fwrite(kGateMagic, 1, 8, f) == 8 && fwrite(hdr, 4, 4, f) == 4 &&
+            fwrite(tau, 4, 2, f) == 2 && fwrite(w.data(), 4, kCnnParams, f) == (size_t)kCnnParams;
+  ok = (fclose(f) == 0) && ok;
+  return ok ? SKM_OK : fail(SKM_EINVAL, "write failed");
+}
+
+skm_status skm_load_cnn(skm_ctx* c, const char* path) {
+  if (!c || !path) return fail(SKM_EINVAL, "NULL argument");
+  FILE* f = fopen(path, "rb");
+  if (!f) return fail(SKM_EINVAL, std::string("cannot open ") + path);
+  char magic[8];
+  uint32_t hdr[4];
+  float tau[2];
+  std::vector<float> w(kCnnParams);
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kGateMagic, 8) == 0 &&
+            fread(hdr, 4, 4, f) == 4 && hdr[0] == 1u && hdr[1] == (uint32_t)kCnnParams &&
+            fread(tau, 4, 2, f) == 2 && fread(w.data(), 4, kCnnParams, f) == (size_t)kCnnParams;
+  fclose(f);
+  if (!ok) return fail(SKM_EINVAL, "not a gate weight file (SKMGATE1, version 1, 19170 weights)");
+  skm_status s = skm_cnn_set_weights(c, w.data(), kCnnParams);
+  if (s != SKM_OK) return s;
+  c->tau1 = tau[0];
+  c->tau2 = tau[1];
+  return SKM_OK;
+}
+
+skm_status skm_cnn_inputs(skm_ctx* c, const uint8_t* d_frame, const uint8_t* d_mask, int32_t width,
+                          int32_t height, int32_t stride, const skm_params* params,
+                          uint16_t* d_inputs, int32_t cap, int32_t* n_lost, void* hip_stream) {
+  if (!c) return fail(SKM_EINVAL, "ctx is NULL");
+  if (!d_frame || !d_mask || !d_inputs) return fail(SKM_EINVAL, "NULL pointer");
+  DevParams p;
+  skm_status s = make_params(params, width, height, stride, &p);
+  if (s != SKM_OK) return s;
+  SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  if ((s = ensure_frame(c, p)) != SKM_OK) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const size_t bytes = (size_t)(height - 1) * stride + width;
+  if ((s = grow(&c->d_out, &c->cap_out, bytes, "scratch plane")) != SKM_OK) return s;
+  FrameArgs a = frame_args(c, d_frame, d_mask, c->d_out);
+  SKM_HIP(launch_init(a, p, st), "geometry kernels");
+  if ((s = read_state(c, st)) != SKM_OK) return s;
+  if ((s = check_err(*c->h_state)) != SKM_OK) return s;
+  const int nl = c->h_state->n_lost;
+  if (n_lost) *n_lost = nl;
+  if (nl > cap) return fail(SKM_EINVAL, "cap smaller than the number of lost blocks");
+  SKM_HIP(launch_cnn_inputs(a, p, d_inputs, p.gh * p.gw, st), "gate inputs");
+  SKM_HIP(hipStreamSynchronize(st), "stream synchronize");
+  return SKM_OK;
+}
+
+skm_status skm_cnn_forward(skm_ctx* c, const uint16_t* d_inputs, int32_t n, float* d_out,
+                           void* hip_stream) {
+  if (!c || !d_inputs || !d_out || n < 1) return fail(SKM_EINVAL, "bad argument");
+  if (!c->cnn_loaded) return fail(SKM_EINVAL, "no network loaded");
+  SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  CnnBuffers b;
+  skm_status s = cnn_buffers(c, n, &b);
+  if (s != SKM_OK) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  SKM_HIP(cnn_forward(b, c->d_cnn + kCnnParams, d_inputs, n, st), "gate forward");
+  SKM_HIP(hipMemcpyAsync(d_out, b.y, sizeof(float) * 2 * n, hipMemcpyDeviceToDevice, st), "copy");
+  SKM_HIP(hipStreamSynchronize(st), "stream synchronize");
+  return SKM_OK;
+}
+
+static skm_status cnn_fwd_bwd(skm_ctx* c, const uint16_t* x, const float* t, int n, hipStream_t st,
+                              float* loss) {
+  CnnBuffers b;
+  skm_status s = cnn_buffers(c, n, &b);
+  if (s != SKM_OK) return s;
+  float* wq = c->d_cnn + kCnnParams;
+  float* grad = c->d_cnn + 4 * kCnnParams;
+  SKM_HIP(cnn_forward(b, wq, x, n, st), "gate forward");
+  SKM_HIP(cnn_backward(b, wq, x, t, n, grad, c->d_cnn_loss, st), "gate backward");
+  if (loss) {
+    SKM_HIP(hipMemcpyAsync(loss, c->d_cnn_loss, sizeof(float), hipMemcpyDeviceToHost, st), "loss");
+  }
+  return SKM_OK;
+}
+
+skm_status skm_cnn_gradients(skm_ctx* c, const uint16_t* d_inputs, const float* d_targets, int32_t n,
+                             float* host_grad, float* loss, void* hip_stream) {
+  if (!c || !d_inputs || !d_targets || !host_grad || n < 1) return fail(SKM_EINVAL, "bad argument");
+  if (!c->cnn_loaded) return fail(SKM_EINVAL, "no network loaded");
+  SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)hip_stream;
+  skm_status s = cnn_fwd_bwd(c, d_inputs, d_targets, n, st, loss);
+  if (s != SKM_OK) return s;
+  SKM_HIP(hipMemcpyAsync(host_grad, c->d_cnn + 4 * kCnnParams, sizeof(float) * kCnnParams,
+                         hipMemcpyDeviceToHost, st), "gradient download");
+  SKM_HIP(hipStreamSynchronize(st), "stream synchronize");
+  return SKM_OK;
+}
+
+skm_status skm_cnn_train_step(skm_ctx* c, const uint16_t* d_inputs, const float* d_targets,
+                              int32_t n, float lr, float* loss, void* hip_stream) {
+  if (!c || !d_inputs || !d_targets || n < 1 || !(lr > 0.0f)) return fail(SKM_EINVAL, "bad argument");
+  if (!c->cnn_loaded) return fail(SKM_EINVAL, "no network loaded");
+  SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)hip_stream;
+  skm_status s = cnn_fwd_bwd(c, d_inputs, d_targets, n, st, loss);
+  if (s != SKM_OK) return s;
+  ++c->cnn_step;
+  SKM_HIP(cnn_adam(c->d_cnn, c->d_cnn + 4 * kCnnParams, c->d_cnn + 2 * kCnnParams,
+                   c->d_cnn + 3 * kCnnParams, c->d_cnn + kCnnParams, lr, c->cnn_step, st), "Adam");
+  if (loss) SKM_HIP(hipStreamSynchronize(st), "stream synchronize");
+  return SKM_OK;
+}
+
+skm_status skm_cnn_last_predictions(skm_ctx* c, float* host, int32_t cap) {
+  if (!c || !host) return fail(SKM_EINVAL, "NULL argument");
+  if (!c->d_gate_pred) return fail(SKM_EINVAL, "no frame concealed yet");
+  const size_t n = (size_t)cap < c->cap_gate ? (size_t)cap : c->cap_gate;
+  SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  SKM_HIP(hipMemcpy(host, c->d_gate_pred, sizeof(float) * 2 * n, hipMemcpyDeviceToHost), "download");
   return SKM_OK;
 }
 

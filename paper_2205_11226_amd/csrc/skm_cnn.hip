@@ -1,0 +1,479 @@
+// Learned layer manager: a small CNN that predicts, from a 48 x 48 window
+// centred on a lost block, the PSNR gain of IDL over BRL (g1) and of HQL over
+// IDL (g2).  It replaces the profile rule of the paper's layer switching
+// (Sec. "Layer switching and profile selection"), choosing the layer before
+// any candidate is examined: BRL if g1 <= tau1, else HQL if g2 > tau2, else
+// IDL.
+//
+// Network: input (2, 48, 48) = ((u - 128)/128 at known pixels, 1 at unknown
+// pixels); three 3x3 convolutions, stride 2, zero padding 1, 32 channels,
+// ReLU; global average pool; linear 32 -> 2.  Weights and the inputs of every
+// convolution are bfloat16 values, accumulation is FP32.  Parameters live in
+// one flat FP32 array (w1, b1, w2, b2, w3, b3, wh, bh); `wq` is the same array
+// with the convolution weights rounded to bfloat16.
+//
+// Training kernels are batched over N samples in NCHW FP32 buffers; every
+// reduction runs in a fixed order, so a training step is deterministic.
+#include "skm_device.h"
+
+namespace skm {
+
+constexpr int kP = 48;          // input window
+constexpr int kC = 32;          // channels
+constexpr int kOffW1 = 0, kOffB1 = 576, kOffW2 = 608, kOffB2 = 9824, kOffW3 = 9856,
+              kOffB3 = 19072, kOffWh = 19104, kOffBh = 19168, kNParams = 19170;
+
+static __device__ __forceinline__ float bf16_round(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+static __device__ __forceinline__ float bf16_to_f(uint16_t h) {
+  return __uint_as_float((uint32_t)h << 16);
+}
+static __device__ __forceinline__ bool is_conv_weight(int k) {
+  return (k >= kOffW1 && k < kOffB1) || (k >= kOffW2 && k < kOffB2) || (k >= kOffW3 && k < kOffB3);
+}
+
+// Input channels of one block from the value plane (known = value >= 0).
+static __device__ __forceinline__ void input_pixel(const FrameArgs& a, const DevParams& p, int by,
+                                                   int bx, int idx, float& c0, float& c1) {
+  const int py = idx / kP, px = idx - py * kP;
+  const int gy = by * p.B + p.B / 2 - kP / 2 + py, gx = bx * p.B + p.B / 2 - kP / 2 + px;
+  int v = -1;
+  if (gy >= 0 && gy < p.height && gx >= 0 && gx < p.width) v = a.val[(size_t)gy * p.width + gx];
+  c0 = v >= 0 ? (float)(v - 128) * (1.0f / 128.0f) : 0.0f;
+  c1 = v >= 0 ? 0.0f : 1.0f;
+}
+
+// inputs of every lost block (received frame), bf16 [n][2][48][48]
+__global__ __launch_bounds__(kThreads) void k_cnn_inputs(FrameArgs a, DevParams p, uint16_t* out) {
+  const int n_lost = a.st->n_lost;
+  for (int i = blockIdx.x; i < n_lost; i += gridDim.x) {
+    const int cell = a.blk[i];
+    const int by = cell / p.gw, bx = cell - by * p.gw;
+    for (int idx = threadIdx.x; idx < kP * kP; idx += kThreads) {
+      float c0, c1;
+      input_pixel(a, p, by, bx, idx, c0, c1);
+      out[(size_t)i * 2 * kP * kP + idx] = (uint16_t)(__float_as_uint(c0) >> 16);
+      out[(size_t)i * 2 * kP * kP + kP * kP + idx] = (uint16_t)(__float_as_uint(c1) >> 16);
+    }
+  }
+}
+
+// ------------------------------------------------------------- training
+
+// z = conv(in) + b, act = relu(z) (rounded to bf16 when round_act); one
+// thread per output element.  The layer-1 input is bf16 (in16).
+__global__ __launch_bounds__(kThreads) void k_conv_fwd(int N, int Cin, int H, const float* in,
+                                                       const uint16_t* in16, const float* w,
+                                                       const float* b, float* z, float* act,
+                                                       int round_act) {
+  const int Ho = H / 2;
+  const long long total = (long long)N * kC * Ho * Ho;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < total;
+       e += (long long)gridDim.x * kThreads) {
+    const int ox = (int)(e % Ho), oy = (int)((e / Ho) % Ho);
+    const int k = (int)((e / ((long long)Ho * Ho)) % kC);
+    const long long n = e / ((long long)kC * Ho * Ho);
+    float s = b[k];
+    for (int c = 0; c < Cin; ++c) {
+      const size_t ib = ((size_t)n * Cin + c) * H * H;
+      const float* wk = w + ((size_t)k * Cin + c) * 9;
+      for (int ky = 0; ky < 3; ++ky) {
+        const int y = 2 * oy + ky - 1;
+        if (y < 0 || y >= H) continue;
+        for (int kx = 0; kx < 3; ++kx) {
+          const int x = 2 * ox + kx - 1;
+          if (x < 0 || x >= H) continue;
+          const float v = in16 ? bf16_to_f(in16[ib + (size_t)y * H + x]) : in[ib + (size_t)y * H + x];
+          s = fmaf(v, wk[ky * 3 + kx], s);
+        }
+      }
+    }
+    z[e] = s;
+    const float r = fmaxf(s, 0.0f);
+    act[e] = round_act ? bf16_round(r) : r;
+  }
+}
+
+// global average pool and linear head, one thread per sample
+__global__ __launch_bounds__(kThreads) void k_head_fwd(int N, const float* a3, const float* wq,
+                                                       float* g, float* y) {
+  const int n = blockIdx.x * kThreads + threadIdx.x;
+  if (n >= N) return;
+  float gv[kC];
+  for (int c = 0; c < kC; ++c) {
+    float s = 0.0f;
+    for (int q = 0; q < 36; ++q) s += a3[((size_t)n * kC + c) * 36 + q];
+    gv[c] = s * (1.0f / 36.0f);
+    g[(size_t)n * kC + c] = gv[c];
+  }
+  for (int o = 0; o < 2; ++o) {
+    float s = wq[kOffBh + o];
+    for (int c = 0; c < kC; ++c) s = fmaf(gv[c], wq[kOffWh + o * kC + c], s);
+    y[(size_t)n * 2 + o] = s;
+  }
+}
+
+// MSE over N x 2 outputs; gy = d loss / d y; loss to out[0] (single workgroup)
+__global__ __launch_bounds__(kThreads) void k_loss(int N, const float* y, const float* t, float* gy,
+                                                   float* out) {
+  __shared__ double red[kThreads / 64];
+  double s = 0.0;
+  const float scale = 2.0f / (2.0f * (float)N);
+  for (int e = threadIdx.x; e < 2 * N; e += kThreads) {
+    const float d = y[e] - t[e];
+    gy[e] = scale * d;
+    s += (double)d * d;
+  }
+  s = wave_sum(s);
+  if (lane_id() == 0) red[wave_id()] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = (float)((((red[0] + red[1]) + red[2]) + red[3]) / (2.0 * N));
+}
+
+// deterministic workgroup reduction of one float per thread (float64 partials)
+static __device__ __forceinline__ float block_sum_f(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane_id() == 0) red[wave_id()] = v;
+  __syncthreads();
+  const double t = ((red[0] + red[1]) + red[2]) + red[3];
+  __syncthreads();
+  return (float)t;
+}
+
+// head gradients: workgroup per (o, c) weight, then per bias
+__global__ __launch_bounds__(kThreads) void k_head_wgrad(int N, const float* gy, const float* g,
+                                                         float* grad) {
+  __shared__ double red[kThreads / 64];
+  const int e = blockIdx.x;                // 0..63 weights, 64..65 biases
+  const int o = e < 64 ? e / kC : e - 64, c = e < 64 ? e % kC : -1;
+  double s = 0.0;
+  for (int n = threadIdx.x; n < N; n += kThreads)
+    s += (double)gy[(size_t)n * 2 + o] * (c >= 0 ? (double)g[(size_t)n * kC + c] : 1.0);
+  const float v = block_sum_f(s, red);
+  if (threadIdx.x == 0) grad[e < 64 ? kOffWh + e : kOffBh + o] = v;
+}
+
+// d loss / d z3 through the head, the pool and the last ReLU
+__global__ __launch_bounds__(kThreads) void k_head_back(int N, const float* gy, const float* wq,
+                                                        const float* z3, float* gz3) {
+  const long long total = (long long)N * kC * 36;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < total;
+       e += (long long)gridDim.x * kThreads) {
+    const long long n = e / (kC * 36);
+    const int c = (int)((e / 36) % kC);
+    const float gg = gy[n * 2] * wq[kOffWh + c] + gy[n * 2 + 1] * wq[kOffWh + kC + c];
+    gz3[e] = z3[e] > 0.0f ? gg * (1.0f / 36.0f) : 0.0f;
+  }
+}
+
+// input gradient of a convolution, times the ReLU mask of the layer below:
+// gz_in[n][c][y][x] = (z_in > 0) * sum_k sum_taps gz[n][k][oy][ox] w[k][c][ky][kx]
+__global__ __launch_bounds__(kThreads) void k_conv_dgrad(int N, int Cin, int H, const float* gz,
+                                                         const float* w, const float* z_in,
+                                                         float* gz_in) {
+  const int Ho = H / 2;
+  const long long total = (long long)N * Cin * H * H;
+  for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < total;
+       e += (long long)gridDim.x * kThreads) {
+    if (!(z_in[e] > 0.0f)) { gz_in[e] = 0.0f; continue; }
+    const int x = (int)(e % H), y = (int)((e / H) % H);
+    const int c = (int)((e / ((long long)H * H)) % Cin);
+    const long long n = e / ((long long)Cin * H * H);
+    float s = 0.0f;
+    for (int ky = 0; ky < 3; ++ky) {
+      const int ty = y + 1 - ky;
+      if (ty < 0 || (ty & 1) || ty / 2 >= Ho) continue;
+      const int oy = ty / 2;
+      for (int kx = 0; kx < 3; ++kx) {
+        const int tx = x + 1 - kx;
+        if (tx < 0 || (tx & 1) || tx / 2 >= Ho) continue;
+        const int ox = tx / 2;
+        for (int k = 0; k < kC; ++k)
+          s = fmaf(gz[(((size_t)n * kC + k) * Ho + oy) * Ho + ox], w[((size_t)k * Cin + c) * 9 + ky * 3 + kx], s);
+      }
+    }
+    gz_in[e] = s;
+  }
+}
+
+// weight and bias gradients of a convolution: one workgroup per weight
+// (K * Cin * 9 of them) followed by one per bias
+__global__ __launch_bounds__(kThreads) void k_conv_wgrad(int N, int Cin, int H, const float* gz,
+                                                         const float* in, const uint16_t* in16,
+                                                         float* gw, float* gb) {
+  __shared__ double red[kThreads / 64];
+  const int Ho = H / 2;
+  const int nw = kC * Cin * 9;
+  const int e = blockIdx.x;
+  double s = 0.0;
+  const long long cnt = (long long)N * Ho * Ho;
+  if (e < nw) {
+    const int k = e / (Cin * 9), c = (e / 9) % Cin, ky = (e % 9) / 3, kx = e % 3;
+    for (long long t = threadIdx.x; t < cnt; t += kThreads) {
+      const int ox = (int)(t % Ho), oy = (int)((t / Ho) % Ho);
+      const long long n = t / ((long long)Ho * Ho);
+      const int y = 2 * oy + ky - 1, x = 2 * ox + kx - 1;
+      if (y < 0 || y >= H || x < 0 || x >= H) continue;
+      const size_t ii = (((size_t)n * Cin + c) * H + y) * H + x;
+      const float v = in16 ? bf16_to_f(in16[ii]) : in[ii];
+      s += (double)gz[(((size_t)n * kC + k) * Ho + oy) * Ho + ox] * v;
+    }
+  } else {
+    const int k = e - nw;
+    for (long long t = threadIdx.x; t < cnt; t += kThreads) {
+      const long long n = t / ((long long)Ho * Ho);
+      const int q = (int)(t % ((long long)Ho * Ho));
+      s += gz[((size_t)n * kC + k) * Ho * Ho + q];
+    }
+  }
+  const float v = block_sum_f(s, red);
+  if (threadIdx.x == 0) {
+    if (e < nw) gw[e] = v; else gb[e - nw] = v;
+  }
+}
+
+// Adam on the FP32 master parameters; refreshes the bf16-rounded copy
+__global__ __launch_bounds__(kThreads) void k_adam(float* prm, const float* grad, float* m, float* v,
+                                                   float* wq, float lr, float b1, float b2, float eps,
+                                                   float bc1, float bc2) {
+  const int k = blockIdx.x * kThreads + threadIdx.x;
+  if (k >= kNParams) return;
+  const float gk = grad[k];
+  const float mk = b1 * m[k] + (1.0f - b1) * gk;
+  const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+  m[k] = mk;
+  v[k] = vk;
+  const float w = prm[k] - lr * (mk / bc1) / (sqrtf(vk / bc2) + eps);
+  prm[k] = w;
+  wq[k] = is_conv_weight(k) ? bf16_round(w) : w;
+}
+
+__global__ __launch_bounds__(kThreads) void k_quantize(const float* prm, float* wq) {
+  const int k = blockIdx.x * kThreads + threadIdx.x;
+  if (k < kNParams) wq[k] = is_conv_weight(k) ? bf16_round(prm[k]) : prm[k];
+}
+
+// He-uniform initialisation from a counter-based generator (splitmix64 of
+// seed + index), zero biases
+__global__ __launch_bounds__(kThreads) void k_cnn_init(float* prm, unsigned long long seed) {
+  const int k = blockIdx.x * kThreads + threadIdx.x;
+  if (k >= kNParams) return;
+  float lim = 0.0f;
+  if (k < kOffB1) lim = sqrtf(6.0f / 18.0f);
+  else if (k >= kOffW2 && k < kOffB2) lim = sqrtf(6.0f / 288.0f);
+  else if (k >= kOffW3 && k < kOffB3) lim = sqrtf(6.0f / 288.0f);
+  else if (k >= kOffWh && k < kOffBh) lim = sqrtf(6.0f / 32.0f);
+  unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (unsigned long long)(k + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  const float u01 = (float)(z >> 40) * (1.0f / 16777216.0f);
+  prm[k] = (2.0f * u01 - 1.0f) * lim;
+}
+
+// ------------------------------------------------------------------ gate
+// One workgroup per eligible pending block of the round: the network on the
+// block's window (LDS resident), then the layer choice into gate[i].
+
+struct GateLds {
+  uint16_t in0[2 * kP * kP];         // bf16 input
+  uint16_t a1[kC * 24 * 24];         // bf16 activations
+  float a2[kC * 12 * 12];
+  float a3[kC * 36];
+  float g[kC];
+};
+
+__global__ __launch_bounds__(kThreads) void k_cnn_gate(FrameArgs a, DevParams p, const float* wq,
+                                                       float tau1, float tau2) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ int red[kThreads / 64][2];
+  GateLds& G = *reinterpret_cast<GateLds*>(lds_raw);
+  RoundState* st = a.st;
+  if (st->remaining == 0) return;
+  const int n_lost = st->n_lost;
+  int nq = 0, maxm0 = 0;
+  for (int gi = threadIdx.x; gi < p.prep_grid; gi += kThreads) {
+    nq += a.part[2 * gi];
+    maxm0 = max(maxm0, a.part[2 * gi + 1]);
+  }
+  nq = wave_sum(nq);
+  maxm0 = wave_max(maxm0);
+  if (lane_id() == 0) { red[wave_id()][0] = nq; red[wave_id()][1] = maxm0; }
+  __syncthreads();
+  nq = 0; maxm0 = 0;
+  for (int w = 0; w < kThreads / 64; ++w) { nq += red[w][0]; maxm0 = max(maxm0, red[w][1]); }
+  const int tid = threadIdx.x;
+  for (int i = blockIdx.x; i < n_lost; i += gridDim.x) {
+    if (a.bstate[i] != 0) continue;
+    const int m0c = a.m0cnt[i];
+    if (!(nq > 0 ? (m0c >= p.r * p.B) : (m0c == maxm0))) continue;
+    const int cell = a.blk[i];
+    const int by = cell / p.gw, bx = cell - by * p.gw;
+    for (int idx = tid; idx < kP * kP; idx += kThreads) {
+      float c0, c1;
+      input_pixel(a, p, by, bx, idx, c0, c1);
+      G.in0[idx] = (uint16_t)(__float_as_uint(c0) >> 16);
+      G.in0[kP * kP + idx] = (uint16_t)(__float_as_uint(c1) >> 16);
+    }
+    __syncthreads();
+    // conv1: 2 -> 32, 48 -> 24
+    for (int e = tid; e < kC * 24 * 24; e += kThreads) {
+      const int k = e / 576, oy = (e / 24) % 24, ox = e % 24;
+      float s = wq[kOffB1 + k];
+      for (int c = 0; c < 2; ++c)
+        for (int ky = 0; ky < 3; ++ky) {
+          const int y = 2 * oy + ky - 1;
+          if (y < 0 || y >= kP) continue;
+          for (int kx = 0; kx < 3; ++kx) {
+            const int x = 2 * ox + kx - 1;
+            if (x < 0 || x >= kP) continue;
+            s = fmaf(bf16_to_f(G.in0[c * kP * kP + y * kP + x]), wq[kOffW1 + (k * 2 + c) * 9 + ky * 3 + kx], s);
+          }
+        }
+      G.a1[e] = (uint16_t)(__float_as_uint(bf16_round(fmaxf(s, 0.0f))) >> 16);
+    }
+    __syncthreads();
+    // conv2: 32 -> 32, 24 -> 12
+    for (int e = tid; e < kC * 144; e += kThreads) {
+      const int k = e / 144, oy = (e / 12) % 12, ox = e % 12;
+      float s = wq[kOffB2 + k];
+      for (int c = 0; c < kC; ++c) {
+        const float* wk = wq + kOffW2 + (k * kC + c) * 9;
+        for (int ky = 0; ky < 3; ++ky) {
+          const int y = 2 * oy + ky - 1;
+          if (y < 0 || y >= 24) continue;
+          for (int kx = 0; kx < 3; ++kx) {
+            const int x = 2 * ox + kx - 1;
+            if (x < 0 || x >= 24) continue;
+            s = fmaf(bf16_to_f(G.a1[c * 576 + y * 24 + x]), wk[ky * 3 + kx], s);
+          }
+        }
+      }
+      G.a2[e] = bf16_round(fmaxf(s, 0.0f));
+    }
+    __syncthreads();
+    // conv3: 32 -> 32, 12 -> 6
+    for (int e = tid; e < kC * 36; e += kThreads) {
+      const int k = e / 36, oy = (e / 6) % 6, ox = e % 6;
+      float s = wq[kOffB3 + k];
+      for (int c = 0; c < kC; ++c) {
+        const float* wk = wq + kOffW3 + (k * kC + c) * 9;
+        for (int ky = 0; ky < 3; ++ky) {
+          const int y = 2 * oy + ky - 1;
+          if (y < 0 || y >= 12) continue;
+          for (int kx = 0; kx < 3; ++kx) {
+            const int x = 2 * ox + kx - 1;
+            if (x < 0 || x >= 12) continue;
+            s = fmaf(G.a2[c * 144 + y * 12 + x], wk[ky * 3 + kx], s);
+          }
+        }
+      }
+      G.a3[e] = fmaxf(s, 0.0f);
+    }
+    __syncthreads();
+    if (tid < kC) {
+      float s = 0.0f;
+      for (int q = 0; q < 36; ++q) s += G.a3[tid * 36 + q];
+      G.g[tid] = s * (1.0f / 36.0f);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      float y0 = wq[kOffBh], y1 = wq[kOffBh + 1];
+      for (int c = 0; c < kC; ++c) {
+        y0 = fmaf(G.g[c], wq[kOffWh + c], y0);
+        y1 = fmaf(G.g[c], wq[kOffWh + kC + c], y1);
+      }
+      a.gate[i] = (int8_t)(y0 <= tau1 ? SKM_LAYER_BRL : (y1 > tau2 ? SKM_LAYER_HQL : SKM_LAYER_IDL));
+      if (a.gate_pred) { a.gate_pred[2 * i] = y0; a.gate_pred[2 * i + 1] = y1; }
+    }
+    __syncthreads();
+  }
+}
+
+// -------------------------------------------------------------- launchers
+
+static int cgrid(long long work) {
+  long long g = (work + kThreads - 1) / kThreads;
+  return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
+}
+
+hipError_t launch_cnn_inputs(const FrameArgs& a, const DevParams& p, uint16_t* out, int max_blocks,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_cnn_inputs, dim3(max_blocks < 1 ? 1 : (max_blocks > 4096 ? 4096 : max_blocks)),
+                     dim3(kThreads), 0, s, a, p, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cnn_gate(const FrameArgs& a, const DevParams& p, const float* wq, float tau1,
+                           float tau2, int max_blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_cnn_gate, dim3(max_blocks < 1 ? 1 : (max_blocks > 2048 ? 2048 : max_blocks)),
+                     dim3(kThreads), sizeof(GateLds), s, a, p, wq, tau1, tau2);
+  return hipGetLastError();
+}
+
+size_t cnn_gate_lds_bytes() { return sizeof(GateLds); }
+
+hipError_t set_cnn_gate_lds_limit(size_t bytes) {
+  return hipFuncSetAttribute((const void*)k_cnn_gate, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+hipError_t cnn_init(float* prm, float* wq, unsigned long long seed, hipStream_t s) {
+  hipLaunchKernelGGL(k_cnn_init, dim3(cgrid(kNParams)), dim3(kThreads), 0, s, prm, seed);
+  hipLaunchKernelGGL(k_quantize, dim3(cgrid(kNParams)), dim3(kThreads), 0, s, prm, wq);
+  return hipGetLastError();
+}
+
+hipError_t cnn_quantize(const float* prm, float* wq, hipStream_t s) {
+  hipLaunchKernelGGL(k_quantize, dim3(cgrid(kNParams)), dim3(kThreads), 0, s, prm, wq);
+  return hipGetLastError();
+}
+
+hipError_t cnn_forward(const CnnBuffers& b, const float* wq, const uint16_t* x, int N, hipStream_t s) {
+  hipLaunchKernelGGL(k_conv_fwd, dim3(cgrid((long long)N * kC * 576)), dim3(kThreads), 0, s, N, 2, 48,
+                     (const float*)nullptr, x, wq + kOffW1, wq + kOffB1, b.z1, b.a1, 1);
+  hipLaunchKernelGGL(k_conv_fwd, dim3(cgrid((long long)N * kC * 144)), dim3(kThreads), 0, s, N, kC, 24,
+                     (const float*)b.a1, (const uint16_t*)nullptr, wq + kOffW2, wq + kOffB2, b.z2, b.a2, 1);
+  hipLaunchKernelGGL(k_conv_fwd, dim3(cgrid((long long)N * kC * 36)), dim3(kThreads), 0, s, N, kC, 12,
+                     (const float*)b.a2, (const uint16_t*)nullptr, wq + kOffW3, wq + kOffB3, b.z3, b.a3, 0);
+  hipLaunchKernelGGL(k_head_fwd, dim3((N + kThreads - 1) / kThreads), dim3(kThreads), 0, s, N,
+                     (const float*)b.a3, wq, b.g, b.y);
+  return hipGetLastError();
+}
+
+hipError_t cnn_backward(const CnnBuffers& b, const float* wq, const uint16_t* x, const float* t,
+                        int N, float* grad, float* loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_loss, dim3(1), dim3(kThreads), 0, s, N, (const float*)b.y, t, b.gy, loss);
+  hipLaunchKernelGGL(k_head_wgrad, dim3(66), dim3(kThreads), 0, s, N, (const float*)b.gy,
+                     (const float*)b.g, grad);
+  hipLaunchKernelGGL(k_head_back, dim3(cgrid((long long)N * kC * 36)), dim3(kThreads), 0, s, N,
+                     (const float*)b.gy, wq, (const float*)b.z3, b.gz3);
+  hipLaunchKernelGGL(k_conv_wgrad, dim3(kC * kC * 9 + kC), dim3(kThreads), 0, s, N, kC, 12,
+                     (const float*)b.gz3, (const float*)b.a2, (const uint16_t*)nullptr, grad + kOffW3,
+                     grad + kOffB3);
+  hipLaunchKernelGGL(k_conv_dgrad, dim3(cgrid((long long)N * kC * 144)), dim3(kThreads), 0, s, N, kC,
+                     12, (const float*)b.gz3, wq + kOffW3, (const float*)b.z2, b.gz2);
+  hipLaunchKernelGGL(k_conv_wgrad, dim3(kC * kC * 9 + kC), dim3(kThreads), 0, s, N, kC, 24,
+                     (const float*)b.gz2, (const float*)b.a1, (const uint16_t*)nullptr, grad + kOffW2,
+                     grad + kOffB2);
+  hipLaunchKernelGGL(k_conv_dgrad, dim3(cgrid((long long)N * kC * 576)), dim3(kThreads), 0, s, N, kC,
+                     24, (const float*)b.gz2, wq + kOffW2, (const float*)b.z1, b.gz1);
+  hipLaunchKernelGGL(k_conv_wgrad, dim3(kC * 2 * 9 + kC), dim3(kThreads), 0, s, N, 2, 48,
+                     (const float*)b.gz1, (const float*)nullptr, x, grad + kOffW1, grad + kOffB1);
+  return hipGetLastError();
+}
+
+hipError_t cnn_adam(float* prm, const float* grad, float* m, float* v, float* wq, float lr, int step,
+                    hipStream_t s) {
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float bc1 = 1.0f - powf(b1, (float)step), bc2 = 1.0f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(cgrid(kNParams)), dim3(kThreads), 0, s, prm, grad, m, v, wq, lr,
+                     b1, b2, 1e-8f, bc1, bc2);
+  return hipGetLastError();
+}
+
+}  // namespace skm

@@ -31,6 +31,7 @@ struct DevParams {
   int radii[kMaxRadii];
   int min_pct, min_hql, mode;
   int prep_grid;   // workgroups of the prep kernel
+  int cnn_active;  // CNN mode with a loaded network (else the profile rule)
   int width, height, stride;
   int gh, gw;      // full cells
   double sigma2, t_phi, log_tnu, ridge_rel;
@@ -65,6 +66,8 @@ struct FrameArgs {
   int* m0cnt;
   int* part;              // 2 * kPrepGridMax prep partials
   int* hql_list;          // lost-block indices waiting for HQL in this round
+  int8_t* gate;           // CNN mode: layer chosen for each lost block
+  float* gate_pred;       // CNN mode: the two predicted gains of each lost block
   RoundState* st;
   skm_block_info* info;   // optional
   float* xhat;            // optional
@@ -85,6 +88,27 @@ hipError_t launch_fill(const FrameArgs& a, const DevParams& p, int max_blocks,
 hipError_t launch_dist(const FrameArgs& a, const DevParams& p, int max_blocks,
                        hipStream_t s);
 hipError_t set_main_lds_limit(size_t bytes);
+// CNN gate (skm_cnn.hip)
+constexpr int kCnnParams = 19170;
+struct CnnBuffers {
+  float *z1, *a1, *z2, *a2, *z3, *a3, *g, *y, *gy, *gz3, *gz2, *gz1;
+};
+constexpr size_t kCnnFloatsPerSample = 2 * 32 * 576 + 2 * 32 * 144 + 2 * 32 * 36 + 32 + 2 + 2 +
+                                       32 * 36 + 32 * 144 + 32 * 576;
+hipError_t launch_cnn_inputs(const FrameArgs& a, const DevParams& p, uint16_t* out, int max_blocks,
+                             hipStream_t s);
+hipError_t launch_cnn_gate(const FrameArgs& a, const DevParams& p, const float* wq, float tau1,
+                           float tau2, int max_blocks, hipStream_t s);
+size_t cnn_gate_lds_bytes();
+hipError_t set_cnn_gate_lds_limit(size_t bytes);
+hipError_t cnn_init(float* prm, float* wq, unsigned long long seed, hipStream_t s);
+hipError_t cnn_quantize(const float* prm, float* wq, hipStream_t s);
+hipError_t cnn_forward(const CnnBuffers& b, const float* wq, const uint16_t* x, int N, hipStream_t s);
+hipError_t cnn_backward(const CnnBuffers& b, const float* wq, const uint16_t* x, const float* t,
+                        int N, float* grad, float* loss, hipStream_t s);
+hipError_t cnn_adam(float* prm, const float* grad, float* m, float* v, float* wq, float lr, int step,
+                    hipStream_t s);
+
 // HQL (skm_hql.hip)
 constexpr int kHqlSlots = 128;     // workgroups of the HQL kernel, one scratch slot each
 size_t hql_slot_bytes(const DevParams& p);

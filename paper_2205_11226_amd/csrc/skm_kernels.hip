@@ -221,9 +221,13 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
     const double mean = n0 > 0 ? (double)rs.sum / (double)n0 : 0.0;
     const int relaxed_flag = (!dist_only && nq == 0) ? SKM_FLAG_CTX_RELAXED : 0;
 
-    // BRL gate: context mean for every pixel of the block
-    const bool profile_like = p.mode == SKM_MODE_PROFILE || p.mode == SKM_MODE_CNN;
-    if (!dist_only && (p.mode == SKM_MODE_BRL || (profile_like && (double)phi <= p.t_phi))) {
+    // BRL gate: context mean for every pixel of the block (profile rule, or
+    // the learned gate's choice in CNN mode)
+    const bool cnn = p.mode == SKM_MODE_CNN && p.cnn_active;
+    const int gsel = (cnn && !dist_only) ? (int)a.gate[i] : -1;
+    const bool profile_rule = p.mode == SKM_MODE_PROFILE || (p.mode == SKM_MODE_CNN && !cnn);
+    if (!dist_only && (p.mode == SKM_MODE_BRL || (profile_rule && (double)phi <= p.t_phi) ||
+                       gsel == SKM_LAYER_BRL)) {
       write_const_block(a, p, i, x0, y0, mean);
       if (tid == 0) {
         write_info(a, i, bx, by, SKM_LAYER_BRL, round, -1, -1, 0, relaxed_flag, phi, n0, NAN);
@@ -336,11 +340,11 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
       if (ncand == 0) {
         layer = SKM_LAYER_BRL;
         flags |= SKM_FLAG_NO_CAND;
-      } else if (p.mode == SKM_MODE_FULL) {
+      } else if (p.mode == SKM_MODE_FULL || gsel == SKM_LAYER_HQL) {
         want_hql = true;
-      } else if (p.mode != SKM_MODE_PLAIN) {  // PROFILE, IDL, CNN without a network
+      } else if (p.mode != SKM_MODE_PLAIN) {  // PROFILE, IDL, CNN (IDL choice or no network)
         if (accm) ridx = __ffsll((unsigned long long)accm) - 1;
-        else want_hql = p.mode != SKM_MODE_IDL;
+        else want_hql = p.mode == SKM_MODE_PROFILE || (p.mode == SKM_MODE_CNN && !cnn);
       }
       if (want_hql) {
         if (ncom >= max(2, p.min_hql)) layer = SKM_LAYER_HQL;

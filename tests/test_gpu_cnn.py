@@ -1,0 +1,165 @@
+"""GPU parity of the learned gate (input map, forward, gradients, training,
+CNN-mode concealment) against the float64 reference in oracle/cnn.py."""
+import math
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cnn as ocnn
+from oracle.skmmse import Params, conceal as oracle_conceal, lost_cells
+from tests.parity import compare, device_params, oracle_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2205_11226_amd as skm
+    assert torch.cuda.is_available()
+    c = skm.Context(0)
+    yield c
+    c.close()
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def bf16_bits_to_float(t):
+    import torch
+    return (t.to(torch.int32) << 16).view(torch.float32).cpu().numpy().astype(np.float64)
+
+
+def frame_inputs(ctx, frame, mask, b=16):
+    p = device_params("profile", block=b)
+    x = ctx.cnn_inputs(to_dev(frame), to_dev(mask), p)
+    ref = np.stack([ocnn.block_input(frame.astype(np.int64), mask == 0, by, bx, b)
+                    for by, bx in lost_cells(mask, b)])
+    return x, ref
+
+
+def test_inputs_match_reference(ctx):
+    f, m = synth.workload_plain_512()
+    x, ref = frame_inputs(ctx, f, m)
+    np.testing.assert_array_equal(bf16_bits_to_float(x), ref)
+    f8 = synth.make_luma(96, 120, 5)
+    m8 = synth.loss_random(96, 120, 8, 0.3, 6)
+    x8, ref8 = frame_inputs(ctx, f8, m8, 8)
+    np.testing.assert_array_equal(bf16_bits_to_float(x8), ref8)
+
+
+def test_forward_matches_reference(ctx):
+    f, m = synth.workload_plain_512()
+    x, ref = frame_inputs(ctx, f, m)
+    params = ocnn.init_params(11)
+    for k in ("b1", "b2", "b3", "bh"):
+        params[k] = np.random.default_rng(2).normal(0, 0.05, size=params[k].shape)
+    w = ocnn.pack(params).astype(np.float32)
+    ctx.cnn_set_weights(w)
+    y = ctx.cnn_forward(x).cpu().numpy().astype(np.float64)
+    yo = ocnn.forward(ocnn.unpack(w.astype(np.float64)), ref)
+    err = np.abs(y - yo)
+    print("forward max err", err.max(), "scale", np.abs(yo).max(), flush=True)
+    assert (err <= 5e-3 + 1e-2 * np.abs(yo)).all(), err.max()
+
+
+def test_gradients_match_reference(ctx):
+    import torch
+    f, m = synth.workload_plain_512()
+    x, ref = frame_inputs(ctx, f, m)
+    x, ref = x[:24], ref[:24]
+    params = ocnn.init_params(12)
+    w = ocnn.pack(params).astype(np.float32)
+    ctx.cnn_set_weights(w)
+    t = np.random.default_rng(4).normal(0, 1, size=(24, 2))
+    loss, g = ctx.cnn_gradients(x, torch.from_numpy(t.astype(np.float32)).cuda())
+    lo, go = ocnn.loss_and_grads(ocnn.unpack(w.astype(np.float64)), ref, t)
+    assert abs(loss - lo) <= 1e-3 * max(1.0, lo)
+    gg = ocnn.unpack(g.astype(np.float64))
+    for k in ocnn.ORDER:
+        rel = np.linalg.norm(gg[k] - go[k]) / max(np.linalg.norm(go[k]), 1e-12)
+        print(k, "grad rel err", rel, flush=True)
+        assert rel <= 2e-2, (k, rel)
+
+
+def test_training_reduces_loss(ctx):
+    import torch
+    f, m = synth.workload_plain_512()
+    x, ref = frame_inputs(ctx, f, m)
+    teacher = ocnn.init_params(21)
+    tgt = ocnn.forward(teacher, ref)                      # learnable targets
+    tgt = (tgt - tgt.mean(0)) / (tgt.std(0) + 1e-9)
+    tt = torch.from_numpy(tgt.astype(np.float32)).cuda()
+    ctx.cnn_init(5)
+    first = ctx.cnn_train_step(x, tt, 3e-3)
+    for _ in range(150):
+        last = ctx.cnn_train_step(x, tt, 3e-3)
+    print("loss", first, "->", last, flush=True)
+    assert last < 0.5 * first
+
+
+def test_save_load_roundtrip(ctx):
+    ctx.cnn_init(7)
+    ctx.cnn_set_thresholds(0.25, 0.5)
+    w = ctx.cnn_get_weights()
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "g.bin")
+        ctx.cnn_save(path)
+        ctx.cnn_init(8)
+        ctx.cnn_load(path)
+    np.testing.assert_array_equal(ctx.cnn_get_weights(), w)
+
+
+@pytest.mark.parametrize("workload", ["plain_512", "random_b8"])
+def test_cnn_mode_parity(ctx, workload):
+    """Concealment in CNN mode: the oracle runs the same network (float64)
+    on its own inputs; decisions may differ only within 1e-3 dB of a
+    threshold."""
+    if workload == "plain_512":
+        f, m = synth.workload_plain_512()
+        kw = dict()
+    else:
+        f = synth.make_luma(120, 152, 33, n_bumps=10, n_edges=5)
+        m = synth.loss_random(120, 152, 8, 0.3, 34)
+        kw = dict(block=8)
+    params = ocnn.init_params(31)
+    w = ocnn.pack(params).astype(np.float32)
+    ctx.cnn_set_weights(w)
+    pw = ocnn.unpack(w.astype(np.float64))
+    b = kw.get("block", 16)
+    # thresholds at quantiles of the predictions on the received frame, so
+    # that all three layers occur
+    y_all = ocnn.forward(pw, np.stack([ocnn.block_input(f.astype(np.int64), m == 0, by, bx, b)
+                                       for by, bx in lost_cells(m, b)]))
+    tau1 = float(np.quantile(y_all[:, 0], 0.3))
+    tau2 = float(np.quantile(y_all[y_all[:, 0] > tau1, 1], 0.5))
+    ctx.cnn_set_thresholds(tau1, tau2)
+    near = {}
+
+    def gate(u, avail, by, bx):
+        y = ocnn.forward(pw, ocnn.block_input(u, avail, by, bx, b)[None])[0]
+        if min(abs(y[0] - tau1), abs(y[1] - tau2)) < 1e-3:
+            near[(by, bx)] = True
+        return 0 if y[0] <= tau1 else (2 if y[1] > tau2 else 1)
+
+    pg = device_params("cnn", **kw)
+    out, info, xh = ctx.conceal_device(to_dev(f), to_dev(m), pg)
+    out_o, xh_o, info_o = oracle_conceal(f, m, Params(mode="cnn", **kw), cnn_gate=gate)
+    byk = {(int(i["by"]), int(i["bx"])): k for k, i in enumerate(info)}
+    layers = {}
+    for io in info_o:
+        key = (io["by"], io["bx"])
+        ig = info[byk[key]]
+        if key in near:
+            continue
+        assert int(ig["layer"]) == io["layer"], (key, int(ig["layer"]), io)
+        layers[io["layer"]] = layers.get(io["layer"], 0) + 1
+        err = float(np.abs(xh.cpu().numpy()[byk[key]].astype(np.float64) - xh_o[key]).max())
+        assert err <= 1e-3, (key, err)
+    print(workload, "layers", layers, "near", len(near), flush=True)
+    assert len(layers) == 3
