@@ -6,7 +6,9 @@ ABI (loss geometry, rounds, context/flatness gate, candidate distances,
 weights, weighted averages, write-back), with the frame and mask already in
 HBM.  Prints ONE JSON line.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode profile]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode cnn|profile|plain|...]
+       python bench.py --traffic-run --steps 3          (under rocprofv3 --pmc)
+       python bench.py --traffic-parse FETCH_DIR WRITE_DIR OUT.json
 """
 from __future__ import annotations
 
@@ -35,36 +37,63 @@ KERNEL = "k_round_main"
 _CPU = {}
 
 
-def _cpu_init(frame, mask, mode, t_nu):
+def read_gate(path):
+    """Thresholds and float32 weights of a gate file written by skm_save_cnn:
+    8-byte magic, four uint32 (version, count, 0, 0), two float32 thresholds,
+    then the weights, all little-endian."""
+    raw = open(path, "rb").read()
+    if raw[:8] != b"SKMGATE1":
+        raise ValueError(f"{path}: not a gate weight file")
+    hdr = np.frombuffer(raw, "<u4", 4, 8)
+    tau = np.frombuffer(raw, "<f4", 2, 24).astype(np.float64)
+    w = np.frombuffer(raw, "<f4", int(hdr[1]), 32).astype(np.float64)
+    return float(tau[0]), float(tau[1]), w
+
+
+def _cpu_init(frame, mask, mode, t_nu, gate_path):
     import oracle.skmmse as o
     _CPU["f"] = frame.astype(np.int64)
     _CPU["a"] = mask == 0
     _CPU["p"] = o.Params(mode=mode, t_nu=t_nu)
     _CPU["est"] = o.estimate_block
+    _CPU["gate"] = None
+    if mode == "cnn":
+        import oracle.cnn as oc
+        t1, t2, w = read_gate(gate_path)
+        pw = oc.unpack(w)
+
+        def gate(u, avail, by, bx):
+            y = oc.forward(pw, oc.block_input(u, avail, by, bx, 16)[None])[0]
+            return 0 if y[0] <= t1 else (2 if y[1] > t2 else 1)
+        _CPU["gate"] = gate
 
 
 def _cpu_work(cells):
     for by, bx in cells:
-        _CPU["est"](_CPU["f"], _CPU["a"], by, bx, _CPU["p"])
+        _CPU["est"](_CPU["f"], _CPU["a"], by, bx, _CPU["p"], _CPU["gate"])
     return len(cells)
 
 
-def cpu_baseline(frame, mask, mode, t_nu, workers):
-    """Time the float64 oracle on every lost block of the frame (one round:
-    all blocks are independent) over a process pool of ``workers``."""
+def cpu_baseline(frame, mask, mode, t_nu, workers, gate_path, frac=1.0):
+    """Time the float64 oracle on the lost blocks of the frame (one round: all
+    blocks are independent) over a process pool of ``workers``; ``frac`` keeps
+    an evenly spaced share of the blocks."""
     import multiprocessing as mp
     from oracle.skmmse import lost_cells
     cells = lost_cells(mask, 16)
+    step = max(1, int(round(1.0 / frac)))
+    cells = cells[::step]
     chunks = [cells[i::workers * 4] for i in range(workers * 4)]
     ctx = mp.get_context("fork")
-    with ctx.Pool(workers, initializer=_cpu_init, initargs=(frame, mask, mode, t_nu)) as pool:
-        pool.map(_cpu_work, chunks[:workers])           # warm the workers
+    with ctx.Pool(workers, initializer=_cpu_init,
+                  initargs=(frame, mask, mode, t_nu, gate_path)) as pool:
+        pool.map(_cpu_work, [c[:2] for c in chunks[:workers]])     # warm the workers
         t0 = time.perf_counter()
         n = sum(pool.map(_cpu_work, chunks))
         dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "blocks/s", "cores": workers, "kind": "oracle",
-            "sample": f"all {n} lost blocks of the 1080p frame, float64 NumPy oracle, "
-                      f"mode={mode}, {workers} worker processes, {dt:.2f} s wall"}
+            "sample": f"{n} of the lost blocks of the 1080p frame (every {step}), float64 "
+                      f"NumPy oracle, mode={mode}, {workers} worker processes, {dt:.2f} s wall"}
 
 
 # ------------------------------------------------------------ algorithmic
@@ -127,6 +156,8 @@ def main():
     ap.add_argument("--profile", default="efficient")
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-run", action="store_true",
+                    help="only conceal --steps frames and copy a known size (counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -136,12 +167,13 @@ def main():
 
     t_nu = {"express": 0.01, "efficient": 0.1, "excellent": 100.0}[args.profile]
     frame, mask = synth.workload_layered_1080p()
+    if args.traffic_run:
+        return traffic_run(args, frame, mask)
 
     cpu = None
     if not args.no_cpu_baseline:
         workers = args.cpu_workers or max(1, min(os.cpu_count() or 1, 16))
-        cpu = cpu_baseline(frame, mask, "plain" if args.mode == "cnn" else args.mode, t_nu,
-                           workers)
+        cpu = cpu_baseline(frame, mask, args.mode, t_nu, workers, args.weights)
         print(f"# cpu baseline: {cpu['value']:.1f} blocks/s on {workers} cores", file=sys.stderr,
               flush=True)
 
@@ -163,31 +195,34 @@ def main():
         for _ in range(k):
             ctx.conceal_device(fd, md, p, out=out, want_info=False, want_xhat=False)
 
-    def timed(p):
+    def timed(p, events=False):
         run(p, args.warmup)
         torch.cuda.synchronize()
+        ctx.profile_enable(events)
+        ctx.profile_read()                  # drop earlier event pairs
         t0 = time.perf_counter()
         run(p, args.steps)
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / args.steps
+        dt = (time.perf_counter() - t0) / args.steps
+        ctx.profile_enable(False)
+        return dt
 
-    sec_lay = timed(p_lay)
-    print(f"# layered: {sec_lay * 1e3:.3f} ms/frame", file=sys.stderr, flush=True)
+    # the estimation kernel is bracketed by HIP events on its own stream
+    # during the timed steps of the headline configuration
+    sec_lay = timed(p_lay, events=True)
+    ms_tot, launches = ctx.profile_read()
+    k_ms = ms_tot / max(launches, 1)
+    print(f"# layered ({args.mode}): {sec_lay * 1e3:.3f} ms/frame, estimation kernel "
+          f"{k_ms * 1e3:.1f} us x {launches / args.steps:.0f} per frame", file=sys.stderr, flush=True)
     sec_plain = timed(p_plain)
     print(f"# plain: {sec_plain * 1e3:.3f} ms/frame", file=sys.stderr, flush=True)
     sec_prof = timed(p_prof)
     print(f"# profile rule: {sec_prof * 1e3:.3f} ms/frame", file=sys.stderr, flush=True)
 
-    # live kernel timing of the estimation kernel (events on its own stream)
-    ctx.profile_enable(True)
-    run(p_lay, args.steps)
-    ms_tot, launches = ctx.profile_read()
-    ctx.profile_enable(False)
-    k_ms = ms_tot / max(launches, 1)
-
-    # statistics of one layered and one plain frame (not timed)
+    # statistics of one frame per mode (not timed)
     o_lay, info_lay, _ = ctx.conceal_device(fd, md, p_lay, want_xhat=False)
     o_prof, info_prof, _ = ctx.conceal_device(fd, md, p_prof, want_xhat=False)
+    o_plain, _, _ = ctx.conceal_device(fd, md, p_plain, want_xhat=False)
     o_full, _, _ = ctx.conceal_device(fd, md, skm.default_params(mode="full"), want_xhat=False)
     d_tab, n_tab = ctx.distances_device(fd, md, p_plain)
     d_tab, n_tab = d_tab.cpu().numpy(), n_tab.cpu().numpy()
@@ -197,9 +232,11 @@ def main():
     ps_lay = psnr(o_lay.cpu().numpy(), frame)
     ps_full = psnr(o_full.cpu().numpy(), frame)
     ps_prof = psnr(o_prof.cpu().numpy(), frame)
-    lay_prof = np.bincount(info_prof["layer"] + 1, minlength=4)
-    layers = np.bincount(info_lay["layer"] + 1, minlength=4)
-    traffic = traffic_from_profile(kernel_source_hash())
+    ps_plain = psnr(o_plain.cpu().numpy(), frame)
+
+    def layer_counts(info):
+        c = np.bincount(info["layer"] + 1, minlength=4)
+        return {"brl": int(c[1]), "idl": int(c[2]), "hql": int(c[3]), "fill": int(c[0])}
 
     res = {
         "metric": METRIC,
@@ -216,21 +253,20 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "1920x1080 luma (150 bumps, 40 edges, texture), 25% dispersed "
-                        "16x16 loss (2040 blocks), single frame per step",
+                        "16x16 loss (2040 blocks), one frame per step",
             "mode": args.mode, "profile": args.profile,
             "lost_blocks": n_lost,
             "frames_per_s": 1.0 / sec_lay,
-            "plain_blocks_per_s": n_lost / sec_plain,
-            "plain_ms_per_frame": sec_plain * 1e3,
-            "speedup_vs_plain": sec_plain / sec_lay,
             "psnr_layered_db": ps_lay,
             "psnr_full_kmmse_db": ps_full,
             "delta_psnr_db": ps_full - ps_lay,
-            "layers": {"brl": int(layers[1]), "idl": int(layers[2]), "hql": int(layers[3])},
+            "layers": layer_counts(info_lay),
+            "plain": {"blocks_per_s": n_lost / sec_plain, "ms_per_frame": sec_plain * 1e3,
+                      "delta_psnr_db": ps_full - ps_plain},
+            "speedup_vs_plain": sec_plain / sec_lay,
             "profile_rule": {"blocks_per_s": n_lost / sec_prof, "ms_per_frame": sec_prof * 1e3,
                              "delta_psnr_db": ps_full - ps_prof,
-                             "layers": {"brl": int(lay_prof[1]), "idl": int(lay_prof[2]),
-                                        "hql": int(lay_prof[3])}},
+                             "layers": layer_counts(info_prof)},
         },
         "roofline": {
             "kernel": KERNEL,
@@ -239,7 +275,7 @@ def main():
             "peak": VALU_PEAK_TOPS,
             "unit": "TOP/s",
             "frac": achieved / VALU_PEAK_TOPS,
-            "traffic": traffic,
+            "traffic": traffic_from_profile(kernel_source_hash()),
             "ops_per_launch": ops,
             "kernel_ms": k_ms,
             "launches_timed": launches,
@@ -250,5 +286,77 @@ def main():
     ctx.close()
 
 
+# ---------------------------------------------------------------- traffic
+#
+# HBM traffic of the estimation kernel comes from two rocprofv3 counter runs
+# of `bench.py --traffic-run` (FETCH_SIZE, then WRITE_SIZE).  Each run also
+# times a plain device-to-device copy of a known size, whose counter reading
+# gives the factor that turns the counter into bytes.
+
+COPY_BYTES = 256 << 20
+
+
+def traffic_run(args, frame, mask):
+    import torch
+    import paper_2205_11226_amd as skm
+    fd = torch.from_numpy(frame).cuda()
+    md = torch.from_numpy(mask).cuda()
+    out = torch.empty_like(fd)
+    ctx = skm.Context(0)
+    if args.mode == "cnn":
+        ctx.cnn_load(args.weights)
+    p = skm.default_params(mode=args.mode, profile=args.profile)
+    for _ in range(args.steps):
+        ctx.conceal_device(fd, md, p, out=out, want_info=False, want_xhat=False)
+    src = torch.ones(COPY_BYTES, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ctx.close()
+    print(f"# traffic run: {args.steps} frames, 3 copies of {COPY_BYTES} bytes", flush=True)
+
+
+def _counter_rows(d):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        rows += list(csv.DictReader(open(f)))
+    if not rows:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    return rows
+
+
+def traffic_parse(fetch_dir, write_dir, out_path):
+    res = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        per = {}
+        for r in _counter_rows(d):
+            if r["Counter_Name"] != counter:
+                continue
+            per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        main = [v for k, v in per.items() if k.startswith(KERNEL)]
+        copy = [v for k, v in per.items() if "copy" in k.lower() and not k.startswith("k_")]
+        if not main or not copy:
+            raise SystemExit(f"{counter}: kernels found {sorted(per)}")
+        main_avg = float(np.mean(main[0]))
+        copy_avg = float(np.mean(copy[0]))
+        # a copy of COPY_BYTES reads and writes COPY_BYTES once each
+        scale = COPY_BYTES / copy_avg
+        res[counter] = {"kernel_counter_avg": main_avg, "copy_counter_avg": copy_avg,
+                        "bytes_per_unit": scale, "bytes": main_avg * scale,
+                        "dispatches": len(main[0])}
+    rec = {"kernel": KERNEL, "kernel_source_sha1": kernel_source_hash(),
+           "bytes_per_launch": res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"],
+           "counters": res}
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "--traffic-parse":
+        traffic_parse(sys.argv[2], sys.argv[3], sys.argv[4])
+    else:
+        main()

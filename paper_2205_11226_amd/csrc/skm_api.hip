@@ -28,6 +28,7 @@ struct skm_ctx {
   int* d_blk = nullptr;
   int* d_bstate = nullptr;
   int* d_m0cnt = nullptr;         size_t cap_cells = 0;
+  int2* d_ring = nullptr;
   int* d_part = nullptr;
   int* d_hql_list = nullptr;
   unsigned char* d_hql_ws = nullptr; size_t cap_hql = 0;
@@ -152,6 +153,7 @@ skm_status ensure_frame(skm_ctx* c, const DevParams& p) {
     (void)hipFree(c->d_blk); c->d_blk = nullptr;
     (void)hipFree(c->d_bstate); c->d_bstate = nullptr;
     (void)hipFree(c->d_m0cnt); c->d_m0cnt = nullptr;
+    (void)hipFree(c->d_ring); c->d_ring = nullptr;
     c->cap_cells = 0;
     if ((s = grow(&c->d_cell_lost, &cap, ncell, "cell table")) != SKM_OK) return s;
     cap = 0;
@@ -160,6 +162,8 @@ skm_status ensure_frame(skm_ctx* c, const DevParams& p) {
     if ((s = grow(&c->d_bstate, &cap, ncell, "block state")) != SKM_OK) return s;
     cap = 0;
     if ((s = grow(&c->d_m0cnt, &cap, ncell, "context counts")) != SKM_OK) return s;
+    cap = 0;
+    if ((s = grow(&c->d_ring, &cap, ncell, "context statistics")) != SKM_OK) return s;
     (void)hipFree(c->d_hql_list); c->d_hql_list = nullptr;
     cap = 0;
     if ((s = grow(&c->d_hql_list, &cap, ncell, "HQL list")) != SKM_OK) return s;
@@ -204,7 +208,7 @@ FrameArgs frame_args(skm_ctx* c, const uint8_t* frame, const uint8_t* mask, uint
   memset(&a, 0, sizeof(a));
   a.frame = frame; a.mask = mask; a.work = out;
   a.val = c->d_val; a.cell_lost = c->d_cell_lost; a.blk = c->d_blk;
-  a.bstate = c->d_bstate; a.m0cnt = c->d_m0cnt; a.part = c->d_part; a.st = c->d_state;
+  a.bstate = c->d_bstate; a.m0cnt = c->d_m0cnt; a.ring = c->d_ring; a.part = c->d_part; a.st = c->d_state;
   a.hql_list = c->d_hql_list;
   a.gate = c->d_gate; a.gate_pred = c->d_gate_pred;
   return a;
@@ -331,6 +335,7 @@ void skm_destroy(skm_ctx* c) {
   (void)hipFree(c->d_blk);
   (void)hipFree(c->d_bstate);
   (void)hipFree(c->d_m0cnt);
+  (void)hipFree(c->d_ring);
   (void)hipFree(c->d_part);
   (void)hipFree(c->d_cnn);
   (void)hipFree(c->d_cnn_loss);
@@ -436,6 +441,7 @@ skm_status skm_distances_device(skm_ctx* c, const uint8_t* d_frame, const uint8_
   if (n_lost) *n_lost = nl;
   if (nl > cap) return fail(SKM_EINVAL, "cap smaller than the number of lost blocks");
   a.dist = d_dist; a.cnt = d_cnt;
+  SKM_HIP(launch_prep(a, p, p.gh * p.gw, st), "prep kernel");   // ring statistics
   SKM_HIP(launch_dist(a, p, p.gh * p.gw, st), "distance kernel");
   SKM_HIP(hipStreamSynchronize(st), "stream synchronize");
   return SKM_OK;
@@ -581,12 +587,12 @@ skm_status skm_cnn_forward(skm_ctx* c, const uint16_t* d_inputs, int32_t n, floa
   if (!c || !d_inputs || !d_out || n < 1) return fail(SKM_EINVAL, "bad argument");
   if (!c->cnn_loaded) return fail(SKM_EINVAL, "no network loaded");
   SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
-  CnnBuffers b;
-  skm_status s = cnn_buffers(c, n, &b);
-  if (s != SKM_OK) return s;
+  if (!c->gate_lds_set) {
+    SKM_HIP(set_cnn_gate_lds_limit(cnn_gate_lds_bytes()), "hipFuncSetAttribute");
+    c->gate_lds_set = true;
+  }
   hipStream_t st = (hipStream_t)hip_stream;
-  SKM_HIP(cnn_forward(b, c->d_cnn + kCnnParams, d_inputs, n, st), "gate forward");
-  SKM_HIP(hipMemcpyAsync(d_out, b.y, sizeof(float) * 2 * n, hipMemcpyDeviceToDevice, st), "copy");
+  SKM_HIP(cnn_infer(d_inputs, n, c->d_cnn + kCnnParams, d_out, st), "gate inference");
   SKM_HIP(hipStreamSynchronize(st), "stream synchronize");
   return SKM_OK;
 }

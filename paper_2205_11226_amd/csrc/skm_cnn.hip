@@ -276,17 +276,205 @@ __global__ __launch_bounds__(kThreads) void k_cnn_init(float* prm, unsigned long
 }
 
 // ------------------------------------------------------------------ gate
-// One workgroup per eligible pending block of the round: the network on the
-// block's window (LDS resident), then the layer choice into gate[i].
+// Inference on MFMA: every convolution is a GEMM of (output positions) x
+// (3x3 taps x input channels) by (taps x channels) x (32 output channels),
+// run as v_mfma_f32_16x16x32_bf16 tiles with FP32 accumulation.  One
+// workgroup (4 waves) owns one block at a time: its input and both hidden
+// activations stay in LDS in a position-major layout (one 80-byte slot of
+// 32 bf16 channels per pixel, padded against bank conflicts) with a zero
+// row and column in front for the convolutions' padding.  The weight
+// fragments of the B operand stay in registers for the workgroup's life.
+//
+// Operand layout of the 16x16x32 MFMA: lane l supplies row (A) or column (B)
+// l % 16 with the eight K values 8 (l / 16) .. 8 (l / 16) + 7; it receives
+// D rows 4 (l / 16) .. + 3 of column l % 16.  K index k = 8 g + e maps to
+// input channel k in layers 2 and 3 (one tap per K step) and to (tap k / 2,
+// channel k % 2) in layer 1 (taps 0..8, the rest zero).
 
-struct GateLds {
-  uint16_t in0[2 * kP * kP];         // bf16 input
-  uint16_t a1[kC * 24 * 24];         // bf16 activations
-  float a2[kC * 12 * 12];
-  float a3[kC * 36];
-  float g[kC];
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kIn = kP + 1;     // padded input side
+constexpr int kS1 = 25;         // padded side of layer-1 output (24 + 1)
+constexpr int kS2 = 13;         // padded side of layer-2 output (12 + 1)
+constexpr int kPix = 40;        // bf16 slots per activation pixel (32 used)
+
+struct __align__(16) GateLds {
+  uint32_t in[(kIn * kIn + 3) / 4 * 4];   // (c0, c1) bf16 pair per input pixel (16-byte multiple)
+  uint16_t a1[kS1 * kS1 * kPix];
+  uint16_t a2[kS2 * kS2 * kPix];
+  float gpart[4][16];                     // per-wave pooled partial sums
 };
 
+static_assert(offsetof(GateLds, a1) % 16 == 0 && offsetof(GateLds, a2) % 16 == 0,
+              "activation images must be 16-byte aligned for 128-bit LDS reads");
+
+struct GateWeights {
+  bf16x8 w1[2];                           // layer 1, both column tiles
+  bf16x8 w2[9], w3[9];                    // layers 2, 3: this wave's column tile, per tap
+  float b1[2], b2, b3;                    // biases of column l % 16 (+ 16 tile)
+};
+
+static __device__ __forceinline__ uint32_t bf16_bits(float x) {   // x already bf16-valued
+  return __float_as_uint(x) >> 16;
+}
+static __device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+static __device__ __forceinline__ GateWeights load_gate_weights(const float* wq) {
+  const int lane = lane_id(), wave = wave_id();
+  const int col = lane & 15, g = lane >> 4, nt = wave & 1;
+  GateWeights W;
+#pragma unroll
+  for (int t2 = 0; t2 < 2; ++t2) {
+    const int n = t2 * 16 + col;
+    uint32_t u[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int tap = 4 * g + q;              // k = 2 tap + c
+      u[q] = tap < 9 ? (bf16_bits(wq[kOffW1 + (n * 2 + 0) * 9 + tap]) |
+                        (bf16_bits(wq[kOffW1 + (n * 2 + 1) * 9 + tap]) << 16))
+                     : 0u;
+    }
+    W.w1[t2] = __builtin_bit_cast(bf16x8, (u32x4){u[0], u[1], u[2], u[3]});
+    W.b1[t2] = wq[kOffB1 + n];
+  }
+  const int n = nt * 16 + col;
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    uint32_t u2[4], u3[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = 8 * g + 2 * q;
+      u2[q] = bf16_bits(wq[kOffW2 + (n * kC + c) * 9 + tap]) |
+              (bf16_bits(wq[kOffW2 + (n * kC + c + 1) * 9 + tap]) << 16);
+      u3[q] = bf16_bits(wq[kOffW3 + (n * kC + c) * 9 + tap]) |
+              (bf16_bits(wq[kOffW3 + (n * kC + c + 1) * 9 + tap]) << 16);
+    }
+    W.w2[tap] = __builtin_bit_cast(bf16x8, (u32x4){u2[0], u2[1], u2[2], u2[3]});
+    W.w3[tap] = __builtin_bit_cast(bf16x8, (u32x4){u3[0], u3[1], u3[2], u3[3]});
+  }
+  W.b2 = wq[kOffB2 + n];
+  W.b3 = wq[kOffB3 + n];
+  return W;
+}
+
+// zero the padding row and column of every LDS image (never written later)
+static __device__ __forceinline__ void gate_clear_padding(GateLds& G) {
+  for (int e = threadIdx.x; e < 2 * kIn; e += kThreads) {
+    const int k = e % kIn;
+    G.in[e < kIn ? k : k * kIn] = 0u;
+  }
+  for (int e = threadIdx.x; e < 2 * kS1 * kPix; e += kThreads) {
+    const int pix = (e / kPix) % kS1, c = e % kPix;
+    G.a1[(e < kS1 * kPix ? pix : pix * kS1) * kPix + c] = 0;
+  }
+  for (int e = threadIdx.x; e < 2 * kS2 * kPix; e += kThreads) {
+    const int pix = (e / kPix) % kS2, c = e % kPix;
+    G.a2[(e < kS2 * kPix ? pix : pix * kS2) * kPix + c] = 0;
+  }
+}
+
+static __device__ __forceinline__ bf16x8 lds_frag(const uint16_t* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
+}
+
+// The network on the input staged in G.in; returns (y0, y1) in lanes of
+// wave 0 (valid in every lane of wave 0).  Barriers inside; the caller
+// syncs before staging the next input.
+static __device__ __forceinline__ void gate_network(GateLds& G, const GateWeights& W,
+                                                    const float* wq, float& y0, float& y1) {
+  const int lane = lane_id(), wave = wave_id();
+  const int col = lane & 15, g = lane >> 4, nt = wave & 1;
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+
+  // layer 1: 576 positions = 36 row tiles, both column tiles, one K step
+  for (int mt = wave; mt < 36; mt += 4) {
+    const int m = mt * 16 + col;
+    const int oy = m / 24, ox = m - oy * 24;
+    uint32_t u[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int tap = 4 * g + q;
+      const int ky = tap / 3, kx = tap - 3 * (tap / 3);
+      u[q] = tap < 9 ? G.in[(2 * oy + ky) * kIn + 2 * ox + kx] : 0u;
+    }
+    const bf16x8 A = __builtin_bit_cast(bf16x8, (u32x4){u[0], u[1], u[2], u[3]});
+#pragma unroll
+    for (int t2 = 0; t2 < 2; ++t2) {
+      const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, W.w1[t2], zero, 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int mo = mt * 16 + 4 * g + j;
+        const int py = mo / 24, px = mo - py * 24;
+        G.a1[((py + 1) * kS1 + px + 1) * kPix + t2 * 16 + col] =
+            (uint16_t)bf16_rne_bits(fmaxf(d[j] + W.b1[t2], 0.0f));
+      }
+    }
+  }
+  __syncthreads();
+
+  // layer 2: 144 positions = 9 row tiles; wave owns column tile nt and row
+  // tiles (wave >> 1) + 2 t
+  for (int mt = wave >> 1; mt < 9; mt += 2) {
+    const int m = mt * 16 + col;
+    const int oy = m / 12, ox = m - oy * 12;
+    f32x4 acc = zero;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ky = tap / 3, kx = tap % 3;
+      const bf16x8 A = lds_frag(&G.a1[((2 * oy + ky) * kS1 + 2 * ox + kx) * kPix + 8 * g]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, W.w2[tap], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int mo = mt * 16 + 4 * g + j;
+      const int py = mo / 12, px = mo - py * 12;
+      G.a2[((py + 1) * kS2 + px + 1) * kPix + nt * 16 + col] =
+          (uint16_t)bf16_rne_bits(fmaxf(acc[j] + W.b2, 0.0f));
+    }
+  }
+  __syncthreads();
+
+  // layer 3: 36 positions = 3 row tiles (the last one 4 rows deep), pooled
+  float pool = 0.0f;
+  for (int mt = wave >> 1; mt < 3; mt += 2) {
+    const int m = min(mt * 16 + col, 35);
+    const int oy = m / 6, ox = m - oy * 6;
+    f32x4 acc = zero;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ky = tap / 3, kx = tap % 3;
+      const bf16x8 A = lds_frag(&G.a2[((2 * oy + ky) * kS2 + 2 * ox + kx) * kPix + 8 * g]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, W.w3[tap], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (mt * 16 + 4 * g + j < 36) pool += fmaxf(acc[j] + W.b3, 0.0f);
+  }
+  pool += __shfl_xor(pool, 16, 64);
+  pool += __shfl_xor(pool, 32, 64);
+  if (lane < 16) G.gpart[wave][lane] = pool;
+  __syncthreads();
+  if (wave == 0) {
+    float h0 = 0.0f, h1 = 0.0f;
+    if (lane < kC) {
+      const int t2 = lane >> 4, c16 = lane & 15;
+      const float gv = (G.gpart[t2][c16] + G.gpart[t2 + 2][c16]) * (1.0f / 36.0f);
+      h0 = gv * wq[kOffWh + lane];
+      h1 = gv * wq[kOffWh + kC + lane];
+    }
+    y0 = wave_sum(h0) + wq[kOffBh];
+    y1 = wave_sum(h1) + wq[kOffBh + 1];
+  }
+}
+
+// In-pipeline gate: one pass over the blocks eligible in this round; the
+// layer choice goes to gate[i] and the predictions to gate_pred.
 __global__ __launch_bounds__(kThreads) void k_cnn_gate(FrameArgs a, DevParams p, const float* wq,
                                                        float tau1, float tau2) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -303,11 +491,18 @@ __global__ __launch_bounds__(kThreads) void k_cnn_gate(FrameArgs a, DevParams p,
   nq = wave_sum(nq);
   maxm0 = wave_max(maxm0);
   if (lane_id() == 0) { red[wave_id()][0] = nq; red[wave_id()][1] = maxm0; }
+  gate_clear_padding(G);
   __syncthreads();
   nq = 0; maxm0 = 0;
   for (int w = 0; w < kThreads / 64; ++w) { nq += red[w][0]; maxm0 = max(maxm0, red[w][1]); }
+  const GateWeights W = load_gate_weights(wq);
   const int tid = threadIdx.x;
-  for (int i = blockIdx.x; i < n_lost; i += gridDim.x) {
+  // XCD x (workgroups x, x + 8, ...) takes a contiguous range of blocks, so
+  // neighbouring windows share its L2
+  const int lw = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  const int per = (n_lost + gridDim.x - 1) / gridDim.x;
+  const int i_end = min(n_lost, (lw + 1) * per);
+  for (int i = lw * per; i < i_end; ++i) {
     if (a.bstate[i] != 0) continue;
     const int m0c = a.m0cnt[i];
     if (!(nq > 0 ? (m0c >= p.r * p.B) : (m0c == maxm0))) continue;
@@ -316,80 +511,38 @@ __global__ __launch_bounds__(kThreads) void k_cnn_gate(FrameArgs a, DevParams p,
     for (int idx = tid; idx < kP * kP; idx += kThreads) {
       float c0, c1;
       input_pixel(a, p, by, bx, idx, c0, c1);
-      G.in0[idx] = (uint16_t)(__float_as_uint(c0) >> 16);
-      G.in0[kP * kP + idx] = (uint16_t)(__float_as_uint(c1) >> 16);
+      const int py = idx / kP, px = idx - py * kP;
+      G.in[(py + 1) * kIn + px + 1] = bf16_bits(c0) | (bf16_bits(c1) << 16);
     }
     __syncthreads();
-    // conv1: 2 -> 32, 48 -> 24
-    for (int e = tid; e < kC * 24 * 24; e += kThreads) {
-      const int k = e / 576, oy = (e / 24) % 24, ox = e % 24;
-      float s = wq[kOffB1 + k];
-      for (int c = 0; c < 2; ++c)
-        for (int ky = 0; ky < 3; ++ky) {
-          const int y = 2 * oy + ky - 1;
-          if (y < 0 || y >= kP) continue;
-          for (int kx = 0; kx < 3; ++kx) {
-            const int x = 2 * ox + kx - 1;
-            if (x < 0 || x >= kP) continue;
-            s = fmaf(bf16_to_f(G.in0[c * kP * kP + y * kP + x]), wq[kOffW1 + (k * 2 + c) * 9 + ky * 3 + kx], s);
-          }
-        }
-      G.a1[e] = (uint16_t)(__float_as_uint(bf16_round(fmaxf(s, 0.0f))) >> 16);
-    }
-    __syncthreads();
-    // conv2: 32 -> 32, 24 -> 12
-    for (int e = tid; e < kC * 144; e += kThreads) {
-      const int k = e / 144, oy = (e / 12) % 12, ox = e % 12;
-      float s = wq[kOffB2 + k];
-      for (int c = 0; c < kC; ++c) {
-        const float* wk = wq + kOffW2 + (k * kC + c) * 9;
-        for (int ky = 0; ky < 3; ++ky) {
-          const int y = 2 * oy + ky - 1;
-          if (y < 0 || y >= 24) continue;
-          for (int kx = 0; kx < 3; ++kx) {
-            const int x = 2 * ox + kx - 1;
-            if (x < 0 || x >= 24) continue;
-            s = fmaf(bf16_to_f(G.a1[c * 576 + y * 24 + x]), wk[ky * 3 + kx], s);
-          }
-        }
-      }
-      G.a2[e] = bf16_round(fmaxf(s, 0.0f));
-    }
-    __syncthreads();
-    // conv3: 32 -> 32, 12 -> 6
-    for (int e = tid; e < kC * 36; e += kThreads) {
-      const int k = e / 36, oy = (e / 6) % 6, ox = e % 6;
-      float s = wq[kOffB3 + k];
-      for (int c = 0; c < kC; ++c) {
-        const float* wk = wq + kOffW3 + (k * kC + c) * 9;
-        for (int ky = 0; ky < 3; ++ky) {
-          const int y = 2 * oy + ky - 1;
-          if (y < 0 || y >= 12) continue;
-          for (int kx = 0; kx < 3; ++kx) {
-            const int x = 2 * ox + kx - 1;
-            if (x < 0 || x >= 12) continue;
-            s = fmaf(G.a2[c * 144 + y * 12 + x], wk[ky * 3 + kx], s);
-          }
-        }
-      }
-      G.a3[e] = fmaxf(s, 0.0f);
-    }
-    __syncthreads();
-    if (tid < kC) {
-      float s = 0.0f;
-      for (int q = 0; q < 36; ++q) s += G.a3[tid * 36 + q];
-      G.g[tid] = s * (1.0f / 36.0f);
-    }
-    __syncthreads();
+    float y0 = 0.0f, y1 = 0.0f;
+    gate_network(G, W, wq, y0, y1);
     if (tid == 0) {
-      float y0 = wq[kOffBh], y1 = wq[kOffBh + 1];
-      for (int c = 0; c < kC; ++c) {
-        y0 = fmaf(G.g[c], wq[kOffWh + c], y0);
-        y1 = fmaf(G.g[c], wq[kOffWh + kC + c], y1);
-      }
       a.gate[i] = (int8_t)(y0 <= tau1 ? SKM_LAYER_BRL : (y1 > tau2 ? SKM_LAYER_HQL : SKM_LAYER_IDL));
       if (a.gate_pred) { a.gate_pred[2 * i] = y0; a.gate_pred[2 * i + 1] = y1; }
     }
+    __syncthreads();
+  }
+}
+
+// Batched inference on prepared inputs x (bf16 bits [n][2][48][48]).
+__global__ __launch_bounds__(kThreads) void k_cnn_infer(const uint16_t* x, int n, const float* wq,
+                                                        float* y) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  GateLds& G = *reinterpret_cast<GateLds*>(lds_raw);
+  gate_clear_padding(G);
+  const GateWeights W = load_gate_weights(wq);
+  const int tid = threadIdx.x;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const uint16_t* xi = x + (size_t)i * 2 * kP * kP;
+    for (int idx = tid; idx < kP * kP; idx += kThreads) {
+      const int py = idx / kP, px = idx - py * kP;
+      G.in[(py + 1) * kIn + px + 1] = (uint32_t)xi[idx] | ((uint32_t)xi[kP * kP + idx] << 16);
+    }
+    __syncthreads();
+    float y0 = 0.0f, y1 = 0.0f;
+    gate_network(G, W, wq, y0, y1);
+    if (tid == 0) { y[2 * (size_t)i] = y0; y[2 * (size_t)i + 1] = y1; }
     __syncthreads();
   }
 }
@@ -408,17 +561,32 @@ hipError_t launch_cnn_inputs(const FrameArgs& a, const DevParams& p, uint16_t* o
   return hipGetLastError();
 }
 
+// two resident workgroups per CU (LDS), 256 CUs
+constexpr int kGateGrid = 512;
+
 hipError_t launch_cnn_gate(const FrameArgs& a, const DevParams& p, const float* wq, float tau1,
                            float tau2, int max_blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_cnn_gate, dim3(max_blocks < 1 ? 1 : (max_blocks > 2048 ? 2048 : max_blocks)),
-                     dim3(kThreads), sizeof(GateLds), s, a, p, wq, tau1, tau2);
+  // a multiple of 8 workgroups (the block ranges follow the XCD order)
+  int grid = max_blocks < 1 ? 1 : (max_blocks > kGateGrid ? kGateGrid : max_blocks);
+  grid = (grid + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_cnn_gate, dim3(grid), dim3(kThreads), sizeof(GateLds), s, a, p, wq, tau1,
+                     tau2);
+  return hipGetLastError();
+}
+
+hipError_t cnn_infer(const uint16_t* x, int n, const float* wq, float* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_cnn_infer, dim3(n > kGateGrid ? kGateGrid : n), dim3(kThreads),
+                     sizeof(GateLds), s, x, n, wq, y);
   return hipGetLastError();
 }
 
 size_t cnn_gate_lds_bytes() { return sizeof(GateLds); }
 
 hipError_t set_cnn_gate_lds_limit(size_t bytes) {
-  return hipFuncSetAttribute((const void*)k_cnn_gate, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void*)k_cnn_gate,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_cnn_infer, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)bytes);
 }
 

@@ -11,6 +11,16 @@ namespace skm {
 
 // ------------------------------------------------------------ wave helpers
 
+// Workgroups are dispatched round-robin to the 8 XCDs.  xcd_block maps a
+// workgroup id to an item index so that XCD x takes the x-th contiguous
+// eighth of [0, n); the grid must hold at least 8 * ceil(n / 8) workgroups.
+// Returns -1 for workgroups without an item.
+static __device__ __forceinline__ int xcd_block(int wg, int n) {
+  const int per = (n + 7) >> 3;
+  const int i = (wg & 7) * per + (wg >> 3);
+  return ((wg >> 3) < per && i < n) ? i : -1;
+}
+
 static __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 static __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
@@ -34,6 +44,43 @@ static __device__ __forceinline__ double wave_max_d(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
+}
+
+// Full-wave reductions on DPP lane moves (no LDS traffic): every lane of the
+// wave must be active.  Quad swaps, half-row and row mirrors leave each
+// 16-lane row holding its sum; two row broadcasts carry the rows into lane 63,
+// whose value is returned to all lanes.  The order is fixed.
+template <int CTRL, int ROWS>
+static __device__ __forceinline__ int dpp_i32(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+static __device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i32<CTRL, ROWS>(0, (int)(b & 0xffffffffll));
+  const int hi = dpp_i32<CTRL, ROWS>(0, (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+static __device__ __forceinline__ int wave_sum_full(int v) {
+  v += dpp_i32<0xB1, 0xf>(0, v);     // quad_perm [1,0,3,2]
+  v += dpp_i32<0x4E, 0xf>(0, v);     // quad_perm [2,3,0,1]
+  v += dpp_i32<0x141, 0xf>(0, v);    // row_half_mirror
+  v += dpp_i32<0x140, 0xf>(0, v);    // row_mirror
+  v += dpp_i32<0x142, 0xa>(0, v);    // row_bcast:15 into rows 1, 3
+  v += dpp_i32<0x143, 0xc>(0, v);    // row_bcast:31 into rows 2, 3
+  return __builtin_amdgcn_readlane(v, 63);
+}
+static __device__ __forceinline__ double wave_sum_full(double v) {
+  v += dpp_f64<0xB1, 0xf>(v);
+  v += dpp_f64<0x4E, 0xf>(v);
+  v += dpp_f64<0x141, 0xf>(v);
+  v += dpp_f64<0x140, 0xf>(v);
+  v += dpp_f64<0x142, 0xa>(v);
+  v += dpp_f64<0x143, 0xc>(v);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 // Merge (m2, s2) into (m, s), both "max and sum of exp(x - max)".  Callers fix
@@ -65,7 +112,8 @@ static __device__ __forceinline__ void shr128(uint64_t lo, uint64_t hi, int s, u
 //                         window offset | bucket << 16 | radius << 24
 //   selw    f32 [MC]      FP32 weights exp(ell - max) of the selected candidates
 //   selo    u16 [MC]      their window offsets
-//   qu      u32x2 [NU]    per unit: packed int16 context pair, footprint offset
+//   qu      u32x2 [NU32]  per unit: packed int16 context pair, footprint offset;
+//                         padded to a multiple of 32 with unknown pairs
 //   utab    u32 [NU]      fixed unit table: footprint offset | single << 16
 //   rowbits u64 [Wd][2]   availability bits of each window row
 //   runbits u64 [Wd][2]   bit c set iff columns c .. c+B-1 are all available
@@ -88,6 +136,7 @@ struct MainLds {
 };
 
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+__host__ __device__ inline int align32(int v) { return (v + 31) & ~31; }
 
 __host__ __device__ inline size_t main_lds_layout(const DevParams& p, size_t* offs) {
   const size_t D2 = 2 * p.W + 1;
@@ -96,7 +145,7 @@ __host__ __device__ inline size_t main_lds_layout(const DevParams& p, size_t* of
   offs[1] = o; o = align_up(o + sizeof(uint32_t) * p.MC, 16);
   offs[2] = o; o = align_up(o + sizeof(float) * p.MC, 16);
   offs[3] = o; o = align_up(o + sizeof(uint16_t) * p.MC, 16);
-  offs[4] = o; o = align_up(o + sizeof(uint2) * p.NR, 16);
+  offs[4] = o; o = align_up(o + sizeof(uint2) * (p.NR + 32), 16);   // units padded to 32
   offs[5] = o; o = align_up(o + sizeof(uint32_t) * p.NR, 16);
   offs[6] = o; o = align_up(o + sizeof(uint64_t) * 2 * p.Wd, 16);
   offs[7] = o; o = align_up(o + sizeof(uint64_t) * 2 * p.Wd, 16);
@@ -122,11 +171,80 @@ static __device__ __forceinline__ MainLds carve_main_lds(unsigned char* raw, con
   return L;
 }
 
+// Candidate word written by phase_candidates: window offset of the
+// prototype's footprint origin (14 bits) | expansion bucket << 14 (4 bits);
+// the estimation kernel adds the known-pair count n << 18 (10 bits).
+static __device__ __forceinline__ int cand_off(uint32_t c) { return (int)(c & 0x3fffu); }
+static __device__ __forceinline__ int cand_bucket(uint32_t c) { return (int)((c >> 14) & 0xfu); }
+static __device__ __forceinline__ int cand_n(uint32_t c) { return (int)(c >> 18); }
+
+// Estimation-kernel LDS (one block per workgroup), smaller than MainLds so
+// that four workgroups fit a CU at the default geometry:
+//   winp    u32 [Wd*Wd]   as in MainLds
+//   qu      u32x2 [NR+32] as in MainLds
+//   utab    u32 [NR]      as in MainLds
+//   cand    u32 [MC]      candidate words; n added by the distance step
+//   dist    u32 [MC]      exact distance d (~0u = dropped); then the FP32
+//                         weight bits of each candidate (0 = not used).
+//                         Before the distance step it holds rowbits,
+//                         runbits and cmask.
+//   part    f64 [kThreads] cross-group sums of the weighted average (only
+//                         when B*B < kThreads); aliases qu and utab
+struct EstLds {
+  uint32_t* winp;
+  uint2* qu;
+  uint32_t* utab;
+  uint32_t* cand;
+  uint32_t* dist;
+  double* part;
+  MainLds m;          // view for the shared phases (ell, selw, selo unused)
+};
+
+__host__ __device__ inline size_t est_lds_layout(const DevParams& p, size_t* offs) {
+  size_t o = 0;
+  offs[0] = o; o = align_up(o + sizeof(uint32_t) * p.Wd * p.Wd, 16);
+  offs[1] = o; o = align_up(o + sizeof(uint2) * (p.NR + 32), 16);
+  offs[2] = o; o = align_up(o + sizeof(uint32_t) * p.NR, 16);
+  const size_t qu_utab = o - offs[1];
+  offs[3] = o; o = align_up(o + sizeof(uint32_t) * p.MC, 16);
+  offs[4] = o;
+  const size_t bits = sizeof(uint64_t) * 2 * (2 * p.Wd + 2 * p.W + 1);
+  const size_t dist = sizeof(uint32_t) * p.MC;
+  o = align_up(o + (dist > bits ? dist : bits), 16);
+  offs[5] = offs[1];
+  const size_t part = (size_t)p.B * p.B < (size_t)kThreads ? sizeof(double) * kThreads : 0;
+  if (part > qu_utab) { offs[5] = o; o = align_up(o + part, 16); }
+  return o;
+}
+
+static __device__ __forceinline__ EstLds carve_est_lds(unsigned char* raw, const DevParams& p) {
+  size_t offs[6];
+  est_lds_layout(p, offs);
+  EstLds E;
+  E.winp = (uint32_t*)(raw + offs[0]);
+  E.qu = (uint2*)(raw + offs[1]);
+  E.utab = (uint32_t*)(raw + offs[2]);
+  E.cand = (uint32_t*)(raw + offs[3]);
+  E.dist = (uint32_t*)(raw + offs[4]);
+  E.part = (double*)(raw + offs[5]);
+  E.m.ell = nullptr;
+  E.m.selw = nullptr;
+  E.m.selo = nullptr;
+  E.m.cand = E.cand;
+  E.m.qu = E.qu;
+  E.m.utab = E.utab;
+  E.m.winp = E.winp;
+  E.m.rowbits = (uint64_t*)E.dist;
+  E.m.runbits = E.m.rowbits + 2 * p.Wd;
+  E.m.cmask = E.m.runbits + 2 * p.Wd;
+  return E;
+}
+
 // Small per-block values shared by the workgroup.
 struct BlockShared {
   int NU, M, n_sel;
   int layer, radius_idx, flags, n_cand, n_complete;
-  double lnu, mstar, den;
+  double lnu, den;
   int red_i[kThreads / 64][4];
   int scan[kThreads / 64];
   int rowbase[2 * kMaxWin + 1];
@@ -135,7 +253,6 @@ struct BlockShared {
   double cm[kMaxRadii];
   double ps[kThreads / 64][kMaxRadii];
   int bucket_of[kMaxWin + 1];
-  double part[kThreads];
 };
 
 typedef short short2v __attribute__((ext_vector_type(2)));
@@ -217,16 +334,18 @@ static __device__ __forceinline__ void phase_tables(const DevParams& p, const Ma
 }
 
 // Stage the window of the block whose window origin is (ox, oy): one wave per
-// row and lanes along it, six rows of loads in flight; pixel pairs by lane
-// shuffle; availability bits per row.  Ends with a barrier.
+// row and lanes along it, up to 18 rows of loads in flight per wave (the
+// whole window up to 72 rows); pixel pairs by lane shuffle; availability
+// bits per row.  Ends with a barrier.
 static __device__ __forceinline__ void phase_stage(const FrameArgs& a, const DevParams& p,
                                                    const MainLds& L, int ox, int oy) {
   const int lane = lane_id(), wave = wave_id();
   const int Wd = p.Wd, nw = kThreads / 64;
-  for (int wy0 = wave; wy0 < Wd; wy0 += 6 * nw) {
-    int v0[6], v1[6];
+  constexpr int kRows = 6;
+  for (int wy0 = wave; wy0 < Wd; wy0 += kRows * nw) {
+    int v0[kRows], v1[kRows];
 #pragma unroll
-    for (int t = 0; t < 6; ++t) {
+    for (int t = 0; t < kRows; ++t) {
       const int wy = wy0 + t * nw;
       const int gy = oy + wy;
       const int cy = min(max(gy, 0), p.height - 1);
@@ -238,7 +357,7 @@ static __device__ __forceinline__ void phase_stage(const FrameArgs& a, const Dev
       v1[t] = (rowok && 64 + lane < Wd && gx1 >= 0 && gx1 < p.width) ? r1 : -1;
     }
 #pragma unroll
-    for (int t = 0; t < 6; ++t) {
+    for (int t = 0; t < kRows; ++t) {
       const int wy = wy0 + t * nw;
       const int n0 = __shfl_down(v0[t], 1, 64);
       const int h0 = __shfl(v1[t], 0, 64);
@@ -280,6 +399,7 @@ static __device__ __forceinline__ RingStats phase_context(const DevParams& p, co
       if (va >= 0) { ++c; vmin = min(vmin, va); vmax = max(vmax, va); vsum += va; }
       if (vb >= 0) { ++c; vmin = min(vmin, vb); vmax = max(vmax, vb); vsum += vb; }
     }
+    for (int u = NU + tid; u < align32(NU); u += kThreads) L.qu[u] = make_uint2(0xffffffffu, 0u);
     c = wave_sum(c); vmin = wave_min(vmin); vmax = wave_max(vmax); vsum = wave_sum(vsum);
     if (lane == 0) {
       sh.red_i[wave][0] = c; sh.red_i[wave][1] = vmin;
@@ -310,7 +430,7 @@ static __device__ __forceinline__ RingStats phase_context(const DevParams& p, co
 
 // Admissible prototypes: vertical AND of B runs per displacement row shifted
 // to displacement columns (cmask), row counts and prefix, then the candidate
-// list in raster order (window offset | bucket << 16 | radius << 24).
+// list in raster order (candidate words, see cand_off).
 // Also resets the per-bucket maxima and counts.  Returns M; ends with a
 // barrier.
 static __device__ __forceinline__ int phase_candidates(const DevParams& p, const MainLds& L,
@@ -347,8 +467,7 @@ static __device__ __forceinline__ int phase_candidates(const DevParams& p, const
         const int rank = dxi < 64 ? __popcll(mlo & ((1ull << dxi) - 1ull))
                                   : __popcll(mlo) + __popcll(mhi & ((1ull << (dxi - 64)) - 1ull));
         const int rho = max(ady, abs(dxi - W));
-        L.cand[base + rank] = (uint32_t)(dyi * Wd + dxi) | ((uint32_t)sh.bucket_of[rho] << 16) |
-                              ((uint32_t)rho << 24);
+        L.cand[base + rank] = (uint32_t)(dyi * Wd + dxi) | ((uint32_t)sh.bucket_of[rho] << 14);
       }
     }
   }
@@ -374,6 +493,28 @@ static __device__ __forceinline__ void cand_distance(const MainLds& L, int base,
   for (; u < NU; ++u) {
     const uint2 qq = L.qu[u];
     pair_dist(qq.x, L.winp[base + (int)qq.y], d, nacc);
+  }
+  d_out = d;
+  n_out = (int)(nacc & 0xffffu) + (int)(nacc >> 16);
+}
+
+// The same distance for one candidate per lane, called by every lane of the
+// wave (a lane without a candidate passes base 0 and ignores the result).
+// The units come 32 at a time into registers and are broadcast by
+// readlane, so each step is one independent LDS read of the window.
+static __device__ __forceinline__ void cand_distance_wave(const MainLds& L, int base, int NU32,
+                                                          int& d_out, int& n_out) {
+  int d = 0;
+  uint32_t nacc = 0;
+  const int lane = lane_id();
+  for (int u0 = 0; u0 < NU32; u0 += 32) {
+    const uint2 qv = L.qu[u0 + (lane & 31)];
+#pragma unroll 16
+    for (int k = 0; k < 32; ++k) {
+      const uint32_t q = (uint32_t)__builtin_amdgcn_readlane((int)qv.x, k);
+      const int off = __builtin_amdgcn_readlane((int)qv.y, k);
+      pair_dist(q, L.winp[base + off], d, nacc);
+    }
   }
   d_out = d;
   n_out = (int)(nacc & 0xffffu) + (int)(nacc >> 16);

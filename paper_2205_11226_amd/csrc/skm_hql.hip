@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
       int cnt = 0;
       for (int j = j0; j < j1; ++j) {
         int d, n;
-        cand_distance(L, (int)(L.cand[j] & 0xffffu), NU, d, n);
+        cand_distance(L, cand_off(L.cand[j]), NU, d, n);
         const bool comp = n == n0 && n >= nmin;
         L.ell[j] = comp ? (double)d : -1.0;
         cnt += comp;
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
       int pos = block_excl_scan(cnt, sh.scan, &tot);
       for (int j = j0; j < j1; ++j) {
         if (L.ell[j] >= 0.0) {
-          compo[pos] = (uint16_t)(L.cand[j] & 0xffffu);
+          compo[pos] = (uint16_t)cand_off(L.cand[j]);
           compd[pos] = (int)L.ell[j];
           ++pos;
         }

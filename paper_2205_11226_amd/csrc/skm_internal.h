@@ -10,6 +10,9 @@ namespace skm {
 
 constexpr int kThreads = 256;        // one workgroup = 4 wave64
 constexpr int kMaxRadii = 16;
+// candidates per thread in a contiguous slice: ceil(MC / kThreads) for the
+// largest admissible window (W = 32, B = 4)
+constexpr int kMaxPer = 17;
 constexpr int kMaxB = 16;
 constexpr int kMaxRing = 8;
 constexpr int kMaxWin = 32;
@@ -63,7 +66,8 @@ struct FrameArgs {
   uint8_t* cell_lost;     // gh * gw
   int* blk;               // lost cell indices, raster order
   int* bstate;
-  int* m0cnt;
+  int* m0cnt;             // known in-frame ring pixels of each pending block
+  int2* ring;             // their sum, and min | max << 16 (prep kernel)
   int* part;              // 2 * kPrepGridMax prep partials
   int* hql_list;          // lost-block indices waiting for HQL in this round
   int8_t* gate;           // CNN mode: layer chosen for each lost block
@@ -99,6 +103,7 @@ hipError_t launch_cnn_inputs(const FrameArgs& a, const DevParams& p, uint16_t* o
                              hipStream_t s);
 hipError_t launch_cnn_gate(const FrameArgs& a, const DevParams& p, const float* wq, float tau1,
                            float tau2, int max_blocks, hipStream_t s);
+hipError_t cnn_infer(const uint16_t* x, int n, const float* wq, float* y, hipStream_t s);
 size_t cnn_gate_lds_bytes();
 hipError_t set_cnn_gate_lds_limit(size_t bytes);
 hipError_t cnn_init(float* prm, float* wq, unsigned long long seed, hipStream_t s);

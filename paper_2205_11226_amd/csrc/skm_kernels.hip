@@ -95,9 +95,10 @@ __global__ __launch_bounds__(1024) void k_compact(FrameArgs a, DevParams p) {
 }
 
 // ------------------------------------------------------------- round prep
-// One wave per pending block: |m0| = known in-frame ring pixels.  Each
-// workgroup publishes (blocks with |m0| >= r B, largest |m0|) in its own
-// slot of `part`; the estimation kernel reduces the slots.  No atomics.
+// One wave per pending block: |m0| = known in-frame ring pixels, with their
+// sum, minimum and maximum (the context mean and flatness of the BRL gate).
+// Each workgroup publishes (blocks with |m0| >= r B, largest |m0|) in its
+// own slot of `part`; the later kernels reduce the slots.  No atomics.
 __global__ __launch_bounds__(kThreads) void k_round_prep(FrameArgs a, DevParams p) {
   __shared__ int s_nq[kThreads / 64], s_mx[kThreads / 64];
   RoundState* st = a.st;
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(kThreads) void k_round_prep(FrameArgs a, DevParams 
     const int cell = a.blk[i];
     const int by = cell / p.gw, bx = cell - by * p.gw;
     const int xr = bx * B - r, yr = by * B - r;
-    int c = 0;
+    int c = 0, sum = 0, vmin = 255, vmax = 0;
 #pragma unroll
     for (int fy0 = 0; fy0 < 2 * kMaxB; fy0 += 2) {     // two footprint rows per step, F <= 32
       const int fy = fy0 + (lane >> 5), fx = lane & 31;
@@ -120,12 +121,16 @@ __global__ __launch_bounds__(kThreads) void k_round_prep(FrameArgs a, DevParams 
       const bool use = fy < F && fx < F && (fy < r || fy >= r + B || fx < r || fx >= r + B) &&
                        gy >= 0 && gy < p.height && gx >= 0 && gx < p.width;
       const int cy = min(max(gy, 0), p.height - 1), cx = min(max(gx, 0), p.width - 1);
-      const int16_t v = a.val[(size_t)cy * p.width + cx];
-      c += (use && v >= 0) ? 1 : 0;
+      const int v = a.val[(size_t)cy * p.width + cx];
+      if (use && v >= 0) { ++c; sum += v; vmin = min(vmin, v); vmax = max(vmax, v); }
     }
     c = wave_sum(c);
+    sum = wave_sum(sum);
+    vmin = wave_min(vmin);
+    vmax = wave_max(vmax);
     if (lane == 0) {
       a.m0cnt[i] = c;
+      a.ring[i] = make_int2(sum, vmin | (vmax << 16));
       my_nq += c >= r * B;
       my_mx = max(my_mx, c);
     }
@@ -143,8 +148,8 @@ __global__ __launch_bounds__(kThreads) void k_round_prep(FrameArgs a, DevParams 
 // ----------------------------------------------------------- main kernel
 
 size_t main_lds_bytes(const DevParams& p) {
-  size_t offs[10];
-  return main_lds_layout(p, offs);
+  size_t offs[6];
+  return est_lds_layout(p, offs);
 }
 
 __device__ void write_info(const FrameArgs& a, int i, int bx, int by, int layer, int round,
@@ -176,289 +181,324 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
   const int remaining = st->remaining;
   if (remaining == 0) return;
   const int n_lost = st->n_lost, round = st->round;
+  // one workgroup per lost block; the grid covers every cell.  Workgroups
+  // go round-robin to the 8 XCDs, so XCD x takes the x-th contiguous eighth
+  // of the (raster ordered) lost blocks: neighbouring windows share its L2.
+  const int i = xcd_block(blockIdx.x, n_lost);
+  if (i < 0 || a.bstate[i] != 0) return;
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   // context-size gate of the round, from the prep kernel's per-workgroup partials
   int nq = 0, maxm0 = 0;
-  for (int g = threadIdx.x; g < p.prep_grid; g += kThreads) {
+  for (int g = tid; g < p.prep_grid; g += kThreads) {
     nq += a.part[2 * g];
     maxm0 = max(maxm0, a.part[2 * g + 1]);
   }
-  nq = wave_sum(nq);
+  nq = wave_sum_full(nq);
   maxm0 = wave_max(maxm0);
-  if (lane_id() == 0) { sh.red_i[wave_id()][0] = nq; sh.red_i[wave_id()][1] = maxm0; }
+  if (lane == 0) { sh.red_i[wave][0] = nq; sh.red_i[wave][1] = maxm0; }
   __syncthreads();
   nq = 0; maxm0 = 0;
   for (int w = 0; w < kThreads / 64; ++w) { nq += sh.red_i[w][0]; maxm0 = max(maxm0, sh.red_i[w][1]); }
   if (!dist_only && nq == 0 && maxm0 == 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&st->err, kErrNoContext);
+    if (tid == 0) atomicOr(&st->err, kErrNoContext);
     return;
   }
-  const MainLds L = carve_main_lds(lds_raw, p);
-  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  const int n0 = a.m0cnt[i];
+  if (!dist_only && !(nq > 0 ? (n0 >= p.r * p.B) : (n0 == maxm0))) return;
+
   const int B = p.B, r = p.r, W = p.W, Wd = p.Wd, D2 = 2 * W + 1;
   const int B2 = B * B;
-  const int nw = kThreads / 64;
-  phase_tables(p, L, sh);
-  const int NU = sh.NU;
+  const int cell = a.blk[i];
+  const int by = cell / p.gw, bx = cell - by * p.gw;
+  const int x0 = bx * B, y0 = by * B;
 
-  for (int i = blockIdx.x; i < n_lost; i += gridDim.x) {
-    if (a.bstate[i] != 0) continue;
-    if (!dist_only) {
-      const int m0c = a.m0cnt[i];
-      const bool elig = nq > 0 ? (m0c >= r * B) : (m0c == maxm0);
-      if (!elig) continue;
-    }
-    const int cell = a.blk[i];
-    const int by = cell / p.gw, bx = cell - by * p.gw;
-    const int x0 = bx * B, y0 = by * B;
-    const int ox = x0 - r - W, oy = y0 - r - W;
-
-    // 1. stage the search window in LDS
-    phase_stage(a, p, L, ox, oy);
-
-    // 2. context ring (packed pairs) and its statistics; row B-runs
-    const RingStats rs = phase_context(p, L, sh, NU);
-    const int n0 = rs.n0, phi = rs.phi;
-    const double mean = n0 > 0 ? (double)rs.sum / (double)n0 : 0.0;
-    const int relaxed_flag = (!dist_only && nq == 0) ? SKM_FLAG_CTX_RELAXED : 0;
-
-    // BRL gate: context mean for every pixel of the block (profile rule, or
-    // the learned gate's choice in CNN mode)
-    const bool cnn = p.mode == SKM_MODE_CNN && p.cnn_active;
-    const int gsel = (cnn && !dist_only) ? (int)a.gate[i] : -1;
-    const bool profile_rule = p.mode == SKM_MODE_PROFILE || (p.mode == SKM_MODE_CNN && !cnn);
-    if (!dist_only && (p.mode == SKM_MODE_BRL || (profile_rule && (double)phi <= p.t_phi) ||
-                       gsel == SKM_LAYER_BRL)) {
-      write_const_block(a, p, i, x0, y0, mean);
-      if (tid == 0) {
-        write_info(a, i, bx, by, SKM_LAYER_BRL, round, -1, -1, 0, relaxed_flag, phi, n0, NAN);
-        a.bstate[i] = round;
-      }
-      __syncthreads();
-      continue;
-    }
-
-    // 3. admissible prototypes in raster order
-    phase_candidates(p, L, sh);
-    const int M = sh.M;
-
-    // 4. exact integer distances over the ring pixels known in both rings
-    const int nmin = max(1, (p.min_pct * n0 + 99) / 100);
-    const double two_s2 = 2.0 * p.sigma2;
-    int nc = 0, ncomp = 0;
-    for (int j = tid; j < M; j += kThreads) {
-      const uint32_t cj = L.cand[j];
-      const int base = (int)(cj & 0xffffu);
-      int d, n;
-      cand_distance(L, base, NU, d, n);
-      const bool ok = n >= nmin;
-      nc += ok;
-      ncomp += ok && n == n0;
-      const double e = ok ? -((double)d / (double)n) / two_s2 : -INFINITY;
-      L.ell[j] = e;
-      if (ok) {
-        const int b = (int)((cj >> 16) & 0xffu);
-        atomicMin(&sh.bmax[b], (unsigned long long)__double_as_longlong(e));
-        atomicAdd(&sh.bcnt[b], 1);
-      }
-      if (dist_only) {
-        const int t = (base / Wd) * D2 + (base % Wd);
-        a.dist[(size_t)i * p.ND + t] = ok ? d : -1;
-        a.cnt[(size_t)i * p.ND + t] = ok ? n : 0;
-      }
-    }
-    if (dist_only) {
-      // displacements without an admissible prototype
-      for (int t = tid; t < p.ND; t += kThreads) {
-        const int dyi = t / D2, dxi = t - dyi * D2;
-        const uint64_t w = dxi < 64 ? L.cmask[2 * dyi] : L.cmask[2 * dyi + 1];
-        const bool adm = (w >> (dxi & 63)) & 1ull;
-        if (!adm) { a.dist[(size_t)i * p.ND + t] = -1; a.cnt[(size_t)i * p.ND + t] = 0; }
-      }
-      __syncthreads();
-      continue;
-    }
-    nc = wave_sum(nc);
-    ncomp = wave_sum(ncomp);
-    if (lane == 0) { sh.red_i[wave][0] = nc; sh.red_i[wave][1] = ncomp; }
-    __syncthreads();
-
-    // 5. log nu per expansion radius.  Bucket maxima came from order-free
-    //    atomic minima of the (negative) bit patterns; cm[b] is their running
-    //    maximum over buckets <= b.  Each candidate adds exp(ell - cm[b_j]) to
-    //    its bucket (register accumulators, then wave sums in fixed order);
-    //    lane b of wave 0 combines the buckets up to b.
-    if (wave == 0) {
-      double m = lane < p.nrad ? __longlong_as_double((long long)sh.bmax[lane]) : -INFINITY;
-#pragma unroll
-      for (int o = 1; o < kMaxRadii; o <<= 1) {
-        const double y = __shfl_up(m, o, 64);
-        if (lane >= o) m = fmax(m, y);
-      }
-      if (lane < p.nrad) sh.cm[lane] = m;
-    }
-    __syncthreads();
-    {
-      double acc[kMaxRadii];
-#pragma unroll
-      for (int b = 0; b < kMaxRadii; ++b) acc[b] = 0.0;
-      for (int j = tid; j < M; j += kThreads) {
-        const double e = L.ell[j];
-        if (e == -INFINITY) continue;
-        const int bj = (int)((L.cand[j] >> 16) & 0xffu);
-        const double t = exp(e - sh.cm[bj]);
-#pragma unroll
-        for (int b = 0; b < kMaxRadii; ++b) acc[b] += (b == bj) ? t : 0.0;
-      }
-#pragma unroll
-      for (int b = 0; b < kMaxRadii; ++b) {
-        if (b < p.nrad) {
-          const double s = wave_sum(acc[b]);
-          if (lane == 0) sh.ps[wave][b] = s;
-        }
-      }
-    }
-    __syncthreads();
-    if (wave == 0) {
-      double cs = 0.0, lnu = -INFINITY;
-      int cc = 0;
-      const int b = lane;
-      if (b < p.nrad) {
-        const double mb = sh.cm[b];
-        for (int bb = 0; bb <= b; ++bb) {
-          const double sb = ((sh.ps[0][bb] + sh.ps[1][bb]) + sh.ps[2][bb]) + sh.ps[3][bb];
-          if (sb > 0.0) cs += sb * exp(sh.cm[bb] - mb);
-          cc += sh.bcnt[bb];
-        }
-        if (cc > 0) lnu = mb + log(cs);
-      }
-      const bool acc_ok = b < p.nrad && cc > 0 && lnu >= p.log_tnu;
-      const uint64_t accm = __ballot(acc_ok);
-      const int ncand = sh.red_i[0][0] + sh.red_i[1][0] + sh.red_i[2][0] + sh.red_i[3][0];
-      const int ncom = sh.red_i[0][1] + sh.red_i[1][1] + sh.red_i[2][1] + sh.red_i[3][1];
-      int layer = SKM_LAYER_IDL, ridx = p.nrad - 1, flags = relaxed_flag;
-      bool want_hql = false;
-      if (ncand == 0) {
-        layer = SKM_LAYER_BRL;
-        flags |= SKM_FLAG_NO_CAND;
-      } else if (p.mode == SKM_MODE_FULL || gsel == SKM_LAYER_HQL) {
-        want_hql = true;
-      } else if (p.mode != SKM_MODE_PLAIN) {  // PROFILE, IDL, CNN (IDL choice or no network)
-        if (accm) ridx = __ffsll((unsigned long long)accm) - 1;
-        else want_hql = p.mode == SKM_MODE_PROFILE || (p.mode == SKM_MODE_CNN && !cnn);
-      }
-      if (want_hql) {
-        if (ncom >= max(2, p.min_hql)) layer = SKM_LAYER_HQL;
-        else flags |= SKM_FLAG_NO_HQL;
-      }
-      const double lnu_r = __shfl(lnu, ridx, 64);
-      const double cs_r = __shfl(cs, ridx, 64);
-      if (lane == 0) {
-        sh.layer = layer; sh.radius_idx = ridx; sh.flags = flags;
-        sh.n_cand = ncand; sh.n_complete = ncom;
-        sh.lnu = ncand > 0 ? lnu_r : NAN;
-        sh.mstar = sh.cm[ridx];
-        sh.den = cs_r;
-      }
-    }
-    __syncthreads();
-    const int layer = sh.layer;
-    if (layer == SKM_LAYER_HQL) {
-      // HQL runs in the dense-algebra kernels after this one
-      if (tid == 0) {
-        write_info(a, i, bx, by, SKM_LAYER_HQL, round, sh.n_cand, sh.n_complete, W, sh.flags,
-                   phi, n0, sh.lnu);
-        a.bstate[i] = kNeedHql + round;
-        a.hql_list[atomicAdd(&st->n_hql, 1)] = i;
-      }
-      __syncthreads();
-      continue;
-    }
-    if (layer == SKM_LAYER_BRL) {
-      write_const_block(a, p, i, x0, y0, mean);
-      if (tid == 0) {
-        write_info(a, i, bx, by, SKM_LAYER_BRL, round, sh.n_cand, sh.n_complete, 0, sh.flags,
-                   phi, n0, sh.lnu);
-        a.bstate[i] = round;
-      }
-      __syncthreads();
-      continue;
-    }
-
-    // 6. IDL weights (eq. slpe) of the candidates inside the accepted radius,
-    //    compacted in raster order: thread t owns a contiguous slice
-    const int ridx = sh.radius_idx;
-    const double mstar = sh.mstar;
-    {
-      const int per = (M + kThreads - 1) / kThreads;
-      const int j0 = min(M, tid * per), j1 = min(M, j0 + per);
-      int cnt = 0;
-      for (int j = j0; j < j1; ++j)
-        cnt += L.ell[j] != -INFINITY && (int)((L.cand[j] >> 16) & 0xffu) <= ridx;
-      int tot = 0;
-      int pos = block_excl_scan(cnt, sh.scan, &tot);
-      for (int j = j0; j < j1; ++j) {
-        const double e = L.ell[j];
-        if (e != -INFINITY && (int)((L.cand[j] >> 16) & 0xffu) <= ridx) {
-          L.selo[pos] = (uint16_t)(L.cand[j] & 0xffffu);
-          L.selw[pos] = expf((float)(e - mstar));
-          ++pos;
-        }
-      }
-      if (tid == 0) sh.n_sel = tot;
-    }
-    __syncthreads();
-
-    // 7. weighted average of the prototypes: FP32 products, four independent
-    //    Kahan chains per pixel; groups of B*B threads split the candidates
-    //    when the block is small
-    {
-      const int nsel = sh.n_sel;
-      const int G = kThreads / B2;
-      const int g = tid / B2, pix = tid - g * B2;
-      const int py = pix / B, px = pix - py * B;
-      const int poff = (r + py) * Wd + (r + px);
-      float acc[4] = {0.f, 0.f, 0.f, 0.f}, comp[4] = {0.f, 0.f, 0.f, 0.f};
-      int j = g;
-      for (; j + 3 * G < nsel; j += 4 * G) {
-        int o[4];
-        float w[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) { o[u] = L.selo[j + u * G]; w[u] = L.selw[j + u * G]; }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const float xv = (float)(int)(int16_t)(L.winp[o[u] + poff] & 0xffffu);
-          const float y = w[u] * xv - comp[u];
-          const float tt = acc[u] + y;
-          comp[u] = (tt - acc[u]) - y;
-          acc[u] = tt;
-        }
-      }
-      for (int u = 0; j < nsel; j += G, ++u) {
-        const float xv = (float)(int)(int16_t)(L.winp[(int)L.selo[j] + poff] & 0xffffu);
-        const float y = L.selw[j] * xv - comp[u & 3];
-        const float tt = acc[u & 3] + y;
-        comp[u & 3] = (tt - acc[u & 3]) - y;
-        acc[u & 3] = tt;
-      }
-      sh.part[tid] = (((double)acc[0] - (double)comp[0]) + ((double)acc[1] - (double)comp[1])) +
-                     (((double)acc[2] - (double)comp[2]) + ((double)acc[3] - (double)comp[3]));
-      __syncthreads();
-      if (g == 0) {
-        double tot = 0.0;
-        for (int gg = 0; gg < G; ++gg) tot += sh.part[gg * B2 + pix];
-        const double xh = tot / sh.den;
-        a.work[(size_t)(y0 + py) * p.stride + x0 + px] =
-            (uint8_t)fmin(fmax(floor(xh + 0.5), 0.0), 255.0);
-        if (a.xhat && i < a.cap) a.xhat[(size_t)i * B2 + pix] = (float)xh;
-      }
-    }
+  // 1. BRL gate on the prep kernel's ring statistics: context mean for every
+  //    pixel of the block (profile rule, or the learned gate's choice in CNN
+  //    mode), without staging the window
+  const int2 rg = a.ring[i];
+  const int phi = n0 > 0 ? (rg.y >> 16) - (rg.y & 0xffff) : 0;
+  const double mean = n0 > 0 ? (double)rg.x / (double)n0 : 0.0;
+  const int relaxed_flag = (!dist_only && nq == 0) ? SKM_FLAG_CTX_RELAXED : 0;
+  const bool cnn = p.mode == SKM_MODE_CNN && p.cnn_active;
+  const int gsel = (cnn && !dist_only) ? (int)a.gate[i] : -1;
+  const bool profile_rule = p.mode == SKM_MODE_PROFILE || (p.mode == SKM_MODE_CNN && !cnn);
+  if (!dist_only && (p.mode == SKM_MODE_BRL || (profile_rule && (double)phi <= p.t_phi) ||
+                     gsel == SKM_LAYER_BRL)) {
+    write_const_block(a, p, i, x0, y0, mean);
     if (tid == 0) {
-      write_info(a, i, bx, by, SKM_LAYER_IDL, round, sh.n_cand, sh.n_complete, p.radii[ridx],
-                 sh.flags, phi, n0, sh.lnu);
+      write_info(a, i, bx, by, SKM_LAYER_BRL, round, -1, -1, 0, relaxed_flag, phi, n0, NAN);
       a.bstate[i] = round;
     }
-    __syncthreads();
+    return;
   }
+
+  // 2. stage the search window in LDS; context ring (packed pairs); row
+  //    B-runs
+  const EstLds E = carve_est_lds(lds_raw, p);
+  phase_tables(p, E.m, sh);
+  const int NU = sh.NU;
+  phase_stage(a, p, E.m, x0 - r - W, y0 - r - W);
+  phase_context(p, E.m, sh, NU);
+
+  // 3. admissible prototypes in raster order
+  phase_candidates(p, E.m, sh);
+  const int M = sh.M;
+
+  // 4. exact integer distances over the ring pixels known in both rings, one
+  //    candidate per lane; bucket maxima of the log raw weights by atomic
+  //    minima of their (negative) bit patterns
+  const int nmin = max(1, (p.min_pct * n0 + 99) / 100);
+  const double two_s2 = 2.0 * p.sigma2;
+  int nc = 0, ncomp = 0;
+  const int NU32 = align32(NU);
+  for (int j0 = wave * 64; j0 < M; j0 += kThreads) {       // uniform per wave
+    const int j = j0 + lane;
+    const bool act = j < M;
+    const uint32_t cj = act ? E.cand[j] : 0u;
+    const int base = cand_off(cj);
+    int d, n;
+    cand_distance_wave(E.m, base, NU32, d, n);
+    if (!act) continue;
+    const bool ok = n >= nmin;
+    nc += ok;
+    ncomp += ok && n == n0;
+    if (dist_only) {
+      const int t = (base / Wd) * D2 + (base % Wd);
+      a.dist[(size_t)i * p.ND + t] = ok ? d : -1;
+      a.cnt[(size_t)i * p.ND + t] = ok ? n : 0;
+      continue;
+    }
+    E.cand[j] = cj | ((uint32_t)n << 18);
+    E.dist[j] = ok ? (uint32_t)d : ~0u;
+    if (ok) {
+      const int b = cand_bucket(cj);
+      const double e = -((double)d / (double)n) / two_s2;
+      atomicMin(&sh.bmax[b], (unsigned long long)__double_as_longlong(e));
+      atomicAdd(&sh.bcnt[b], 1);
+    }
+  }
+  if (dist_only) {
+    // displacements without an admissible prototype (cmask is intact: the
+    // distance step wrote no LDS)
+    for (int t = tid; t < p.ND; t += kThreads) {
+      const int dyi = t / D2, dxi = t - dyi * D2;
+      const uint64_t w = dxi < 64 ? E.m.cmask[2 * dyi] : E.m.cmask[2 * dyi + 1];
+      const bool adm = (w >> (dxi & 63)) & 1ull;
+      if (!adm) { a.dist[(size_t)i * p.ND + t] = -1; a.cnt[(size_t)i * p.ND + t] = 0; }
+    }
+    return;
+  }
+  nc = wave_sum_full(nc);
+  ncomp = wave_sum_full(ncomp);
+  if (lane == 0) { sh.red_i[wave][0] = nc; sh.red_i[wave][1] = ncomp; }
+  __syncthreads();
+
+  // 5. log nu per expansion radius.  cm[b] is the running maximum of the
+  //    bucket maxima over buckets <= b.  Each candidate's term
+  //    exp(ell - cm[b_j]) goes to a register accumulator of its bucket; wave
+  //    sums in fixed order; lane b of wave 0 combines the buckets <= b.
+  if (wave == 0) {
+    double m = lane < p.nrad ? __longlong_as_double((long long)sh.bmax[lane]) : -INFINITY;
+#pragma unroll
+    for (int o = 1; o < kMaxRadii; o <<= 1) {
+      const double y = __shfl_up(m, o, 64);
+      if (lane >= o) m = fmax(m, y);
+    }
+    if (lane < p.nrad) sh.cm[lane] = m;
+  }
+  __syncthreads();
+  {
+    double acc[kMaxRadii];
+#pragma unroll
+    for (int b = 0; b < kMaxRadii; ++b) acc[b] = 0.0;
+    for (int j = tid; j < M; j += kThreads) {
+      const uint32_t d = E.dist[j];
+      if (d == ~0u) continue;
+      const uint32_t cj = E.cand[j];
+      const int bj = cand_bucket(cj);
+      const double t = exp(-((double)d / (double)cand_n(cj)) / two_s2 - sh.cm[bj]);
+#pragma unroll
+      for (int b = 0; b < kMaxRadii; ++b) acc[b] += (b == bj) ? t : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < kMaxRadii; ++b) {
+      if (b < p.nrad) {
+        const double s = wave_sum_full(acc[b]);
+        if (lane == 0) sh.ps[wave][b] = s;
+      }
+    }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    double cs = 0.0, lnu = -INFINITY;
+    int cc = 0;
+    const int b = lane;
+    if (b < p.nrad) {
+      const double mb = sh.cm[b];
+      for (int bb = 0; bb <= b; ++bb) {
+        const double sb = ((sh.ps[0][bb] + sh.ps[1][bb]) + sh.ps[2][bb]) + sh.ps[3][bb];
+        if (sb > 0.0) cs += sb * exp(sh.cm[bb] - mb);
+        cc += sh.bcnt[bb];
+      }
+      if (cc > 0) lnu = mb + log(cs);
+    }
+    const bool acc_ok = b < p.nrad && cc > 0 && lnu >= p.log_tnu;
+    const uint64_t accm = __ballot(acc_ok);
+    const int ncand = sh.red_i[0][0] + sh.red_i[1][0] + sh.red_i[2][0] + sh.red_i[3][0];
+    const int ncom = sh.red_i[0][1] + sh.red_i[1][1] + sh.red_i[2][1] + sh.red_i[3][1];
+    int layer = SKM_LAYER_IDL, ridx = p.nrad - 1, flags = relaxed_flag;
+    bool want_hql = false;
+    if (ncand == 0) {
+      layer = SKM_LAYER_BRL;
+      flags |= SKM_FLAG_NO_CAND;
+    } else if (p.mode == SKM_MODE_FULL || gsel == SKM_LAYER_HQL) {
+      want_hql = true;
+    } else if (p.mode != SKM_MODE_PLAIN) {  // PROFILE, IDL, CNN (IDL choice or no network)
+      if (accm) ridx = __ffsll((unsigned long long)accm) - 1;
+      else want_hql = p.mode == SKM_MODE_PROFILE || (p.mode == SKM_MODE_CNN && !cnn);
+    }
+    if (want_hql) {
+      if (ncom >= max(2, p.min_hql)) layer = SKM_LAYER_HQL;
+      else flags |= SKM_FLAG_NO_HQL;
+    }
+    const double lnu_r = __shfl(lnu, ridx, 64);
+    const double cs_r = __shfl(cs, ridx, 64);
+    if (lane == 0) {
+      sh.layer = layer; sh.radius_idx = ridx; sh.flags = flags;
+      sh.n_cand = ncand; sh.n_complete = ncom;
+      sh.lnu = ncand > 0 ? lnu_r : NAN;
+      sh.den = cs_r;
+    }
+  }
+  __syncthreads();
+  const int layer = sh.layer;
+  if (layer == SKM_LAYER_HQL) {
+    // HQL runs in the dense-algebra kernel after this one
+    if (tid == 0) {
+      write_info(a, i, bx, by, SKM_LAYER_HQL, round, sh.n_cand, sh.n_complete, W, sh.flags,
+                 phi, n0, sh.lnu);
+      a.bstate[i] = kNeedHql + round;
+      a.hql_list[atomicAdd(&st->n_hql, 1)] = i;
+    }
+    return;
+  }
+  if (layer == SKM_LAYER_BRL) {
+    write_const_block(a, p, i, x0, y0, mean);
+    if (tid == 0) {
+      write_info(a, i, bx, by, SKM_LAYER_BRL, round, sh.n_cand, sh.n_complete, 0, sh.flags,
+                 phi, n0, sh.lnu);
+      a.bstate[i] = round;
+    }
+    return;
+  }
+
+  // 6. IDL weights (eq. slpe): exp(ell - cm[ridx]) in FP64, rounded to FP32,
+  //    for the candidates inside the accepted radius, compacted in raster
+  //    order into (cand, dist) = (window offset, weight bits).  Thread t owns
+  //    a contiguous slice, read into registers before the scan's barriers.
+  const int ridx = sh.radius_idx;
+  {
+    const double mstar = sh.cm[ridx];
+    const int per = (M + kThreads - 1) / kThreads;
+    const int j0 = min(M, tid * per);
+    uint32_t o_r[kMaxPer], w_r[kMaxPer];
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxPer; ++k) {
+      const int j = j0 + k;
+      o_r[k] = 0u; w_r[k] = 0u;
+      if (k < per && j < M) {
+        const uint32_t d = E.dist[j];
+        const uint32_t cj = E.cand[j];
+        if (d != ~0u && cand_bucket(cj) <= ridx) {
+          // a weight that underflows FP32 adds nothing and is left out
+          const float w = (float)exp(-((double)d / (double)cand_n(cj)) / two_s2 - mstar);
+          o_r[k] = (uint32_t)cand_off(cj);
+          w_r[k] = __float_as_uint(w);
+          cnt += w_r[k] != 0u;
+        }
+      }
+    }
+    int tot = 0;
+    int pos = block_excl_scan(cnt, sh.scan, &tot);     // barriers inside
+#pragma unroll
+    for (int k = 0; k < kMaxPer; ++k) {
+      if (w_r[k] != 0u) { E.cand[pos] = o_r[k]; E.dist[pos] = w_r[k]; ++pos; }
+    }
+    if (tid == 0) sh.n_sel = tot;
+  }
+  __syncthreads();
+
+  // 7. weighted average of the prototypes: FP32 products, four independent
+  //    Kahan chains per pixel.  With whole waves per pixel group, 64 selected
+  //    candidates at a time come into registers and are broadcast by
+  //    readlane, eight per step: eight independent LDS reads.  Groups of B*B
+  //    threads split the candidates when the block is small.
+  {
+    const int nsel = sh.n_sel;
+    const int G = kThreads / B2;
+    const int g = tid / B2, pix = tid - g * B2;
+    const int py = pix / B, px = pix - py * B;
+    const int poff = (r + py) * Wd + (r + px);
+    float acc[4] = {0.f, 0.f, 0.f, 0.f}, comp[4] = {0.f, 0.f, 0.f, 0.f};
+    if (B2 % 64 == 0) {
+      // every lane of a wave shares g; this wave takes the chunks c with
+      // c % G == g; padding slots carry weight 0
+      for (int c0 = 64 * g; c0 < nsel; c0 += 64 * G) {
+        const int jl = c0 + lane;
+        const int ov = jl < nsel ? (int)E.cand[jl] : 0;
+        const int wv = jl < nsel ? (int)E.dist[jl] : 0;
+        const int cnt = min(64, nsel - c0);
+        for (int k0 = 0; k0 < cnt; k0 += 8) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int o = __builtin_amdgcn_readlane(ov, k0 + u);
+            const float w = __int_as_float(__builtin_amdgcn_readlane(wv, k0 + u));
+            const float xv = (float)(E.winp[o + poff] & 0xffu);
+            const float y = w * xv - comp[u & 3];
+            const float tt = acc[u & 3] + y;
+            comp[u & 3] = (tt - acc[u & 3]) - y;
+            acc[u & 3] = tt;
+          }
+        }
+      }
+    } else {
+      for (int j = g; j < nsel; j += 4 * G) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int jj = j + u * G;
+          if (jj < nsel) {
+            const float w = __uint_as_float(E.dist[jj]);
+            const float xv = (float)(E.winp[(int)E.cand[jj] + poff] & 0xffu);
+            const float y = w * xv - comp[u];
+            const float tt = acc[u] + y;
+            comp[u] = (tt - acc[u]) - y;
+            acc[u] = tt;
+          }
+        }
+      }
+    }
+    const double tot_g = (((double)acc[0] - (double)comp[0]) + ((double)acc[1] - (double)comp[1])) +
+                         (((double)acc[2] - (double)comp[2]) + ((double)acc[3] - (double)comp[3]));
+    double tot = tot_g;
+    if (G > 1) {
+      E.part[tid] = tot_g;
+      __syncthreads();
+      tot = 0.0;
+      if (g == 0)
+        for (int gg = 0; gg < G; ++gg) tot += E.part[gg * B2 + pix];
+    }
+    if (g == 0) {
+      const double xh = tot / sh.den;
+      a.work[(size_t)(y0 + py) * p.stride + x0 + px] =
+          (uint8_t)fmin(fmax(floor(xh + 0.5), 0.0), 255.0);
+      if (a.xhat && i < a.cap) a.xhat[(size_t)i * B2 + pix] = (float)xh;
+    }
+  }
+  if (tid == 0)
+    write_info(a, i, bx, by, SKM_LAYER_IDL, round, sh.n_cand, sh.n_complete, p.radii[ridx],
+               sh.flags, phi, n0, sh.lnu);
+  if (tid == 0) a.bstate[i] = round;
 }
 
 // -------------------------------------------------------------- finalize
@@ -597,8 +637,8 @@ hipError_t launch_init(const FrameArgs& a, const DevParams& p, hipStream_t s) {
 static hipError_t launch_main(const FrameArgs& a, const DevParams& p, int max_blocks,
                               int dist_only, hipStream_t s) {
   const size_t lds = main_lds_bytes(p);
-  hipLaunchKernelGGL(k_round_main, dim3(clamp_grid(max_blocks, 2048)), dim3(kThreads), lds, s, a,
-                     p, dist_only);
+  const int grid = ((max_blocks < 1 ? 1 : max_blocks) + 7) / 8 * 8;   // xcd_block cover
+  hipLaunchKernelGGL(k_round_main, dim3(grid), dim3(kThreads), lds, s, a, p, dist_only);
   return hipGetLastError();
 }
 

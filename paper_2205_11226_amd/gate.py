@@ -24,9 +24,10 @@ import time
 
 import numpy as np
 
-# relative cost of a block per layer, for choosing thresholds (measured order
-# of magnitude on MI355X: context mean vs distances + weights vs full K-MMSE)
-LAYER_COST = {"brl": 0.25, "idl": 1.0, "hql": 100.0}
+# relative cost of a block per layer, for choosing thresholds (order of
+# magnitude measured on MI355X: a context mean is nearly free next to the
+# distances and weights of IDL, and full K-MMSE costs thousands of IDL blocks)
+LAYER_COST = {"brl": 0.2, "idl": 1.0, "hql": 2000.0}
 
 
 def _psnr_from_sse(sse, npx):
@@ -67,23 +68,33 @@ def block_labels(ctx, frame, mask, b=16, t_nu=0.1):
             "npx": frame.size}
 
 
+KINDS = ("lattice", "isolated", "smooth")
+
+
 def _gen(args):
+    """One training frame: 1080p textured luma with 25% dispersed loss
+    (lattice), 720p textured luma with isolated loss (isolated), or 720p
+    luma without texture with isolated loss (smooth)."""
     import synth
     kind, seed = args
     if kind == "lattice":
         f = synth.make_luma(1080, 1920, seed, n_bumps=150, n_edges=40, texture=True)
         r = np.random.default_rng(seed + 1)
         m = synth.loss_dispersed(1080, 1920, 16, int(r.integers(2)), int(r.integers(2)))
-    else:
+    elif kind == "isolated":
         f = synth.make_luma(720, 1280, seed, n_bumps=80, n_edges=24, texture=True)
+        m = synth.loss_isolated(720, 1280, 16, 420, seed + 1)
+    else:
+        f = synth.make_luma(720, 1280, seed, n_bumps=80, n_edges=24, texture=False)
         m = synth.loss_isolated(720, 1280, 16, 420, seed + 1)
     return f, m
 
 
-def make_frames(n_lattice, n_isolated, seed0, workers=8):
+def make_frames(counts, seed0, workers=8):
+    """counts: frames per kind, in KINDS order."""
     import multiprocessing as mp
-    jobs = [("lattice", seed0 + i) for i in range(n_lattice)] + \
-           [("isolated", seed0 + 5000 + i) for i in range(n_isolated)]
+    jobs = [(k, seed0 + 5000 * j + i) for j, (k, n) in enumerate(zip(KINDS, counts))
+            for i in range(n)]
     with mp.get_context("fork").Pool(workers) as pool:
         return pool.map(_gen, jobs)
 
@@ -130,8 +141,8 @@ def train(ctx, x, y, epochs=8, batch=256, lr=1e-3, seed=0, log=print):
 
 
 def fit_thresholds(pred, recs, max_dpsnr=0.05, margin=0.01):
-    """Thresholds minimising the layer cost subject to a mean frame PSNR loss
-    against full K-MMSE of at most max_dpsnr - margin dB."""
+    """Thresholds minimising the layer cost subject to a PSNR loss against
+    full K-MMSE of at most max_dpsnr - margin dB on every frame."""
     q1 = np.unique(np.quantile(pred[:, 0], np.linspace(0, 1, 121)))
     q2 = np.unique(np.quantile(pred[:, 1], np.linspace(0, 1, 61)))
     best = None
@@ -154,9 +165,9 @@ def fit_thresholds(pred, recs, max_dpsnr=0.05, margin=0.01):
                 dps.append(fp - _psnr_from_sse(sse, r["npx"]))
                 cost += (LAYER_COST["brl"] * brl.sum() + LAYER_COST["idl"] * idl.sum() +
                          LAYER_COST["hql"] * hql.sum())
-            dmean = float(np.mean(dps))
-            if dmean <= max_dpsnr - margin and (best is None or cost < best[0]):
-                best = (cost, float(t1), float(t2), dmean)
+            dworst = float(np.max(dps))
+            if dworst <= max_dpsnr - margin and (best is None or cost < best[0]):
+                best = (cost, float(t1), float(t2), dworst)
     return best
 
 
@@ -164,8 +175,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
     ap.add_argument("--lattice", type=int, default=80)
-    ap.add_argument("--isolated", type=int, default=90)
-    ap.add_argument("--val", type=int, default=8)
+    ap.add_argument("--isolated", type=int, default=60)
+    ap.add_argument("--smooth", type=int, default=60)
+    ap.add_argument("--val", type=int, default=6, help="validation frames per kind")
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--seed", type=int, default=4000)
     ap.add_argument("--workers", type=int, default=8)
@@ -173,8 +185,8 @@ def main():
     import torch
     import paper_2205_11226_amd as skm
     t0 = time.time()
-    frames = make_frames(args.lattice, args.isolated, args.seed, args.workers)
-    vframes = make_frames(args.val, args.val, args.seed + 20000, args.workers)
+    frames = make_frames((args.lattice, args.isolated, args.smooth), args.seed, args.workers)
+    vframes = make_frames((args.val,) * len(KINDS), args.seed + 20000, args.workers)
     print(f"frames generated in {time.time() - t0:.1f}s", flush=True)
     ctx = skm.Context(0)
     t0 = time.time()
@@ -197,8 +209,8 @@ def main():
         print("no threshold pair meets the PSNR bound; keeping the profile rule", flush=True)
         sys.exit(1)
     cost, t1, t2, dps = best
-    print(f"thresholds tau1 {t1:.4f} tau2 {t2:.4f}: mean dPSNR {dps:.4f} dB, cost {cost:.0f}",
-          flush=True)
+    print(f"thresholds tau1 {t1:.4f} tau2 {t2:.4f}: worst-frame dPSNR {dps:.4f} dB, "
+          f"cost {cost:.0f}", flush=True)
     ctx.cnn_set_thresholds(t1 if math.isfinite(t1) else -1e30, t2 if math.isfinite(t2) else 1e30)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     ctx.cnn_save(args.out)
