@@ -502,19 +502,45 @@ __global__ __launch_bounds__(kThreads) void k_cnn_gate(FrameArgs a, DevParams p,
   const int lw = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   const int per = (n_lost + gridDim.x - 1) / gridDim.x;
   const int i_end = min(n_lost, (lw + 1) * per);
-  for (int i = lw * per; i < i_end; ++i) {
-    if (a.bstate[i] != 0) continue;
-    const int m0c = a.m0cnt[i];
-    if (!(nq > 0 ? (m0c >= p.r * p.B) : (m0c == maxm0))) continue;
-    const int cell = a.blk[i];
+  // the input pixels of block i + 1 are loaded while block i runs
+  constexpr int kPer = (kP * kP + kThreads - 1) / kThreads;
+  int v[kPer];
+  auto load_block = [&](int blk) {
+    const int cell = a.blk[blk];
     const int by = cell / p.gw, bx = cell - by * p.gw;
-    for (int idx = tid; idx < kP * kP; idx += kThreads) {
-      float c0, c1;
-      input_pixel(a, p, by, bx, idx, c0, c1);
+    const int gy0 = by * p.B + p.B / 2 - kP / 2, gx0 = bx * p.B + p.B / 2 - kP / 2;
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int idx = tid + t * kThreads;
       const int py = idx / kP, px = idx - py * kP;
-      G.in[(py + 1) * kIn + px + 1] = bf16_bits(c0) | (bf16_bits(c1) << 16);
+      const int gy = gy0 + py, gx = gx0 + px;
+      const bool in = idx < kP * kP && gy >= 0 && gy < p.height && gx >= 0 && gx < p.width;
+      const int cy = min(max(gy, 0), p.height - 1), cx = min(max(gx, 0), p.width - 1);
+      const int val = a.val[(size_t)cy * p.width + cx];
+      v[t] = in ? val : -1;
+    }
+  };
+  const int i_begin = lw * per;
+  if (i_begin < i_end) load_block(i_begin);
+  for (int i = i_begin; i < i_end; ++i) {
+    const bool elig = a.bstate[i] == 0 &&
+                      (nq > 0 ? (a.m0cnt[i] >= p.r * p.B) : (a.m0cnt[i] == maxm0));
+    if (elig) {
+      // c0 = (u - 128) / 128 at known pixels (exact in bf16), c1 = 1 at unknown
+#pragma unroll
+      for (int t = 0; t < kPer; ++t) {
+        const int idx = tid + t * kThreads;
+        if (idx < kP * kP) {
+          const int py = idx / kP, px = idx - py * kP;
+          const float c0 = v[t] >= 0 ? (float)(v[t] - 128) * (1.0f / 128.0f) : 0.0f;
+          const float c1 = v[t] >= 0 ? 0.0f : 1.0f;
+          G.in[(py + 1) * kIn + px + 1] = bf16_bits(c0) | (bf16_bits(c1) << 16);
+        }
+      }
     }
     __syncthreads();
+    if (i + 1 < i_end) load_block(i + 1);
+    if (!elig) continue;
     float y0 = 0.0f, y1 = 0.0f;
     gate_network(G, W, wq, y0, y1);
     if (tid == 0) {

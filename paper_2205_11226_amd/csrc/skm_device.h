@@ -183,20 +183,22 @@ static __device__ __forceinline__ int cand_n(uint32_t c) { return (int)(c >> 18)
 //   winp    u32 [Wd*Wd]   as in MainLds
 //   qu      u32x2 [NR+32] as in MainLds
 //   utab    u32 [NR]      as in MainLds
-//   cand    u32 [MC]      candidate words; n added by the distance step
-//   dist    u32 [MC]      exact distance d (~0u = dropped); then the FP32
-//                         weight bits of each candidate (0 = not used).
-//                         Before the distance step it holds rowbits,
-//                         runbits and cmask.
-//   part    f64 [kThreads] cross-group sums of the weighted average (only
-//                         when B*B < kThreads); aliases qu and utab
+//   cand    u32 [MC+16]   candidate words; n added by the distance step
+//   dist    u32 [MC]      exact distance d (~0u = dropped).  Before the
+//                         distance step it holds rowbits, runbits and cmask.
+//   sel     u32x2         after the weights step, cand and dist together
+//                         hold the selected (window offset, FP32 weight)
+//                         pairs, zero-padded to a multiple of 8
+//   part    f32 [2*kThreads] cross-group sums of the weighted average;
+//                         aliases qu and utab when they are large enough
 struct EstLds {
   uint32_t* winp;
   uint2* qu;
   uint32_t* utab;
   uint32_t* cand;
   uint32_t* dist;
-  double* part;
+  uint2* sel;
+  float* part;
   MainLds m;          // view for the shared phases (ell, selw, selo unused)
 };
 
@@ -206,13 +208,13 @@ __host__ __device__ inline size_t est_lds_layout(const DevParams& p, size_t* off
   offs[1] = o; o = align_up(o + sizeof(uint2) * (p.NR + 32), 16);
   offs[2] = o; o = align_up(o + sizeof(uint32_t) * p.NR, 16);
   const size_t qu_utab = o - offs[1];
-  offs[3] = o; o = align_up(o + sizeof(uint32_t) * p.MC, 16);
-  offs[4] = o;
+  offs[3] = o; o = align_up(o + sizeof(uint32_t) * (p.MC + 16), 16);
+  offs[4] = o;                                       // contiguous with cand
   const size_t bits = sizeof(uint64_t) * 2 * (2 * p.Wd + 2 * p.W + 1);
   const size_t dist = sizeof(uint32_t) * p.MC;
   o = align_up(o + (dist > bits ? dist : bits), 16);
   offs[5] = offs[1];
-  const size_t part = (size_t)p.B * p.B < (size_t)kThreads ? sizeof(double) * kThreads : 0;
+  const size_t part = sizeof(float) * 2 * kThreads;
   if (part > qu_utab) { offs[5] = o; o = align_up(o + part, 16); }
   return o;
 }
@@ -226,7 +228,8 @@ static __device__ __forceinline__ EstLds carve_est_lds(unsigned char* raw, const
   E.utab = (uint32_t*)(raw + offs[2]);
   E.cand = (uint32_t*)(raw + offs[3]);
   E.dist = (uint32_t*)(raw + offs[4]);
-  E.part = (double*)(raw + offs[5]);
+  E.sel = (uint2*)(raw + offs[3]);
+  E.part = (float*)(raw + offs[5]);
   E.m.ell = nullptr;
   E.m.selw = nullptr;
   E.m.selo = nullptr;
@@ -341,7 +344,7 @@ static __device__ __forceinline__ void phase_stage(const FrameArgs& a, const Dev
                                                    const MainLds& L, int ox, int oy) {
   const int lane = lane_id(), wave = wave_id();
   const int Wd = p.Wd, nw = kThreads / 64;
-  constexpr int kRows = 6;
+  constexpr int kRows = 18;
   for (int wy0 = wave; wy0 < Wd; wy0 += kRows * nw) {
     int v0[kRows], v1[kRows];
 #pragma unroll
@@ -498,26 +501,36 @@ static __device__ __forceinline__ void cand_distance(const MainLds& L, int base,
   n_out = (int)(nacc & 0xffffu) + (int)(nacc >> 16);
 }
 
-// The same distance for one candidate per lane, called by every lane of the
-// wave (a lane without a candidate passes base 0 and ignores the result).
-// The units come 32 at a time into registers and are broadcast by
-// readlane, so each step is one independent LDS read of the window.
+// Six-operation form of pair_dist: unknown halves of either side give a
+// zero difference; `nbad` counts them (sdot2 of the 0 / -1 masks).
+static __device__ __forceinline__ void pair_dist6(uint32_t q, uint32_t pp, int& d, int& nbad) {
+  const short2v qa = __builtin_bit_cast(short2v, q), pa = __builtin_bit_cast(short2v, pp);
+  const short2v bad = (qa | pa) >> (short2v){15, 15};          // -1 where unknown
+  const short2v df = (qa - pa) & ~bad;
+  d = __builtin_amdgcn_sdot2(df, df, d, false);
+  nbad = __builtin_amdgcn_sdot2(bad, bad, nbad, false);
+}
+
+// Distance of one candidate per lane (footprint origin `base`; a lane
+// without a candidate passes 0 and ignores the result).  Every lane reads
+// the same unit (q pair, offset) -- an LDS broadcast -- and its own window
+// pair; 16 units per step keep 32 independent reads in flight.  NU32 is a
+// multiple of 32 (padded units are unknown pairs).
 static __device__ __forceinline__ void cand_distance_wave(const MainLds& L, int base, int NU32,
                                                           int& d_out, int& n_out) {
-  int d = 0;
-  uint32_t nacc = 0;
-  const int lane = lane_id();
-  for (int u0 = 0; u0 < NU32; u0 += 32) {
-    const uint2 qv = L.qu[u0 + (lane & 31)];
-#pragma unroll 16
-    for (int k = 0; k < 32; ++k) {
-      const uint32_t q = (uint32_t)__builtin_amdgcn_readlane((int)qv.x, k);
-      const int off = __builtin_amdgcn_readlane((int)qv.y, k);
-      pair_dist(q, L.winp[base + off], d, nacc);
-    }
+  int d = 0, nbad = 0;
+  for (int u0 = 0; u0 < NU32; u0 += 16) {
+    uint2 qq[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) qq[t] = L.qu[u0 + t];
+    uint32_t pv[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) pv[t] = L.winp[base + (int)qq[t].y];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) pair_dist6(qq[t].x, pv[t], d, nbad);
   }
   d_out = d;
-  n_out = (int)(nacc & 0xffffu) + (int)(nacc >> 16);
+  n_out = 2 * NU32 - nbad;
 }
 
 }  // namespace skm

@@ -423,76 +423,75 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
     int pos = block_excl_scan(cnt, sh.scan, &tot);     // barriers inside
 #pragma unroll
     for (int k = 0; k < kMaxPer; ++k) {
-      if (w_r[k] != 0u) { E.cand[pos] = o_r[k]; E.dist[pos] = w_r[k]; ++pos; }
+      if (w_r[k] != 0u) { E.sel[pos] = make_uint2(o_r[k], w_r[k]); ++pos; }
     }
+    if (tid < ((tot + 7) & ~7) - tot) E.sel[tot + tid] = make_uint2(0u, 0u);
     if (tid == 0) sh.n_sel = tot;
   }
   __syncthreads();
 
-  // 7. weighted average of the prototypes: FP32 products, four independent
-  //    Kahan chains per pixel.  With whole waves per pixel group, 64 selected
-  //    candidates at a time come into registers and are broadcast by
-  //    readlane, eight per step: eight independent LDS reads.  Groups of B*B
-  //    threads split the candidates when the block is small.
+  // 7. weighted average of the prototypes.  A lane owns two horizontally
+  //    adjacent pixels (one LDS read of a window pair); candidate groups of
+  //    B*B/2 lanes split the selected candidates in blocks of 8: each lane of
+  //    a group reads the same (offset, weight) -- an LDS broadcast.  Within a
+  //    block FP32 FMA; blocks enter a Kahan-compensated sum.
   {
     const int nsel = sh.n_sel;
-    const int G = kThreads / B2;
-    const int g = tid / B2, pix = tid - g * B2;
-    const int py = pix / B, px = pix - py * B;
+    const int NP = B2 / 2;                  // pixel pairs per block
+    const int GG = kThreads / NP;           // candidate groups
+    const int h = tid / NP, q = tid - h * NP;
+    const int py = (2 * q) / B, px = 2 * q - py * B;
     const int poff = (r + py) * Wd + (r + px);
-    float acc[4] = {0.f, 0.f, 0.f, 0.f}, comp[4] = {0.f, 0.f, 0.f, 0.f};
-    if (B2 % 64 == 0) {
-      // every lane of a wave shares g; this wave takes the chunks c with
-      // c % G == g; padding slots carry weight 0
-      for (int c0 = 64 * g; c0 < nsel; c0 += 64 * G) {
-        const int jl = c0 + lane;
-        const int ov = jl < nsel ? (int)E.cand[jl] : 0;
-        const int wv = jl < nsel ? (int)E.dist[jl] : 0;
-        const int cnt = min(64, nsel - c0);
-        for (int k0 = 0; k0 < cnt; k0 += 8) {
+    float acc0 = 0.f, acc1 = 0.f, comp0 = 0.f, comp1 = 0.f;
+    for (int j0 = 8 * h; j0 < nsel; j0 += 8 * GG) {
+      uint2 sv[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int o = __builtin_amdgcn_readlane(ov, k0 + u);
-            const float w = __int_as_float(__builtin_amdgcn_readlane(wv, k0 + u));
-            const float xv = (float)(E.winp[o + poff] & 0xffu);
-            const float y = w * xv - comp[u & 3];
-            const float tt = acc[u & 3] + y;
-            comp[u & 3] = (tt - acc[u & 3]) - y;
-            acc[u & 3] = tt;
-          }
+      for (int t = 0; t < 8; ++t) sv[t] = E.sel[j0 + t];
+      uint32_t pv[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) pv[t] = E.winp[(int)sv[t].x + poff];
+      float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const float w = __uint_as_float(sv[t].y);
+        s0 = fmaf(w, (float)(pv[t] & 0xffu), s0);
+        s1 = fmaf(w, (float)((pv[t] >> 16) & 0xffu), s1);
+      }
+      float y = s0 - comp0, tt = acc0 + y;
+      comp0 = (tt - acc0) - y; acc0 = tt;
+      y = s1 - comp1; tt = acc1 + y;
+      comp1 = (tt - acc1) - y; acc1 = tt;
+    }
+    float v0 = acc0 - comp0, v1 = acc1 - comp1;
+    if (GG > 1) {
+      E.part[2 * tid] = v0;
+      E.part[2 * tid + 1] = v1;
+      __syncthreads();
+      if (h == 0) {
+        double t0 = 0.0, t1 = 0.0;
+        for (int hh = 0; hh < GG; ++hh) {
+          t0 += (double)E.part[2 * (hh * NP + q)];
+          t1 += (double)E.part[2 * (hh * NP + q) + 1];
+        }
+        v0 = 0.f; v1 = 0.f;
+        const double x0h = t0 / sh.den, x1h = t1 / sh.den;
+        uint8_t* o = a.work + (size_t)(y0 + py) * p.stride + x0 + px;
+        o[0] = (uint8_t)fmin(fmax(floor(x0h + 0.5), 0.0), 255.0);
+        o[1] = (uint8_t)fmin(fmax(floor(x1h + 0.5), 0.0), 255.0);
+        if (a.xhat && i < a.cap) {
+          a.xhat[(size_t)i * B2 + 2 * q] = (float)x0h;
+          a.xhat[(size_t)i * B2 + 2 * q + 1] = (float)x1h;
         }
       }
     } else {
-      for (int j = g; j < nsel; j += 4 * G) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int jj = j + u * G;
-          if (jj < nsel) {
-            const float w = __uint_as_float(E.dist[jj]);
-            const float xv = (float)(E.winp[(int)E.cand[jj] + poff] & 0xffu);
-            const float y = w * xv - comp[u];
-            const float tt = acc[u] + y;
-            comp[u] = (tt - acc[u]) - y;
-            acc[u] = tt;
-          }
-        }
+      const double x0h = (double)v0 / sh.den, x1h = (double)v1 / sh.den;
+      uint8_t* o = a.work + (size_t)(y0 + py) * p.stride + x0 + px;
+      o[0] = (uint8_t)fmin(fmax(floor(x0h + 0.5), 0.0), 255.0);
+      o[1] = (uint8_t)fmin(fmax(floor(x1h + 0.5), 0.0), 255.0);
+      if (a.xhat && i < a.cap) {
+        a.xhat[(size_t)i * B2 + 2 * q] = (float)x0h;
+        a.xhat[(size_t)i * B2 + 2 * q + 1] = (float)x1h;
       }
-    }
-    const double tot_g = (((double)acc[0] - (double)comp[0]) + ((double)acc[1] - (double)comp[1])) +
-                         (((double)acc[2] - (double)comp[2]) + ((double)acc[3] - (double)comp[3]));
-    double tot = tot_g;
-    if (G > 1) {
-      E.part[tid] = tot_g;
-      __syncthreads();
-      tot = 0.0;
-      if (g == 0)
-        for (int gg = 0; gg < G; ++gg) tot += E.part[gg * B2 + pix];
-    }
-    if (g == 0) {
-      const double xh = tot / sh.den;
-      a.work[(size_t)(y0 + py) * p.stride + x0 + px] =
-          (uint8_t)fmin(fmax(floor(xh + 0.5), 0.0), 255.0);
-      if (a.xhat && i < a.cap) a.xhat[(size_t)i * B2 + pix] = (float)xh;
     }
   }
   if (tid == 0)

@@ -41,7 +41,8 @@ def check(ctx, frame, mask, mode, **kw):
     out_g, info_g, xh_g, out_o, xh_o, info_o = run_both(ctx, frame, mask, mode, **kw)
     t_nu = kw.get("t_nu", 0.1)
     b = kw.get("block", 16)
-    st = compare(frame, mask, out_g, info_g, xh_g, out_o, xh_o, info_o, t_nu, b)
+    st = compare(frame, mask, out_g, info_g, xh_g, out_o, xh_o, info_o, t_nu, b,
+                 ring=kw.get("ring", 4), window=kw.get("window", 24))
     print(mode, kw, st, flush=True)
     return st, info_g
 
