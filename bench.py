@@ -191,32 +191,58 @@ def main():
     p_prof = skm.default_params(mode="profile", profile=args.profile)
     p_plain = skm.default_params(mode="plain")
 
-    def run(p, k):
-        for _ in range(k):
-            ctx.conceal_device(fd, md, p, out=out, want_info=False, want_xhat=False)
+    outs = [torch.empty_like(fd) for _ in range(8)]
 
-    def timed(p, events=False):
-        run(p, args.warmup)
+    def jobs_for(p, k):
+        return [(fd, md, outs[j % len(outs)], p) for j in range(k)]
+
+    def timed_batch(p, events=False):
+        """One skm_conceal_batch over `steps` frames (frames in flight on the
+        context's streams, graphs replayed), after an untimed warm-up batch."""
+        ctx.conceal_batch(jobs_for(p, max(args.warmup, 1)))
+        jobs = jobs_for(p, args.steps)
         torch.cuda.synchronize()
         ctx.profile_enable(events)
         ctx.profile_read()                  # drop earlier event pairs
         t0 = time.perf_counter()
-        run(p, args.steps)
+        res = ctx.conceal_batch(jobs)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         ctx.profile_enable(False)
+        assert all(r[2] == 0 and r[0] == res[0][0] for r in res)
         return dt
 
-    # the estimation kernel is bracketed by HIP events on its own stream
-    # during the timed steps of the headline configuration
-    sec_lay = timed(p_lay, events=True)
+    def timed_single(p, k):
+        """Synchronous single-frame calls: latency per frame."""
+        for _ in range(max(args.warmup, 1)):
+            ctx.conceal_device(fd, md, p, out=out, want_info=False, want_xhat=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            ctx.conceal_device(fd, md, p, out=out, want_info=False, want_xhat=False)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    # launch configuration picked by the library's autotuner on a short batch
+    tune_ms = ctx.autotune(jobs_for(p_lay, 8), reps=2)
+    tuned = {"batch_streams": ctx.get_option(skm.OPT_BATCH_STREAMS),
+             "graphs": ctx.get_option(skm.OPT_GRAPHS),
+             "gate_grid": ctx.get_option(skm.OPT_GATE_GRID), "tune_batch8_ms": tune_ms}
+    print(f"# autotune: {tuned}", file=sys.stderr, flush=True)
+
+    sec_lay = timed_batch(p_lay)
+    # the estimation kernel bracketed by HIP events on its own stream, over
+    # the same batch again (event timing makes the library launch eagerly)
+    sec_lay_ev = timed_batch(p_lay, events=True)
     ms_tot, launches = ctx.profile_read()
     k_ms = ms_tot / max(launches, 1)
-    print(f"# layered ({args.mode}): {sec_lay * 1e3:.3f} ms/frame, estimation kernel "
-          f"{k_ms * 1e3:.1f} us x {launches / args.steps:.0f} per frame", file=sys.stderr, flush=True)
-    sec_plain = timed(p_plain)
+    print(f"# layered ({args.mode}): {sec_lay * 1e3:.3f} ms/frame ({sec_lay_ev * 1e3:.3f} with "
+          f"event timing), estimation kernel {k_ms * 1e3:.1f} us x {launches / args.steps:.0f} "
+          f"per frame", file=sys.stderr, flush=True)
+    lat_lay = timed_single(p_lay, min(args.steps, 20))
+    sec_plain = timed_batch(p_plain)
     print(f"# plain: {sec_plain * 1e3:.3f} ms/frame", file=sys.stderr, flush=True)
-    sec_prof = timed(p_prof)
+    sec_prof = timed_batch(p_prof)
     print(f"# profile rule: {sec_prof * 1e3:.3f} ms/frame", file=sys.stderr, flush=True)
 
     # statistics of one frame per mode (not timed)
@@ -257,6 +283,10 @@ def main():
             "mode": args.mode, "profile": args.profile,
             "lost_blocks": n_lost,
             "frames_per_s": 1.0 / sec_lay,
+            "timed": f"one skm_conceal_batch call over {args.steps} frames (the same input, "
+                     f"outputs in 8 rotating buffers), launch configuration from skm_autotune",
+            "launch_config": tuned,
+            "single_frame_latency_ms": lat_lay * 1e3,
             "psnr_layered_db": ps_lay,
             "psnr_full_kmmse_db": ps_full,
             "delta_psnr_db": ps_full - ps_lay,
@@ -279,6 +309,8 @@ def main():
             "ops_per_launch": ops,
             "kernel_ms": k_ms,
             "launches_timed": launches,
+            "kernel_timing": "HIP events around each launch, over a second run of the timed "
+                             "batch (eager launches)",
         },
         "cpu_baseline": cpu,
     }

@@ -216,13 +216,60 @@ skm_status skm_cnn_train_step(skm_ctx* ctx, const uint16_t* d_inputs, const floa
  * lost-cell raster order (entries of blocks the gate did not see are stale). */
 skm_status skm_cnn_last_predictions(skm_ctx* ctx, float* host, int32_t cap);
 
+/* Batch: conceal n independent frames (device buffers), each with its own
+ * geometry and parameters (block sizes may differ).  The frames are spread
+ * over up to SKM_OPT_BATCH_STREAMS frame slots, each with its own device
+ * workspace and HIP stream, so that several frames are in flight; each
+ * frame's pipeline (loss geometry, rounds, state copy) is replayed from a
+ * captured hipGraph when its arguments repeat.  Work starts after the work
+ * already enqueued on hip_stream and is complete (every frame) when the call
+ * returns.  Per frame: `n_lost`, `rounds` and `status` are written; the
+ * call returns the first non-OK status, after finishing every frame it could.
+ * Not in the paper: batching is an implementation layer around the
+ * per-frame method (Sec. "Reconstruction framework"). */
+typedef struct skm_frame_desc {
+  const uint8_t* frame;        /* device, stride-pitched uint8 plane          */
+  const uint8_t* mask;         /* device, same pitch, nonzero = lost          */
+  uint8_t* out;                /* device, same pitch; may alias frame         */
+  int32_t width, height, stride;
+  const skm_params* params;    /* host pointer, read during the call          */
+  skm_block_info* info;        /* device, optional                            */
+  float* xhat;                 /* device, optional                            */
+  int32_t cap;                 /* capacity of info / xhat in blocks           */
+  int32_t n_lost;              /* out */
+  int32_t rounds;              /* out */
+  int32_t status;              /* out: skm_status of this frame               */
+  int32_t reserved;
+} skm_frame_desc;
+skm_status skm_conceal_batch(skm_ctx* ctx, skm_frame_desc* frames, int32_t n, void* hip_stream);
+
+/* Launch configuration (library-level, not the method's parameters). */
+enum {
+  SKM_OPT_GRAPHS = 1,         /* 1 (default): replay captured hipGraphs; 0: eager */
+  SKM_OPT_BATCH_STREAMS = 2,  /* frames in flight in skm_conceal_batch, 1..8 (4)  */
+  SKM_OPT_GATE_GRID = 3       /* workgroups of the CNN gate kernel, multiple of 8
+                                 in 8..4096 (512)                                 */
+};
+skm_status skm_set_option(skm_ctx* ctx, int32_t option, int64_t value);
+skm_status skm_get_option(skm_ctx* ctx, int32_t option, int64_t* value);
+
+/* Autotuner: times skm_conceal_batch on these frames under each launch
+ * configuration (1, 2, 4, 8 streams; graphs on and off; gate grids 256, 512
+ * and 1024 when a frame uses SKM_MODE_CNN), keeping the best of `reps` runs
+ * each, and sets the fastest configuration on the context.  The frames are
+ * concealed several times.  best_ms (optional) receives the best batch time. */
+skm_status skm_autotune(skm_ctx* ctx, skm_frame_desc* frames, int32_t n, int32_t reps,
+                        double* best_ms);
+
 /* Kernel timing for measurement tools (not needed for concealment).  While
  * enabled, the context brackets every launch of its per-block estimation
  * kernel (the kernel that stages the search window, computes the distances,
  * weights and weighted averages) with a HIP event pair on the stream that
- * launch uses.  skm_profile_read synchronises on those events, returns the
- * summed elapsed time in milliseconds and the number of launches since the
- * last read, and resets both.  Either pointer may be NULL. */
+ * launch uses; while enabled, frames are launched eagerly (no graph
+ * replay).  Each frame's pairs are read when the frame completes;
+ * skm_profile_read returns the summed elapsed time in milliseconds and the
+ * number of launches since the last read, and resets both.  Either pointer
+ * may be NULL. */
 skm_status skm_profile_enable(skm_ctx* ctx, int32_t enable);
 skm_status skm_profile_read(skm_ctx* ctx, double* total_ms, int32_t* launches);
 

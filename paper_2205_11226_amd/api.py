@@ -20,7 +20,9 @@ EXPORTS = ("skm_default_params", "skm_create", "skm_destroy", "skm_conceal",
            "skm_conceal_device", "skm_distances_device", "skm_cnn_init", "skm_cnn_set_weights",
            "skm_cnn_get_weights", "skm_cnn_set_thresholds", "skm_save_cnn", "skm_load_cnn",
            "skm_cnn_inputs", "skm_cnn_forward", "skm_cnn_gradients", "skm_cnn_train_step",
-           "skm_cnn_last_predictions", "skm_profile_enable", "skm_profile_read", "skm_last_error")
+           "skm_cnn_last_predictions", "skm_conceal_batch", "skm_set_option", "skm_get_option",
+           "skm_autotune", "skm_profile_enable", "skm_profile_read", "skm_last_error")
+OPT_GRAPHS, OPT_BATCH_STREAMS, OPT_GATE_GRID = 1, 2, 3
 CNN_PARAMS = 19170
 
 
@@ -44,6 +46,16 @@ class BlockInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "bx", "by", "layer", "round", "n_cand", "n_complete", "radius", "flags", "phi",
         "n_ctx")] + [("log_nu", ctypes.c_double)]
+
+
+class FrameDesc(ctypes.Structure):
+    _fields_ = [
+        ("frame", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("out", ctypes.c_void_p),
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("stride", ctypes.c_int32),
+        ("params", ctypes.POINTER(Params)), ("info", ctypes.c_void_p), ("xhat", ctypes.c_void_p),
+        ("cap", ctypes.c_int32), ("n_lost", ctypes.c_int32), ("rounds", ctypes.c_int32),
+        ("status", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
 
 
 BLOCK_INFO_DTYPE = np.dtype([(n, "<i4") for n in (
@@ -96,6 +108,14 @@ def _load():
               "skm_cnn_forward", "skm_cnn_gradients", "skm_cnn_train_step",
               "skm_cnn_last_predictions"):
         getattr(so, n).restype = i32
+    so.skm_conceal_batch.argtypes = [vp, p(FrameDesc), i32, vp]
+    so.skm_conceal_batch.restype = i32
+    so.skm_set_option.argtypes = [vp, i32, ctypes.c_int64]
+    so.skm_set_option.restype = i32
+    so.skm_get_option.argtypes = [vp, i32, p(ctypes.c_int64)]
+    so.skm_get_option.restype = i32
+    so.skm_autotune.argtypes = [vp, p(FrameDesc), i32, i32, p(ctypes.c_double)]
+    so.skm_autotune.restype = i32
     so.skm_profile_enable.argtypes = [vp, i32]
     so.skm_profile_enable.restype = i32
     so.skm_profile_read.argtypes = [vp, p(ctypes.c_double), p(i32)]
@@ -171,6 +191,61 @@ class Context:
         n = ctypes.c_int32(0)
         _check(lib.skm_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    # ------------------------------------------------------------ options
+    def set_option(self, option: int, value: int):
+        _check(lib.skm_set_option(self._h, int(option), int(value)))
+
+    def get_option(self, option: int) -> int:
+        v = ctypes.c_int64(0)
+        _check(lib.skm_get_option(self._h, int(option), ctypes.byref(v)))
+        return v.value
+
+    # -------------------------------------------------------------- batch
+    @staticmethod
+    def _frame_descs(jobs):
+        """jobs: sequence of (frame, mask, out, params[, info, xhat, cap])."""
+        descs = (FrameDesc * len(jobs))()
+        keep = []
+        for k, job in enumerate(jobs):
+            frame, mask, out, prm = job[:4]
+            _dev_check(frame, mask)
+            d = descs[k]
+            d.frame, d.mask, d.out = frame.data_ptr(), mask.data_ptr(), out.data_ptr()
+            d.height, d.width = frame.shape
+            d.stride = frame.stride(0)
+            d.params = ctypes.pointer(prm)
+            keep.append(prm)
+            if len(job) > 4:
+                info, xhat, cap = job[4:7]
+                d.info = info.data_ptr() if info is not None else None
+                d.xhat = xhat.data_ptr() if xhat is not None else None
+                d.cap = cap
+        return descs, keep
+
+    def conceal_batch(self, jobs, stream=None):
+        """Conceal several device frames; jobs as in _frame_descs.  Returns
+        the list of (n_lost, rounds, status) per frame; raises on the first
+        error."""
+        import torch
+        descs, keep = self._frame_descs(jobs)
+        dev = jobs[0][0].device if jobs else None
+        s = (torch.cuda.current_stream(dev) if stream is None else stream) if jobs else None
+        st = lib.skm_conceal_batch(self._h, descs, len(jobs),
+                                   ctypes.c_void_p(s.cuda_stream) if s is not None else None)
+        res = [(d.n_lost, d.rounds, d.status) for d in descs]
+        _check(st)
+        del keep
+        return res
+
+    def autotune(self, jobs, reps: int = 3) -> float:
+        """Pick the fastest launch configuration for these frames; returns the
+        best batch time in ms."""
+        descs, keep = self._frame_descs(jobs)
+        ms = ctypes.c_double(0.0)
+        _check(lib.skm_autotune(self._h, descs, len(jobs), int(reps), ctypes.byref(ms)))
+        del keep
+        return ms.value
 
     # ------------------------------------------------------- learned gate
     def cnn_init(self, seed: int = 0):

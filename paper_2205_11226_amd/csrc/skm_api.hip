@@ -1,15 +1,24 @@
 // Host side of the C ABI declared in include/skmmse.h.
 //
-// A context owns a stream for the host-memory entry point and a device
-// workspace that grows on demand (never shrinks until skm_destroy).  The
-// per-frame pipeline is: loss geometry (k_init, k_cells, k_compact), then
-// rounds of (prep, main, finalize) until no block is pending.  Rounds are
-// enqueued in batches; one small counter read-back per batch decides whether
-// more are needed, and the batch size is remembered for the next frame.
+// A context owns frame slots.  A slot is the device workspace of one frame in
+// flight (value plane, block tables, round state, gate and HQL scratch), a
+// private stream and one cached executable hipGraph of the frame pipeline.
+// Slot 0 serves the single-frame entry points; slots 1.. serve
+// skm_conceal_batch, which keeps several frames in flight on their streams.
+//
+// The frame pipeline is: loss geometry (k_zero_state, k_init, k_compact),
+// then rounds of (prep, [gate], estimation, [HQL], finalize + count) until
+// no block is pending.  A frame is enqueued with R rounds (the count its slot
+// needed last time; rounds past the last are no-ops on the device) followed
+// by a copy of the round state into pinned memory.  After the frame's stream
+// is synchronised, more rounds are run if blocks are still pending.  The
+// enqueued part is captured once into a hipGraph and replayed while the
+// frame pointers, parameters and R stay the same.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <chrono>
 #include <string>
 #include <vector>
 
@@ -17,30 +26,49 @@
 
 using namespace skm;
 
-struct skm_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  int max_lds = 65536;
-  size_t lds_limit_set = 65536;
-  // frame workspace
+struct FrameSlot {
   int16_t* d_val = nullptr;       size_t cap_px = 0;
   uint8_t* d_cell_lost = nullptr;
   int* d_blk = nullptr;
   int* d_bstate = nullptr;
-  int* d_m0cnt = nullptr;         size_t cap_cells = 0;
+  int* d_m0cnt = nullptr;
   int2* d_ring = nullptr;
+  int* d_hql_list = nullptr;      size_t cap_cells = 0;
   int* d_part = nullptr;
-  int* d_hql_list = nullptr;
   unsigned char* d_hql_ws = nullptr; size_t cap_hql = 0;
-  size_t hql_lds_set = 65536;
+  int8_t* d_gate = nullptr;
+  float* d_gate_pred = nullptr;   size_t cap_gate = 0;
   RoundState* d_state = nullptr;
   RoundState* h_state = nullptr;  // pinned
+  hipStream_t stream = nullptr;   // private: graph capture and batch work
+  int last_rounds = 1;
+  // cached executable graph of (geometry + R rounds + state copy)
+  std::vector<unsigned char> gkey;
+  hipGraphExec_t gexec = nullptr;
+  // kernel timing: event pairs around the estimation kernel, per round
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
+  // batch bookkeeping: the frame in flight on this slot
+  int pending = -1;
+  DevParams pp;
+  FrameArgs pa;
+  int max_rounds = 0;
+  int rounds_enqueued = 0;
+};
+
+struct skm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;   // host-memory entry point, CNN calls
+  int max_lds = 65536;
+  size_t lds_limit_set = 65536;
+  size_t hql_lds_set = 65536;
+  bool gate_lds_set = false;
+  std::vector<FrameSlot*> slots;  // [0] single-frame calls, [1..] batch
   // staging for the host-memory entry point
   uint8_t* d_frame = nullptr;     size_t cap_frame = 0;
   uint8_t* d_mask = nullptr;      size_t cap_mask = 0;
   uint8_t* d_out = nullptr;       size_t cap_out = 0;
   skm_block_info* d_info = nullptr; size_t cap_info = 0;
-  int last_rounds = 1;
   // learned gate
   float* d_cnn = nullptr;       // [5][kCnnParams]: master, bf16 copy, Adam m, Adam v, gradient
   float* d_cnn_loss = nullptr;
@@ -48,13 +76,14 @@ struct skm_ctx {
   int cnn_step = 0;
   float tau1 = 0.0f, tau2 = 0.0f;
   float* d_cnn_buf = nullptr;   size_t cap_cnn_buf = 0;   // training activations
-  int8_t* d_gate = nullptr;
-  float* d_gate_pred = nullptr; size_t cap_gate = 0;
-  bool gate_lds_set = false;
+  // options
+  bool use_graphs = true;
+  int batch_streams = 4;
+  int gate_grid = 512;
   // kernel timing (skm_profile_*)
   bool prof = false;
-  std::vector<hipEvent_t> ev;     // pairs: [2k] before, [2k+1] after
-  int ev_used = 0;
+  double prof_ms = 0.0;
+  int prof_launches = 0;
 };
 
 namespace {
@@ -122,6 +151,7 @@ skm_status make_params(const skm_params* in, int width, int height, int stride, 
     p->MC = p->ND - side * side;
     if (p->MC < 1) p->MC = 1;
   }
+  if (p->MC > kMaxPer * kThreads) return fail(SKM_EINVAL, "window too large for the block size");
   int n = 0;
   for (int rho = in->expand_step; rho < p->W; rho += in->expand_step) {
     if (n >= kMaxRadii - 1) return fail(SKM_EINVAL, "expand_step gives more than 16 radii");
@@ -142,41 +172,77 @@ skm_status make_params(const skm_params* in, int width, int height, int stride, 
   return SKM_OK;
 }
 
-skm_status ensure_frame(skm_ctx* c, const DevParams& p) {
+skm_status slot_create(skm_ctx* c, FrameSlot** out) {
+  FrameSlot* f = new (std::nothrow) FrameSlot();
+  if (!f) return fail(SKM_ENOMEM, "slot allocation");
+  *out = f;
+  SKM_HIP(hipStreamCreateWithFlags(&f->stream, hipStreamNonBlocking), "hipStreamCreate");
+  SKM_HIP(hipMalloc((void**)&f->d_state, sizeof(RoundState)), "round state");
+  SKM_HIP(hipHostMalloc((void**)&f->h_state, sizeof(RoundState), hipHostMallocDefault),
+          "pinned round state");
+  SKM_HIP(hipMalloc((void**)&f->d_part, sizeof(int) * 2 * kPrepGridMax), "prep slots");
+  (void)c;
+  return SKM_OK;
+}
+
+void slot_destroy(FrameSlot* f) {
+  if (!f) return;
+  if (f->stream) (void)hipStreamSynchronize(f->stream);
+  if (f->gexec) (void)hipGraphExecDestroy(f->gexec);
+  (void)hipFree(f->d_val);
+  (void)hipFree(f->d_cell_lost);
+  (void)hipFree(f->d_blk);
+  (void)hipFree(f->d_bstate);
+  (void)hipFree(f->d_m0cnt);
+  (void)hipFree(f->d_ring);
+  (void)hipFree(f->d_hql_list);
+  (void)hipFree(f->d_part);
+  (void)hipFree(f->d_hql_ws);
+  (void)hipFree(f->d_gate);
+  (void)hipFree(f->d_gate_pred);
+  (void)hipFree(f->d_state);
+  if (f->h_state) (void)hipHostFree(f->h_state);
+  for (hipEvent_t e : f->ev) (void)hipEventDestroy(e);
+  if (f->stream) (void)hipStreamDestroy(f->stream);
+  delete f;
+}
+
+// Workspace of slot f for frames of p's geometry (grows, never shrinks), and
+// the kernels' LDS limits.
+skm_status ensure_frame(skm_ctx* c, FrameSlot* f, const DevParams& p) {
   size_t npx = (size_t)p.width * p.height;
   size_t ncell = (size_t)p.gh * p.gw;
   skm_status s;
-  if ((s = grow(&c->d_val, &c->cap_px, npx, "workspace plane")) != SKM_OK) return s;
-  if (ncell > c->cap_cells || !c->d_blk) {
+  if ((s = grow(&f->d_val, &f->cap_px, npx, "workspace plane")) != SKM_OK) return s;
+  if (ncell > f->cap_cells || !f->d_blk) {
     size_t cap = 0;
-    (void)hipFree(c->d_cell_lost); c->d_cell_lost = nullptr;
-    (void)hipFree(c->d_blk); c->d_blk = nullptr;
-    (void)hipFree(c->d_bstate); c->d_bstate = nullptr;
-    (void)hipFree(c->d_m0cnt); c->d_m0cnt = nullptr;
-    (void)hipFree(c->d_ring); c->d_ring = nullptr;
-    c->cap_cells = 0;
-    if ((s = grow(&c->d_cell_lost, &cap, ncell, "cell table")) != SKM_OK) return s;
+    (void)hipFree(f->d_cell_lost); f->d_cell_lost = nullptr;
+    (void)hipFree(f->d_blk); f->d_blk = nullptr;
+    (void)hipFree(f->d_bstate); f->d_bstate = nullptr;
+    (void)hipFree(f->d_m0cnt); f->d_m0cnt = nullptr;
+    (void)hipFree(f->d_ring); f->d_ring = nullptr;
+    (void)hipFree(f->d_hql_list); f->d_hql_list = nullptr;
+    f->cap_cells = 0;
+    if ((s = grow(&f->d_cell_lost, &cap, ncell, "cell table")) != SKM_OK) return s;
     cap = 0;
-    if ((s = grow(&c->d_blk, &cap, ncell, "block list")) != SKM_OK) return s;
+    if ((s = grow(&f->d_blk, &cap, ncell, "block list")) != SKM_OK) return s;
     cap = 0;
-    if ((s = grow(&c->d_bstate, &cap, ncell, "block state")) != SKM_OK) return s;
+    if ((s = grow(&f->d_bstate, &cap, ncell, "block state")) != SKM_OK) return s;
     cap = 0;
-    if ((s = grow(&c->d_m0cnt, &cap, ncell, "context counts")) != SKM_OK) return s;
+    if ((s = grow(&f->d_m0cnt, &cap, ncell, "context counts")) != SKM_OK) return s;
     cap = 0;
-    if ((s = grow(&c->d_ring, &cap, ncell, "context statistics")) != SKM_OK) return s;
-    (void)hipFree(c->d_hql_list); c->d_hql_list = nullptr;
+    if ((s = grow(&f->d_ring, &cap, ncell, "context statistics")) != SKM_OK) return s;
     cap = 0;
-    if ((s = grow(&c->d_hql_list, &cap, ncell, "HQL list")) != SKM_OK) return s;
-    c->cap_cells = ncell < 1 ? 1 : ncell;
+    if ((s = grow(&f->d_hql_list, &cap, ncell, "HQL list")) != SKM_OK) return s;
+    f->cap_cells = ncell < 1 ? 1 : ncell;
   }
-  if (!c->d_part) SKM_HIP(hipMalloc((void**)&c->d_part, sizeof(int) * 2 * kPrepGridMax), "prep slots");
-  if (ncell > c->cap_gate || !c->d_gate) {
-    (void)hipFree(c->d_gate); c->d_gate = nullptr;
-    (void)hipFree(c->d_gate_pred); c->d_gate_pred = nullptr;
+  if (ncell > f->cap_gate || !f->d_gate) {
+    (void)hipFree(f->d_gate); f->d_gate = nullptr;
+    (void)hipFree(f->d_gate_pred); f->d_gate_pred = nullptr;
     const size_t n = ncell < 1 ? 1 : ncell;
-    SKM_HIP(hipMalloc((void**)&c->d_gate, n), "gate");
-    SKM_HIP(hipMalloc((void**)&c->d_gate_pred, sizeof(float) * 2 * n), "gate predictions");
-    c->cap_gate = n;
+    SKM_HIP(hipMalloc((void**)&f->d_gate, n), "gate");
+    SKM_HIP(hipMalloc((void**)&f->d_gate_pred, sizeof(float) * 2 * n), "gate predictions");
+    f->cap_gate = n;
   }
   if (!c->gate_lds_set) {
     SKM_HIP(set_cnn_gate_lds_limit(cnn_gate_lds_bytes()), "hipFuncSetAttribute");
@@ -184,7 +250,7 @@ skm_status ensure_frame(skm_ctx* c, const DevParams& p) {
   }
   if (mode_uses_hql(p.mode)) {
     const size_t need = hql_slot_bytes(p) * kHqlSlots;
-    if ((s = grow(&c->d_hql_ws, &c->cap_hql, need, "HQL scratch")) != SKM_OK) return s;
+    if ((s = grow(&f->d_hql_ws, &f->cap_hql, need, "HQL scratch")) != SKM_OK) return s;
     const size_t hl = hql_lds_bytes(p);
     if ((int)hl > c->max_lds)
       return fail(SKM_EUNSUPPORTED, "window/ring/block need more LDS than the device has");
@@ -203,19 +269,20 @@ skm_status ensure_frame(skm_ctx* c, const DevParams& p) {
   return SKM_OK;
 }
 
-FrameArgs frame_args(skm_ctx* c, const uint8_t* frame, const uint8_t* mask, uint8_t* out) {
+FrameArgs frame_args(FrameSlot* f, const uint8_t* frame, const uint8_t* mask, uint8_t* out) {
   FrameArgs a;
   memset(&a, 0, sizeof(a));
   a.frame = frame; a.mask = mask; a.work = out;
-  a.val = c->d_val; a.cell_lost = c->d_cell_lost; a.blk = c->d_blk;
-  a.bstate = c->d_bstate; a.m0cnt = c->d_m0cnt; a.ring = c->d_ring; a.part = c->d_part; a.st = c->d_state;
-  a.hql_list = c->d_hql_list;
-  a.gate = c->d_gate; a.gate_pred = c->d_gate_pred;
+  a.val = f->d_val; a.cell_lost = f->d_cell_lost; a.blk = f->d_blk;
+  a.bstate = f->d_bstate; a.m0cnt = f->d_m0cnt; a.ring = f->d_ring; a.part = f->d_part;
+  a.st = f->d_state;
+  a.hql_list = f->d_hql_list;
+  a.gate = f->d_gate; a.gate_pred = f->d_gate_pred;
   return a;
 }
 
-skm_status read_state(skm_ctx* c, hipStream_t s) {
-  SKM_HIP(hipMemcpyAsync(c->h_state, c->d_state, sizeof(RoundState), hipMemcpyDeviceToHost, s),
+skm_status read_state(FrameSlot* f, hipStream_t s) {
+  SKM_HIP(hipMemcpyAsync(f->h_state, f->d_state, sizeof(RoundState), hipMemcpyDeviceToHost, s),
           "state read-back");
   SKM_HIP(hipStreamSynchronize(s), "stream synchronize");
   return SKM_OK;
@@ -231,61 +298,152 @@ skm_status check_err(const RoundState& st) {
   return SKM_OK;
 }
 
-// One round: context counts, estimation, availability update.  With timing on,
-// the estimation kernel is bracketed by an event pair on `s`.
-skm_status launch_round(skm_ctx* c, const DevParams& p, FrameArgs& a, int nb, hipStream_t s) {
+// One round on s.  With timing on, the estimation kernel of round k of the
+// enqueue is bracketed by event pair k of the slot.
+skm_status launch_round(skm_ctx* c, FrameSlot* f, const DevParams& p, FrameArgs& a, int k,
+                        hipStream_t s) {
+  const int nb = p.gh * p.gw;
   SKM_HIP(launch_prep(a, p, nb, s), "prep kernel");
   if (p.cnn_active)
-    SKM_HIP(launch_cnn_gate(a, p, c->d_cnn + kCnnParams, c->tau1, c->tau2, nb, s), "gate kernel");
+    SKM_HIP(launch_cnn_gate(a, p, c->d_cnn + kCnnParams, c->tau1, c->tau2, c->gate_grid, s),
+            "gate kernel");
   if (c->prof) {
-    if ((int)c->ev.size() < 2 * (c->ev_used + 1)) {
-      for (int k = 0; k < 2; ++k) {
-        hipEvent_t e;
-        SKM_HIP(hipEventCreate(&e), "hipEventCreate");
-        c->ev.push_back(e);
-      }
+    while ((int)f->ev.size() < 2 * (k + 1)) {
+      hipEvent_t e;
+      SKM_HIP(hipEventCreate(&e), "hipEventCreate");
+      f->ev.push_back(e);
     }
-    SKM_HIP(hipEventRecord(c->ev[2 * c->ev_used], s), "hipEventRecord");
+    SKM_HIP(hipEventRecord(f->ev[2 * k], s), "hipEventRecord");
   }
   SKM_HIP(launch_est(a, p, nb, s), "estimation kernel");
-  if (c->prof) {
-    SKM_HIP(hipEventRecord(c->ev[2 * c->ev_used + 1], s), "hipEventRecord");
-    ++c->ev_used;
-  }
+  if (c->prof) SKM_HIP(hipEventRecord(f->ev[2 * k + 1], s), "hipEventRecord");
   if (mode_uses_hql(p.mode))
-    SKM_HIP(launch_hql(a, p, c->d_hql_ws, hql_slot_bytes(p), kHqlSlots, s), "HQL kernel");
+    SKM_HIP(launch_hql(a, p, f->d_hql_ws, hql_slot_bytes(p), kHqlSlots, s), "HQL kernel");
   SKM_HIP(launch_finalize(a, p, nb, s), "finalize kernel");
   return SKM_OK;
 }
 
-// Whole-frame pipeline on `s`; the frame is complete when this returns SKM_OK.
-skm_status run_frame(skm_ctx* c, const DevParams& p, FrameArgs& a, int max_rounds,
-                     hipStream_t s, int* n_lost_out) {
-  const int ncell = p.gh * p.gw;
+// Geometry + R rounds + state copy, eagerly on s.
+skm_status enqueue_eager(skm_ctx* c, FrameSlot* f, const DevParams& p, FrameArgs& a, int R,
+                         hipStream_t s) {
   SKM_HIP(launch_init(a, p, s), "geometry kernels");
-  int done = 0;
-  int batch = c->last_rounds < 1 ? 1 : c->last_rounds;
-  for (;;) {
-    if (max_rounds && batch > max_rounds - done) batch = max_rounds - done;
-    skm_status st;
-    for (int k = 0; k < batch; ++k)
-      if ((st = launch_round(c, p, a, ncell, s)) != SKM_OK) return st;
-    done += batch;
-    st = read_state(c, s);
+  for (int k = 0; k < R; ++k) {
+    skm_status st = launch_round(c, f, p, a, k, s);
     if (st != SKM_OK) return st;
-    if ((st = check_err(*c->h_state)) != SKM_OK) return st;
-    if (c->h_state->remaining == 0) break;
+  }
+  SKM_HIP(hipMemcpyAsync(f->h_state, f->d_state, sizeof(RoundState), hipMemcpyDeviceToHost, s),
+          "state read-back");
+  return SKM_OK;
+}
+
+// Enqueue a frame with R rounds on s: replay the slot's graph when its key
+// (arguments, parameters, R, gate state, timing) matches, else capture one on
+// the slot's private stream first.  Falls back to eager launches if graphs
+// are off or capture fails.
+skm_status enqueue_frame(skm_ctx* c, FrameSlot* f, const DevParams& p, FrameArgs& a, int R,
+                         hipStream_t s) {
+  f->ev_used = c->prof ? R : 0;
+  f->rounds_enqueued = R;
+  // with kernel timing on, launches are eager: the event pairs are read
+  // back per frame, which this runtime does not allow for events recorded
+  // by graph nodes
+  if (!c->use_graphs || c->prof) return enqueue_eager(c, f, p, a, R, s);
+  std::vector<unsigned char> key(sizeof(FrameArgs) + sizeof(DevParams) + 4 * sizeof(int) +
+                                 2 * sizeof(float) + sizeof(void*));
+  unsigned char* kp = key.data();
+  memcpy(kp, &a, sizeof(FrameArgs)); kp += sizeof(FrameArgs);
+  memcpy(kp, &p, sizeof(DevParams)); kp += sizeof(DevParams);
+  const int ints[4] = {R, c->prof ? 1 : 0, c->gate_grid, (int)f->ev.size()};
+  memcpy(kp, ints, sizeof(ints)); kp += sizeof(ints);
+  memcpy(kp, &c->tau1, sizeof(float)); kp += sizeof(float);
+  memcpy(kp, &c->tau2, sizeof(float)); kp += sizeof(float);
+  memcpy(kp, &c->d_cnn, sizeof(void*));
+  if (!f->gexec || key != f->gkey) {
+    if (c->prof) {          // events must exist before capture
+      while ((int)f->ev.size() < 2 * R) {
+        hipEvent_t e;
+        SKM_HIP(hipEventCreate(&e), "hipEventCreate");
+        f->ev.push_back(e);
+      }
+      const int ev_n = (int)f->ev.size();
+      memcpy(key.data() + sizeof(FrameArgs) + sizeof(DevParams) + 3 * sizeof(int), &ev_n,
+             sizeof(int));
+    }
+    if (f->gexec) { (void)hipGraphExecDestroy(f->gexec); f->gexec = nullptr; }
+    f->gkey.clear();
+    hipGraph_t g = nullptr;
+    SKM_HIP(hipStreamBeginCapture(f->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    skm_status st = enqueue_eager(c, f, p, a, R, f->stream);
+    hipError_t e = hipStreamEndCapture(f->stream, &g);
+    if (st != SKM_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      return st != SKM_OK ? st : hip_fail(e, "end capture");
+    }
+    e = hipGraphInstantiate(&f->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { f->gexec = nullptr; return hip_fail(e, "graph instantiate"); }
+    f->gkey = key;
+  }
+  SKM_HIP(hipGraphLaunch(f->gexec, s), "graph launch");
+  return SKM_OK;
+}
+
+// Wait for the frame enqueued on s, then run rounds until none is pending
+// (or the round limit, then fill).  Reads kernel timing if it is on.
+skm_status finish_frame(skm_ctx* c, FrameSlot* f, const DevParams& p, FrameArgs& a,
+                        int max_rounds, hipStream_t s, int* n_lost_out, int* rounds_out) {
+  SKM_HIP(hipStreamSynchronize(s), "stream synchronize");
+  auto take_timing = [&]() -> skm_status {
+    for (int k = 0; k < f->ev_used; ++k) {
+      float ms = 0.f;
+      SKM_HIP(hipEventElapsedTime(&ms, f->ev[2 * k], f->ev[2 * k + 1]), "hipEventElapsedTime");
+      c->prof_ms += ms;
+      ++c->prof_launches;
+    }
+    f->ev_used = 0;
+    return SKM_OK;
+  };
+  skm_status st;
+  if ((st = take_timing()) != SKM_OK) return st;
+  if ((st = check_err(*f->h_state)) != SKM_OK) return st;
+  int done = f->rounds_enqueued;
+  int batch = done;
+  while (f->h_state->remaining != 0) {
     if (max_rounds && done >= max_rounds) {
-      SKM_HIP(launch_fill(a, p, ncell, s), "fill kernels");
-      if ((st = read_state(c, s)) != SKM_OK) return st;
+      SKM_HIP(launch_fill(a, p, p.gh * p.gw, s), "fill kernels");
+      if ((st = read_state(f, s)) != SKM_OK) return st;
       break;
     }
     batch *= 2;
+    if (max_rounds && batch > max_rounds - done) batch = max_rounds - done;
+    f->ev_used = c->prof ? batch : 0;
+    for (int k = 0; k < batch; ++k)
+      if ((st = launch_round(c, f, p, a, k, s)) != SKM_OK) return st;
+    done += batch;
+    if ((st = read_state(f, s)) != SKM_OK) return st;
+    if ((st = take_timing()) != SKM_OK) return st;
+    if ((st = check_err(*f->h_state)) != SKM_OK) return st;
   }
-  int used = c->h_state->round - 1;
-  c->last_rounds = used < 1 ? 1 : (used > 64 ? 64 : used);
-  if (n_lost_out) *n_lost_out = c->h_state->n_lost;
+  const int used = f->h_state->round - 1;
+  f->last_rounds = used < 1 ? 1 : (used > 64 ? 64 : used);
+  if (n_lost_out) *n_lost_out = f->h_state->n_lost;
+  if (rounds_out) *rounds_out = used;
   return SKM_OK;
+}
+
+int initial_rounds(const FrameSlot* f, int max_rounds) {
+  int R = f->last_rounds < 1 ? 1 : f->last_rounds;
+  if (max_rounds && R > max_rounds) R = max_rounds;
+  return R;
+}
+
+// Whole-frame pipeline on s; the frame is complete when this returns SKM_OK.
+skm_status run_frame(skm_ctx* c, FrameSlot* f, const DevParams& p, FrameArgs& a, int max_rounds,
+                     hipStream_t s, int* n_lost_out) {
+  skm_status st = enqueue_frame(c, f, p, a, initial_rounds(f, max_rounds), s);
+  if (st != SKM_OK) return st;
+  return finish_frame(c, f, p, a, max_rounds, s, n_lost_out, nullptr);
 }
 
 }  // namespace
@@ -316,11 +474,16 @@ skm_status skm_create(int32_t hip_device, skm_ctx** out) {
           hipSuccess && lds > 0)
     c->max_lds = lds;
   hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipMalloc((void**)&c->d_state, sizeof(RoundState));
-  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_state, sizeof(RoundState), hipHostMallocDefault);
   if (e != hipSuccess) {
     skm_destroy(c);
     return hip_fail(e, "context setup");
+  }
+  FrameSlot* f0 = nullptr;
+  skm_status s = slot_create(c, &f0);
+  if (f0) c->slots.push_back(f0);
+  if (s != SKM_OK) {
+    skm_destroy(c);
+    return s;
   }
   *out = c;
   return SKM_OK;
@@ -330,29 +493,48 @@ void skm_destroy(skm_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  (void)hipFree(c->d_val);
-  (void)hipFree(c->d_cell_lost);
-  (void)hipFree(c->d_blk);
-  (void)hipFree(c->d_bstate);
-  (void)hipFree(c->d_m0cnt);
-  (void)hipFree(c->d_ring);
-  (void)hipFree(c->d_part);
+  for (FrameSlot* f : c->slots) slot_destroy(f);
   (void)hipFree(c->d_cnn);
   (void)hipFree(c->d_cnn_loss);
   (void)hipFree(c->d_cnn_buf);
-  (void)hipFree(c->d_gate);
-  (void)hipFree(c->d_gate_pred);
-  (void)hipFree(c->d_hql_list);
-  (void)hipFree(c->d_hql_ws);
-  (void)hipFree(c->d_state);
   (void)hipFree(c->d_frame);
   (void)hipFree(c->d_mask);
   (void)hipFree(c->d_out);
   (void)hipFree(c->d_info);
-  if (c->h_state) (void)hipHostFree(c->h_state);
-  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
+}
+
+skm_status skm_set_option(skm_ctx* c, int32_t option, int64_t value) {
+  if (!c) return fail(SKM_EINVAL, "ctx is NULL");
+  switch (option) {
+    case SKM_OPT_GRAPHS:
+      if (value != 0 && value != 1) return fail(SKM_EINVAL, "SKM_OPT_GRAPHS takes 0 or 1");
+      c->use_graphs = value != 0;
+      return SKM_OK;
+    case SKM_OPT_BATCH_STREAMS:
+      if (value < 1 || value > kMaxBatchStreams)
+        return fail(SKM_EINVAL, "SKM_OPT_BATCH_STREAMS takes 1..8");
+      c->batch_streams = (int)value;
+      return SKM_OK;
+    case SKM_OPT_GATE_GRID:
+      if (value < 8 || value > 4096 || value % 8 != 0)
+        return fail(SKM_EINVAL, "SKM_OPT_GATE_GRID takes a multiple of 8 in 8..4096");
+      c->gate_grid = (int)value;
+      return SKM_OK;
+    default:
+      return fail(SKM_EINVAL, "unknown option");
+  }
+}
+
+skm_status skm_get_option(skm_ctx* c, int32_t option, int64_t* value) {
+  if (!c || !value) return fail(SKM_EINVAL, "NULL argument");
+  switch (option) {
+    case SKM_OPT_GRAPHS: *value = c->use_graphs ? 1 : 0; return SKM_OK;
+    case SKM_OPT_BATCH_STREAMS: *value = c->batch_streams; return SKM_OK;
+    case SKM_OPT_GATE_GRID: *value = c->gate_grid; return SKM_OK;
+    default: return fail(SKM_EINVAL, "unknown option");
+  }
 }
 
 skm_status skm_conceal_device(skm_ctx* c, const uint8_t* d_frame, const uint8_t* d_mask,
@@ -367,13 +549,14 @@ skm_status skm_conceal_device(skm_ctx* c, const uint8_t* d_frame, const uint8_t*
   skm_status s = make_params(params, width, height, stride, &p);
   if (s != SKM_OK) return s;
   SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
-  if ((s = ensure_frame(c, p)) != SKM_OK) return s;
+  FrameSlot* f = c->slots[0];
+  if ((s = ensure_frame(c, f, p)) != SKM_OK) return s;
   hipStream_t st = (hipStream_t)hip_stream;
   p.cnn_active = p.mode == SKM_MODE_CNN && c->cnn_loaded;
-  FrameArgs a = frame_args(c, d_frame, d_mask, d_out);
+  FrameArgs a = frame_args(f, d_frame, d_mask, d_out);
   a.info = d_info; a.xhat = d_xhat; a.cap = (d_info || d_xhat) ? cap : 0;
   int nl = 0;
-  if ((s = run_frame(c, p, a, params->max_rounds, st, &nl)) != SKM_OK) return s;
+  if ((s = run_frame(c, f, p, a, params->max_rounds, st, &nl)) != SKM_OK) return s;
   if (n_lost) *n_lost = nl;
   if ((d_info || d_xhat) && nl > cap)
     return fail(SKM_EINVAL, "info/xhat capacity smaller than the number of lost blocks");
@@ -398,16 +581,17 @@ skm_status skm_conceal(skm_ctx* c, const uint8_t* frame, const uint8_t* loss_mas
   int ncell = (width / params->block) * (height / params->block);
   if (info && (s = grow(&c->d_info, &c->cap_info, (size_t)(ncell < 1 ? 1 : ncell), "info")) != SKM_OK)
     return s;
-  if ((s = ensure_frame(c, p)) != SKM_OK) return s;
+  FrameSlot* f = c->slots[0];
+  if ((s = ensure_frame(c, f, p)) != SKM_OK) return s;
   hipStream_t st = c->stream;
   p.cnn_active = p.mode == SKM_MODE_CNN && c->cnn_loaded;
   SKM_HIP(hipMemcpyAsync(c->d_frame, frame, bytes, hipMemcpyHostToDevice, st), "frame upload");
   SKM_HIP(hipMemcpyAsync(c->d_mask, loss_mask, bytes, hipMemcpyHostToDevice, st), "mask upload");
-  FrameArgs a = frame_args(c, c->d_frame, c->d_mask, c->d_out);
+  FrameArgs a = frame_args(f, c->d_frame, c->d_mask, c->d_out);
   a.info = info ? c->d_info : nullptr;
   a.cap = info ? ncell : 0;
   int nl = 0;
-  if ((s = run_frame(c, p, a, params->max_rounds, st, &nl)) != SKM_OK) return s;
+  if ((s = run_frame(c, f, p, a, params->max_rounds, st, &nl)) != SKM_OK) return s;
   if (n_lost) *n_lost = nl;
   if (info && nl > info_cap)
     return fail(SKM_EINVAL, "info_cap smaller than the number of lost blocks");
@@ -416,6 +600,128 @@ skm_status skm_conceal(skm_ctx* c, const uint8_t* frame, const uint8_t* loss_mas
     SKM_HIP(hipMemcpyAsync(info, c->d_info, sizeof(skm_block_info) * nl, hipMemcpyDeviceToHost, st),
             "info download");
   SKM_HIP(hipStreamSynchronize(st), "stream synchronize");
+  return SKM_OK;
+}
+
+// ------------------------------------------------------------------ batch
+
+static skm_status batch_finish(skm_ctx* c, FrameSlot* f, skm_frame_desc* frames) {
+  skm_frame_desc& d = frames[f->pending];
+  int nl = 0, rounds = 0;
+  skm_status s = finish_frame(c, f, f->pp, f->pa, f->max_rounds, f->stream, &nl, &rounds);
+  f->pending = -1;
+  d.n_lost = nl;
+  d.rounds = rounds;
+  if (s == SKM_OK && (d.info || d.xhat) && nl > d.cap)
+    s = fail(SKM_EINVAL, "info/xhat capacity smaller than the number of lost blocks");
+  d.status = s;
+  return s;
+}
+
+skm_status skm_conceal_batch(skm_ctx* c, skm_frame_desc* frames, int32_t n, void* hip_stream) {
+  if (!c) return fail(SKM_EINVAL, "ctx is NULL");
+  if (n < 0 || (n > 0 && !frames)) return fail(SKM_EINVAL, "bad frame list");
+  if (n == 0) return SKM_OK;
+  SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  const int S = n < c->batch_streams ? n : c->batch_streams;
+  skm_status s;
+  while ((int)c->slots.size() < 1 + S) {
+    FrameSlot* f = nullptr;
+    s = slot_create(c, &f);
+    if (f) c->slots.push_back(f);
+    if (s != SKM_OK) return s;
+  }
+  // order the batch after the caller's earlier work on hip_stream
+  hipEvent_t ready = nullptr;
+  SKM_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming), "hipEventCreate");
+  hipError_t e = hipEventRecord(ready, (hipStream_t)hip_stream);
+  for (int k = 1; k <= S && e == hipSuccess; ++k) e = hipStreamWaitEvent(c->slots[k]->stream, ready, 0);
+  (void)hipEventDestroy(ready);
+  if (e != hipSuccess) return hip_fail(e, "batch ordering");
+  skm_status first = SKM_OK;
+  for (int k = 0; k < n; ++k) {
+    skm_frame_desc& d = frames[k];
+    d.status = SKM_OK; d.n_lost = 0; d.rounds = 0;
+    FrameSlot* f = c->slots[1 + k % S];
+    if (f->pending >= 0 && (s = batch_finish(c, f, frames)) != SKM_OK && first == SKM_OK) first = s;
+    if (!d.frame || !d.mask || !d.out || !d.params) {
+      d.status = fail(SKM_EINVAL, "frame, mask, out and params are required");
+      if (first == SKM_OK) first = (skm_status)d.status;
+      continue;
+    }
+    if ((d.info || d.xhat) && d.cap < 0) {
+      d.status = fail(SKM_EINVAL, "cap must be >= 0");
+      if (first == SKM_OK) first = (skm_status)d.status;
+      continue;
+    }
+    DevParams p;
+    if ((s = make_params(d.params, d.width, d.height, d.stride, &p)) == SKM_OK)
+      s = ensure_frame(c, f, p);
+    if (s != SKM_OK) {
+      d.status = s;
+      if (first == SKM_OK) first = s;
+      continue;
+    }
+    p.cnn_active = p.mode == SKM_MODE_CNN && c->cnn_loaded;
+    f->pp = p;
+    f->pa = frame_args(f, d.frame, d.mask, d.out);
+    f->pa.info = d.info; f->pa.xhat = d.xhat; f->pa.cap = (d.info || d.xhat) ? d.cap : 0;
+    f->max_rounds = d.params->max_rounds;
+    if ((s = enqueue_frame(c, f, f->pp, f->pa, initial_rounds(f, f->max_rounds), f->stream)) != SKM_OK) {
+      d.status = s;
+      if (first == SKM_OK) first = s;
+      continue;
+    }
+    f->pending = k;
+  }
+  for (int k = 1; k <= S; ++k) {
+    FrameSlot* f = c->slots[k];
+    if (f->pending >= 0 && (s = batch_finish(c, f, frames)) != SKM_OK && first == SKM_OK) first = s;
+  }
+  return first;
+}
+
+// Times the batch under each launch configuration (streams 1, 2, 4, 8 with
+// graphs on and off; gate grids 256, 512, 1024 in CNN mode), repeats`reps`
+// times, keeps the fastest and reports its time.  The frames are concealed
+// (several times) as a side effect.
+skm_status skm_autotune(skm_ctx* c, skm_frame_desc* frames, int32_t n, int32_t reps,
+                        double* best_ms) {
+  if (!c) return fail(SKM_EINVAL, "ctx is NULL");
+  if (n < 1 || !frames || reps < 1) return fail(SKM_EINVAL, "bad arguments");
+  bool cnn = false;
+  for (int k = 0; k < n; ++k) cnn = cnn || (frames[k].params && frames[k].params->mode == SKM_MODE_CNN);
+  const int streams[4] = {1, 2, 4, 8};
+  const int grids[3] = {256, 512, 1024};
+  double best = 1e300;
+  int bs = c->batch_streams, bg = c->use_graphs ? 1 : 0, bgg = c->gate_grid;
+  for (int gi = 0; gi < (cnn ? 3 : 1); ++gi) {
+    for (int graphs = 0; graphs <= 1; ++graphs) {
+      for (int si = 0; si < 4; ++si) {
+        c->batch_streams = streams[si];
+        c->use_graphs = graphs != 0;
+        if (cnn) c->gate_grid = grids[gi];
+        skm_status s = skm_conceal_batch(c, frames, n, nullptr);   // warm (captures graphs)
+        if (s != SKM_OK) return s;
+        double t_best = 1e300;
+        for (int r = 0; r < reps; ++r) {
+          const auto t0 = std::chrono::steady_clock::now();
+          if ((s = skm_conceal_batch(c, frames, n, nullptr)) != SKM_OK) return s;
+          const double ms = std::chrono::duration<double, std::milli>(
+                                std::chrono::steady_clock::now() - t0).count();
+          if (ms < t_best) t_best = ms;
+        }
+        if (t_best < best) {
+          best = t_best;
+          bs = streams[si]; bg = graphs; bgg = c->gate_grid;
+        }
+      }
+    }
+  }
+  c->batch_streams = bs;
+  c->use_graphs = bg != 0;
+  c->gate_grid = bgg;
+  if (best_ms) *best_ms = best;
   return SKM_OK;
 }
 
@@ -429,15 +735,16 @@ skm_status skm_distances_device(skm_ctx* c, const uint8_t* d_frame, const uint8_
   skm_status s = make_params(params, width, height, stride, &p);
   if (s != SKM_OK) return s;
   SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
-  if ((s = ensure_frame(c, p)) != SKM_OK) return s;
+  FrameSlot* f = c->slots[0];
+  if ((s = ensure_frame(c, f, p)) != SKM_OK) return s;
   hipStream_t st = (hipStream_t)hip_stream;
   size_t bytes = (size_t)(height - 1) * stride + width;
   if ((s = grow(&c->d_out, &c->cap_out, bytes, "scratch plane")) != SKM_OK) return s;
-  FrameArgs a = frame_args(c, d_frame, d_mask, c->d_out);
+  FrameArgs a = frame_args(f, d_frame, d_mask, c->d_out);
   SKM_HIP(launch_init(a, p, st), "geometry kernels");
-  if ((s = read_state(c, st)) != SKM_OK) return s;
-  if ((s = check_err(*c->h_state)) != SKM_OK) return s;
-  int nl = c->h_state->n_lost;
+  if ((s = read_state(f, st)) != SKM_OK) return s;
+  if ((s = check_err(*f->h_state)) != SKM_OK) return s;
+  int nl = f->h_state->n_lost;
   if (n_lost) *n_lost = nl;
   if (nl > cap) return fail(SKM_EINVAL, "cap smaller than the number of lost blocks");
   a.dist = d_dist; a.cnt = d_cnt;
@@ -566,15 +873,15 @@ skm_status skm_cnn_inputs(skm_ctx* c, const uint8_t* d_frame, const uint8_t* d_m
   skm_status s = make_params(params, width, height, stride, &p);
   if (s != SKM_OK) return s;
   SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
-  if ((s = ensure_frame(c, p)) != SKM_OK) return s;
+  if ((s = ensure_frame(c, c->slots[0], p)) != SKM_OK) return s;
   hipStream_t st = (hipStream_t)hip_stream;
   const size_t bytes = (size_t)(height - 1) * stride + width;
   if ((s = grow(&c->d_out, &c->cap_out, bytes, "scratch plane")) != SKM_OK) return s;
-  FrameArgs a = frame_args(c, d_frame, d_mask, c->d_out);
+  FrameArgs a = frame_args(c->slots[0], d_frame, d_mask, c->d_out);
   SKM_HIP(launch_init(a, p, st), "geometry kernels");
-  if ((s = read_state(c, st)) != SKM_OK) return s;
-  if ((s = check_err(*c->h_state)) != SKM_OK) return s;
-  const int nl = c->h_state->n_lost;
+  if ((s = read_state(c->slots[0], st)) != SKM_OK) return s;
+  if ((s = check_err(*c->slots[0]->h_state)) != SKM_OK) return s;
+  const int nl = c->slots[0]->h_state->n_lost;
   if (n_lost) *n_lost = nl;
   if (nl > cap) return fail(SKM_EINVAL, "cap smaller than the number of lost blocks");
   SKM_HIP(launch_cnn_inputs(a, p, d_inputs, p.gh * p.gw, st), "gate inputs");
@@ -643,10 +950,10 @@ skm_status skm_cnn_train_step(skm_ctx* c, const uint16_t* d_inputs, const float*
 
 skm_status skm_cnn_last_predictions(skm_ctx* c, float* host, int32_t cap) {
   if (!c || !host) return fail(SKM_EINVAL, "NULL argument");
-  if (!c->d_gate_pred) return fail(SKM_EINVAL, "no frame concealed yet");
-  const size_t n = (size_t)cap < c->cap_gate ? (size_t)cap : c->cap_gate;
+  if (!c->slots[0]->d_gate_pred) return fail(SKM_EINVAL, "no frame concealed yet");
+  const size_t n = (size_t)cap < c->slots[0]->cap_gate ? (size_t)cap : c->slots[0]->cap_gate;
   SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
-  SKM_HIP(hipMemcpy(host, c->d_gate_pred, sizeof(float) * 2 * n, hipMemcpyDeviceToHost), "download");
+  SKM_HIP(hipMemcpy(host, c->slots[0]->d_gate_pred, sizeof(float) * 2 * n, hipMemcpyDeviceToHost), "download");
   return SKM_OK;
 }
 
@@ -658,17 +965,10 @@ skm_status skm_profile_enable(skm_ctx* c, int32_t enable) {
 
 skm_status skm_profile_read(skm_ctx* c, double* total_ms, int32_t* launches) {
   if (!c) return fail(SKM_EINVAL, "ctx is NULL");
-  SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
-  double tot = 0.0;
-  for (int k = 0; k < c->ev_used; ++k) {
-    SKM_HIP(hipEventSynchronize(c->ev[2 * k + 1]), "hipEventSynchronize");
-    float ms = 0.f;
-    SKM_HIP(hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]), "hipEventElapsedTime");
-    tot += ms;
-  }
-  if (total_ms) *total_ms = tot;
-  if (launches) *launches = c->ev_used;
-  c->ev_used = 0;
+  if (total_ms) *total_ms = c->prof_ms;
+  if (launches) *launches = c->prof_launches;
+  c->prof_ms = 0.0;
+  c->prof_launches = 0;
   return SKM_OK;
 }
 

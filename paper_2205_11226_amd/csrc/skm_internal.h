@@ -13,6 +13,8 @@ constexpr int kMaxRadii = 16;
 // candidates per thread in a contiguous slice: ceil(MC / kThreads) for the
 // largest admissible window (W = 32, B = 4)
 constexpr int kMaxPer = 17;
+// frame slots in flight in skm_conceal_batch
+constexpr int kMaxBatchStreams = 8;
 constexpr int kMaxB = 16;
 constexpr int kMaxRing = 8;
 constexpr int kMaxWin = 32;
