@@ -177,27 +177,31 @@ skm_status skm_distances_device(skm_ctx* ctx, const uint8_t* d_frame, const uint
  * of HQL over IDL.  In SKM_MODE_CNN a block takes BRL if g1 <= tau1, else HQL
  * if g2 > tau2 (full-window IDL when HQL is unavailable), else IDL with the
  * support-area expansion of t_nu.  Without a loaded network SKM_MODE_CNN
- * applies the profile rule.  Network: three 3x3 convolutions (stride 2, zero
- * padding 1, 32 channels, ReLU), global average pool, linear 32 -> 2;
- * bfloat16 weights and convolution inputs, FP32 accumulation; 19170 FP32
- * master parameters in the order w1[32][2][3][3], b1[32], w2[32][32][3][3],
- * b2[32], w3[32][32][3][3], b3[32], wh[2][32], bh[2].
- * Training inputs are bfloat16 bit patterns, [n][2][48][48]; targets FP32
- * [n][2].  All device pointers belong to the caller. */
+ * applies the profile rule.  Network: the (2, 48, 48) window rearranged
+ * without loss into (8, 24, 24) (channel 4 c + 2 dy + dx at (Y, X) holds
+ * channel c at pixel (2 Y + dy, 2 X + dx)); three 3x3 convolutions (stride
+ * 2, zero padding 1, 32 channels, ReLU: 24 -> 12 -> 6 -> 3), global average
+ * pool, linear 32 -> 2; bfloat16 weights and convolution inputs, FP32
+ * accumulation; 20898 FP32 master parameters in the order w1[32][8][3][3],
+ * b1[32], w2[32][32][3][3], b2[32], w3[32][32][3][3], b3[32], wh[2][32],
+ * bh[2].  Training inputs are bfloat16 bit patterns in the rearranged layout,
+ * [n][8][24][24]; targets FP32 [n][2].  All device pointers belong to the
+ * caller.  The gate is not in the paper. */
 
 /* He-uniform initialisation from `seed` (zero biases, Adam state reset). */
 skm_status skm_cnn_init(skm_ctx* ctx, uint64_t seed);
-/* Copy the 19170 master parameters in (resets Adam) or out (host arrays). */
+/* Copy the 20898 master parameters in (resets Adam) or out (host arrays). */
 skm_status skm_cnn_set_weights(skm_ctx* ctx, const float* host_weights, int32_t n);
 skm_status skm_cnn_get_weights(skm_ctx* ctx, float* host_weights, int32_t n);
 /* Decision thresholds in dB (see above). */
 skm_status skm_cnn_set_thresholds(skm_ctx* ctx, double tau1, double tau2);
-/* Weight file: "SKMGATE1", uint32 version 1, uint32 19170, 2 x uint32 0,
- * float32 tau1, tau2, 19170 float32 weights; little endian. */
+/* Weight file: "SKMGATE1", uint32 version 2, uint32 20898, 2 x uint32 0,
+ * float32 tau1, tau2, 20898 float32 weights; little endian. */
 skm_status skm_save_cnn(skm_ctx* ctx, const char* path);
 skm_status skm_load_cnn(skm_ctx* ctx, const char* path);
-/* Network inputs of every lost block of a frame (received pixels only), in
- * lost-cell raster order; SKM_EINVAL if cap < number of lost blocks. */
+/* Network inputs of every lost block of a frame (received pixels only),
+ * [n][8][24][24] bfloat16 bits in lost-cell raster order; SKM_EINVAL if
+ * cap < number of lost blocks. */
 skm_status skm_cnn_inputs(skm_ctx* ctx, const uint8_t* d_frame, const uint8_t* d_mask,
                           int32_t width, int32_t height, int32_t stride, const skm_params* params,
                           uint16_t* d_inputs, int32_t cap, int32_t* n_lost, void* hip_stream);
@@ -205,7 +209,7 @@ skm_status skm_cnn_inputs(skm_ctx* ctx, const uint8_t* d_frame, const uint8_t* d
 skm_status skm_cnn_forward(skm_ctx* ctx, const uint16_t* d_inputs, int32_t n, float* d_out,
                            void* hip_stream);
 /* Mean squared error over the batch and both outputs and its gradient with
- * respect to the master parameters (copied to host_grad[19170]). */
+ * respect to the master parameters (copied to host_grad[20898]). */
 skm_status skm_cnn_gradients(skm_ctx* ctx, const uint16_t* d_inputs, const float* d_targets,
                              int32_t n, float* host_grad, float* loss, void* hip_stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) at learning rate lr on a
@@ -248,7 +252,7 @@ enum {
   SKM_OPT_GRAPHS = 1,         /* 1 (default): replay captured hipGraphs; 0: eager */
   SKM_OPT_BATCH_STREAMS = 2,  /* frames in flight in skm_conceal_batch, 1..8 (4)  */
   SKM_OPT_GATE_GRID = 3       /* workgroups of the CNN gate kernel, multiple of 8
-                                 in 8..4096 (512)                                 */
+                                 in 8..4096 (768)                                 */
 };
 skm_status skm_set_option(skm_ctx* ctx, int32_t option, int64_t value);
 skm_status skm_get_option(skm_ctx* ctx, int32_t option, int64_t* value);

@@ -11,9 +11,11 @@ K-MMSE estimator" defines the layers; the gate replaces the profile rule of
 Sec. "Layer switching and profile selection").
 
 Input channels: c0 = (u - 128) / 128 at known pixels, 0 elsewhere; c1 = 1 at
-unknown pixels (lost or outside the frame), 0 elsewhere.
+unknown pixels (lost or outside the frame), 0 elsewhere.  The (2, 48, 48)
+input is rearranged without loss into (8, 24, 24): channel 4 c + 2 dy + dx
+at (Y, X) holds channel c at pixel (2 Y + dy, 2 X + dx) (space to depth).
 Layers: three 3x3 convolutions, stride 2, zero padding 1, 32 channels, ReLU
-(48 -> 24 -> 12 -> 6), global average pool, linear 32 -> 2.
+(24 -> 12 -> 6 -> 3), global average pool, linear 32 -> 2.
 Precision model of the GPU network: weights and the inputs of every
 convolution are rounded to bfloat16 (round to nearest even); sums are exact
 here (float64) and FP32 on the GPU; pooling and head in full precision.
@@ -24,7 +26,7 @@ from __future__ import annotations
 import numpy as np
 
 SHAPES = {
-    "w1": (32, 2, 3, 3), "b1": (32,),
+    "w1": (32, 8, 3, 3), "b1": (32,),
     "w2": (32, 32, 3, 3), "b2": (32,),
     "w3": (32, 32, 3, 3), "b3": (32,),
     "wh": (2, 32), "bh": (2,),
@@ -74,6 +76,18 @@ def block_input(u: np.ndarray, avail: np.ndarray, by: int, bx: int, b: int) -> n
     return np.stack([c0, c1])
 
 
+def space_to_depth(x: np.ndarray) -> np.ndarray:
+    """(N, 2, 48, 48) -> (N, 8, 24, 24); channel 4 c + 2 dy + dx at (Y, X) is
+    channel c at pixel (2 Y + dy, 2 X + dx)."""
+    n, c, h, w = x.shape
+    out = np.empty((n, 4 * c, h // 2, w // 2), dtype=x.dtype)
+    for ch in range(c):
+        for dy in range(2):
+            for dx in range(2):
+                out[:, 4 * ch + 2 * dy + dx] = x[:, ch, dy::2, dx::2]
+    return out
+
+
 def _conv_s2(x: np.ndarray, w: np.ndarray, b: np.ndarray) -> np.ndarray:
     """3x3 convolution, stride 2, zero padding 1: x (N, C, H, H) -> (N, K, H/2, H/2)."""
     n, c, hh, _ = x.shape
@@ -111,7 +125,7 @@ def forward(params: dict, x: np.ndarray, keep=False, quant=True):
     quant=False skips the bfloat16 rounding (exact float64 network)."""
     rq = bf16 if quant else (lambda v: np.asarray(v, dtype=np.float64))
     q = {k: rq(v) if k.startswith("w") and k != "wh" else v for k, v in params.items()}
-    a0 = rq(x)
+    a0 = rq(space_to_depth(x))
     z1 = _conv_s2(a0, q["w1"], q["b1"])
     a1 = rq(np.maximum(z1, 0.0))
     z2 = _conv_s2(a1, q["w2"], q["b2"])
@@ -136,7 +150,7 @@ def loss_and_grads(params: dict, x: np.ndarray, t: np.ndarray, quant=True):
     q = c["q"]
     grads = {"wh": gy.T @ c["g"], "bh": gy.sum(axis=0)}
     gg = gy @ q["wh"]                                              # (N, 32)
-    ga3 = np.repeat(np.repeat(gg[:, :, None, None] / 36.0, 6, axis=2), 6, axis=3)
+    ga3 = np.repeat(np.repeat(gg[:, :, None, None] / 9.0, 3, axis=2), 3, axis=3)
     gz3 = ga3 * (c["z3"] > 0)
     ga2, grads["w3"], grads["b3"] = _conv_s2_back(c["a2"], q["w3"], gz3)
     gz2 = ga2 * (c["z2"] > 0)

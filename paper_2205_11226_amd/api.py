@@ -23,7 +23,7 @@ EXPORTS = ("skm_default_params", "skm_create", "skm_destroy", "skm_conceal",
            "skm_cnn_last_predictions", "skm_conceal_batch", "skm_set_option", "skm_get_option",
            "skm_autotune", "skm_profile_enable", "skm_profile_read", "skm_last_error")
 OPT_GRAPHS, OPT_BATCH_STREAMS, OPT_GATE_GRID = 1, 2, 3
-CNN_PARAMS = 19170
+CNN_PARAMS = 20898
 
 
 class SkmError(RuntimeError):
@@ -270,12 +270,13 @@ class Context:
         _check(lib.skm_load_cnn(self._h, os.fsencode(path)))
 
     def cnn_inputs(self, frame, mask, params: Params, stream=None):
-        """bf16 bit patterns (int16 tensor) [n_lost, 2, 48, 48] of every lost block."""
+        """bf16 bit patterns (int16 tensor) [n_lost, 8, 24, 24] of every lost block
+        (the 48 x 48 two-channel window, space to depth)."""
         import torch
         _dev_check(frame, mask)
         h, w = frame.shape
         cap = max((h // params.block) * (w // params.block), 1)
-        out = torch.empty((cap, 2, 48, 48), dtype=torch.int16, device=frame.device)
+        out = torch.empty((cap, 8, 24, 24), dtype=torch.int16, device=frame.device)
         n = ctypes.c_int32(0)
         s = torch.cuda.current_stream(frame.device) if stream is None else stream
         _check(lib.skm_cnn_inputs(self._h, frame.data_ptr(), mask.data_ptr(), w, h,

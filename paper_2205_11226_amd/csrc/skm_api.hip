@@ -79,7 +79,7 @@ struct skm_ctx {
   // options
   bool use_graphs = true;
   int batch_streams = 4;
-  int gate_grid = 512;
+  int gate_grid = 768;
   // kernel timing (skm_profile_*)
   bool prof = false;
   double prof_ms = 0.0;
@@ -213,7 +213,8 @@ skm_status ensure_frame(skm_ctx* c, FrameSlot* f, const DevParams& p) {
   size_t npx = (size_t)p.width * p.height;
   size_t ncell = (size_t)p.gh * p.gw;
   skm_status s;
-  if ((s = grow(&f->d_val, &f->cap_px, npx, "workspace plane")) != SKM_OK) return s;
+  if ((s = grow(&f->d_val, &f->cap_px, npx + 2 * kValGuard, "workspace plane")) != SKM_OK)
+    return s;
   if (ncell > f->cap_cells || !f->d_blk) {
     size_t cap = 0;
     (void)hipFree(f->d_cell_lost); f->d_cell_lost = nullptr;
@@ -273,7 +274,7 @@ FrameArgs frame_args(FrameSlot* f, const uint8_t* frame, const uint8_t* mask, ui
   FrameArgs a;
   memset(&a, 0, sizeof(a));
   a.frame = frame; a.mask = mask; a.work = out;
-  a.val = f->d_val; a.cell_lost = f->d_cell_lost; a.blk = f->d_blk;
+  a.val = f->d_val + kValGuard; a.cell_lost = f->d_cell_lost; a.blk = f->d_blk;
   a.bstate = f->d_bstate; a.m0cnt = f->d_m0cnt; a.ring = f->d_ring; a.part = f->d_part;
   a.st = f->d_state;
   a.hql_list = f->d_hql_list;
@@ -692,7 +693,7 @@ skm_status skm_autotune(skm_ctx* c, skm_frame_desc* frames, int32_t n, int32_t r
   bool cnn = false;
   for (int k = 0; k < n; ++k) cnn = cnn || (frames[k].params && frames[k].params->mode == SKM_MODE_CNN);
   const int streams[4] = {1, 2, 4, 8};
-  const int grids[3] = {256, 512, 1024};
+  const int grids[3] = {512, 768, 1536};
   double best = 1e300;
   int bs = c->batch_streams, bg = c->use_graphs ? 1 : 0, bgg = c->gate_grid;
   for (int gi = 0; gi < (cnn ? 3 : 1); ++gi) {
@@ -770,9 +771,9 @@ static skm_status cnn_buffers(skm_ctx* c, int n, CnnBuffers* b) {
   if (s != SKM_OK) return s;
   float* q = c->d_cnn_buf;
   auto take = [&](size_t per) { float* r = q; q += per * (size_t)n; return r; };
-  b->z1 = take(32 * 576); b->a1 = take(32 * 576); b->z2 = take(32 * 144); b->a2 = take(32 * 144);
-  b->z3 = take(32 * 36); b->a3 = take(32 * 36); b->g = take(32); b->y = take(2); b->gy = take(2);
-  b->gz3 = take(32 * 36); b->gz2 = take(32 * 144); b->gz1 = take(32 * 576);
+  b->z1 = take(32 * 144); b->a1 = take(32 * 144); b->z2 = take(32 * 36); b->a2 = take(32 * 36);
+  b->z3 = take(32 * 9); b->a3 = take(32 * 9); b->g = take(32); b->y = take(2); b->gy = take(2);
+  b->gz3 = take(32 * 9); b->gz2 = take(32 * 36); b->gz1 = take(32 * 144);
   return SKM_OK;
 }
 
@@ -792,7 +793,7 @@ skm_status skm_cnn_init(skm_ctx* c, uint64_t seed) {
 
 skm_status skm_cnn_set_weights(skm_ctx* c, const float* host, int32_t n) {
   if (!c || !host) return fail(SKM_EINVAL, "NULL argument");
-  if (n != kCnnParams) return fail(SKM_EINVAL, "weight count must be 19170");
+  if (n != kCnnParams) return fail(SKM_EINVAL, "weight count must be 20898");
   SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
   skm_status s = cnn_params_alloc(c);
   if (s != SKM_OK) return s;
@@ -809,7 +810,7 @@ skm_status skm_cnn_set_weights(skm_ctx* c, const float* host, int32_t n) {
 
 skm_status skm_cnn_get_weights(skm_ctx* c, float* host, int32_t n) {
   if (!c || !host) return fail(SKM_EINVAL, "NULL argument");
-  if (n != kCnnParams) return fail(SKM_EINVAL, "weight count must be 19170");
+  if (n != kCnnParams) return fail(SKM_EINVAL, "weight count must be 20898");
   if (!c->cnn_loaded) return fail(SKM_EINVAL, "no network loaded");
   SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
   SKM_HIP(hipMemcpyAsync(host, c->d_cnn, sizeof(float) * kCnnParams, hipMemcpyDeviceToHost, c->stream),
@@ -827,6 +828,7 @@ skm_status skm_cnn_set_thresholds(skm_ctx* c, double tau1, double tau2) {
 }
 
 static const char kGateMagic[8] = {'S', 'K', 'M', 'G', 'A', 'T', 'E', '1'};
+static const uint32_t kGateVersion = 2u;   // space-to-depth input, 20898 weights
 
 skm_status skm_save_cnn(skm_ctx* c, const char* path) {
   if (!c || !path) return fail(SKM_EINVAL, "NULL argument");
@@ -836,7 +838,7 @@ skm_status skm_save_cnn(skm_ctx* c, const char* path) {
   if (s != SKM_OK) return s;
   FILE* f = fopen(path, "wb");
   if (!f) return fail(SKM_EINVAL, std::string("cannot open ") + path);
-  const uint32_t hdr[4] = {1u, (uint32_t)kCnnParams, 0u, 0u};
+  const uint32_t hdr[4] = {kGateVersion, (uint32_t)kCnnParams, 0u, 0u};
   const float tau[2] = {c->tau1, c->tau2};
   bool ok = fwrite(kGateMagic, 1, 8, f) == 8 && fwrite(hdr, 4, 4, f) == 4 &&
             fwrite(tau, 4, 2, f) == 2 && fwrite(w.data(), 4, kCnnParams, f) == (size_t)kCnnParams;
@@ -853,10 +855,10 @@ skm_status skm_load_cnn(skm_ctx* c, const char* path) {
   float tau[2];
   std::vector<float> w(kCnnParams);
   bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kGateMagic, 8) == 0 &&
-            fread(hdr, 4, 4, f) == 4 && hdr[0] == 1u && hdr[1] == (uint32_t)kCnnParams &&
+            fread(hdr, 4, 4, f) == 4 && hdr[0] == kGateVersion && hdr[1] == (uint32_t)kCnnParams &&
             fread(tau, 4, 2, f) == 2 && fread(w.data(), 4, kCnnParams, f) == (size_t)kCnnParams;
   fclose(f);
-  if (!ok) return fail(SKM_EINVAL, "not a gate weight file (SKMGATE1, version 1, 19170 weights)");
+  if (!ok) return fail(SKM_EINVAL, "not a gate weight file (SKMGATE1, version 2, 20898 weights)");
   skm_status s = skm_cnn_set_weights(c, w.data(), kCnnParams);
   if (s != SKM_OK) return s;
   c->tau1 = tau[0];

@@ -6,8 +6,10 @@
 // IDL.
 //
 // Network: input (2, 48, 48) = ((u - 128)/128 at known pixels, 1 at unknown
-// pixels); three 3x3 convolutions, stride 2, zero padding 1, 32 channels,
-// ReLU; global average pool; linear 32 -> 2.  Weights and the inputs of every
+// pixels), rearranged without loss into (8, 24, 24) (channel 4 c + 2 dy + dx
+// at (Y, X) is channel c at pixel (2 Y + dy, 2 X + dx)); three 3x3
+// convolutions, stride 2, zero padding 1, 32 channels, ReLU (24 -> 12 -> 6 ->
+// 3); global average pool; linear 32 -> 2.  Weights and the inputs of every
 // convolution are bfloat16 values, accumulation is FP32.  Parameters live in
 // one flat FP32 array (w1, b1, w2, b2, w3, b3, wh, bh); `wq` is the same array
 // with the convolution weights rounded to bfloat16.
@@ -19,9 +21,13 @@
 namespace skm {
 
 constexpr int kP = 48;          // input window
+constexpr int kS = 24;          // its space-to-depth side
+constexpr int kC0 = 8;          // space-to-depth channels
 constexpr int kC = 32;          // channels
-constexpr int kOffW1 = 0, kOffB1 = 576, kOffW2 = 608, kOffB2 = 9824, kOffW3 = 9856,
-              kOffB3 = 19072, kOffWh = 19104, kOffBh = 19168, kNParams = 19170;
+constexpr int kPool = 9;        // positions of the last layer (3 x 3)
+constexpr int kOffW1 = 0, kOffB1 = 2304, kOffW2 = 2336, kOffB2 = 11552, kOffW3 = 11584,
+              kOffB3 = 20800, kOffWh = 20832, kOffBh = 20896, kNParams = 20898;
+static_assert(kNParams == kCnnParams, "parameter count");
 
 static __device__ __forceinline__ float bf16_round(float x) {
   uint32_t u = __float_as_uint(x);
@@ -46,17 +52,19 @@ static __device__ __forceinline__ void input_pixel(const FrameArgs& a, const Dev
   c1 = v >= 0 ? 0.0f : 1.0f;
 }
 
-// inputs of every lost block (received frame), bf16 [n][2][48][48]
+// inputs of every lost block (received frame), bf16 [n][8][24][24]
 __global__ __launch_bounds__(kThreads) void k_cnn_inputs(FrameArgs a, DevParams p, uint16_t* out) {
   const int n_lost = a.st->n_lost;
   for (int i = blockIdx.x; i < n_lost; i += gridDim.x) {
     const int cell = a.blk[i];
     const int by = cell / p.gw, bx = cell - by * p.gw;
-    for (int idx = threadIdx.x; idx < kP * kP; idx += kThreads) {
+    for (int e = threadIdx.x; e < kC0 * kS * kS; e += kThreads) {
+      const int ch = e / (kS * kS), q = e - ch * (kS * kS);
+      const int Y = q / kS, X = q - Y * kS;
+      const int dy = (ch >> 1) & 1, dx = ch & 1;
       float c0, c1;
-      input_pixel(a, p, by, bx, idx, c0, c1);
-      out[(size_t)i * 2 * kP * kP + idx] = (uint16_t)(__float_as_uint(c0) >> 16);
-      out[(size_t)i * 2 * kP * kP + kP * kP + idx] = (uint16_t)(__float_as_uint(c1) >> 16);
+      input_pixel(a, p, by, bx, (2 * Y + dy) * kP + 2 * X + dx, c0, c1);
+      out[(size_t)i * kC0 * kS * kS + e] = (uint16_t)(__float_as_uint(ch < 4 ? c0 : c1) >> 16);
     }
   }
 }
@@ -105,8 +113,8 @@ __global__ __launch_bounds__(kThreads) void k_head_fwd(int N, const float* a3, c
   float gv[kC];
   for (int c = 0; c < kC; ++c) {
     float s = 0.0f;
-    for (int q = 0; q < 36; ++q) s += a3[((size_t)n * kC + c) * 36 + q];
-    gv[c] = s * (1.0f / 36.0f);
+    for (int q = 0; q < kPool; ++q) s += a3[((size_t)n * kC + c) * kPool + q];
+    gv[c] = s * (1.0f / kPool);
     g[(size_t)n * kC + c] = gv[c];
   }
   for (int o = 0; o < 2; ++o) {
@@ -160,13 +168,13 @@ __global__ __launch_bounds__(kThreads) void k_head_wgrad(int N, const float* gy,
 // d loss / d z3 through the head, the pool and the last ReLU
 __global__ __launch_bounds__(kThreads) void k_head_back(int N, const float* gy, const float* wq,
                                                         const float* z3, float* gz3) {
-  const long long total = (long long)N * kC * 36;
+  const long long total = (long long)N * kC * kPool;
   for (long long e = (long long)blockIdx.x * kThreads + threadIdx.x; e < total;
        e += (long long)gridDim.x * kThreads) {
-    const long long n = e / (kC * 36);
-    const int c = (int)((e / 36) % kC);
+    const long long n = e / (kC * kPool);
+    const int c = (int)((e / kPool) % kC);
     const float gg = gy[n * 2] * wq[kOffWh + c] + gy[n * 2 + 1] * wq[kOffWh + kC + c];
-    gz3[e] = z3[e] > 0.0f ? gg * (1.0f / 36.0f) : 0.0f;
+    gz3[e] = z3[e] > 0.0f ? gg * (1.0f / kPool) : 0.0f;
   }
 }
 
@@ -263,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_cnn_init(float* prm, unsigned long
   const int k = blockIdx.x * kThreads + threadIdx.x;
   if (k >= kNParams) return;
   float lim = 0.0f;
-  if (k < kOffB1) lim = sqrtf(6.0f / 18.0f);
+  if (k < kOffB1) lim = sqrtf(6.0f / 72.0f);
   else if (k >= kOffW2 && k < kOffB2) lim = sqrtf(6.0f / 288.0f);
   else if (k >= kOffW3 && k < kOffB3) lim = sqrtf(6.0f / 288.0f);
   else if (k >= kOffWh && k < kOffBh) lim = sqrtf(6.0f / 32.0f);
@@ -276,90 +284,112 @@ __global__ __launch_bounds__(kThreads) void k_cnn_init(float* prm, unsigned long
 }
 
 // ------------------------------------------------------------------ gate
-// Inference on MFMA: every convolution is a GEMM of (output positions) x
-// (3x3 taps x input channels) by (taps x channels) x (32 output channels),
-// run as v_mfma_f32_16x16x32_bf16 tiles with FP32 accumulation.  One
-// workgroup (4 waves) owns one block at a time: its input and both hidden
-// activations stay in LDS in a position-major layout (one 80-byte slot of
-// 32 bf16 channels per pixel, padded against bank conflicts) with a zero
-// row and column in front for the convolutions' padding.  The weight
-// fragments of the B operand stay in registers for the workgroup's life.
+// Inference on MFMA: every convolution is a GEMM of 32 output channels by
+// (3x3 taps x input channels) times (taps x channels) by (output positions),
+// run as v_mfma_f32_16x16x32_bf16 tiles with FP32 accumulation: the weights
+// are the A operand (rows = output channels), the im2col activations the B
+// operand (columns = positions).  One workgroup (4 waves) owns one block at a
+// time: its input and both hidden activations stay in LDS in a
+// position-major layout (one 80-byte slot of 32 bf16 channels per pixel,
+// padded against bank conflicts) with a zero row and column in front for the
+// convolutions' padding.  The weight fragments stay in registers for the
+// workgroup's life.
 //
 // Operand layout of the 16x16x32 MFMA: lane l supplies row (A) or column (B)
 // l % 16 with the eight K values 8 (l / 16) .. 8 (l / 16) + 7; it receives
-// D rows 4 (l / 16) .. + 3 of column l % 16.  K index k = 8 g + e maps to
+// D rows 4 (l / 16) .. + 3 of column l % 16, i.e. four consecutive output
+// channels of one position, stored as one 8-byte LDS write of packed bf16
+// (v_cvt_pk_bf16_f32, round to nearest even).  K index k = 8 g + e maps to
 // input channel k in layers 2 and 3 (one tap per K step) and to (tap k / 2,
 // channel k % 2) in layer 1 (taps 0..8, the rest zero).
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kIn = kP + 1;     // padded input side
-constexpr int kS1 = 25;         // padded side of layer-1 output (24 + 1)
-constexpr int kS2 = 13;         // padded side of layer-2 output (12 + 1)
+constexpr int kIn = kS + 1;     // padded side of the space-to-depth input
+constexpr int kS1 = 13;         // padded side of layer-1 output (12 + 1)
+constexpr int kS2 = 7;          // padded side of layer-2 output (6 + 1)
 constexpr int kPix = 40;        // bf16 slots per activation pixel (32 used)
 
 struct __align__(16) GateLds {
-  uint32_t in[(kIn * kIn + 3) / 4 * 4];   // (c0, c1) bf16 pair per input pixel (16-byte multiple)
+  u32x4 in[kIn * kIn];                    // the 8 input channels of a pixel (16 B)
   uint16_t a1[kS1 * kS1 * kPix];
   uint16_t a2[kS2 * kS2 * kPix];
-  float gpart[4][16];                     // per-wave pooled partial sums
+  float p3[4][16][17];                    // layer-3 partial sums: wave, channel row, position
 };
-
 static_assert(offsetof(GateLds, a1) % 16 == 0 && offsetof(GateLds, a2) % 16 == 0,
               "activation images must be 16-byte aligned for 128-bit LDS reads");
 
+// Work split of the four waves: wave w owns output-channel tile mt = w & 1 in
+// every layer; layers 1 and 2 split the position tiles between the wave
+// pairs (tiles (w >> 1) + 2 t), layer 3 (one position tile) splits its taps
+// (taps (w >> 1) + 2 u) and sums the two halves in LDS.  A wave thus holds
+// one channel tile of the weights of layers 1 and 2 and about half the taps
+// of layer 3 in registers.
+constexpr int kL3Taps = 5;                // taps of layer 3 per wave (the last pair holds 4)
+
 struct GateWeights {
-  bf16x8 w1[2];                           // layer 1, both column tiles
-  bf16x8 w2[9], w3[9];                    // layers 2, 3: this wave's column tile, per tap
-  float b1[2], b2, b3;                    // biases of column l % 16 (+ 16 tile)
+  bf16x8 w1[3];                           // layer 1: K steps of 4 taps x 8 channels
+  bf16x8 w2[9];                           // layer 2: per tap
+  bf16x8 w3[kL3Taps];                     // layer 3: taps (w >> 1) + 2 u
+  float b1[4], b2[4];                     // biases of this lane's four D rows
+  float b3, wh0, wh1;                     // channel `lane` of layer 3 and the head (lanes < 32)
+  float bh0, bh1;                         // head biases
 };
 
 static __device__ __forceinline__ uint32_t bf16_bits(float x) {   // x already bf16-valued
   return __float_as_uint(x) >> 16;
 }
-static __device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
+
+// relu(v + b) of four accumulator rows, packed to bf16 (RNE): 8 bytes
+static __device__ __forceinline__ uint2 relu_pack4(const f32x4& v, const float* b) {
+  const bf16x2 lo = {(__bf16)fmaxf(v[0] + b[0], 0.0f), (__bf16)fmaxf(v[1] + b[1], 0.0f)};
+  const bf16x2 hi = {(__bf16)fmaxf(v[2] + b[2], 0.0f), (__bf16)fmaxf(v[3] + b[3], 0.0f)};
+  return make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
+}
+
+// eight consecutive input channels c0 .. c0 + 7 of weight row n at one tap
+static __device__ __forceinline__ bf16x8 weight_frag(const float* w, int cin, int n, int c0,
+                                                     int tap) {
+  uint32_t u[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    u[q] = bf16_bits(w[(n * cin + c0 + 2 * q) * 9 + tap]) |
+           (bf16_bits(w[(n * cin + c0 + 2 * q + 1) * 9 + tap]) << 16);
+  return __builtin_bit_cast(bf16x8, (u32x4){u[0], u[1], u[2], u[3]});
 }
 
 static __device__ __forceinline__ GateWeights load_gate_weights(const float* wq) {
   const int lane = lane_id(), wave = wave_id();
-  const int col = lane & 15, g = lane >> 4, nt = wave & 1;
+  const int row = lane & 15, g = lane >> 4, mt = wave & 1;
+  const int n = mt * 16 + row;
+  const bf16x8 zero = __builtin_bit_cast(bf16x8, (u32x4){0u, 0u, 0u, 0u});
   GateWeights W;
 #pragma unroll
-  for (int t2 = 0; t2 < 2; ++t2) {
-    const int n = t2 * 16 + col;
-    uint32_t u[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int tap = 4 * g + q;              // k = 2 tap + c
-      u[q] = tap < 9 ? (bf16_bits(wq[kOffW1 + (n * 2 + 0) * 9 + tap]) |
-                        (bf16_bits(wq[kOffW1 + (n * 2 + 1) * 9 + tap]) << 16))
-                     : 0u;
-    }
-    W.w1[t2] = __builtin_bit_cast(bf16x8, (u32x4){u[0], u[1], u[2], u[3]});
-    W.b1[t2] = wq[kOffB1 + n];
+  for (int ks = 0; ks < 3; ++ks) {
+    const int tap = 4 * ks + g;                 // k = 32 ks + 8 g + channel
+    W.w1[ks] = tap < 9 ? weight_frag(wq + kOffW1, kC0, n, 0, tap) : zero;
   }
-  const int n = nt * 16 + col;
 #pragma unroll
-  for (int tap = 0; tap < 9; ++tap) {
-    uint32_t u2[4], u3[4];
+  for (int tap = 0; tap < 9; ++tap) W.w2[tap] = weight_frag(wq + kOffW2, kC, n, 8 * g, tap);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = 8 * g + 2 * q;
-      u2[q] = bf16_bits(wq[kOffW2 + (n * kC + c) * 9 + tap]) |
-              (bf16_bits(wq[kOffW2 + (n * kC + c + 1) * 9 + tap]) << 16);
-      u3[q] = bf16_bits(wq[kOffW3 + (n * kC + c) * 9 + tap]) |
-              (bf16_bits(wq[kOffW3 + (n * kC + c + 1) * 9 + tap]) << 16);
-    }
-    W.w2[tap] = __builtin_bit_cast(bf16x8, (u32x4){u2[0], u2[1], u2[2], u2[3]});
-    W.w3[tap] = __builtin_bit_cast(bf16x8, (u32x4){u3[0], u3[1], u3[2], u3[3]});
+  for (int u = 0; u < kL3Taps; ++u) {
+    const int tap = (wave >> 1) + 2 * u;
+    W.w3[u] = tap < 9 ? weight_frag(wq + kOffW3, kC, n, 8 * g, tap) : zero;
   }
-  W.b2 = wq[kOffB2 + n];
-  W.b3 = wq[kOffB3 + n];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    W.b1[j] = wq[kOffB1 + mt * 16 + 4 * g + j];
+    W.b2[j] = wq[kOffB2 + mt * 16 + 4 * g + j];
+  }
+  const int c = lane & (kC - 1);
+  W.b3 = wq[kOffB3 + c];
+  W.wh0 = wq[kOffWh + c];
+  W.wh1 = wq[kOffWh + kC + c];
+  W.bh0 = wq[kOffBh];
+  W.bh1 = wq[kOffBh + 1];
   return W;
 }
 
@@ -367,7 +397,7 @@ static __device__ __forceinline__ GateWeights load_gate_weights(const float* wq)
 static __device__ __forceinline__ void gate_clear_padding(GateLds& G) {
   for (int e = threadIdx.x; e < 2 * kIn; e += kThreads) {
     const int k = e % kIn;
-    G.in[e < kIn ? k : k * kIn] = 0u;
+    G.in[e < kIn ? k : k * kIn] = (u32x4){0u, 0u, 0u, 0u};
   }
   for (int e = threadIdx.x; e < 2 * kS1 * kPix; e += kThreads) {
     const int pix = (e / kPix) % kS1, c = e % kPix;
@@ -383,99 +413,126 @@ static __device__ __forceinline__ bf16x8 lds_frag(const uint16_t* p) {
   return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
 }
 
-// The network on the input staged in G.in; returns (y0, y1) in lanes of
-// wave 0 (valid in every lane of wave 0).  Barriers inside; the caller
-// syncs before staging the next input.
-static __device__ __forceinline__ void gate_network(GateLds& G, const GateWeights& W,
-                                                    const float* wq, float& y0, float& y1) {
+// The network on the input staged in G.in; returns (y0, y1) in every lane of
+// wave 0.  Barriers inside; the caller syncs before staging the next input.
+static __device__ __forceinline__ void gate_network(GateLds& G, const GateWeights& W, float& y0,
+                                                    float& y1) {
   const int lane = lane_id(), wave = wave_id();
-  const int col = lane & 15, g = lane >> 4, nt = wave & 1;
+  const int col = lane & 15, g = lane >> 4, mt = wave & 1;
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
 
-  // layer 1: 576 positions = 36 row tiles, both column tiles, one K step
-  for (int mt = wave; mt < 36; mt += 4) {
-    const int m = mt * 16 + col;
-    const int oy = m / 24, ox = m - oy * 24;
-    uint32_t u[4];
+  // layer 1: 144 positions = 9 column tiles; K = 9 taps x 8 channels in
+  // three steps (lane group g takes tap 4 step + g; tap 9 .. 11 are zero).
+  // The next tile's fragments are read while this tile's products run.
+  {
+    u32x4 Xn[3];
+    auto read_tile = [&](int nt) {
+      const int m = nt * 16 + col;
+      const int oy = m / 12, ox = m - oy * 12;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int tap = 4 * g + q;
-      const int ky = tap / 3, kx = tap - 3 * (tap / 3);
-      u[q] = tap < 9 ? G.in[(2 * oy + ky) * kIn + 2 * ox + kx] : 0u;
-    }
-    const bf16x8 A = __builtin_bit_cast(bf16x8, (u32x4){u[0], u[1], u[2], u[3]});
-#pragma unroll
-    for (int t2 = 0; t2 < 2; ++t2) {
-      const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, W.w1[t2], zero, 0, 0, 0);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int mo = mt * 16 + 4 * g + j;
-        const int py = mo / 24, px = mo - py * 24;
-        G.a1[((py + 1) * kS1 + px + 1) * kPix + t2 * 16 + col] =
-            (uint16_t)bf16_rne_bits(fmaxf(d[j] + W.b1[t2], 0.0f));
+      for (int ks = 0; ks < 3; ++ks) {
+        const int tap = 4 * ks + g;
+        const int ky = tap / 3, kx = tap - 3 * (tap / 3);
+        Xn[ks] = tap < 9 ? G.in[(2 * oy + ky) * kIn + 2 * ox + kx] : (u32x4){0u, 0u, 0u, 0u};
       }
+    };
+    read_tile(wave >> 1);
+#pragma unroll 1
+    for (int nt = wave >> 1; nt < 9; nt += 2) {
+      u32x4 X[3];
+#pragma unroll
+      for (int ks = 0; ks < 3; ++ks) X[ks] = Xn[ks];
+      if (nt + 2 < 9) read_tile(nt + 2);
+      f32x4 d = zero;
+#pragma unroll
+      for (int ks = 0; ks < 3; ++ks)
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.w1[ks], __builtin_bit_cast(bf16x8, X[ks]), d,
+                                                    0, 0, 0);
+      const int m = nt * 16 + col;
+      const int oy = m / 12, ox = m - oy * 12;
+      *reinterpret_cast<uint2*>(&G.a1[((oy + 1) * kS1 + ox + 1) * kPix + mt * 16 + 4 * g]) =
+          relu_pack4(d, W.b1);
     }
   }
   __syncthreads();
 
-  // layer 2: 144 positions = 9 row tiles; wave owns column tile nt and row
-  // tiles (wave >> 1) + 2 t
-  for (int mt = wave >> 1; mt < 9; mt += 2) {
-    const int m = mt * 16 + col;
-    const int oy = m / 12, ox = m - oy * 12;
-    f32x4 acc = zero;
-#pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-      const int ky = tap / 3, kx = tap % 3;
-      const bf16x8 A = lds_frag(&G.a1[((2 * oy + ky) * kS1 + 2 * ox + kx) * kPix + 8 * g]);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, W.w2[tap], acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int mo = mt * 16 + 4 * g + j;
-      const int py = mo / 12, px = mo - py * 12;
-      G.a2[((py + 1) * kS2 + px + 1) * kPix + nt * 16 + col] =
-          (uint16_t)bf16_rne_bits(fmaxf(acc[j] + W.b2, 0.0f));
-    }
-  }
-  __syncthreads();
-
-  // layer 3: 36 positions = 3 row tiles (the last one 4 rows deep), pooled
-  float pool = 0.0f;
-  for (int mt = wave >> 1; mt < 3; mt += 2) {
-    const int m = min(mt * 16 + col, 35);
+  // layer 2: 36 positions = 3 column tiles (the last 4 columns wide)
+#pragma unroll 1
+  for (int nt = wave >> 1; nt < 3; nt += 2) {
+    const int mv = nt * 16 + col;
+    const int m = min(mv, 35);
     const int oy = m / 6, ox = m - oy * 6;
     f32x4 acc = zero;
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int ky = tap / 3, kx = tap % 3;
-      const bf16x8 A = lds_frag(&G.a2[((2 * oy + ky) * kS2 + 2 * ox + kx) * kPix + 8 * g]);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, W.w3[tap], acc, 0, 0, 0);
+      const bf16x8 X = lds_frag(&G.a1[((2 * oy + ky) * kS1 + 2 * ox + kx) * kPix + 8 * g]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.w2[tap], X, acc, 0, 0, 0);
+      // at most three fragments in flight: keeps the registers within four
+      // waves per SIMD
+      if (tap % 3 == 2) __builtin_amdgcn_sched_barrier(0);
+    }
+    if (mv < 36)
+      *reinterpret_cast<uint2*>(&G.a2[((oy + 1) * kS2 + ox + 1) * kPix + mt * 16 + 4 * g]) =
+          relu_pack4(acc, W.b2);
+  }
+  __syncthreads();
+
+  // layer 3: 9 positions = one column tile (columns 9 .. 15 repeat position
+  // 8 and are dropped below); this wave's taps, partial sums to LDS
+  {
+    const int m = min(col, kPool - 1);
+    const int oy = m / 3, ox = m - oy * 3;
+    f32x4 acc = zero;
+#pragma unroll
+    for (int u = 0; u < kL3Taps; ++u) {
+      const int tap = (wave >> 1) + 2 * u;
+      if (tap < 9) {
+        const int ky = tap / 3, kx = tap % 3;
+        const bf16x8 X = lds_frag(&G.a2[((2 * oy + ky) * kS2 + 2 * ox + kx) * kPix + 8 * g]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.w3[u], X, acc, 0, 0, 0);
+      }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (mt * 16 + 4 * g + j < 36) pool += fmaxf(acc[j] + W.b3, 0.0f);
+    for (int j = 0; j < 4; ++j) G.p3[wave][4 * g + j][col] = acc[j];
   }
-  pool += __shfl_xor(pool, 16, 64);
-  pool += __shfl_xor(pool, 32, 64);
-  if (lane < 16) G.gpart[wave][lane] = pool;
   __syncthreads();
+
+  // pooled relu(conv + b3) per channel, then the two head outputs (wave 0)
   if (wave == 0) {
     float h0 = 0.0f, h1 = 0.0f;
     if (lane < kC) {
-      const int t2 = lane >> 4, c16 = lane & 15;
-      const float gv = (G.gpart[t2][c16] + G.gpart[t2 + 2][c16]) * (1.0f / 36.0f);
-      h0 = gv * wq[kOffWh + lane];
-      h1 = gv * wq[kOffWh + kC + lane];
+      const int t = lane >> 4, r = lane & 15;
+      float s = 0.0f;
+#pragma unroll
+      for (int mm = 0; mm < kPool; ++mm)
+        s += fmaxf(G.p3[t][r][mm] + G.p3[t + 2][r][mm] + W.b3, 0.0f);
+      const float gv = s * (1.0f / kPool);
+      h0 = gv * W.wh0;
+      h1 = gv * W.wh1;
     }
-    y0 = wave_sum(h0) + wq[kOffBh];
-    y1 = wave_sum(h1) + wq[kOffBh + 1];
+    y0 = wave_sum(h0) + W.bh0;
+    y1 = wave_sum(h1) + W.bh1;
   }
+}
+
+// the 8 space-to-depth channels of input pixel (Y, X) from the four window
+// pixels (2 Y + dy, 2 X + dx), dy, dx in {0, 1} (value -1 = unknown)
+static __device__ __forceinline__ u32x4 s2d_pixel(const int* v) {
+  uint32_t c0[4], c1[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    // (u - 128) / 128 is exact in bf16
+    c0[q] = v[q] >= 0 ? bf16_bits((float)(v[q] - 128) * (1.0f / 128.0f)) : 0u;
+    c1[q] = v[q] >= 0 ? 0u : 0x3f80u;                   // bf16 1.0
+  }
+  return (u32x4){c0[0] | (c0[1] << 16), c0[2] | (c0[3] << 16), c1[0] | (c1[1] << 16),
+                 c1[2] | (c1[3] << 16)};
 }
 
 // In-pipeline gate: one pass over the blocks eligible in this round; the
 // layer choice goes to gate[i] and the predictions to gate_pred.
-__global__ __launch_bounds__(kThreads) void k_cnn_gate(FrameArgs a, DevParams p, const float* wq,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_gate(FrameArgs a, DevParams p, const float* wq,
                                                        float tau1, float tau2) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int red[kThreads / 64][2];
@@ -502,9 +559,10 @@ __global__ __launch_bounds__(kThreads) void k_cnn_gate(FrameArgs a, DevParams p,
   const int lw = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   const int per = (n_lost + gridDim.x - 1) / gridDim.x;
   const int i_end = min(n_lost, (lw + 1) * per);
-  // the input pixels of block i + 1 are loaded while block i runs
-  constexpr int kPer = (kP * kP + kThreads - 1) / kThreads;
-  int v[kPer];
+  // the window pixels of block i + 1 are loaded while block i runs: thread t
+  // owns input pixels t + 256 k, four window pixels each
+  constexpr int kPer = (kS * kS + kThreads - 1) / kThreads;
+  int v[kPer][4];
   auto load_block = [&](int blk) {
     const int cell = a.blk[blk];
     const int by = cell / p.gw, bx = cell - by * p.gw;
@@ -512,37 +570,43 @@ __global__ __launch_bounds__(kThreads) void k_cnn_gate(FrameArgs a, DevParams p,
 #pragma unroll
     for (int t = 0; t < kPer; ++t) {
       const int idx = tid + t * kThreads;
-      const int py = idx / kP, px = idx - py * kP;
-      const int gy = gy0 + py, gx = gx0 + px;
-      const bool in = idx < kP * kP && gy >= 0 && gy < p.height && gx >= 0 && gx < p.width;
-      const int cy = min(max(gy, 0), p.height - 1), cx = min(max(gx, 0), p.width - 1);
-      const int val = a.val[(size_t)cy * p.width + cx];
-      v[t] = in ? val : -1;
+      const int Y = idx / kS, X = idx - Y * kS;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gy = gy0 + 2 * Y + (q >> 1), gx = gx0 + 2 * X + (q & 1);
+        const bool in = idx < kS * kS && gy >= 0 && gy < p.height && gx >= 0 && gx < p.width;
+        const int cy = min(max(gy, 0), p.height - 1), cx = min(max(gx, 0), p.width - 1);
+        const int val = a.val[(size_t)cy * p.width + cx];
+        v[t][q] = in ? val : -1;
+      }
     }
   };
+  // state and ring count of the next block travel with its pixels
+  int nx_state = 1, nx_m0 = 0;
+  auto load_next = [&](int blk) {
+    load_block(blk);
+    nx_state = a.bstate[blk];
+    nx_m0 = a.m0cnt[blk];
+  };
   const int i_begin = lw * per;
-  if (i_begin < i_end) load_block(i_begin);
+  if (i_begin < i_end) load_next(i_begin);
   for (int i = i_begin; i < i_end; ++i) {
-    const bool elig = a.bstate[i] == 0 &&
-                      (nq > 0 ? (a.m0cnt[i] >= p.r * p.B) : (a.m0cnt[i] == maxm0));
+    const bool elig = nx_state == 0 && (nq > 0 ? (nx_m0 >= p.r * p.B) : (nx_m0 == maxm0));
     if (elig) {
-      // c0 = (u - 128) / 128 at known pixels (exact in bf16), c1 = 1 at unknown
 #pragma unroll
       for (int t = 0; t < kPer; ++t) {
         const int idx = tid + t * kThreads;
-        if (idx < kP * kP) {
-          const int py = idx / kP, px = idx - py * kP;
-          const float c0 = v[t] >= 0 ? (float)(v[t] - 128) * (1.0f / 128.0f) : 0.0f;
-          const float c1 = v[t] >= 0 ? 0.0f : 1.0f;
-          G.in[(py + 1) * kIn + px + 1] = bf16_bits(c0) | (bf16_bits(c1) << 16);
+        if (idx < kS * kS) {
+          const int Y = idx / kS, X = idx - Y * kS;
+          G.in[(Y + 1) * kIn + X + 1] = s2d_pixel(v[t]);
         }
       }
     }
     __syncthreads();
-    if (i + 1 < i_end) load_block(i + 1);
+    if (i + 1 < i_end) load_next(i + 1);
     if (!elig) continue;
     float y0 = 0.0f, y1 = 0.0f;
-    gate_network(G, W, wq, y0, y1);
+    gate_network(G, W, y0, y1);
     if (tid == 0) {
       a.gate[i] = (int8_t)(y0 <= tau1 ? SKM_LAYER_BRL : (y1 > tau2 ? SKM_LAYER_HQL : SKM_LAYER_IDL));
       if (a.gate_pred) { a.gate_pred[2 * i] = y0; a.gate_pred[2 * i + 1] = y1; }
@@ -551,8 +615,8 @@ __global__ __launch_bounds__(kThreads) void k_cnn_gate(FrameArgs a, DevParams p,
   }
 }
 
-// Batched inference on prepared inputs x (bf16 bits [n][2][48][48]).
-__global__ __launch_bounds__(kThreads) void k_cnn_infer(const uint16_t* x, int n, const float* wq,
+// Batched inference on prepared inputs x (bf16 bits [n][8][24][24]).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_infer(const uint16_t* x, int n, const float* wq,
                                                         float* y) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   GateLds& G = *reinterpret_cast<GateLds*>(lds_raw);
@@ -560,14 +624,18 @@ __global__ __launch_bounds__(kThreads) void k_cnn_infer(const uint16_t* x, int n
   const GateWeights W = load_gate_weights(wq);
   const int tid = threadIdx.x;
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
-    const uint16_t* xi = x + (size_t)i * 2 * kP * kP;
-    for (int idx = tid; idx < kP * kP; idx += kThreads) {
-      const int py = idx / kP, px = idx - py * kP;
-      G.in[(py + 1) * kIn + px + 1] = (uint32_t)xi[idx] | ((uint32_t)xi[kP * kP + idx] << 16);
+    const uint16_t* xi = x + (size_t)i * kC0 * kS * kS;
+    for (int idx = tid; idx < kS * kS; idx += kThreads) {
+      uint32_t u[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        u[q] = (uint32_t)xi[(2 * q) * kS * kS + idx] | ((uint32_t)xi[(2 * q + 1) * kS * kS + idx] << 16);
+      const int Y = idx / kS, X = idx - Y * kS;
+      G.in[(Y + 1) * kIn + X + 1] = (u32x4){u[0], u[1], u[2], u[3]};
     }
     __syncthreads();
     float y0 = 0.0f, y1 = 0.0f;
-    gate_network(G, W, wq, y0, y1);
+    gate_network(G, W, y0, y1);
     if (tid == 0) { y[2 * (size_t)i] = y0; y[2 * (size_t)i + 1] = y1; }
     __syncthreads();
   }
@@ -587,8 +655,10 @@ hipError_t launch_cnn_inputs(const FrameArgs& a, const DevParams& p, uint16_t* o
   return hipGetLastError();
 }
 
-// two resident workgroups per CU (LDS), 256 CUs
-constexpr int kGateGrid = 512;
+// upper bound of the gate's persistent grid (three workgroups per CU are
+// resident: registers; the caller picks the grid below this)
+constexpr int kGateGrid = 4096;
+constexpr int kInferGrid = 768;
 
 hipError_t launch_cnn_gate(const FrameArgs& a, const DevParams& p, const float* wq, float tau1,
                            float tau2, int max_blocks, hipStream_t s) {
@@ -601,7 +671,7 @@ hipError_t launch_cnn_gate(const FrameArgs& a, const DevParams& p, const float* 
 }
 
 hipError_t cnn_infer(const uint16_t* x, int n, const float* wq, float* y, hipStream_t s) {
-  hipLaunchKernelGGL(k_cnn_infer, dim3(n > kGateGrid ? kGateGrid : n), dim3(kThreads),
+  hipLaunchKernelGGL(k_cnn_infer, dim3(n > kInferGrid ? kInferGrid : n), dim3(kThreads),
                      sizeof(GateLds), s, x, n, wq, y);
   return hipGetLastError();
 }
@@ -628,12 +698,13 @@ hipError_t cnn_quantize(const float* prm, float* wq, hipStream_t s) {
 }
 
 hipError_t cnn_forward(const CnnBuffers& b, const float* wq, const uint16_t* x, int N, hipStream_t s) {
-  hipLaunchKernelGGL(k_conv_fwd, dim3(cgrid((long long)N * kC * 576)), dim3(kThreads), 0, s, N, 2, 48,
-                     (const float*)nullptr, x, wq + kOffW1, wq + kOffB1, b.z1, b.a1, 1);
-  hipLaunchKernelGGL(k_conv_fwd, dim3(cgrid((long long)N * kC * 144)), dim3(kThreads), 0, s, N, kC, 24,
-                     (const float*)b.a1, (const uint16_t*)nullptr, wq + kOffW2, wq + kOffB2, b.z2, b.a2, 1);
+  hipLaunchKernelGGL(k_conv_fwd, dim3(cgrid((long long)N * kC * 144)), dim3(kThreads), 0, s, N, kC0,
+                     kS, (const float*)nullptr, x, wq + kOffW1, wq + kOffB1, b.z1, b.a1, 1);
   hipLaunchKernelGGL(k_conv_fwd, dim3(cgrid((long long)N * kC * 36)), dim3(kThreads), 0, s, N, kC, 12,
-                     (const float*)b.a2, (const uint16_t*)nullptr, wq + kOffW3, wq + kOffB3, b.z3, b.a3, 0);
+                     (const float*)b.a1, (const uint16_t*)nullptr, wq + kOffW2, wq + kOffB2, b.z2, b.a2, 1);
+  hipLaunchKernelGGL(k_conv_fwd, dim3(cgrid((long long)N * kC * kPool)), dim3(kThreads), 0, s, N, kC,
+                     6, (const float*)b.a2, (const uint16_t*)nullptr, wq + kOffW3, wq + kOffB3, b.z3,
+                     b.a3, 0);
   hipLaunchKernelGGL(k_head_fwd, dim3((N + kThreads - 1) / kThreads), dim3(kThreads), 0, s, N,
                      (const float*)b.a3, wq, b.g, b.y);
   return hipGetLastError();
@@ -644,19 +715,19 @@ hipError_t cnn_backward(const CnnBuffers& b, const float* wq, const uint16_t* x,
   hipLaunchKernelGGL(k_loss, dim3(1), dim3(kThreads), 0, s, N, (const float*)b.y, t, b.gy, loss);
   hipLaunchKernelGGL(k_head_wgrad, dim3(66), dim3(kThreads), 0, s, N, (const float*)b.gy,
                      (const float*)b.g, grad);
-  hipLaunchKernelGGL(k_head_back, dim3(cgrid((long long)N * kC * 36)), dim3(kThreads), 0, s, N,
+  hipLaunchKernelGGL(k_head_back, dim3(cgrid((long long)N * kC * kPool)), dim3(kThreads), 0, s, N,
                      (const float*)b.gy, wq, (const float*)b.z3, b.gz3);
-  hipLaunchKernelGGL(k_conv_wgrad, dim3(kC * kC * 9 + kC), dim3(kThreads), 0, s, N, kC, 12,
+  hipLaunchKernelGGL(k_conv_wgrad, dim3(kC * kC * 9 + kC), dim3(kThreads), 0, s, N, kC, 6,
                      (const float*)b.gz3, (const float*)b.a2, (const uint16_t*)nullptr, grad + kOffW3,
                      grad + kOffB3);
-  hipLaunchKernelGGL(k_conv_dgrad, dim3(cgrid((long long)N * kC * 144)), dim3(kThreads), 0, s, N, kC,
-                     12, (const float*)b.gz3, wq + kOffW3, (const float*)b.z2, b.gz2);
-  hipLaunchKernelGGL(k_conv_wgrad, dim3(kC * kC * 9 + kC), dim3(kThreads), 0, s, N, kC, 24,
+  hipLaunchKernelGGL(k_conv_dgrad, dim3(cgrid((long long)N * kC * 36)), dim3(kThreads), 0, s, N, kC,
+                     6, (const float*)b.gz3, wq + kOffW3, (const float*)b.z2, b.gz2);
+  hipLaunchKernelGGL(k_conv_wgrad, dim3(kC * kC * 9 + kC), dim3(kThreads), 0, s, N, kC, 12,
                      (const float*)b.gz2, (const float*)b.a1, (const uint16_t*)nullptr, grad + kOffW2,
                      grad + kOffB2);
-  hipLaunchKernelGGL(k_conv_dgrad, dim3(cgrid((long long)N * kC * 576)), dim3(kThreads), 0, s, N, kC,
-                     24, (const float*)b.gz2, wq + kOffW2, (const float*)b.z1, b.gz1);
-  hipLaunchKernelGGL(k_conv_wgrad, dim3(kC * 2 * 9 + kC), dim3(kThreads), 0, s, N, 2, 48,
+  hipLaunchKernelGGL(k_conv_dgrad, dim3(cgrid((long long)N * kC * 144)), dim3(kThreads), 0, s, N, kC,
+                     12, (const float*)b.gz2, wq + kOffW2, (const float*)b.z1, b.gz1);
+  hipLaunchKernelGGL(k_conv_wgrad, dim3(kC * kC0 * 9 + kC), dim3(kThreads), 0, s, N, kC0, kS,
                      (const float*)b.gz1, (const float*)nullptr, x, grad + kOffW1, grad + kOffB1);
   return hipGetLastError();
 }

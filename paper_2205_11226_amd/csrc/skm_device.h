@@ -22,6 +22,16 @@ static __device__ __forceinline__ int xcd_block(int wg, int n) {
 }
 
 static __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// n / d for 0 <= n < 2^22 and 1 <= d < 2^10, with inv_d = 1.0f / d: a float
+// estimate (within one of the quotient) and one exact integer correction,
+// instead of the long integer division sequence
+static __device__ __forceinline__ int quot_small(int n, int d, float inv_d) {
+  int q = (int)(((float)n + 0.5f) * inv_d);
+  q -= q * d > n ? 1 : 0;
+  q += (q + 1) * d <= n ? 1 : 0;
+  return q;
+}
 static __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
 template <typename T>
@@ -253,7 +263,7 @@ struct BlockShared {
   int rowbase[2 * kMaxWin + 1];
   unsigned long long bmax[kMaxRadii];
   int bcnt[kMaxRadii];
-  double cm[kMaxRadii];
+  double fsc[kMaxRadii];
   double ps[kThreads / 64][kMaxRadii];
   int bucket_of[kMaxWin + 1];
 };
@@ -304,6 +314,7 @@ static __device__ __forceinline__ void phase_tables(const DevParams& p, const Ma
                                                     BlockShared& sh) {
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   const int B = p.B, r = p.r, W = p.W, Wd = p.Wd, F = p.F;
+  for (int k = tid; k < 2 * Wd; k += kThreads) L.rowbits[k] = 0ull;
   if (tid <= W) {
     int b = p.nrad - 1;
     for (int ri = 0; ri < p.nrad; ++ri) if (p.radii[ri] >= tid) { b = ri; break; }
@@ -336,45 +347,76 @@ static __device__ __forceinline__ void phase_tables(const DevParams& p, const Ma
   __syncthreads();
 }
 
-// Stage the window of the block whose window origin is (ox, oy): one wave per
-// row and lanes along it, up to 18 rows of loads in flight per wave (the
-// whole window up to 72 rows); pixel pairs by lane shuffle; availability
-// bits per row.  Ends with a barrier.
+// Stage the window of the block whose window origin is (ox, oy).  A lane
+// owns a segment of four window columns of one row (S = ceil(Wd / 4)
+// segments a row, 64 / S rows per wave and pass) and reads the five values
+// it needs (its four pixels and the right partner of the last) with one
+// 12-byte load from the dword-aligned element below; a funnel shift aligns
+// them.  Pixels outside the frame or past the window's last column become
+// unknown (-1).  Reads stay within the value plane and its guard bands: a
+// segment with an in-frame pixel starts at most 6 elements before the plane
+// or ends at most 5 after it, and segments entirely outside (masked anyway)
+// are clamped into the same range.  Each lane also ORs the availability bits
+// of its four pixels into the row's 128-bit mask (rowbits, cleared by
+// phase_tables).  Ends with a barrier.
 static __device__ __forceinline__ void phase_stage(const FrameArgs& a, const DevParams& p,
                                                    const MainLds& L, int ox, int oy) {
   const int lane = lane_id(), wave = wave_id();
-  const int Wd = p.Wd, nw = kThreads / 64;
-  constexpr int kRows = 18;
-  for (int wy0 = wave; wy0 < Wd; wy0 += kRows * nw) {
-    int v0[kRows], v1[kRows];
+  const int Wd = p.Wd;
+  const int S = (Wd + 3) >> 2;
+  const int R = 64 / S;
+  const int g = lane / S, c0 = 4 * (lane - g * S);
+  const int npx = p.width * p.height;
+  const int rstep = R * (kThreads / 64);
+  constexpr int kPass = 6;
+  const int gx = ox + c0;
+  // unknown marks of the five values from the column tests alone (bit q)
+  uint32_t colbad = 0;
 #pragma unroll
-    for (int t = 0; t < kRows; ++t) {
-      const int wy = wy0 + t * nw;
+  for (int q = 0; q < 5; ++q)
+    colbad |= (uint32_t)((unsigned)(gx + q) >= (unsigned)p.width || c0 + q >= Wd) << q;
+  for (int wy0 = wave * R + g; wy0 < Wd + g; wy0 += kPass * rstep) {
+    uint32_t w0[kPass], w1[kPass], w2[kPass];
+    uint32_t shv[kPass];
+#pragma unroll
+    for (int t = 0; t < kPass; ++t) {
+      const int wy = wy0 + t * rstep;
       const int gy = oy + wy;
       const int cy = min(max(gy, 0), p.height - 1);
-      const bool rowok = wy < Wd && gy >= 0 && gy < p.height;
-      const int gx0 = ox + lane, gx1 = ox + 64 + lane;
-      const int16_t r0 = a.val[(size_t)cy * p.width + min(max(gx0, 0), p.width - 1)];
-      const int16_t r1 = a.val[(size_t)cy * p.width + min(max(gx1, 0), p.width - 1)];
-      v0[t] = (rowok && lane < Wd && gx0 >= 0 && gx0 < p.width) ? r0 : -1;
-      v1[t] = (rowok && 64 + lane < Wd && gx1 >= 0 && gx1 < p.width) ? r1 : -1;
+      const int e = cy * p.width + gx;
+      const int e2 = min(max(e & ~1, -kValGuard), npx + 2);
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(a.val + e2);
+      shv[t] = (uint32_t)(e & 1) << 4;
+      w0[t] = src[0]; w1[t] = src[1]; w2[t] = src[2];
     }
 #pragma unroll
-    for (int t = 0; t < kRows; ++t) {
-      const int wy = wy0 + t * nw;
-      const int n0 = __shfl_down(v0[t], 1, 64);
-      const int h0 = __shfl(v1[t], 0, 64);
-      const int n1 = __shfl_down(v1[t], 1, 64);
-      const int nx0 = lane == 63 ? h0 : n0;
-      const int nx1 = (lane == 63 || 64 + lane + 1 >= Wd) ? -1 : n1;
-      const int nxa = (lane + 1 >= Wd) ? -1 : nx0;
-      const uint64_t lo = __ballot(v0[t] >= 0), hi = __ballot(v1[t] >= 0);
-      if (wy < Wd) {
-        if (lane < Wd)
-          L.winp[wy * Wd + lane] = (uint32_t)(uint16_t)v0[t] | ((uint32_t)(uint16_t)nxa << 16);
-        if (64 + lane < Wd)
-          L.winp[wy * Wd + 64 + lane] = (uint32_t)(uint16_t)v1[t] | ((uint32_t)(uint16_t)nx1 << 16);
-        if (lane == 0) { L.rowbits[2 * wy] = lo; L.rowbits[2 * wy + 1] = hi; }
+    for (int t = 0; t < kPass; ++t) {
+      const int wy = wy0 + t * rstep;
+      if (g >= R || wy >= Wd) continue;
+      const int gy = oy + wy;
+      const uint32_t bad = (gy >= 0 && gy < p.height) ? colbad : 0x1fu;
+      // x0 = (p0, p1), x1 = (p2, p3), low half of x2 = p4
+      const uint32_t x0 = __builtin_amdgcn_alignbit(w1[t], w0[t], shv[t]);
+      const uint32_t x1 = __builtin_amdgcn_alignbit(w2[t], w1[t], shv[t]);
+      const uint32_t x2 = w2[t] >> shv[t];
+      uint32_t pr[4] = {x0, __builtin_amdgcn_alignbit(x1, x0, 16), x1,
+                        __builtin_amdgcn_alignbit(x2, x1, 16)};
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        pr[q] |= (((bad >> q) & 1u) ? 0x0000ffffu : 0u) | (((bad >> (q + 1)) & 1u) ? 0xffff0000u : 0u);
+      // availability bits of the row: this segment's nibble (rows cleared
+      // by phase_tables)
+      uint32_t nib = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) nib |= (uint32_t)((pr[q] & 0x8000u) == 0u) << q;
+      if (nib) atomicOr(reinterpret_cast<uint32_t*>(L.rowbits) + 4 * wy + (c0 >> 5), nib << (c0 & 31));
+      uint32_t* dst = L.winp + wy * Wd + c0;
+      if ((Wd & 3) == 0) {
+        *reinterpret_cast<uint4*>(dst) = make_uint4(pr[0], pr[1], pr[2], pr[3]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (c0 + q < Wd) dst[q] = pr[q];
       }
     }
   }
@@ -460,17 +502,32 @@ static __device__ __forceinline__ int phase_candidates(const DevParams& p, const
   }
   if (tid < p.nrad) { sh.bmax[tid] = 0xFFF0000000000000ull; sh.bcnt[tid] = 0; }
   __syncthreads();
-  for (int dyi = wave; dyi < D2; dyi += nw) {
-    const uint64_t mlo = L.cmask[2 * dyi], mhi = L.cmask[2 * dyi + 1];
-    const int base = sh.rowbase[dyi];
-    const int ady = abs(dyi - W);
-    for (int dxi = lane; dxi < D2; dxi += 64) {
-      const bool ok = dxi < 64 ? ((mlo >> dxi) & 1ull) : ((mhi >> (dxi - 64)) & 1ull);
-      if (ok) {
-        const int rank = dxi < 64 ? __popcll(mlo & ((1ull << dxi) - 1ull))
-                                  : __popcll(mlo) + __popcll(mhi & ((1ull << (dxi - 64)) - 1ull));
-        const int rho = max(ady, abs(dxi - W));
-        L.cand[base + rank] = (uint32_t)(dyi * Wd + dxi) | ((uint32_t)sh.bucket_of[rho] << 14);
+  // thread t takes the displacements t, t + 256, ... (raster order), four at
+  // a time so that their LDS reads are in flight together
+  const int nd = D2 * D2;
+  const float inv_d2 = 1.0f / (float)D2;
+  constexpr int kU = 4;
+  for (int pos0 = tid; pos0 < nd; pos0 += kU * kThreads) {
+    uint64_t w[kU], below[kU];
+    int base[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int pos = min(pos0 + u * kThreads, nd - 1);
+      const int dyi = quot_small(pos, D2, inv_d2), dxi = pos - dyi * D2;
+      const uint64_t mlo = L.cmask[2 * dyi];
+      w[u] = dxi < 64 ? mlo : L.cmask[2 * dyi + 1];
+      below[u] = dxi < 64 ? 0ull : mlo;
+      base[u] = sh.rowbase[dyi];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int pos = pos0 + u * kThreads;
+      const int dyi = quot_small(pos, D2, inv_d2), dxi = pos - dyi * D2;
+      const int b = dxi & 63;
+      if (pos < nd && ((w[u] >> b) & 1ull)) {
+        const int rank = __popcll(below[u]) + __popcll(w[u] & ((1ull << b) - 1ull));
+        const int rho = max(abs(dyi - W), abs(dxi - W));
+        L.cand[base[u] + rank] = (uint32_t)(dyi * Wd + dxi) | ((uint32_t)sh.bucket_of[rho] << 14);
       }
     }
   }
@@ -503,10 +560,16 @@ static __device__ __forceinline__ void cand_distance(const MainLds& L, int base,
 
 // Six-operation form of pair_dist: unknown halves of either side give a
 // zero difference; `nbad` counts them (sdot2 of the 0 / -1 masks).
+// The masking is one v_bfi_b32 (written as an ALU-only asm statement: the
+// compiler otherwise turns the and-not of a sign mask into per-half compares
+// and selects, five more instructions).
 static __device__ __forceinline__ void pair_dist6(uint32_t q, uint32_t pp, int& d, int& nbad) {
   const short2v qa = __builtin_bit_cast(short2v, q), pa = __builtin_bit_cast(short2v, pp);
   const short2v bad = (qa | pa) >> (short2v){15, 15};          // -1 where unknown
-  const short2v df = (qa - pa) & ~bad;
+  const uint32_t diff = __builtin_bit_cast(uint32_t, (short2v)(qa - pa));
+  uint32_t dm;
+  asm("v_bfi_b32 %0, %1, 0, %2" : "=v"(dm) : "v"(__builtin_bit_cast(uint32_t, bad)), "v"(diff));
+  const short2v df = __builtin_bit_cast(short2v, dm);
   d = __builtin_amdgcn_sdot2(df, df, d, false);
   nbad = __builtin_amdgcn_sdot2(bad, bad, nbad, false);
 }
@@ -532,5 +595,71 @@ static __device__ __forceinline__ void cand_distance_wave(const MainLds& L, int 
   d_out = d;
   n_out = 2 * NU32 - nbad;
 }
+
+// Context units of a geometry fixed at compile time (block B, ring R,
+// search radius W): the same enumeration as phase_tables (footprint rows top
+// to bottom; full rows in pairs of columns, the rows beside the block in the
+// left and right ring parts), so unit u of the table matches qu[u].
+template <int B, int R, int W>
+struct FixedGeom {
+  static constexpr int kB = B, kR = R, kW = W;
+  static constexpr int F = B + 2 * R;
+  static constexpr int Wd = B + 2 * R + 2 * W;
+  static constexpr int NU = 2 * R * ((F + 1) / 2) + B * 2 * ((R + 1) / 2);
+  static_assert(F % 2 == 0 && R % 2 == 0, "units must be whole pixel pairs");
+  static_assert(NU % 32 == 0, "unit count must fill the 16-unit steps without padding");
+  struct Table { int off[NU]; };
+  static constexpr Table table() {
+    Table t{};
+    int u = 0;
+    for (int fy = 0; fy < F; ++fy) {
+      const bool full = fy < R || fy >= R + B;
+      for (int c = 0; c < F; c += 2)
+        if (full || c < R || c >= R + B) t.off[u++] = fy * Wd + c;
+    }
+    return t;
+  }
+  static constexpr Table kUnits = table();
+};
+
+// cand_distance_wave for a fixed geometry: the window offset of every unit
+// is a compile-time constant, so each lane's window reads are immediate
+// offsets from its own footprint origin and do not wait for the unit table.
+template <class G>
+static __device__ __forceinline__ void cand_distance_fixed(const MainLds& L, int base, int& d_out,
+                                                           int& n_out) {
+  int d = 0, nbad = 0;
+  const uint32_t* wb = L.winp + base;
+  // two 16-unit steps in flight: the reads of step k + 1 are issued before
+  // the arithmetic of step k; scheduling barriers keep the compiler from
+  // hoisting further reads (registers)
+  constexpr int kSteps = G::NU / 16;
+  uint32_t qv[2][16], pv[2][16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    qv[0][t] = L.qu[t].x;
+    pv[0][t] = wb[G::kUnits.off[t]];
+  }
+#pragma unroll
+  for (int k = 0; k < kSteps; ++k) {
+    if (k + 1 < kSteps) {
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        qv[(k + 1) & 1][t] = L.qu[16 * (k + 1) + t].x;
+        pv[(k + 1) & 1][t] = wb[G::kUnits.off[16 * (k + 1) + t]];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) pair_dist6(qv[k & 1][t], pv[k & 1][t], d, nbad);
+    // pin the sums here: otherwise the (pure) dot products sink past the
+    // loop and every masked difference stays live until the end
+    asm volatile("" : "+v"(d), "+v"(nbad));
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  d_out = d;
+  n_out = 2 * G::NU - nbad;
+}
+
+using Geom16 = FixedGeom<16, 4, 24>;
 
 }  // namespace skm

@@ -19,6 +19,9 @@ constexpr int kMaxB = 16;
 constexpr int kMaxRing = 8;
 constexpr int kMaxWin = 32;
 constexpr int kMaxWd = kMaxB + 2 * kMaxRing + 2 * kMaxWin;   // 96 window side
+// elements of slack before and after the int16 value plane: window loads of
+// the estimation kernels may touch up to 8 elements beyond either end
+constexpr int kValGuard = 8;
 
 // device error bits (RoundState::err)
 constexpr int kErrPartial = 1;       // lost pixel outside a whole in-frame cell
@@ -95,12 +98,12 @@ hipError_t launch_dist(const FrameArgs& a, const DevParams& p, int max_blocks,
                        hipStream_t s);
 hipError_t set_main_lds_limit(size_t bytes);
 // CNN gate (skm_cnn.hip)
-constexpr int kCnnParams = 19170;
+constexpr int kCnnParams = 20898;
 struct CnnBuffers {
   float *z1, *a1, *z2, *a2, *z3, *a3, *g, *y, *gy, *gz3, *gz2, *gz1;
 };
-constexpr size_t kCnnFloatsPerSample = 2 * 32 * 576 + 2 * 32 * 144 + 2 * 32 * 36 + 32 + 2 + 2 +
-                                       32 * 36 + 32 * 144 + 32 * 576;
+constexpr size_t kCnnFloatsPerSample = 2 * 32 * 144 + 2 * 32 * 36 + 2 * 32 * 9 + 32 + 2 + 2 +
+                                       32 * 9 + 32 * 36 + 32 * 144;
 hipError_t launch_cnn_inputs(const FrameArgs& a, const DevParams& p, uint16_t* out, int max_blocks,
                              hipStream_t s);
 hipError_t launch_cnn_gate(const FrameArgs& a, const DevParams& p, const float* wq, float tau1,

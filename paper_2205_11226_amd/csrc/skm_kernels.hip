@@ -174,6 +174,12 @@ __device__ void write_const_block(const FrameArgs& a, const DevParams& p, int i,
   }
 }
 
+// KP bounds the candidates of one thread's contiguous slice (ceil(MC / 256))
+// and KR the expansion radii; launch_main picks the smallest instance that
+// fits the geometry.
+// FG selects the distance loop of the 16 x 16 block, ring 4, radius 24
+// geometry (compile-time unit offsets); launch_main uses it only there.
+template <int KP, int KR, bool FG>
 __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams p, int dist_only) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ BlockShared sh;
@@ -257,7 +263,10 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
     const uint32_t cj = act ? E.cand[j] : 0u;
     const int base = cand_off(cj);
     int d, n;
-    cand_distance_wave(E.m, base, NU32, d, n);
+    if (FG)
+      cand_distance_fixed<Geom16>(E.m, base, d, n);
+    else
+      cand_distance_wave(E.m, base, NU32, d, n);
     if (!act) continue;
     const bool ok = n >= nmin;
     nc += ok;
@@ -272,7 +281,7 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
     E.dist[j] = ok ? (uint32_t)d : ~0u;
     if (ok) {
       const int b = cand_bucket(cj);
-      const double e = -((double)d / (double)n) / two_s2;
+      const double e = -(double)d / ((double)n * two_s2);
       atomicMin(&sh.bmax[b], (unsigned long long)__double_as_longlong(e));
       atomicAdd(&sh.bcnt[b], 1);
     }
@@ -293,35 +302,41 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
   if (lane == 0) { sh.red_i[wave][0] = nc; sh.red_i[wave][1] = ncomp; }
   __syncthreads();
 
-  // 5. log nu per expansion radius.  cm[b] is the running maximum of the
-  //    bucket maxima over buckets <= b.  Each candidate's term
-  //    exp(ell - cm[b_j]) goes to a register accumulator of its bucket; wave
-  //    sums in fixed order; lane b of wave 0 combines the buckets <= b.
-  if (wave == 0) {
-    double m = lane < p.nrad ? __longlong_as_double((long long)sh.bmax[lane]) : -INFINITY;
-#pragma unroll
-    for (int o = 1; o < kMaxRadii; o <<= 1) {
-      const double y = __shfl_up(m, o, 64);
-      if (lane >= o) m = fmax(m, y);
-    }
-    if (lane < p.nrad) sh.cm[lane] = m;
-  }
-  __syncthreads();
+  // 5. log nu per expansion radius.  bm[b] is the maximum log raw weight of
+  //    bucket b.  Thread t owns the contiguous slice [t per, t per + per) of
+  //    the candidates; each kept candidate's term exp(ell - bm[b_j]) stays in
+  //    registers for the weights and goes to a register accumulator of its
+  //    bucket; wave sums in fixed order; wave 0 combines the buckets <= b by
+  //    a prefix log-sum-exp across lanes.
+  const int per = (M + kThreads - 1) / kThreads;
+  const int js = min(M, tid * per);
+  double t_r[KP];
+  uint32_t c_r[KP];
   {
-    double acc[kMaxRadii];
+    double acc[KR];
 #pragma unroll
-    for (int b = 0; b < kMaxRadii; ++b) acc[b] = 0.0;
-    for (int j = tid; j < M; j += kThreads) {
-      const uint32_t d = E.dist[j];
-      if (d == ~0u) continue;
-      const uint32_t cj = E.cand[j];
-      const int bj = cand_bucket(cj);
-      const double t = exp(-((double)d / (double)cand_n(cj)) / two_s2 - sh.cm[bj]);
+    for (int b = 0; b < KR; ++b) acc[b] = 0.0;
 #pragma unroll
-      for (int b = 0; b < kMaxRadii; ++b) acc[b] += (b == bj) ? t : 0.0;
+    for (int k = 0; k < KP; ++k) {
+      const int j = js + k;
+      t_r[k] = -1.0;
+      c_r[k] = 0u;
+      if (k < per && j < M) {
+        const uint32_t d = E.dist[j];
+        const uint32_t cj = E.cand[j];
+        c_r[k] = cj;
+        if (d != ~0u) {
+          const int bj = cand_bucket(cj);
+          const double t = exp(-(double)d / ((double)cand_n(cj) * two_s2) -
+                               __longlong_as_double((long long)sh.bmax[bj]));
+          t_r[k] = t;
+#pragma unroll
+          for (int b = 0; b < KR; ++b) acc[b] += (b == bj) ? t : 0.0;
+        }
+      }
     }
 #pragma unroll
-    for (int b = 0; b < kMaxRadii; ++b) {
+    for (int b = 0; b < KR; ++b) {
       if (b < p.nrad) {
         const double s = wave_sum_full(acc[b]);
         if (lane == 0) sh.ps[wave][b] = s;
@@ -330,18 +345,26 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
   }
   __syncthreads();
   if (wave == 0) {
-    double cs = 0.0, lnu = -INFINITY;
-    int cc = 0;
+    // lane b: (m, cs) = (max, sum of exp(ell - max)) over buckets <= b, cc
+    // their candidate count.  Each combining step rescales the side with the
+    // smaller maximum; an empty side (m = -inf) contributes nothing.
     const int b = lane;
-    if (b < p.nrad) {
-      const double mb = sh.cm[b];
-      for (int bb = 0; bb <= b; ++bb) {
-        const double sb = ((sh.ps[0][bb] + sh.ps[1][bb]) + sh.ps[2][bb]) + sh.ps[3][bb];
-        if (sb > 0.0) cs += sb * exp(sh.cm[bb] - mb);
-        cc += sh.bcnt[bb];
+    const double bm = b < p.nrad ? __longlong_as_double((long long)sh.bmax[b]) : -INFINITY;
+    double m = bm;
+    double cs = b < p.nrad ? ((sh.ps[0][b] + sh.ps[1][b]) + sh.ps[2][b]) + sh.ps[3][b] : 0.0;
+    int cc = b < p.nrad ? sh.bcnt[b] : 0;
+    for (int o = 1; o < p.nrad; o <<= 1) {
+      const double m2 = __shfl_up(m, o, 64), s2 = __shfl_up(cs, o, 64);
+      const int c2 = __shfl_up(cc, o, 64);
+      if (lane >= o) {
+        const double mx = fmax(m, m2), mn = fmin(m, m2);
+        const double f = mn == mx ? 1.0 : (mn == -INFINITY ? 0.0 : exp(mn - mx));
+        cs = m >= m2 ? cs + s2 * f : cs * f + s2;
+        m = mx;
+        cc += c2;
       }
-      if (cc > 0) lnu = mb + log(cs);
     }
+    const double lnu = (b < p.nrad && cc > 0) ? m + log(cs) : -INFINITY;
     const bool acc_ok = b < p.nrad && cc > 0 && lnu >= p.log_tnu;
     const uint64_t accm = __ballot(acc_ok);
     const int ncand = sh.red_i[0][0] + sh.red_i[1][0] + sh.red_i[2][0] + sh.red_i[3][0];
@@ -363,6 +386,11 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
     }
     const double lnu_r = __shfl(lnu, ridx, 64);
     const double cs_r = __shfl(cs, ridx, 64);
+    const double m_r = __shfl(m, ridx, 64);
+    // weight of a candidate of bucket b <= ridx: term * exp(bm[b] - max over
+    // buckets <= ridx); sums (cs_r) are relative to the same maximum
+    if (lane < p.nrad)
+      sh.fsc[lane] = (lane <= ridx && bm != -INFINITY) ? (bm == m_r ? 1.0 : exp(bm - m_r)) : 0.0;
     if (lane == 0) {
       sh.layer = layer; sh.radius_idx = ridx; sh.flags = flags;
       sh.n_cand = ncand; sh.n_complete = ncom;
@@ -392,37 +420,30 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
     return;
   }
 
-  // 6. IDL weights (eq. slpe): exp(ell - cm[ridx]) in FP64, rounded to FP32,
-  //    for the candidates inside the accepted radius, compacted in raster
-  //    order into (cand, dist) = (window offset, weight bits).  Thread t owns
-  //    a contiguous slice, read into registers before the scan's barriers.
+  // 6. IDL weights (eq. slpe): term * fsc[b] = exp(ell - ell_max) in FP64,
+  //    ell_max over the buckets <= ridx, rounded to FP32, for the candidates inside the
+  //    accepted radius, compacted in raster order into (cand, dist) =
+  //    (window offset, weight bits) after the scan's barriers.
   const int ridx = sh.radius_idx;
   {
-    const double mstar = sh.cm[ridx];
-    const int per = (M + kThreads - 1) / kThreads;
-    const int j0 = min(M, tid * per);
-    uint32_t o_r[kMaxPer], w_r[kMaxPer];
+    uint32_t o_r[KP], w_r[KP];
     int cnt = 0;
 #pragma unroll
-    for (int k = 0; k < kMaxPer; ++k) {
-      const int j = j0 + k;
+    for (int k = 0; k < KP; ++k) {
       o_r[k] = 0u; w_r[k] = 0u;
-      if (k < per && j < M) {
-        const uint32_t d = E.dist[j];
-        const uint32_t cj = E.cand[j];
-        if (d != ~0u && cand_bucket(cj) <= ridx) {
-          // a weight that underflows FP32 adds nothing and is left out
-          const float w = (float)exp(-((double)d / (double)cand_n(cj)) / two_s2 - mstar);
-          o_r[k] = (uint32_t)cand_off(cj);
-          w_r[k] = __float_as_uint(w);
-          cnt += w_r[k] != 0u;
-        }
+      const int bj = cand_bucket(c_r[k]);
+      if (t_r[k] >= 0.0 && bj <= ridx) {
+        // a weight that underflows FP32 adds nothing and is left out
+        const float w = (float)(t_r[k] * sh.fsc[bj]);
+        o_r[k] = (uint32_t)cand_off(c_r[k]);
+        w_r[k] = __float_as_uint(w);
+        cnt += w_r[k] != 0u;
       }
     }
     int tot = 0;
     int pos = block_excl_scan(cnt, sh.scan, &tot);     // barriers inside
 #pragma unroll
-    for (int k = 0; k < kMaxPer; ++k) {
+    for (int k = 0; k < KP; ++k) {
       if (w_r[k] != 0u) { E.sel[pos] = make_uint2(o_r[k], w_r[k]); ++pos; }
     }
     if (tid < ((tot + 7) & ~7) - tot) E.sel[tot + tid] = make_uint2(0u, 0u);
@@ -637,7 +658,20 @@ static hipError_t launch_main(const FrameArgs& a, const DevParams& p, int max_bl
                               int dist_only, hipStream_t s) {
   const size_t lds = main_lds_bytes(p);
   const int grid = ((max_blocks < 1 ? 1 : max_blocks) + 7) / 8 * 8;   // xcd_block cover
-  hipLaunchKernelGGL(k_round_main, dim3(grid), dim3(kThreads), lds, s, a, p, dist_only);
+  const int per = (p.MC + kThreads - 1) / kThreads;
+  const bool fg = p.B == Geom16::kB && p.r == Geom16::kR && p.W == Geom16::kW;
+  if (fg && per <= 6 && p.nrad <= 8)
+    hipLaunchKernelGGL((k_round_main<6, 8, true>), dim3(grid), dim3(kThreads), lds, s, a, p,
+                       dist_only);
+  else if (per <= 6 && p.nrad <= 8)
+    hipLaunchKernelGGL((k_round_main<6, 8, false>), dim3(grid), dim3(kThreads), lds, s, a, p,
+                       dist_only);
+  else if (per <= 9 && p.nrad <= 8)
+    hipLaunchKernelGGL((k_round_main<9, 8, false>), dim3(grid), dim3(kThreads), lds, s, a, p,
+                       dist_only);
+  else
+    hipLaunchKernelGGL((k_round_main<kMaxPer, kMaxRadii, false>), dim3(grid), dim3(kThreads), lds,
+                       s, a, p, dist_only);
   return hipGetLastError();
 }
 
@@ -672,8 +706,14 @@ hipError_t launch_fill(const FrameArgs& a, const DevParams& p, int max_blocks, h
 }
 
 hipError_t set_main_lds_limit(size_t bytes) {
-  return hipFuncSetAttribute((const void*)k_round_main,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const void* fns[4] = {(const void*)k_round_main<6, 8, true>, (const void*)k_round_main<6, 8, false>,
+                        (const void*)k_round_main<9, 8, false>,
+                        (const void*)k_round_main<kMaxPer, kMaxRadii, false>};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace skm

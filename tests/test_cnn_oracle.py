@@ -53,7 +53,8 @@ def test_forward_matches_torch_network():
     x, _ = _rand(4)
     ours = cnn.forward(p, x, quant=False)
     t = {k: torch.from_numpy(v) for k, v in p.items()}
-    h = torch.from_numpy(x)
+    # space to depth by torch's own pixel_unshuffle (channel c*4 + dy*2 + dx)
+    h = torch.nn.functional.pixel_unshuffle(torch.from_numpy(x), 2)
     for i in (1, 2, 3):
         h = torch.relu(torch.nn.functional.conv2d(h, t[f"w{i}"], t[f"b{i}"], stride=2, padding=1))
     ref = (h.mean(dim=(2, 3)) @ t["wh"].T + t["bh"]).numpy()
@@ -79,4 +80,12 @@ def test_input_map_centres_the_block_and_hides_lost_pixels():
     x8 = cnn.block_input(u, np.ones((64, 64), bool), 2, 3, 8)   # origin (y, x) = (-4, 4)
     assert x8[1, 3, 0] == 1 and x8[0, 3, 0] == 0                # row -1: outside
     assert x8[1, 4, 0] == 0 and x8[0, 4, 0] == (u[0, 4] - 128) / 128.0
-    assert cnn.N_PARAMS == 19170
+    assert cnn.N_PARAMS == 20898
+
+
+def test_space_to_depth_is_a_lossless_rearrangement():
+    x, _ = _rand(11, n=2)
+    s = cnn.space_to_depth(x)
+    assert s.shape == (2, 8, 24, 24)
+    np.testing.assert_array_equal(np.sort(s.ravel()), np.sort(x.ravel()))
+    assert s[1, 4 * 1 + 2 * 1 + 0, 5, 7] == x[1, 1, 11, 14]
