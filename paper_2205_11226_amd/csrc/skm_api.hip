@@ -71,6 +71,7 @@ struct skm_ctx {
   skm_block_info* d_info = nullptr; size_t cap_info = 0;
   // learned gate
   float* d_cnn = nullptr;       // [5][kCnnParams]: master, bf16 copy, Adam m, Adam v, gradient
+  uint4* d_gate_pack = nullptr; // register images of the bf16 copy for the inference kernels
   float* d_cnn_loss = nullptr;
   bool cnn_loaded = false;
   int cnn_step = 0;
@@ -159,6 +160,13 @@ skm_status make_params(const skm_params* in, int width, int height, int stride, 
   }
   p->radii[n++] = p->W;
   p->nrad = n;
+  p->bucket_lut[0] = p->bucket_lut[1] = p->bucket_lut[2] = 0ull;
+  for (int rho = 0; rho <= p->W; ++rho) {
+    int b = n - 1;
+    for (int ri = 0; ri < n; ++ri)
+      if (p->radii[ri] >= rho) { b = ri; break; }
+    p->bucket_lut[rho >> 4] |= (unsigned long long)b << (4 * (rho & 15));
+  }
   p->min_pct = in->min_overlap_pct;
   p->min_hql = in->min_hql_cands;
   p->mode = in->mode;
@@ -306,7 +314,8 @@ skm_status launch_round(skm_ctx* c, FrameSlot* f, const DevParams& p, FrameArgs&
   const int nb = p.gh * p.gw;
   SKM_HIP(launch_prep(a, p, nb, s), "prep kernel");
   if (p.cnn_active)
-    SKM_HIP(launch_cnn_gate(a, p, c->d_cnn + kCnnParams, c->tau1, c->tau2, c->gate_grid, s),
+    SKM_HIP(launch_cnn_gate(a, p, c->d_gate_pack, c->d_cnn + kCnnParams, c->tau1, c->tau2,
+                            c->gate_grid, s),
             "gate kernel");
   if (c->prof) {
     while ((int)f->ev.size() < 2 * (k + 1)) {
@@ -496,6 +505,7 @@ void skm_destroy(skm_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (FrameSlot* f : c->slots) slot_destroy(f);
   (void)hipFree(c->d_cnn);
+  (void)hipFree(c->d_gate_pack);
   (void)hipFree(c->d_cnn_loss);
   (void)hipFree(c->d_cnn_buf);
   (void)hipFree(c->d_frame);
@@ -761,6 +771,7 @@ static skm_status cnn_params_alloc(skm_ctx* c) {
   if (c->d_cnn) return SKM_OK;
   SKM_HIP(hipMalloc((void**)&c->d_cnn, sizeof(float) * 5 * kCnnParams), "gate parameters");
   SKM_HIP(hipMemset(c->d_cnn, 0, sizeof(float) * 5 * kCnnParams), "gate parameters");
+  SKM_HIP(hipMalloc((void**)&c->d_gate_pack, cnn_pack_bytes()), "packed gate weights");
   SKM_HIP(hipMalloc((void**)&c->d_cnn_loss, sizeof(float) * 4), "gate loss");
   return SKM_OK;
 }
@@ -785,6 +796,7 @@ skm_status skm_cnn_init(skm_ctx* c, uint64_t seed) {
   SKM_HIP(hipMemsetAsync(c->d_cnn + 2 * kCnnParams, 0, sizeof(float) * 2 * kCnnParams, c->stream),
           "Adam state");
   SKM_HIP(cnn_init(c->d_cnn, c->d_cnn + kCnnParams, seed, c->stream), "gate init");
+  SKM_HIP(cnn_pack(c->d_cnn + kCnnParams, c->d_gate_pack, c->stream), "gate weight packing");
   SKM_HIP(hipStreamSynchronize(c->stream), "stream synchronize");
   c->cnn_step = 0;
   c->cnn_loaded = true;
@@ -802,6 +814,7 @@ skm_status skm_cnn_set_weights(skm_ctx* c, const float* host, int32_t n) {
   SKM_HIP(hipMemsetAsync(c->d_cnn + 2 * kCnnParams, 0, sizeof(float) * 2 * kCnnParams, c->stream),
           "Adam state");
   SKM_HIP(cnn_quantize(c->d_cnn, c->d_cnn + kCnnParams, c->stream), "quantize");
+  SKM_HIP(cnn_pack(c->d_cnn + kCnnParams, c->d_gate_pack, c->stream), "gate weight packing");
   SKM_HIP(hipStreamSynchronize(c->stream), "stream synchronize");
   c->cnn_step = 0;
   c->cnn_loaded = true;
@@ -901,7 +914,8 @@ skm_status skm_cnn_forward(skm_ctx* c, const uint16_t* d_inputs, int32_t n, floa
     c->gate_lds_set = true;
   }
   hipStream_t st = (hipStream_t)hip_stream;
-  SKM_HIP(cnn_infer(d_inputs, n, c->d_cnn + kCnnParams, d_out, st), "gate inference");
+  SKM_HIP(cnn_infer(d_inputs, n, c->d_gate_pack, c->d_cnn + kCnnParams, d_out, st),
+          "gate inference");
   SKM_HIP(hipStreamSynchronize(st), "stream synchronize");
   return SKM_OK;
 }
@@ -946,6 +960,7 @@ skm_status skm_cnn_train_step(skm_ctx* c, const uint16_t* d_inputs, const float*
   ++c->cnn_step;
   SKM_HIP(cnn_adam(c->d_cnn, c->d_cnn + 4 * kCnnParams, c->d_cnn + 2 * kCnnParams,
                    c->d_cnn + 3 * kCnnParams, c->d_cnn + kCnnParams, lr, c->cnn_step, st), "Adam");
+  SKM_HIP(cnn_pack(c->d_cnn + kCnnParams, c->d_gate_pack, st), "gate weight packing");
   if (loss) SKM_HIP(hipStreamSynchronize(st), "stream synchronize");
   return SKM_OK;
 }

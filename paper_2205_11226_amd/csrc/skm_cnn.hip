@@ -361,8 +361,15 @@ static __device__ __forceinline__ bf16x8 weight_frag(const float* w, int cin, in
   return __builtin_bit_cast(bf16x8, (u32x4){u[0], u[1], u[2], u[3]});
 }
 
-static __device__ __forceinline__ GateWeights load_gate_weights(const float* wq) {
-  const int lane = lane_id(), wave = wave_id();
+// The register image of one wave's weights, per lane: 17 bf16x8 MFMA
+// fragments (layer 1: 3, layer 2: 9, layer 3: 5), then b1, b2 and (b3, wh0,
+// wh1, 0) as float4.  Packed once per weight update (k_gate_pack) into
+// [role = wave][item][lane] order, so that a workgroup loads its weights
+// with 16-byte coalesced reads.
+constexpr int kPackItems = 3 + 9 + kL3Taps + 3;
+
+static __device__ __forceinline__ GateWeights gate_weights_from(const float* wq, int wave,
+                                                                int lane) {
   const int row = lane & 15, g = lane >> 4, mt = wave & 1;
   const int n = mt * 16 + row;
   const bf16x8 zero = __builtin_bit_cast(bf16x8, (u32x4){0u, 0u, 0u, 0u});
@@ -388,6 +395,51 @@ static __device__ __forceinline__ GateWeights load_gate_weights(const float* wq)
   W.b3 = wq[kOffB3 + c];
   W.wh0 = wq[kOffWh + c];
   W.wh1 = wq[kOffWh + kC + c];
+  W.bh0 = wq[kOffBh];
+  W.bh1 = wq[kOffBh + 1];
+  return W;
+}
+
+// one workgroup per role (wave index of the gate kernels), one thread per lane
+__global__ __launch_bounds__(64) void k_gate_pack(const float* wq, uint4* pk) {
+  const int role = blockIdx.x, lane = threadIdx.x;
+  const GateWeights W = gate_weights_from(wq, role, lane);
+  uint4* o = pk + (size_t)role * kPackItems * 64 + lane;
+  int f = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) o[64 * f++] = __builtin_bit_cast(uint4, W.w1[k]);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) o[64 * f++] = __builtin_bit_cast(uint4, W.w2[k]);
+#pragma unroll
+  for (int k = 0; k < kL3Taps; ++k) o[64 * f++] = __builtin_bit_cast(uint4, W.w3[k]);
+  o[64 * f++] = make_uint4(__float_as_uint(W.b1[0]), __float_as_uint(W.b1[1]),
+                           __float_as_uint(W.b1[2]), __float_as_uint(W.b1[3]));
+  o[64 * f++] = make_uint4(__float_as_uint(W.b2[0]), __float_as_uint(W.b2[1]),
+                           __float_as_uint(W.b2[2]), __float_as_uint(W.b2[3]));
+  o[64 * f++] = make_uint4(__float_as_uint(W.b3), __float_as_uint(W.wh0), __float_as_uint(W.wh1),
+                           0u);
+}
+
+static __device__ __forceinline__ GateWeights load_gate_weights(const uint4* pk, const float* wq) {
+  const int lane = lane_id(), wave = wave_id();
+  const uint4* src = pk + (size_t)wave * kPackItems * 64 + lane;
+  uint4 v[kPackItems];
+#pragma unroll
+  for (int f = 0; f < kPackItems; ++f) v[f] = src[64 * f];
+  GateWeights W;
+  int f = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) W.w1[k] = __builtin_bit_cast(bf16x8, v[f++]);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) W.w2[k] = __builtin_bit_cast(bf16x8, v[f++]);
+#pragma unroll
+  for (int k = 0; k < kL3Taps; ++k) W.w3[k] = __builtin_bit_cast(bf16x8, v[f++]);
+  const uint4 b1 = v[f++], b2 = v[f++], hb = v[f++];
+  W.b1[0] = __uint_as_float(b1.x); W.b1[1] = __uint_as_float(b1.y);
+  W.b1[2] = __uint_as_float(b1.z); W.b1[3] = __uint_as_float(b1.w);
+  W.b2[0] = __uint_as_float(b2.x); W.b2[1] = __uint_as_float(b2.y);
+  W.b2[2] = __uint_as_float(b2.z); W.b2[3] = __uint_as_float(b2.w);
+  W.b3 = __uint_as_float(hb.x); W.wh0 = __uint_as_float(hb.y); W.wh1 = __uint_as_float(hb.z);
   W.bh0 = wq[kOffBh];
   W.bh1 = wq[kOffBh + 1];
   return W;
@@ -532,8 +584,8 @@ static __device__ __forceinline__ u32x4 s2d_pixel(const int* v) {
 
 // In-pipeline gate: one pass over the blocks eligible in this round; the
 // layer choice goes to gate[i] and the predictions to gate_pred.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_gate(FrameArgs a, DevParams p, const float* wq,
-                                                       float tau1, float tau2) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_gate(
+    FrameArgs a, DevParams p, const uint4* pk, const float* wq, float tau1, float tau2) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int red[kThreads / 64][2];
   GateLds& G = *reinterpret_cast<GateLds*>(lds_raw);
@@ -552,7 +604,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
   __syncthreads();
   nq = 0; maxm0 = 0;
   for (int w = 0; w < kThreads / 64; ++w) { nq += red[w][0]; maxm0 = max(maxm0, red[w][1]); }
-  const GateWeights W = load_gate_weights(wq);
+  const GateWeights W = load_gate_weights(pk, wq);
   const int tid = threadIdx.x;
   // XCD x (workgroups x, x + 8, ...) takes a contiguous range of blocks, so
   // neighbouring windows share its L2
@@ -616,12 +668,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
 }
 
 // Batched inference on prepared inputs x (bf16 bits [n][8][24][24]).
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_infer(const uint16_t* x, int n, const float* wq,
-                                                        float* y) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_infer(
+    const uint16_t* x, int n, const uint4* pk, const float* wq, float* y) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   GateLds& G = *reinterpret_cast<GateLds*>(lds_raw);
   gate_clear_padding(G);
-  const GateWeights W = load_gate_weights(wq);
+  const GateWeights W = load_gate_weights(pk, wq);
   const int tid = threadIdx.x;
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const uint16_t* xi = x + (size_t)i * kC0 * kS * kS;
@@ -660,21 +712,29 @@ hipError_t launch_cnn_inputs(const FrameArgs& a, const DevParams& p, uint16_t* o
 constexpr int kGateGrid = 4096;
 constexpr int kInferGrid = 768;
 
-hipError_t launch_cnn_gate(const FrameArgs& a, const DevParams& p, const float* wq, float tau1,
-                           float tau2, int max_blocks, hipStream_t s) {
+hipError_t launch_cnn_gate(const FrameArgs& a, const DevParams& p, const uint4* pk,
+                           const float* wq, float tau1, float tau2, int max_blocks, hipStream_t s) {
   // a multiple of 8 workgroups (the block ranges follow the XCD order)
   int grid = max_blocks < 1 ? 1 : (max_blocks > kGateGrid ? kGateGrid : max_blocks);
   grid = (grid + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_cnn_gate, dim3(grid), dim3(kThreads), sizeof(GateLds), s, a, p, wq, tau1,
-                     tau2);
+  hipLaunchKernelGGL(k_cnn_gate, dim3(grid), dim3(kThreads), sizeof(GateLds), s, a, p, pk, wq,
+                     tau1, tau2);
   return hipGetLastError();
 }
 
-hipError_t cnn_infer(const uint16_t* x, int n, const float* wq, float* y, hipStream_t s) {
+hipError_t cnn_infer(const uint16_t* x, int n, const uint4* pk, const float* wq, float* y,
+                     hipStream_t s) {
   hipLaunchKernelGGL(k_cnn_infer, dim3(n > kInferGrid ? kInferGrid : n), dim3(kThreads),
-                     sizeof(GateLds), s, x, n, wq, y);
+                     sizeof(GateLds), s, x, n, pk, wq, y);
   return hipGetLastError();
 }
+
+hipError_t cnn_pack(const float* wq, uint4* pk, hipStream_t s) {
+  hipLaunchKernelGGL(k_gate_pack, dim3(kThreads / 64), dim3(64), 0, s, wq, pk);
+  return hipGetLastError();
+}
+
+size_t cnn_pack_bytes() { return sizeof(uint4) * (kThreads / 64) * kPackItems * 64; }
 
 size_t cnn_gate_lds_bytes() { return sizeof(GateLds); }
 

@@ -23,15 +23,6 @@ static __device__ __forceinline__ int xcd_block(int wg, int n) {
 
 static __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
-// n / d for 0 <= n < 2^22 and 1 <= d < 2^10, with inv_d = 1.0f / d: a float
-// estimate (within one of the quotient) and one exact integer correction,
-// instead of the long integer division sequence
-static __device__ __forceinline__ int quot_small(int n, int d, float inv_d) {
-  int q = (int)(((float)n + 0.5f) * inv_d);
-  q -= q * d > n ? 1 : 0;
-  q += (q + 1) * d <= n ? 1 : 0;
-  return q;
-}
 static __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
 template <typename T>
@@ -260,12 +251,11 @@ struct BlockShared {
   double lnu, den;
   int red_i[kThreads / 64][4];
   int scan[kThreads / 64];
-  int rowbase[2 * kMaxWin + 1];
   unsigned long long bmax[kMaxRadii];
   int bcnt[kMaxRadii];
   double fsc[kMaxRadii];
   double ps[kThreads / 64][kMaxRadii];
-  int bucket_of[kMaxWin + 1];
+  int rowbase[2 * kMaxWin + 1];
 };
 
 typedef short short2v __attribute__((ext_vector_type(2)));
@@ -306,8 +296,7 @@ static __device__ __forceinline__ void pair_dist(uint32_t q, uint32_t pp, int& d
 // ---------------------------------------------------------------- phases
 // All functions below are called by every thread of the workgroup.
 
-// Fixed tables, once per workgroup.  bucket_of: radius -> first schedule
-// radius >= it.  utab: the ring pixels of each footprint row taken left to
+// Fixed tables, once per workgroup.  utab: the ring pixels of each footprint row taken left to
 // right in pairs of horizontal neighbours (a lone pixel gets a dummy
 // partner); lane fy owns footprint row fy, a wave scan orders the rows.
 static __device__ __forceinline__ void phase_tables(const DevParams& p, const MainLds& L,
@@ -315,11 +304,6 @@ static __device__ __forceinline__ void phase_tables(const DevParams& p, const Ma
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   const int B = p.B, r = p.r, W = p.W, Wd = p.Wd, F = p.F;
   for (int k = tid; k < 2 * Wd; k += kThreads) L.rowbits[k] = 0ull;
-  if (tid <= W) {
-    int b = p.nrad - 1;
-    for (int ri = 0; ri < p.nrad; ++ri) if (p.radii[ri] >= tid) { b = ri; break; }
-    sh.bucket_of[tid] = b;
-  }
   if (wave == 0) {
     const int fy = lane;
     const bool full = fy < r || fy >= r + B;
@@ -358,69 +342,119 @@ static __device__ __forceinline__ void phase_tables(const DevParams& p, const Ma
 // or ends at most 5 after it, and segments entirely outside (masked anyway)
 // are clamped into the same range.  Each lane also ORs the availability bits
 // of its four pixels into the row's 128-bit mask (rowbits, cleared by
-// phase_tables).  Ends with a barrier.
-static __device__ __forceinline__ void phase_stage(const FrameArgs& a, const DevParams& p,
-                                                   const MainLds& L, int ox, int oy) {
-  const int lane = lane_id(), wave = wave_id();
-  const int Wd = p.Wd;
-  const int S = (Wd + 3) >> 2;
-  const int R = 64 / S;
-  const int g = lane / S, c0 = 4 * (lane - g * S);
-  const int npx = p.width * p.height;
-  const int rstep = R * (kThreads / 64);
-  constexpr int kPass = 6;
-  const int gx = ox + c0;
+// phase_tables).  stage_issue starts the loads, stage_finish writes LDS and
+// ends with a barrier; phase_stage does both.
+constexpr int kStagePass = 6;     // window rows a wave loads per lane row group at once
+
+// The first kStagePass passes of a lane's window loads, held in registers so
+// that the kernel can issue them before unrelated latency-bound work.
+struct StageRegs {
+  uint32_t w0[kStagePass], w1[kStagePass], w2[kStagePass], sh[kStagePass];
+};
+
+struct StageGeom {
+  int S, R, g, c0, gx, rstep, npx;
+  uint32_t colbad;
+};
+
+static __device__ __forceinline__ StageGeom stage_geom(const DevParams& p, int ox) {
+  StageGeom G;
+  const int lane = lane_id();
+  G.S = (p.Wd + 3) >> 2;
+  G.R = 64 / G.S;
+  G.g = lane / G.S;
+  G.c0 = 4 * (lane - G.g * G.S);
+  G.gx = ox + G.c0;
+  G.rstep = G.R * (kThreads / 64);
+  G.npx = p.width * p.height;
   // unknown marks of the five values from the column tests alone (bit q)
-  uint32_t colbad = 0;
+  G.colbad = 0;
 #pragma unroll
   for (int q = 0; q < 5; ++q)
-    colbad |= (uint32_t)((unsigned)(gx + q) >= (unsigned)p.width || c0 + q >= Wd) << q;
-  for (int wy0 = wave * R + g; wy0 < Wd + g; wy0 += kPass * rstep) {
-    uint32_t w0[kPass], w1[kPass], w2[kPass];
-    uint32_t shv[kPass];
+    G.colbad |= (uint32_t)((unsigned)(G.gx + q) >= (unsigned)p.width || G.c0 + q >= p.Wd) << q;
+  return G;
+}
+
+static __device__ __forceinline__ void stage_load(const FrameArgs& a, const DevParams& p,
+                                                  const StageGeom& G, int oy, int wy0,
+                                                  StageRegs& S) {
 #pragma unroll
-    for (int t = 0; t < kPass; ++t) {
-      const int wy = wy0 + t * rstep;
-      const int gy = oy + wy;
-      const int cy = min(max(gy, 0), p.height - 1);
-      const int e = cy * p.width + gx;
-      const int e2 = min(max(e & ~1, -kValGuard), npx + 2);
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(a.val + e2);
-      shv[t] = (uint32_t)(e & 1) << 4;
-      w0[t] = src[0]; w1[t] = src[1]; w2[t] = src[2];
-    }
+  for (int t = 0; t < kStagePass; ++t) {
+    const int wy = wy0 + t * G.rstep;
+    const int gy = oy + wy;
+    const int cy = min(max(gy, 0), p.height - 1);
+    const int e = cy * p.width + G.gx;
+    const int e2 = min(max(e & ~1, -kValGuard), G.npx + 2);
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.val + e2);
+    S.sh[t] = (uint32_t)(e & 1) << 4;
+    S.w0[t] = src[0]; S.w1[t] = src[1]; S.w2[t] = src[2];
+  }
+}
+
+static __device__ __forceinline__ void stage_store(const DevParams& p, const MainLds& L,
+                                                   const StageGeom& G, int oy, int wy0,
+                                                   const StageRegs& S) {
+  const int Wd = p.Wd;
 #pragma unroll
-    for (int t = 0; t < kPass; ++t) {
-      const int wy = wy0 + t * rstep;
-      if (g >= R || wy >= Wd) continue;
-      const int gy = oy + wy;
-      const uint32_t bad = (gy >= 0 && gy < p.height) ? colbad : 0x1fu;
-      // x0 = (p0, p1), x1 = (p2, p3), low half of x2 = p4
-      const uint32_t x0 = __builtin_amdgcn_alignbit(w1[t], w0[t], shv[t]);
-      const uint32_t x1 = __builtin_amdgcn_alignbit(w2[t], w1[t], shv[t]);
-      const uint32_t x2 = w2[t] >> shv[t];
-      uint32_t pr[4] = {x0, __builtin_amdgcn_alignbit(x1, x0, 16), x1,
-                        __builtin_amdgcn_alignbit(x2, x1, 16)};
+  for (int t = 0; t < kStagePass; ++t) {
+    const int wy = wy0 + t * G.rstep;
+    if (G.g >= G.R || wy >= Wd) continue;
+    const int gy = oy + wy;
+    const uint32_t bad = (gy >= 0 && gy < p.height) ? G.colbad : 0x1fu;
+    // x0 = (p0, p1), x1 = (p2, p3), low half of x2 = p4
+    const uint32_t x0 = __builtin_amdgcn_alignbit(S.w1[t], S.w0[t], S.sh[t]);
+    const uint32_t x1 = __builtin_amdgcn_alignbit(S.w2[t], S.w1[t], S.sh[t]);
+    const uint32_t x2 = S.w2[t] >> S.sh[t];
+    uint32_t pr[4] = {x0, __builtin_amdgcn_alignbit(x1, x0, 16), x1,
+                      __builtin_amdgcn_alignbit(x2, x1, 16)};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      pr[q] |= (((bad >> q) & 1u) ? 0x0000ffffu : 0u) | (((bad >> (q + 1)) & 1u) ? 0xffff0000u : 0u);
+    // availability bits of the row: this segment's nibble (rows cleared by
+    // phase_tables)
+    uint32_t nib = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) nib |= (uint32_t)((pr[q] & 0x8000u) == 0u) << q;
+    if (nib)
+      atomicOr(reinterpret_cast<uint32_t*>(L.rowbits) + 4 * wy + (G.c0 >> 5), nib << (G.c0 & 31));
+    uint32_t* dst = L.winp + wy * Wd + G.c0;
+    if ((Wd & 3) == 0) {
+      *reinterpret_cast<uint4*>(dst) = make_uint4(pr[0], pr[1], pr[2], pr[3]);
+    } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        pr[q] |= (((bad >> q) & 1u) ? 0x0000ffffu : 0u) | (((bad >> (q + 1)) & 1u) ? 0xffff0000u : 0u);
-      // availability bits of the row: this segment's nibble (rows cleared
-      // by phase_tables)
-      uint32_t nib = 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) nib |= (uint32_t)((pr[q] & 0x8000u) == 0u) << q;
-      if (nib) atomicOr(reinterpret_cast<uint32_t*>(L.rowbits) + 4 * wy + (c0 >> 5), nib << (c0 & 31));
-      uint32_t* dst = L.winp + wy * Wd + c0;
-      if ((Wd & 3) == 0) {
-        *reinterpret_cast<uint4*>(dst) = make_uint4(pr[0], pr[1], pr[2], pr[3]);
-      } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (c0 + q < Wd) dst[q] = pr[q];
-      }
+        if (G.c0 + q < Wd) dst[q] = pr[q];
     }
   }
+}
+
+// Loads of the first passes (issued early by the caller) are in S; the rest
+// of the window, if any, is loaded and stored here.  Ends with a barrier.
+static __device__ __forceinline__ void stage_finish(const FrameArgs& a, const DevParams& p,
+                                                    const MainLds& L, const StageGeom& G, int oy,
+                                                    const StageRegs& S) {
+  const int wave = wave_id();
+  int wy0 = wave * G.R + G.g;
+  stage_store(p, L, G, oy, wy0, S);
+  for (wy0 += kStagePass * G.rstep; wy0 < p.Wd + G.g; wy0 += kStagePass * G.rstep) {
+    StageRegs T;
+    stage_load(a, p, G, oy, wy0, T);
+    stage_store(p, L, G, oy, wy0, T);
+  }
   __syncthreads();
+}
+
+static __device__ __forceinline__ void stage_issue(const FrameArgs& a, const DevParams& p,
+                                                   const StageGeom& G, int oy, StageRegs& S) {
+  stage_load(a, p, G, oy, wave_id() * G.R + G.g, S);
+}
+
+static __device__ __forceinline__ void phase_stage(const FrameArgs& a, const DevParams& p,
+                                                   const MainLds& L, int ox, int oy) {
+  const StageGeom G = stage_geom(p, ox);
+  StageRegs S;
+  stage_issue(a, p, G, oy, S);
+  stage_finish(a, p, L, G, oy, S);
 }
 
 struct RingStats { int n0, phi, sum; };
@@ -483,10 +517,10 @@ static __device__ __forceinline__ int phase_candidates(const DevParams& p, const
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   const int B = p.B, r = p.r, W = p.W, Wd = p.Wd, D2 = 2 * W + 1, nw = kThreads / 64;
   int rowcnt = 0;
+  uint64_t mlo = 0ull, mhi = 0ull;
   if (tid < D2) {
     uint64_t lo = ~0ull, hi = ~0ull;
     for (int k = 0; k < B; ++k) { lo &= L.runbits[2 * (r + tid + k)]; hi &= L.runbits[2 * (r + tid + k) + 1]; }
-    uint64_t mlo, mhi;
     shr128(lo, hi, r, mlo, mhi);
     if (D2 < 64) { mlo &= (1ull << D2) - 1ull; mhi = 0; }
     else { mhi &= (D2 >= 128) ? ~0ull : ((1ull << (D2 - 64)) - 1ull); }
@@ -494,40 +528,43 @@ static __device__ __forceinline__ int phase_candidates(const DevParams& p, const
     L.cmask[2 * tid] = mlo; L.cmask[2 * tid + 1] = mhi;
     rowcnt = __popcll(mlo) + __popcll(mhi);
   }
-  {
-    int tot = 0;
-    const int rb = block_excl_scan(rowcnt, sh.scan, &tot);   // barriers inside
-    if (tid < D2) sh.rowbase[tid] = rb;
-    if (tid == 0) sh.M = tot;
-  }
+  int tot = 0;
+  const int rb = block_excl_scan(rowcnt, sh.scan, &tot);   // barriers inside
+  if (tid < D2) sh.rowbase[tid] = rb;
+  if (tid == 0) sh.M = tot;
   if (tid < p.nrad) { sh.bmax[tid] = 0xFFF0000000000000ull; sh.bcnt[tid] = 0; }
   __syncthreads();
-  // thread t takes the displacements t, t + 256, ... (raster order), four at
-  // a time so that their LDS reads are in flight together
-  const int nd = D2 * D2;
-  const float inv_d2 = 1.0f / (float)D2;
-  constexpr int kU = 4;
-  for (int pos0 = tid; pos0 < nd; pos0 += kU * kThreads) {
-    uint64_t w[kU], below[kU];
-    int base[kU];
+  // wave w writes displacement rows w, w + 4, ..., lanes along the columns;
+  // the masks and offsets of kAhead rows are read before any row is written,
+  // and the expansion bucket comes from a 4-bit-per-radius table in the
+  // parameters
+  constexpr int kAhead = 5;
+  const unsigned long long lut0 = p.bucket_lut[0], lut1 = p.bucket_lut[1], lut2 = p.bucket_lut[2];
+  for (int dy0 = wave; dy0 < D2; dy0 += kAhead * nw) {
+    uint64_t ml[kAhead], mh[kAhead];
+    int rbv[kAhead];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int pos = min(pos0 + u * kThreads, nd - 1);
-      const int dyi = quot_small(pos, D2, inv_d2), dxi = pos - dyi * D2;
-      const uint64_t mlo = L.cmask[2 * dyi];
-      w[u] = dxi < 64 ? mlo : L.cmask[2 * dyi + 1];
-      below[u] = dxi < 64 ? 0ull : mlo;
-      base[u] = sh.rowbase[dyi];
+    for (int u = 0; u < kAhead; ++u) {
+      const int dyi = min(dy0 + u * nw, D2 - 1);
+      ml[u] = L.cmask[2 * dyi];
+      mh[u] = L.cmask[2 * dyi + 1];
+      rbv[u] = sh.rowbase[dyi];
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int pos = pos0 + u * kThreads;
-      const int dyi = quot_small(pos, D2, inv_d2), dxi = pos - dyi * D2;
-      const int b = dxi & 63;
-      if (pos < nd && ((w[u] >> b) & 1ull)) {
-        const int rank = __popcll(below[u]) + __popcll(w[u] & ((1ull << b) - 1ull));
-        const int rho = max(abs(dyi - W), abs(dxi - W));
-        L.cand[base[u] + rank] = (uint32_t)(dyi * Wd + dxi) | ((uint32_t)sh.bucket_of[rho] << 14);
+    for (int u = 0; u < kAhead; ++u) {
+      const int dyi = dy0 + u * nw;
+      if (dyi >= D2) break;
+      const int ady = abs(dyi - W);
+      for (int dxi = lane; dxi < D2; dxi += 64) {
+        const bool ok = dxi < 64 ? ((ml[u] >> dxi) & 1ull) : ((mh[u] >> (dxi - 64)) & 1ull);
+        if (ok) {
+          const int rank = dxi < 64 ? __popcll(ml[u] & ((1ull << dxi) - 1ull))
+                                    : __popcll(ml[u]) + __popcll(mh[u] & ((1ull << (dxi - 64)) - 1ull));
+          const int rho = max(ady, abs(dxi - W));
+          const unsigned long long lw = rho < 16 ? lut0 : (rho < 32 ? lut1 : lut2);
+          const uint32_t bk = (uint32_t)(lw >> (4 * (rho & 15))) & 15u;
+          L.cand[rbv[u] + rank] = (uint32_t)(dyi * Wd + dxi) | (bk << 14);
+        }
       }
     }
   }

@@ -37,6 +37,9 @@ struct DevParams {
   int MC;          // bound on admissible candidates
   int nrad;
   int radii[kMaxRadii];
+  // expansion bucket of each Chebyshev radius rho <= W (4 bits per rho: the
+  // first schedule radius >= rho), word rho / 16
+  unsigned long long bucket_lut[3];
   int min_pct, min_hql, mode;
   int prep_grid;   // workgroups of the prep kernel
   int cnn_active;  // CNN mode with a loaded network (else the profile rule)
@@ -106,9 +109,15 @@ constexpr size_t kCnnFloatsPerSample = 2 * 32 * 144 + 2 * 32 * 36 + 2 * 32 * 9 +
                                        32 * 9 + 32 * 36 + 32 * 144;
 hipError_t launch_cnn_inputs(const FrameArgs& a, const DevParams& p, uint16_t* out, int max_blocks,
                              hipStream_t s);
-hipError_t launch_cnn_gate(const FrameArgs& a, const DevParams& p, const float* wq, float tau1,
+hipError_t launch_cnn_gate(const FrameArgs& a, const DevParams& p, const uint4* pk,
+                           const float* wq, float tau1,
                            float tau2, int max_blocks, hipStream_t s);
-hipError_t cnn_infer(const uint16_t* x, int n, const float* wq, float* y, hipStream_t s);
+hipError_t cnn_infer(const uint16_t* x, int n, const uint4* pk, const float* wq, float* y,
+                     hipStream_t s);
+// register images of the gate weights for the inference kernels (after every
+// change of the rounded weights)
+hipError_t cnn_pack(const float* wq, uint4* pk, hipStream_t s);
+size_t cnn_pack_bytes();
 size_t cnn_gate_lds_bytes();
 hipError_t set_cnn_gate_lds_limit(size_t bytes);
 hipError_t cnn_init(float* prm, float* wq, unsigned long long seed, hipStream_t s);

@@ -193,6 +193,16 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
   const int i = xcd_block(blockIdx.x, n_lost);
   if (i < 0 || a.bstate[i] != 0) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  const int B = p.B, r = p.r, W = p.W, Wd = p.Wd, D2 = 2 * W + 1;
+  const int B2 = B * B;
+  const int cell = a.blk[i];
+  const int by = cell / p.gw, bx = cell - by * p.gw;
+  const int x0 = bx * B, y0 = by * B;
+  // the window loads go out first; they land while the round's context
+  // statistics are reduced
+  const StageGeom SG = stage_geom(p, x0 - r - W);
+  StageRegs SR;
+  if (!dist_only) stage_issue(a, p, SG, y0 - r - W, SR);
   // context-size gate of the round, from the prep kernel's per-workgroup partials
   int nq = 0, maxm0 = 0;
   for (int g = tid; g < p.prep_grid; g += kThreads) {
@@ -212,11 +222,6 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
   const int n0 = a.m0cnt[i];
   if (!dist_only && !(nq > 0 ? (n0 >= p.r * p.B) : (n0 == maxm0))) return;
 
-  const int B = p.B, r = p.r, W = p.W, Wd = p.Wd, D2 = 2 * W + 1;
-  const int B2 = B * B;
-  const int cell = a.blk[i];
-  const int by = cell / p.gw, bx = cell - by * p.gw;
-  const int x0 = bx * B, y0 = by * B;
 
   // 1. BRL gate on the prep kernel's ring statistics: context mean for every
   //    pixel of the block (profile rule, or the learned gate's choice in CNN
@@ -243,7 +248,8 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
   const EstLds E = carve_est_lds(lds_raw, p);
   phase_tables(p, E.m, sh);
   const int NU = sh.NU;
-  phase_stage(a, p, E.m, x0 - r - W, y0 - r - W);
+  if (dist_only) stage_issue(a, p, SG, y0 - r - W, SR);
+  stage_finish(a, p, E.m, SG, y0 - r - W, SR);
   phase_context(p, E.m, sh, NU);
 
   // 3. admissible prototypes in raster order
