@@ -6,12 +6,13 @@
 // Slot 0 serves the single-frame entry points; slots 1.. serve
 // skm_conceal_batch, which keeps several frames in flight on their streams.
 //
-// The frame pipeline is: loss geometry (k_zero_state, k_init, k_compact),
-// then rounds of (prep, [gate], estimation, [HQL], finalize + count) until
-// no block is pending.  A frame is enqueued with R rounds (the count its slot
-// needed last time; rounds past the last are no-ops on the device) followed
-// by a copy of the round state into pinned memory.  After the frame's stream
-// is synchronised, more rounds are run if blocks are still pending.  The
+// The frame pipeline is: loss geometry (k_init, k_compact), then rounds of
+// (prep, [gate], estimation, [HQL], finalize) until no block is pending;
+// k_compact and the last workgroup of each finalize write the round state
+// into coherent pinned memory.  A frame is
+// enqueued with R rounds (the count its slot needed last time; rounds past
+// the last are no-ops on the device).  After the frame's stream is
+// synchronised, more rounds are run if blocks are still pending.  The
 // enqueued part is captured once into a hipGraph and replayed while the
 // frame pointers, parameters and R stay the same.
 #include <math.h>
@@ -186,8 +187,12 @@ skm_status slot_create(skm_ctx* c, FrameSlot** out) {
   *out = f;
   SKM_HIP(hipStreamCreateWithFlags(&f->stream, hipStreamNonBlocking), "hipStreamCreate");
   SKM_HIP(hipMalloc((void**)&f->d_state, sizeof(RoundState)), "round state");
-  SKM_HIP(hipHostMalloc((void**)&f->h_state, sizeof(RoundState), hipHostMallocDefault),
+  SKM_HIP(hipMemset(f->d_state, 0, sizeof(RoundState)), "round state");
+  // coherent: kernels write the state here and the host reads it after a
+  // stream synchronization
+  SKM_HIP(hipHostMalloc((void**)&f->h_state, sizeof(RoundState), hipHostMallocCoherent),
           "pinned round state");
+  memset(f->h_state, 0, sizeof(RoundState));
   SKM_HIP(hipMalloc((void**)&f->d_part, sizeof(int) * 2 * kPrepGridMax), "prep slots");
   (void)c;
   return SKM_OK;
@@ -285,6 +290,7 @@ FrameArgs frame_args(FrameSlot* f, const uint8_t* frame, const uint8_t* mask, ui
   a.val = f->d_val + kValGuard; a.cell_lost = f->d_cell_lost; a.blk = f->d_blk;
   a.bstate = f->d_bstate; a.m0cnt = f->d_m0cnt; a.ring = f->d_ring; a.part = f->d_part;
   a.st = f->d_state;
+  a.hstate = f->h_state;
   a.hql_list = f->d_hql_list;
   a.gate = f->d_gate; a.gate_pred = f->d_gate_pred;
   return a;
@@ -333,7 +339,7 @@ skm_status launch_round(skm_ctx* c, FrameSlot* f, const DevParams& p, FrameArgs&
   return SKM_OK;
 }
 
-// Geometry + R rounds + state copy, eagerly on s.
+// Geometry + R rounds, eagerly on s.
 skm_status enqueue_eager(skm_ctx* c, FrameSlot* f, const DevParams& p, FrameArgs& a, int R,
                          hipStream_t s) {
   SKM_HIP(launch_init(a, p, s), "geometry kernels");
@@ -341,8 +347,6 @@ skm_status enqueue_eager(skm_ctx* c, FrameSlot* f, const DevParams& p, FrameArgs
     skm_status st = launch_round(c, f, p, a, k, s);
     if (st != SKM_OK) return st;
   }
-  SKM_HIP(hipMemcpyAsync(f->h_state, f->d_state, sizeof(RoundState), hipMemcpyDeviceToHost, s),
-          "state read-back");
   return SKM_OK;
 }
 

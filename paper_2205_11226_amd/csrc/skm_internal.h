@@ -56,6 +56,10 @@ struct RoundState {
   int n_hql;           // blocks of this round waiting for the HQL kernel
   unsigned long long n_avail;     // fill: known pixels and their sum
   unsigned long long sum_avail;
+  // Zero between launches (the slot's allocation starts zeroed; the kernel
+  // that consumes a field clears it):
+  int err_geo;                    // geometry errors found by k_init (k_compact)
+  unsigned long long round_acc;   // end-of-round counts and ticket (k_round_finalize)
 };
 
 constexpr int kPrepGridMax = 512;   // workgroups of the prep kernel (slots in `part`)
@@ -81,6 +85,7 @@ struct FrameArgs {
   int8_t* gate;           // CNN mode: layer chosen for each lost block
   float* gate_pred;       // CNN mode: the two predicted gains of each lost block
   RoundState* st;
+  RoundState* hstate;     // host-visible copy, written when a step publishes the state
   skm_block_info* info;   // optional
   float* xhat;            // optional
   int* dist;              // optional distance table (parity entry point)

@@ -21,18 +21,23 @@ namespace skm {
 
 // ---------------------------------------------------------- state / setup
 
-__global__ void k_zero_state(RoundState* st) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st->n_lost = 0; st->remaining = 0; st->round = 1; st->err = 0; st->n_hql = 0;
-    st->n_avail = 0; st->sum_avail = 0;
-  }
+// Host-visible copy of the frame state (pinned, coherent host memory): the
+// host reads it after synchronizing the stream instead of a copy node.
+__device__ __forceinline__ void publish_state(const FrameArgs& a) {
+  if (!a.hstate) return;
+  const RoundState* st = a.st;
+  RoundState* h = a.hstate;
+  h->n_lost = st->n_lost; h->remaining = st->remaining; h->round = st->round;
+  h->err = st->err; h->n_hql = st->n_hql;
+  h->n_avail = st->n_avail; h->sum_avail = st->sum_avail;
 }
 
 // Loss geometry, one pass over the frame.  Grid (ceil(width/256), bands of B
 // rows); one thread per column of a band: copies received pixels to `work`
 // (lost ones become 128 and are never read), writes the value plane (-1 =
 // lost), and the B lanes of one cell vote whether the cell is wholly lost.  A
-// lost pixel outside the full-cell grid, or a partly lost cell, is an error.
+// lost pixel outside the full-cell grid, or a partly lost cell, is an error
+// (err_geo, read and cleared by k_compact).
 __global__ __launch_bounds__(kThreads) void k_init(FrameArgs a, DevParams p) {
   const int x = blockIdx.x * kThreads + threadIdx.x;
   const int band = blockIdx.y;
@@ -59,10 +64,11 @@ __global__ __launch_bounds__(kThreads) void k_init(FrameArgs a, DevParams p) {
     a.cell_lost[band * p.gw + x / B] = (v == B * B) ? 1 : 0;
     if (v != 0 && v != B * B) bad = 1;
   }
-  if (__ballot(bad != 0) != 0ull && lane_id() == 0) atomicOr(&a.st->err, kErrPartial);
+  if (__ballot(bad != 0) != 0ull && lane_id() == 0) atomicOr(&a.st->err_geo, kErrPartial);
 }
 
-// single workgroup of 1024: ordered compaction of lost cells
+// Single workgroup of 1024: ordered compaction of the lost cells, and the
+// frame state for round 1 (published to the host copy).
 __global__ __launch_bounds__(1024) void k_compact(FrameArgs a, DevParams p) {
   __shared__ int s_cnt[1024];
   const int ncell = p.gh * p.gw;
@@ -88,9 +94,13 @@ __global__ __launch_bounds__(1024) void k_compact(FrameArgs a, DevParams p) {
     }
   }
   if (tid == 1023) {
-    a.st->n_lost = s_cnt[1023];
-    a.st->remaining = s_cnt[1023];
-    a.st->round = 1;
+    RoundState* st = a.st;
+    st->n_lost = s_cnt[1023];
+    st->remaining = s_cnt[1023];
+    st->round = 1;
+    st->err = atomicExch(&st->err_geo, 0);
+    st->n_hql = 0; st->n_avail = 0; st->sum_avail = 0;
+    publish_state(a);
   }
 }
 
@@ -529,14 +539,19 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
 
 // -------------------------------------------------------------- finalize
 // Blocks concealed in this round become known: their output pixels enter
-// the value plane.
+// the value plane.  The workgroups also count the blocks still pending (and
+// those left waiting for HQL); the last one sets the next round's state.
 __global__ __launch_bounds__(kThreads) void k_round_finalize(FrameArgs a, DevParams p) {
   RoundState* st = a.st;
   if (st->remaining == 0) return;
   const int n_lost = st->n_lost, round = st->round;
   const int B = p.B, B2 = B * B;
+  int pend = 0, hql = 0;
   for (int i = blockIdx.x; i < n_lost; i += gridDim.x) {
-    if (a.bstate[i] != round) continue;
+    const int bs = a.bstate[i];
+    pend += bs == 0;
+    hql += bs >= kNeedHql;
+    if (bs != round) continue;
     const int cell = a.blk[i];
     const int by = cell / p.gw, bx = cell - by * p.gw;
     for (int pix = threadIdx.x; pix < B2; pix += blockDim.x) {
@@ -545,30 +560,21 @@ __global__ __launch_bounds__(kThreads) void k_round_finalize(FrameArgs a, DevPar
       a.val[(size_t)y * p.width + x] = (int16_t)a.work[(size_t)y * p.stride + x];
     }
   }
-}
-
-// single workgroup: pending blocks after the round, next round number
-__global__ __launch_bounds__(1024) void k_round_count(FrameArgs a, DevParams p) {
-  __shared__ int s_p[1024 / 64], s_h[1024 / 64];
-  RoundState* st = a.st;
-  if (st->remaining == 0) return;
-  const int n_lost = st->n_lost, round = st->round;
-  int pend = 0, hql = 0;
-  for (int i = threadIdx.x; i < n_lost; i += 1024) {
-    const int bs = a.bstate[i];
-    pend += bs == 0;
-    hql |= bs >= kNeedHql;
-  }
-  pend = wave_sum(pend);
-  hql = wave_max(hql);
-  if (lane_id() == 0) { s_p[wave_id()] = pend; s_h[wave_id()] = hql; }
-  __syncthreads();
+  // one 64-bit atomic per workgroup: pending count (bits 0-23), blocks
+  // waiting for HQL (24-47) and a ticket (48-63); the workgroup that takes
+  // the last ticket has every count in the value it gets back
   if (threadIdx.x == 0) {
-    int t = 0, h = 0;
-    for (int w = 0; w < 1024 / 64; ++w) { t += s_p[w]; h |= s_h[w]; }
-    st->remaining = t;
-    st->round = round + 1;
-    if (h) st->err |= kErrHqlPending;
+    const unsigned long long mine =
+        (unsigned long long)pend | ((unsigned long long)hql << 24) | (1ull << 48);
+    const unsigned long long prev = atomicAdd(&st->round_acc, mine);
+    if ((prev >> 48) + 1 == gridDim.x) {
+      const unsigned long long tot = prev + mine;
+      st->round_acc = 0ull;
+      st->remaining = (int)(tot & 0xffffffull);
+      st->round = round + 1;
+      if ((tot >> 24) & 0xffffffull) st->err |= kErrHqlPending;
+      publish_state(a);
+    }
   }
 }
 
@@ -653,7 +659,6 @@ static int clamp_grid(long long g, int hi) {
 }
 
 hipError_t launch_init(const FrameArgs& a, const DevParams& p, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(64), 0, s, a.st);
   dim3 g((p.width + kThreads - 1) / kThreads, (p.height + p.B - 1) / p.B);
   hipLaunchKernelGGL(k_init, g, dim3(kThreads), 0, s, a, p);
   hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, a, p);
@@ -694,9 +699,8 @@ hipError_t launch_est(const FrameArgs& a, const DevParams& p, int max_blocks, hi
 
 hipError_t launch_finalize(const FrameArgs& a, const DevParams& p, int max_blocks,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_round_finalize, dim3(clamp_grid(max_blocks, 2048)), dim3(kThreads), 0, s,
+  hipLaunchKernelGGL(k_round_finalize, dim3(clamp_grid(max_blocks, 256)), dim3(kThreads), 0, s,
                      a, p);
-  hipLaunchKernelGGL(k_round_count, dim3(1), dim3(1024), 0, s, a, p);
   return hipGetLastError();
 }
 
