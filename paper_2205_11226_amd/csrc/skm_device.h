@@ -71,6 +71,16 @@ static __device__ __forceinline__ int wave_sum_full(int v) {
   v += dpp_i32<0x143, 0xc>(0, v);    // row_bcast:31 into rows 2, 3
   return __builtin_amdgcn_readlane(v, 63);
 }
+// inclusive prefix sum across the wave (row shifts, then row broadcasts)
+static __device__ __forceinline__ int wave_incl_scan(int v) {
+  v += dpp_i32<0x111, 0xf>(0, v);    // row_shr:1
+  v += dpp_i32<0x112, 0xf>(0, v);    // row_shr:2
+  v += dpp_i32<0x114, 0xf>(0, v);    // row_shr:4
+  v += dpp_i32<0x118, 0xf>(0, v);    // row_shr:8
+  v += dpp_i32<0x142, 0xa>(0, v);    // row_bcast:15 into rows 1, 3
+  v += dpp_i32<0x143, 0xc>(0, v);    // row_bcast:31 into rows 2, 3
+  return v;
+}
 static __device__ __forceinline__ double wave_sum_full(double v) {
   v += dpp_f64<0xB1, 0xf>(v);
   v += dpp_f64<0x4E, 0xf>(v);
@@ -263,12 +273,7 @@ typedef short short2v __attribute__((ext_vector_type(2)));
 // exclusive scan of one int per thread over the workgroup (fixed order)
 static __device__ __forceinline__ int block_excl_scan(int v, int* s_w, int* total) {
   const int lane = lane_id(), wave = wave_id();
-  int x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
+  const int x = wave_incl_scan(v);
   if (lane == 63) s_w[wave] = x;
   __syncthreads();
   int base = 0, tot = 0;
@@ -528,10 +533,18 @@ static __device__ __forceinline__ int phase_candidates(const DevParams& p, const
     L.cmask[2 * tid] = mlo; L.cmask[2 * tid + 1] = mhi;
     rowcnt = __popcll(mlo) + __popcll(mhi);
   }
-  int tot = 0;
-  const int rb = block_excl_scan(rowcnt, sh.scan, &tot);   // barriers inside
-  if (tid < D2) sh.rowbase[tid] = rb;
-  if (tid == 0) sh.M = tot;
+  if (D2 <= 64) {                        // every row in wave 0
+    if (wave == 0) {
+      const int incl = wave_incl_scan(rowcnt);
+      if (lane < D2) sh.rowbase[lane] = incl - rowcnt;
+      if (lane == 63) sh.M = incl;
+    }
+  } else {
+    int tot = 0;
+    const int rb = block_excl_scan(rowcnt, sh.scan, &tot);   // barriers inside
+    if (tid < D2) sh.rowbase[tid] = rb;
+    if (tid == 0) sh.M = tot;
+  }
   if (tid < p.nrad) { sh.bmax[tid] = 0xFFF0000000000000ull; sh.bcnt[tid] = 0; }
   __syncthreads();
   // wave w writes displacement rows w, w + 4, ..., lanes along the columns;
@@ -549,6 +562,24 @@ static __device__ __forceinline__ int phase_candidates(const DevParams& p, const
       ml[u] = L.cmask[2 * dyi];
       mh[u] = L.cmask[2 * dyi + 1];
       rbv[u] = sh.rowbase[dyi];
+    }
+    if (D2 <= 64) {
+      // one 64-bit mask per row: lane dx tests its bit, its rank is the
+      // count of set bits below it (v_mbcnt)
+      const int adx = abs(lane - W);
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        const int dyi = dy0 + u * nw;
+        const uint64_t m = ml[u];
+        if (dyi < D2 && ((m >> lane) & 1ull)) {
+          const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          const int rho = max(abs(dyi - W), adx);
+          const uint32_t bk = (uint32_t)((rho < 16 ? lut0 : lut1) >> (4 * (rho & 15))) & 15u;
+          L.cand[rbv[u] + rank] = (uint32_t)(dyi * Wd + lane) | (bk << 14);
+        }
+      }
+      continue;
     }
 #pragma unroll
     for (int u = 0; u < kAhead; ++u) {

@@ -362,22 +362,50 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
   __syncthreads();
   if (wave == 0) {
     // lane b: (m, cs) = (max, sum of exp(ell - max)) over buckets <= b, cc
-    // their candidate count.  Each combining step rescales the side with the
-    // smaller maximum; an empty side (m = -inf) contributes nothing.
+    // their candidate count.
     const int b = lane;
     const double bm = b < p.nrad ? __longlong_as_double((long long)sh.bmax[b]) : -INFINITY;
-    double m = bm;
-    double cs = b < p.nrad ? ((sh.ps[0][b] + sh.ps[1][b]) + sh.ps[2][b]) + sh.ps[3][b] : 0.0;
-    int cc = b < p.nrad ? sh.bcnt[b] : 0;
-    for (int o = 1; o < p.nrad; o <<= 1) {
-      const double m2 = __shfl_up(m, o, 64), s2 = __shfl_up(cs, o, 64);
-      const int c2 = __shfl_up(cc, o, 64);
-      if (lane >= o) {
-        const double mx = fmax(m, m2), mn = fmin(m, m2);
-        const double f = mn == mx ? 1.0 : (mn == -INFINITY ? 0.0 : exp(mn - mx));
-        cs = m >= m2 ? cs + s2 * f : cs * f + s2;
-        m = mx;
-        cc += c2;
+    double m, cs;
+    int cc;
+    double fpair = 0.0;   // KR <= 8: exp(bm[lane & 7] - m[lane >> 3]) for lane & 7 <= lane >> 3
+    if (KR <= 8) {
+      // lane (g, h) = (lane >> 3, lane & 7) holds bucket h's term of prefix g:
+      // one exponential per lane, then sums over the eight lanes of a group
+      const int g = lane >> 3, h = lane & 7;
+      const bool on = g < p.nrad && h <= g;
+      const double bmh = on ? __longlong_as_double((long long)sh.bmax[h]) : -INFINITY;
+      // group-of-8 reductions by DPP: quad_perm [1,0,3,2], [2,3,0,1], then
+      // row_half_mirror (lane i of the eight with lane 7 - i)
+      double mg = bmh;
+      mg = fmax(mg, dpp_f64<0xB1, 0xf>(mg));
+      mg = fmax(mg, dpp_f64<0x4E, 0xf>(mg));
+      mg = fmax(mg, dpp_f64<0x141, 0xf>(mg));
+      fpair = bmh == -INFINITY ? 0.0 : (bmh == mg ? 1.0 : exp(bmh - mg));
+      double t = on ? (((sh.ps[0][h] + sh.ps[1][h]) + sh.ps[2][h]) + sh.ps[3][h]) * fpair : 0.0;
+      int c = on ? sh.bcnt[h] : 0;
+      t += dpp_f64<0xB1, 0xf>(t); c += dpp_i32<0xB1, 0xf>(0, c);
+      t += dpp_f64<0x4E, 0xf>(t); c += dpp_i32<0x4E, 0xf>(0, c);
+      t += dpp_f64<0x141, 0xf>(t); c += dpp_i32<0x141, 0xf>(0, c);
+      const int src = 8 * min(lane, 7);
+      m = __shfl(mg, src, 64);
+      cs = __shfl(t, src, 64);
+      cc = __shfl(c, src, 64);
+    } else {
+      // Hillis-Steele prefix: each step rescales the side with the smaller
+      // maximum; an empty side (m = -inf) contributes nothing
+      m = bm;
+      cs = b < p.nrad ? ((sh.ps[0][b] + sh.ps[1][b]) + sh.ps[2][b]) + sh.ps[3][b] : 0.0;
+      cc = b < p.nrad ? sh.bcnt[b] : 0;
+      for (int o = 1; o < p.nrad; o <<= 1) {
+        const double m2 = __shfl_up(m, o, 64), s2 = __shfl_up(cs, o, 64);
+        const int c2 = __shfl_up(cc, o, 64);
+        if (lane >= o) {
+          const double mx = fmax(m, m2), mn = fmin(m, m2);
+          const double f = mn == mx ? 1.0 : (mn == -INFINITY ? 0.0 : exp(mn - mx));
+          cs = m >= m2 ? cs + s2 * f : cs * f + s2;
+          m = mx;
+          cc += c2;
+        }
       }
     }
     const double lnu = (b < p.nrad && cc > 0) ? m + log(cs) : -INFINITY;
@@ -405,8 +433,11 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
     const double m_r = __shfl(m, ridx, 64);
     // weight of a candidate of bucket b <= ridx: term * exp(bm[b] - max over
     // buckets <= ridx); sums (cs_r) are relative to the same maximum
-    if (lane < p.nrad)
+    if (KR <= 8) {
+      if ((lane >> 3) == ridx && (lane & 7) < p.nrad) sh.fsc[lane & 7] = fpair;   // 0 past ridx
+    } else if (lane < p.nrad) {
       sh.fsc[lane] = (lane <= ridx && bm != -INFINITY) ? (bm == m_r ? 1.0 : exp(bm - m_r)) : 0.0;
+    }
     if (lane == 0) {
       sh.layer = layer; sh.radius_idx = ridx; sh.flags = flags;
       sh.n_cand = ncand; sh.n_complete = ncom;
