@@ -178,7 +178,7 @@ def main():
     ap.add_argument("--isolated", type=int, default=60)
     ap.add_argument("--smooth", type=int, default=60)
     ap.add_argument("--val", type=int, default=6, help="validation frames per kind")
-    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--seed", type=int, default=4000)
     ap.add_argument("--workers", type=int, default=8)
     args = ap.parse_args()
