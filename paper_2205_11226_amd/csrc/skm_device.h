@@ -3,6 +3,7 @@
 // search window and find its admissible candidates with exact distances.
 #pragma once
 
+#include <limits.h>
 #include <math.h>
 
 #include "skm_internal.h"
@@ -29,16 +30,6 @@ template <typename T>
 static __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-static __device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
-}
-static __device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
   return v;
 }
 static __device__ __forceinline__ double wave_max_d(double v) {
@@ -92,6 +83,39 @@ static __device__ __forceinline__ double wave_sum_full(double v) {
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// The same reductions for the common 32-bit types and doubles (the shuffle
+// template above stays for 64-bit integers); every lane gets the result.
+static __device__ __forceinline__ int wave_sum(int v) { return wave_sum_full(v); }
+static __device__ __forceinline__ double wave_sum(double v) { return wave_sum_full(v); }
+static __device__ __forceinline__ float wave_sum(float v) {
+  v += __int_as_float(dpp_i32<0xB1, 0xf>(0, __float_as_int(v)));
+  v += __int_as_float(dpp_i32<0x4E, 0xf>(0, __float_as_int(v)));
+  v += __int_as_float(dpp_i32<0x141, 0xf>(0, __float_as_int(v)));
+  v += __int_as_float(dpp_i32<0x140, 0xf>(0, __float_as_int(v)));
+  v += __int_as_float(dpp_i32<0x142, 0xa>(0, __float_as_int(v)));
+  v += __int_as_float(dpp_i32<0x143, 0xc>(0, __float_as_int(v)));
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+// masked-off rows of the broadcasts read `old`: the neutral element
+static __device__ __forceinline__ int wave_max(int v) {
+  v = max(v, dpp_i32<0xB1, 0xf>(v, v));
+  v = max(v, dpp_i32<0x4E, 0xf>(v, v));
+  v = max(v, dpp_i32<0x141, 0xf>(v, v));
+  v = max(v, dpp_i32<0x140, 0xf>(v, v));
+  v = max(v, dpp_i32<0x142, 0xa>(INT_MIN, v));
+  v = max(v, dpp_i32<0x143, 0xc>(INT_MIN, v));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+static __device__ __forceinline__ int wave_min(int v) {
+  v = min(v, dpp_i32<0xB1, 0xf>(v, v));
+  v = min(v, dpp_i32<0x4E, 0xf>(v, v));
+  v = min(v, dpp_i32<0x141, 0xf>(v, v));
+  v = min(v, dpp_i32<0x140, 0xf>(v, v));
+  v = min(v, dpp_i32<0x142, 0xa>(INT_MAX, v));
+  v = min(v, dpp_i32<0x143, 0xc>(INT_MAX, v));
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Merge (m2, s2) into (m, s), both "max and sum of exp(x - max)".  Callers fix

@@ -570,41 +570,64 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
 
 // -------------------------------------------------------------- finalize
 // Blocks concealed in this round become known: their output pixels enter
-// the value plane.  The workgroups also count the blocks still pending (and
-// those left waiting for HQL); the last one sets the next round's state.
+// the value plane.  A workgroup takes kFinPer consecutive lost blocks at a
+// time (their states read together, then one pixel per thread of each) and
+// counts the blocks still pending and those left waiting for HQL; the
+// workgroup that finishes last sets the next round's state.
+constexpr int kFinPer = 16;
+
 __global__ __launch_bounds__(kThreads) void k_round_finalize(FrameArgs a, DevParams p) {
+  __shared__ int s_bs[kFinPer];
+  __shared__ int s_vo[kFinPer], s_wo[kFinPer];
   RoundState* st = a.st;
   if (st->remaining == 0) return;
   const int n_lost = st->n_lost, round = st->round;
-  const int B = p.B, B2 = B * B;
+  const int B = p.B, B2 = B * B, tid = threadIdx.x;
+  const int lb = __ffs(B) - 1;                     // B is a power of two
+  const int py = tid >> lb, px = tid & (B - 1);
   int pend = 0, hql = 0;
-  for (int i = blockIdx.x; i < n_lost; i += gridDim.x) {
-    const int bs = a.bstate[i];
-    pend += bs == 0;
-    hql += bs >= kNeedHql;
-    if (bs != round) continue;
-    const int cell = a.blk[i];
-    const int by = cell / p.gw, bx = cell - by * p.gw;
-    for (int pix = threadIdx.x; pix < B2; pix += blockDim.x) {
-      const int py = pix / B, px = pix - py * B;
-      const int y = by * B + py, x = bx * B + px;
-      a.val[(size_t)y * p.width + x] = (int16_t)a.work[(size_t)y * p.stride + x];
+  for (int i0 = blockIdx.x * kFinPer; i0 < n_lost; i0 += gridDim.x * kFinPer) {
+    if (tid < kFinPer) {
+      const int i = i0 + tid;
+      const int bs = i < n_lost ? a.bstate[i] : -1;
+      const int cell = i < n_lost ? a.blk[i] : 0;
+      const int by = cell / p.gw, bx = cell - by * p.gw;
+      s_bs[tid] = bs;
+      s_vo[tid] = by * B * p.width + bx * B;
+      s_wo[tid] = by * B * p.stride + bx * B;
+      pend += bs == 0;
+      hql += bs >= kNeedHql;
     }
+    __syncthreads();
+    uint8_t v[kFinPer];
+#pragma unroll
+    for (int k = 0; k < kFinPer; ++k)
+      v[k] = (tid < B2 && s_bs[k] == round) ? a.work[(size_t)s_wo[k] + (size_t)py * p.stride + px]
+                                            : (uint8_t)0;
+#pragma unroll
+    for (int k = 0; k < kFinPer; ++k)
+      if (tid < B2 && s_bs[k] == round)
+        a.val[(size_t)s_vo[k] + (size_t)py * p.width + px] = (int16_t)v[k];
+    __syncthreads();
   }
   // one 64-bit atomic per workgroup: pending count (bits 0-23), blocks
   // waiting for HQL (24-47) and a ticket (48-63); the workgroup that takes
   // the last ticket has every count in the value it gets back
-  if (threadIdx.x == 0) {
-    const unsigned long long mine =
-        (unsigned long long)pend | ((unsigned long long)hql << 24) | (1ull << 48);
-    const unsigned long long prev = atomicAdd(&st->round_acc, mine);
-    if ((prev >> 48) + 1 == gridDim.x) {
-      const unsigned long long tot = prev + mine;
-      st->round_acc = 0ull;
-      st->remaining = (int)(tot & 0xffffffull);
-      st->round = round + 1;
-      if ((tot >> 24) & 0xffffffull) st->err |= kErrHqlPending;
-      publish_state(a);
+  if (tid < 64) {
+    pend = wave_sum(pend);
+    hql = wave_sum(hql);
+    if (tid == 0) {
+      const unsigned long long mine =
+          (unsigned long long)pend | ((unsigned long long)hql << 24) | (1ull << 48);
+      const unsigned long long prev = atomicAdd(&st->round_acc, mine);
+      if ((prev >> 48) + 1 == gridDim.x) {
+        const unsigned long long tot = prev + mine;
+        st->round_acc = 0ull;
+        st->remaining = (int)(tot & 0xffffffull);
+        st->round = round + 1;
+        if ((tot >> 24) & 0xffffffull) st->err |= kErrHqlPending;
+        publish_state(a);
+      }
     }
   }
 }
@@ -730,8 +753,8 @@ hipError_t launch_est(const FrameArgs& a, const DevParams& p, int max_blocks, hi
 
 hipError_t launch_finalize(const FrameArgs& a, const DevParams& p, int max_blocks,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_round_finalize, dim3(clamp_grid(max_blocks, 256)), dim3(kThreads), 0, s,
-                     a, p);
+  hipLaunchKernelGGL(k_round_finalize, dim3(clamp_grid((max_blocks + kFinPer - 1) / kFinPer, 256)),
+                     dim3(kThreads), 0, s, a, p);
   return hipGetLastError();
 }
 
