@@ -62,6 +62,14 @@ static __device__ __forceinline__ int wave_sum_full(int v) {
   v += dpp_i32<0x143, 0xc>(0, v);    // row_bcast:31 into rows 2, 3
   return __builtin_amdgcn_readlane(v, 63);
 }
+// value of lane `l` (wave-uniform) in every lane
+static __device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // inclusive prefix sum across the wave (row shifts, then row broadcasts)
 static __device__ __forceinline__ int wave_incl_scan(int v) {
   v += dpp_i32<0x111, 0xf>(0, v);    // row_shr:1
@@ -338,11 +346,7 @@ static __device__ __forceinline__ void phase_tables(const DevParams& p, const Ma
     const bool full = fy < r || fy >= r + B;
     int cnt = 0;
     if (fy < F) cnt = full ? (F + 1) / 2 : 2 * ((r + 1) / 2);
-    int x = cnt;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
+    const int x = wave_incl_scan(cnt);
     int pos = x - cnt;
     if (fy < F) {
       if (full) {
@@ -595,6 +599,7 @@ static __device__ __forceinline__ int phase_candidates(const DevParams& p, const
       for (int u = 0; u < kAhead; ++u) {
         const int dyi = dy0 + u * nw;
         const uint64_t m = ml[u];
+        if (m == 0ull) continue;                  // uniform: no prototype in this row
         if (dyi < D2 && ((m >> lane) & 1ull)) {
           const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));

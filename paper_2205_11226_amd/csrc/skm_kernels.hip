@@ -428,9 +428,9 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
       if (ncom >= max(2, p.min_hql)) layer = SKM_LAYER_HQL;
       else flags |= SKM_FLAG_NO_HQL;
     }
-    const double lnu_r = __shfl(lnu, ridx, 64);
-    const double cs_r = __shfl(cs, ridx, 64);
-    const double m_r = __shfl(m, ridx, 64);
+    const double lnu_r = readlane_f64(lnu, ridx);      // ridx is uniform in the wave
+    const double cs_r = readlane_f64(cs, ridx);
+    const double m_r = readlane_f64(m, ridx);
     // weight of a candidate of bucket b <= ridx: term * exp(bm[b] - max over
     // buckets <= ridx); sums (cs_r) are relative to the same maximum
     if (KR <= 8) {
