@@ -193,7 +193,7 @@ skm_status slot_create(skm_ctx* c, FrameSlot** out) {
   SKM_HIP(hipHostMalloc((void**)&f->h_state, sizeof(RoundState), hipHostMallocCoherent),
           "pinned round state");
   memset(f->h_state, 0, sizeof(RoundState));
-  SKM_HIP(hipMalloc((void**)&f->d_part, sizeof(int) * 2 * kPrepGridMax), "prep slots");
+  SKM_HIP(hipMalloc((void**)&f->d_part, sizeof(int) * 2 * kPartSlots), "prep slots");
   (void)c;
   return SKM_OK;
 }
@@ -313,16 +313,24 @@ skm_status check_err(const RoundState& st) {
   return SKM_OK;
 }
 
+// CNN mode with a loaded network: the gate kernel also prepares the round
+// (ring statistics, per-workgroup context counts), in place of the prep kernel.
+void activate_gate(const skm_ctx* c, DevParams& p) {
+  p.cnn_active = p.mode == SKM_MODE_CNN && c->cnn_loaded;
+  if (p.cnn_active) p.prep_grid = cnn_gate_grid(c->gate_grid);
+}
+
 // One round on s.  With timing on, the estimation kernel of round k of the
 // enqueue is bracketed by event pair k of the slot.
 skm_status launch_round(skm_ctx* c, FrameSlot* f, const DevParams& p, FrameArgs& a, int k,
                         hipStream_t s) {
   const int nb = p.gh * p.gw;
-  SKM_HIP(launch_prep(a, p, nb, s), "prep kernel");
   if (p.cnn_active)
     SKM_HIP(launch_cnn_gate(a, p, c->d_gate_pack, c->d_cnn + kCnnParams, c->tau1, c->tau2,
                             c->gate_grid, s),
             "gate kernel");
+  else
+    SKM_HIP(launch_prep(a, p, nb, s), "prep kernel");
   if (c->prof) {
     while ((int)f->ev.size() < 2 * (k + 1)) {
       hipEvent_t e;
@@ -567,7 +575,7 @@ skm_status skm_conceal_device(skm_ctx* c, const uint8_t* d_frame, const uint8_t*
   FrameSlot* f = c->slots[0];
   if ((s = ensure_frame(c, f, p)) != SKM_OK) return s;
   hipStream_t st = (hipStream_t)hip_stream;
-  p.cnn_active = p.mode == SKM_MODE_CNN && c->cnn_loaded;
+  activate_gate(c, p);
   FrameArgs a = frame_args(f, d_frame, d_mask, d_out);
   a.info = d_info; a.xhat = d_xhat; a.cap = (d_info || d_xhat) ? cap : 0;
   int nl = 0;
@@ -599,7 +607,7 @@ skm_status skm_conceal(skm_ctx* c, const uint8_t* frame, const uint8_t* loss_mas
   FrameSlot* f = c->slots[0];
   if ((s = ensure_frame(c, f, p)) != SKM_OK) return s;
   hipStream_t st = c->stream;
-  p.cnn_active = p.mode == SKM_MODE_CNN && c->cnn_loaded;
+  activate_gate(c, p);
   SKM_HIP(hipMemcpyAsync(c->d_frame, frame, bytes, hipMemcpyHostToDevice, st), "frame upload");
   SKM_HIP(hipMemcpyAsync(c->d_mask, loss_mask, bytes, hipMemcpyHostToDevice, st), "mask upload");
   FrameArgs a = frame_args(f, c->d_frame, c->d_mask, c->d_out);
@@ -677,7 +685,7 @@ skm_status skm_conceal_batch(skm_ctx* c, skm_frame_desc* frames, int32_t n, void
       if (first == SKM_OK) first = s;
       continue;
     }
-    p.cnn_active = p.mode == SKM_MODE_CNN && c->cnn_loaded;
+    activate_gate(c, p);
     f->pp = p;
     f->pa = frame_args(f, d.frame, d.mask, d.out);
     f->pa.info = d.info; f->pa.xhat = d.xhat; f->pa.cap = (d.info || d.xhat) ? d.cap : 0;

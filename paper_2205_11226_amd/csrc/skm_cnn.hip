@@ -582,35 +582,32 @@ static __device__ __forceinline__ u32x4 s2d_pixel(const int* v) {
                  c1[2] | (c1[3] << 16)};
 }
 
-// In-pipeline gate: one pass over the blocks eligible in this round; the
-// layer choice goes to gate[i] and the predictions to gate_pred.
+// In-pipeline gate, which also does the round preparation in CNN mode: one
+// pass over the pending blocks of the round.  For each it records the
+// known in-frame ring pixels (count, sum, minimum, maximum) from the window
+// it has loaded anyway, evaluates the network and writes the layer choice to
+// gate[i] (the predictions to gate_pred).  Workgroup w publishes (blocks
+// with |m0| >= r B, largest |m0|) in part slot w, as the prep kernel does.
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_gate(
     FrameArgs a, DevParams p, const uint4* pk, const float* wq, float tau1, float tau2) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  __shared__ int red[kThreads / 64][2];
+  __shared__ int red[kThreads / 64][4];
   GateLds& G = *reinterpret_cast<GateLds*>(lds_raw);
   RoundState* st = a.st;
   if (st->remaining == 0) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->n_hql = 0;
   const int n_lost = st->n_lost;
-  int nq = 0, maxm0 = 0;
-  for (int gi = threadIdx.x; gi < p.prep_grid; gi += kThreads) {
-    nq += a.part[2 * gi];
-    maxm0 = max(maxm0, a.part[2 * gi + 1]);
-  }
-  nq = wave_sum(nq);
-  maxm0 = wave_max(maxm0);
-  if (lane_id() == 0) { red[wave_id()][0] = nq; red[wave_id()][1] = maxm0; }
   gate_clear_padding(G);
-  __syncthreads();
-  nq = 0; maxm0 = 0;
-  for (int w = 0; w < kThreads / 64; ++w) { nq += red[w][0]; maxm0 = max(maxm0, red[w][1]); }
   const GateWeights W = load_gate_weights(pk, wq);
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   // XCD x (workgroups x, x + 8, ...) takes a contiguous range of blocks, so
   // neighbouring windows share its L2
   const int lw = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   const int per = (n_lost + gridDim.x - 1) / gridDim.x;
   const int i_end = min(n_lost, (lw + 1) * per);
+  // ring of the block in window coordinates: footprint rows/columns
+  // [f0, f1), block [b0, b1)
+  const int b0 = kP / 2 - p.B / 2, b1 = b0 + p.B, f0 = b0 - p.r, f1 = b1 + p.r;
   // the window pixels of block i + 1 are loaded while block i runs: thread t
   // owns input pixels t + 256 k, four window pixels each
   constexpr int kPer = (kS * kS + kThreads - 1) / kThreads;
@@ -633,30 +630,47 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
       }
     }
   };
-  // state and ring count of the next block travel with its pixels
-  int nx_state = 1, nx_m0 = 0;
-  auto load_next = [&](int blk) {
-    load_block(blk);
-    nx_state = a.bstate[blk];
-    nx_m0 = a.m0cnt[blk];
-  };
+  int nx_state = 1;                        // state of the next block travels with its pixels
   const int i_begin = lw * per;
-  if (i_begin < i_end) load_next(i_begin);
+  if (i_begin < i_end) { load_block(i_begin); nx_state = a.bstate[i_begin]; }
+  int wg_nq = 0, wg_max = 0;
   for (int i = i_begin; i < i_end; ++i) {
-    const bool elig = nx_state == 0 && (nq > 0 ? (nx_m0 >= p.r * p.B) : (nx_m0 == maxm0));
-    if (elig) {
+    const bool pending = nx_state == 0;
+    if (pending) {
+      int c = 0, sum = 0, vmin = 255, vmax = 0;
 #pragma unroll
       for (int t = 0; t < kPer; ++t) {
         const int idx = tid + t * kThreads;
         if (idx < kS * kS) {
           const int Y = idx / kS, X = idx - Y * kS;
           G.in[(Y + 1) * kIn + X + 1] = s2d_pixel(v[t]);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int wy = 2 * Y + (q >> 1), wx = 2 * X + (q & 1);
+            const bool ring = wy >= f0 && wy < f1 && wx >= f0 && wx < f1 &&
+                              !(wy >= b0 && wy < b1 && wx >= b0 && wx < b1);
+            if (ring && v[t][q] >= 0) {
+              ++c; sum += v[t][q]; vmin = min(vmin, v[t][q]); vmax = max(vmax, v[t][q]);
+            }
+          }
         }
       }
+      c = wave_sum(c); sum = wave_sum(sum); vmin = wave_min(vmin); vmax = wave_max(vmax);
+      if (lane == 0) { red[wave][0] = c; red[wave][1] = sum; red[wave][2] = vmin; red[wave][3] = vmax; }
     }
     __syncthreads();
-    if (i + 1 < i_end) load_next(i + 1);
-    if (!elig) continue;
+    if (pending && tid == 0) {
+      int c = 0, sum = 0, vmin = 255, vmax = 0;
+      for (int w = 0; w < kThreads / 64; ++w) {
+        c += red[w][0]; sum += red[w][1]; vmin = min(vmin, red[w][2]); vmax = max(vmax, red[w][3]);
+      }
+      a.m0cnt[i] = c;
+      a.ring[i] = make_int2(sum, vmin | (vmax << 16));
+      wg_nq += c >= p.r * p.B;
+      wg_max = max(wg_max, c);
+    }
+    if (i + 1 < i_end) { load_block(i + 1); nx_state = a.bstate[i + 1]; }
+    if (!pending) continue;
     float y0 = 0.0f, y1 = 0.0f;
     gate_network(G, W, y0, y1);
     if (tid == 0) {
@@ -664,6 +678,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
       if (a.gate_pred) { a.gate_pred[2 * i] = y0; a.gate_pred[2 * i + 1] = y1; }
     }
     __syncthreads();
+  }
+  if (tid == 0) {
+    a.part[2 * blockIdx.x] = wg_nq;
+    a.part[2 * blockIdx.x + 1] = wg_max;
   }
 }
 
@@ -712,13 +730,16 @@ hipError_t launch_cnn_inputs(const FrameArgs& a, const DevParams& p, uint16_t* o
 constexpr int kGateGrid = 4096;
 constexpr int kInferGrid = 768;
 
+// a multiple of 8 workgroups (the block ranges follow the XCD order)
+int cnn_gate_grid(int requested) {
+  const int g = requested < 1 ? 1 : (requested > kGateGrid ? kGateGrid : requested);
+  return (g + 7) / 8 * 8;
+}
+
 hipError_t launch_cnn_gate(const FrameArgs& a, const DevParams& p, const uint4* pk,
                            const float* wq, float tau1, float tau2, int max_blocks, hipStream_t s) {
-  // a multiple of 8 workgroups (the block ranges follow the XCD order)
-  int grid = max_blocks < 1 ? 1 : (max_blocks > kGateGrid ? kGateGrid : max_blocks);
-  grid = (grid + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_cnn_gate, dim3(grid), dim3(kThreads), sizeof(GateLds), s, a, p, pk, wq,
-                     tau1, tau2);
+  hipLaunchKernelGGL(k_cnn_gate, dim3(cnn_gate_grid(max_blocks)), dim3(kThreads), sizeof(GateLds),
+                     s, a, p, pk, wq, tau1, tau2);
   return hipGetLastError();
 }
 

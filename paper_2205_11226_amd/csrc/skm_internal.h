@@ -41,7 +41,7 @@ struct DevParams {
   // first schedule radius >= rho), word rho / 16
   unsigned long long bucket_lut[3];
   int min_pct, min_hql, mode;
-  int prep_grid;   // workgroups of the prep kernel
+  int prep_grid;   // workgroups that wrote `part` (prep kernel, or the gate in CNN mode)
   int cnn_active;  // CNN mode with a loaded network (else the profile rule)
   int width, height, stride;
   int gh, gw;      // full cells
@@ -62,7 +62,8 @@ struct RoundState {
   unsigned long long round_acc;   // end-of-round counts and ticket (k_round_finalize)
 };
 
-constexpr int kPrepGridMax = 512;   // workgroups of the prep kernel (slots in `part`)
+constexpr int kPrepGridMax = 512;   // workgroups of the prep kernel
+constexpr int kPartSlots = 4096;    // slots in `part`: the prep kernel's or the gate's workgroups
 
 // bstate values: 0 pending, > 0 concealed in that round, kNeedHql + round:
 // waiting for the HQL kernels in that round.
@@ -80,7 +81,7 @@ struct FrameArgs {
   int* bstate;
   int* m0cnt;             // known in-frame ring pixels of each pending block
   int2* ring;             // their sum, and min | max << 16 (prep kernel)
-  int* part;              // 2 * kPrepGridMax prep partials
+  int* part;              // 2 * kPartSlots round-preparation partials
   int* hql_list;          // lost-block indices waiting for HQL in this round
   int8_t* gate;           // CNN mode: layer chosen for each lost block
   float* gate_pred;       // CNN mode: the two predicted gains of each lost block
@@ -123,6 +124,7 @@ hipError_t cnn_infer(const uint16_t* x, int n, const uint4* pk, const float* wq,
 // change of the rounded weights)
 hipError_t cnn_pack(const float* wq, uint4* pk, hipStream_t s);
 size_t cnn_pack_bytes();
+int cnn_gate_grid(int requested);
 size_t cnn_gate_lds_bytes();
 hipError_t set_cnn_gate_lds_limit(size_t bytes);
 hipError_t cnn_init(float* prm, float* wq, unsigned long long seed, hipStream_t s);
