@@ -6,10 +6,10 @@
 // Slot 0 serves the single-frame entry points; slots 1.. serve
 // skm_conceal_batch, which keeps several frames in flight on their streams.
 //
-// The frame pipeline is: loss geometry (k_init, k_compact), then rounds of
-// (prep, [gate], estimation, [HQL], finalize) until no block is pending;
-// k_compact and the last workgroup of each finalize write the round state
-// into coherent pinned memory.  A frame is
+// The frame pipeline is: loss geometry (k_init; its last workgroup lists the
+// lost cells), then rounds of ([prep | gate], estimation, [HQL], finalize)
+// until no block is pending; the last workgroups of k_init and of each
+// finalize write the round state into coherent pinned memory.  A frame is
 // enqueued with R rounds (the count its slot needed last time; rounds past
 // the last are no-ops on the device).  After the frame's stream is
 // synchronised, more rounds are run if blocks are still pending.  The
@@ -29,7 +29,7 @@ using namespace skm;
 
 struct FrameSlot {
   int16_t* d_val = nullptr;       size_t cap_px = 0;
-  uint8_t* d_cell_lost = nullptr;
+  unsigned int* d_cellbits = nullptr;
   int* d_blk = nullptr;
   int* d_bstate = nullptr;
   int* d_m0cnt = nullptr;
@@ -203,7 +203,7 @@ void slot_destroy(FrameSlot* f) {
   if (f->stream) (void)hipStreamSynchronize(f->stream);
   if (f->gexec) (void)hipGraphExecDestroy(f->gexec);
   (void)hipFree(f->d_val);
-  (void)hipFree(f->d_cell_lost);
+  (void)hipFree(f->d_cellbits);
   (void)hipFree(f->d_blk);
   (void)hipFree(f->d_bstate);
   (void)hipFree(f->d_m0cnt);
@@ -230,14 +230,15 @@ skm_status ensure_frame(skm_ctx* c, FrameSlot* f, const DevParams& p) {
     return s;
   if (ncell > f->cap_cells || !f->d_blk) {
     size_t cap = 0;
-    (void)hipFree(f->d_cell_lost); f->d_cell_lost = nullptr;
+    (void)hipFree(f->d_cellbits); f->d_cellbits = nullptr;
     (void)hipFree(f->d_blk); f->d_blk = nullptr;
     (void)hipFree(f->d_bstate); f->d_bstate = nullptr;
     (void)hipFree(f->d_m0cnt); f->d_m0cnt = nullptr;
     (void)hipFree(f->d_ring); f->d_ring = nullptr;
     (void)hipFree(f->d_hql_list); f->d_hql_list = nullptr;
     f->cap_cells = 0;
-    if ((s = grow(&f->d_cell_lost, &cap, ncell, "cell table")) != SKM_OK) return s;
+    if ((s = grow(&f->d_cellbits, &cap, (ncell + 31) / 32, "cell table")) != SKM_OK) return s;
+    SKM_HIP(hipMemset(f->d_cellbits, 0, sizeof(unsigned int) * cap), "cell table");
     cap = 0;
     if ((s = grow(&f->d_blk, &cap, ncell, "block list")) != SKM_OK) return s;
     cap = 0;
@@ -287,7 +288,7 @@ FrameArgs frame_args(FrameSlot* f, const uint8_t* frame, const uint8_t* mask, ui
   FrameArgs a;
   memset(&a, 0, sizeof(a));
   a.frame = frame; a.mask = mask; a.work = out;
-  a.val = f->d_val + kValGuard; a.cell_lost = f->d_cell_lost; a.blk = f->d_blk;
+  a.val = f->d_val + kValGuard; a.cellbits = f->d_cellbits; a.blk = f->d_blk;
   a.bstate = f->d_bstate; a.m0cnt = f->d_m0cnt; a.ring = f->d_ring; a.part = f->d_part;
   a.st = f->d_state;
   a.hstate = f->h_state;

@@ -58,7 +58,8 @@ struct RoundState {
   unsigned long long sum_avail;
   // Zero between launches (the slot's allocation starts zeroed; the kernel
   // that consumes a field clears it):
-  int err_geo;                    // geometry errors found by k_init (k_compact)
+  int err_geo;                    // geometry errors found by k_init
+  unsigned int ticket;            // k_init workgroups done (the last one clears it)
   unsigned long long round_acc;   // end-of-round counts and ticket (k_round_finalize)
 };
 
@@ -76,7 +77,7 @@ struct FrameArgs {
   int16_t* val;           // workspace plane, pitch = width: pixel value where
                           // known (received or concealed in an earlier round),
                           // -1 where still lost
-  uint8_t* cell_lost;     // gh * gw
+  unsigned int* cellbits; // lost-cell bit table, ceil(gh * gw / 32) words, zero between frames
   int* blk;               // lost cell indices, raster order
   int* bstate;
   int* m0cnt;             // known in-frame ring pixels of each pending block

@@ -32,72 +32,128 @@ __device__ __forceinline__ void publish_state(const FrameArgs& a) {
   h->n_avail = st->n_avail; h->sum_avail = st->sum_avail;
 }
 
-// Loss geometry, one pass over the frame.  Grid (ceil(width/256), bands of B
-// rows); one thread per column of a band: copies received pixels to `work`
-// (lost ones become 128 and are never read), writes the value plane (-1 =
-// lost), and the B lanes of one cell vote whether the cell is wholly lost.  A
-// lost pixel outside the full-cell grid, or a partly lost cell, is an error
-// (err_geo, read and cleared by k_compact).
+// Loss geometry, one pass over the frame.  Grid (ceil(width/1024), bands of
+// B rows); each thread owns four adjacent columns of a band (32-bit loads and
+// stores where the rows allow them): copies received pixels to `work` (lost
+// ones become 128 and are never read), writes the value plane (-1 = lost),
+// and the B / 4 threads of one cell vote whether the cell is wholly lost.  A
+// lost pixel outside the full-cell grid, or a partly lost cell, is an error.
+// Lost cells are ORed into a bit table with device-scope atomics (coherent
+// across XCDs without a cache flush); the workgroup that finishes last lists
+// them in raster order, clears the table and starts the frame state.
 __global__ __launch_bounds__(kThreads) void k_init(FrameArgs a, DevParams p) {
-  const int x = blockIdx.x * kThreads + threadIdx.x;
+  __shared__ int s_scan[kThreads / 64];
+  __shared__ int s_last;
+  const int lane = lane_id(), wave = wave_id(), tid = threadIdx.x;
+  const int x = (blockIdx.x * kThreads + tid) * 4;
   const int band = blockIdx.y;
   const int B = p.B;
   const int y0 = band * B;
   const int rows = min(B, p.height - y0);
+  RoundState* st = a.st;
+  // 32-bit accesses when the four columns are in the frame and aligned
+  const bool vec = x + 3 < p.width && ((p.stride | p.width) & 3) == 0 &&
+                   (((uintptr_t)a.frame | (uintptr_t)a.mask | (uintptr_t)a.work) & 3) == 0;
   int nl = 0;
-  if (x < p.width) {
-    for (int i = 0; i < rows; ++i) {
-      const int y = y0 + i;
-      const size_t off = (size_t)y * p.stride + x;
-      const bool lost = a.mask[off] != 0;
-      const uint8_t v = a.frame[off];
-      a.work[off] = lost ? (uint8_t)128 : v;
-      a.val[(size_t)y * p.width + x] = lost ? (int16_t)-1 : (int16_t)v;
-      nl += lost;
+  if (vec) {
+    uint32_t mk[kMaxB], fv[kMaxB];
+#pragma unroll
+    for (int i = 0; i < kMaxB; ++i) {
+      const size_t off = (size_t)(y0 + min(i, rows - 1)) * p.stride + x;
+      mk[i] = *reinterpret_cast<const uint32_t*>(a.mask + off);
+      fv[i] = *reinterpret_cast<const uint32_t*>(a.frame + off);
+    }
+#pragma unroll
+    for (int i = 0; i < kMaxB; ++i) {
+      if (i < rows) {
+        uint32_t wk = 0, v01 = 0, v23 = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bool lost = ((mk[i] >> (8 * q)) & 0xffu) != 0u;
+          const uint32_t pix = (fv[i] >> (8 * q)) & 0xffu;
+          wk |= (lost ? 128u : pix) << (8 * q);
+          const uint32_t vv = lost ? 0xffffu : pix;
+          if (q < 2) v01 |= vv << (16 * q); else v23 |= vv << (16 * (q - 2));
+          nl += lost;
+        }
+        const int y = y0 + i;
+        *reinterpret_cast<uint32_t*>(a.work + (size_t)y * p.stride + x) = wk;
+        *reinterpret_cast<uint2*>(a.val + (size_t)y * p.width + x) = make_uint2(v01, v23);
+      }
+    }
+  } else {
+    for (int q = 0; q < 4; ++q) {
+      const int xq = x + q;
+      if (xq >= p.width) break;
+      for (int i = 0; i < rows; ++i) {
+        const int y = y0 + i;
+        const size_t off = (size_t)y * p.stride + xq;
+        const bool lost = a.mask[off] != 0;
+        const uint8_t v = a.frame[off];
+        a.work[off] = lost ? (uint8_t)128 : v;
+        a.val[(size_t)y * p.width + xq] = lost ? (int16_t)-1 : (int16_t)v;
+        nl += lost;
+      }
     }
   }
+  const int TB = B >> 2;                             // threads per cell
   const bool in_cells = band < p.gh && x < p.gw * B;
   int bad = (nl > 0 && !in_cells) ? 1 : 0;
   int v = nl;
-  for (int o = 1; o < B; o <<= 1) v += __shfl_xor(v, o, 64);   // cells never straddle waves
-  if (in_cells && (lane_id() & (B - 1)) == 0) {
-    a.cell_lost[band * p.gw + x / B] = (v == B * B) ? 1 : 0;
-    if (v != 0 && v != B * B) bad = 1;
+  for (int o = 1; o < TB; o <<= 1) v += __shfl_xor(v, o, 64);   // cells never straddle waves
+  const bool leader = in_cells && (lane & (TB - 1)) == 0;
+  if (leader && v != 0 && v != B * B) bad = 1;
+  const uint64_t lm = __ballot(leader && v == B * B);
+  const bool any_bad = __ballot(bad != 0) != 0ull;
+  if (lane == 0) {
+    unsigned int sink = 0;
+    if (lm) {
+      // this wave's cells are consecutive: 256 / B of them from cell cb
+      const int cb = band * p.gw + (blockIdx.x * kThreads + wave * 64) * 4 / B;
+      uint64_t bits = 0;
+      for (int k = 0; k < 64 / TB; ++k) bits |= ((lm >> (k * TB)) & 1ull) << k;
+      const int w = cb >> 5, sh = cb & 31;
+      const uint32_t p0 = (uint32_t)(bits << sh);
+      const uint32_t p1 = (uint32_t)(sh ? (bits >> (32 - sh)) : (bits >> 32));
+      const uint32_t p2 = sh ? (uint32_t)(bits >> (64 - sh)) : 0u;
+      if (p0) sink ^= atomicOr(&a.cellbits[w], p0);
+      if (p1) sink ^= atomicOr(&a.cellbits[w + 1], p1);
+      if (p2) sink ^= atomicOr(&a.cellbits[w + 2], p2);
+    }
+    if (any_bad) sink ^= (unsigned int)atomicOr(&st->err_geo, kErrPartial);
+    asm volatile("" ::"v"(sink));        // the atomics have completed before the ticket
   }
-  if (__ballot(bad != 0) != 0ull && lane_id() == 0) atomicOr(&a.st->err_geo, kErrPartial);
-}
-
-// Single workgroup of 1024: ordered compaction of the lost cells, and the
-// frame state for round 1 (published to the host copy).
-__global__ __launch_bounds__(1024) void k_compact(FrameArgs a, DevParams p) {
-  __shared__ int s_cnt[1024];
-  const int ncell = p.gh * p.gw;
-  const int tid = threadIdx.x;
-  const int chunk = (ncell + 1023) / 1024;
-  const int c0 = min(ncell, tid * chunk), c1 = min(ncell, c0 + chunk);
-  int n = 0;
-  for (int c = c0; c < c1; ++c) n += a.cell_lost[c];
-  s_cnt[tid] = n;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {     // Hillis-Steele inclusive scan
-    int v = tid >= o ? s_cnt[tid - o] : 0;
-    __syncthreads();
-    s_cnt[tid] += v;
-    __syncthreads();
+  if (tid == 0) {
+    const unsigned t = atomicAdd(&st->ticket, 1u);
+    s_last = t + 1 == gridDim.x * gridDim.y;
+    if (s_last) atomicExch(&st->ticket, 0u);
   }
-  int pos = s_cnt[tid] - n;
-  for (int c = c0; c < c1; ++c) {
-    if (a.cell_lost[c]) {
-      a.blk[pos] = c;
+  __syncthreads();
+  if (!s_last) return;
+
+  // ordered compaction: thread t takes a contiguous run of table words
+  const int ncell = p.gh * p.gw, nw = (ncell + 31) >> 5;
+  const int per = (nw + kThreads - 1) / kThreads;
+  const int w0 = min(nw, tid * per), w1 = min(nw, w0 + per);
+  int n = 0;
+  for (int w = w0; w < w1; ++w)
+    n += __popc(__hip_atomic_load(&a.cellbits[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  int tot = 0;
+  int pos = block_excl_scan(n, s_scan, &tot);
+  for (int w = w0; w < w1; ++w) {
+    uint32_t bits = __hip_atomic_load(&a.cellbits[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (bits) {
+      const int b = __ffs(bits) - 1;
+      bits &= bits - 1u;
+      a.blk[pos] = w * 32 + b;
       a.bstate[pos] = 0;
       ++pos;
     }
+    __hip_atomic_store(&a.cellbits[w], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (tid == 1023) {
-    RoundState* st = a.st;
-    st->n_lost = s_cnt[1023];
-    st->remaining = s_cnt[1023];
-    st->round = 1;
+  if (tid == 0) {
+    st->n_lost = tot; st->remaining = tot; st->round = 1;
     st->err = atomicExch(&st->err_geo, 0);
     st->n_hql = 0; st->n_avail = 0; st->sum_avail = 0;
     publish_state(a);
@@ -713,9 +769,8 @@ static int clamp_grid(long long g, int hi) {
 }
 
 hipError_t launch_init(const FrameArgs& a, const DevParams& p, hipStream_t s) {
-  dim3 g((p.width + kThreads - 1) / kThreads, (p.height + p.B - 1) / p.B);
+  dim3 g((p.width + 4 * kThreads - 1) / (4 * kThreads), (p.height + p.B - 1) / p.B);
   hipLaunchKernelGGL(k_init, g, dim3(kThreads), 0, s, a, p);
-  hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, a, p);
   return hipGetLastError();
 }
 
