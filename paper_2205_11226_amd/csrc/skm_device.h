@@ -575,55 +575,61 @@ static __device__ __forceinline__ int phase_candidates(const DevParams& p, const
   }
   if (tid < p.nrad) { sh.bmax[tid] = 0xFFF0000000000000ull; sh.bcnt[tid] = 0; }
   __syncthreads();
-  // wave w writes displacement rows w, w + 4, ..., lanes along the columns;
-  // the masks and offsets of kAhead rows are read before any row is written,
-  // and the expansion bucket comes from a 4-bit-per-radius table in the
-  // parameters
-  constexpr int kAhead = 5;
   const unsigned long long lut0 = p.bucket_lut[0], lut1 = p.bucket_lut[1], lut2 = p.bucket_lut[2];
-  for (int dy0 = wave; dy0 < D2; dy0 += kAhead * nw) {
-    uint64_t ml[kAhead], mh[kAhead];
-    int rbv[kAhead];
-#pragma unroll
-    for (int u = 0; u < kAhead; ++u) {
-      const int dyi = min(dy0 + u * nw, D2 - 1);
-      ml[u] = L.cmask[2 * dyi];
-      mh[u] = L.cmask[2 * dyi + 1];
-      rbv[u] = sh.rowbase[dyi];
+  if (D2 <= 64) {
+    // one 64-bit mask per displacement row; thread t takes (row, group of 8
+    // columns) units t, t + 256, ...: the rank of the group's first column is
+    // the row offset plus the set bits below it, then its set bits in order
+    const int ngr = (D2 + 7) >> 3;
+    const int nunits = D2 * ngr;
+    const float inv_ngr = 1.0f / (float)ngr;
+    for (int u = tid; u < nunits; u += kThreads) {
+      int dyi = (int)(((float)u + 0.5f) * inv_ngr);          // u / ngr (u < 2^12: exact)
+      dyi -= dyi * ngr > u ? 1 : 0;
+      dyi += (dyi + 1) * ngr <= u ? 1 : 0;
+      const int g = u - dyi * ngr;
+      const uint64_t m = L.cmask[2 * dyi];
+      uint32_t bits = (uint32_t)(m >> (8 * g)) & 0xffu;
+      if (!bits) continue;
+      int pos = sh.rowbase[dyi] + __popcll(m & ((1ull << (8 * g)) - 1ull));
+      const int ady = abs(dyi - W);
+      while (bits) {
+        const int dxi = 8 * g + __ffs(bits) - 1;
+        bits &= bits - 1u;
+        const int rho = max(ady, abs(dxi - W));
+        const uint32_t bk = (uint32_t)((rho < 16 ? lut0 : lut1) >> (4 * (rho & 15))) & 15u;
+        L.cand[pos++] = (uint32_t)(dyi * Wd + dxi) | (bk << 14);
+      }
     }
-    if (D2 <= 64) {
-      // one 64-bit mask per row: lane dx tests its bit, its rank is the
-      // count of set bits below it (v_mbcnt)
-      const int adx = abs(lane - W);
+  } else {
+    // wave w writes displacement rows w, w + 4, ..., lanes along the columns;
+    // the masks and offsets of kAhead rows are read before any row is written
+    constexpr int kAhead = 5;
+    for (int dy0 = wave; dy0 < D2; dy0 += kAhead * nw) {
+      uint64_t ml[kAhead], mh[kAhead];
+      int rbv[kAhead];
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        const int dyi = min(dy0 + u * nw, D2 - 1);
+        ml[u] = L.cmask[2 * dyi];
+        mh[u] = L.cmask[2 * dyi + 1];
+        rbv[u] = sh.rowbase[dyi];
+      }
 #pragma unroll
       for (int u = 0; u < kAhead; ++u) {
         const int dyi = dy0 + u * nw;
-        const uint64_t m = ml[u];
-        if (m == 0ull) continue;                  // uniform: no prototype in this row
-        if (dyi < D2 && ((m >> lane) & 1ull)) {
-          const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-          const int rho = max(abs(dyi - W), adx);
-          const uint32_t bk = (uint32_t)((rho < 16 ? lut0 : lut1) >> (4 * (rho & 15))) & 15u;
-          L.cand[rbv[u] + rank] = (uint32_t)(dyi * Wd + lane) | (bk << 14);
-        }
-      }
-      continue;
-    }
-#pragma unroll
-    for (int u = 0; u < kAhead; ++u) {
-      const int dyi = dy0 + u * nw;
-      if (dyi >= D2) break;
-      const int ady = abs(dyi - W);
-      for (int dxi = lane; dxi < D2; dxi += 64) {
-        const bool ok = dxi < 64 ? ((ml[u] >> dxi) & 1ull) : ((mh[u] >> (dxi - 64)) & 1ull);
-        if (ok) {
-          const int rank = dxi < 64 ? __popcll(ml[u] & ((1ull << dxi) - 1ull))
-                                    : __popcll(ml[u]) + __popcll(mh[u] & ((1ull << (dxi - 64)) - 1ull));
-          const int rho = max(ady, abs(dxi - W));
-          const unsigned long long lw = rho < 16 ? lut0 : (rho < 32 ? lut1 : lut2);
-          const uint32_t bk = (uint32_t)(lw >> (4 * (rho & 15))) & 15u;
-          L.cand[rbv[u] + rank] = (uint32_t)(dyi * Wd + dxi) | (bk << 14);
+        if (dyi >= D2) break;
+        const int ady = abs(dyi - W);
+        for (int dxi = lane; dxi < D2; dxi += 64) {
+          const bool ok = dxi < 64 ? ((ml[u] >> dxi) & 1ull) : ((mh[u] >> (dxi - 64)) & 1ull);
+          if (ok) {
+            const int rank = dxi < 64 ? __popcll(ml[u] & ((1ull << dxi) - 1ull))
+                                      : __popcll(ml[u]) + __popcll(mh[u] & ((1ull << (dxi - 64)) - 1ull));
+            const int rho = max(ady, abs(dxi - W));
+            const unsigned long long lw = rho < 16 ? lut0 : (rho < 32 ? lut1 : lut2);
+            const uint32_t bk = (uint32_t)(lw >> (4 * (rho & 15))) & 15u;
+            L.cand[rbv[u] + rank] = (uint32_t)(dyi * Wd + dxi) | (bk << 14);
+          }
         }
       }
     }

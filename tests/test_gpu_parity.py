@@ -185,6 +185,32 @@ def test_strided_frame(ctx):
     assert (out_s[:, 112:] == 0).all()
 
 
+def test_odd_width_misaligned_frame(ctx):
+    """A width and a row pitch that are not multiples of 4 and a frame that
+    starts one byte into its allocation: the geometry kernel's per-column
+    path.  The result must match the oracle and a contiguous copy."""
+    import torch
+    import paper_2205_11226_amd as skm
+    h, w, pitch = 88, 117, 123
+    f = synth.make_luma(h, w, 76, n_bumps=8, n_edges=4)
+    m = np.zeros((h, w), dtype=np.uint8)
+    m[:, :112] = synth.loss_random(h, 112, 8, 0.3, 77)
+    big_f = torch.zeros((h * pitch + 1,), dtype=torch.uint8, device="cuda")
+    big_m = torch.zeros_like(big_f)
+    big_o = torch.zeros_like(big_f)
+    vf = big_f[1:].as_strided((h, w), (pitch, 1))
+    vm = big_m[1:].as_strided((h, w), (pitch, 1))
+    vo = big_o[1:].as_strided((h, w), (pitch, 1))
+    vf.copy_(to_dev(f))
+    vm.copy_(to_dev(m))
+    p = skm.default_params(mode="plain", block=8)
+    o1, i1, x1 = ctx.conceal_device(vf, vm, p, out=vo)
+    o2, i2, x2 = ctx.conceal_device(to_dev(f), to_dev(m), p)
+    assert np.array_equal(o1.cpu().numpy(), o2.cpu().numpy())
+    assert i1.tobytes() == i2.tobytes()
+    check(ctx, f, m, "plain", block=8)
+
+
 def test_no_loss_copies_frame(ctx):
     import paper_2205_11226_amd as skm
     f = synth.make_luma(64, 80, 74)
