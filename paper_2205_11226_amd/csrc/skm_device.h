@@ -231,7 +231,8 @@ static __device__ __forceinline__ int cand_n(uint32_t c) { return (int)(c >> 18)
 //                         distance step it holds rowbits, runbits and cmask.
 //   sel     u32x2         after the weights step, cand and dist together
 //                         hold the selected (window offset, FP32 weight)
-//                         pairs, zero-padded to a multiple of 8
+//                         pairs, padded to a multiple of 8 with weight-0
+//                         copies of the last pair's offset
 //   part    f32 [2*kThreads] cross-group sums of the weighted average;
 //                         aliases qu and utab when they are large enough
 struct EstLds {
@@ -290,7 +291,7 @@ static __device__ __forceinline__ EstLds carve_est_lds(unsigned char* raw, const
 struct BlockShared {
   int NU, M, n_sel;
   int layer, radius_idx, flags, n_cand, n_complete;
-  double lnu, den;
+  double lnu, den, xs;       // xs = 2^24 / den scales the weighted sums
   int red_i[kThreads / 64][4];
   int scan[kThreads / 64];
   unsigned long long bmax[kMaxRadii];
@@ -328,6 +329,16 @@ static __device__ __forceinline__ void pair_dist(uint32_t q, uint32_t pp, int& d
   d = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, df), __builtin_bit_cast(short2v, df), d,
                              false);
   nacc += ~bad & 0x00010001u;
+}
+
+// A known pixel value v (0..255) in one half of a packed int16 pair, read as
+// a binary16 bit pattern: the subnormal v * 2^-24, exactly.  Used as an FMA
+// operand it becomes a mixed-precision FMA with no separate conversion.
+static __device__ __forceinline__ float half_lo(uint32_t pp) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)(pp & 0xffffu));
+}
+static __device__ __forceinline__ float half_hi(uint32_t pp) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)(pp >> 16));
 }
 
 // ---------------------------------------------------------------- phases

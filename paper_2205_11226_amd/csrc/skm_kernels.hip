@@ -499,6 +499,7 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
       sh.n_cand = ncand; sh.n_complete = ncom;
       sh.lnu = ncand > 0 ? lnu_r : NAN;
       sh.den = cs_r;
+      sh.xs = 16777216.0 / cs_r;
     }
   }
   __syncthreads();
@@ -545,70 +546,70 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
     }
     int tot = 0;
     int pos = block_excl_scan(cnt, sh.scan, &tot);     // barriers inside
+    uint32_t last_o = 0u;
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-      if (w_r[k] != 0u) { E.sel[pos] = make_uint2(o_r[k], w_r[k]); ++pos; }
+      if (w_r[k] != 0u) { E.sel[pos] = make_uint2(o_r[k], w_r[k]); ++pos; last_o = o_r[k]; }
     }
-    if (tid < ((tot + 7) & ~7) - tot) E.sel[tot + tid] = make_uint2(0u, 0u);
+    // padding to a multiple of 8, by the lane that wrote the last entry:
+    // weight 0 at that entry's offset, whose prototype pixels are all known
+    // (an unknown pixel read as binary16 is a NaN, and 0 * NaN is NaN)
+    if (cnt > 0 && pos == tot)
+      for (int e = tot; e < ((tot + 7) & ~7); ++e) E.sel[e] = make_uint2(last_o, 0u);
     if (tid == 0) sh.n_sel = tot;
   }
   __syncthreads();
 
   // 7. weighted average of the prototypes.  A lane owns two horizontally
-  //    adjacent pixels (one LDS read of a window pair); candidate groups of
-  //    B*B/2 lanes split the selected candidates in blocks of 8: each lane of
-  //    a group reads the same (offset, weight) -- an LDS broadcast.  Within a
-  //    block FP32 FMA; blocks enter a Kahan-compensated sum.
+  //    adjacent pixels, one window pair per candidate.  A pixel value 0..255
+  //    in the low or high half of a pair, taken as the bits of a binary16
+  //    number, is the subnormal value * 2^-24 (exact), so the mixed-precision
+  //    FMA uses it without a conversion and the sums are scaled back by 2^24
+  //    (exact) at the end.  Candidate groups of B*B/2 lanes split the
+  //    selected candidates in blocks of 8; each lane of a group reads the
+  //    same (offset, weight), an LDS broadcast.  Within a block FP32 FMA;
+  //    blocks enter a Kahan-compensated sum; the groups' sums are added in
+  //    FP64.
   {
     const int nsel = sh.n_sel;
-    const int NP = B2 / 2;                  // pixel pairs per block
-    const int GG = kThreads / NP;           // candidate groups
+    const int NP = B2 / 2;                  // pixel pairs per block (B is 4, 8 or 16)
+    const int GG = kThreads / NP;           // candidate groups, at least 2
     const int h = tid / NP, q = tid - h * NP;
     const int py = (2 * q) / B, px = 2 * q - py * B;
-    const int poff = (r + py) * Wd + (r + px);
+    const uint32_t* wq = E.winp + (r + py) * Wd + (r + px);
     float acc0 = 0.f, acc1 = 0.f, comp0 = 0.f, comp1 = 0.f;
     for (int j0 = 8 * h; j0 < nsel; j0 += 8 * GG) {
       uint2 sv[8];
 #pragma unroll
       for (int t = 0; t < 8; ++t) sv[t] = E.sel[j0 + t];
       uint32_t pv[8];
+      float wv[8];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) pv[t] = E.winp[(int)sv[t].x + poff];
+      for (int t = 0; t < 8; ++t) {
+        pv[t] = wq[(int)sv[t].x];
+        wv[t] = __uint_as_float(sv[t].y);
+      }
       float s0 = 0.f, s1 = 0.f;
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
-        const float w = __uint_as_float(sv[t].y);
-        s0 = fmaf(w, (float)(pv[t] & 0xffu), s0);
-        s1 = fmaf(w, (float)((pv[t] >> 16) & 0xffu), s1);
+        s0 = fmaf(wv[t], half_lo(pv[t]), s0);
+        s1 = fmaf(wv[t], half_hi(pv[t]), s1);
       }
       float y = s0 - comp0, tt = acc0 + y;
       comp0 = (tt - acc0) - y; acc0 = tt;
       y = s1 - comp1; tt = acc1 + y;
       comp1 = (tt - acc1) - y; acc1 = tt;
     }
-    float v0 = acc0 - comp0, v1 = acc1 - comp1;
-    if (GG > 1) {
-      E.part[2 * tid] = v0;
-      E.part[2 * tid + 1] = v1;
-      __syncthreads();
-      if (h == 0) {
-        double t0 = 0.0, t1 = 0.0;
-        for (int hh = 0; hh < GG; ++hh) {
-          t0 += (double)E.part[2 * (hh * NP + q)];
-          t1 += (double)E.part[2 * (hh * NP + q) + 1];
-        }
-        v0 = 0.f; v1 = 0.f;
-        const double x0h = t0 / sh.den, x1h = t1 / sh.den;
-        uint8_t* o = a.work + (size_t)(y0 + py) * p.stride + x0 + px;
-        o[0] = (uint8_t)fmin(fmax(floor(x0h + 0.5), 0.0), 255.0);
-        o[1] = (uint8_t)fmin(fmax(floor(x1h + 0.5), 0.0), 255.0);
-        if (a.xhat && i < a.cap) {
-          a.xhat[(size_t)i * B2 + 2 * q] = (float)x0h;
-          a.xhat[(size_t)i * B2 + 2 * q + 1] = (float)x1h;
-        }
+    *reinterpret_cast<float2*>(E.part + 2 * tid) = make_float2(acc0 - comp0, acc1 - comp1);
+    __syncthreads();
+    if (h == 0) {
+      double t0 = 0.0, t1 = 0.0;
+      for (int hh = 0; hh < GG; ++hh) {
+        const float2 v = *reinterpret_cast<const float2*>(E.part + 2 * (hh * NP + q));
+        t0 += (double)v.x;
+        t1 += (double)v.y;
       }
-    } else {
-      const double x0h = (double)v0 / sh.den, x1h = (double)v1 / sh.den;
+      const double x0h = t0 * sh.xs, x1h = t1 * sh.xs;
       uint8_t* o = a.work + (size_t)(y0 + py) * p.stride + x0 + px;
       o[0] = (uint8_t)fmin(fmax(floor(x0h + 0.5), 0.0), 255.0);
       o[1] = (uint8_t)fmin(fmax(floor(x1h + 0.5), 0.0), 255.0);
