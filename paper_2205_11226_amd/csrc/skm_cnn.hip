@@ -600,11 +600,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
   gate_clear_padding(G);
   const GateWeights W = load_gate_weights(pk, wq);
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
-  // XCD x (workgroups x, x + 8, ...) takes a contiguous range of blocks, so
-  // neighbouring windows share its L2
-  const int lw = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
-  const int per = (n_lost + gridDim.x - 1) / gridDim.x;
-  const int i_end = min(n_lost, (lw + 1) * per);
+  // XCD x (workgroups x, x + 8, ...) takes the x-th contiguous eighth of the
+  // blocks, the same eighth as in the estimation kernel, so that the window
+  // pixels read here are still in that XCD's L2 when the block is estimated;
+  // its workgroups split the eighth evenly (the grid is a multiple of 8)
+  const int per8 = (n_lost + 7) >> 3, xcd = blockIdx.x & 7;
+  const int xend = min(n_lost, (xcd + 1) * per8);
+  const int pw = (per8 + (int)(gridDim.x >> 3) - 1) / (int)(gridDim.x >> 3);
+  const int i_begin = min(xend, xcd * per8 + (int)(blockIdx.x >> 3) * pw);
+  const int i_end = min(xend, i_begin + pw);
   // ring of the block in window coordinates: footprint rows/columns
   // [f0, f1), block [b0, b1)
   const int b0 = kP / 2 - p.B / 2, b1 = b0 + p.B, f0 = b0 - p.r, f1 = b1 + p.r;
@@ -631,7 +635,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     }
   };
   int nx_state = 1;                        // state of the next block travels with its pixels
-  const int i_begin = lw * per;
   if (i_begin < i_end) { load_block(i_begin); nx_state = a.bstate[i_begin]; }
   int wg_nq = 0, wg_max = 0;
   for (int i = i_begin; i < i_end; ++i) {

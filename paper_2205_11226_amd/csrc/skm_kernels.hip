@@ -174,7 +174,17 @@ __global__ __launch_bounds__(kThreads) void k_round_prep(FrameArgs a, DevParams 
   const int lane = lane_id(), wave = wave_id();
   const int F = p.F, B = p.B, r = p.r;
   int my_nq = 0, my_mx = 0;
-  for (int i = blockIdx.x * (kThreads / 64) + wave; i < n_lost; i += gridDim.x * (kThreads / 64)) {
+  // with a grid of whole XCD groups, XCD x takes the x-th contiguous eighth
+  // of the blocks, as in the estimation kernel (its L2 then holds the rings)
+  constexpr int nwv = kThreads / 64;
+  int i0 = blockIdx.x * nwv + wave, i1 = n_lost, step = gridDim.x * nwv;
+  if ((gridDim.x & 7) == 0) {
+    const int per8 = (n_lost + 7) >> 3, xcd = blockIdx.x & 7;
+    i0 = xcd * per8 + (int)(blockIdx.x >> 3) * nwv + wave;
+    i1 = min(n_lost, (xcd + 1) * per8);
+    step = (int)(gridDim.x >> 3) * nwv;
+  }
+  for (int i = i0; i < i1; i += step) {
     if (a.bstate[i] != 0) continue;
     const int cell = a.blk[i];
     const int by = cell / p.gw, bx = cell - by * p.gw;
@@ -796,7 +806,10 @@ static hipError_t launch_main(const FrameArgs& a, const DevParams& p, int max_bl
   return hipGetLastError();
 }
 
-int prep_grid_for(int max_blocks) { return clamp_grid((max_blocks + 3) / 4, kPrepGridMax); }
+int prep_grid_for(int max_blocks) {
+  const int g = clamp_grid((max_blocks + 3) / 4, kPrepGridMax);
+  return g >= 8 ? (g + 7) / 8 * 8 : g;       // whole XCD groups (kPrepGridMax is one)
+}
 
 hipError_t launch_prep(const FrameArgs& a, const DevParams& p, int max_blocks, hipStream_t s) {
   hipLaunchKernelGGL(k_round_prep, dim3(p.prep_grid), dim3(kThreads), 0, s, a, p);
