@@ -688,6 +688,19 @@ static __device__ __forceinline__ void pair_dist6(uint32_t q, uint32_t pp, int& 
   nbad = __builtin_amdgcn_sdot2(bad, bad, nbad, false);
 }
 
+// pair_dist6 for a context pair known in both halves: only the window side
+// can be unknown, one operation fewer.
+static __device__ __forceinline__ void pair_dist5(uint32_t q, uint32_t pp, int& d, int& nbad) {
+  const short2v qa = __builtin_bit_cast(short2v, q), pa = __builtin_bit_cast(short2v, pp);
+  const short2v bad = pa >> (short2v){15, 15};                 // -1 where unknown
+  const uint32_t diff = __builtin_bit_cast(uint32_t, (short2v)(qa - pa));
+  uint32_t dm;
+  asm("v_bfi_b32 %0, %1, 0, %2" : "=v"(dm) : "v"(__builtin_bit_cast(uint32_t, bad)), "v"(diff));
+  const short2v df = __builtin_bit_cast(short2v, dm);
+  d = __builtin_amdgcn_sdot2(df, df, d, false);
+  nbad = __builtin_amdgcn_sdot2(bad, bad, nbad, false);
+}
+
 // Distance of one candidate per lane (footprint origin `base`; a lane
 // without a candidate passes 0 and ignores the result).  Every lane reads
 // the same unit (q pair, offset) -- an LDS broadcast -- and its own window
@@ -739,7 +752,8 @@ struct FixedGeom {
 // cand_distance_wave for a fixed geometry: the window offset of every unit
 // is a compile-time constant, so each lane's window reads are immediate
 // offsets from its own footprint origin and do not wait for the unit table.
-template <class G>
+// QKnown: every context pixel of the block is known (pair_dist5).
+template <class G, bool QKnown>
 static __device__ __forceinline__ void cand_distance_fixed(const MainLds& L, int base, int& d_out,
                                                            int& n_out) {
   int d = 0, nbad = 0;
@@ -764,7 +778,10 @@ static __device__ __forceinline__ void cand_distance_fixed(const MainLds& L, int
       }
     }
 #pragma unroll
-    for (int t = 0; t < 16; ++t) pair_dist6(qv[k & 1][t], pv[k & 1][t], d, nbad);
+    for (int t = 0; t < 16; ++t) {
+      if (QKnown) pair_dist5(qv[k & 1][t], pv[k & 1][t], d, nbad);
+      else pair_dist6(qv[k & 1][t], pv[k & 1][t], d, nbad);
+    }
     // pin the sums here: otherwise the (pure) dot products sink past the
     // loop and every masked difference stays live until the end
     asm volatile("" : "+v"(d), "+v"(nbad));

@@ -15,6 +15,8 @@
 //   transfer of estimates into S   end of Sec. "K-MMSE overview"
 #include <math.h>
 
+#include <type_traits>
+
 #include "skm_device.h"
 
 namespace skm {
@@ -326,7 +328,8 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
   const int NU = sh.NU;
   if (dist_only) stage_issue(a, p, SG, y0 - r - W, SR);
   stage_finish(a, p, E.m, SG, y0 - r - W, SR);
-  phase_context(p, E.m, sh, NU);
+  // every context pixel known: the distance step masks the window side only
+  const bool qfull = phase_context(p, E.m, sh, NU).n0 == 2 * NU;
 
   // 3. admissible prototypes in raster order
   phase_candidates(p, E.m, sh);
@@ -339,35 +342,40 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
   const double two_s2 = 2.0 * p.sigma2;
   int nc = 0, ncomp = 0;
   const int NU32 = align32(NU);
-  for (int j0 = wave * 64; j0 < M; j0 += kThreads) {       // uniform per wave
-    const int j = j0 + lane;
-    const bool act = j < M;
-    const uint32_t cj = act ? E.cand[j] : 0u;
-    const int base = cand_off(cj);
-    int d, n;
-    if (FG)
-      cand_distance_fixed<Geom16>(E.m, base, d, n);
-    else
-      cand_distance_wave(E.m, base, NU32, d, n);
-    if (!act) continue;
-    const bool ok = n >= nmin;
-    nc += ok;
-    ncomp += ok && n == n0;
-    if (dist_only) {
-      const int t = (base / Wd) * D2 + (base % Wd);
-      a.dist[(size_t)i * p.ND + t] = ok ? d : -1;
-      a.cnt[(size_t)i * p.ND + t] = ok ? n : 0;
-      continue;
+  // one copy of the loop per distance routine, chosen once per block
+  auto dist_loop = [&](auto qknown) {
+    for (int j0 = wave * 64; j0 < M; j0 += kThreads) {     // uniform per wave
+      const int j = j0 + lane;
+      const bool act = j < M;
+      const uint32_t cj = act ? E.cand[j] : 0u;
+      const int base = cand_off(cj);
+      int d, n;
+      if (FG)
+        cand_distance_fixed<Geom16, decltype(qknown)::value>(E.m, base, d, n);
+      else
+        cand_distance_wave(E.m, base, NU32, d, n);
+      if (!act) continue;
+      const bool ok = n >= nmin;
+      nc += ok;
+      ncomp += ok && n == n0;
+      if (dist_only) {
+        const int t = (base / Wd) * D2 + (base % Wd);
+        a.dist[(size_t)i * p.ND + t] = ok ? d : -1;
+        a.cnt[(size_t)i * p.ND + t] = ok ? n : 0;
+        continue;
+      }
+      E.cand[j] = cj | ((uint32_t)n << 18);
+      E.dist[j] = ok ? (uint32_t)d : ~0u;
+      if (ok) {
+        const int b = cand_bucket(cj);
+        const double e = -(double)d / ((double)n * two_s2);
+        atomicMin(&sh.bmax[b], (unsigned long long)__double_as_longlong(e));
+        atomicAdd(&sh.bcnt[b], 1);
+      }
     }
-    E.cand[j] = cj | ((uint32_t)n << 18);
-    E.dist[j] = ok ? (uint32_t)d : ~0u;
-    if (ok) {
-      const int b = cand_bucket(cj);
-      const double e = -(double)d / ((double)n * two_s2);
-      atomicMin(&sh.bmax[b], (unsigned long long)__double_as_longlong(e));
-      atomicAdd(&sh.bcnt[b], 1);
-    }
-  }
+  };
+  if (FG && qfull) dist_loop(std::true_type{});
+  else dist_loop(std::false_type{});
   if (dist_only) {
     // displacements without an admissible prototype (cmask is intact: the
     // distance step wrote no LDS)
