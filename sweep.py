@@ -3,12 +3,12 @@
 Re-runs, on synthetic frames, the three studies of the paper's section on
 layer switching and profile selection and of its still-image results:
 
-* E1, flatness threshold T_phi: BRL where phi(y0) <= T_phi, full K-MMSE
+* flatness threshold T_phi: BRL where phi(y0) <= T_phi, full K-MMSE
   elsewhere (IDL switched off), quality gain and time reduction relative to
   full K-MMSE as T_phi grows;
-* E2, normalisation threshold T_nu (log scale): IDL where nu(y0) >= T_nu,
+* normalisation threshold T_nu (log scale): IDL where nu(y0) >= T_nu,
   full K-MMSE elsewhere (BRL switched off);
-* E7, the three named profiles (express, efficient, excellent: T_phi = 20 and
+* the three named profiles (express, efficient, excellent: T_phi = 20 and
   T_nu = 0.01, 0.1, 100), as in the profile table.
 
 "Full K-MMSE" is mode ``full``: HQL where the block has enough candidates
@@ -90,9 +90,9 @@ PROFILES = (("express", 20.0, 0.01), ("efficient", 20.0, 0.1), ("excellent", 20.
 
 def settings():
     """(study, label, t_phi, t_nu) for every setting of the three studies."""
-    out = [("E1", f"T_phi={t:g}", t, BIG) for t in T_PHI_SWEEP]
-    out += [("E2", f"T_nu={t:g}", -1.0, t) for t in T_NU_SWEEP]
-    out += [("E7", name, tphi, tnu) for name, tphi, tnu in PROFILES]
+    out = [("flatness", f"T_phi={t:g}", t, BIG) for t in T_PHI_SWEEP]
+    out += [("normalisation", f"T_nu={t:g}", -1.0, t) for t in T_NU_SWEEP]
+    out += [("profiles", name, tphi, tnu) for name, tphi, tnu in PROFILES]
     return out
 
 
@@ -120,7 +120,7 @@ def run_one(ctx, fd, md, prm, reps: int):
     times = []
     s = torch.cuda.current_stream()
     for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0, flat = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)
         ctx.conceal_device(fd, md, prm, out=out, want_info=False, want_xhat=False)
         e1.record(s)
@@ -189,7 +189,7 @@ def summarise(rows):
 
 def markdown(summary) -> str:
     lines = []
-    for study in ("E1", "E2", "E7"):
+    for study in ("flatness", "normalisation", "profiles"):
         lines.append(f"\n{study}\n")
         lines.append("| setting | loss | dPSNR (dB) | dSSIM x100 | time reduction (x) | ms/frame |"
                      " BRL | IDL | HQL | IDL, no HQL |")

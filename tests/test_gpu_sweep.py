@@ -64,15 +64,15 @@ def test_sweep_runs_every_setting(ctx):
     # the dispersed lattice is concealed in one round, so raising T_phi can
     # only move blocks to BRL (later rounds of random loss start from other
     # concealed pixels)
-    brl = [by[("E1", f"T_phi={t:g}", "dispersed")]["brl"] for t in sweep.T_PHI_SWEEP]
+    brl = [by[("flatness", f"T_phi={t:g}", "dispersed")]["brl"] for t in sweep.T_PHI_SWEEP]
     assert all(b1 >= b0 for b0, b1 in zip(brl, brl[1:]))
     # and raising T_nu can only move blocks from IDL to full K-MMSE, which on
     # the lattice is IDL over the whole window (no complete candidates)
-    d2 = [by[("E2", f"T_nu={t:g}", "dispersed")] for t in sweep.T_NU_SWEEP]
+    d2 = [by[("normalisation", f"T_nu={t:g}", "dispersed")] for t in sweep.T_NU_SWEEP]
     assert all(s["hql"] == 0 for s in d2)
     full = [s["idl_full"] for s in d2]
     assert all(b1 >= b0 for b0, b1 in zip(full, full[1:]))
     # BRL only where a block has no admissible candidate, whatever T_nu
     assert len({s["brl"] for s in d2}) == 1
     md = sweep.markdown(summ)
-    assert "E1" in md and "E7" in md and "excellent" in md
+    assert "flatness" in md and "profiles" in md and "excellent" in md

@@ -64,24 +64,24 @@ def test_ssim_rejects_small_planes():
 
 def test_study_settings():
     st = sweep.settings()
-    e1 = [s for s in st if s[0] == "E1"]
-    e2 = [s for s in st if s[0] == "E2"]
-    e7 = {s[1]: (s[2], s[3]) for s in st if s[0] == "E7"}
+    flat = [s for s in st if s[0] == "flatness"]
+    norm = [s for s in st if s[0] == "normalisation"]
+    prof = {s[1]: (s[2], s[3]) for s in st if s[0] == "profiles"}
     # flatness sweep: IDL never accepted; the paper's profile value 20 included
-    assert all(s[3] == sweep.BIG for s in e1) and any(s[2] == 20.0 for s in e1)
+    assert all(s[3] == sweep.BIG for s in flat) and any(s[2] == 20.0 for s in flat)
     # normalisation sweep: BRL never taken (phi >= 0 > T_phi), log-spaced T_nu
-    assert all(s[2] < 0 for s in e2)
-    tn = [s[3] for s in e2]
+    assert all(s[2] < 0 for s in norm)
+    tn = [s[3] for s in norm]
     assert np.allclose(np.diff(np.log10(tn)), 1.0)
     assert {0.01, 0.1, 100.0} <= set(np.round(tn, 12))
     # the three named profiles of the paper
-    assert e7 == {"express": (20.0, 0.01), "efficient": (20.0, 0.1),
+    assert prof == {"express": (20.0, 0.01), "efficient": (20.0, 0.1),
                   "excellent": (20.0, 100.0)}
 
 
 def test_summary_gains_and_reduction():
     lay = {"brl": 1, "idl": 2, "hql": 1, "idl_full": 0}
-    rows = [dict(study="E7", label="x", pattern="random", frame=f, psnr=30.0 + f, ssim=0.9,
+    rows = [dict(study="profiles", label="x", pattern="random", frame=f, psnr=30.0 + f, ssim=0.9,
                  ms=1.0, layers=lay, full_psnr=31.0 + f, full_ssim=0.95, full_ms=4.0,
                  full_layers=lay) for f in range(2)]
     (s,) = sweep.summarise(rows)
