@@ -16,8 +16,11 @@ import math
 
 
 def _ring(b, r):
-    return [(oy, ox) for oy in range(-r, b + r) for ox in range(-r, b + r)
+    """Context positions relative to the block origin: the ring of width r,
+    then the block's own positions (they count where received)."""
+    ring = [(oy, ox) for oy in range(-r, b + r) for ox in range(-r, b + r)
             if not (0 <= oy < b and 0 <= ox < b)]
+    return ring + [(oy, ox) for oy in range(b) for ox in range(b)]
 
 
 def _px(u, av, y, x):
@@ -46,7 +49,7 @@ def candidates(u, av, by, bx, b, r, W, pct):
     out = []
     for dy in range(-W, W + 1):
         for dx in range(-W, W + 1):
-            if dx == 0 and dy == 0:
+            if abs(dx) < b and abs(dy) < b:      # overlaps the block itself
                 continue
             py, px = by * b + dy, bx * b + dx
             if py < 0 or px < 0 or py + b > h or px + b > w:
@@ -251,7 +254,7 @@ def conceal(frame, mask, b, r, W, sigma2=10.0, t_phi=20.0, t_nu=0.1, step=4, pct
     av = [[mask[y][x] == 0 for x in range(w)] for y in range(h)]
     u = [[frame[y][x] if av[y][x] else 0 for x in range(w)] for y in range(h)]
     cells = [(by, bx) for by in range(h // b) for bx in range(w // b)
-             if all(mask[by * b + i][bx * b + j] for i in range(b) for j in range(b))]
+             if any(mask[by * b + i][bx * b + j] for i in range(b) for j in range(b))]
     xh_all, layers = {}, {}
     pending = list(cells)
     while pending:
@@ -285,7 +288,8 @@ def conceal(frame, mask, b, r, W, sigma2=10.0, t_phi=20.0, t_nu=0.1, step=4, pct
             if not done:
                 want = mode in ("full", "profile")
                 comp = [c for c in cs if c["n"] == sum(m0)]
-                if want and len(comp) >= max(2, min_hql):
+                own = any(av[by * b + i][bx * b + j] for i in range(b) for j in range(b))
+                if want and len(comp) >= max(2, min_hql) and not own:
                     ys = [[c["y"][k] for k in range(len(m0)) if m0[k]] for c in comp]
                     layer = 2
                     xh = hql([c["x"] for c in comp], ys, known, [c["d"] for c in comp],
@@ -296,6 +300,8 @@ def conceal(frame, mask, b, r, W, sigma2=10.0, t_phi=20.0, t_nu=0.1, step=4, pct
         for (by, bx), xh, layer in res:
             for i in range(b):
                 for j in range(b):
+                    if av[by * b + i][bx * b + j]:
+                        continue                 # a received pixel of the block
                     v = min(255, max(0, math.floor(xh[i * b + j] + 0.5)))
                     u[by * b + i][bx * b + j] = v
                     av[by * b + i][bx * b + j] = True

@@ -8,16 +8,21 @@ Square Error Estimator for Accelerated Image Error Concealment" (arXiv
 2205.11226).  Section names below refer to it.
 
 Geometry (block mode).  The paper estimates 2x2 patches from a 6x6 context
-(Sec. "Reconstruction framework").  Here a whole lost B x B block is x0; its
-context y0 is the ring of width r around it, restricted to available pixels
-(mask m0); candidates z_j are all displacements (dx, dy) in [-W, W]^2 \\ {0}
-whose B x B prototype lies in the frame and is fully available.  A candidate's
+(Sec. "Reconstruction framework").  Here a B x B cell of the block grid that
+holds any lost pixel is x0; its context y0 is the ring of width r around it
+and the cell's own received pixels (the paper's loss patterns may have any
+shape, Sec. "Reconstruction framework"), restricted to available pixels (mask
+m0); candidates z_j are all displacements (dx, dy) in [-W, W]^2 whose B x B
+prototype does not overlap the cell, lies in the frame and is fully
+available.  A candidate's
 ring may be partly unavailable: its distance to y0 is taken over the pixels
 known in both rings (count n_j) and normalised by n_j, the "average
 distortion per context pixel" that the IDL bandwidth sigma^2 N_y expresses
 (Sec. "Intermediate dynamic layer").  Candidates with n_j below
 ceil(min_overlap_pct * |m0| / 100) are dropped.  HQL, whose covariance needs
-every coordinate, uses only candidates whose ring covers all of m0.
+every coordinate, uses only candidates whose ring covers all of m0, and is
+not used for a cell with received pixels (such a cell takes IDL over the
+whole window instead).
 
 Layers and gate (Sec. "Scalable K-MMSE estimator", Sec. "Layer switching"):
 * BRL: mean of y0 (eq. "mean"), chosen when phi = max(y0) - min(y0) <= T_phi;
@@ -29,10 +34,11 @@ Layers and gate (Sec. "Scalable K-MMSE estimator", Sec. "Layer switching"):
 * HQL: full K-MMSE with covariance-scaled bandwidth (eqs. "kmmse",
   "weights", "bandwidthScaled", "epsy", "epsx").
 
-Lost blocks are concealed in Jacobi rounds: every block whose available ring
-holds at least r*B pixels is estimated from the state at the start of the
-round, then all of them become available (the transfer of x0 into S, end of
-Sec. "K-MMSE overview").
+Lost blocks are concealed in Jacobi rounds: every block whose available
+context holds at least r*B pixels is estimated from the state at the start of
+the round, then its lost pixels take the rounded estimates and become
+available (the transfer of x0 into S, end of Sec. "K-MMSE overview"); its
+received pixels are never changed.
 """
 from __future__ import annotations
 
@@ -62,7 +68,7 @@ MODES = ("plain", "full", "profile", "brl", "idl", "cnn")
 
 
 class UnsupportedLoss(ValueError):
-    """Loss mask with lost pixels outside whole in-frame B x B cells."""
+    """Loss mask with lost pixels outside the in-frame B x B cells."""
 
 
 @dataclass(frozen=True)
@@ -94,22 +100,29 @@ def ring_offsets(b: int, r: int) -> np.ndarray:
     return np.asarray(out, dtype=np.int64).reshape(-1, 2)
 
 
+def context_offsets(b: int, r: int) -> np.ndarray:
+    """(oy, ox) of every context position: the ring (raster order), then the
+    block's own B x B positions (raster order), which count where received."""
+    inner = [(oy, ox) for oy in range(b) for ox in range(b)]
+    return np.concatenate([ring_offsets(b, r),
+                           np.asarray(inner, dtype=np.int64).reshape(-1, 2)])
+
+
 def lost_cells(mask: np.ndarray, b: int) -> list[tuple[int, int]]:
-    """Lost cells (by, bx) in raster order; every lost pixel must lie in a
-    fully lost B x B cell that is entirely inside the frame."""
+    """Cells (by, bx) in raster order that hold at least one lost pixel; every
+    lost pixel must lie in a B x B cell that is entirely inside the frame."""
     h, w = mask.shape
     lost = mask != 0
     gh, gw = h // b, w // b
     cells = []
     covered = np.zeros_like(lost)
+    covered[:gh * b, :gw * b] = True
+    if (lost & ~covered).any():
+        raise UnsupportedLoss("lost pixels outside the in-frame B x B cells")
     for by in range(gh):
         for bx in range(gw):
-            c = lost[by * b:(by + 1) * b, bx * b:(bx + 1) * b]
-            if c.all():
+            if lost[by * b:(by + 1) * b, bx * b:(bx + 1) * b].any():
                 cells.append((by, bx))
-                covered[by * b:(by + 1) * b, bx * b:(bx + 1) * b] = True
-    if (lost & ~covered).any():
-        raise UnsupportedLoss("lost pixels outside whole in-frame B x B cells")
     return cells
 
 
@@ -125,9 +138,15 @@ def _gather(u: np.ndarray, avail: np.ndarray, ys: np.ndarray, xs: np.ndarray):
 
 
 def block_context(u, avail, by, bx, p: Params):
-    """Context y0 and its mask m0 over the ring (values 0 where unknown)."""
-    off = ring_offsets(p.block, p.ring)
+    """Context y0 and its mask m0 over the ring and the block's own positions
+    (values 0 where unknown)."""
+    off = context_offsets(p.block, p.ring)
     return _gather(u, avail, by * p.block + off[:, 0], bx * p.block + off[:, 1])
+
+
+def is_partial(m0: np.ndarray, p: Params) -> bool:
+    """True when the block holds received pixels (its own context positions)."""
+    return bool(m0[-p.block * p.block:].any())
 
 
 @dataclass
@@ -137,8 +156,8 @@ class Candidates:
     n: np.ndarray         # |m0 and m_j|
     d: np.ndarray         # sum over m0 and m_j of (y0 - y_j)^2, exact integer
     x: np.ndarray         # (M, B*B) prototypes
-    y: np.ndarray         # (M, N_ring) context vectors (0 where unknown)
-    m: np.ndarray         # (M, N_ring) candidate ring availability
+    y: np.ndarray         # (M, N_ctx) context vectors (0 where unknown)
+    m: np.ndarray         # (M, N_ctx) candidate context availability
 
     @property
     def size(self) -> int:
@@ -152,19 +171,21 @@ class Candidates:
 def candidate_set(u, avail, by, bx, p: Params, y0, m0) -> Candidates:
     """All admissible candidates of block (by, bx) with their exact distances.
 
-    A displacement is admissible when its prototype is in the frame and fully
-    available and its ring shares at least ceil(min_overlap_pct |m0| / 100)
-    (and at least one) known pixels with m0.
+    A displacement is admissible when its prototype does not overlap the
+    block, is in the frame and fully available, and its context shares at
+    least ceil(min_overlap_pct |m0| / 100) (and at least one) known pixels
+    with m0.  At the block's own positions a candidate's context is its
+    prototype (always available).
     """
     b, W = p.block, p.window
     h, w = u.shape
-    off = ring_offsets(b, p.ring)
+    off = context_offsets(b, p.ring)
     n0 = int(m0.sum())
     nmin = max(1, (p.min_overlap_pct * n0 + 99) // 100)
     dys, dxs = np.meshgrid(np.arange(-W, W + 1), np.arange(-W, W + 1), indexing="ij")
     dys = dys.ravel()
     dxs = dxs.ravel()
-    keep = ~((dys == 0) & (dxs == 0))
+    keep = ~((np.abs(dys) < b) & (np.abs(dxs) < b))
     dys, dxs = dys[keep], dxs[keep]
     py = by * b + dys
     px = bx * b + dxs
@@ -394,6 +415,7 @@ def estimate_block(u, avail, by, bx, p: Params, cnn_gate=None):
     if mode == "brl":
         return brl, info
     want_hql = None
+    partial = is_partial(m0, p)
     if mode == "profile" and phi <= p.t_phi:
         return brl, info
     cnn_choice = None
@@ -435,7 +457,7 @@ def estimate_block(u, avail, by, bx, p: Params, cnn_gate=None):
         want_hql = True
 
     if want_hql:
-        if info["n_complete"] >= max(2, p.min_hql_cands):
+        if info["n_complete"] >= max(2, p.min_hql_cands) and not partial:
             info["layer"] = LAYER_HQL
             xs = c.x[complete]
             ys = c.y[complete][:, m0]
@@ -488,7 +510,8 @@ def conceal(frame: np.ndarray, mask: np.ndarray, p: Params, cnn_gate=None):
                     info["flags"] |= FLAG_EMPTY_CTX
                 xh = np.full((b, b), v)
                 xhats[(by, bx)] = xh
-                out[by * b:(by + 1) * b, bx * b:(bx + 1) * b] = _round_pixel(xh)
+                lost = ~avail[by * b:(by + 1) * b, bx * b:(bx + 1) * b]
+                out[by * b:(by + 1) * b, bx * b:(bx + 1) * b][lost] = _round_pixel(xh)[lost]
                 infos.append(info)
             break
         counts = {c: int(block_context(u, avail, c[0], c[1], p)[1].sum()) for c in pending}
@@ -510,9 +533,11 @@ def conceal(frame: np.ndarray, mask: np.ndarray, p: Params, cnn_gate=None):
             results.append(((by, bx), xh.reshape(b, b), info))
         for (by, bx), xh, info in results:
             v = _round_pixel(xh)
-            out[by * b:(by + 1) * b, bx * b:(bx + 1) * b] = v
-            u[by * b:(by + 1) * b, bx * b:(bx + 1) * b] = v
-            avail[by * b:(by + 1) * b, bx * b:(bx + 1) * b] = True
+            sl = (slice(by * b, (by + 1) * b), slice(bx * b, (bx + 1) * b))
+            lost = ~avail[sl]                 # received pixels keep their values
+            out[sl][lost] = v[lost]
+            u[sl][lost] = v[lost]
+            avail[sl] = True
             xhats[(by, bx)] = xh
             infos.append(info)
         done = set(eligible)

@@ -61,11 +61,71 @@ def test_dispersed_pattern_is_quarter_loss_with_received_neighbours():
                     assert (by + ddy, bx + ddx) not in s
 
 
-def test_partial_cell_loss_is_rejected():
-    m = np.zeros((32, 32), np.uint8)
-    m[3:9, 3:9] = 1
+def test_lost_pixels_outside_the_cells_are_rejected():
+    m = np.zeros((36, 32), np.uint8)
+    m[33, 5] = 1                          # rows 32..35 hold no full 8 x 8 cell
     with pytest.raises(UnsupportedLoss):
         lost_cells(m, 8)
+
+
+def test_any_lost_pixel_makes_its_cell_a_block():
+    m = np.zeros((32, 32), np.uint8)
+    m[3:9, 3:9] = 1                       # touches cells (0,0) (0,1) (1,0) (1,1)
+    m[20, 30] = 1                         # one pixel of cell (2,3)
+    assert lost_cells(m, 8) == [(0, 0), (0, 1), (1, 0), (1, 1), (2, 3)]
+
+
+def partial_mask(h, w, b, seed, frac=0.5, rate=0.25):
+    """Cells lost with probability ``rate``; a share ``frac`` of them keep a
+    random subset of their pixels (arbitrary-shape loss)."""
+    rng = np.random.default_rng(seed)
+    m = np.zeros((h, w), np.uint8)
+    for by in range(h // b):
+        for bx in range(w // b):
+            if rng.uniform() < rate:
+                c = np.ones((b, b), np.uint8)
+                if rng.uniform() < frac:
+                    c = (rng.uniform(size=(b, b)) < rng.uniform(0.3, 0.9)).astype(np.uint8)
+                    c[rng.integers(b), rng.integers(b)] = 1
+                m[by * b:(by + 1) * b, bx * b:(bx + 1) * b] = c
+    return m
+
+
+def test_received_pixels_of_a_lost_cell_are_kept():
+    f = tiny_frame(31, 48, 48)
+    m = partial_mask(48, 48, 8, 32, frac=1.0, rate=0.3)
+    assert ((m != 0).sum() > 0) and len(lost_cells(m, 8)) > 0
+    for mode in ("plain", "profile", "full"):
+        out, _, _ = conceal(f, m, Params(block=8, ring=2, window=8, min_hql_cands=8,
+                                         mode=mode))
+        assert np.array_equal(out[m == 0], f[m == 0])
+
+
+def test_constant_frame_with_arbitrary_loss_is_restored():
+    # every context and prototype holds the same value: BRL gives it, and all
+    # IDL distances are 0 so the weighted average of equal prototypes gives it
+    f = np.full((48, 48), 93, np.uint8)
+    m = partial_mask(48, 48, 8, 33, frac=0.7, rate=0.4)
+    for mode in ("plain", "profile", "idl", "brl"):
+        out, xh, _ = conceal(f, m, Params(block=8, ring=2, window=8, mode=mode))
+        assert np.array_equal(out, f)
+        for v in xh.values():
+            np.testing.assert_allclose(v, 93.0, rtol=0, atol=1e-12)
+
+
+def test_partial_cells_never_take_hql():
+    f = tiny_frame(34, 40, 40)
+    m = cells_mask(40, 40, 8, [(2, 2)])
+    m[16, 16] = 0                          # one received pixel in the cell
+    p = Params(block=8, ring=2, window=12, min_hql_cands=8, mode="full")
+    out, xh, info = conceal(f, m, p)
+    (i,) = info
+    assert i["layer"] == LAYER_IDL and i["flags"] & 2
+    assert i["n_ctx"] == (8 + 4) ** 2 - 64 + 1
+    assert out[16, 16] == f[16, 16]
+    # the same cell fully lost does reach HQL (enough complete candidates)
+    _, _, info2 = conceal(f, cells_mask(40, 40, 8, [(2, 2)]), p)
+    assert info2[0]["layer"] == LAYER_HQL
 
 
 # ------------------------------------------------------------------ distances
@@ -124,6 +184,32 @@ def test_vectorised_oracle_equals_loop_oracle(seed, cells, mode, tnu, win):
         k = (i["by"], i["bx"])
         assert i["layer"] == blay[k]
         np.testing.assert_allclose(xh[k].ravel(), np.array(bxh[k]), rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("seed,mode,tnu,win,frac", [
+    (41, "plain", 0.1, 8, 1.0),
+    (42, "profile", 0.1, 8, 0.5),
+    (43, "profile", 100.0, 12, 0.5),
+    (44, "idl", 1.0, 8, 0.8),
+    (45, "full", 0.1, 12, 0.5),
+    (46, "brl", 0.1, 8, 1.0),
+])
+def test_partial_loss_vectorised_oracle_equals_loop_oracle(seed, mode, tnu, win, frac):
+    f = tiny_frame(seed)
+    m = partial_mask(32, 32, 8, seed + 100, frac=frac, rate=0.35)
+    p = Params(block=8, ring=2, window=win, min_hql_cands=8, t_nu=tnu, mode=mode)
+    out, xh, info = conceal(f, m, p)
+    bu, bxh, blay = brute.conceal(f.tolist(), m.tolist(), 8, 2, win, t_nu=tnu, min_hql=8,
+                                  mode=mode)
+    assert len(info) == len(lost_cells(m, 8)) > 0
+    assert np.array_equal(out, np.array(bu, dtype=np.uint8))
+    for i in info:
+        k = (i["by"], i["bx"])
+        assert i["layer"] == blay[k]
+        # HQL: Cholesky solves and 40 golden-section steps in two summation
+        # orders differ by up to ~2e-8
+        tol = 1e-7 if i["layer"] == LAYER_HQL else 1e-9
+        np.testing.assert_allclose(xh[k].ravel(), np.array(bxh[k]), rtol=0, atol=tol)
 
 
 def test_hql_vectorised_equals_loop_version():
