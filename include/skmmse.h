@@ -14,23 +14,29 @@
  * selection" (flatness phi, normalisation factor nu of eq. factor, Table
  * "Profile definitions").
  *
- * Geometry (block mode): a lost B x B block is x0, its context is the ring of
- * width `ring` around it, candidates are the displacements in
- * [-window, window]^2 whose B x B prototype is received.  Distances run over
- * the ring pixels known in both rings and are normalised by their count.
+ * Geometry (block mode): a B x B cell of the block grid that holds any lost
+ * pixel is a block x0 (loss of any shape, Sec. "Reconstruction framework").
+ * Its context is the ring of width `ring` around it plus the cell's own
+ * received pixels; candidates are the displacements in [-window, window]^2
+ * whose B x B prototype does not overlap the cell and is received.  Distances
+ * run over the context pixels known on both sides (a candidate's own positions
+ * are its prototype) and are normalised by their count.  A cell holding
+ * received pixels never takes HQL (IDL over the whole window instead).
  *
  * Conventions shared by every entry point
  *  - All pixel planes are 8-bit, row-major, `stride` bytes between rows
  *    (stride >= width).  `loss_mask` has one byte per pixel, nonzero = lost.
- *  - Lost pixels must form whole B x B cells of the block grid that lie fully
- *    inside the frame; anything else returns SKM_EUNSUPPORTED.  Values at lost
- *    pixels are never read.  Received pixels are copied unchanged.
+ *  - Lost pixels must lie in B x B cells of the block grid that are fully
+ *    inside the frame (not in a partial last row or column of cells);
+ *    anything else returns SKM_EUNSUPPORTED.  Values at lost pixels are never
+ *    read.  Received pixels are copied unchanged, also inside a block.
  *  - The caller owns every buffer; the library keeps no pointer after return.
  *    `out` may alias `frame` (in place).
  *  - Lost blocks are concealed in rounds: a round takes every pending block
- *    whose known ring holds at least ring*block pixels (or, if none does, the
- *    pending blocks with the most known ring pixels), estimates them all from
- *    the state at the start of the round and only then marks them received.
+ *    whose known context holds at least ring*block pixels (or, if none does,
+ *    the pending blocks with the most known context pixels), estimates them
+ *    all from the state at the start of the round and only then marks them
+ *    received.
  *  - Output is bitwise deterministic for identical inputs and parameters.
  *  - Errors are status codes; a thread-local message is kept for
  *    skm_last_error().  Nothing throws across the ABI.
@@ -50,7 +56,7 @@ typedef enum skm_status {
   SKM_EINVAL = -1,        /* bad argument, or a frame with no received pixel */
   SKM_ENOMEM = -2,        /* device or host allocation failed */
   SKM_EDEVICE = -3,       /* HIP runtime error */
-  SKM_EUNSUPPORTED = -4   /* loss mask not made of whole in-frame B x B cells */
+  SKM_EUNSUPPORTED = -4   /* lost pixels outside the in-frame B x B cells     */
 } skm_status;
 
 /* Estimation modes (skm_params.mode). */
@@ -85,7 +91,7 @@ typedef struct skm_params {
   int32_t expand_step;     /* IDL support-area growth step (Chebyshev px);
                               radii step, 2 step, ..., window (at most 16)    */
   int32_t min_overlap_pct; /* candidate needs >= ceil(pct*|m0|/100) common
-                              known ring pixels (and >= 1), 0..100            */
+                              known context pixels (and >= 1), 0..100         */
   int32_t min_hql_cands;   /* HQL needs this many complete candidates (>= 2) */
   int32_t mode;            /* SKM_MODE_*                                       */
   int32_t max_rounds;      /* 0 = until every block is concealed; otherwise
@@ -106,7 +112,7 @@ typedef struct skm_block_info {
   int32_t radius;          /* accepted IDL radius, or window; 0 for BRL       */
   int32_t flags;           /* SKM_FLAG_*                                       */
   int32_t phi;             /* flatness max(y0) - min(y0) of the known ring    */
-  int32_t n_ctx;           /* |m0|: known ring pixels                          */
+  int32_t n_ctx;           /* |m0|: known context pixels (ring and own)        */
   double log_nu;           /* log of the sum of raw IDL weights at `radius`
                               (NaN when not evaluated)                        */
 } skm_block_info;
@@ -158,7 +164,7 @@ skm_status skm_conceal_device(skm_ctx* ctx, const uint8_t* d_frame, const uint8_
 /* Distance table of the kernel-regression core (eq. weights / eq. slpe):
  * for each lost block i (lost-cell raster order) and each displacement
  * (dx, dy) in [-W, W]^2 (index (dy+W)*(2W+1) + (dx+W)), the exact integer
- * d = sum over ring pixels known in both rings of (y0 - y_j)^2 and their
+ * d = sum over context pixels known on both sides of (y0 - y_j)^2 and their
  * count n, evaluated on the received frame before any concealment.
  * d = -1 (and n = 0) where the displacement is not an admissible candidate.
  *   d_dist, d_cnt : device int32 arrays of cap * (2W+1)^2 entries.

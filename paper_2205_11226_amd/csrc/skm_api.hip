@@ -306,7 +306,7 @@ skm_status read_state(FrameSlot* f, hipStream_t s) {
 
 skm_status check_err(const RoundState& st) {
   if (st.err & kErrPartial)
-    return fail(SKM_EUNSUPPORTED, "lost pixels must form whole B x B cells inside the frame");
+    return fail(SKM_EUNSUPPORTED, "lost pixels must lie in the B x B cells inside the frame");
   if (st.err & kErrNoContext)
     return fail(SKM_EINVAL, "no lost block touches a received pixel (frame with no received pixel?)");
   if (st.err & kErrHqlPending)

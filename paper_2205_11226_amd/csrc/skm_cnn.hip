@@ -649,11 +649,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
           G.in[(Y + 1) * kIn + X + 1] = s2d_pixel(v[t]);
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
+            // context: the footprint, with the block's own received pixels
+            // (counted again in bits 16.. to flag a partly received block)
             const int wy = 2 * Y + (q >> 1), wx = 2 * X + (q & 1);
-            const bool ring = wy >= f0 && wy < f1 && wx >= f0 && wx < f1 &&
-                              !(wy >= b0 && wy < b1 && wx >= b0 && wx < b1);
-            if (ring && v[t][q] >= 0) {
-              ++c; sum += v[t][q]; vmin = min(vmin, v[t][q]); vmax = max(vmax, v[t][q]);
+            const bool ctx = wy >= f0 && wy < f1 && wx >= f0 && wx < f1;
+            const bool own = wy >= b0 && wy < b1 && wx >= b0 && wx < b1;
+            if (ctx && v[t][q] >= 0) {
+              c += own ? 1 + (1 << 16) : 1;
+              sum += v[t][q]; vmin = min(vmin, v[t][q]); vmax = max(vmax, v[t][q]);
             }
           }
         }
@@ -667,7 +670,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
       for (int w = 0; w < kThreads / 64; ++w) {
         c += red[w][0]; sum += red[w][1]; vmin = min(vmin, red[w][2]); vmax = max(vmax, red[w][3]);
       }
-      a.m0cnt[i] = c;
+      const int nown = c >> 16;
+      c &= 0xffff;
+      a.m0cnt[i] = c | (nown > 0 ? kPartialBit : 0);
       a.ring[i] = make_int2(sum, vmin | (vmax << 16));
       wg_nq += c >= p.r * p.B;
       wg_max = max(wg_max, c);

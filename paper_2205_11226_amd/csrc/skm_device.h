@@ -156,7 +156,9 @@ static __device__ __forceinline__ void shr128(uint64_t lo, uint64_t hi, int s, u
 //   selw    f32 [MC]      FP32 weights exp(ell - max) of the selected candidates
 //   selo    u16 [MC]      their window offsets
 //   qu      u32x2 [NU32]  per unit: packed int16 context pair, footprint offset;
-//                         padded to a multiple of 32 with unknown pairs
+//                         the ring units, then (for a block holding received
+//                         pixels) its own B x B / 2 pairs, padded to a
+//                         multiple of 32 with unknown pairs
 //   utab    u32 [NU]      fixed unit table: footprint offset | single << 16
 //   rowbits u64 [Wd][2]   availability bits of each window row
 //   runbits u64 [Wd][2]   bit c set iff columns c .. c+B-1 are all available
@@ -188,7 +190,7 @@ __host__ __device__ inline size_t main_lds_layout(const DevParams& p, size_t* of
   offs[1] = o; o = align_up(o + sizeof(uint32_t) * p.MC, 16);
   offs[2] = o; o = align_up(o + sizeof(float) * p.MC, 16);
   offs[3] = o; o = align_up(o + sizeof(uint16_t) * p.MC, 16);
-  offs[4] = o; o = align_up(o + sizeof(uint2) * (p.NR + 32), 16);   // units padded to 32
+  offs[4] = o; o = align_up(o + sizeof(uint2) * (p.NR + p.B * p.B / 2 + 32), 16);   // + own, padded
   offs[5] = o; o = align_up(o + sizeof(uint32_t) * p.NR, 16);
   offs[6] = o; o = align_up(o + sizeof(uint64_t) * 2 * p.Wd, 16);
   offs[7] = o; o = align_up(o + sizeof(uint64_t) * 2 * p.Wd, 16);
@@ -224,7 +226,7 @@ static __device__ __forceinline__ int cand_n(uint32_t c) { return (int)(c >> 18)
 // Estimation-kernel LDS (one block per workgroup), smaller than MainLds so
 // that four workgroups fit a CU at the default geometry:
 //   winp    u32 [Wd*Wd]   as in MainLds
-//   qu      u32x2 [NR+32] as in MainLds
+//   qu      u32x2 [NR+B*B/2+32] as in MainLds
 //   utab    u32 [NR]      as in MainLds
 //   cand    u32 [MC+16]   candidate words; n added by the distance step
 //   dist    u32 [MC]      exact distance d (~0u = dropped).  Before the
@@ -249,7 +251,7 @@ struct EstLds {
 __host__ __device__ inline size_t est_lds_layout(const DevParams& p, size_t* offs) {
   size_t o = 0;
   offs[0] = o; o = align_up(o + sizeof(uint32_t) * p.Wd * p.Wd, 16);
-  offs[1] = o; o = align_up(o + sizeof(uint2) * (p.NR + 32), 16);
+  offs[1] = o; o = align_up(o + sizeof(uint2) * (p.NR + p.B * p.B / 2 + 32), 16);
   offs[2] = o; o = align_up(o + sizeof(uint32_t) * p.NR, 16);
   const size_t qu_utab = o - offs[1];
   offs[3] = o; o = align_up(o + sizeof(uint32_t) * (p.MC + 16), 16);
@@ -506,23 +508,34 @@ struct RingStats { int n0, phi, sum; };
 // Context units of the block (footprint origin qbase in the window) and ring
 // statistics; horizontal B-runs of every window row by doubling.  Ends with a
 // barrier.
+// NUe >= NU: units NU .. NUe - 1 are the block's own positions in pairs of
+// columns (B x B / 2 of them, for a block that holds received pixels; the
+// lost ones read -1 and drop out of every sum).
 static __device__ __forceinline__ RingStats phase_context(const DevParams& p, const MainLds& L,
-                                                          BlockShared& sh, int NU) {
+                                                          BlockShared& sh, int NU, int NUe) {
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   const int qbase = p.W * p.Wd + p.W;
   {
     int c = 0, vmin = 255, vmax = 0, vsum = 0;
-    for (int u = tid; u < NU; u += kThreads) {
-      const uint32_t e = L.utab[u];
-      const int off = (int)(e & 0xffffu);
-      uint32_t qp = L.winp[qbase + off];
-      if (e >> 16) qp |= 0xffff0000u;
+    for (int u = tid; u < NUe; u += kThreads) {
+      int off;
+      uint32_t qp;
+      if (u < NU) {
+        const uint32_t e = L.utab[u];
+        off = (int)(e & 0xffffu);
+        qp = L.winp[qbase + off];
+        if (e >> 16) qp |= 0xffff0000u;
+      } else {
+        const int k2 = 2 * (u - NU), iy = k2 / p.B, ix = k2 - iy * p.B;
+        off = (p.r + iy) * p.Wd + p.r + ix;
+        qp = L.winp[qbase + off];
+      }
       L.qu[u] = make_uint2(qp, (uint32_t)off);
       const int va = (int)(int16_t)(qp & 0xffffu), vb = (int)(int16_t)(qp >> 16);
       if (va >= 0) { ++c; vmin = min(vmin, va); vmax = max(vmax, va); vsum += va; }
       if (vb >= 0) { ++c; vmin = min(vmin, vb); vmax = max(vmax, vb); vsum += vb; }
     }
-    for (int u = NU + tid; u < align32(NU); u += kThreads) L.qu[u] = make_uint2(0xffffffffu, 0u);
+    for (int u = NUe + tid; u < align32(NUe); u += kThreads) L.qu[u] = make_uint2(0xffffffffu, 0u);
     c = wave_sum(c); vmin = wave_min(vmin); vmax = wave_max(vmax); vsum = wave_sum(vsum);
     if (lane == 0) {
       sh.red_i[wave][0] = c; sh.red_i[wave][1] = vmin;
@@ -568,7 +581,16 @@ static __device__ __forceinline__ int phase_candidates(const DevParams& p, const
     shr128(lo, hi, r, mlo, mhi);
     if (D2 < 64) { mlo &= (1ull << D2) - 1ull; mhi = 0; }
     else { mhi &= (D2 >= 128) ? ~0ull : ((1ull << (D2 - 64)) - 1ull); }
-    if (tid == W) mlo &= ~(1ull << W);          // W < 64: the block itself
+    // prototypes never overlap the block: displacements with |dy| < B and
+    // |dx| < B are out (for a fully lost block they are unavailable anyway)
+    if (abs(tid - W) < B) {
+      const int c0 = max(0, W - B + 1), c1 = min(D2 - 1, W + B - 1);
+      uint64_t klo, khi;                      // bits c0 .. c1
+      shr128(~0ull, ~0ull, 127 - (c1 - c0), klo, khi);
+      if (c0 >= 64) { khi = klo << (c0 - 64); klo = 0ull; }
+      else if (c0 > 0) { khi = (khi << c0) | (klo >> (64 - c0)); klo <<= c0; }
+      mlo &= ~klo; mhi &= ~khi;
+    }
     L.cmask[2 * tid] = mlo; L.cmask[2 * tid + 1] = mhi;
     rowcnt = __popcll(mlo) + __popcll(mhi);
   }

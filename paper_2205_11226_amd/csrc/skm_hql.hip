@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
 
     // -- candidates: the estimation kernel's phases, then the complete ones
     phase_stage(a, p, L, x0 - r - W, y0 - r - W);
-    const RingStats rs = phase_context(p, L, sh, NU);
+    const RingStats rs = phase_context(p, L, sh, NU, NU);   // HQL blocks are fully lost
     const int n0 = rs.n0;
     const int M = phase_candidates(p, L, sh);
     const int nmin = max(1, (p.min_pct * n0 + 99) / 100);

@@ -24,7 +24,8 @@ constexpr int kMaxWd = kMaxB + 2 * kMaxRing + 2 * kMaxWin;   // 96 window side
 constexpr int kValGuard = 8;
 
 // device error bits (RoundState::err)
-constexpr int kErrPartial = 1;       // lost pixel outside a whole in-frame cell
+constexpr int kPartialBit = 1 << 16;   // m0cnt flag: the block holds received pixels
+constexpr int kErrPartial = 1;       // lost pixel outside the in-frame cells
 constexpr int kErrNoContext = 2;     // pending blocks, none touches a known pixel
 constexpr int kErrHqlPending = 4;    // a block needs HQL and no HQL pass ran
 
@@ -80,7 +81,9 @@ struct FrameArgs {
   unsigned int* cellbits; // lost-cell bit table, ceil(gh * gw / 32) words, zero between frames
   int* blk;               // lost cell indices, raster order
   int* bstate;
-  int* m0cnt;             // known in-frame ring pixels of each pending block
+  int* m0cnt;             // known in-frame context pixels of each pending block
+                          // (ring and the block's own), | kPartialBit when
+                          // the block holds received pixels
   int2* ring;             // their sum, and min | max << 16 (prep kernel)
   int* part;              // 2 * kPartSlots round-preparation partials
   int* hql_list;          // lost-block indices waiting for HQL in this round

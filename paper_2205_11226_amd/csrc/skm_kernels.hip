@@ -104,8 +104,8 @@ __global__ __launch_bounds__(kThreads) void k_init(FrameArgs a, DevParams p) {
   int v = nl;
   for (int o = 1; o < TB; o <<= 1) v += __shfl_xor(v, o, 64);   // cells never straddle waves
   const bool leader = in_cells && (lane & (TB - 1)) == 0;
-  if (leader && v != 0 && v != B * B) bad = 1;
-  const uint64_t lm = __ballot(leader && v == B * B);
+  // a cell with any lost pixel is a block (its received pixels join the context)
+  const uint64_t lm = __ballot(leader && v > 0);
   const bool any_bad = __ballot(bad != 0) != 0ull;
   if (lane == 0) {
     unsigned int sink = 0;
@@ -191,23 +191,29 @@ __global__ __launch_bounds__(kThreads) void k_round_prep(FrameArgs a, DevParams 
     const int cell = a.blk[i];
     const int by = cell / p.gw, bx = cell - by * p.gw;
     const int xr = bx * B - r, yr = by * B - r;
+    // context statistics over the footprint: the ring and the block's own
+    // received pixels (lost ones read -1)
     int c = 0, sum = 0, vmin = 255, vmax = 0;
+    bool own = false;
 #pragma unroll
     for (int fy0 = 0; fy0 < 2 * kMaxB; fy0 += 2) {     // two footprint rows per step, F <= 32
       const int fy = fy0 + (lane >> 5), fx = lane & 31;
       const int gy = yr + fy, gx = xr + fx;
-      const bool use = fy < F && fx < F && (fy < r || fy >= r + B || fx < r || fx >= r + B) &&
-                       gy >= 0 && gy < p.height && gx >= 0 && gx < p.width;
+      const bool use = fy < F && fx < F && gy >= 0 && gy < p.height && gx >= 0 && gx < p.width;
       const int cy = min(max(gy, 0), p.height - 1), cx = min(max(gx, 0), p.width - 1);
       const int v = a.val[(size_t)cy * p.width + cx];
-      if (use && v >= 0) { ++c; sum += v; vmin = min(vmin, v); vmax = max(vmax, v); }
+      if (use && v >= 0) {
+        ++c; sum += v; vmin = min(vmin, v); vmax = max(vmax, v);
+        own = own || (fy >= r && fy < r + B && fx >= r && fx < r + B);
+      }
     }
     c = wave_sum(c);
     sum = wave_sum(sum);
     vmin = wave_min(vmin);
     vmax = wave_max(vmax);
+    const bool partial = __ballot(own) != 0ull;
     if (lane == 0) {
-      a.m0cnt[i] = c;
+      a.m0cnt[i] = c | (partial ? kPartialBit : 0);
       a.ring[i] = make_int2(sum, vmin | (vmax << 16));
       my_nq += c >= r * B;
       my_mx = max(my_mx, c);
@@ -242,12 +248,14 @@ __device__ void write_info(const FrameArgs& a, int i, int bx, int by, int layer,
 }
 
 __device__ void write_const_block(const FrameArgs& a, const DevParams& p, int i, int x0, int y0,
-                                  double v) {
+                                  double v, bool partial) {
   const int B2 = p.B * p.B;
   const uint8_t u = (uint8_t)fmin(fmax(floor(v + 0.5), 0.0), 255.0);
   for (int pix = threadIdx.x; pix < B2; pix += kThreads) {
     const int py = pix / p.B, px = pix - py * p.B;
-    a.work[(size_t)(y0 + py) * p.stride + x0 + px] = u;
+    // a block holding received pixels keeps them
+    if (!partial || a.val[(size_t)(y0 + py) * p.width + x0 + px] < 0)
+      a.work[(size_t)(y0 + py) * p.stride + x0 + px] = u;
     if (a.xhat && i < a.cap) a.xhat[(size_t)i * B2 + pix] = (float)v;
   }
 }
@@ -297,7 +305,9 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
     if (tid == 0) atomicOr(&st->err, kErrNoContext);
     return;
   }
-  const int n0 = a.m0cnt[i];
+  const int m0w = a.m0cnt[i];
+  const int n0 = m0w & (kPartialBit - 1);
+  const bool partial = (m0w & kPartialBit) != 0;      // the block holds received pixels
   if (!dist_only && !(nq > 0 ? (n0 >= p.r * p.B) : (n0 == maxm0))) return;
 
 
@@ -313,7 +323,7 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
   const bool profile_rule = p.mode == SKM_MODE_PROFILE || (p.mode == SKM_MODE_CNN && !cnn);
   if (!dist_only && (p.mode == SKM_MODE_BRL || (profile_rule && (double)phi <= p.t_phi) ||
                      gsel == SKM_LAYER_BRL)) {
-    write_const_block(a, p, i, x0, y0, mean);
+    write_const_block(a, p, i, x0, y0, mean, partial);
     if (tid == 0) {
       write_info(a, i, bx, by, SKM_LAYER_BRL, round, -1, -1, 0, relaxed_flag, phi, n0, NAN);
       a.bstate[i] = round;
@@ -328,8 +338,11 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
   const int NU = sh.NU;
   if (dist_only) stage_issue(a, p, SG, y0 - r - W, SR);
   stage_finish(a, p, E.m, SG, y0 - r - W, SR);
-  // every context pixel known: the distance step masks the window side only
-  const bool qfull = phase_context(p, E.m, sh, NU).n0 == 2 * NU;
+  // context units: the ring, then the block's own pixel pairs if it holds
+  // received pixels.  Every ring pixel known and no own units: the distance
+  // step masks the window side only
+  const int NUe = partial ? NU + p.B * p.B / 2 : NU;
+  const bool qfull = phase_context(p, E.m, sh, NU, NUe).n0 == 2 * NU && !partial;
 
   // 3. admissible prototypes in raster order
   phase_candidates(p, E.m, sh);
@@ -341,17 +354,19 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
   const int nmin = max(1, (p.min_pct * n0 + 99) / 100);
   const double two_s2 = 2.0 * p.sigma2;
   int nc = 0, ncomp = 0;
-  const int NU32 = align32(NU);
-  // one copy of the loop per distance routine, chosen once per block
-  auto dist_loop = [&](auto qknown) {
+  const int NU32 = align32(NUe);
+  // one copy of the loop per distance routine, chosen once per block:
+  // compile-time unit offsets with or without the context-side mask, or the
+  // unit table (other geometries, and blocks with own units)
+  auto dist_loop = [&](auto kind) {
     for (int j0 = wave * 64; j0 < M; j0 += kThreads) {     // uniform per wave
       const int j = j0 + lane;
       const bool act = j < M;
       const uint32_t cj = act ? E.cand[j] : 0u;
       const int base = cand_off(cj);
       int d, n;
-      if (FG)
-        cand_distance_fixed<Geom16, decltype(qknown)::value>(E.m, base, d, n);
+      if constexpr (decltype(kind)::value < 2)
+        cand_distance_fixed<Geom16, decltype(kind)::value == 0>(E.m, base, d, n);
       else
         cand_distance_wave(E.m, base, NU32, d, n);
       if (!act) continue;
@@ -374,8 +389,13 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
       }
     }
   };
-  if (FG && qfull) dist_loop(std::true_type{});
-  else dist_loop(std::false_type{});
+  if constexpr (FG) {
+    if (!partial && qfull) dist_loop(std::integral_constant<int, 0>{});
+    else if (!partial) dist_loop(std::integral_constant<int, 1>{});
+    else dist_loop(std::integral_constant<int, 2>{});
+  } else {
+    dist_loop(std::integral_constant<int, 2>{});
+  }
   if (dist_only) {
     // displacements without an admissible prototype (cmask is intact: the
     // distance step wrote no LDS)
@@ -499,7 +519,7 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
       else want_hql = p.mode == SKM_MODE_PROFILE || (p.mode == SKM_MODE_CNN && !cnn);
     }
     if (want_hql) {
-      if (ncom >= max(2, p.min_hql)) layer = SKM_LAYER_HQL;
+      if (ncom >= max(2, p.min_hql) && !partial) layer = SKM_LAYER_HQL;
       else flags |= SKM_FLAG_NO_HQL;
     }
     const double lnu_r = readlane_f64(lnu, ridx);      // ridx is uniform in the wave
@@ -533,7 +553,7 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
     return;
   }
   if (layer == SKM_LAYER_BRL) {
-    write_const_block(a, p, i, x0, y0, mean);
+    write_const_block(a, p, i, x0, y0, mean, partial);
     if (tid == 0) {
       write_info(a, i, bx, by, SKM_LAYER_BRL, round, sh.n_cand, sh.n_complete, 0, sh.flags,
                  phi, n0, sh.lnu);
@@ -629,8 +649,10 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
       }
       const double x0h = t0 * sh.xs, x1h = t1 * sh.xs;
       uint8_t* o = a.work + (size_t)(y0 + py) * p.stride + x0 + px;
-      o[0] = (uint8_t)fmin(fmax(floor(x0h + 0.5), 0.0), 255.0);
-      o[1] = (uint8_t)fmin(fmax(floor(x1h + 0.5), 0.0), 255.0);
+      // the block's own pair in the window: received pixels are kept
+      const uint32_t own = partial ? wq[W * Wd + W] : 0xffffffffu;
+      if ((int16_t)(own & 0xffffu) < 0) o[0] = (uint8_t)fmin(fmax(floor(x0h + 0.5), 0.0), 255.0);
+      if ((int16_t)(own >> 16) < 0) o[1] = (uint8_t)fmin(fmax(floor(x1h + 0.5), 0.0), 255.0);
       if (a.xhat && i < a.cap) {
         a.xhat[(size_t)i * B2 + 2 * q] = (float)x0h;
         a.xhat[(size_t)i * B2 + 2 * q + 1] = (float)x1h;
@@ -758,20 +780,24 @@ __global__ __launch_bounds__(kThreads) void k_fill(FrameArgs a, DevParams p) {
     const int cell = a.blk[i];
     const int by = cell / p.gw, bx = cell - by * p.gw;
     const int xr = bx * B - r, yr = by * B - r;
+    // context: the footprint, with the block's own received pixels (counted
+    // again in bits 16.. to flag a partly received block)
     int c = 0, s = 0;
     for (int pos = threadIdx.x; pos < F * F; pos += blockDim.x) {
       const int fy = pos / F, fx = pos - fy * F;
-      const bool ring = fy < r || fy >= r + B || fx < r || fx >= r + B;
+      const bool own = fy >= r && fy < r + B && fx >= r && fx < r + B;
       const int gy = yr + fy, gx = xr + fx;
-      if (ring && gy >= 0 && gy < p.height && gx >= 0 && gx < p.width) {
+      if (gy >= 0 && gy < p.height && gx >= 0 && gx < p.width) {
         const int v = a.val[(size_t)gy * p.width + gx];
-        if (v >= 0) { ++c; s += v; }
+        if (v >= 0) { c += own ? 1 + (1 << 16) : 1; s += v; }
       }
     }
     c = block_sum_int(c, s_red);
     s = block_sum_int(s, s_red);
+    const bool partial = (c >> 16) > 0;
+    c &= 0xffff;
     const double v = c > 0 ? (double)s / (double)c : fmean;
-    write_const_block(a, p, i, bx * B, by * B, v);
+    write_const_block(a, p, i, bx * B, by * B, v, partial);
     if (threadIdx.x == 0) {
       write_info(a, i, bx, by, SKM_LAYER_FILL, round, -1, -1, 0,
                  c > 0 ? 0 : SKM_FLAG_EMPTY_CTX, 0, c, NAN);

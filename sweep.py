@@ -120,7 +120,7 @@ def run_one(ctx, fd, md, prm, reps: int):
     times = []
     s = torch.cuda.current_stream()
     for _ in range(reps):
-        e0, flat = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)
         ctx.conceal_device(fd, md, prm, out=out, want_info=False, want_xhat=False)
         e1.record(s)

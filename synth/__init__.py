@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs: luma/chroma planes and block-loss masks.
+"""Seeded synthetic inputs: luma/chroma planes and loss masks.
 
 This package holds input generation only.  It contains none of the
 concealment arithmetic, so both the HIP product path and the CPU oracle can
@@ -12,6 +12,7 @@ from .generator import (
     loss_random,
     loss_slices,
     loss_random_bursts,
+    loss_partial_cells,
     workload_plain_512,
     workload_layered_1080p,
     workload_batch,
@@ -21,6 +22,6 @@ from .generator import (
 
 __all__ = [
     "make_luma", "make_chroma", "loss_isolated", "loss_dispersed", "loss_random",
-    "loss_slices", "loss_random_bursts", "workload_plain_512",
+    "loss_slices", "loss_random_bursts", "loss_partial_cells", "workload_plain_512",
     "workload_layered_1080p", "workload_batch", "workload_stream_4k", "seed_for",
 ]

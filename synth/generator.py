@@ -153,6 +153,26 @@ def loss_random(h: int, w: int, b: int, rate: float, seed: int) -> np.ndarray:
     return _mask_from_cells(h, w, b, list(zip(*np.nonzero(lost))))
 
 
+def loss_partial_cells(h: int, w: int, b: int, rate: float, seed: int,
+                       frac: float = 0.5) -> np.ndarray:
+    """Arbitrary-shape loss: each full cell is hit with probability ``rate``;
+    a share ``frac`` of the hit cells lose a random subset of their pixels
+    (each pixel with a per-cell probability in [0.3, 0.9), at least one),
+    the others lose every pixel."""
+    rng = np.random.default_rng(seed)
+    gh, gw = _grid(h, w, b)
+    m = np.zeros((h, w), dtype=np.uint8)
+    for by in range(gh):
+        for bx in range(gw):
+            if rng.uniform() < rate:
+                c = np.ones((b, b), dtype=np.uint8)
+                if rng.uniform() < frac:
+                    c = (rng.uniform(size=(b, b)) < rng.uniform(0.3, 0.9)).astype(np.uint8)
+                    c[rng.integers(b), rng.integers(b)] = 1
+                m[by * b:(by + 1) * b, bx * b:(bx + 1) * b] = c
+    return m
+
+
 def loss_slices(h: int, w: int, b: int, rate: float, seed: int) -> np.ndarray:
     """Whole rows of cells lost; round(rate * rows) distinct rows, uniform."""
     rng = np.random.default_rng(seed)

@@ -110,12 +110,12 @@ def test_batch_reports_errors_per_frame(ctx):
     import paper_2205_11226_amd as skm
     f = synth.make_luma(128, 128, 5)
     good = synth.loss_random(128, 128, 16, 0.2, 6)
-    bad = good.copy()
-    bad[3, 5] = 1                                      # a lost pixel outside whole cells
-    if good[3, 5]:
-        bad[3, 5] = 0
+    f2 = synth.make_luma(136, 128, 5)                  # 8 rows below the last cell row
+    bad = np.zeros((136, 128), np.uint8)
+    bad[:128] = good
+    bad[130, 5] = 1                                    # a lost pixel outside the cells
     prm = device_params("plain")
-    jobs, _ = _batch_jobs([(f, good), (f, bad), (f, good)], [prm] * 3)
+    jobs, _ = _batch_jobs([(f, good), (f2, bad), (f, good)], [prm] * 3)
     with pytest.raises(skm.SkmError):
         ctx.conceal_batch(jobs)
     descs, keep = ctx._frame_descs(jobs)

@@ -111,6 +111,40 @@ def test_random_loss_multiround_parity(ctx, b, r, w):
     st, info = check(ctx, f, m, "profile", block=b, ring=r, window=w, t_nu=0.1)
 
 
+@pytest.mark.parametrize("b,r,w,mode", [
+    (16, 4, 24, "plain"), (16, 4, 24, "profile"), (16, 4, 24, "brl"),
+    (8, 2, 12, "full"), (8, 4, 24, "idl"), (8, 3, 10, "profile"),
+])
+def test_arbitrary_shape_loss_parity(ctx, b, r, w, mode):
+    """Cells that keep some received pixels: those join the context, are
+    never overwritten, and the cell takes no HQL."""
+    f = synth.make_luma(112, 144, 80 + b, n_bumps=10, n_edges=5)
+    m = synth.loss_partial_cells(112, 144, b, 0.35, 81 + b + r, frac=0.6)
+    st, info = check(ctx, f, m, mode, block=b, ring=r, window=w, t_nu=0.1,
+                     min_hql_cands=8)
+    own = [(int(i["by"]), int(i["bx"])) for i in info
+           if (m[int(i["by"]) * b:(int(i["by"]) + 1) * b,
+                 int(i["bx"]) * b:(int(i["bx"]) + 1) * b] == 0).any()]
+    assert own, "the mask should leave received pixels in some lost cells"
+    layer = {(int(i["by"]), int(i["bx"])): int(i["layer"]) for i in info}
+    assert all(layer[k] != 2 for k in own)
+
+
+def test_arbitrary_shape_loss_distances_bit_exact(ctx):
+    f = synth.make_luma(96, 128, 90, n_bumps=8, n_edges=4)
+    m = synth.loss_partial_cells(96, 128, 16, 0.4, 91, frac=0.7)
+    p = device_params("plain")
+    d, n = ctx.distances_device(to_dev(f), to_dev(m), p)
+    d, n = d.cpu().numpy(), n.cpu().numpy()
+    op = oracle_params("plain")
+    cells = lost_cells(m, 16)
+    assert d.shape[0] == len(cells) > 0
+    for i, (by, bx) in enumerate(cells):
+        do, no = block_distances(f.astype(np.int64), m == 0, by, bx, op)
+        assert np.array_equal(d[i], do), (by, bx)
+        assert np.array_equal(n[i][do >= 0], no[do >= 0])
+
+
 def test_slice_loss_rounds_parity(ctx):
     f = synth.make_luma(160, 192, 50, n_bumps=10, n_edges=5)
     m = synth.loss_slices(160, 192, 16, 0.5, 51)
@@ -227,10 +261,9 @@ def test_error_codes(ctx):
         ctx.conceal_device(to_dev(f), to_dev(allm), skm.default_params())
     assert e.value.status == -1
     part = np.zeros_like(f)
-    part[3:9, 5:20] = 1
-    with pytest.raises(skm.SkmError) as e:
-        ctx.conceal_device(to_dev(f), to_dev(part), skm.default_params())
-    assert e.value.status == -4
+    part[3:9, 5:20] = 1                    # cells with received pixels: accepted
+    out, info, _ = ctx.conceal_device(to_dev(f), to_dev(part), skm.default_params())
+    assert len(info) == 2 and np.array_equal(out.cpu().numpy()[part == 0], f[part == 0])
     edge = np.zeros((70, 64), np.uint8)
     edge[66:, :16] = 1                     # partial bottom cell row
     with pytest.raises(skm.SkmError) as e:

@@ -76,19 +76,7 @@ def test_any_lost_pixel_makes_its_cell_a_block():
 
 
 def partial_mask(h, w, b, seed, frac=0.5, rate=0.25):
-    """Cells lost with probability ``rate``; a share ``frac`` of them keep a
-    random subset of their pixels (arbitrary-shape loss)."""
-    rng = np.random.default_rng(seed)
-    m = np.zeros((h, w), np.uint8)
-    for by in range(h // b):
-        for bx in range(w // b):
-            if rng.uniform() < rate:
-                c = np.ones((b, b), np.uint8)
-                if rng.uniform() < frac:
-                    c = (rng.uniform(size=(b, b)) < rng.uniform(0.3, 0.9)).astype(np.uint8)
-                    c[rng.integers(b), rng.integers(b)] = 1
-                m[by * b:(by + 1) * b, bx * b:(bx + 1) * b] = c
-    return m
+    return synth.loss_partial_cells(h, w, b, rate, seed, frac=frac)
 
 
 def test_received_pixels_of_a_lost_cell_are_kept():
