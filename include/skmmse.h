@@ -20,8 +20,7 @@
  * received pixels; candidates are the displacements in [-window, window]^2
  * whose B x B prototype does not overlap the cell and is received.  Distances
  * run over the context pixels known on both sides (a candidate's own positions
- * are its prototype) and are normalised by their count.  A cell holding
- * received pixels never takes HQL (IDL over the whole window instead).
+ * are its prototype) and are normalised by their count.
  *
  * Conventions shared by every entry point
  *  - All pixel planes are 8-bit, row-major, `stride` bytes between rows

@@ -288,8 +288,7 @@ def conceal(frame, mask, b, r, W, sigma2=10.0, t_phi=20.0, t_nu=0.1, step=4, pct
             if not done:
                 want = mode in ("full", "profile")
                 comp = [c for c in cs if c["n"] == sum(m0)]
-                own = any(av[by * b + i][bx * b + j] for i in range(b) for j in range(b))
-                if want and len(comp) >= max(2, min_hql) and not own:
+                if want and len(comp) >= max(2, min_hql):
                     ys = [[c["y"][k] for k in range(len(m0)) if m0[k]] for c in comp]
                     layer = 2
                     xh = hql([c["x"] for c in comp], ys, known, [c["d"] for c in comp],

@@ -20,9 +20,7 @@ known in both rings (count n_j) and normalised by n_j, the "average
 distortion per context pixel" that the IDL bandwidth sigma^2 N_y expresses
 (Sec. "Intermediate dynamic layer").  Candidates with n_j below
 ceil(min_overlap_pct * |m0| / 100) are dropped.  HQL, whose covariance needs
-every coordinate, uses only candidates whose ring covers all of m0, and is
-not used for a cell with received pixels (such a cell takes IDL over the
-whole window instead).
+every coordinate, uses only candidates whose context covers all of m0.
 
 Layers and gate (Sec. "Scalable K-MMSE estimator", Sec. "Layer switching"):
 * BRL: mean of y0 (eq. "mean"), chosen when phi = max(y0) - min(y0) <= T_phi;
@@ -143,10 +141,6 @@ def block_context(u, avail, by, bx, p: Params):
     off = context_offsets(p.block, p.ring)
     return _gather(u, avail, by * p.block + off[:, 0], bx * p.block + off[:, 1])
 
-
-def is_partial(m0: np.ndarray, p: Params) -> bool:
-    """True when the block holds received pixels (its own context positions)."""
-    return bool(m0[-p.block * p.block:].any())
 
 
 @dataclass
@@ -415,7 +409,6 @@ def estimate_block(u, avail, by, bx, p: Params, cnn_gate=None):
     if mode == "brl":
         return brl, info
     want_hql = None
-    partial = is_partial(m0, p)
     if mode == "profile" and phi <= p.t_phi:
         return brl, info
     cnn_choice = None
@@ -457,7 +450,7 @@ def estimate_block(u, avail, by, bx, p: Params, cnn_gate=None):
         want_hql = True
 
     if want_hql:
-        if info["n_complete"] >= max(2, p.min_hql_cands) and not partial:
+        if info["n_complete"] >= max(2, p.min_hql_cands):
             info["layer"] = LAYER_HQL
             xs = c.x[complete]
             ys = c.y[complete][:, m0]

@@ -26,32 +26,35 @@ struct HqlLayout {
   size_t yt, xt, cyy, axy, v, v0, y0, meany, meanx, dm0, ew, ytil, xtil, vn, dch, zch, i0;
   size_t total;
   int ldm;     // leading dimension (candidates) of yt / xt, multiple of 64
-  int ldz;     // row length of zch: B^2 + NR
+  int ldz;     // row length of zch: B^2 + NY
+  int ny;      // NY: most context pixels of a block (ring, and own pixels when received)
 };
 
 __host__ __device__ inline HqlLayout hql_layout(const DevParams& p) {
   HqlLayout h;
-  const size_t NR = p.NR, MC = p.MC, B2 = (size_t)p.B * p.B;
+  const size_t MC = p.MC, B2 = (size_t)p.B * p.B;
+  const size_t NY = (size_t)p.NR + B2;          // a block's received own pixels join y0
+  h.ny = (int)NY;
   h.ldm = (int)align_up(MC, 64);
-  h.ldz = (int)(B2 + NR);
+  h.ldz = (int)(B2 + NY);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
-  h.yt = take(NR * h.ldm);
+  h.yt = take(NY * h.ldm);
   h.xt = take(B2 * h.ldm);
-  h.cyy = take(8 * NR * NR);
-  h.axy = take(8 * B2 * NR);
-  h.v = take(8 * MC * NR);
-  h.v0 = take(8 * NR);
-  h.y0 = take(8 * NR);
-  h.meany = take(8 * NR);
+  h.cyy = take(8 * NY * NY);
+  h.axy = take(8 * B2 * NY);
+  h.v = take(8 * MC * NY);
+  h.v0 = take(8 * NY);
+  h.y0 = take(8 * NY);
+  h.meany = take(8 * NY);
   h.meanx = take(8 * B2);
   h.dm0 = take(8 * MC);
   h.ew = take(8 * MC);
-  h.ytil = take(8 * NR);
+  h.ytil = take(8 * NY);
   h.xtil = take(8 * B2);
   h.vn = take(8 * MC);
   h.dch = take(8 * 64 * MC);
-  h.zch = take(8 * 64 * (B2 + NR));
+  h.zch = take(8 * 64 * (B2 + NY));
   h.i0 = take(4 * MC);
   h.total = o;
   return h;
@@ -67,7 +70,8 @@ size_t hql_lds_bytes(const DevParams& p) {
   size_t need = (size_t)4 * p.Wd * p.Wd;
   need = need > 16384 ? need : 16384;                      // FP64 GEMM tiles
   need = need > (size_t)2 * 64 * 17 * 4 ? need : (size_t)2 * 64 * 17 * 4;   // Gram tiles
-  need = need > (size_t)8 * p.NR ? need : (size_t)8 * p.NR; // Cholesky pivot row
+  const size_t ny = (size_t)p.NR + (size_t)p.B * p.B;
+  need = need > 8 * ny ? need : 8 * ny;                     // Cholesky pivot row
   return align_up(offs[9] + need, 16);
 }
 
@@ -230,7 +234,7 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
   double* dch = (double*)(slot + hl.dch);
   double* zch = (double*)(slot + hl.zch);
   int* i0l = (int*)(slot + hl.i0);
-  const int ldm = hl.ldm, ldz = hl.ldz, NRs = p.NR;
+  const int ldm = hl.ldm, ldz = hl.ldz, NRs = hl.ny;      // NRs: row stride of Ny rows
 
   // LDS reuse once the window has been gathered
   uint32_t* ta = (uint32_t*)L.winp;                  // gram tiles, 2 x 64 x 17 words
@@ -250,7 +254,11 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
 
     // -- candidates: the estimation kernel's phases, then the complete ones
     phase_stage(a, p, L, x0 - r - W, y0 - r - W);
-    const RingStats rs = phase_context(p, L, sh, NU, NU);   // HQL blocks are fully lost
+    // context units: the ring, then the block's own pixel pairs if it holds
+    // received pixels
+    const bool partial = (a.m0cnt[i] & kPartialBit) != 0;
+    const int NUe = partial ? NU + B2 / 2 : NU;
+    const RingStats rs = phase_context(p, L, sh, NU, NUe);
     const int n0 = rs.n0;
     const int M = phase_candidates(p, L, sh);
     const int nmin = max(1, (p.min_pct * n0 + 99) / 100);
@@ -260,7 +268,7 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
       int cnt = 0;
       for (int j = j0; j < j1; ++j) {
         int d, n;
-        cand_distance(L, cand_off(L.cand[j]), NU, d, n);
+        cand_distance(L, cand_off(L.cand[j]), NUe, d, n);
         const bool comp = n == n0 && n >= nmin;
         L.ell[j] = comp ? (double)d : -1.0;
         cnt += comp;
@@ -276,10 +284,11 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
       }
       if (tid == 0) sh.M = tot;
     }
-    // known ring pixels in raster order (units are raster ordered pairs)
+    // known context pixels in unit order (ring pairs in raster order, then
+    // the block's own pairs)
     {
-      const int per = (NU + kThreads - 1) / kThreads;
-      const int u0 = min(NU, tid * per), u1 = min(NU, u0 + per);
+      const int per = (NUe + kThreads - 1) / kThreads;
+      const int u0 = min(NUe, tid * per), u1 = min(NUe, u0 + per);
       int cnt = 0;
       for (int u = u0; u < u1; ++u) {
         const uint32_t qp = L.qu[u].x;
@@ -614,7 +623,9 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
       double xh = xtil[q] + alpha * corr;
       if (fail) xh = (double)rs.sum / (double)n0;
       const int py = q / B, px = q - py * B;
-      a.work[(size_t)(y0 + py) * p.stride + x0 + px] = (uint8_t)fmin(fmax(floor(xh + 0.5), 0.0), 255.0);
+      // a block holding received pixels keeps them
+      if (!partial || a.val[(size_t)(y0 + py) * p.width + x0 + px] < 0)
+        a.work[(size_t)(y0 + py) * p.stride + x0 + px] = (uint8_t)fmin(fmax(floor(xh + 0.5), 0.0), 255.0);
       if (a.xhat && i < a.cap) a.xhat[(size_t)i * B2 + q] = (float)xh;
     }
     if (tid == 0) {

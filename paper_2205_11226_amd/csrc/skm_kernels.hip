@@ -519,7 +519,7 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
       else want_hql = p.mode == SKM_MODE_PROFILE || (p.mode == SKM_MODE_CNN && !cnn);
     }
     if (want_hql) {
-      if (ncom >= max(2, p.min_hql) && !partial) layer = SKM_LAYER_HQL;
+      if (ncom >= max(2, p.min_hql)) layer = SKM_LAYER_HQL;
       else flags |= SKM_FLAG_NO_HQL;
     }
     const double lnu_r = readlane_f64(lnu, ridx);      // ridx is uniform in the wave

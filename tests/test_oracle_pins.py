@@ -101,19 +101,22 @@ def test_constant_frame_with_arbitrary_loss_is_restored():
             np.testing.assert_allclose(v, 93.0, rtol=0, atol=1e-12)
 
 
-def test_partial_cells_never_take_hql():
+def test_received_pixels_of_a_cell_join_the_hql_context():
     f = tiny_frame(34, 40, 40)
     m = cells_mask(40, 40, 8, [(2, 2)])
     m[16, 16] = 0                          # one received pixel in the cell
     p = Params(block=8, ring=2, window=12, min_hql_cands=8, mode="full")
     out, xh, info = conceal(f, m, p)
     (i,) = info
-    assert i["layer"] == LAYER_IDL and i["flags"] & 2
+    assert i["layer"] == LAYER_HQL
     assert i["n_ctx"] == (8 + 4) ** 2 - 64 + 1
     assert out[16, 16] == f[16, 16]
-    # the same cell fully lost does reach HQL (enough complete candidates)
-    _, _, info2 = conceal(f, cells_mask(40, 40, 8, [(2, 2)]), p)
-    assert info2[0]["layer"] == LAYER_HQL
+    # an affine ramp is reproduced exactly by HQL with the extra context pixel
+    yy, xx = np.mgrid[0:40, 0:40]
+    ramp = (40 + 2 * yy + 3 * xx).astype(np.uint8)
+    out_r, xh_r, info_r = conceal(ramp, m, p)
+    assert info_r[0]["layer"] == LAYER_HQL
+    np.testing.assert_allclose(xh_r[(2, 2)], ramp[16:24, 16:24], rtol=0, atol=1e-6)
 
 
 # ------------------------------------------------------------------ distances
