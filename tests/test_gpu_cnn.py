@@ -118,7 +118,7 @@ def test_save_load_roundtrip(ctx):
     np.testing.assert_array_equal(ctx.cnn_get_weights(), w)
 
 
-@pytest.mark.parametrize("workload", ["plain_512", "random_b8"])
+@pytest.mark.parametrize("workload", ["plain_512", "random_b8", "arbitrary_shape"])
 def test_cnn_mode_parity(ctx, workload):
     """Concealment in CNN mode: the oracle runs the same network (float64)
     on its own inputs; decisions may differ only within 1e-3 dB of a
@@ -126,10 +126,14 @@ def test_cnn_mode_parity(ctx, workload):
     if workload == "plain_512":
         f, m = synth.workload_plain_512()
         kw = dict()
-    else:
+    elif workload == "random_b8":
         f = synth.make_luma(120, 152, 33, n_bumps=10, n_edges=5)
         m = synth.loss_random(120, 152, 8, 0.3, 34)
         kw = dict(block=8)
+    else:                                  # cells keeping some received pixels
+        f = synth.make_luma(144, 176, 35, n_bumps=10, n_edges=5)
+        m = synth.loss_partial_cells(144, 176, 16, 0.4, 36, frac=0.6)
+        kw = dict(min_hql_cands=8)
     params = ocnn.init_params(31)
     w = ocnn.pack(params).astype(np.float32)
     ctx.cnn_set_weights(w)
@@ -166,6 +170,8 @@ def test_cnn_mode_parity(ctx, workload):
         assert err <= 1e-3, (key, err)
     print(workload, "layers", layers, "near", len(near), flush=True)
     assert len(layers) == 3
+    keep = m == 0
+    assert np.array_equal(out.cpu().numpy()[keep], f[keep])
 
 
 def _psnr(a, b):
