@@ -106,6 +106,34 @@ def test_batch_matches_single_frames(ctx):
     ctx.set_option(skm.OPT_BATCH_STREAMS, 4)
 
 
+def test_batch_arbitrary_shape_loss_matches_single_frames(ctx):
+    """Cells that keep received pixels, in a batch of mixed geometry and
+    modes (graph replay on and off): bit-identical to single-frame runs."""
+    import paper_2205_11226_amd as skm
+    frames, prms = [], []
+    for k, (h, w, b, mode) in enumerate([(144, 176, 16, "profile"), (120, 152, 8, "plain"),
+                                          (144, 176, 16, "cnn"), (96, 128, 8, "full")]):
+        f = synth.make_luma(h, w, 300 + k, n_bumps=10, n_edges=5)
+        m = synth.loss_partial_cells(h, w, b, 0.35, 310 + k, frac=0.6)
+        frames.append((f, m))
+        prms.append(device_params(mode, block=b, min_hql_cands=8))
+    refs = [run_single(ctx, f, m, prm) for (f, m), prm in zip(frames, prms)]
+    for (f, m), ref in zip(frames, refs):
+        assert np.array_equal(ref[0][m == 0], f[m == 0])
+    for graphs in (0, 1):
+        ctx.set_option(skm.OPT_GRAPHS, graphs)
+        jobs, outs = _batch_jobs(frames, prms)
+        res = ctx.conceal_batch(jobs)
+        for k, ((out, info, xh), ref) in enumerate(zip(outs, refs)):
+            n, rounds, st = res[k]
+            assert st == 0 and n == len(ref[1]), (graphs, k)
+            assert np.array_equal(out.cpu().numpy(), ref[0]), (graphs, k)
+            gi = info.cpu().numpy().view(skm.BLOCK_INFO_DTYPE)[:n]
+            assert gi.tobytes() == ref[1].tobytes(), (graphs, k)
+            assert np.array_equal(xh[:n].cpu().numpy(), ref[2]), (graphs, k)
+    ctx.set_option(skm.OPT_GRAPHS, 1)
+
+
 def test_batch_reports_errors_per_frame(ctx):
     import paper_2205_11226_amd as skm
     f = synth.make_luma(128, 128, 5)
