@@ -35,7 +35,6 @@ struct FrameSlot {
   int* d_m0cnt = nullptr;
   int2* d_ring = nullptr;
   int* d_hql_list = nullptr;      size_t cap_cells = 0;
-  int* d_part = nullptr;
   unsigned char* d_hql_ws = nullptr; size_t cap_hql = 0;
   int8_t* d_gate = nullptr;
   float* d_gate_pred = nullptr;   size_t cap_gate = 0;
@@ -193,7 +192,6 @@ skm_status slot_create(skm_ctx* c, FrameSlot** out) {
   SKM_HIP(hipHostMalloc((void**)&f->h_state, sizeof(RoundState), hipHostMallocCoherent),
           "pinned round state");
   memset(f->h_state, 0, sizeof(RoundState));
-  SKM_HIP(hipMalloc((void**)&f->d_part, sizeof(int) * 2 * kPartSlots), "prep slots");
   (void)c;
   return SKM_OK;
 }
@@ -209,7 +207,6 @@ void slot_destroy(FrameSlot* f) {
   (void)hipFree(f->d_m0cnt);
   (void)hipFree(f->d_ring);
   (void)hipFree(f->d_hql_list);
-  (void)hipFree(f->d_part);
   (void)hipFree(f->d_hql_ws);
   (void)hipFree(f->d_gate);
   (void)hipFree(f->d_gate_pred);
@@ -289,7 +286,7 @@ FrameArgs frame_args(FrameSlot* f, const uint8_t* frame, const uint8_t* mask, ui
   memset(&a, 0, sizeof(a));
   a.frame = frame; a.mask = mask; a.work = out;
   a.val = f->d_val + kValGuard; a.cellbits = f->d_cellbits; a.blk = f->d_blk;
-  a.bstate = f->d_bstate; a.m0cnt = f->d_m0cnt; a.ring = f->d_ring; a.part = f->d_part;
+  a.bstate = f->d_bstate; a.m0cnt = f->d_m0cnt; a.ring = f->d_ring;
   a.st = f->d_state;
   a.hstate = f->h_state;
   a.hql_list = f->d_hql_list;

@@ -586,8 +586,9 @@ static __device__ __forceinline__ u32x4 s2d_pixel(const int* v) {
 // pass over the pending blocks of the round.  For each it records the
 // known in-frame ring pixels (count, sum, minimum, maximum) from the window
 // it has loaded anyway, evaluates the network and writes the layer choice to
-// gate[i] (the predictions to gate_pred).  Workgroup w publishes (blocks
-// with |m0| >= r B, largest |m0|) in part slot w, as the prep kernel does.
+// gate[i] (the predictions to gate_pred).  Each workgroup adds its (blocks
+// with |m0| >= r B, largest |m0|) to the round's context rule, as the prep
+// kernel does.
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_gate(
     FrameArgs a, DevParams p, const uint4* pk, const float* wq, float tau1, float tau2) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -688,8 +689,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     __syncthreads();
   }
   if (tid == 0) {
-    a.part[2 * blockIdx.x] = wg_nq;
-    a.part[2 * blockIdx.x + 1] = wg_max;
+    note_context_rule(st, wg_nq, wg_max);
   }
 }
 

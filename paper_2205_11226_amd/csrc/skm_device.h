@@ -143,6 +143,21 @@ static __device__ __forceinline__ void shr128(uint64_t lo, uint64_t hi, int s, u
   else { olo = hi >> (s - 64); ohi = 0; }
 }
 
+// Adds a workgroup's (blocks with |m0| >= r B, largest |m0|) to the round's
+// context rule (thread 0 calls it).  Only "some block is eligible" and, when
+// none is, the largest |m0| matter, so the field is read first and the
+// device-scope atomic is skipped when it would change nothing: after the
+// first few workgroups, most do no atomic at all.
+static __device__ __forceinline__ void note_context_rule(RoundState* st, int nq, int mx) {
+  if (nq > 0) {
+    if (__hip_atomic_load(&st->ctx_nq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+      atomicMax(&st->ctx_nq, 1);
+  } else if (mx > 0) {
+    if (__hip_atomic_load(&st->ctx_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < mx)
+      atomicMax(&st->ctx_max, mx);
+  }
+}
+
 // ------------------------------------------------------------ LDS layout
 //
 // Per-block LDS carve-up (dynamic).  MC bounds the number of admissible

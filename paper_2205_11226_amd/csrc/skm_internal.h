@@ -42,7 +42,7 @@ struct DevParams {
   // first schedule radius >= rho), word rho / 16
   unsigned long long bucket_lut[3];
   int min_pct, min_hql, mode;
-  int prep_grid;   // workgroups that wrote `part` (prep kernel, or the gate in CNN mode)
+  int prep_grid;   // workgroups of the round preparation (prep kernel, or the gate in CNN mode)
   int cnn_active;  // CNN mode with a loaded network (else the profile rule)
   int width, height, stride;
   int gh, gw;      // full cells
@@ -57,6 +57,12 @@ struct RoundState {
   int n_hql;           // blocks of this round waiting for the HQL kernel
   unsigned long long n_avail;     // fill: known pixels and their sum
   unsigned long long sum_avail;
+  // Context rule of the round, from the prep or gate workgroups: ctx_nq is 1
+  // when some pending block has |m0| >= r B, ctx_max the largest |m0| of the
+  // workgroups without one; zeroed where a round starts (k_init,
+  // k_round_finalize).  See note_context_rule.
+  int ctx_nq;
+  int ctx_max;
   // Zero between launches (the slot's allocation starts zeroed; the kernel
   // that consumes a field clears it):
   int err_geo;                    // geometry errors found by k_init
@@ -65,7 +71,6 @@ struct RoundState {
 };
 
 constexpr int kPrepGridMax = 512;   // workgroups of the prep kernel
-constexpr int kPartSlots = 4096;    // slots in `part`: the prep kernel's or the gate's workgroups
 
 // bstate values: 0 pending, > 0 concealed in that round, kNeedHql + round:
 // waiting for the HQL kernels in that round.
@@ -85,7 +90,6 @@ struct FrameArgs {
                           // (ring and the block's own), | kPartialBit when
                           // the block holds received pixels
   int2* ring;             // their sum, and min | max << 16 (prep kernel)
-  int* part;              // 2 * kPartSlots round-preparation partials
   int* hql_list;          // lost-block indices waiting for HQL in this round
   int8_t* gate;           // CNN mode: layer chosen for each lost block
   float* gate_pred;       // CNN mode: the two predicted gains of each lost block

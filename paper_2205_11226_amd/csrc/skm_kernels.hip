@@ -158,15 +158,16 @@ __global__ __launch_bounds__(kThreads) void k_init(FrameArgs a, DevParams p) {
     st->n_lost = tot; st->remaining = tot; st->round = 1;
     st->err = atomicExch(&st->err_geo, 0);
     st->n_hql = 0; st->n_avail = 0; st->sum_avail = 0;
+    st->ctx_nq = 0; st->ctx_max = 0;
     publish_state(a);
   }
 }
 
 // ------------------------------------------------------------- round prep
-// One wave per pending block: |m0| = known in-frame ring pixels, with their
+// One wave per pending block: |m0| = known in-frame context pixels, with their
 // sum, minimum and maximum (the context mean and flatness of the BRL gate).
-// Each workgroup publishes (blocks with |m0| >= r B, largest |m0|) in its
-// own slot of `part`; the later kernels reduce the slots.  No atomics.
+// Each workgroup adds its (blocks with |m0| >= r B, largest |m0|) to the
+// round state's context rule (integer atomics, so the result is order-free).
 __global__ __launch_bounds__(kThreads) void k_round_prep(FrameArgs a, DevParams p) {
   __shared__ int s_nq[kThreads / 64], s_mx[kThreads / 64];
   RoundState* st = a.st;
@@ -224,8 +225,7 @@ __global__ __launch_bounds__(kThreads) void k_round_prep(FrameArgs a, DevParams 
   if (threadIdx.x == 0) {
     int nq = 0, mx = 0;
     for (int w = 0; w < kThreads / 64; ++w) { nq += s_nq[w]; mx = max(mx, s_mx[w]); }
-    a.part[2 * blockIdx.x] = nq;
-    a.part[2 * blockIdx.x + 1] = mx;
+    note_context_rule(st, nq, mx);
   }
 }
 
@@ -277,35 +277,28 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
   // go round-robin to the 8 XCDs, so XCD x takes the x-th contiguous eighth
   // of the (raster ordered) lost blocks: neighbouring windows share its L2.
   const int i = xcd_block(blockIdx.x, n_lost);
-  if (i < 0 || a.bstate[i] != 0) return;
+  if (i < 0) return;
+  // the block's values in one round trip, tested afterwards
+  const int bst = a.bstate[i], cell = a.blk[i], m0w = a.m0cnt[i];
+  const int2 rg = a.ring[i];
+  const bool cnn = p.mode == SKM_MODE_CNN && p.cnn_active;
+  const int gsel = (cnn && !dist_only) ? (int)a.gate[i] : -1;
+  // context rule of the round (prep or gate workgroups)
+  const int nq = st->ctx_nq, maxm0 = st->ctx_max;
+  if (bst != 0) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   const int B = p.B, r = p.r, W = p.W, Wd = p.Wd, D2 = 2 * W + 1;
   const int B2 = B * B;
-  const int cell = a.blk[i];
   const int by = cell / p.gw, bx = cell - by * p.gw;
   const int x0 = bx * B, y0 = by * B;
-  // the window loads go out first; they land while the round's context
-  // statistics are reduced
+  // the window loads go out first; they land while the decisions below run
   const StageGeom SG = stage_geom(p, x0 - r - W);
   StageRegs SR;
   if (!dist_only) stage_issue(a, p, SG, y0 - r - W, SR);
-  // context-size gate of the round, from the prep kernel's per-workgroup partials
-  int nq = 0, maxm0 = 0;
-  for (int g = tid; g < p.prep_grid; g += kThreads) {
-    nq += a.part[2 * g];
-    maxm0 = max(maxm0, a.part[2 * g + 1]);
-  }
-  nq = wave_sum_full(nq);
-  maxm0 = wave_max(maxm0);
-  if (lane == 0) { sh.red_i[wave][0] = nq; sh.red_i[wave][1] = maxm0; }
-  __syncthreads();
-  nq = 0; maxm0 = 0;
-  for (int w = 0; w < kThreads / 64; ++w) { nq += sh.red_i[w][0]; maxm0 = max(maxm0, sh.red_i[w][1]); }
   if (!dist_only && nq == 0 && maxm0 == 0) {
     if (tid == 0) atomicOr(&st->err, kErrNoContext);
     return;
   }
-  const int m0w = a.m0cnt[i];
   const int n0 = m0w & (kPartialBit - 1);
   const bool partial = (m0w & kPartialBit) != 0;      // the block holds received pixels
   if (!dist_only && !(nq > 0 ? (n0 >= p.r * p.B) : (n0 == maxm0))) return;
@@ -314,12 +307,9 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
   // 1. BRL gate on the prep kernel's ring statistics: context mean for every
   //    pixel of the block (profile rule, or the learned gate's choice in CNN
   //    mode), without staging the window
-  const int2 rg = a.ring[i];
   const int phi = n0 > 0 ? (rg.y >> 16) - (rg.y & 0xffff) : 0;
   const double mean = n0 > 0 ? (double)rg.x / (double)n0 : 0.0;
   const int relaxed_flag = (!dist_only && nq == 0) ? SKM_FLAG_CTX_RELAXED : 0;
-  const bool cnn = p.mode == SKM_MODE_CNN && p.cnn_active;
-  const int gsel = (cnn && !dist_only) ? (int)a.gate[i] : -1;
   const bool profile_rule = p.mode == SKM_MODE_PROFILE || (p.mode == SKM_MODE_CNN && !cnn);
   if (!dist_only && (p.mode == SKM_MODE_BRL || (profile_rule && (double)phi <= p.t_phi) ||
                      gsel == SKM_LAYER_BRL)) {
@@ -722,6 +712,7 @@ __global__ __launch_bounds__(kThreads) void k_round_finalize(FrameArgs a, DevPar
         st->round_acc = 0ull;
         st->remaining = (int)(tot & 0xffffffull);
         st->round = round + 1;
+        st->ctx_nq = 0; st->ctx_max = 0;
         if ((tot >> 24) & 0xffffffull) st->err |= kErrHqlPending;
         publish_state(a);
       }
