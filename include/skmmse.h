@@ -84,7 +84,7 @@ enum {
 };
 
 typedef struct skm_params {
-  int32_t block;           /* B: 4, 8 or 16                                    */
+  int32_t block;           /* B: 2, 4, 8 or 16 (2: no SKM_MODE_CNN)           */
   int32_t ring;            /* context ring width r, 1..8                      */
   int32_t window;          /* search window half-size W, 1..32                */
   int32_t expand_step;     /* IDL support-area growth step (Chebyshev px);
@@ -122,6 +122,18 @@ typedef struct skm_ctx skm_ctx;
  * overlap 50 %, HQL from 64 complete candidates, sigma^2 10, the "efficient"
  * profile (T_phi 20, T_nu 0.1), ridge 1e-3, SKM_MODE_PROFILE, no round limit. */
 void skm_default_params(skm_params* p);
+
+/* Fill `p` with the paper's own patch geometry (Sec. "Reconstruction
+ * framework"): the missing vector x0 is a 2 x 2 patch and its context the
+ * available pixels of the 6 x 6 neighbourhood centred on it, so B 2 and
+ * ring 2; everything else as skm_default_params.  The window of +-24 pixels
+ * around a patch at the centre of a lost 16 x 16 block spans the 8
+ * neighbouring blocks, the support area of the paper's experiments.
+ * Patches whose ring holds fewer than ring*block = 4 known pixels wait for
+ * the next round, so the rounds fill a lost region layer by layer from its
+ * border towards its centre (the sequential order of the same section and
+ * its filling-order figure).  SKM_MODE_CNN is not available. */
+void skm_patch_params(skm_params* p);
 
 /* Create a context bound to HIP device `hip_device`.  The context owns its
  * device workspace (grown on demand) and, once loaded, the CNN gate weights.

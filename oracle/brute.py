@@ -201,7 +201,10 @@ def hql(xs, ys, y0, deu, ridge_rel):
     d0 = max(min(dm0), 1e-9)
     grid = [d0 * 2.0 ** (g / 2.0) for g in range(-8, 25)]
     eg = [eps(bt) for bt in grid]
-    gs = eg.index(min(eg))
+    emin = min(eg)
+    gs = 0
+    while eg[gs] > emin * (1.0 + 1e-12):          # flat minimum: smallest beta
+        gs += 1
     a_t = math.log(grid[max(gs - 1, 0)])
     b_t = math.log(grid[min(gs + 1, len(grid) - 1)])
     ip = (math.sqrt(5.0) - 1.0) / 2.0
@@ -218,7 +221,7 @@ def hql(xs, ys, y0, deu, ridge_rel):
             d_t = a_t + ip * (b_t - a_t)
             fd = eps(math.exp(d_t))
     beta = math.exp(0.5 * (a_t + b_t))
-    if eps(beta) > eg[gs]:
+    if not eps(beta) < eg[gs] * (1.0 - 1e-12):
         beta = grid[gs]
     w = wts(beta)
     xt = [sum(w[j] * xs[j][p] for j in range(M)) for p in range(nx)]

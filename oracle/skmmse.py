@@ -282,6 +282,11 @@ def _softmax_rows(logits: np.ndarray) -> np.ndarray:
 
 
 BETA_G_LO, BETA_G_HI, GOLDEN_STEPS = -8, 24, 40
+# eps_y values within this relative margin count as equal: where eps_y is
+# flat (as beta -> 0 the weights become one-hot on the nearest candidate and
+# eps_y saturates), the argmin of eq. epsy is not unique and rounding alone
+# would pick among the flat betas, which alpha then depends on
+EPS_TIE_REL = 1e-12
 
 
 def hql_estimate(x: np.ndarray, y: np.ndarray, y0: np.ndarray, d_euclid: np.ndarray,
@@ -301,7 +306,9 @@ def hql_estimate(x: np.ndarray, y: np.ndarray, y0: np.ndarray, d_euclid: np.ndar
     4. beta = argmin eps_y(beta) (eq. epsy): first minimiser on the grid
        D0 2^(g/2), g = -8..24, D0 = max(min_j D(y0, y_j), 1e-9), refined by
        40 golden-section steps on log beta between the neighbouring grid
-       points; the refined value is kept only if it is not worse;
+       points; grid values within a relative EPS_TIE_REL of the smallest count
+       as minimisers, and the refined value is kept only if it is better than
+       the grid's by that margin (a flat minimum keeps its smallest beta);
     5. alpha = argmin eps_x(alpha) (eq. epsx) over I0 = the Ny + 1 candidates
        closest to y0 in Euclidean distance (ties by raster index); each x_i is
        predicted leave-one-out from the other candidates with the same beta
@@ -339,7 +346,9 @@ def hql_estimate(x: np.ndarray, y: np.ndarray, y0: np.ndarray, d_euclid: np.ndar
     d0 = max(float(dmah0.min()), 1e-9)
     grid = [d0 * 2.0 ** (g / 2.0) for g in range(BETA_G_LO, BETA_G_HI + 1)]
     eg = [eps_y(bt) for bt in grid]
-    gstar = int(np.argmin(eg))                        # first minimiser
+    emin = min(eg)
+    # first minimiser; a flat minimum resolves to its smallest beta
+    gstar = next(g for g, e in enumerate(eg) if e <= emin * (1.0 + EPS_TIE_REL))
     a_t = math.log(grid[max(gstar - 1, 0)])
     b_t = math.log(grid[min(gstar + 1, len(grid) - 1)])
     invphi = (math.sqrt(5.0) - 1.0) / 2.0
@@ -357,7 +366,7 @@ def hql_estimate(x: np.ndarray, y: np.ndarray, y0: np.ndarray, d_euclid: np.ndar
             d_t = a_t + invphi * (b_t - a_t)
             fd = eps_y(math.exp(d_t))
     beta = math.exp(0.5 * (a_t + b_t))
-    if eps_y(beta) > eg[gstar]:
+    if not eps_y(beta) < eg[gstar] * (1.0 - EPS_TIE_REL):    # kept only if better
         beta = grid[gstar]
 
     w0 = weights(beta)

@@ -16,7 +16,7 @@ MODES = {"profile": 0, "cnn": 1, "brl": 2, "idl": 3, "full": 4, "plain": 5}
 LAYER_FILL, LAYER_BRL, LAYER_IDL, LAYER_HQL = -1, 0, 1, 2
 FLAG_CTX_RELAXED, FLAG_NO_HQL, FLAG_NO_CAND, FLAG_EMPTY_CTX = 1, 2, 4, 8
 
-EXPORTS = ("skm_default_params", "skm_create", "skm_destroy", "skm_conceal",
+EXPORTS = ("skm_default_params", "skm_patch_params", "skm_create", "skm_destroy", "skm_conceal",
            "skm_conceal_device", "skm_distances_device", "skm_cnn_init", "skm_cnn_set_weights",
            "skm_cnn_get_weights", "skm_cnn_set_thresholds", "skm_save_cnn", "skm_load_cnn",
            "skm_cnn_inputs", "skm_cnn_forward", "skm_cnn_gradients", "skm_cnn_train_step",
@@ -79,6 +79,8 @@ def _load():
     p, i32, vp = ctypes.POINTER, ctypes.c_int32, ctypes.c_void_p
     so.skm_default_params.argtypes = [p(Params)]
     so.skm_default_params.restype = None
+    so.skm_patch_params.argtypes = [p(Params)]
+    so.skm_patch_params.restype = None
     so.skm_create.argtypes = [i32, p(vp)]
     so.skm_create.restype = i32
     so.skm_destroy.argtypes = [vp]
@@ -141,6 +143,17 @@ def default_params(**kw) -> Params:
     """Paper defaults; keyword overrides (``mode`` may be a name)."""
     prm = Params()
     lib.skm_default_params(ctypes.byref(prm))
+    return _override(prm, kw)
+
+
+def patch_params(**kw) -> Params:
+    """The paper's 2 x 2 patch geometry (B 2, ring 2); keyword overrides."""
+    prm = Params()
+    lib.skm_patch_params(ctypes.byref(prm))
+    return _override(prm, kw)
+
+
+def _override(prm: Params, kw: dict) -> Params:
     profile = kw.pop("profile", None)
     if profile is not None:
         tphi, tnu = {"express": (20.0, 0.01), "efficient": (20.0, 0.1),

@@ -125,8 +125,10 @@ skm_status make_params(const skm_params* in, int width, int height, int stride, 
   if (!in) return fail(SKM_EINVAL, "params is NULL");
   if (width <= 0 || height <= 0) return fail(SKM_EINVAL, "width and height must be positive");
   if (stride < width) return fail(SKM_EINVAL, "stride must be >= width");
-  if (!(in->block == 4 || in->block == 8 || in->block == 16))
-    return fail(SKM_EINVAL, "block must be 4, 8 or 16");
+  if (!(in->block == 2 || in->block == 4 || in->block == 8 || in->block == 16))
+    return fail(SKM_EINVAL, "block must be 2, 4, 8 or 16");
+  if (in->block == 2 && in->mode == SKM_MODE_CNN)
+    return fail(SKM_EINVAL, "cnn mode needs block 4, 8 or 16");
   if (in->ring < 1 || in->ring > kMaxRing) return fail(SKM_EINVAL, "ring must be in 1..8");
   if (in->window < 1 || in->window > kMaxWin) return fail(SKM_EINVAL, "window must be in 1..32");
   if (in->expand_step < 1) return fail(SKM_EINVAL, "expand_step must be >= 1");
@@ -475,6 +477,12 @@ void skm_default_params(skm_params* p) {
   p->block = 16; p->ring = 4; p->window = 24; p->expand_step = 4;
   p->min_overlap_pct = 50; p->min_hql_cands = 64; p->mode = SKM_MODE_PROFILE;
   p->max_rounds = 0; p->sigma2 = 10.0; p->t_phi = 20.0; p->t_nu = 0.1; p->ridge_rel = 1e-3;
+}
+
+void skm_patch_params(skm_params* p) {
+  if (!p) return;
+  skm_default_params(p);
+  p->block = 2; p->ring = 2;
 }
 
 const char* skm_last_error(void) { return g_err.c_str(); }

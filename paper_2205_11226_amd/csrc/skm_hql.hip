@@ -9,8 +9,9 @@
 //           I0 = the N_y + 1 observations closest to y0                (eq. epsx)
 // Readings where the paper is silent: C_ZZ normalised by 1/M with a ridge
 // lambda = ridge_rel tr(C_YY)/N_y + 1e-12 on C_YY; beta from the first
-// minimiser of a grid D0 2^(g/2), g = -8..24, refined by 40 golden-section
-// steps on log beta and kept only if not worse; I0 by Euclidean distance with
+// minimiser of a grid D0 2^(g/2), g = -8..24 (grid values within a relative
+// 1e-12 of the smallest count as minimisers), refined by 40 golden-section
+// steps on log beta and kept only if better by that margin; I0 by Euclidean distance with
 // ties to the lower raster index; each x_i predicted leave-one-out; alpha in
 // closed form (x_i_hat is affine in alpha).
 //
@@ -75,8 +76,15 @@ size_t hql_lds_bytes(const DevParams& p) {
   return align_up(offs[9] + need, 16);
 }
 
+// eps_y values within this relative margin count as equal: where eps_y is
+// flat (as beta -> 0 the weights become one-hot on the nearest candidate), the
+// argmin of eq. epsy is not unique, so the smallest flat beta is taken and a
+// refined beta must improve on it by more than the margin
+constexpr double kEpsTieRel = 1e-12;
+
 struct HqlShared {
   double red[kThreads / 64];
+  double eg[33];                 // eps_y on the beta grid g = -8 .. 24
   double dk, lam, S, eps, dmin;
   int fail;
   double rowS[64];
@@ -252,7 +260,13 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
     const int by = cell / p.gw, bx = cell - by * p.gw;
     const int x0 = bx * B, y0 = by * B;
 
-    // -- candidates: the estimation kernel's phases, then the complete ones
+    // -- candidates: the estimation kernel's phases, then the complete ones.
+    //    Staging ORs the window's availability into rowbits, so a workgroup
+    //    that takes several blocks clears it for each one.
+    if (h != (int)blockIdx.x) {
+      for (int k = tid; k < 2 * Wd; k += kThreads) L.rowbits[k] = 0ull;
+      __syncthreads();
+    }
     phase_stage(a, p, L, x0 - r - W, y0 - r - W);
     // context units: the ring, then the block's own pixel pairs if it holds
     // received pixels
@@ -420,13 +434,18 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
 
     // -- beta: first grid minimiser, golden-section refinement on log beta
     const double D0 = fmax(dmin, 1e-9);
-    double best_eps = INFINITY;
-    int gstar = 0;
+    double emin = INFINITY;
     for (int g = -8; g <= 24; ++g) {
       const double bt = D0 * exp2((double)g / 2.0);
       const double e = eval_eps(bt, Mc, Ny, B2, ldm, dm0, dmin, ew, yt, nullptr, y0v, ytil, nullptr, hs);
-      if (e < best_eps) { best_eps = e; gstar = g; }
+      if (tid == 0) hs.eg[g + 8] = e;
+      emin = fmin(emin, e);
     }
+    __syncthreads();
+    int gstar = 24;
+    for (int g = 24; g >= -8; --g)
+      if (hs.eg[g + 8] <= emin * (1.0 + kEpsTieRel)) gstar = g;
+    const double best_eps = hs.eg[gstar + 8];
     double beta;
     {
       const int glo = max(gstar - 1, -8), ghi = min(gstar + 1, 24);
@@ -450,7 +469,7 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
       }
       beta = exp(0.5 * (at + bt));
       const double eb = eval_eps(beta, Mc, Ny, B2, ldm, dm0, dmin, ew, yt, nullptr, y0v, ytil, nullptr, hs);
-      if (eb > best_eps) beta = D0 * exp2((double)gstar / 2.0);
+      if (!(eb < best_eps * (1.0 - kEpsTieRel))) beta = D0 * exp2((double)gstar / 2.0);
     }
 
     // -- I0: the min(Ny + 1, Mc) candidates of smallest (distance, index),

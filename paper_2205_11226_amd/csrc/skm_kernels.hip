@@ -38,8 +38,9 @@ __device__ __forceinline__ void publish_state(const FrameArgs& a) {
 // B rows); each thread owns four adjacent columns of a band (32-bit loads and
 // stores where the rows allow them): copies received pixels to `work` (lost
 // ones become 128 and are never read), writes the value plane (-1 = lost),
-// and the B / 4 threads of one cell vote whether the cell is wholly lost.  A
-// lost pixel outside the full-cell grid, or a partly lost cell, is an error.
+// and the B / 4 threads of one cell (for B = 2: each thread's two cells) vote
+// whether the cell holds a lost pixel.  A lost pixel outside the full-cell
+// grid is an error.
 // Lost cells are ORed into a bit table with device-scope atomics (coherent
 // across XCDs without a cache flush); the workgroup that finishes last lists
 // them in raster order, clears the table and starts the frame state.
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(kThreads) void k_init(FrameArgs a, DevParams p) {
   // 32-bit accesses when the four columns are in the frame and aligned
   const bool vec = x + 3 < p.width && ((p.stride | p.width) & 3) == 0 &&
                    (((uintptr_t)a.frame | (uintptr_t)a.mask | (uintptr_t)a.work) & 3) == 0;
-  int nl = 0;
+  int nl = 0, nl_hi = 0;                             // lost pixels; of columns 2, 3
   if (vec) {
     uint32_t mk[kMaxB], fv[kMaxB];
 #pragma unroll
@@ -77,6 +78,7 @@ __global__ __launch_bounds__(kThreads) void k_init(FrameArgs a, DevParams p) {
           const uint32_t vv = lost ? 0xffffu : pix;
           if (q < 2) v01 |= vv << (16 * q); else v23 |= vv << (16 * (q - 2));
           nl += lost;
+          nl_hi += q >= 2 && lost;
         }
         const int y = y0 + i;
         *reinterpret_cast<uint32_t*>(a.work + (size_t)y * p.stride + x) = wk;
@@ -95,32 +97,52 @@ __global__ __launch_bounds__(kThreads) void k_init(FrameArgs a, DevParams p) {
         a.work[off] = lost ? (uint8_t)128 : v;
         a.val[(size_t)y * p.width + xq] = lost ? (int16_t)-1 : (int16_t)v;
         nl += lost;
+        nl_hi += q >= 2 && lost;
       }
     }
   }
-  const int TB = B >> 2;                             // threads per cell
-  const bool in_cells = band < p.gh && x < p.gw * B;
-  int bad = (nl > 0 && !in_cells) ? 1 : 0;
-  int v = nl;
-  for (int o = 1; o < TB; o <<= 1) v += __shfl_xor(v, o, 64);   // cells never straddle waves
-  const bool leader = in_cells && (lane & (TB - 1)) == 0;
-  // a cell with any lost pixel is a block (its received pixels join the context)
-  const uint64_t lm = __ballot(leader && v > 0);
-  const bool any_bad = __ballot(bad != 0) != 0ull;
+  uint64_t lm = 0, lm_hi = 0;
+  bool any_bad;
+  if (B == 2) {
+    // two cells per thread: columns 0-1 and 2-3
+    const int cx = x >> 1;
+    const bool in0 = band < p.gh && cx < p.gw, in1 = band < p.gh && cx + 1 < p.gw;
+    const int n0 = nl - nl_hi;
+    lm = __ballot(in0 && n0 > 0);
+    lm_hi = __ballot(in1 && nl_hi > 0);
+    any_bad = __ballot((n0 > 0 && !in0) || (nl_hi > 0 && !in1)) != 0ull;
+  } else {
+    const int TB = B >> 2;                           // threads per cell
+    const bool in_cells = band < p.gh && x < p.gw * B;
+    int v = nl;
+    for (int o = 1; o < TB; o <<= 1) v += __shfl_xor(v, o, 64);   // cells never straddle waves
+    const bool leader = in_cells && (lane & (TB - 1)) == 0;
+    // a cell with any lost pixel is a block (its received pixels join the context)
+    const uint64_t lv = __ballot(leader && v > 0);
+    for (int k = 0; k < 64 / TB; ++k) lm |= ((lv >> (k * TB)) & 1ull) << k;
+    any_bad = __ballot(nl > 0 && !in_cells) != 0ull;
+  }
   if (lane == 0) {
     unsigned int sink = 0;
-    if (lm) {
-      // this wave's cells are consecutive: 256 / B of them from cell cb
+    if (lm | lm_hi) {
+      // this wave's cells are consecutive from cell cb: 256 / B of them, bit
+      // k of the 128-bit run (lo, hi) for cell cb + k
       const int cb = band * p.gw + (blockIdx.x * kThreads + wave * 64) * 4 / B;
-      uint64_t bits = 0;
-      for (int k = 0; k < 64 / TB; ++k) bits |= ((lm >> (k * TB)) & 1ull) << k;
+      uint64_t lo = lm, hi = 0;
+      if (B == 2) {
+        lo = 0;
+        for (int k = 0; k < 32; ++k) {
+          lo |= ((lm >> k) & 1ull) << (2 * k) | ((lm_hi >> k) & 1ull) << (2 * k + 1);
+          hi |= ((lm >> (k + 32)) & 1ull) << (2 * k) | ((lm_hi >> (k + 32)) & 1ull) << (2 * k + 1);
+        }
+      }
+      const uint32_t src[4] = {(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)};
       const int w = cb >> 5, sh = cb & 31;
-      const uint32_t p0 = (uint32_t)(bits << sh);
-      const uint32_t p1 = (uint32_t)(sh ? (bits >> (32 - sh)) : (bits >> 32));
-      const uint32_t p2 = sh ? (uint32_t)(bits >> (64 - sh)) : 0u;
-      if (p0) sink ^= atomicOr(&a.cellbits[w], p0);
-      if (p1) sink ^= atomicOr(&a.cellbits[w + 1], p1);
-      if (p2) sink ^= atomicOr(&a.cellbits[w + 2], p2);
+      for (int k = 0; k < 5; ++k) {
+        uint32_t pk = k < 4 ? src[k] << sh : 0u;
+        if (k > 0 && sh) pk |= src[k - 1] >> (32 - sh);
+        if (pk) sink ^= atomicOr(&a.cellbits[w + k], pk);
+      }
     }
     if (any_bad) sink ^= (unsigned int)atomicOr(&st->err_geo, kErrPartial);
     asm volatile("" ::"v"(sink));        // the atomics have completed before the ticket

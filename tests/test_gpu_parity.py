@@ -131,6 +131,16 @@ def test_arbitrary_shape_loss_parity(ctx, b, r, w, mode):
         assert any(layer[k] == 2 for k in own), "some partly received cell should take HQL"
 
 
+def test_more_hql_blocks_than_hql_workgroups_parity(ctx):
+    """150 HQL blocks in one round: the HQL kernel's 128 workgroups take
+    more than one block each, so nothing of one block may leak into the
+    next."""
+    f = synth.make_luma(256, 320, 170, n_bumps=20, n_edges=8)
+    m = synth.loss_isolated(256, 320, 8, 150, 171)
+    st, info = check(ctx, f, m, "full", block=8, ring=2, window=12, min_hql_cands=16)
+    assert len(info) == 150 and (info["layer"] == 2).all() and (info["round"] == 1).all()
+
+
 def test_arbitrary_shape_loss_distances_bit_exact(ctx):
     f = synth.make_luma(96, 128, 90, n_bumps=8, n_edges=4)
     m = synth.loss_partial_cells(96, 128, 16, 0.4, 91, frac=0.7)

@@ -421,3 +421,76 @@ def test_oracle_runs_plain_512_workload_in_seconds():
     out, xh, inf = conceal(f, m, Params(mode="plain"))
     assert len(inf) == 64 and all(i["layer"] == LAYER_IDL for i in inf)
     assert all(i["n_cand"] > 0 for i in inf)
+
+
+# -------------------------------------------- the paper's 2 x 2 patch mode
+
+PATCH = dict(block=2, ring=2)
+
+
+def test_patch_mode_fills_a_lost_block_from_its_border_to_its_centre():
+    """2 x 2 patches with a 6 x 6 context (Sec. "Reconstruction framework"):
+    a patch is concealed once its ring holds ring*block known pixels, so the
+    round of patch (i, j) of a lost 16 x 16 block is its layer,
+    1 + min(i, j, 7 - i, 7 - j) -- the border-to-centre filling order of the
+    paper's filling-order figure."""
+    f = tiny_frame(61, 48, 48)
+    m = cells_mask(48, 48, 16, [(1, 1)])
+    p = Params(window=12, mode="plain", **PATCH)
+    out, xh, info = conceal(f, m, p)
+    assert len(info) == 64
+    for i in info:
+        pi, pj = i["by"] - 8, i["bx"] - 8
+        assert i["round"] == 1 + min(pi, pj, 7 - pi, 7 - pj)
+        assert i["n_ctx"] >= 4
+    assert np.array_equal(out[m == 0], f[m == 0])
+
+
+@pytest.mark.parametrize("seed,mode,tnu,win", [
+    (71, "plain", 0.1, 8),
+    (72, "profile", 0.1, 8),
+    (73, "profile", 100.0, 10),        # profile reaching HQL
+    (74, "full", 0.1, 10),
+])
+def test_patch_mode_vectorised_oracle_equals_loop_oracle(seed, mode, tnu, win):
+    f = tiny_frame(seed)
+    m = cells_mask(32, 32, 8, [(1, 1), (2, 3)])
+    p = Params(window=win, min_hql_cands=8, t_nu=tnu, mode=mode, **PATCH)
+    out, xh, info = conceal(f, m, p)
+    bu, bxh, blay = brute.conceal(f.tolist(), m.tolist(), 2, 2, win, t_nu=tnu, min_hql=8,
+                                  mode=mode)
+    assert np.array_equal(out, np.array(bu, dtype=np.uint8))
+    assert len(info) == 32
+    for i in info:
+        k = (i["by"], i["bx"])
+        assert i["layer"] == blay[k]
+        # HQL: eps_y is flat to rounding (1e-14 relative) within ~1e-7 of
+        # log beta at the minimum, so a search by function values fixes beta
+        # only that far, and x-hat moves by up to ~15 per unit of log beta
+        # with 32 context pixels: two summation orders agree to ~1e-5
+        tol = 1e-5 if i["layer"] == LAYER_HQL else 1e-9
+        np.testing.assert_allclose(xh[k].ravel(), np.array(bxh[k]), rtol=0, atol=tol)
+    if mode == "full":
+        assert any(i["layer"] == LAYER_HQL for i in info)
+
+
+def test_hql_flat_eps_minimum_takes_its_smallest_beta():
+    """As beta -> 0 the weights of eq. weights become one-hot on the nearest
+    candidate and eps_y (eq. epsy) saturates at ||y0 - y_nearest||^2, so its
+    argmin is not unique; the smallest grid beta on the flat part is taken
+    (the refinement inside the flat part does not count as better)."""
+    f = synth.make_luma(80, 112, 112, n_bumps=10, n_edges=5)
+    m = synth.loss_dispersed(80, 112, 16, ox=1, oy=1)
+    p = Params(window=12, **PATCH)
+    u, av = f.astype(np.int64), m == 0
+    y0, m0 = block_context(u, av, 12, 24, p)
+    c = candidate_set(u, av, 12, 24, p, y0, m0)
+    comp = c.n == m0.sum()
+    ys = c.y[comp][:, m0].astype(float)
+    _, parts = hql_estimate(c.x[comp].astype(float), ys, y0[m0].astype(float), c.d[comp],
+                            p.ridge_rel, return_parts=True)
+    eg = parts["eps_grid"]
+    near = float(((ys[np.argmin(parts["dmah0"])] - y0[m0]) ** 2).sum())
+    assert eg[0] == pytest.approx(near, rel=1e-12)          # saturated at the nearest context
+    assert abs(eg[1] - eg[0]) < 1e-9 * eg[0] and min(eg) >= eg[0] * (1 - 1e-12)
+    assert parts["beta"] == parts["grid"][0]
