@@ -268,8 +268,11 @@ skm_status skm_conceal_batch(skm_ctx* ctx, skm_frame_desc* frames, int32_t n, vo
 enum {
   SKM_OPT_GRAPHS = 1,         /* 1 (default): replay captured hipGraphs; 0: eager */
   SKM_OPT_BATCH_STREAMS = 2,  /* frames in flight in skm_conceal_batch, 1..8 (4)  */
-  SKM_OPT_GATE_GRID = 3       /* workgroups of the CNN gate kernel, multiple of 8
+  SKM_OPT_GATE_GRID = 3,      /* workgroups of the CNN gate kernel, multiple of 8
                                  in 8..4096 (768)                                 */
+  SKM_OPT_HQL_GRID = 4        /* most workgroups of the HQL kernel, 1..1024; 0
+                                 (default): as many as 1 GiB of scratch per frame
+                                 slot holds, 128..1024 by geometry                */
 };
 skm_status skm_set_option(skm_ctx* ctx, int32_t option, int64_t value);
 skm_status skm_get_option(skm_ctx* ctx, int32_t option, int64_t* value);

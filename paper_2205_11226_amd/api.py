@@ -22,7 +22,7 @@ EXPORTS = ("skm_default_params", "skm_patch_params", "skm_create", "skm_destroy"
            "skm_cnn_inputs", "skm_cnn_forward", "skm_cnn_gradients", "skm_cnn_train_step",
            "skm_cnn_last_predictions", "skm_conceal_batch", "skm_set_option", "skm_get_option",
            "skm_autotune", "skm_profile_enable", "skm_profile_read", "skm_last_error")
-OPT_GRAPHS, OPT_BATCH_STREAMS, OPT_GATE_GRID = 1, 2, 3
+OPT_GRAPHS, OPT_BATCH_STREAMS, OPT_GATE_GRID, OPT_HQL_GRID = 1, 2, 3, 4
 CNN_PARAMS = 20898
 
 

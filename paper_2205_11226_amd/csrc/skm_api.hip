@@ -81,6 +81,7 @@ struct skm_ctx {
   bool use_graphs = true;
   int batch_streams = 4;
   int gate_grid = 768;
+  int hql_grid = 0;               // 0: hql_slots(p)
   // kernel timing (skm_profile_*)
   bool prof = false;
   double prof_ms = 0.0;
@@ -263,7 +264,7 @@ skm_status ensure_frame(skm_ctx* c, FrameSlot* f, const DevParams& p) {
     c->gate_lds_set = true;
   }
   if (mode_uses_hql(p.mode)) {
-    const size_t need = hql_slot_bytes(p) * kHqlSlots;
+    const size_t need = hql_slot_bytes(p) * (size_t)hql_slots(p);
     if ((s = grow(&f->d_hql_ws, &f->cap_hql, need, "HQL scratch")) != SKM_OK) return s;
     const size_t hl = hql_lds_bytes(p);
     if ((int)hl > c->max_lds)
@@ -342,7 +343,10 @@ skm_status launch_round(skm_ctx* c, FrameSlot* f, const DevParams& p, FrameArgs&
   SKM_HIP(launch_est(a, p, nb, s), "estimation kernel");
   if (c->prof) SKM_HIP(hipEventRecord(f->ev[2 * k + 1], s), "hipEventRecord");
   if (mode_uses_hql(p.mode))
-    SKM_HIP(launch_hql(a, p, f->d_hql_ws, hql_slot_bytes(p), kHqlSlots, s), "HQL kernel");
+    SKM_HIP(launch_hql(a, p, f->d_hql_ws, hql_slot_bytes(p),
+                       c->hql_grid > 0 && c->hql_grid < hql_slots(p) ? c->hql_grid : hql_slots(p),
+                       s),
+            "HQL kernel");
   SKM_HIP(launch_finalize(a, p, nb, s), "finalize kernel");
   return SKM_OK;
 }
@@ -370,12 +374,12 @@ skm_status enqueue_frame(skm_ctx* c, FrameSlot* f, const DevParams& p, FrameArgs
   // back per frame, which this runtime does not allow for events recorded
   // by graph nodes
   if (!c->use_graphs || c->prof) return enqueue_eager(c, f, p, a, R, s);
-  std::vector<unsigned char> key(sizeof(FrameArgs) + sizeof(DevParams) + 4 * sizeof(int) +
+  std::vector<unsigned char> key(sizeof(FrameArgs) + sizeof(DevParams) + 5 * sizeof(int) +
                                  2 * sizeof(float) + sizeof(void*));
   unsigned char* kp = key.data();
   memcpy(kp, &a, sizeof(FrameArgs)); kp += sizeof(FrameArgs);
   memcpy(kp, &p, sizeof(DevParams)); kp += sizeof(DevParams);
-  const int ints[4] = {R, c->prof ? 1 : 0, c->gate_grid, (int)f->ev.size()};
+  const int ints[5] = {R, c->prof ? 1 : 0, c->gate_grid, (int)f->ev.size(), c->hql_grid};
   memcpy(kp, ints, sizeof(ints)); kp += sizeof(ints);
   memcpy(kp, &c->tau1, sizeof(float)); kp += sizeof(float);
   memcpy(kp, &c->tau2, sizeof(float)); kp += sizeof(float);
@@ -551,6 +555,11 @@ skm_status skm_set_option(skm_ctx* c, int32_t option, int64_t value) {
         return fail(SKM_EINVAL, "SKM_OPT_GATE_GRID takes a multiple of 8 in 8..4096");
       c->gate_grid = (int)value;
       return SKM_OK;
+    case SKM_OPT_HQL_GRID:
+      if (value < 0 || value > kHqlSlotsMax)
+        return fail(SKM_EINVAL, "SKM_OPT_HQL_GRID takes 0..1024");
+      c->hql_grid = (int)value;
+      return SKM_OK;
     default:
       return fail(SKM_EINVAL, "unknown option");
   }
@@ -562,6 +571,7 @@ skm_status skm_get_option(skm_ctx* c, int32_t option, int64_t* value) {
     case SKM_OPT_GRAPHS: *value = c->use_graphs ? 1 : 0; return SKM_OK;
     case SKM_OPT_BATCH_STREAMS: *value = c->batch_streams; return SKM_OK;
     case SKM_OPT_GATE_GRID: *value = c->gate_grid; return SKM_OK;
+    case SKM_OPT_HQL_GRID: *value = c->hql_grid; return SKM_OK;
     default: return fail(SKM_EINVAL, "unknown option");
   }
 }

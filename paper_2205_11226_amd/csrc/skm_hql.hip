@@ -63,6 +63,11 @@ __host__ __device__ inline HqlLayout hql_layout(const DevParams& p) {
 
 size_t hql_slot_bytes(const DevParams& p) { return hql_layout(p).total; }
 
+int hql_slots(const DevParams& p) {
+  const size_t n = kHqlScratchBudget / hql_slot_bytes(p);
+  return n < (size_t)kHqlSlots ? kHqlSlots : (n > (size_t)kHqlSlotsMax ? kHqlSlotsMax : (int)n);
+}
+
 // the estimation kernel's layout, with the window region large enough for
 // the HQL tiles that reuse it
 size_t hql_lds_bytes(const DevParams& p) {
@@ -184,22 +189,29 @@ static __device__ double eval_eps(double beta, int Mc, int Ny, int B2, int ldm, 
     s += e;
   }
   const double S = block_sum_d(s, hs.red);     // barrier: ew visible
+  // a wave per row, its lanes striding the candidates (coalesced), then a
+  // fixed-order wave sum
+  const int lane = lane_id(), wave = wave_id();
   double part = 0.0;
-  for (int a = tid; a < Ny; a += kThreads) {
+  for (int a = wave; a < Ny; a += kThreads / 64) {
     const uint8_t* row = yt + (size_t)a * ldm;
     double acc = 0.0;
-    for (int j = 0; j < Mc; ++j) acc += ew[j] * (double)row[j];
+    for (int j = lane; j < Mc; j += 64) acc += ew[j] * (double)row[j];
+    acc = wave_sum(acc);
     const double yt_a = acc / S;
-    ytil[a] = yt_a;
-    const double r = y0[a] - yt_a;
-    part += r * r;
+    if (lane == 0) {
+      ytil[a] = yt_a;
+      const double r = y0[a] - yt_a;
+      part += r * r;
+    }
   }
   if (xt) {
-    for (int q = tid; q < B2; q += kThreads) {
+    for (int q = wave; q < B2; q += kThreads / 64) {
       const uint8_t* row = xt + (size_t)q * ldm;
       double acc = 0.0;
-      for (int j = 0; j < Mc; ++j) acc += ew[j] * (double)row[j];
-      xtil[q] = acc / S;
+      for (int j = lane; j < Mc; j += 64) acc += ew[j] * (double)row[j];
+      acc = wave_sum(acc);
+      if (lane == 0) xtil[q] = acc / S;
     }
   }
   hs.S = S;
@@ -338,15 +350,18 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
     for (int aa = tid; aa < Ny; aa += kThreads)
       y0v[aa] = (double)(int)(int16_t)(L.winp[qbase + m0off[aa]] & 0xffffu);
     __syncthreads();
-    for (int aa = tid; aa < Ny; aa += kThreads) {
-      unsigned s = 0;
-      for (int k = 0; k < Mc; ++k) s += yt[(size_t)aa * ldm + k];
-      meany[aa] = (double)s / (double)Mc;
+    // column means: a wave per row, exact integer sums
+    for (int aa = wave; aa < Ny; aa += kThreads / 64) {
+      int s = 0;
+      for (int k = lane; k < Mc; k += 64) s += yt[(size_t)aa * ldm + k];
+      s = wave_sum(s);
+      if (lane == 0) meany[aa] = (double)s / (double)Mc;
     }
-    for (int q = tid; q < B2; q += kThreads) {
-      unsigned s = 0;
-      for (int k = 0; k < Mc; ++k) s += xt[(size_t)q * ldm + k];
-      meanx[q] = (double)s / (double)Mc;
+    for (int q = wave; q < B2; q += kThreads / 64) {
+      int s = 0;
+      for (int k = lane; k < Mc; k += 64) s += xt[(size_t)q * ldm + k];
+      s = wave_sum(s);
+      if (lane == 0) meanx[q] = (double)s / (double)Mc;
     }
     __syncthreads();
 

@@ -144,8 +144,14 @@ hipError_t cnn_adam(float* prm, const float* grad, float* m, float* v, float* wq
                     hipStream_t s);
 
 // HQL (skm_hql.hip)
-constexpr int kHqlSlots = 128;     // workgroups of the HQL kernel, one scratch slot each
+// workgroups of the HQL kernel, one scratch slot each: as many as a 1 GiB
+// scratch holds, within [kHqlSlots, kHqlSlotsMax] (128 for 16 x 16 blocks,
+// whose slots take ~13 MB; ~1000 for 2 x 2 patches)
+constexpr int kHqlSlots = 128;
+constexpr int kHqlSlotsMax = 1024;
+constexpr size_t kHqlScratchBudget = size_t(1) << 30;
 size_t hql_slot_bytes(const DevParams& p);
+int hql_slots(const DevParams& p);
 size_t hql_lds_bytes(const DevParams& p);
 hipError_t launch_hql(const FrameArgs& a, const DevParams& p, unsigned char* ws, size_t slot_bytes,
                       int slots, hipStream_t s);

@@ -131,13 +131,23 @@ def test_arbitrary_shape_loss_parity(ctx, b, r, w, mode):
         assert any(layer[k] == 2 for k in own), "some partly received cell should take HQL"
 
 
-def test_more_hql_blocks_than_hql_workgroups_parity(ctx):
-    """150 HQL blocks in one round: the HQL kernel's 128 workgroups take
-    more than one block each, so nothing of one block may leak into the
-    next."""
+@pytest.mark.parametrize("grid", [64, 0])
+def test_more_hql_blocks_than_hql_workgroups_parity(ctx, grid):
+    """150 HQL blocks in one round on 64 HQL workgroups: each takes two or
+    three blocks, so nothing of one block may leak into the next (grid 0:
+    the automatic count, one block each)."""
+    import paper_2205_11226_amd as skm
     f = synth.make_luma(256, 320, 170, n_bumps=20, n_edges=8)
     m = synth.loss_isolated(256, 320, 8, 150, 171)
-    st, info = check(ctx, f, m, "full", block=8, ring=2, window=12, min_hql_cands=16)
+    for bad in (-1, 1025):
+        with pytest.raises(skm.SkmError):
+            ctx.set_option(skm.OPT_HQL_GRID, bad)
+    ctx.set_option(skm.OPT_HQL_GRID, grid)
+    try:
+        assert ctx.get_option(skm.OPT_HQL_GRID) == grid
+        st, info = check(ctx, f, m, "full", block=8, ring=2, window=12, min_hql_cands=16)
+    finally:
+        ctx.set_option(skm.OPT_HQL_GRID, 0)
     assert len(info) == 150 and (info["layer"] == 2).all() and (info["round"] == 1).all()
 
 
