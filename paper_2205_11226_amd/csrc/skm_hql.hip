@@ -24,7 +24,7 @@
 namespace skm {
 
 struct HqlLayout {
-  size_t yt, xt, cyy, axy, v, v0, y0, meany, meanx, dm0, ew, ytil, xtil, vn, dch, zch, i0;
+  size_t yt, xt, cyy, axy, v, v0, y0, meany, meanx, dm0, ytil, xtil, vn, dch, zch, i0;
   size_t total;
   int ldm;     // leading dimension (candidates) of yt / xt, multiple of 64
   int ldz;     // row length of zch: B^2 + NY
@@ -50,7 +50,6 @@ __host__ __device__ inline HqlLayout hql_layout(const DevParams& p) {
   h.meany = take(8 * NY);
   h.meanx = take(8 * B2);
   h.dm0 = take(8 * MC);
-  h.ew = take(8 * MC);
   h.ytil = take(8 * NY);
   h.xtil = take(8 * B2);
   h.vn = take(8 * MC);
@@ -74,7 +73,7 @@ size_t hql_lds_bytes(const DevParams& p) {
   size_t offs[10];
   main_lds_layout(p, offs);
   size_t need = (size_t)4 * p.Wd * p.Wd;
-  need = need > 16384 ? need : 16384;                      // FP64 GEMM tiles
+  need = need > 32768 ? need : 32768;                      // FP64 GEMM tiles
   need = need > (size_t)2 * 64 * 17 * 4 ? need : (size_t)2 * 64 * 17 * 4;   // Gram tiles
   const size_t ny = (size_t)p.NR + (size_t)p.B * p.B;
   need = need > 8 * ny ? need : 8 * ny;                     // Cholesky pivot row
@@ -247,7 +246,9 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
   double* meany = (double*)(slot + hl.meany);
   double* meanx = (double*)(slot + hl.meanx);
   double* dm0 = (double*)(slot + hl.dm0);
-  double* ew = (double*)(slot + hl.ew);
+  // the candidates' weights of the eps_y evaluations live in LDS (the log
+  // weight array is free once the complete candidates are listed)
+  double* ew = L.ell;
   double* ytil = (double*)(slot + hl.ytil);
   double* xtil = (double*)(slot + hl.xtil);
   double* vn = (double*)(slot + hl.vn);
@@ -262,6 +263,8 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
   double* piv = (double*)L.winp;                     // Cholesky pivot row
   double* ga = (double*)L.winp;                      // FP64 GEMM tiles, 2 x 16 x 64
   double* gb = ga + 16 * 64;
+  double* ca = ga;                                   // leave-one-out sums: 2 x 32 x 64
+  double* cb = ga + 32 * 64;
   uint16_t* m0off = (uint16_t*)L.qu;                 // known ring pixels (footprint offsets)
   uint16_t* compo = L.selo;                          // complete candidates: window offset
   int* compd = (int*)L.selw;                         //   and exact Euclidean distance
@@ -589,25 +592,25 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
         for (int x = 0; x < 4; ++x)
 #pragma unroll
           for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-        for (int k0_ = 0; k0_ < Mc; k0_ += 16) {
-          for (int e = tid; e < 16 * 64; e += kThreads) {
+        for (int k0_ = 0; k0_ < Mc; k0_ += 32) {
+          for (int e = tid; e < 32 * 64; e += kThreads) {
             const int kk = e >> 6, c = e & 63;
             const int kg = k0_ + kk;
-            ga[kk * 64 + c] = (c < nc && kg < Mc) ? dch[(size_t)c * Mc + kg] : 0.0;
+            ca[kk * 64 + c] = (c < nc && kg < Mc) ? dch[(size_t)c * Mc + kg] : 0.0;
             const int dd = d0 + c;
             double zv = 0.0;
             if (dd < nd && kg < Mc)
               zv = dd < B2 ? (double)xt[(size_t)dd * ldm + kg] : (double)yt[(size_t)(dd - B2) * ldm + kg];
-            gb[kk * 64 + c] = zv;
+            cb[kk * 64 + c] = zv;
           }
           __syncthreads();
 #pragma unroll 4
-          for (int kk = 0; kk < 16; ++kk) {
+          for (int kk = 0; kk < 32; ++kk) {
             double av[4], bv[4];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) av[x] = ga[kk * 64 + ty * 4 + x];
+            for (int x = 0; x < 4; ++x) av[x] = ca[kk * 64 + ty * 4 + x];
 #pragma unroll
-            for (int y = 0; y < 4; ++y) bv[y] = gb[kk * 64 + tx * 4 + y];
+            for (int y = 0; y < 4; ++y) bv[y] = cb[kk * 64 + tx * 4 + y];
 #pragma unroll
             for (int x = 0; x < 4; ++x)
 #pragma unroll

@@ -257,3 +257,34 @@ def test_autotune_keeps_results(ctx):
     ctx.set_option(skm.OPT_BATCH_STREAMS, 4)
     ctx.set_option(skm.OPT_GRAPHS, 1)
     ctx.set_option(skm.OPT_GATE_GRID, 768)
+
+
+def test_batch_patch_geometry_matches_single_frames(ctx):
+    """The paper's 2x2 patches (several rounds per frame) next to a block
+    frame in one batch; graphs off, then on twice (the second call replays
+    the captured graphs): bit-identical to single-frame runs."""
+    import paper_2205_11226_amd as skm
+    frames, prms = [], []
+    for k, (h, w, mode, win) in enumerate([(80, 112, "profile", 24), (64, 96, "full", 12),
+                                           (96, 128, "plain", 24)]):
+        f = synth.make_luma(h, w, 400 + k, n_bumps=10, n_edges=5)
+        m = synth.loss_random(h, w, 16, 0.3, 410 + k)
+        frames.append((f, m))
+        prms.append(skm.patch_params(mode=mode, window=win, min_hql_cands=16))
+    f = synth.make_luma(144, 176, 420, n_bumps=10, n_edges=5)
+    frames.append((f, synth.loss_random(144, 176, 16, 0.3, 421)))
+    prms.append(device_params("profile"))
+    refs = [run_single(ctx, f, m, prm) for (f, m), prm in zip(frames, prms)]
+    assert max(int(r[1]["round"].max()) for r in refs[:3]) >= 4
+    for graphs in (0, 1, 1):
+        ctx.set_option(skm.OPT_GRAPHS, graphs)
+        jobs, outs = _batch_jobs(frames, prms)
+        res = ctx.conceal_batch(jobs)
+        for k, ((out, info, xh), ref) in enumerate(zip(outs, refs)):
+            n, rounds, st = res[k]
+            assert st == 0 and n == len(ref[1]), (graphs, k)
+            assert np.array_equal(out.cpu().numpy(), ref[0]), (graphs, k)
+            gi = info.cpu().numpy().view(skm.BLOCK_INFO_DTYPE)[:n]
+            assert gi.tobytes() == ref[1].tobytes(), (graphs, k)
+            assert np.array_equal(xh[:n].cpu().numpy(), ref[2]), (graphs, k)
+    ctx.set_option(skm.OPT_GRAPHS, 1)
