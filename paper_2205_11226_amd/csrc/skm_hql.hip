@@ -73,7 +73,7 @@ size_t hql_lds_bytes(const DevParams& p) {
   size_t offs[10];
   main_lds_layout(p, offs);
   size_t need = (size_t)4 * p.Wd * p.Wd;
-  need = need > 32768 ? need : 32768;                      // FP64 GEMM tiles
+  need = need > 2 * 32 * 65 * 8 ? need : 2 * 32 * 65 * 8;   // FP64 GEMM tiles
   need = need > (size_t)2 * 64 * 17 * 4 ? need : (size_t)2 * 64 * 17 * 4;   // Gram tiles
   const size_t ny = (size_t)p.NR + (size_t)p.B * p.B;
   need = need > 8 * ny ? need : 8 * ny;                     // Cholesky pivot row
@@ -188,29 +188,54 @@ static __device__ double eval_eps(double beta, int Mc, int Ny, int B2, int ldm, 
     s += e;
   }
   const double S = block_sum_d(s, hs.red);     // barrier: ew visible
-  // a wave per row, its lanes striding the candidates (coalesced), then a
-  // fixed-order wave sum
+  // eight rows per wave at a time; a lane takes four consecutive candidates
+  // per step (one 32-bit load per row: the byte rows are zero-padded to ldm,
+  // a multiple of 64), then fixed-order wave sums
   const int lane = lane_id(), wave = wave_id();
   double part = 0.0;
-  for (int a = wave; a < Ny; a += kThreads / 64) {
-    const uint8_t* row = yt + (size_t)a * ldm;
-    double acc = 0.0;
-    for (int j = lane; j < Mc; j += 64) acc += ew[j] * (double)row[j];
-    acc = wave_sum(acc);
-    const double yt_a = acc / S;
+  auto rows8 = [&](const uint8_t* base, int a0, int nrow, double* acc) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) acc[r] = 0.0;
+    for (int j = 4 * lane; j < Mc; j += 256) {
+      double e[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) e[q] = j + q < Mc ? ew[j + q] : 0.0;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        if (a0 + r < nrow) {
+          const uint32_t w = *reinterpret_cast<const uint32_t*>(base + (size_t)(a0 + r) * ldm + j);
+          acc[r] += e[0] * (double)(w & 0xffu) + e[1] * (double)((w >> 8) & 0xffu) +
+                    e[2] * (double)((w >> 16) & 0xffu) + e[3] * (double)(w >> 24);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) acc[r] = wave_sum(acc[r]);
+  };
+  for (int a0 = 8 * wave; a0 < Ny; a0 += 8 * (kThreads / 64)) {
+    double acc[8];
+    rows8(yt, a0, Ny, acc);
     if (lane == 0) {
-      ytil[a] = yt_a;
-      const double r = y0[a] - yt_a;
-      part += r * r;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        if (a0 + r < Ny) {
+          const double yt_a = acc[r] / S;
+          ytil[a0 + r] = yt_a;
+          const double d = y0[a0 + r] - yt_a;
+          part += d * d;
+        }
+      }
     }
   }
   if (xt) {
-    for (int q = wave; q < B2; q += kThreads / 64) {
-      const uint8_t* row = xt + (size_t)q * ldm;
-      double acc = 0.0;
-      for (int j = lane; j < Mc; j += 64) acc += ew[j] * (double)row[j];
-      acc = wave_sum(acc);
-      if (lane == 0) xtil[q] = acc / S;
+    for (int q0 = 8 * wave; q0 < B2; q0 += 8 * (kThreads / 64)) {
+      double acc[8];
+      rows8(xt, q0, B2, acc);
+      if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+          if (q0 + r < B2) xtil[q0 + r] = acc[r] / S;
+      }
     }
   }
   hs.S = S;
@@ -263,8 +288,8 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
   double* piv = (double*)L.winp;                     // Cholesky pivot row
   double* ga = (double*)L.winp;                      // FP64 GEMM tiles, 2 x 16 x 64
   double* gb = ga + 16 * 64;
-  double* ca = ga;                                   // leave-one-out sums: 2 x 32 x 64
-  double* cb = ga + 32 * 64;
+  double* ca = ga;                                   // leave-one-out sums: 2 x 32 x 64,
+  double* cb = ga + 32 * 65;                         //   row pitch 65
   uint16_t* m0off = (uint16_t*)L.qu;                 // known ring pixels (footprint offsets)
   uint16_t* compo = L.selo;                          // complete candidates: window offset
   int* compd = (int*)L.selw;                         //   and exact Euclidean distance
@@ -561,27 +586,21 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
         }
       }
       __syncthreads();
-      // (b) row softmax (the member itself excluded): 4 threads per row
-      {
-        const int c = tid >> 2, part = tid & 3;
+      // (b) row softmax (the member itself excluded): a wave per row, its
+      //     lanes striding the candidates (coalesced), fixed-order wave sums
+      for (int c = wave; c < nc; c += kThreads / 64) {
+        double* row = dch + (size_t)c * Mc;
         double m = -INFINITY;
-        if (c < nc)
-          for (int j = part; j < Mc; j += 4) m = fmax(m, dch[(size_t)c * Mc + j]);
-        m = fmax(m, __shfl_xor(m, 1, 64));
-        m = fmax(m, __shfl_xor(m, 2, 64));
+        for (int j = lane; j < Mc; j += 64) m = fmax(m, row[j]);
+        m = wave_max_d(m);
         double s = 0.0;
-        if (c < nc) {
-          for (int j = part; j < Mc; j += 4) {
-            const double e = exp(dch[(size_t)c * Mc + j] - m);
-            dch[(size_t)c * Mc + j] = e;
-            s += e;
-          }
+        for (int j = lane; j < Mc; j += 64) {
+          const double e = exp(row[j] - m);
+          row[j] = e;
+          s += e;
         }
-        const double s1 = __shfl_xor(s, 1, 64);
-        s = (part & 1) ? s1 + s : s + s1;
-        const double s2 = __shfl_xor(s, 2, 64);
-        s = (part & 2) ? s2 + s : s + s2;
-        if (c < nc && part == 0) hs.rowS[c] = s;
+        s = wave_sum(s);
+        if (lane == 0) hs.rowS[c] = s;
       }
       __syncthreads();
       // (c) z~_c = sum_j e_cj z_j over the dims of x (B2) and y (Ny)
@@ -593,24 +612,25 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
 #pragma unroll
           for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
         for (int k0_ = 0; k0_ < Mc; k0_ += 32) {
+          // consecutive lanes take consecutive candidates (coalesced reads)
           for (int e = tid; e < 32 * 64; e += kThreads) {
-            const int kk = e >> 6, c = e & 63;
+            const int kk = e & 31, c = e >> 5;
             const int kg = k0_ + kk;
-            ca[kk * 64 + c] = (c < nc && kg < Mc) ? dch[(size_t)c * Mc + kg] : 0.0;
+            ca[kk * 65 + c] = (c < nc && kg < Mc) ? dch[(size_t)c * Mc + kg] : 0.0;
             const int dd = d0 + c;
             double zv = 0.0;
             if (dd < nd && kg < Mc)
               zv = dd < B2 ? (double)xt[(size_t)dd * ldm + kg] : (double)yt[(size_t)(dd - B2) * ldm + kg];
-            cb[kk * 64 + c] = zv;
+            cb[kk * 65 + c] = zv;
           }
           __syncthreads();
 #pragma unroll 4
           for (int kk = 0; kk < 32; ++kk) {
             double av[4], bv[4];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) av[x] = ca[kk * 64 + ty * 4 + x];
+            for (int x = 0; x < 4; ++x) av[x] = ca[kk * 65 + ty * 4 + x];
 #pragma unroll
-            for (int y = 0; y < 4; ++y) bv[y] = cb[kk * 64 + tx * 4 + y];
+            for (int y = 0; y < 4; ++y) bv[y] = cb[kk * 65 + tx * 4 + y];
 #pragma unroll
             for (int x = 0; x < 4; ++x)
 #pragma unroll
