@@ -494,3 +494,23 @@ def test_hql_flat_eps_minimum_takes_its_smallest_beta():
     assert eg[0] == pytest.approx(near, rel=1e-12)          # saturated at the nearest context
     assert abs(eg[1] - eg[0]) < 1e-9 * eg[0] and min(eg) >= eg[0] * (1 - 1e-12)
     assert parts["beta"] == parts["grid"][0]
+
+
+@pytest.mark.parametrize("seed,mode,tnu", [(81, "profile", 0.1), (82, "full", 0.1)])
+def test_patch_mode_partial_cells_vectorised_oracle_equals_loop_oracle(seed, mode, tnu):
+    """2 x 2 cells that keep some received pixels: those join the context,
+    are never overwritten, and both oracles agree."""
+    f = tiny_frame(seed)
+    m = synth.loss_partial_cells(32, 32, 2, 0.3, seed + 100, frac=0.6)
+    p = Params(window=8, min_hql_cands=8, t_nu=tnu, mode=mode, **PATCH)
+    out, xh, info = conceal(f, m, p)
+    bu, bxh, blay = brute.conceal(f.tolist(), m.tolist(), 2, 2, 8, t_nu=tnu, min_hql=8,
+                                  mode=mode)
+    assert len(info) == len(lost_cells(m, 2)) > 0
+    assert np.array_equal(out, np.array(bu, dtype=np.uint8))
+    assert np.array_equal(out[m == 0], f[m == 0])
+    for i in info:
+        k = (i["by"], i["bx"])
+        assert i["layer"] == blay[k]
+        tol = 1e-5 if i["layer"] == LAYER_HQL else 1e-9
+        np.testing.assert_allclose(xh[k].ravel(), np.array(bxh[k]), rtol=0, atol=tol)
