@@ -179,11 +179,11 @@ static __device__ double eval_eps(double beta, int Mc, int Ny, int B2, int ldm, 
                                   double dmin, double* ew, const uint8_t* yt, const uint8_t* xt,
                                   const double* y0, double* ytil, double* xtil, HqlShared& hs) {
   const int tid = threadIdx.x;
-  const double two_b = 2.0 * beta;
-  const double m = -dmin / two_b;
+  const double inv2b = 1.0 / (2.0 * beta);      // one division per evaluation
+  const double m = -dmin * inv2b;
   double s = 0.0;
   for (int j = tid; j < Mc; j += kThreads) {
-    const double e = exp(-dm0[j] / two_b - m);
+    const double e = exp(-dm0[j] * inv2b - m);
     ew[j] = e;
     s += e;
   }
@@ -541,6 +541,7 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
     // -- leave-one-out predictions of the I0 members, 64 at a time
     double num = 0.0, den = 0.0;
     const int ty = tid >> 4, tx = tid & 15;
+    const double inv2b = 1.0 / (2.0 * beta);
     for (int c0 = 0; c0 < k0; c0 += 64) {
       const int nc = min(64, k0 - c0);
       // (a) logits -D(y_i, y_j) / (2 beta), D from whitened dot products
@@ -580,7 +581,7 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
             if (c < nc && j < Mc) {
               const int ii = i0l[c0 + c];
               const double D = vn[ii] + vn[j] - 2.0 * acc[x][y];
-              dch[(size_t)c * Mc + j] = (j == ii) ? -INFINITY : -D / (2.0 * beta);
+              dch[(size_t)c * Mc + j] = (j == ii) ? -INFINITY : -D * inv2b;
             }
           }
         }
