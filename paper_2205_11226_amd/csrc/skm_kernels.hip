@@ -160,21 +160,41 @@ __global__ __launch_bounds__(kThreads) void k_init(FrameArgs a, DevParams p) {
   const int ncell = p.gh * p.gw, nw = (ncell + 31) >> 5;
   const int per = (nw + kThreads - 1) / kThreads;
   const int w0 = min(nw, tid * per), w1 = min(nw, w0 + per);
+  // eight independent loads in flight per step (a large table, e.g. 2 x 2
+  // cells, gives each thread tens of words)
   int n = 0;
-  for (int w = w0; w < w1; ++w)
-    n += __popc(__hip_atomic_load(&a.cellbits[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  for (int w = w0; w < w1; w += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      v[q] = w + q < w1 ? __hip_atomic_load(&a.cellbits[w + q], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT)
+                        : 0u;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) n += __popc(v[q]);
+  }
   int tot = 0;
   int pos = block_excl_scan(n, s_scan, &tot);
-  for (int w = w0; w < w1; ++w) {
-    uint32_t bits = __hip_atomic_load(&a.cellbits[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while (bits) {
-      const int b = __ffs(bits) - 1;
-      bits &= bits - 1u;
-      a.blk[pos] = w * 32 + b;
-      a.bstate[pos] = 0;
-      ++pos;
+  for (int w = w0; w < w1; w += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      v[q] = w + q < w1 ? __hip_atomic_load(&a.cellbits[w + q], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT)
+                        : 0u;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      uint32_t bits = v[q];
+      while (bits) {
+        const int b = __ffs(bits) - 1;
+        bits &= bits - 1u;
+        a.blk[pos] = (w + q) * 32 + b;
+        a.bstate[pos] = 0;
+        ++pos;
+      }
+      if (w + q < w1)
+        __hip_atomic_store(&a.cellbits[w + q], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __hip_atomic_store(&a.cellbits[w], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (tid == 0) {
     st->n_lost = tot; st->remaining = tot; st->round = 1;
