@@ -231,10 +231,10 @@ def main():
         return (time.perf_counter() - t0) / k
 
     # launch configuration picked by the library's autotuner on a short batch
-    tune_ms = ctx.autotune(jobs_for(p_lay, 8), reps=2)
+    tune_ms = ctx.autotune(jobs_for(p_lay, 16), reps=3)
     tuned = {"batch_streams": ctx.get_option(skm.OPT_BATCH_STREAMS),
              "graphs": ctx.get_option(skm.OPT_GRAPHS),
-             "gate_grid": ctx.get_option(skm.OPT_GATE_GRID), "tune_batch8_ms": tune_ms}
+             "gate_grid": ctx.get_option(skm.OPT_GATE_GRID), "tune_batch16_ms": tune_ms}
     print(f"# autotune: {tuned}", file=sys.stderr, flush=True)
 
     sec_lay = timed_batch(p_lay)

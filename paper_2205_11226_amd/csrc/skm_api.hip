@@ -721,7 +721,7 @@ skm_status skm_conceal_batch(skm_ctx* c, skm_frame_desc* frames, int32_t n, void
 }
 
 // Times the batch under each launch configuration (streams 1, 2, 4, 8 with
-// graphs on and off; gate grids 256, 512, 1024 in CNN mode), repeats`reps`
+// graphs on and off; gate grids 512, 768, 1536 in CNN mode), repeats `reps`
 // times, keeps the fastest and reports its time.  The frames are concealed
 // (several times) as a side effect.
 skm_status skm_autotune(skm_ctx* c, skm_frame_desc* frames, int32_t n, int32_t reps,

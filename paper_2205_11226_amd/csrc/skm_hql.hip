@@ -73,7 +73,8 @@ size_t hql_lds_bytes(const DevParams& p) {
   size_t offs[10];
   main_lds_layout(p, offs);
   size_t need = (size_t)4 * p.Wd * p.Wd;
-  need = need > 2 * 32 * 65 * 8 ? need : 2 * 32 * 65 * 8;   // FP64 GEMM tiles
+  need = need > 16384 ? need : 16384;                      // FP64 GEMM tiles
+  need = need > 2 * 16 * 65 * 8 ? need : 2 * 16 * 65 * 8;   // (pitch 65 for the sums)
   need = need > (size_t)2 * 64 * 17 * 4 ? need : (size_t)2 * 64 * 17 * 4;   // Gram tiles
   const size_t ny = (size_t)p.NR + (size_t)p.B * p.B;
   need = need > 8 * ny ? need : 8 * ny;                     // Cholesky pivot row
@@ -288,8 +289,8 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
   double* piv = (double*)L.winp;                     // Cholesky pivot row
   double* ga = (double*)L.winp;                      // FP64 GEMM tiles, 2 x 16 x 64
   double* gb = ga + 16 * 64;
-  double* ca = ga;                                   // leave-one-out sums: 2 x 32 x 64,
-  double* cb = ga + 32 * 65;                         //   row pitch 65
+  double* ca = ga;                                   // leave-one-out sums: 2 x 16 x 64,
+  double* cb = ga + 16 * 65;                         //   row pitch 65
   uint16_t* m0off = (uint16_t*)L.qu;                 // known ring pixels (footprint offsets)
   uint16_t* compo = L.selo;                          // complete candidates: window offset
   int* compd = (int*)L.selw;                         //   and exact Euclidean distance
@@ -612,10 +613,10 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
         for (int x = 0; x < 4; ++x)
 #pragma unroll
           for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-        for (int k0_ = 0; k0_ < Mc; k0_ += 32) {
+        for (int k0_ = 0; k0_ < Mc; k0_ += 16) {
           // consecutive lanes take consecutive candidates (coalesced reads)
-          for (int e = tid; e < 32 * 64; e += kThreads) {
-            const int kk = e & 31, c = e >> 5;
+          for (int e = tid; e < 16 * 64; e += kThreads) {
+            const int kk = e & 15, c = e >> 4;
             const int kg = k0_ + kk;
             ca[kk * 65 + c] = (c < nc && kg < Mc) ? dch[(size_t)c * Mc + kg] : 0.0;
             const int dd = d0 + c;
@@ -626,7 +627,7 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
           }
           __syncthreads();
 #pragma unroll 4
-          for (int kk = 0; kk < 32; ++kk) {
+          for (int kk = 0; kk < 16; ++kk) {
             double av[4], bv[4];
 #pragma unroll
             for (int x = 0; x < 4; ++x) av[x] = ca[kk * 65 + ty * 4 + x];
