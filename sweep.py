@@ -141,19 +141,27 @@ def layer_counts(info) -> dict:
                 hql=int(np.sum(lay == 2)), idl_full=int(np.sum(fb)))
 
 
-def sweep(n_frames: int = 4, reps: int = 3, block: int = 16, h: int = 512, w: int = 768):
+def sweep(n_frames: int = 4, reps: int = 3, block: int = 16, h: int = 512, w: int = 768,
+          geometry: str = "block"):
+    """geometry "patch": the same 16 x 16 loss, concealed as the paper's 2x2
+    patches with 6x6 contexts."""
     import torch
     import paper_2205_11226_amd as skm
+    if geometry == "patch":
+        def mk(**kw):
+            return skm.patch_params(**kw)
+    else:
+        def mk(**kw):
+            return skm.default_params(block=block, **kw)
     ctx = skm.Context(0)
     rows = []
     for pattern, f, frame, mask in workloads(n_frames, h, w, block):
         fd = torch.from_numpy(frame).cuda()
         md = torch.from_numpy(mask).cuda()
-        t_full, o_full, l_full = run_one(ctx, fd, md, skm.default_params(mode="full", block=block),
-                                         reps)
+        t_full, o_full, l_full = run_one(ctx, fd, md, mk(mode="full"), reps)
         ref = dict(psnr=psnr(frame, o_full), ssim=ssim(frame, o_full), ms=t_full)
         for study, label, tphi, tnu in settings():
-            prm = skm.default_params(mode="profile", block=block, t_phi=tphi, t_nu=tnu)
+            prm = mk(mode="profile", t_phi=tphi, t_nu=tnu)
             t, o, lay = run_one(ctx, fd, md, prm, reps)
             rows.append(dict(study=study, label=label, pattern=pattern, frame=f,
                              psnr=psnr(frame, o), ssim=ssim(frame, o), ms=t, layers=lay,
@@ -209,8 +217,9 @@ def main(argv=None):
     ap.add_argument("--frames", type=int, default=4)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--json", default=None)
+    ap.add_argument("--geometry", choices=("block", "patch"), default="block")
     a = ap.parse_args(argv)
-    rows = sweep(a.frames, a.reps)
+    rows = sweep(a.frames, a.reps, geometry=a.geometry)
     summ = summarise(rows)
     if a.json:
         with open(a.json, "w") as f:
