@@ -76,3 +76,24 @@ def test_sweep_runs_every_setting(ctx):
     assert len({s["brl"] for s in d2}) == 1
     md = sweep.markdown(summ)
     assert "flatness" in md and "profiles" in md and "excellent" in md
+
+
+def test_patch_geometry_gate_limit_and_sweep(ctx):
+    """The paper's 2x2 patches: with T_nu out of reach and T_phi below any
+    flatness the profile rule is full K-MMSE bit for bit, and the sweep runs
+    every setting in that geometry."""
+    import paper_2205_11226_amd as skm
+    f = synth.make_luma(80, 112, 93, n_bumps=10, n_edges=5, texture=True)
+    m = synth.loss_dispersed(80, 112, 16, ox=1, oy=1)
+    o_full, i_full, x_full = run(ctx, f, m, skm.patch_params(mode="full"))
+    o_lim, i_lim, x_lim = run(ctx, f, m, skm.patch_params(mode="profile", t_phi=-1.0,
+                                                          t_nu=sweep.BIG))
+    assert np.all(i_full["layer"] == 2)
+    assert np.array_equal(o_full, o_lim) and np.array_equal(x_full, x_lim)
+    assert np.array_equal(i_full["layer"], i_lim["layer"])
+    rows = sweep.sweep(n_frames=1, reps=1, h=96, w=128, geometry="patch")
+    summ = sweep.summarise(rows)
+    assert len(summ) == 2 * len(sweep.settings())
+    for s in summ:
+        assert math.isfinite(s["dpsnr"]) and s["speedup"] > 0
+        assert s["brl"] + s["idl"] + s["hql"] + s["idl_full"] == pytest.approx(1.0)
