@@ -80,7 +80,10 @@ enum {
   SKM_FLAG_CTX_RELAXED = 1, /* concealed with fewer than ring*block context px */
   SKM_FLAG_NO_HQL = 2,      /* HQL wanted, too few complete candidates: IDL   */
   SKM_FLAG_NO_CAND = 4,     /* no admissible candidate: BRL                   */
-  SKM_FLAG_EMPTY_CTX = 8    /* forced fill without context: frame mean        */
+  SKM_FLAG_EMPTY_CTX = 8,   /* forced fill without context: frame mean        */
+  SKM_FLAG_HQL_SINGULAR = 16 /* HQL: C_YY + lambda I met a Cholesky pivot <= 0
+                                in FP64 (no covariance model): context mean,
+                                layer reported as SKM_LAYER_BRL               */
 };
 
 typedef struct skm_params {
@@ -98,7 +101,12 @@ typedef struct skm_params {
   double sigma2;           /* IDL kernel decay factor (paper: 10)             */
   double t_phi;            /* flatness threshold T_phi (BRL iff phi <= T_phi) */
   double t_nu;             /* normalisation threshold T_nu (IDL iff nu >= T_nu)*/
-  double ridge_rel;        /* HQL ridge: lambda = ridge_rel tr(C_YY)/N_y + 1e-12 */
+  double ridge_rel;        /* HQL ridge: lambda = ridge_rel tr(C_YY)/N_y + 1e-12,
+                              ridge_rel >= -1.  C_YY + lambda I is positive
+                              definite for ridge_rel >= 0 (up to rounding); a
+                              negative value makes it indefinite for any
+                              non-isotropic C_YY, which sends HQL blocks to
+                              the SKM_FLAG_HQL_SINGULAR fallback (for tests) */
 } skm_params;
 
 /* Per lost block result, in the raster order (by, then bx) of the lost cells. */
@@ -278,8 +286,8 @@ skm_status skm_set_option(skm_ctx* ctx, int32_t option, int64_t value);
 skm_status skm_get_option(skm_ctx* ctx, int32_t option, int64_t* value);
 
 /* Autotuner: times skm_conceal_batch on these frames under each launch
- * configuration (1, 2, 4, 8 streams; graphs on and off; gate grids 256, 512
- * and 1024 when a frame uses SKM_MODE_CNN), keeping the best of `reps` runs
+ * configuration (1, 2, 4, 8 streams; graphs on and off; gate grids 512, 768
+ * and 1536 when a frame uses SKM_MODE_CNN), keeping the best of `reps` runs
  * each, and sets the fastest configuration on the context.  The frames are
  * concealed several times.  best_ms (optional) receives the best batch time. */
 skm_status skm_autotune(skm_ctx* ctx, skm_frame_desc* frames, int32_t n, int32_t reps,

@@ -115,6 +115,10 @@ def idl(cands, rho, sigma2, nx):
 
 # ----------------------------------------------------------- linear algebra
 
+class NotPositiveDefinite(ArithmeticError):
+    """A Cholesky pivot came out <= 0 (or NaN)."""
+
+
 def _cholesky(a):
     n = len(a)
     L = [[0.0] * n for _ in range(n)]
@@ -124,6 +128,8 @@ def _cholesky(a):
             for k in range(j):
                 s -= L[i][k] * L[j][k]
             if i == j:
+                if not s > 0.0:
+                    raise NotPositiveDefinite(i)
                 L[i][i] = math.sqrt(s)
             else:
                 L[i][j] = s / L[j][j]
@@ -293,9 +299,12 @@ def conceal(frame, mask, b, r, W, sigma2=10.0, t_phi=20.0, t_nu=0.1, step=4, pct
                 comp = [c for c in cs if c["n"] == sum(m0)]
                 if want and len(comp) >= max(2, min_hql):
                     ys = [[c["y"][k] for k in range(len(m0)) if m0[k]] for c in comp]
-                    layer = 2
-                    xh = hql([c["x"] for c in comp], ys, known, [c["d"] for c in comp],
-                             ridge_rel)
+                    try:
+                        xh = hql([c["x"] for c in comp], ys, known, [c["d"] for c in comp],
+                                 ridge_rel)
+                        layer = 2
+                    except NotPositiveDefinite:
+                        layer, xh = 0, brl     # no covariance model: context mean
                 else:
                     layer, xh = 1, idl(cs, W, sigma2, b * b)
             res.append(((by, bx), xh, layer))

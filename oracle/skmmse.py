@@ -54,6 +54,7 @@ FLAG_CTX_RELAXED = 1   # block proceeded with fewer than r*B context pixels
 FLAG_NO_HQL = 2        # HQL wanted but too few complete candidates: full IDL
 FLAG_NO_CAND = 4       # no candidate at all: BRL
 FLAG_EMPTY_CTX = 8     # forced fill with no context pixel: frame mean
+FLAG_HQL_SINGULAR = 16  # HQL's C_YY + lambda I not positive definite in float64: BRL
 
 # Profile table of the paper (Table "Profile definitions"): (T_phi, T_nu).
 PROFILES = {
@@ -289,6 +290,27 @@ BETA_G_LO, BETA_G_HI, GOLDEN_STEPS = -8, 24, 40
 EPS_TIE_REL = 1e-12
 
 
+def golden_section(f, a: float, b: float, steps: int) -> tuple[float, float]:
+    """Golden-section search for a minimiser of f on [a, b] (Kiefer 1953):
+    two interior points at the golden ratio; each step keeps the sub-interval
+    on the side of the lower value and reuses the surviving point.  Returns
+    the final bracket."""
+    invphi = (math.sqrt(5.0) - 1.0) / 2.0
+    c = b - invphi * (b - a)
+    d = a + invphi * (b - a)
+    fc, fd = f(c), f(d)
+    for _ in range(steps):
+        if fc <= fd:
+            b, d, fd = d, c, fc
+            c = b - invphi * (b - a)
+            fc = f(c)
+        else:
+            a, c, fc = c, d, fd
+            d = a + invphi * (b - a)
+            fd = f(d)
+    return a, b
+
+
 def hql_estimate(x: np.ndarray, y: np.ndarray, y0: np.ndarray, d_euclid: np.ndarray,
                  ridge_rel: float, return_parts: bool = False, alpha_override=None):
     """Full-featured K-MMSE (HQL) for one block.
@@ -299,7 +321,10 @@ def hql_estimate(x: np.ndarray, y: np.ndarray, y0: np.ndarray, d_euclid: np.ndar
     Steps (Sec. "K-MMSE overview"):
     1. C_ZZ from z_j = (x_j, y_j), 1/M normalised; C_YY gets a ridge
        lambda = ridge_rel tr(C_YY)/Ny + 1e-12 (the paper does not regularise;
-       C_YY is singular whenever M <= Ny or the content is flat);
+       C_YY is singular whenever M <= Ny or the content is flat).  If the
+       Cholesky factorisation meets a pivot <= 0 (possible only through
+       rounding when ridge_rel >= 0, and always when a negative ridge_rel
+       makes the matrix indefinite) np.linalg.LinAlgError propagates;
     2. A = C_XY C_YY^-1 (the correction matrix of eq. kmmse with H = beta C);
     3. Mahalanobis distances D(u, v) = (u-v)^T C_YY^-1 (u-v), weights
        proportional to exp(-D / (2 beta)) (eq. weights with H_YY = beta C_YY);
@@ -349,22 +374,9 @@ def hql_estimate(x: np.ndarray, y: np.ndarray, y0: np.ndarray, d_euclid: np.ndar
     emin = min(eg)
     # first minimiser; a flat minimum resolves to its smallest beta
     gstar = next(g for g, e in enumerate(eg) if e <= emin * (1.0 + EPS_TIE_REL))
-    a_t = math.log(grid[max(gstar - 1, 0)])
-    b_t = math.log(grid[min(gstar + 1, len(grid) - 1)])
-    invphi = (math.sqrt(5.0) - 1.0) / 2.0
-    c_t = b_t - invphi * (b_t - a_t)
-    d_t = a_t + invphi * (b_t - a_t)
-    fc = eps_y(math.exp(c_t))
-    fd = eps_y(math.exp(d_t))
-    for _ in range(GOLDEN_STEPS):
-        if fc <= fd:
-            b_t, d_t, fd = d_t, c_t, fc
-            c_t = b_t - invphi * (b_t - a_t)
-            fc = eps_y(math.exp(c_t))
-        else:
-            a_t, c_t, fc = c_t, d_t, fd
-            d_t = a_t + invphi * (b_t - a_t)
-            fd = eps_y(math.exp(d_t))
+    a_t, b_t = golden_section(lambda t: eps_y(math.exp(t)),
+                              math.log(grid[max(gstar - 1, 0)]),
+                              math.log(grid[min(gstar + 1, len(grid) - 1)]), GOLDEN_STEPS)
     beta = math.exp(0.5 * (a_t + b_t))
     if not eps_y(beta) < eg[gstar] * (1.0 - EPS_TIE_REL):    # kept only if better
         beta = grid[gstar]
@@ -460,10 +472,18 @@ def estimate_block(u, avail, by, bx, p: Params, cnn_gate=None):
 
     if want_hql:
         if info["n_complete"] >= max(2, p.min_hql_cands):
-            info["layer"] = LAYER_HQL
             xs = c.x[complete]
             ys = c.y[complete][:, m0]
-            return hql_estimate(xs, ys, y0[m0], c.d[complete], p.ridge_rel), info
+            try:
+                xh = hql_estimate(xs, ys, y0[m0], c.d[complete], p.ridge_rel)
+            except np.linalg.LinAlgError:
+                # a Cholesky pivot <= 0: the covariance model of eq. kmmse does
+                # not exist for this block; the paper gives no rule, the reading
+                # is the context mean of eq. mean, flagged
+                info["flags"] |= FLAG_HQL_SINGULAR
+                return brl, info
+            info["layer"] = LAYER_HQL
+            return xh, info
         info["flags"] |= FLAG_NO_HQL
     info["layer"] = LAYER_IDL
     return idl_estimate(c, full_sel, p.sigma2), info

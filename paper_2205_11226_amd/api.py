@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libskmmse.s
 
 MODES = {"profile": 0, "cnn": 1, "brl": 2, "idl": 3, "full": 4, "plain": 5}
 LAYER_FILL, LAYER_BRL, LAYER_IDL, LAYER_HQL = -1, 0, 1, 2
-FLAG_CTX_RELAXED, FLAG_NO_HQL, FLAG_NO_CAND, FLAG_EMPTY_CTX = 1, 2, 4, 8
+FLAG_CTX_RELAXED, FLAG_NO_HQL, FLAG_NO_CAND, FLAG_EMPTY_CTX, FLAG_HQL_SINGULAR = 1, 2, 4, 8, 16
 
 EXPORTS = ("skm_default_params", "skm_patch_params", "skm_create", "skm_destroy", "skm_conceal",
            "skm_conceal_device", "skm_distances_device", "skm_cnn_init", "skm_cnn_set_weights",

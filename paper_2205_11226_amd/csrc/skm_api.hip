@@ -142,8 +142,8 @@ skm_status make_params(const skm_params* in, int width, int height, int stride, 
   if (!(in->sigma2 > 0.0) || !isfinite(in->sigma2)) return fail(SKM_EINVAL, "sigma2 must be > 0");
   if (isnan(in->t_phi)) return fail(SKM_EINVAL, "t_phi is NaN");
   if (isnan(in->t_nu) || in->t_nu < 0.0) return fail(SKM_EINVAL, "t_nu must be >= 0");
-  if (!(in->ridge_rel >= 0.0) || !isfinite(in->ridge_rel))
-    return fail(SKM_EINVAL, "ridge_rel must be finite and >= 0");
+  if (!(in->ridge_rel >= -1.0) || !isfinite(in->ridge_rel))
+    return fail(SKM_EINVAL, "ridge_rel must be finite and >= -1");
   memset(p, 0, sizeof(*p));
   p->B = in->block; p->r = in->ring; p->W = in->window;
   p->Wd = p->B + 2 * p->r + 2 * p->W;

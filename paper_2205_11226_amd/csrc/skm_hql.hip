@@ -423,6 +423,7 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
         }
       }
       __syncthreads();
+      if (hs.fail) break;                 // uniform: written before the barrier
       const double dk = hs.dk;
       for (int ii = k + 1 + tid; ii < Ny; ii += kThreads) {
         double* rowi = cyy + (size_t)ii * NRs;
@@ -431,6 +432,28 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
         rowi[k] = s / dk;
       }
       __syncthreads();
+    }
+    if (hs.fail) {
+      // C_YY + lambda I is not positive definite in FP64 (a pivot <= 0): the
+      // covariance model of eq. kmmse does not exist for this block, which
+      // takes the context mean of eq. mean, flagged
+      const double mean = (double)rs.sum / (double)n0;
+      const uint8_t u8 = (uint8_t)fmin(fmax(floor(mean + 0.5), 0.0), 255.0);
+      for (int q = tid; q < B2; q += kThreads) {
+        const int py = q / B, px = q - py * B;
+        if (!partial || a.val[(size_t)(y0 + py) * p.width + x0 + px] < 0)
+          a.work[(size_t)(y0 + py) * p.stride + x0 + px] = u8;
+        if (a.xhat && i < a.cap) a.xhat[(size_t)i * B2 + q] = (float)mean;
+      }
+      if (tid == 0) {
+        if (a.info && i < a.cap) {
+          a.info[i].layer = SKM_LAYER_BRL;
+          a.info[i].flags |= SKM_FLAG_HQL_SINGULAR;
+        }
+        a.bstate[i] = round;
+      }
+      __syncthreads();
+      continue;
     }
     const double* Lc = cyy;   // lower triangle holds L
 
@@ -674,26 +697,18 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
 
     // -- x0_hat = x~(beta) + alpha A (y0 - y~(beta))
     eval_eps(beta, Mc, Ny, B2, ldm, dm0, dmin, ew, yt, xt, y0v, ytil, xtil, hs);
-    const bool fail = hs.fail != 0;
     for (int q = tid; q < B2; q += kThreads) {
       const double* arow = axy + (size_t)q * NRs;
       double corr = 0.0;
       for (int k = 0; k < Ny; ++k) corr += arow[k] * (y0v[k] - ytil[k]);
-      double xh = xtil[q] + alpha * corr;
-      if (fail) xh = (double)rs.sum / (double)n0;
+      const double xh = xtil[q] + alpha * corr;
       const int py = q / B, px = q - py * B;
       // a block holding received pixels keeps them
       if (!partial || a.val[(size_t)(y0 + py) * p.width + x0 + px] < 0)
         a.work[(size_t)(y0 + py) * p.stride + x0 + px] = (uint8_t)fmin(fmax(floor(xh + 0.5), 0.0), 255.0);
       if (a.xhat && i < a.cap) a.xhat[(size_t)i * B2 + q] = (float)xh;
     }
-    if (tid == 0) {
-      if (fail && a.info && i < a.cap) {
-        a.info[i].layer = SKM_LAYER_BRL;
-        a.info[i].flags |= SKM_FLAG_NO_HQL;
-      }
-      a.bstate[i] = round;
-    }
+    if (tid == 0) a.bstate[i] = round;
     __syncthreads();
   }
 }

@@ -292,7 +292,8 @@ def test_error_codes(ctx):
                            skm.default_params())
     assert e.value.status == -4
     for bad in (dict(block=12), dict(ring=0), dict(window=40), dict(sigma2=0.0),
-                dict(min_hql_cands=1), dict(mode=9), dict(t_nu=-1.0), dict(expand_step=1)):
+                dict(min_hql_cands=1), dict(mode=9), dict(t_nu=-1.0), dict(expand_step=1),
+                dict(ridge_rel=-1.5)):
         with pytest.raises(skm.SkmError) as e:
             ctx.conceal_device(to_dev(f), to_dev(np.zeros_like(f)), skm.default_params(**bad))
         assert e.value.status == -1, bad
@@ -386,3 +387,17 @@ def test_hql_ramp_is_exact(ctx):
     out, info, xh = ctx.conceal_device(to_dev(f), to_dev(m), pg)
     assert int(info[0]["layer"]) == 2
     np.testing.assert_allclose(xh.cpu().numpy()[0], f[40:48, 40:48], rtol=0, atol=1e-3)
+
+
+def test_hql_indefinite_covariance_falls_back_to_context_mean(ctx):
+    """A negative ridge makes C_YY + lambda I indefinite: the Cholesky
+    factorisation meets a pivot <= 0 and every HQL block takes the context
+    mean, flagged, as in the oracle (forced from the host through ridge_rel)."""
+    import paper_2205_11226_amd as skm
+    f = synth.make_luma(80, 96, 98, n_bumps=6, n_edges=4)
+    m = synth.loss_random(80, 96, 8, 0.15, 99)
+    st, info = check(ctx, f, m, "full", block=8, ring=2, window=12, min_hql_cands=8,
+                     ridge_rel=-1.0)
+    sing = (info["flags"] & skm.FLAG_HQL_SINGULAR) != 0
+    assert sing.sum() >= 3 and (info["layer"][sing] == 0).all()
+    assert not (info["layer"] == 2).any()

@@ -7,6 +7,7 @@ independent loop implementation (``oracle.brute``) on tiny frames.
 import json
 import math
 import os
+from dataclasses import replace
 
 import numpy as np
 import pytest
@@ -408,6 +409,30 @@ def test_hql_beta_not_worse_than_any_grid_point():
     _, _, _, _, _, parts, _ = _hql_parts(52)
     e = parts["eps_y"](parts["beta"])
     assert all(e <= g + 1e-12 * max(1.0, g) for g in parts["eps_grid"])
+
+
+def test_hql_with_indefinite_covariance_falls_back_to_context_mean():
+    """A negative ridge (lambda = -tr(C_YY)/N_y + 1e-12) makes C_YY + lambda I
+    indefinite for any non-isotropic covariance: the Cholesky factorisation
+    meets a pivot <= 0, and the block takes the context mean of eq. mean,
+    flagged (both oracles)."""
+    from oracle.skmmse import FLAG_HQL_SINGULAR
+    f, m = tiny_frame(51, 48, 48), cells_mask(48, 48, 8, [(2, 2), (3, 4)])
+    p = Params(block=8, ring=2, window=12, min_hql_cands=8, mode="full", ridge_rel=-1.0)
+    out, xh, info = conceal(f, m, p)
+    u, av = f.astype(np.int64), m == 0
+    for i in info:
+        assert i["layer"] == LAYER_BRL and i["flags"] & FLAG_HQL_SINGULAR, i
+        assert i["n_complete"] >= 8
+        y0, m0 = block_context(u, av, i["by"], i["bx"], p)
+        np.testing.assert_allclose(xh[(i["by"], i["bx"])], y0[m0].mean(), rtol=0, atol=1e-12)
+    bu, bxh, blay = brute.conceal(f.tolist(), m.tolist(), 8, 2, 12, min_hql=8, mode="full",
+                                  ridge_rel=-1.0)
+    assert np.array_equal(out, np.array(bu, dtype=np.uint8))
+    assert all(v == LAYER_BRL for v in blay.values())
+    # the default ridge keeps the same blocks on HQL
+    _, _, info_d = conceal(f, m, replace(p, ridge_rel=1e-3))
+    assert all(i["layer"] == LAYER_HQL and not i["flags"] for i in info_d)
 
 
 def test_covariance_matches_numpy_cov():
