@@ -180,6 +180,30 @@ skm_status skm_conceal_device(skm_ctx* ctx, const uint8_t* d_frame, const uint8_
                               skm_block_info* d_info, float* d_xhat, int32_t cap,
                               int32_t* n_lost, void* hip_stream);
 
+/* Allocation-free variant of skm_conceal_device, for callers that cannot
+ * allocate device memory while concealing (tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and return behaviour as
+ * skm_conceal_device, bitwise; the caller still owns frame, mask, out, info
+ * and xhat.  The call makes no hipMalloc, hipFree or other allocation: the
+ * frame's workspace (value plane, block tables, round state, gate and HQL
+ * scratch) is carved from a 64 MiB device array of the library, one per GPU,
+ * held from skm_create until the process ends.  Frames whose workspace does
+ * not fit return SKM_EINVAL with the size they need: without HQL scratch
+ * this is about 2 bytes per pixel plus 33 bytes per B x B cell (a 1920 x 1080
+ * frame takes 4.4 MB, a 3840 x 2160 frame at B = 16 17.7 MB); modes that may run HQL
+ * (SKM_MODE_PROFILE, SKM_MODE_CNN, SKM_MODE_FULL) also need one HQL slot,
+ * 12.9 MB at B = 16 (ring 4, window 24), and use as many HQL workgroups
+ * as the rest of the array holds (fewer than skm_conceal_device: slower HQL,
+ * same results).  Frames are launched eagerly (no graph) and without kernel
+ * timing.  Every call on one GPU, from any context, shares that GPU's array,
+ * which keeps the last call's contents: calls that overlap in time on one GPU
+ * race and must be serialised by the caller. */
+skm_status skm_conceal_device_noalloc(skm_ctx* ctx, const uint8_t* d_frame,
+                                      const uint8_t* d_mask, int32_t width, int32_t height,
+                                      int32_t stride, const skm_params* params, uint8_t* d_out,
+                                      skm_block_info* d_info, float* d_xhat, int32_t cap,
+                                      int32_t* n_lost, void* hip_stream);
+
 /* Distance table of the kernel-regression core (eq. weights / eq. slpe):
  * for each lost block i (lost-cell raster order) and each displacement
  * (dx, dy) in [-W, W]^2 (index (dy+W)*(2W+1) + (dx+W)), the exact integer

@@ -17,7 +17,7 @@ LAYER_FILL, LAYER_BRL, LAYER_IDL, LAYER_HQL = -1, 0, 1, 2
 FLAG_CTX_RELAXED, FLAG_NO_HQL, FLAG_NO_CAND, FLAG_EMPTY_CTX, FLAG_HQL_SINGULAR = 1, 2, 4, 8, 16
 
 EXPORTS = ("skm_default_params", "skm_patch_params", "skm_create", "skm_destroy", "skm_conceal",
-           "skm_conceal_device", "skm_distances_device", "skm_cnn_init", "skm_cnn_set_weights",
+           "skm_conceal_device", "skm_conceal_device_noalloc", "skm_distances_device", "skm_cnn_init", "skm_cnn_set_weights",
            "skm_cnn_get_weights", "skm_cnn_set_thresholds", "skm_save_cnn", "skm_load_cnn",
            "skm_cnn_inputs", "skm_cnn_forward", "skm_cnn_gradients", "skm_cnn_train_step",
            "skm_cnn_last_predictions", "skm_conceal_batch", "skm_set_option", "skm_get_option",
@@ -90,6 +90,8 @@ def _load():
     so.skm_conceal_device.argtypes = [vp, vp, vp, i32, i32, i32, p(Params), vp, vp, vp, i32,
                                       p(i32), vp]
     so.skm_conceal_device.restype = i32
+    so.skm_conceal_device_noalloc.argtypes = so.skm_conceal_device.argtypes
+    so.skm_conceal_device_noalloc.restype = so.skm_conceal_device.restype
     so.skm_distances_device.argtypes = [vp, vp, vp, i32, i32, i32, p(Params), vp, vp, i32,
                                         p(i32), vp]
     so.skm_distances_device.restype = i32
@@ -358,6 +360,18 @@ class Context:
         Returns (out tensor, info structured array or None, xhat float32
         tensor (n_lost, B, B) or None).
         """
+        return self._conceal_device(lib.skm_conceal_device, frame, mask, params, out,
+                                    want_info, want_xhat, stream)
+
+    def conceal_device_noalloc(self, frame, mask, params: Params, out=None, want_info=True,
+                               want_xhat=True, stream=None):
+        """skm_conceal_device_noalloc: as conceal_device, with the library's
+        workspace taken from its fixed per-GPU array (no device allocation by
+        the library; the output tensors here are the caller's)."""
+        return self._conceal_device(lib.skm_conceal_device_noalloc, frame, mask, params, out,
+                                    want_info, want_xhat, stream)
+
+    def _conceal_device(self, entry, frame, mask, params, out, want_info, want_xhat, stream):
         import torch
         _dev_check(frame, mask)
         h, w = frame.shape
@@ -371,7 +385,7 @@ class Context:
               if want_xhat else None)
         n = ctypes.c_int32(0)
         s = torch.cuda.current_stream(frame.device) if stream is None else stream
-        _check(lib.skm_conceal_device(
+        _check(entry(
             self._h, frame.data_ptr(), mask.data_ptr(), w, h, frame.stride(0),
             ctypes.byref(params), out.data_ptr(),
             dinfo.data_ptr() if dinfo is not None else None,

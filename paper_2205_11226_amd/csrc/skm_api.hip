@@ -20,6 +20,7 @@
 #include <string.h>
 
 #include <chrono>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -54,6 +55,10 @@ struct FrameSlot {
   FrameArgs pa;
   int max_rounds = 0;
   int rounds_enqueued = 0;
+  // the allocation-free slot: no kernel timing (no events), and at most this
+  // many HQL workgroups (0: no cap beyond the context's)
+  bool timing_off = false;
+  int hql_slot_cap = 0;
 };
 
 struct skm_ctx {
@@ -64,6 +69,11 @@ struct skm_ctx {
   size_t hql_lds_set = 65536;
   bool gate_lds_set = false;
   std::vector<FrameSlot*> slots;  // [0] single-frame calls, [1..] batch
+  // skm_conceal_device_noalloc: its buffers are carved from the device's
+  // `scratch` array per call; only the pinned host copy of the round state
+  // is its own (allocated by skm_create)
+  FrameSlot* na = nullptr;
+  unsigned char* scratch_dev = nullptr;   // this device's copy of `scratch`
   // staging for the host-memory entry point
   uint8_t* d_frame = nullptr;     size_t cap_frame = 0;
   uint8_t* d_mask = nullptr;      size_t cap_mask = 0;
@@ -87,6 +97,15 @@ struct skm_ctx {
   double prof_ms = 0.0;
   int prof_launches = 0;
 };
+
+// ------------------------------------------- allocation-free workspace
+// Device workspace of skm_conceal_device_noalloc.  Each GPU the library runs
+// on holds its own copy of this array until the process ends.  In host code
+// the name is only a stand-in: the address of a device's copy comes from
+// hipGetSymbolAddress with that device current (resolve_scratch, called by
+// skm_create) and is kept per device; only that address reaches kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -115,6 +134,23 @@ skm_status grow(T** ptr, size_t* cap, size_t need, const char* what) {
   size_t n = need < 1 ? 1 : need;
   SKM_HIP(hipMalloc((void**)ptr, n * sizeof(T)), what);
   *cap = n;
+  return SKM_OK;
+}
+
+std::mutex g_scratch_mu;
+std::vector<unsigned char*> g_scratch_dev;   // per device, resolved once
+
+// Address of this device's copy of `scratch` (hip_device must be current).
+skm_status resolve_scratch(int hip_device, unsigned char** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= hip_device) g_scratch_dev.resize(hip_device + 1, nullptr);
+  if (!g_scratch_dev[hip_device]) {
+    void* ptr = nullptr;
+    SKM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(SKM_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_dev[hip_device] = (unsigned char*)ptr;
+  }
+  *out = g_scratch_dev[hip_device];
   return SKM_OK;
 }
 
@@ -220,6 +256,48 @@ void slot_destroy(FrameSlot* f) {
   delete f;
 }
 
+// The allocation-free slot of context c: this device's copy of `scratch`
+// (resolved here, at set-up, with c's device current) and a pinned host copy
+// of the round state.  Its device pointers are set per call.
+skm_status na_create(skm_ctx* c) {
+  skm_status s = resolve_scratch(c->device, &c->scratch_dev);
+  if (s != SKM_OK) return s;
+  FrameSlot* f = new (std::nothrow) FrameSlot();
+  if (!f) return fail(SKM_ENOMEM, "slot allocation");
+  c->na = f;
+  f->timing_off = true;
+  SKM_HIP(hipHostMalloc((void**)&f->h_state, sizeof(RoundState), hipHostMallocCoherent),
+          "pinned round state");
+  memset(f->h_state, 0, sizeof(RoundState));
+  return SKM_OK;
+}
+
+// Dynamic LDS limits of the kernels for p's geometry (raised once, never
+// lowered); fails if the device has too little LDS.
+skm_status ensure_lds(skm_ctx* c, const DevParams& p) {
+  if (!c->gate_lds_set) {
+    SKM_HIP(set_cnn_gate_lds_limit(cnn_gate_lds_bytes()), "hipFuncSetAttribute");
+    c->gate_lds_set = true;
+  }
+  if (mode_uses_hql(p.mode)) {
+    const size_t hl = hql_lds_bytes(p);
+    if ((int)hl > c->max_lds)
+      return fail(SKM_EUNSUPPORTED, "window/ring/block need more LDS than the device has");
+    if (hl > c->hql_lds_set) {
+      SKM_HIP(set_hql_lds_limit(hl), "hipFuncSetAttribute");
+      c->hql_lds_set = hl;
+    }
+  }
+  size_t lds = main_lds_bytes(p);
+  if ((int)lds > c->max_lds)
+    return fail(SKM_EUNSUPPORTED, "window/ring/block need more LDS than the device has");
+  if (lds > c->lds_limit_set) {
+    SKM_HIP(set_main_lds_limit(lds), "hipFuncSetAttribute");
+    c->lds_limit_set = lds;
+  }
+  return SKM_OK;
+}
+
 // Workspace of slot f for frames of p's geometry (grows, never shrinks), and
 // the kernels' LDS limits.
 skm_status ensure_frame(skm_ctx* c, FrameSlot* f, const DevParams& p) {
@@ -259,29 +337,11 @@ skm_status ensure_frame(skm_ctx* c, FrameSlot* f, const DevParams& p) {
     SKM_HIP(hipMalloc((void**)&f->d_gate_pred, sizeof(float) * 2 * n), "gate predictions");
     f->cap_gate = n;
   }
-  if (!c->gate_lds_set) {
-    SKM_HIP(set_cnn_gate_lds_limit(cnn_gate_lds_bytes()), "hipFuncSetAttribute");
-    c->gate_lds_set = true;
-  }
   if (mode_uses_hql(p.mode)) {
     const size_t need = hql_slot_bytes(p) * (size_t)hql_slots(p);
     if ((s = grow(&f->d_hql_ws, &f->cap_hql, need, "HQL scratch")) != SKM_OK) return s;
-    const size_t hl = hql_lds_bytes(p);
-    if ((int)hl > c->max_lds)
-      return fail(SKM_EUNSUPPORTED, "window/ring/block need more LDS than the device has");
-    if (hl > c->hql_lds_set) {
-      SKM_HIP(set_hql_lds_limit(hl), "hipFuncSetAttribute");
-      c->hql_lds_set = hl;
-    }
   }
-  size_t lds = main_lds_bytes(p);
-  if ((int)lds > c->max_lds)
-    return fail(SKM_EUNSUPPORTED, "window/ring/block need more LDS than the device has");
-  if (lds > c->lds_limit_set) {
-    SKM_HIP(set_main_lds_limit(lds), "hipFuncSetAttribute");
-    c->lds_limit_set = lds;
-  }
-  return SKM_OK;
+  return ensure_lds(c, p);
 }
 
 FrameArgs frame_args(FrameSlot* f, const uint8_t* frame, const uint8_t* mask, uint8_t* out) {
@@ -332,7 +392,8 @@ skm_status launch_round(skm_ctx* c, FrameSlot* f, const DevParams& p, FrameArgs&
             "gate kernel");
   else
     SKM_HIP(launch_prep(a, p, nb, s), "prep kernel");
-  if (c->prof) {
+  const bool timed = c->prof && !f->timing_off;
+  if (timed) {
     while ((int)f->ev.size() < 2 * (k + 1)) {
       hipEvent_t e;
       SKM_HIP(hipEventCreate(&e), "hipEventCreate");
@@ -341,12 +402,12 @@ skm_status launch_round(skm_ctx* c, FrameSlot* f, const DevParams& p, FrameArgs&
     SKM_HIP(hipEventRecord(f->ev[2 * k], s), "hipEventRecord");
   }
   SKM_HIP(launch_est(a, p, nb, s), "estimation kernel");
-  if (c->prof) SKM_HIP(hipEventRecord(f->ev[2 * k + 1], s), "hipEventRecord");
-  if (mode_uses_hql(p.mode))
-    SKM_HIP(launch_hql(a, p, f->d_hql_ws, hql_slot_bytes(p),
-                       c->hql_grid > 0 && c->hql_grid < hql_slots(p) ? c->hql_grid : hql_slots(p),
-                       s),
-            "HQL kernel");
+  if (timed) SKM_HIP(hipEventRecord(f->ev[2 * k + 1], s), "hipEventRecord");
+  if (mode_uses_hql(p.mode)) {
+    int hg = c->hql_grid > 0 && c->hql_grid < hql_slots(p) ? c->hql_grid : hql_slots(p);
+    if (f->hql_slot_cap > 0 && hg > f->hql_slot_cap) hg = f->hql_slot_cap;
+    SKM_HIP(launch_hql(a, p, f->d_hql_ws, hql_slot_bytes(p), hg, s), "HQL kernel");
+  }
   SKM_HIP(launch_finalize(a, p, nb, s), "finalize kernel");
   return SKM_OK;
 }
@@ -443,7 +504,7 @@ skm_status finish_frame(skm_ctx* c, FrameSlot* f, const DevParams& p, FrameArgs&
     }
     batch *= 2;
     if (max_rounds && batch > max_rounds - done) batch = max_rounds - done;
-    f->ev_used = c->prof ? batch : 0;
+    f->ev_used = c->prof && !f->timing_off ? batch : 0;
     for (int k = 0; k < batch; ++k)
       if ((st = launch_round(c, f, p, a, k, s)) != SKM_OK) return st;
     done += batch;
@@ -513,6 +574,7 @@ skm_status skm_create(int32_t hip_device, skm_ctx** out) {
   FrameSlot* f0 = nullptr;
   skm_status s = slot_create(c, &f0);
   if (f0) c->slots.push_back(f0);
+  if (s == SKM_OK) s = na_create(c);
   if (s != SKM_OK) {
     skm_destroy(c);
     return s;
@@ -526,6 +588,10 @@ void skm_destroy(skm_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (FrameSlot* f : c->slots) slot_destroy(f);
+  if (c->na) {   // its device buffers live in `scratch`
+    if (c->na->h_state) (void)hipHostFree(c->na->h_state);
+    delete c->na;
+  }
   (void)hipFree(c->d_cnn);
   (void)hipFree(c->d_gate_pack);
   (void)hipFree(c->d_cnn_loss);
@@ -596,6 +662,91 @@ skm_status skm_conceal_device(skm_ctx* c, const uint8_t* d_frame, const uint8_t*
   a.info = d_info; a.xhat = d_xhat; a.cap = (d_info || d_xhat) ? cap : 0;
   int nl = 0;
   if ((s = run_frame(c, f, p, a, params->max_rounds, st, &nl)) != SKM_OK) return s;
+  if (n_lost) *n_lost = nl;
+  if ((d_info || d_xhat) && nl > cap)
+    return fail(SKM_EINVAL, "info/xhat capacity smaller than the number of lost blocks");
+  return SKM_OK;
+}
+
+skm_status skm_conceal_device_noalloc(skm_ctx* c, const uint8_t* d_frame, const uint8_t* d_mask,
+                                      int32_t width, int32_t height, int32_t stride,
+                                      const skm_params* params, uint8_t* d_out,
+                                      skm_block_info* d_info, float* d_xhat, int32_t cap,
+                                      int32_t* n_lost, void* hip_stream) {
+  if (!c) return fail(SKM_EINVAL, "ctx is NULL");
+  if (!d_frame || !d_mask || !d_out) return fail(SKM_EINVAL, "frame, mask and out are required");
+  if ((d_info || d_xhat) && cap < 0) return fail(SKM_EINVAL, "cap must be >= 0");
+  if (!c->na || !c->scratch_dev) return fail(SKM_EDEVICE, "allocation-free workspace not set up");
+  DevParams p;
+  skm_status s = make_params(params, width, height, stride, &p);
+  if (s != SKM_OK) return s;
+  // carve the frame's buffers out of this device's scratch copy
+  const size_t npx = (size_t)p.width * p.height;
+  const size_t ncell = (size_t)p.gh * p.gw < 1 ? 1 : (size_t)p.gh * p.gw;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) / 256 * 256;
+    return o;
+  };
+  const size_t o_state = take(sizeof(RoundState));
+  const size_t o_bits = take(sizeof(unsigned int) * ((ncell + 31) / 32));
+  const size_t o_val = take(sizeof(int16_t) * (npx + 2 * kValGuard));
+  const size_t o_blk = take(sizeof(int) * ncell);
+  const size_t o_bst = take(sizeof(int) * ncell);
+  const size_t o_m0 = take(sizeof(int) * ncell);
+  const size_t o_ring = take(sizeof(int2) * ncell);
+  const size_t o_hl = take(sizeof(int) * ncell);
+  const size_t o_gate = take(ncell);
+  const size_t o_gp = take(sizeof(float) * 2 * ncell);
+  int hql_cap = 0;
+  size_t o_hql = off;
+  if (mode_uses_hql(p.mode)) {
+    const size_t sb = hql_slot_bytes(p);
+    const size_t room = off < kScratchBytes ? (kScratchBytes - off) / sb : 0;
+    int want = c->hql_grid > 0 && c->hql_grid < hql_slots(p) ? c->hql_grid : hql_slots(p);
+    hql_cap = room < (size_t)want ? (int)room : want;
+    if (hql_cap < 1) off += sb;                 // report the size that one HQL slot needs
+    else o_hql = take(sb * (size_t)hql_cap);
+  }
+  if (off > kScratchBytes) {
+    char msg[200];
+    snprintf(msg, sizeof msg,
+             "frame needs %zu bytes of workspace; skm_conceal_device_noalloc has %zu "
+             "(use skm_conceal_device)", off, kScratchBytes);
+    return fail(SKM_EINVAL, msg);
+  }
+  SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  if ((s = ensure_lds(c, p)) != SKM_OK) return s;
+  unsigned char* base = c->scratch_dev;
+  FrameSlot* f = c->na;
+  f->d_state = (RoundState*)(base + o_state);
+  f->d_cellbits = (unsigned int*)(base + o_bits);
+  f->d_val = (int16_t*)(base + o_val);
+  f->d_blk = (int*)(base + o_blk);
+  f->d_bstate = (int*)(base + o_bst);
+  f->d_m0cnt = (int*)(base + o_m0);
+  f->d_ring = (int2*)(base + o_ring);
+  f->d_hql_list = (int*)(base + o_hl);
+  f->d_gate = (int8_t*)(base + o_gate);
+  f->d_gate_pred = (float*)(base + o_gp);
+  f->d_hql_ws = hql_cap > 0 ? base + o_hql : nullptr;
+  f->hql_slot_cap = hql_cap;
+  hipStream_t st = (hipStream_t)hip_stream;
+  // the array keeps the last call's contents: the round state and the cell
+  // table start at zero (a fill kernel, no memset node)
+  SKM_HIP(launch_zero_words((unsigned int*)(base + o_state),
+                            (o_val - o_state) / sizeof(unsigned int), st),
+          "workspace clear");
+  activate_gate(c, p);
+  FrameArgs a = frame_args(f, d_frame, d_mask, d_out);
+  a.info = d_info; a.xhat = d_xhat; a.cap = (d_info || d_xhat) ? cap : 0;
+  const int R = initial_rounds(f, params->max_rounds);
+  f->ev_used = 0;
+  f->rounds_enqueued = R;
+  if ((s = enqueue_eager(c, f, p, a, R, st)) != SKM_OK) return s;
+  int nl = 0;
+  if ((s = finish_frame(c, f, p, a, params->max_rounds, st, &nl, nullptr)) != SKM_OK) return s;
   if (n_lost) *n_lost = nl;
   if ((d_info || d_xhat) && nl > cap)
     return fail(SKM_EINVAL, "info/xhat capacity smaller than the number of lost blocks");

@@ -114,6 +114,8 @@ hipError_t launch_fill(const FrameArgs& a, const DevParams& p, int max_blocks,
 hipError_t launch_dist(const FrameArgs& a, const DevParams& p, int max_blocks,
                        hipStream_t s);
 hipError_t set_main_lds_limit(size_t bytes);
+// n 32-bit words at p set to zero by a fill kernel (no memset node)
+hipError_t launch_zero_words(unsigned int* p, size_t n, hipStream_t s);
 // CNN gate (skm_cnn.hip)
 constexpr int kCnnParams = 20898;
 struct CnnBuffers {

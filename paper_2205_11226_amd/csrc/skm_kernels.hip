@@ -905,6 +905,18 @@ hipError_t launch_fill(const FrameArgs& a, const DevParams& p, int max_blocks, h
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(kThreads) void k_zero_words(unsigned int* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads)
+    p[i] = 0u;
+}
+
+hipError_t launch_zero_words(unsigned int* p, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_words, dim3(clamp_grid((long long)((n + kThreads - 1) / kThreads), 256)),
+                     dim3(kThreads), 0, s, p, n);
+  return hipGetLastError();
+}
+
 hipError_t set_main_lds_limit(size_t bytes) {
   const void* fns[4] = {(const void*)k_round_main<6, 8, true>, (const void*)k_round_main<6, 8, false>,
                         (const void*)k_round_main<9, 8, false>,
