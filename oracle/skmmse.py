@@ -84,6 +84,9 @@ class Params:
     ridge_rel: float = 1e-3
     mode: str = "profile"
     max_rounds: int = 0           # 0 = until every block is concealed
+    # HQL over every admissible candidate, completing partly known candidate
+    # contexts (hql_estimate_partial); False: complete candidates only
+    hql_partial: bool = False
 
     def with_profile(self, name: str) -> "Params":
         tphi, tnu = PROFILES[name]
@@ -325,6 +328,25 @@ def hql_estimate(x: np.ndarray, y: np.ndarray, y0: np.ndarray, d_euclid: np.ndar
        Cholesky factorisation meets a pivot <= 0 (possible only through
        rounding when ridge_rel >= 0, and always when a negative ridge_rel
        makes the matrix indefinite) np.linalg.LinAlgError propagates;
+    2.-6. as in hql_core.
+    """
+    x = x.astype(np.float64)
+    y = y.astype(np.float64)
+    nx = x.shape[1]
+    z = np.concatenate([x, y], axis=1)
+    c = _cov(z)
+    cyy = c[nx:, nx:].copy()
+    ny = cyy.shape[0]
+    lam = ridge_rel * np.trace(cyy) / ny + 1e-12
+    cyy[np.diag_indices(ny)] += lam
+    chol = np.linalg.cholesky(cyy)
+    return hql_core(x, y, y0, d_euclid.astype(np.float64), c[:nx, nx:], cyy, chol, lam,
+                    return_parts, alpha_override)
+
+
+def hql_core(x, y, y0, order_key, cxy, cyy, chol, lam, return_parts=False, alpha_override=None):
+    """The estimate of eq. kmmse given the covariance blocks C_XY and the
+    regularised C_YY (with its Cholesky factor):
     2. A = C_XY C_YY^-1 (the correction matrix of eq. kmmse with H = beta C);
     3. Mahalanobis distances D(u, v) = (u-v)^T C_YY^-1 (u-v), weights
        proportional to exp(-D / (2 beta)) (eq. weights with H_YY = beta C_YY);
@@ -335,23 +357,16 @@ def hql_estimate(x: np.ndarray, y: np.ndarray, y0: np.ndarray, d_euclid: np.ndar
        as minimisers, and the refined value is kept only if it is better than
        the grid's by that margin (a flat minimum keeps its smallest beta);
     5. alpha = argmin eps_x(alpha) (eq. epsx) over I0 = the Ny + 1 candidates
-       closest to y0 in Euclidean distance (ties by raster index); each x_i is
+       with the smallest order_key (ties by raster index); each x_i is
        predicted leave-one-out from the other candidates with the same beta
        and A.  x_i_hat is affine in alpha, so the argmin is closed form;
     6. x0_hat = x~(beta) + alpha A (y0 - y~(beta)).
     """
-    x = x.astype(np.float64)
-    y = y.astype(np.float64)
-    y0 = y0.astype(np.float64)
-    m, nx = x.shape
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    y0 = np.asarray(y0, dtype=np.float64)
+    m = x.shape[0]
     ny = y.shape[1]
-    z = np.concatenate([x, y], axis=1)
-    c = _cov(z)
-    cxy = c[:nx, nx:]
-    cyy = c[nx:, nx:].copy()
-    lam = ridge_rel * np.trace(cyy) / ny + 1e-12
-    cyy[np.diag_indices(ny)] += lam
-    chol = np.linalg.cholesky(cyy)
     amat = np.linalg.solve(cyy, cxy.T).T            # C_XY C_YY^-1  (Nx x Ny)
 
     def whiten(v):                                    # L^-1 v  (rows)
@@ -385,9 +400,9 @@ def hql_estimate(x: np.ndarray, y: np.ndarray, y0: np.ndarray, d_euclid: np.ndar
     xt = w0 @ x
     yt = w0 @ y
 
-    # I0: Ny + 1 nearest candidates in Euclidean distance, ties by index
+    # I0: Ny + 1 candidates with the smallest key, ties by index
     k = min(ny + 1, m)
-    order = np.argsort(d_euclid, kind="stable")[:k]
+    order = np.argsort(order_key, kind="stable")[:k]
     vi = vy[order]
     dmah = ((vi[:, None, :] - vy[None, :, :]) ** 2).sum(axis=2)   # (k, M)
     logits = -dmah / (2.0 * beta)
@@ -407,6 +422,80 @@ def hql_estimate(x: np.ndarray, y: np.ndarray, y0: np.ndarray, d_euclid: np.ndar
                       "w": w0, "grid": grid, "eps_grid": eg, "eps_y": eps_y,
                       "dmah0": dmah0, "I0": order, "ci": ci, "ei": ei, "lam": lam}
     return xhat
+
+
+PSD_REPAIR_STEPS = 6
+
+
+def pairwise_covariance(x: np.ndarray, y: np.ndarray, o: np.ndarray):
+    """Pairwise-complete covariance of z_j = (x_j, y_j) when y_j is known only
+    where o_j is set (x_j always known).  For coordinates a, b the estimate
+    uses the candidates that know both: with N_ab their count,
+    C_ab = (1/N_ab) sum z_a z_b - (1/N_ab) sum z_a * (1/N_ab) sum z_b, each sum
+    over those candidates (0 where N_ab = 0).  With every coordinate known it
+    is the 1/M covariance of eq. covariance.  Returns (C_XY, C_YY)."""
+    x = x.astype(np.float64)
+    yz = np.where(o, y, 0).astype(np.float64)
+    of = o.astype(np.float64)
+    n_yy = of.T @ of                                   # candidates knowing a and b
+    s_yy = yz.T @ of                                   # [a, b]: sum of y_a where both known
+    g_yy = yz.T @ yz
+    with np.errstate(divide="ignore", invalid="ignore"):
+        cyy = np.where(n_yy > 0, g_yy / n_yy - (s_yy * s_yy.T) / (n_yy * n_yy), 0.0)
+    n_b = of.sum(axis=0)                               # x known everywhere: N_qb = N_b
+    sx_b = x.T @ of                                    # [q, b]: sum of x_q where y_b known
+    sy_b = yz.sum(axis=0)                              # sum of y_b where known
+    g_xy = x.T @ yz
+    with np.errstate(divide="ignore", invalid="ignore"):
+        cxy = np.where(n_b[None, :] > 0,
+                       g_xy / n_b[None, :] - (sx_b / n_b[None, :]) * (sy_b / n_b)[None, :], 0.0)
+    return cxy, cyy
+
+
+def complete_contexts(y: np.ndarray, o: np.ndarray, y0: np.ndarray) -> np.ndarray:
+    """Unknown context pixels of a candidate take the mean of that coordinate
+    over the candidates that know it, rounded half up to an integer (the
+    coordinate of y0 where no candidate knows it)."""
+    yz = np.where(o, y, 0).astype(np.int64)
+    cnt = o.sum(axis=0).astype(np.int64)
+    tot = yz.sum(axis=0)
+    safe = np.maximum(cnt, 1)
+    mean = np.where(cnt > 0, (2 * tot + safe) // (2 * safe), np.asarray(y0, dtype=np.int64))
+    return np.where(o, y, mean[None, :]).astype(np.int64)
+
+
+def hql_estimate_partial(x, y, o, y0, d, n, ridge_rel, return_parts=False):
+    """HQL over candidates whose contexts are known only where o is set
+    (reading of Sec. "K-MMSE overview" for partly lost supports; the paper's
+    candidates always have complete contexts):
+    1. C_ZZ pairwise complete (pairwise_covariance), C_YY + lambda I with
+       lambda as in hql_estimate; where the Cholesky factorisation meets a
+       pivot <= 0 (a pairwise estimate need not be positive semi-definite)
+       lambda is multiplied by 10 and the factorisation repeated, at most
+       PSD_REPAIR_STEPS times, then np.linalg.LinAlgError propagates;
+    2. unknown context pixels are completed (complete_contexts);
+    3. hql_core on the completed contexts, with I0 ordered by the normalised
+       distance d_j / n_j of the candidates (d_j over the pixels both
+       contexts know).
+    With every context complete it is hql_estimate."""
+    x = np.asarray(x, dtype=np.float64)
+    cxy, cyy0 = pairwise_covariance(x, y, o)
+    ny = cyy0.shape[0]
+    lam0 = ridge_rel * np.trace(cyy0) / ny + 1e-12
+    chol, cyy, lam = None, None, lam0
+    for k in range(PSD_REPAIR_STEPS + 1):
+        lam = lam0 * 10.0 ** k
+        cyy = cyy0.copy()
+        cyy[np.diag_indices(ny)] += lam
+        try:
+            chol = np.linalg.cholesky(cyy)
+            break
+        except np.linalg.LinAlgError:
+            if k == PSD_REPAIR_STEPS:
+                raise
+    yc = complete_contexts(y, o, y0).astype(np.float64)
+    key = np.asarray(d, dtype=np.float64) / np.asarray(n, dtype=np.float64)
+    return hql_core(x, yc, y0, key, cxy, cyy, chol, lam, return_parts)
 
 
 # ---------------------------------------------------------------- one block
@@ -471,11 +560,15 @@ def estimate_block(u, avail, by, bx, p: Params, cnn_gate=None):
         want_hql = True
 
     if want_hql:
-        if info["n_complete"] >= max(2, p.min_hql_cands):
-            xs = c.x[complete]
-            ys = c.y[complete][:, m0]
+        avail_hql = c.size if p.hql_partial else info["n_complete"]
+        if avail_hql >= max(2, p.min_hql_cands):
             try:
-                xh = hql_estimate(xs, ys, y0[m0], c.d[complete], p.ridge_rel)
+                if p.hql_partial:
+                    xh = hql_estimate_partial(c.x, c.y[:, m0], c.m[:, m0], y0[m0], c.d, c.n,
+                                              p.ridge_rel)
+                else:
+                    xh = hql_estimate(c.x[complete], c.y[complete][:, m0], y0[m0],
+                                      c.d[complete], p.ridge_rel)
             except np.linalg.LinAlgError:
                 # a Cholesky pivot <= 0: the covariance model of eq. kmmse does
                 # not exist for this block; the paper gives no rule, the reading
