@@ -6,9 +6,16 @@ ABI (loss geometry, rounds, context/flatness gate, candidate distances,
 weights, weighted averages, write-back), with the frame and mask already in
 HBM.  Prints ONE JSON line.
 
+Other workloads print a line of their own (not the headline):
+  --workload plain512   plain and full K-MMSE on a 512x512 image, 64 isolated blocks
+  --workload batch      64 mixed frames (720p, 1080p, 2160p; B 8 or 16; scattered
+                        or slice loss) in one skm_conceal_batch call
+  --workload stream4k   120 frames of 3840x2160 YUV 4:2:0, 30 % bursty loss
+  --geometry patch      the paper's 2x2 patches on the headline frame
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode cnn|profile|plain|...]
        python bench.py --traffic-run --steps 3          (under rocprofv3 --pmc)
-       python bench.py --traffic-parse FETCH_DIR WRITE_DIR OUT.json
+       python bench.py --traffic-parse FETCH_DIR WRITE_DIR OUT.json FRAMES_PER_LAUNCH
 """
 from __future__ import annotations
 
@@ -28,8 +35,15 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 METRIC = "concealed 16x16 blocks/s @1080p 25% loss, layered+CNN vs plain, ΔPSNR≤0.05dB"
-VALU_PEAK_TOPS = 78.6   # 256 CU x 64 lanes x 2 ops (mul+add) x 2.4 GHz, no packed math
-KERNEL = "k_round_main"
+# Published MI355X peaks.  The estimation kernel's arithmetic runs on the
+# vector ALUs (int16 dot products for the distances, FP32 FMA for the
+# weighted sums): its roofline is the FP32 vector peak.  The int8 MFMA peak is
+# reported beside it for the distance stage, the HBM peak for the gather and
+# weighted-sum traffic.
+VALU_PEAK_TOPS = 157.3      # FP32 vector, TFLOP/s
+INT8_MFMA_PEAK_TOPS = 5000.0
+HBM_PEAK_GBS = 8000.0
+KERNEL = "k_round_main"   # matches the batched k_round_main_b too
 
 
 # ----------------------------------------------------------- CPU baseline
@@ -101,35 +115,78 @@ def cpu_baseline(frame, mask, mode, t_nu, workers, gate_path, frac=1.0, passes=4
 # ------------------------------------------------------------ algorithmic
 
 def algorithmic_ops(d_tab, n_tab, info, b):
-    """Ops of one launch of the estimation kernel on this frame.
+    """Algorithmic work of one launch of the estimation kernel on this frame.
 
-    Per block that computes distances: 3 ops (difference, multiply, add) per
-    pair of ring pixels compared, summed over candidates; plus 2 ops (FMA)
-    per prototype pixel per candidate inside the accepted radius.  Context-
-    mean blocks count one add per known ring pixel."""
+    Distance stage: one multiply-accumulate per pair of context pixels
+    compared, summed over every admissible candidate (2 ops per MAC).
+    Weighted sum: one FMA per prototype pixel per candidate inside the
+    accepted radius (2 ops).  Context-mean blocks: one add per known context
+    pixel.  Returns a dict of op counts."""
     W = (d_tab.shape[1] - 1) // 2
     yy, xx = np.mgrid[-W:W + 1, -W:W + 1]
     rad = np.maximum(np.abs(yy), np.abs(xx))
-    total = 0
+    dist = wsum = brl = 0
     for k, inf in enumerate(info):
         if inf["layer"] == 0 and inf["n_cand"] < 0:
-            total += int(inf["n_ctx"])
+            brl += int(inf["n_ctx"])
             continue
         ok = d_tab[k] >= 0
-        total += 3 * int(n_tab[k][ok].sum())
+        dist += 2 * int(n_tab[k][ok].sum())
         if inf["layer"] == 1:
-            total += 2 * b * b * int((ok & (rad <= inf["radius"])).sum())
-    return total
+            wsum += 2 * b * b * int((ok & (rad <= inf["radius"])).sum())
+    return {"distance_ops": dist, "weighted_sum_ops": wsum, "brl_ops": brl,
+            "total": dist + wsum + brl}
 
 
-def traffic_from_profile(kernel_src_hash):
+def algorithmic_bytes(frame, n_lost, b):
+    """HBM bytes of one launch of the estimation kernel that the method needs:
+    one read of the 8-bit plane and one write of the lost blocks' pixels."""
+    return int(frame.size) + int(n_lost) * b * b
+
+
+def roofline_record(ops, nbytes, k_ms, traffic, launches, frames_per_launch):
+    sec = k_ms * 1e-3
+    achieved = ops["total"] / sec / 1e12
+    hbm = nbytes / sec / 1e9
+    rec = {
+        "kernel": KERNEL,
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": VALU_PEAK_TOPS,
+        "unit": "TOP/s",
+        "frac": achieved / VALU_PEAK_TOPS,
+        "traffic": traffic,
+        "ops_per_launch": ops,
+        "int8_mfma_distance_stage": {
+            "achieved_tops": ops["distance_ops"] / sec / 1e12, "peak_tops": INT8_MFMA_PEAK_TOPS,
+            "frac": ops["distance_ops"] / sec / 1e12 / INT8_MFMA_PEAK_TOPS,
+            "note": "distances run on VALU int16 dot products, not MFMA"},
+        "hbm": {"algorithmic_bytes": nbytes, "achieved_gbs": hbm, "peak_gbs": HBM_PEAK_GBS,
+                "frac": hbm / HBM_PEAK_GBS,
+                "counter_bytes": traffic,
+                "counter_frac": (traffic / sec / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                "counter_over_algorithmic": (traffic / nbytes) if traffic else None},
+        "kernel_ms": k_ms,
+        "launches_timed": launches,
+        "frames_per_launch": frames_per_launch,
+        "kernel_timing": "HIP events around each launch on the stream it is launched on, over "
+                         "a second run of the timed batch (eager launches, one batch in flight)",
+    }
+    return rec
+
+
+def traffic_from_profile(kernel_src_hash, frames_per_launch):
+    """Counter bytes of one estimation-kernel launch covering
+    frames_per_launch frames, from the committed counter record (None when
+    it was taken on other kernel sources)."""
     path = os.path.join(ROOT, "profiles", "traffic_k_round_main_1080p.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_source_sha1") != kernel_src_hash:
         return None
-    return rec.get("bytes_per_launch")
+    per_frame = rec.get("bytes_per_frame")
+    return None if per_frame is None else per_frame * frames_per_launch
 
 
 def kernel_source_hash():
@@ -163,6 +220,11 @@ def main():
     ap.add_argument("--geometry", choices=("block", "patch"), default="block",
                     help="patch: the paper's 2x2 patches with a 6x6 context on the same frame "
                          "(a line of its own; the default line is the block workload)")
+    ap.add_argument("--workload", choices=("layered1080p", "plain512", "batch", "stream4k"),
+                    default="layered1080p",
+                    help="layered1080p: the headline line; the others print a line of their own")
+    ap.add_argument("--distinct", type=int, default=16,
+                    help="stream4k: distinct generated frames, cycled over the 120-frame stream")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -171,6 +233,12 @@ def main():
         sys.exit(2)
 
     t_nu = {"express": 0.01, "efficient": 0.1, "excellent": 100.0}[args.profile]
+    if args.workload == "plain512":
+        return bench_plain512(args)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "stream4k":
+        return bench_stream4k(args)
     frame, mask = synth.workload_layered_1080p()
     if args.traffic_run:
         return traffic_run(args, frame, mask)
@@ -230,11 +298,14 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / k
 
-    # launch configuration picked by the library's autotuner on a short batch
-    tune_ms = ctx.autotune(jobs_for(p_lay, 16), reps=3)
-    tuned = {"batch_streams": ctx.get_option(skm.OPT_BATCH_STREAMS),
+    # launch configuration picked by the library's autotuner on a batch of the
+    # timed size (this also sizes the workspaces, so that no allocation falls
+    # in the timed region)
+    tune_ms = ctx.autotune(jobs_for(p_lay, args.steps), reps=3)
+    tuned = {"batch_mode": ctx.get_option(skm.OPT_BATCH_MODE),
+             "batch_streams": ctx.get_option(skm.OPT_BATCH_STREAMS),
              "graphs": ctx.get_option(skm.OPT_GRAPHS),
-             "gate_grid": ctx.get_option(skm.OPT_GATE_GRID), "tune_batch16_ms": tune_ms}
+             "gate_grid": ctx.get_option(skm.OPT_GATE_GRID), "tune_batch_ms": tune_ms}
     print(f"# autotune: {tuned}", file=sys.stderr, flush=True)
 
     sec_lay = timed_batch(p_lay)
@@ -247,9 +318,12 @@ def main():
     ctx.set_option(skm.OPT_BATCH_STREAMS, streams)
     ms_tot, launches = ctx.profile_read()
     k_ms = ms_tot / max(launches, 1)
+    # every frame of this workload takes one round: a launch of the batched
+    # estimation kernel covers steps / launches frames (1 in frame-pipeline mode)
+    frames_per_launch = args.steps / max(launches, 1)
     print(f"# layered ({args.mode}): {sec_lay * 1e3:.3f} ms/frame ({sec_lay_ev * 1e3:.3f} with "
-          f"event timing), estimation kernel {k_ms * 1e3:.1f} us x {launches / args.steps:.0f} "
-          f"per frame", file=sys.stderr, flush=True)
+          f"event timing), estimation kernel {k_ms * 1e3:.1f} us per launch of "
+          f"{frames_per_launch:.0f} frames", file=sys.stderr, flush=True)
     lat_lay = timed_single(p_lay, min(args.steps, 20))
     sec_plain = timed_batch(p_plain)
     print(f"# plain: {sec_plain * 1e3:.3f} ms/frame", file=sys.stderr, flush=True)
@@ -265,7 +339,6 @@ def main():
     d_tab, n_tab = d_tab.cpu().numpy(), n_tab.cpu().numpy()
     n_lost = len(info_lay)
     ops = algorithmic_ops(d_tab, n_tab, info_lay, 16)
-    achieved = ops / (k_ms * 1e-3) / 1e12
     ps_lay = psnr(o_lay.cpu().numpy(), frame)
     ps_full = psnr(o_full.cpu().numpy(), frame)
     ps_prof = psnr(o_prof.cpu().numpy(), frame)
@@ -295,7 +368,8 @@ def main():
             "lost_blocks": n_lost,
             "frames_per_s": 1.0 / sec_lay,
             "timed": f"one skm_conceal_batch call over {args.steps} frames (the same input, "
-                     f"outputs in 8 rotating buffers), launch configuration from skm_autotune",
+                     f"outputs in 8 rotating buffers), launch configuration from skm_autotune "
+                     f"on a batch of the same size",
             "launch_config": tuned,
             "single_frame_latency_ms": lat_lay * 1e3,
             "psnr_layered_db": ps_lay,
@@ -309,24 +383,211 @@ def main():
                              "delta_psnr_db": ps_full - ps_prof,
                              "layers": layer_counts(info_prof)},
         },
-        "roofline": {
-            "kernel": KERNEL,
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": VALU_PEAK_TOPS,
-            "unit": "TOP/s",
-            "frac": achieved / VALU_PEAK_TOPS,
-            "traffic": traffic_from_profile(kernel_source_hash()),
-            "ops_per_launch": ops,
-            "kernel_ms": k_ms,
-            "launches_timed": launches,
-            "kernel_timing": "HIP events around each launch, over a second run of the timed "
-                             "batch with one frame in flight (eager launches)",
-        },
+        "roofline": roofline_record(
+            {k: v * frames_per_launch for k, v in ops.items()},
+            algorithmic_bytes(frame, n_lost, 16) * frames_per_launch, k_ms,
+            traffic_from_profile(kernel_source_hash(), frames_per_launch), launches,
+            frames_per_launch),
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
     ctx.close()
+
+
+# ------------------------------------------------------ other workloads
+
+def _line(metric, value, unit, args, ms_per_step, config, higher=True, **extra):
+    rec = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": higher,
+           "scaling": "weak", "vs_baseline": None, "dtype": "i32+f32+f64", "data": "synthetic",
+           "config": config}
+    rec.update(extra)
+    print(json.dumps(rec), flush=True)
+
+
+def _timed_batches(ctx, jobs, steps, warmup):
+    """`warmup` untimed skm_conceal_batch calls over `jobs`, then `steps` timed
+    ones; returns seconds per call and the last call's results."""
+    import torch
+    for _ in range(max(warmup, 1)):
+        ctx.conceal_batch(jobs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = ctx.conceal_batch(jobs)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / max(steps, 1)
+    if any(r[2] != 0 for r in res):
+        raise SystemExit(f"batch status {[r[2] for r in res]}")
+    return sec, res
+
+
+def _oracle_blocks(args):
+    f, m, mode = args
+    from oracle.skmmse import Params, estimate_block, lost_cells
+    u = np.where(m == 0, f, 0).astype(np.int64)
+    t0 = time.perf_counter()
+    cells = lost_cells(m, 16)
+    for by, bx in cells:
+        estimate_block(u, m == 0, by, bx, Params(mode=mode))
+    return len(cells), time.perf_counter() - t0
+
+
+def bench_plain512(args):
+    """Plain (fixed-bandwidth IDL over the whole window) and full K-MMSE (HQL
+    wherever 64 complete candidates exist) on the 512x512 image with 64
+    isolated lost blocks: blocks/s and ms per block, one frame per step
+    (frames of a step's batch in flight together)."""
+    import torch
+    import paper_2205_11226_amd as skm
+    frame, mask = synth.workload_plain_512()
+    fd, md = torch.from_numpy(frame).cuda(), torch.from_numpy(mask).cuda()
+    outs = [torch.empty_like(fd) for _ in range(8)]
+    ctx = skm.Context(0)
+    res = {}
+    for mode in ("plain", "full"):
+        p = skm.default_params(mode=mode)
+        o, info, _ = ctx.conceal_device(fd, md, p, want_xhat=False)
+        jobs = [(fd, md, outs[j % 8], p) for j in range(args.steps)]
+        sec, _ = _timed_batches(ctx, jobs, 1, args.warmup)
+        sec /= args.steps
+        n = len(info)
+        res[mode] = {"blocks_per_s": n / sec, "ms_per_frame": sec * 1e3,
+                     "ms_per_block_sequential_equiv": sec * 1e3 / n,
+                     "psnr_db": psnr(o.cpu().numpy(), frame),
+                     "layers": {"brl": int((info["layer"] == 0).sum()),
+                                "idl": int((info["layer"] == 1).sum()),
+                                "hql": int((info["layer"] == 2).sum())}}
+        print(f"# {mode}: {sec * 1e3:.3f} ms/frame", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(2) as pool:
+            r = pool.map(_oracle_blocks, [(frame, mask, "plain"), (frame, mask, "full")])
+        cpu = {"value": r[1][0] / r[1][1], "unit": "blocks/s", "cores": 1, "kind": "oracle",
+               "sample": f"all {r[1][0]} blocks of the frame, float64 NumPy oracle on one core "
+                         f"each: full K-MMSE {r[1][1]:.2f} s, plain {r[0][1]:.2f} s "
+                         f"({r[0][0] / r[0][1]:.1f} blocks/s)"}
+    ctx.close()
+    _line("full K-MMSE blocks/s, 512x512, 64 isolated 16x16 blocks", res["full"]["blocks_per_s"],
+          "blocks/s", args, res["full"]["ms_per_frame"],
+          {"workload": "512x512 luma (40 bumps, 12 edges), 64 isolated 16x16 lost blocks, "
+                       "plain and full K-MMSE, one frame per step", "modes": res},
+          cpu_baseline=cpu)
+
+
+def _gen_batch(args):
+    base, f, hw = args
+    return synth.workload_batch(1, seed=base + f, sizes=[hw])[0]
+
+
+def bench_batch(args):
+    """The mixed batch: 24 x 1280x720, 32 x 1920x1080, 8 x 3840x2160 frames;
+    per frame the seed picks B (8 or 16) and scattered (10-30 %) or slice
+    (5-50 %) loss.  One step = one skm_conceal_batch call over the 64 frames
+    in --mode (default: layered with the learned gate), launch configuration
+    from skm_autotune."""
+    import multiprocessing as mp
+    import torch
+    import paper_2205_11226_amd as skm
+    sizes = [(720, 1280)] * 24 + [(1080, 1920)] * 32 + [(2160, 3840)] * 8
+    base = synth.seed_for(3)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        frames = pool.map(_gen_batch, [(base, f, hw) for f, hw in enumerate(sizes)])
+    print(f"# generated 64 frames in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    ctx = skm.Context(0)
+    ctx.cnn_load(args.weights)
+    jobs, n_px = [], 0
+    for w in frames:
+        fd = torch.from_numpy(w["frame"]).cuda()
+        md = torch.from_numpy(w["mask"]).cuda()
+        jobs.append((fd, md, torch.empty_like(fd), skm.default_params(mode=args.mode,
+                                                                      block=w["block"])))
+        n_px += w["frame"].size
+    tune_ms = ctx.autotune(jobs, reps=2)
+    sec, res = _timed_batches(ctx, jobs, args.steps, args.warmup)
+    blocks = sum(r[0] for r in res)
+    rounds = [r[1] for r in res]
+    tuned = {"batch_mode": ctx.get_option(skm.OPT_BATCH_MODE),
+             "batch_streams": ctx.get_option(skm.OPT_BATCH_STREAMS),
+             "graphs": ctx.get_option(skm.OPT_GRAPHS),
+             "gate_grid": ctx.get_option(skm.OPT_GATE_GRID), "tune_batch_ms": tune_ms}
+    ctx.close()
+    kinds = {}
+    for w in frames:
+        key = f"B{w['block']}-{w['kind']}"
+        kinds[key] = kinds.get(key, 0) + 1
+    _line("concealed blocks/s, 64-frame mixed batch (720p/1080p/2160p, B 8|16, scattered|slice "
+          "loss)", blocks / sec, "blocks/s", args, sec * 1e3,
+          {"workload": "64 frames: 24 x 1280x720, 32 x 1920x1080, 8 x 3840x2160 luma; per frame "
+                       "B 8|16 and scattered 10-30 % or slice 5-50 % loss by seed; one "
+                       "skm_conceal_batch call over the 64 frames per step",
+           "mode": args.mode, "frames_per_s": 64 / sec, "megapixels": n_px / 1e6,
+           "lost_blocks": blocks, "rounds_max": max(rounds), "frame_kinds": kinds,
+           "launch_config": tuned})
+
+
+def _gen_stream(k):
+    return synth.workload_stream_4k(k)
+
+
+def bench_stream4k(args):
+    """120 frames of 3840x2160 YUV 4:2:0 (Y in 16x16 blocks, U and V in 8x8
+    cells co-located with the lost luma macroblocks), 30 % random loss in
+    bursts of up to 4 blocks, layered with the learned gate.  `--distinct`
+    frames are generated and cycled over the 120 (each a different input in
+    HBM; more than the last-level cache holds).  One step = one
+    skm_conceal_batch call over the 360 planes of the 120 frames.  Delta PSNR
+    (full K-MMSE minus layered) over frames 0-9, untimed."""
+    import multiprocessing as mp
+    import torch
+    import paper_2205_11226_amd as skm
+    nd = max(10, args.distinct)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        gen = pool.map(_gen_stream, range(nd))
+    print(f"# generated {nd} frames in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    ctx = skm.Context(0)
+    ctx.cnn_load(args.weights)
+    dev = []
+    for planes, masks in gen:
+        dev.append([(torch.from_numpy(p).cuda(), torch.from_numpy(m).cuda()) for p, m in
+                    zip(planes, masks)])
+    prm = {16: skm.default_params(mode=args.mode, block=16),
+           8: skm.default_params(mode=args.mode, block=8)}
+    full = {16: skm.default_params(mode="full", block=16),
+            8: skm.default_params(mode="full", block=8)}
+    jobs = []
+    for k in range(120):
+        for c, (fd, md) in enumerate(dev[k % nd]):
+            jobs.append((fd, md, torch.empty_like(fd), prm[16 if c == 0 else 8]))
+    tune_ms = ctx.autotune(jobs[:48], reps=2)
+    sec, res = _timed_batches(ctx, jobs, args.steps, args.warmup)
+    blocks = sum(r[0] for r in res)
+    luma_blocks = sum(r[0] for r in res[0::3])
+    # quality over frames 0-9 (untimed)
+    d_lay, d_full = [], []
+    for k in range(10):
+        (yf, ym) = dev[k][0]
+        o_l, _, _ = ctx.conceal_device(yf, ym, prm[16], want_info=False, want_xhat=False)
+        o_f, _, _ = ctx.conceal_device(yf, ym, full[16], want_info=False, want_xhat=False)
+        truth = gen[k][0][0]
+        d_lay.append(psnr(o_l.cpu().numpy(), truth))
+        d_full.append(psnr(o_f.cpu().numpy(), truth))
+    ctx.close()
+    _line("concealed 4K YUV 4:2:0 frames/s, 30% bursty 16x16 loss, layered+CNN",
+          120 / sec, "frames/s", args, sec * 1e3 / 120,
+          {"workload": f"120 frames of 3840x2160 YUV 4:2:0 ({nd} distinct generated frames "
+                       "cycled), Y in 16x16 blocks, U/V in co-located 8x8 cells, 30 % random "
+                       "loss in bursts of <= 4; one skm_conceal_batch over the 360 planes per "
+                       "step", "mode": args.mode,
+           "blocks_per_s": blocks / sec, "lost_blocks_per_frame": blocks / 120,
+           "luma_blocks_per_frame": luma_blocks / 120, "tune_ms": tune_ms,
+           "psnr_luma_layered_db_frames0_9": float(np.mean(d_lay)),
+           "psnr_luma_full_kmmse_db_frames0_9": float(np.mean(d_full)),
+           "delta_psnr_db_frames0_9": float(np.mean(d_full) - np.mean(d_lay))})
 
 
 # ------------------------------------------------------ 2x2 patch geometry
@@ -396,15 +657,18 @@ def traffic_run(args, frame, mask):
     if args.mode == "cnn":
         ctx.cnn_load(args.weights)
     p = skm.default_params(mode=args.mode, profile=args.profile)
-    for _ in range(args.steps):
-        ctx.conceal_device(fd, md, p, out=out, want_info=False, want_xhat=False)
+    # the timed configuration: one skm_conceal_batch over --steps frames
+    # (batched kernels: one estimation launch covers every frame)
+    outs = [torch.empty_like(fd) for _ in range(8)]
+    ctx.conceal_batch([(fd, md, outs[j % 8], p) for j in range(args.steps)])
     src = torch.ones(COPY_BYTES, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
     ctx.close()
-    print(f"# traffic run: {args.steps} frames, 3 copies of {COPY_BYTES} bytes", flush=True)
+    print(f"# traffic run: one batch of {args.steps} frames, 3 copies of {COPY_BYTES} bytes",
+          flush=True)
 
 
 def _counter_rows(d):
@@ -418,7 +682,7 @@ def _counter_rows(d):
     return rows
 
 
-def traffic_parse(fetch_dir, write_dir, out_path):
+def traffic_parse(fetch_dir, write_dir, out_path, frames_per_launch):
     res = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         per = {}
@@ -439,8 +703,10 @@ def traffic_parse(fetch_dir, write_dir, out_path):
         res[counter] = {"kernel_counter_avg": main_avg, "copy_counter_avg": copy_avg,
                         "bytes_per_unit": scale, "bytes": main_avg * scale,
                         "dispatches": len(main[0])}
+    per_launch = res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"]
     rec = {"kernel": KERNEL, "kernel_source_sha1": kernel_source_hash(),
-           "bytes_per_launch": res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"],
+           "frames_per_launch": frames_per_launch,
+           "bytes_per_launch": per_launch, "bytes_per_frame": per_launch / frames_per_launch,
            "counters": res}
     with open(out_path, "w") as f:
         json.dump(rec, f, indent=1)
@@ -449,6 +715,6 @@ def traffic_parse(fetch_dir, write_dir, out_path):
 
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "--traffic-parse":
-        traffic_parse(sys.argv[2], sys.argv[3], sys.argv[4])
+        traffic_parse(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]))
     else:
         main()

@@ -78,7 +78,8 @@ enum { SKM_LAYER_FILL = -1, SKM_LAYER_BRL = 0, SKM_LAYER_IDL = 1, SKM_LAYER_HQL 
 /* skm_block_info.flags bits. */
 enum {
   SKM_FLAG_CTX_RELAXED = 1, /* concealed with fewer than ring*block context px */
-  SKM_FLAG_NO_HQL = 2,      /* HQL wanted, too few complete candidates: IDL   */
+  SKM_FLAG_NO_HQL = 2,      /* HQL wanted, too few complete (with hql_partial:
+                               admissible) candidates: IDL                    */
   SKM_FLAG_NO_CAND = 4,     /* no admissible candidate: BRL                   */
   SKM_FLAG_EMPTY_CTX = 8,   /* forced fill without context: frame mean        */
   SKM_FLAG_HQL_SINGULAR = 16 /* HQL: C_YY + lambda I met a Cholesky pivot <= 0
@@ -107,6 +108,18 @@ typedef struct skm_params {
                               negative value makes it indefinite for any
                               non-isotropic C_YY, which sends HQL blocks to
                               the SKM_FLAG_HQL_SINGULAR fallback (for tests) */
+  int32_t hql_partial;     /* 0: HQL over the candidates whose context covers
+                              all of m0 (the paper's candidates); 1: over every
+                              admissible candidate, partly known contexts
+                              completed -- pairwise-complete covariance (each
+                              pair of coordinates over the candidates knowing
+                              both), lambda x10 up to 6 times until C_YY +
+                              lambda I factorises, unknown context pixels set
+                              to their coordinate's rounded mean over the
+                              candidates knowing it, I0 by d_j / n_j.  Makes
+                              full K-MMSE available under lattice and slice
+                              loss (a reading: the paper is silent)           */
+  int32_t reserved;        /* must be 0                                       */
 } skm_params;
 
 /* Per lost block result, in the raster order (by, then bx) of the lost cells. */
@@ -270,14 +283,26 @@ skm_status skm_cnn_train_step(skm_ctx* ctx, const uint16_t* d_inputs, const floa
 skm_status skm_cnn_last_predictions(skm_ctx* ctx, float* host, int32_t cap);
 
 /* Batch: conceal n independent frames (device buffers), each with its own
- * geometry and parameters (block sizes may differ).  The frames are spread
- * over up to SKM_OPT_BATCH_STREAMS frame slots, each with its own device
- * workspace and HIP stream, so that several frames are in flight; each
- * frame's pipeline (loss geometry, rounds, state copy) is replayed from a
- * captured hipGraph when its arguments repeat.  Work starts after the work
- * already enqueued on hip_stream and is complete (every frame) when the call
- * returns.  Per frame: `n_lost`, `rounds` and `status` are written; the
+ * geometry and parameters (block sizes may differ).  Work starts after the
+ * work already enqueued on hip_stream and is complete (every frame) when the
+ * call returns.  Per frame: `n_lost`, `rounds` and `status` are written; the
  * call returns the first non-OK status, after finishing every frame it could.
+ * Two launch modes (SKM_OPT_BATCH_MODE):
+ *  1 (default), batched kernels: frames of equal size and parameters form a
+ *    group whose pipeline is one launch per stage over the (frame, lost
+ *    block) items of all its frames -- loss geometry, then per round the
+ *    context statistics or the learned gate (persistent workgroups), the
+ *    estimation kernel (one workgroup per item), HQL and the end-of-round
+ *    bookkeeping -- with every frame's rounds and results as if it were
+ *    concealed alone.  A group's launches are replayed from a captured
+ *    hipGraph while the launch shapes repeat.  Up to SKM_OPT_BATCH_STREAMS
+ *    groups run at once on their own streams.  The estimation variant and
+ *    gate grid of a group come from the tile table (skm_autotune), else from
+ *    SKM_OPT_EST_VARIANT and SKM_OPT_GATE_GRID.
+ *  0, frame pipelines: frames are spread over up to SKM_OPT_BATCH_STREAMS
+ *    frame slots, each with its own workspace, stream and captured graph of
+ *    one frame's pipeline.
+ * Results are bitwise those of skm_conceal_device in both modes.
  * Not in the paper: batching is an implementation layer around the
  * per-frame method (Sec. "Reconstruction framework"). */
 typedef struct skm_frame_desc {
@@ -302,20 +327,41 @@ enum {
   SKM_OPT_BATCH_STREAMS = 2,  /* frames in flight in skm_conceal_batch, 1..8 (4)  */
   SKM_OPT_GATE_GRID = 3,      /* workgroups of the CNN gate kernel, multiple of 8
                                  in 8..4096 (768)                                 */
-  SKM_OPT_HQL_GRID = 4        /* most workgroups of the HQL kernel, 1..1024; 0
+  SKM_OPT_HQL_GRID = 4,       /* most workgroups of the HQL kernel, 1..1024; 0
                                  (default): as many as 1 GiB of scratch per frame
                                  slot holds, 128..1024 by geometry                */
+  SKM_OPT_BATCH_MODE = 5,     /* skm_conceal_batch: 1 (default) batched kernels per
+                                 group of equal frames, 0 frame pipelines         */
+  SKM_OPT_EST_VARIANT = 6     /* batched estimation kernel variant: -1 (default)
+                                 the geometry's first; 0: compile-time unit offsets
+                                 of B 16 / ring 4 / window 24 (6 candidates per
+                                 thread); 1, 2, 3: 6, 9, 17 candidates per thread
+                                 (variants too small for the geometry are replaced
+                                 by its first).  Setting it, or SKM_OPT_GATE_GRID,
+                                 clears the tile table                           */
 };
 skm_status skm_set_option(skm_ctx* ctx, int32_t option, int64_t value);
 skm_status skm_get_option(skm_ctx* ctx, int32_t option, int64_t* value);
 
 /* Autotuner: times skm_conceal_batch on these frames under each launch
- * configuration (1, 2, 4, 8 streams; graphs on and off; gate grids 512, 768
- * and 1536 when a frame uses SKM_MODE_CNN), keeping the best of `reps` runs
- * each, and sets the fastest configuration on the context.  The frames are
+ * configuration -- batched mode with every estimation variant of the first
+ * frame's geometry and gate grids 512, 768, 1536 and 3072 (CNN mode), and
+ * frame pipelines on 1, 2, 4 and 8 streams with gate grids 512, 768 and 1536
+ * (CNN mode); graphs on and off -- keeping the best of `reps` runs each.  The
+ * winner's batch mode, streams and graph use are set on the context; in
+ * batched mode its estimation variant and gate grid are kept in the tile
+ * table under the first frame's (block, ring, window).  The frames are
  * concealed several times.  best_ms (optional) receives the best batch time. */
 skm_status skm_autotune(skm_ctx* ctx, skm_frame_desc* frames, int32_t n, int32_t reps,
                         double* best_ms);
+
+/* Tuning cache as JSON: {"version": 1, "batch_mode", "batch_streams",
+ * "graphs", "gate_grid", "tiles": [{"block", "ring", "window", "est_variant",
+ * "gate_grid", "batch_ms"}, ...]}.  Save writes the context's options and
+ * tile table; load validates every field (SKM_EINVAL on a missing or
+ * out-of-range one, the context unchanged) and replaces them. */
+skm_status skm_autotune_save(skm_ctx* ctx, const char* path);
+skm_status skm_autotune_load(skm_ctx* ctx, const char* path);
 
 /* Kernel timing for measurement tools (not needed for concealment).  While
  * enabled, the context brackets every launch of its per-block estimation

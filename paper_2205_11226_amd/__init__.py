@@ -9,5 +9,5 @@ from .api import (  # noqa: F401
     FLAG_CTX_RELAXED, FLAG_NO_HQL, FLAG_NO_CAND, FLAG_EMPTY_CTX, FLAG_HQL_SINGULAR, SkmError,
     Params,
     default_params, patch_params, Context, lib, exported_symbols, FrameDesc, OPT_GRAPHS, OPT_BATCH_STREAMS,
-    OPT_GATE_GRID, OPT_HQL_GRID,
+    OPT_GATE_GRID, OPT_HQL_GRID, OPT_BATCH_MODE, OPT_EST_VARIANT,
 )

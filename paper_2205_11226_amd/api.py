@@ -21,8 +21,10 @@ EXPORTS = ("skm_default_params", "skm_patch_params", "skm_create", "skm_destroy"
            "skm_cnn_get_weights", "skm_cnn_set_thresholds", "skm_save_cnn", "skm_load_cnn",
            "skm_cnn_inputs", "skm_cnn_forward", "skm_cnn_gradients", "skm_cnn_train_step",
            "skm_cnn_last_predictions", "skm_conceal_batch", "skm_set_option", "skm_get_option",
-           "skm_autotune", "skm_profile_enable", "skm_profile_read", "skm_last_error")
+           "skm_autotune", "skm_autotune_save", "skm_autotune_load", "skm_profile_enable",
+           "skm_profile_read", "skm_last_error")
 OPT_GRAPHS, OPT_BATCH_STREAMS, OPT_GATE_GRID, OPT_HQL_GRID = 1, 2, 3, 4
+OPT_BATCH_MODE, OPT_EST_VARIANT = 5, 6
 CNN_PARAMS = 20898
 
 
@@ -39,6 +41,7 @@ class Params(ctypes.Structure):
         ("min_hql_cands", ctypes.c_int32), ("mode", ctypes.c_int32),
         ("max_rounds", ctypes.c_int32), ("sigma2", ctypes.c_double),
         ("t_phi", ctypes.c_double), ("t_nu", ctypes.c_double), ("ridge_rel", ctypes.c_double),
+        ("hql_partial", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -120,6 +123,10 @@ def _load():
     so.skm_get_option.restype = i32
     so.skm_autotune.argtypes = [vp, p(FrameDesc), i32, i32, p(ctypes.c_double)]
     so.skm_autotune.restype = i32
+    so.skm_autotune_save.argtypes = [vp, cp]
+    so.skm_autotune_save.restype = i32
+    so.skm_autotune_load.argtypes = [vp, cp]
+    so.skm_autotune_load.restype = i32
     so.skm_profile_enable.argtypes = [vp, i32]
     so.skm_profile_enable.restype = i32
     so.skm_profile_read.argtypes = [vp, p(ctypes.c_double), p(i32)]
@@ -261,6 +268,14 @@ class Context:
         _check(lib.skm_autotune(self._h, descs, len(jobs), int(reps), ctypes.byref(ms)))
         del keep
         return ms.value
+
+    def autotune_save(self, path: str):
+        """Write the launch options and per-geometry tile table as JSON."""
+        _check(lib.skm_autotune_save(self._h, os.fsencode(path)))
+
+    def autotune_load(self, path: str):
+        """Read a tuning file written by autotune_save."""
+        _check(lib.skm_autotune_load(self._h, os.fsencode(path)))
 
     # ------------------------------------------------------- learned gate
     def cnn_init(self, seed: int = 0):

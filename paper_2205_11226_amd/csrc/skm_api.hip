@@ -61,6 +61,48 @@ struct FrameSlot {
   int hql_slot_cap = 0;
 };
 
+// Launch shape of the batched pipeline for one geometry (block, ring, window):
+// estimation kernel variant (candidate slices per thread) and the gate's
+// workgroup count.
+struct TileConfig {
+  int block, ring, window;
+  int est_variant;
+  int gate_grid;
+  double batch_ms;     // the autotuner's best batch time (informational)
+};
+
+// A group of batch frames with equal size and parameters, concealed by the
+// batched kernels: one launch per stage over the (frame, block) items of all
+// its frames.  Its workspace holds nf equal per-frame slices.
+struct GroupSlot {
+  unsigned char* d_pool = nullptr; size_t cap_pool = 0;
+  std::vector<size_t> layout_key;    // offsets of the last layout (re-zeroed on change)
+  FrameIO* d_io = nullptr;
+  FrameIO* h_io = nullptr;           // pinned staging of the caller-buffer table
+  size_t cap_io = 0;
+  int* d_cum = nullptr; size_t cap_cum = 0;
+  BatchState* d_bs = nullptr;
+  BatchState* h_bs = nullptr;        // pinned, coherent: published by the kernels
+  RoundState* h_states = nullptr;    // pinned, coherent: per-frame states
+  size_t cap_states = 0;
+  unsigned char* d_hql_ws = nullptr; size_t cap_hql = 0;
+  hipStream_t stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<unsigned char> gkey;
+  int last_rounds = 1;
+  // the group in flight
+  bool pending = false;
+  std::vector<int> frames;           // indices into the caller's frame list
+  DevParams p;
+  BatchArgs b;
+  int max_rounds = 0;
+  int rounds_enqueued = 0;
+  int est_variant = 0, gate_grid = 768;
+  // kernel timing: event pairs around the batched estimation kernel
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
+};
+
 struct skm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;   // host-memory entry point, CNN calls
@@ -87,11 +129,17 @@ struct skm_ctx {
   int cnn_step = 0;
   float tau1 = 0.0f, tau2 = 0.0f;
   float* d_cnn_buf = nullptr;   size_t cap_cnn_buf = 0;   // training activations
+  // batched mode of skm_conceal_batch: group slots (workspace, stream, graph)
+  std::vector<GroupSlot*> groups;
+  // tuned tile shapes per (block, ring, window), from skm_autotune or a cache
+  std::vector<TileConfig> tiles;
   // options
   bool use_graphs = true;
+  int batch_mode = 1;             // 1: batched kernels per group; 0: frame pipelines
   int batch_streams = 4;
   int gate_grid = 768;
   int hql_grid = 0;               // 0: hql_slots(p)
+  int est_variant = -1;           // -1: tuned or default
   // kernel timing (skm_profile_*)
   bool prof = false;
   double prof_ms = 0.0;
@@ -180,6 +228,9 @@ skm_status make_params(const skm_params* in, int width, int height, int stride, 
   if (isnan(in->t_nu) || in->t_nu < 0.0) return fail(SKM_EINVAL, "t_nu must be >= 0");
   if (!(in->ridge_rel >= -1.0) || !isfinite(in->ridge_rel))
     return fail(SKM_EINVAL, "ridge_rel must be finite and >= -1");
+  if (in->hql_partial != 0 && in->hql_partial != 1)
+    return fail(SKM_EINVAL, "hql_partial must be 0 or 1");
+  if (in->reserved != 0) return fail(SKM_EINVAL, "reserved must be 0");
   memset(p, 0, sizeof(*p));
   p->B = in->block; p->r = in->ring; p->W = in->window;
   p->Wd = p->B + 2 * p->r + 2 * p->W;
@@ -206,6 +257,7 @@ skm_status make_params(const skm_params* in, int width, int height, int stride, 
       if (p->radii[ri] >= rho) { b = ri; break; }
     p->bucket_lut[rho >> 4] |= (unsigned long long)b << (4 * (rho & 15));
   }
+  p->hql_partial = in->hql_partial;
   p->min_pct = in->min_overlap_pct;
   p->min_hql = in->min_hql_cands;
   p->mode = in->mode;
@@ -533,7 +585,434 @@ skm_status run_frame(skm_ctx* c, FrameSlot* f, const DevParams& p, FrameArgs& a,
   return finish_frame(c, f, p, a, max_rounds, s, n_lost_out, nullptr);
 }
 
+// ----------------------------------------------------------- batch groups
+
+skm_status group_create(GroupSlot** out) {
+  GroupSlot* g = new (std::nothrow) GroupSlot();
+  if (!g) return fail(SKM_ENOMEM, "group allocation");
+  *out = g;
+  SKM_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking), "hipStreamCreate");
+  SKM_HIP(hipMalloc((void**)&g->d_bs, sizeof(BatchState)), "batch state");
+  SKM_HIP(hipMemset(g->d_bs, 0, sizeof(BatchState)), "batch state");
+  SKM_HIP(hipHostMalloc((void**)&g->h_bs, sizeof(BatchState), hipHostMallocCoherent),
+          "pinned batch state");
+  memset(g->h_bs, 0, sizeof(BatchState));
+  return SKM_OK;
+}
+
+void group_destroy(GroupSlot* g) {
+  if (!g) return;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+  (void)hipFree(g->d_pool);
+  (void)hipFree(g->d_io);
+  (void)hipFree(g->d_cum);
+  (void)hipFree(g->d_bs);
+  (void)hipFree(g->d_hql_ws);
+  for (hipEvent_t e : g->ev) (void)hipEventDestroy(e);
+  if (g->h_io) (void)hipHostFree(g->h_io);
+  if (g->h_bs) (void)hipHostFree(g->h_bs);
+  if (g->h_states) (void)hipHostFree(g->h_states);
+  if (g->stream) (void)hipStreamDestroy(g->stream);
+  delete g;
+}
+
+// Per-frame slices of a group's workspace: nf copies of each table.
+struct PoolLayout {
+  size_t val_stride, bits_stride, cell_stride;
+  size_t o_state, o_bits, o_val, o_blk, o_bst, o_m0, o_ring, o_hl, o_gate, o_gp, total;
+};
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+PoolLayout pool_layout(const DevParams& p, int nf) {
+  PoolLayout L;
+  const size_t npx = (size_t)p.width * p.height;
+  const size_t ncell = (size_t)p.gh * p.gw < 1 ? 1 : (size_t)p.gh * p.gw;
+  L.val_stride = round_up(npx + 2 * kValGuard, 128);
+  L.bits_stride = round_up((ncell + 31) / 32, 64);
+  L.cell_stride = round_up(ncell, 64);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = round_up(off + bytes, 256);
+    return o;
+  };
+  const size_t n = (size_t)nf;
+  L.o_state = take(sizeof(RoundState) * n);
+  L.o_bits = take(sizeof(unsigned int) * L.bits_stride * n);
+  L.o_val = take(sizeof(int16_t) * L.val_stride * n);
+  L.o_blk = take(sizeof(int) * L.cell_stride * n);
+  L.o_bst = take(sizeof(int) * L.cell_stride * n);
+  L.o_m0 = take(sizeof(int) * L.cell_stride * n);
+  L.o_ring = take(sizeof(int2) * L.cell_stride * n);
+  L.o_hl = take(sizeof(int) * L.cell_stride * n);
+  L.o_gate = take(L.cell_stride * n);
+  L.o_gp = take(sizeof(float) * 2 * L.cell_stride * n);
+  L.total = off;
+  return L;
+}
+
+// Workspace and batch arguments of group g for nf frames of p's geometry.
+// The round states and cell tables (the front of the pool) must be zero
+// between launches: they are cleared when the pool is new or its layout
+// changed; the kernels leave them zero after every frame.
+skm_status group_prepare(skm_ctx* c, GroupSlot* g, const DevParams& p, int nf) {
+  const PoolLayout L = pool_layout(p, nf);
+  skm_status s;
+  bool fresh = false;
+  if (L.total > g->cap_pool || !g->d_pool) {
+    if ((s = grow(&g->d_pool, &g->cap_pool, L.total, "batch workspace")) != SKM_OK) return s;
+    fresh = true;
+  }
+  const std::vector<size_t> key = {L.o_state, L.o_bits, L.o_val, L.bits_stride};
+  if (fresh || key != g->layout_key) {
+    SKM_HIP(launch_zero_words((unsigned int*)(g->d_pool + L.o_state),
+                              (L.o_val - L.o_state) / sizeof(unsigned int), g->stream),
+            "batch workspace clear");
+    g->layout_key = key;
+  }
+  if ((size_t)nf > g->cap_io || !g->d_io) {
+    (void)hipFree(g->d_io); g->d_io = nullptr;
+    if (g->h_io) { (void)hipHostFree(g->h_io); g->h_io = nullptr; }
+    g->cap_io = 0;
+    SKM_HIP(hipMalloc((void**)&g->d_io, sizeof(FrameIO) * nf), "frame table");
+    SKM_HIP(hipHostMalloc((void**)&g->h_io, sizeof(FrameIO) * nf, 0), "frame table staging");
+    g->cap_io = nf;
+  }
+  if ((s = grow(&g->d_cum, &g->cap_cum, (size_t)nf + 1, "item offsets")) != SKM_OK) return s;
+  if ((size_t)nf > g->cap_states || !g->h_states) {
+    if (g->h_states) (void)hipHostFree(g->h_states);
+    g->h_states = nullptr;
+    g->cap_states = 0;
+    SKM_HIP(hipHostMalloc((void**)&g->h_states, sizeof(RoundState) * nf, hipHostMallocCoherent),
+            "pinned frame states");
+    memset(g->h_states, 0, sizeof(RoundState) * nf);
+    g->cap_states = nf;
+  }
+  if (mode_uses_hql(p.mode)) {
+    const size_t need = hql_slot_bytes(p) * (size_t)hql_slots(p);
+    if ((s = grow(&g->d_hql_ws, &g->cap_hql, need, "HQL scratch")) != SKM_OK) return s;
+  }
+  if ((s = ensure_lds(c, p)) != SKM_OK) return s;
+  BatchArgs& b = g->b;
+  memset(&b, 0, sizeof(b));
+  unsigned char* pool = g->d_pool;
+  FrameArgs& a0 = b.a0;
+  a0.st = (RoundState*)(pool + L.o_state);
+  a0.hstate = g->h_states;
+  a0.cellbits = (unsigned int*)(pool + L.o_bits);
+  a0.val = (int16_t*)(pool + L.o_val) + kValGuard;
+  a0.blk = (int*)(pool + L.o_blk);
+  a0.bstate = (int*)(pool + L.o_bst);
+  a0.m0cnt = (int*)(pool + L.o_m0);
+  a0.ring = (int2*)(pool + L.o_ring);
+  a0.hql_list = (int*)(pool + L.o_hl);
+  a0.gate = (int8_t*)(pool + L.o_gate);
+  a0.gate_pred = (float*)(pool + L.o_gp);
+  b.val_stride = L.val_stride;
+  b.cell_stride = (int)L.cell_stride;
+  b.bits_stride = (int)L.bits_stride;
+  b.nf = nf;
+  b.io = g->d_io;
+  b.cum = g->d_cum;
+  b.bs = g->d_bs;
+  b.hbs = g->h_bs;
+  g->p = p;
+  return SKM_OK;
+}
+
+// FrameArgs of frame f of group g on the host (caller buffers from the
+// staging table)
+FrameArgs group_frame_host(const GroupSlot* g, int f) {
+  FrameArgs a = g->b.a0;
+  a.val += (size_t)f * g->b.val_stride;
+  a.cellbits += (size_t)f * g->b.bits_stride;
+  const size_t cs = (size_t)f * g->b.cell_stride;
+  a.blk += cs; a.bstate += cs; a.m0cnt += cs; a.ring += cs; a.hql_list += cs;
+  a.gate += cs; a.gate_pred += 2 * cs;
+  a.st += f;
+  a.hstate += f;
+  const FrameIO& io = g->h_io[f];
+  a.frame = io.frame; a.mask = io.mask; a.work = io.out;
+  a.info = io.info; a.xhat = io.xhat; a.cap = io.cap;
+  return a;
+}
+
+int group_prep_grid(const DevParams& p, int nf) {
+  const long long waves = (long long)nf * p.gh * p.gw;
+  long long g = (waves + 3) / 4;
+  if (g > 2048) g = 2048;
+  if (g < 8) g = 8;
+  return (int)((g + 7) / 8 * 8);
+}
+
+int group_fin_grid(const DevParams& p, int nf) {
+  long long g = ((long long)nf * p.gh * p.gw + 15) / 16;
+  return (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
+}
+
+int group_hql_slots(const skm_ctx* c, const DevParams& p) {
+  return c->hql_grid > 0 && c->hql_grid < hql_slots(p) ? c->hql_grid : hql_slots(p);
+}
+
+skm_status launch_round_b(skm_ctx* c, GroupSlot* g, hipStream_t s) {
+  const DevParams& p = g->p;
+  const BatchArgs& b = g->b;
+  if (p.cnn_active)
+    SKM_HIP(launch_cnn_gate_b(b, p, c->d_gate_pack, c->d_cnn + kCnnParams, c->tau1, c->tau2,
+                              g->gate_grid, s),
+            "batched gate kernel");
+  else
+    SKM_HIP(launch_prep_b(b, p, group_prep_grid(p, b.nf), s), "batched prep kernel");
+  const int k = g->ev_used;
+  if (c->prof) {
+    while ((int)g->ev.size() < 2 * (k + 1)) {
+      hipEvent_t e;
+      SKM_HIP(hipEventCreate(&e), "hipEventCreate");
+      g->ev.push_back(e);
+    }
+    SKM_HIP(hipEventRecord(g->ev[2 * k], s), "hipEventRecord");
+  }
+  SKM_HIP(launch_est_b(b, p, g->est_variant, s), "batched estimation kernel");
+  if (c->prof) {
+    SKM_HIP(hipEventRecord(g->ev[2 * k + 1], s), "hipEventRecord");
+    g->ev_used = k + 1;
+  }
+  if (mode_uses_hql(p.mode))
+    SKM_HIP(launch_hql_b(b, p, g->d_hql_ws, hql_slot_bytes(p), group_hql_slots(c, p), s),
+            "batched HQL kernel");
+  SKM_HIP(launch_finalize_b(b, p, group_fin_grid(p, b.nf), s), "batched finalize kernel");
+  return SKM_OK;
+}
+
+skm_status group_enqueue_eager(skm_ctx* c, GroupSlot* g, int R, hipStream_t s) {
+  SKM_HIP(launch_init_b(g->b, g->p, s), "batched geometry kernel");
+  for (int k = 0; k < R; ++k) {
+    skm_status st = launch_round_b(c, g, s);
+    if (st != SKM_OK) return st;
+  }
+  return SKM_OK;
+}
+
+// Geometry + R rounds of group g on its stream, replayed from a captured
+// graph while the launch arguments repeat (the kernels read the caller
+// buffers from the frame table, uploaded before each launch).
+skm_status group_enqueue(skm_ctx* c, GroupSlot* g, int R) {
+  g->rounds_enqueued = R;
+  SKM_HIP(hipMemcpyAsync(g->d_io, g->h_io, sizeof(FrameIO) * g->b.nf, hipMemcpyHostToDevice,
+                         g->stream),
+          "frame table upload");
+  g->ev_used = 0;
+  // with kernel timing on, launches are eager (events recorded by graph
+  // nodes cannot be queried for elapsed time)
+  if (!c->use_graphs || c->prof) return group_enqueue_eager(c, g, R, g->stream);
+  std::vector<unsigned char> key(sizeof(BatchArgs) + sizeof(DevParams) + 4 * sizeof(int) +
+                                 2 * sizeof(float) + sizeof(void*));
+  unsigned char* kp = key.data();
+  memcpy(kp, &g->b, sizeof(BatchArgs)); kp += sizeof(BatchArgs);
+  memcpy(kp, &g->p, sizeof(DevParams)); kp += sizeof(DevParams);
+  const int ints[4] = {R, g->gate_grid, g->est_variant, c->hql_grid};
+  memcpy(kp, ints, sizeof(ints)); kp += sizeof(ints);
+  memcpy(kp, &c->tau1, sizeof(float)); kp += sizeof(float);
+  memcpy(kp, &c->tau2, sizeof(float)); kp += sizeof(float);
+  memcpy(kp, &c->d_cnn, sizeof(void*));
+  if (!g->gexec || key != g->gkey) {
+    if (g->gexec) { (void)hipGraphExecDestroy(g->gexec); g->gexec = nullptr; }
+    g->gkey.clear();
+    hipGraph_t graph = nullptr;
+    SKM_HIP(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    skm_status st = group_enqueue_eager(c, g, R, g->stream);
+    hipError_t e = hipStreamEndCapture(g->stream, &graph);
+    if (st != SKM_OK || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      return st != SKM_OK ? st : hip_fail(e, "end capture");
+    }
+    e = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) { g->gexec = nullptr; return hip_fail(e, "graph instantiate"); }
+    g->gkey = key;
+  }
+  SKM_HIP(hipGraphLaunch(g->gexec, g->stream), "graph launch");
+  return SKM_OK;
+}
+
+// Wait for group g, run more rounds while blocks are pending (up to the
+// round limit, then fill per frame), and write every frame's results.
+skm_status group_finish(skm_ctx* c, GroupSlot* g, skm_frame_desc* frames) {
+  g->pending = false;
+  hipStream_t s = g->stream;
+  SKM_HIP(hipStreamSynchronize(s), "stream synchronize");
+  auto take_timing = [&]() -> skm_status {
+    for (int k = 0; k < g->ev_used; ++k) {
+      float ms = 0.f;
+      SKM_HIP(hipEventElapsedTime(&ms, g->ev[2 * k], g->ev[2 * k + 1]), "hipEventElapsedTime");
+      c->prof_ms += ms;
+      ++c->prof_launches;
+    }
+    g->ev_used = 0;
+    return SKM_OK;
+  };
+  skm_status tst = take_timing();
+  if (tst != SKM_OK) return tst;
+  int done = g->rounds_enqueued, batch = done < 1 ? 1 : done;
+  skm_status st;
+  while (g->h_bs->remaining != 0 && !(g->max_rounds && done >= g->max_rounds)) {
+    batch *= 2;
+    if (g->max_rounds && batch > g->max_rounds - done) batch = g->max_rounds - done;
+    for (int k = 0; k < batch; ++k)
+      if ((st = launch_round_b(c, g, s)) != SKM_OK) return st;
+    done += batch;
+    SKM_HIP(hipStreamSynchronize(s), "stream synchronize");
+    if ((st = take_timing()) != SKM_OK) return st;
+  }
+  const int nf = g->b.nf;
+  if (g->h_bs->remaining != 0) {
+    // round limit: context-mean fill of each frame still pending
+    for (int f = 0; f < nf; ++f) {
+      if (g->h_states[f].remaining == 0) continue;
+      SKM_HIP(launch_fill(group_frame_host(g, f), g->p, g->p.gh * g->p.gw, s), "fill kernels");
+    }
+    SKM_HIP(hipStreamSynchronize(s), "stream synchronize");
+  }
+  skm_status first = SKM_OK;
+  int used_max = 1;
+  for (int f = 0; f < nf; ++f) {
+    skm_frame_desc& d = frames[g->frames[f]];
+    const RoundState& rs = g->h_states[f];
+    d.n_lost = rs.n_lost;
+    const int used = rs.round - 1;
+    d.rounds = used;
+    used_max = used > used_max ? used : used_max;
+    skm_status fs = check_err(rs);
+    if (fs == SKM_OK && (d.info || d.xhat) && rs.n_lost > d.cap)
+      fs = fail(SKM_EINVAL, "info/xhat capacity smaller than the number of lost blocks");
+    d.status = fs;
+    if (fs != SKM_OK && first == SKM_OK) first = fs;
+  }
+  g->last_rounds = used_max > 64 ? 64 : used_max;
+  return first;
+}
+
+const TileConfig* tile_for(const skm_ctx* c, const DevParams& p) {
+  for (const TileConfig& t : c->tiles)
+    if (t.block == p.B && t.ring == p.r && t.window == p.W) return &t;
+  return nullptr;
+}
+
+// skm_conceal_batch in batched mode.
+skm_status batch_groups_run(skm_ctx* c, skm_frame_desc* frames, int32_t n, hipStream_t caller) {
+  skm_status first = SKM_OK;
+  std::vector<DevParams> prm(n);
+  std::vector<int> ok(n, 0);
+  for (int k = 0; k < n; ++k) {
+    skm_frame_desc& d = frames[k];
+    d.status = SKM_OK; d.n_lost = 0; d.rounds = 0;
+    skm_status s = SKM_OK;
+    if (!d.frame || !d.mask || !d.out || !d.params)
+      s = fail(SKM_EINVAL, "frame, mask, out and params are required");
+    else if ((d.info || d.xhat) && d.cap < 0)
+      s = fail(SKM_EINVAL, "cap must be >= 0");
+    else if ((s = make_params(d.params, d.width, d.height, d.stride, &prm[k])) == SKM_OK)
+      activate_gate(c, prm[k]);
+    if (s != SKM_OK) {
+      d.status = s;
+      if (first == SKM_OK) first = s;
+      continue;
+    }
+    ok[k] = 1;
+  }
+  // groups of equal parameters and size, in order of their first frame
+  std::vector<std::vector<int>> groups;
+  std::vector<int> gmax;
+  for (int k = 0; k < n; ++k) {
+    if (!ok[k]) continue;
+    int gi = -1;
+    for (size_t q = 0; q < groups.size(); ++q) {
+      const int r = groups[q][0];
+      if (memcmp(&prm[r], &prm[k], sizeof(DevParams)) == 0 &&
+          frames[r].params->max_rounds == frames[k].params->max_rounds) { gi = (int)q; break; }
+    }
+    if (gi < 0) { groups.push_back({}); gi = (int)groups.size() - 1; }
+    groups[gi].push_back(k);
+  }
+  const int S = (int)groups.size() < c->batch_streams ? (int)groups.size() : c->batch_streams;
+  while ((int)c->groups.size() < S) {
+    GroupSlot* g = nullptr;
+    skm_status s = group_create(&g);
+    if (g) c->groups.push_back(g);
+    if (s != SKM_OK) return s;
+  }
+  // order the groups' work after the caller's earlier work
+  hipEvent_t ready = nullptr;
+  SKM_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming), "hipEventCreate");
+  hipError_t e = hipEventRecord(ready, caller);
+  for (int k = 0; k < S && e == hipSuccess; ++k) e = hipStreamWaitEvent(c->groups[k]->stream, ready, 0);
+  (void)hipEventDestroy(ready);
+  if (e != hipSuccess) return hip_fail(e, "batch ordering");
+  for (size_t q = 0; q < groups.size(); ++q) {
+    GroupSlot* g = c->groups[q % S];
+    skm_status s;
+    if (g->pending && (s = group_finish(c, g, frames)) != SKM_OK && first == SKM_OK) first = s;
+    const std::vector<int>& fr = groups[q];
+    const DevParams& p = prm[fr[0]];
+    if ((s = group_prepare(c, g, p, (int)fr.size())) != SKM_OK) {
+      for (int k : fr) frames[k].status = s;
+      if (first == SKM_OK) first = s;
+      continue;
+    }
+    for (size_t j = 0; j < fr.size(); ++j) {
+      const skm_frame_desc& d = frames[fr[j]];
+      FrameIO& io = g->h_io[j];
+      io.frame = d.frame; io.mask = d.mask; io.out = d.out;
+      io.info = d.info; io.xhat = d.xhat;
+      io.cap = (d.info || d.xhat) ? d.cap : 0;
+      io.pad = 0;
+    }
+    g->frames = fr;
+    g->max_rounds = frames[fr[0]].params->max_rounds;
+    // launch shape: the tuned one of this geometry, else the options
+    const TileConfig* t = tile_for(c, p);
+    int variants[4];
+    const int nv = est_variants(p, variants);
+    int v = t ? t->est_variant : (c->est_variant >= 0 ? c->est_variant : variants[0]);
+    bool valid = false;
+    for (int k = 0; k < nv; ++k) valid = valid || variants[k] == v;
+    g->est_variant = valid ? v : variants[0];
+    g->gate_grid = t ? t->gate_grid : c->gate_grid;
+    int R = g->last_rounds < 1 ? 1 : g->last_rounds;
+    if (g->max_rounds && R > g->max_rounds) R = g->max_rounds;
+    if ((s = group_enqueue(c, g, R)) != SKM_OK) {
+      for (int k : fr) frames[k].status = s;
+      if (first == SKM_OK) first = s;
+      continue;
+    }
+    g->pending = true;
+  }
+  for (int k = 0; k < S; ++k) {
+    GroupSlot* g = c->groups[k];
+    skm_status s;
+    if (g->pending && (s = group_finish(c, g, frames)) != SKM_OK && first == SKM_OK) first = s;
+  }
+  return first;
+}
+
 }  // namespace
+
+// integer value of "key": in text [b, e), or false
+static bool json_int(const std::string& t, size_t b, size_t e, const char* key, int* out) {
+  const std::string k = std::string("\"") + key + "\"";
+  const size_t at = t.find(k, b);
+  if (at == std::string::npos || at >= e) return false;
+  size_t q = t.find(':', at + k.size());
+  if (q == std::string::npos || q >= e) return false;
+  char* end = nullptr;
+  const long v = strtol(t.c_str() + q + 1, &end, 10);
+  if (end == t.c_str() + q + 1) return false;
+  *out = (int)v;
+  return true;
+}
 
 extern "C" {
 
@@ -542,6 +1021,7 @@ void skm_default_params(skm_params* p) {
   p->block = 16; p->ring = 4; p->window = 24; p->expand_step = 4;
   p->min_overlap_pct = 50; p->min_hql_cands = 64; p->mode = SKM_MODE_PROFILE;
   p->max_rounds = 0; p->sigma2 = 10.0; p->t_phi = 20.0; p->t_nu = 0.1; p->ridge_rel = 1e-3;
+  p->hql_partial = 0; p->reserved = 0;
 }
 
 void skm_patch_params(skm_params* p) {
@@ -588,6 +1068,7 @@ void skm_destroy(skm_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (FrameSlot* f : c->slots) slot_destroy(f);
+  for (GroupSlot* g : c->groups) group_destroy(g);
   if (c->na) {   // its device buffers live in `scratch`
     if (c->na->h_state) (void)hipHostFree(c->na->h_state);
     delete c->na;
@@ -620,11 +1101,21 @@ skm_status skm_set_option(skm_ctx* c, int32_t option, int64_t value) {
       if (value < 8 || value > 4096 || value % 8 != 0)
         return fail(SKM_EINVAL, "SKM_OPT_GATE_GRID takes a multiple of 8 in 8..4096");
       c->gate_grid = (int)value;
+      c->tiles.clear();
       return SKM_OK;
     case SKM_OPT_HQL_GRID:
       if (value < 0 || value > kHqlSlotsMax)
         return fail(SKM_EINVAL, "SKM_OPT_HQL_GRID takes 0..1024");
       c->hql_grid = (int)value;
+      return SKM_OK;
+    case SKM_OPT_BATCH_MODE:
+      if (value != 0 && value != 1) return fail(SKM_EINVAL, "SKM_OPT_BATCH_MODE takes 0 or 1");
+      c->batch_mode = (int)value;
+      return SKM_OK;
+    case SKM_OPT_EST_VARIANT:
+      if (value < -1 || value > 3) return fail(SKM_EINVAL, "SKM_OPT_EST_VARIANT takes -1..3");
+      c->est_variant = (int)value;
+      c->tiles.clear();
       return SKM_OK;
     default:
       return fail(SKM_EINVAL, "unknown option");
@@ -638,6 +1129,8 @@ skm_status skm_get_option(skm_ctx* c, int32_t option, int64_t* value) {
     case SKM_OPT_BATCH_STREAMS: *value = c->batch_streams; return SKM_OK;
     case SKM_OPT_GATE_GRID: *value = c->gate_grid; return SKM_OK;
     case SKM_OPT_HQL_GRID: *value = c->hql_grid; return SKM_OK;
+    case SKM_OPT_BATCH_MODE: *value = c->batch_mode; return SKM_OK;
+    case SKM_OPT_EST_VARIANT: *value = c->est_variant; return SKM_OK;
     default: return fail(SKM_EINVAL, "unknown option");
   }
 }
@@ -813,6 +1306,7 @@ skm_status skm_conceal_batch(skm_ctx* c, skm_frame_desc* frames, int32_t n, void
   if (n < 0 || (n > 0 && !frames)) return fail(SKM_EINVAL, "bad frame list");
   if (n == 0) return SKM_OK;
   SKM_HIP(hipSetDevice(c->device), "hipSetDevice");
+  if (c->batch_mode == 1) return batch_groups_run(c, frames, n, (hipStream_t)hip_stream);
   const int S = n < c->batch_streams ? n : c->batch_streams;
   skm_status s;
   while ((int)c->slots.size() < 1 + S) {
@@ -871,47 +1365,155 @@ skm_status skm_conceal_batch(skm_ctx* c, skm_frame_desc* frames, int32_t n, void
   return first;
 }
 
-// Times the batch under each launch configuration (streams 1, 2, 4, 8 with
-// graphs on and off; gate grids 512, 768, 1536 in CNN mode), repeats `reps`
-// times, keeps the fastest and reports its time.  The frames are concealed
+// Times the batch under each launch configuration and keeps the fastest:
+// batched mode with every estimation variant of the first frame's geometry
+// and gate grids 512, 768, 1536 and 3072 (CNN mode), graphs on and off; and
+// frame pipelines on 1, 2, 4 or 8 streams with graphs on and off (gate grids
+// 512, 768, 1536).  Each configuration: one warm call, then the best of
+// `reps`.  The winner's batch mode, streams and graphs are set on the
+// context; its estimation variant and gate grid are kept for the first
+// frame's (block, ring, window) in the tile table.  The frames are concealed
 // (several times) as a side effect.
 skm_status skm_autotune(skm_ctx* c, skm_frame_desc* frames, int32_t n, int32_t reps,
                         double* best_ms) {
   if (!c) return fail(SKM_EINVAL, "ctx is NULL");
-  if (n < 1 || !frames || reps < 1) return fail(SKM_EINVAL, "bad arguments");
+  if (n < 1 || !frames || reps < 1 || !frames[0].params) return fail(SKM_EINVAL, "bad arguments");
   bool cnn = false;
   for (int k = 0; k < n; ++k) cnn = cnn || (frames[k].params && frames[k].params->mode == SKM_MODE_CNN);
+  DevParams p0;
+  skm_status s = make_params(frames[0].params, frames[0].width, frames[0].height, frames[0].stride,
+                             &p0);
+  if (s != SKM_OK) return s;
+  int variants[4];
+  const int nv = est_variants(p0, variants);
+  const int grids_b[4] = {512, 768, 1536, 3072};
+  const int grids_s[3] = {512, 768, 1536};
   const int streams[4] = {1, 2, 4, 8};
-  const int grids[3] = {512, 768, 1536};
+  struct Cfg { int mode, streams, graphs, gate, variant; };
+  std::vector<Cfg> cfgs;
+  for (int graphs = 0; graphs <= 1; ++graphs) {
+    for (int vi = 0; vi < nv; ++vi)
+      for (int gi = 0; gi < (cnn ? 4 : 1); ++gi)
+        cfgs.push_back({1, 8, graphs, cnn ? grids_b[gi] : c->gate_grid, variants[vi]});
+    for (int si = 0; si < 4; ++si)
+      for (int gi = 0; gi < (cnn ? 3 : 1); ++gi)
+        cfgs.push_back({0, streams[si], graphs, cnn ? grids_s[gi] : c->gate_grid, -1});
+  }
+  const int keep_mode = c->batch_mode, keep_streams = c->batch_streams;
+  const bool keep_graphs = c->use_graphs;
+  const int keep_gate = c->gate_grid, keep_var = c->est_variant;
+  std::vector<TileConfig> keep_tiles = c->tiles;
+  c->tiles.clear();
   double best = 1e300;
-  int bs = c->batch_streams, bg = c->use_graphs ? 1 : 0, bgg = c->gate_grid;
-  for (int gi = 0; gi < (cnn ? 3 : 1); ++gi) {
-    for (int graphs = 0; graphs <= 1; ++graphs) {
-      for (int si = 0; si < 4; ++si) {
-        c->batch_streams = streams[si];
-        c->use_graphs = graphs != 0;
-        if (cnn) c->gate_grid = grids[gi];
-        skm_status s = skm_conceal_batch(c, frames, n, nullptr);   // warm (captures graphs)
-        if (s != SKM_OK) return s;
-        double t_best = 1e300;
-        for (int r = 0; r < reps; ++r) {
-          const auto t0 = std::chrono::steady_clock::now();
-          if ((s = skm_conceal_batch(c, frames, n, nullptr)) != SKM_OK) return s;
-          const double ms = std::chrono::duration<double, std::milli>(
-                                std::chrono::steady_clock::now() - t0).count();
-          if (ms < t_best) t_best = ms;
-        }
-        if (t_best < best) {
-          best = t_best;
-          bs = streams[si]; bg = graphs; bgg = c->gate_grid;
-        }
-      }
+  Cfg win = {keep_mode, keep_streams, keep_graphs ? 1 : 0, keep_gate, keep_var};
+  for (const Cfg& k : cfgs) {
+    c->batch_mode = k.mode;
+    c->batch_streams = k.streams;
+    c->use_graphs = k.graphs != 0;
+    c->gate_grid = k.gate;
+    c->est_variant = k.variant;
+    s = skm_conceal_batch(c, frames, n, nullptr);            // warm (captures graphs)
+    if (s != SKM_OK) break;
+    double t_best = 1e300;
+    for (int r = 0; r < reps && s == SKM_OK; ++r) {
+      const auto t0 = std::chrono::steady_clock::now();
+      s = skm_conceal_batch(c, frames, n, nullptr);
+      const double ms = std::chrono::duration<double, std::milli>(
+                            std::chrono::steady_clock::now() - t0).count();
+      if (ms < t_best) t_best = ms;
+    }
+    if (s != SKM_OK) break;
+    if (t_best < best) { best = t_best; win = k; }
+  }
+  c->tiles = keep_tiles;
+  if (s != SKM_OK) {
+    c->batch_mode = keep_mode; c->batch_streams = keep_streams; c->use_graphs = keep_graphs;
+    c->gate_grid = keep_gate; c->est_variant = keep_var;
+    return s;
+  }
+  c->batch_mode = win.mode;
+  c->batch_streams = win.mode == 1 ? keep_streams : win.streams;
+  c->use_graphs = win.graphs != 0;
+  c->est_variant = keep_var;
+  if (win.mode == 1) {
+    c->gate_grid = keep_gate;
+    TileConfig t = {p0.B, p0.r, p0.W, win.variant, win.gate, best};
+    bool found = false;
+    for (TileConfig& q : c->tiles)
+      if (q.block == t.block && q.ring == t.ring && q.window == t.window) { q = t; found = true; }
+    if (!found) c->tiles.push_back(t);
+  } else {
+    c->gate_grid = win.gate;
+  }
+  if (best_ms) *best_ms = best;
+  return SKM_OK;
+}
+
+// Tuning cache: the context's launch options and tile table as JSON.
+skm_status skm_autotune_save(skm_ctx* c, const char* path) {
+  if (!c || !path) return fail(SKM_EINVAL, "NULL argument");
+  FILE* fp = fopen(path, "w");
+  if (!fp) return fail(SKM_EINVAL, std::string("cannot write ") + path);
+  fprintf(fp, "{\n  \"version\": 1,\n  \"batch_mode\": %d,\n  \"batch_streams\": %d,\n"
+              "  \"graphs\": %d,\n  \"gate_grid\": %d,\n  \"tiles\": [",
+          c->batch_mode, c->batch_streams, c->use_graphs ? 1 : 0, c->gate_grid);
+  for (size_t k = 0; k < c->tiles.size(); ++k) {
+    const TileConfig& t = c->tiles[k];
+    fprintf(fp, "%s\n    {\"block\": %d, \"ring\": %d, \"window\": %d, \"est_variant\": %d, "
+                "\"gate_grid\": %d, \"batch_ms\": %.6f}",
+            k ? "," : "", t.block, t.ring, t.window, t.est_variant, t.gate_grid, t.batch_ms);
+  }
+  fprintf(fp, "\n  ]\n}\n");
+  const bool bad = ferror(fp) != 0;
+  fclose(fp);
+  return bad ? fail(SKM_EINVAL, std::string("write error on ") + path) : SKM_OK;
+}
+
+skm_status skm_autotune_load(skm_ctx* c, const char* path) {
+  if (!c || !path) return fail(SKM_EINVAL, "NULL argument");
+  FILE* fp = fopen(path, "r");
+  if (!fp) return fail(SKM_EINVAL, std::string("cannot read ") + path);
+  std::string t;
+  char buf[4096];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof buf, fp)) > 0) t.append(buf, got);
+  fclose(fp);
+  const size_t tiles_at = t.find("\"tiles\"");
+  int version = 0, mode = 1, streams = 4, graphs = 1, gate = 768;
+  const size_t head_end = tiles_at == std::string::npos ? t.size() : tiles_at;
+  if (!json_int(t, 0, head_end, "version", &version) || version != 1)
+    return fail(SKM_EINVAL, "not a version-1 tuning file");
+  if (!json_int(t, 0, head_end, "batch_mode", &mode) ||
+      !json_int(t, 0, head_end, "batch_streams", &streams) ||
+      !json_int(t, 0, head_end, "graphs", &graphs) || !json_int(t, 0, head_end, "gate_grid", &gate))
+    return fail(SKM_EINVAL, "tuning file lacks a launch option");
+  if ((mode != 0 && mode != 1) || streams < 1 || streams > kMaxBatchStreams ||
+      (graphs != 0 && graphs != 1) || gate < 8 || gate > 4096 || gate % 8)
+    return fail(SKM_EINVAL, "tuning file holds an out-of-range option");
+  std::vector<TileConfig> tiles;
+  if (tiles_at != std::string::npos) {
+    size_t b = t.find('{', tiles_at);
+    while (b != std::string::npos) {
+      const size_t e = t.find('}', b);
+      if (e == std::string::npos) return fail(SKM_EINVAL, "unterminated tile entry");
+      TileConfig q = {0, 0, 0, 0, 0, 0.0};
+      if (!json_int(t, b, e, "block", &q.block) || !json_int(t, b, e, "ring", &q.ring) ||
+          !json_int(t, b, e, "window", &q.window) ||
+          !json_int(t, b, e, "est_variant", &q.est_variant) ||
+          !json_int(t, b, e, "gate_grid", &q.gate_grid))
+        return fail(SKM_EINVAL, "tile entry lacks a field");
+      if (q.est_variant < 0 || q.est_variant > 3 || q.gate_grid < 8 || q.gate_grid > 4096 ||
+          q.gate_grid % 8)
+        return fail(SKM_EINVAL, "tile entry out of range");
+      tiles.push_back(q);
+      b = t.find('{', e);
     }
   }
-  c->batch_streams = bs;
-  c->use_graphs = bg != 0;
-  c->gate_grid = bgg;
-  if (best_ms) *best_ms = best;
+  c->batch_mode = mode;
+  c->batch_streams = streams;
+  c->use_graphs = graphs != 0;
+  c->gate_grid = gate;
+  c->tiles = tiles;
   return SKM_OK;
 }
 

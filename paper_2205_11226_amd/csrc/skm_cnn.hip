@@ -693,6 +693,129 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
   }
 }
 
+// The gate over every frame of a batch (same block size and ring): as
+// k_cnn_gate, with the items (frame, lost block) of all frames split among
+// the workgroups by XCD eighths.  The weights are loaded once per workgroup
+// for all its blocks.  Each workgroup adds its blocks to the context rule of
+// their frame when it moves to the next frame.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_gate_b(
+    BatchArgs b, DevParams p, const uint4* pk, const float* wq, float tau1, float tau2) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ int red[kThreads / 64][4];
+  GateLds& G = *reinterpret_cast<GateLds*>(lds_raw);
+  if (b.bs->remaining == 0) return;
+  if (blockIdx.x == 0)
+    for (int f = threadIdx.x; f < b.nf; f += kThreads) b.a0.st[f].n_hql = 0;
+  const int total = b.bs->total;
+  const int per8 = (total + 7) >> 3, xcd = blockIdx.x & 7;
+  const int xend = min(total, (xcd + 1) * per8);
+  const int pw = (per8 + (int)(gridDim.x >> 3) - 1) / (int)(gridDim.x >> 3);
+  const int g_begin = min(xend, xcd * per8 + (int)(blockIdx.x >> 3) * pw);
+  const int g_end = min(xend, g_begin + pw);
+  if (g_begin >= g_end) return;
+  gate_clear_padding(G);
+  const GateWeights W = load_gate_weights(pk, wq);
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  const int b0 = kP / 2 - p.B / 2, b1 = b0 + p.B, f0 = b0 - p.r, f1 = b1 + p.r;
+  const int rB = p.r * p.B;
+  constexpr int kPer = (kS * kS + kThreads - 1) / kThreads;
+  int v[kPer][4];
+  auto load_block = [&](const FrameArgs& a, int blk) {
+    const int cell = a.blk[blk];
+    const int by = cell / p.gw, bx = cell - by * p.gw;
+    const int gy0 = by * p.B + p.B / 2 - kP / 2, gx0 = bx * p.B + p.B / 2 - kP / 2;
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int idx = tid + t * kThreads;
+      const int Y = idx / kS, X = idx - Y * kS;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gy = gy0 + 2 * Y + (q >> 1), gx = gx0 + 2 * X + (q & 1);
+        const bool in = idx < kS * kS && gy >= 0 && gy < p.height && gx >= 0 && gx < p.width;
+        const int cy = min(max(gy, 0), p.height - 1), cx = min(max(gx, 0), p.width - 1);
+        const int val = a.val[(size_t)cy * p.width + cx];
+        v[t][q] = in ? val : -1;
+      }
+    }
+  };
+  // frame of the prefetched item (fn) and of the current one (fc)
+  int fn = frame_of(b.cum, b.nf, g_begin);
+  FrameArgs an = batch_frame(b, fn);
+  int nx_state = 1;
+  {
+    const int i = g_begin - b.cum[fn];
+    load_block(an, i);
+    nx_state = an.st->remaining ? an.bstate[i] : 1;
+  }
+  int fc = -1;
+  FrameArgs ac = an;
+  int wg_nq = 0, wg_max = 0;
+  for (int g = g_begin; g < g_end; ++g) {
+    if (fn != fc) {
+      if (fc >= 0 && tid == 0) note_context_rule(ac.st, wg_nq, wg_max);
+      wg_nq = 0; wg_max = 0;
+      fc = fn;
+      ac = an;
+    }
+    const int i = g - b.cum[fc];
+    const bool pending = nx_state == 0;
+    if (pending) {
+      int c = 0, sum = 0, vmin = 255, vmax = 0;
+#pragma unroll
+      for (int t = 0; t < kPer; ++t) {
+        const int idx = tid + t * kThreads;
+        if (idx < kS * kS) {
+          const int Y = idx / kS, X = idx - Y * kS;
+          G.in[(Y + 1) * kIn + X + 1] = s2d_pixel(v[t]);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int wy = 2 * Y + (q >> 1), wx = 2 * X + (q & 1);
+            const bool ctx = wy >= f0 && wy < f1 && wx >= f0 && wx < f1;
+            const bool own = wy >= b0 && wy < b1 && wx >= b0 && wx < b1;
+            if (ctx && v[t][q] >= 0) {
+              c += own ? 1 + (1 << 16) : 1;
+              sum += v[t][q]; vmin = min(vmin, v[t][q]); vmax = max(vmax, v[t][q]);
+            }
+          }
+        }
+      }
+      c = wave_sum(c); sum = wave_sum(sum); vmin = wave_min(vmin); vmax = wave_max(vmax);
+      if (lane == 0) { red[wave][0] = c; red[wave][1] = sum; red[wave][2] = vmin; red[wave][3] = vmax; }
+    }
+    __syncthreads();
+    if (pending && tid == 0) {
+      int c = 0, sum = 0, vmin = 255, vmax = 0;
+      for (int w = 0; w < kThreads / 64; ++w) {
+        c += red[w][0]; sum += red[w][1]; vmin = min(vmin, red[w][2]); vmax = max(vmax, red[w][3]);
+      }
+      const int nown = c >> 16;
+      c &= 0xffff;
+      ac.m0cnt[i] = c | (nown > 0 ? kPartialBit : 0);
+      ac.ring[i] = make_int2(sum, vmin | (vmax << 16));
+      wg_nq += c >= rB;
+      wg_max = max(wg_max, c);
+    }
+    if (g + 1 < g_end) {
+      if (g + 1 >= b.cum[fn + 1]) {
+        while (g + 1 >= b.cum[fn + 1]) ++fn;
+        an = batch_frame(b, fn);
+      }
+      const int in = g + 1 - b.cum[fn];
+      load_block(an, in);
+      nx_state = an.st->remaining ? an.bstate[in] : 1;
+    }
+    if (!pending) continue;
+    float y0 = 0.0f, y1 = 0.0f;
+    gate_network(G, W, y0, y1);
+    if (tid == 0) {
+      ac.gate[i] = (int8_t)(y0 <= tau1 ? SKM_LAYER_BRL : (y1 > tau2 ? SKM_LAYER_HQL : SKM_LAYER_IDL));
+      if (ac.gate_pred) { ac.gate_pred[2 * i] = y0; ac.gate_pred[2 * i + 1] = y1; }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) note_context_rule(ac.st, wg_nq, wg_max);
+}
+
 // Batched inference on prepared inputs x (bf16 bits [n][8][24][24]).
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_infer(
     const uint16_t* x, int n, const uint4* pk, const float* wq, float* y) {
@@ -751,6 +874,13 @@ hipError_t launch_cnn_gate(const FrameArgs& a, const DevParams& p, const uint4* 
   return hipGetLastError();
 }
 
+hipError_t launch_cnn_gate_b(const BatchArgs& b, const DevParams& p, const uint4* pk,
+                             const float* wq, float tau1, float tau2, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_cnn_gate_b, dim3(cnn_gate_grid(grid)), dim3(kThreads), sizeof(GateLds), s,
+                     b, p, pk, wq, tau1, tau2);
+  return hipGetLastError();
+}
+
 hipError_t cnn_infer(const uint16_t* x, int n, const uint4* pk, const float* wq, float* y,
                      hipStream_t s) {
   hipLaunchKernelGGL(k_cnn_infer, dim3(n > kInferGrid ? kInferGrid : n), dim3(kThreads),
@@ -770,6 +900,9 @@ size_t cnn_gate_lds_bytes() { return sizeof(GateLds); }
 hipError_t set_cnn_gate_lds_limit(size_t bytes) {
   hipError_t e = hipFuncSetAttribute((const void*)k_cnn_gate,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_cnn_gate_b, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)bytes);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_cnn_infer, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)bytes);

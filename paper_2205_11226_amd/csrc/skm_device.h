@@ -22,6 +22,17 @@ static __device__ __forceinline__ int xcd_block(int wg, int n) {
   return ((wg >> 3) < per && i < n) ? i : -1;
 }
 
+// Batched kernels: frame of item (or workgroup) g, the largest f with
+// begin[f] <= g (begin is non-decreasing with begin[0] = 0).
+static __device__ __forceinline__ int frame_of(const int* begin, int nf, int g) {
+  int lo = 0, hi = nf - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 static __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
 static __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }

@@ -25,6 +25,10 @@ namespace skm {
 
 struct HqlLayout {
   size_t yt, xt, cyy, axy, v, v0, y0, meany, meanx, dm0, ytil, xtil, vn, dch, zch, i0;
+  // partly known contexts (hql_partial): availability bytes, overlap counts,
+  // integer Grams of the masks (gn), of values by masks (gs, gsx), and a copy
+  // of C_YY for the repair's retries
+  size_t ot, cn, gn, gs, gsx, cyy0;
   size_t total;
   int ldm;     // leading dimension (candidates) of yt / xt, multiple of 64
   int ldz;     // row length of zch: B^2 + NY
@@ -56,6 +60,13 @@ __host__ __device__ inline HqlLayout hql_layout(const DevParams& p) {
   h.dch = take(8 * 64 * MC);
   h.zch = take(8 * 64 * (B2 + NY));
   h.i0 = take(4 * MC);
+  const bool pt = p.hql_partial != 0;
+  h.ot = take(pt ? NY * h.ldm : 0);
+  h.cn = take(pt ? 4 * MC : 0);
+  h.gn = take(pt ? 4 * NY * NY : 0);
+  h.gs = take(pt ? 4 * NY * NY : 0);
+  h.gsx = take(pt ? 4 * B2 * NY : 0);
+  h.cyy0 = take(pt ? 8 * NY * NY : 0);
   h.total = o;
   return h;
 }
@@ -80,6 +91,11 @@ size_t hql_lds_bytes(const DevParams& p) {
   need = need > 8 * ny ? need : 8 * ny;                     // Cholesky pivot row
   return align_up(offs[9] + need, 16);
 }
+
+// PSD repair of a pairwise-complete C_YY: lambda x 10, at most this often
+constexpr int kPsdRepair = 6;
+__device__ __constant__ const double kPow10[kPsdRepair + 1] = {1.0, 10.0, 100.0, 1e3, 1e4, 1e5,
+                                                                1e6};
 
 // eps_y values within this relative margin count as equal: where eps_y is
 // flat (as beta -> 0 the weights become one-hot on the nearest candidate), the
@@ -173,6 +189,60 @@ static __device__ void gram_cov(const uint8_t* P, const uint8_t* Q, int R1, int 
   __syncthreads();
 }
 
+// Exact integer Gram P Q^T (rows of P and Q are R1 and R2 byte vectors of
+// length ld, zero padded) stored as Out, without normalisation: the tiles of
+// gram_cov.
+template <typename Out>
+static __device__ void gram_raw(const uint8_t* P, const uint8_t* Q, int R1, int R2, int ld,
+                                Out* out, int ldo, bool sym, uint32_t* ta, uint32_t* tb) {
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  const int nt1 = (R1 + 63) / 64, nt2 = (R2 + 63) / 64;
+  for (int t1 = 0; t1 < nt1; ++t1) {
+    for (int t2 = 0; t2 < nt2; ++t2) {
+      if (sym && t2 > t1) continue;
+      uint32_t acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0u;
+      for (int kk = 0; kk < ld; kk += 64) {
+        for (int e = tid; e < 64 * 16; e += kThreads) {
+          const int row = e >> 4, w = e & 15;
+          const int r1 = t1 * 64 + row, r2 = t2 * 64 + row;
+          ta[row * 17 + w] = r1 < R1 ? *(const uint32_t*)(P + (size_t)r1 * ld + kk + 4 * w) : 0u;
+          tb[row * 17 + w] = r2 < R2 ? *(const uint32_t*)(Q + (size_t)r2 * ld + kk + 4 * w) : 0u;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int w = 0; w < 16; ++w) {
+          uint32_t av[4], bv[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) av[a] = ta[(ty * 4 + a) * 17 + w];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) bv[b] = tb[(tx * 4 + b) * 17 + w];
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_udot4(av[a], bv[b], acc[a][b], false);
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int i = t1 * 64 + ty * 4 + a, j = t2 * 64 + tx * 4 + b;
+          if (i < R1 && j < R2) {
+            out[(size_t)i * ldo + j] = (Out)acc[a][b];
+            if (sym) out[(size_t)j * ldo + i] = (Out)acc[a][b];
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // One evaluation of eps_y(beta) (eq. epsy): weights e_j = exp(-dm0_j/(2 beta)
 // - max), S = sum e_j, y~ = sum e_j y_j / S; returns ||y0 - y~||^2.  Leaves
 // ew, S (in hs.S) and ytil for the caller.  With xt != nullptr also x~.
@@ -243,15 +313,13 @@ static __device__ double eval_eps(double beta, int Mc, int Ny, int B2, int ldm, 
   return block_sum_d(part, hs.red);
 }
 
-__global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsigned char* ws,
-                                                  size_t slot_bytes) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  __shared__ BlockShared sh;
-  __shared__ HqlShared hs;
-  RoundState* st = a.st;
-  if (st->remaining == 0) return;
-  const int n_hql = st->n_hql, round = st->round;
-  if ((int)blockIdx.x >= n_hql) return;
+// The HQL blocks h = blockIdx.x, blockIdx.x + gridDim.x, ... of one frame's
+// list (n_hql entries).  `first` is true until the workgroup has taken a
+// block (from any frame).
+static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevParams& p,
+                                                 unsigned char* ws, size_t slot_bytes, int round,
+                                                 int n_hql, bool& first, unsigned char* lds_raw,
+                                                 BlockShared& sh, HqlShared& hs) {
   const MainLds L = carve_main_lds(lds_raw, p);
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   const int B = p.B, r = p.r, W = p.W, Wd = p.Wd;
@@ -281,6 +349,13 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
   double* dch = (double*)(slot + hl.dch);
   double* zch = (double*)(slot + hl.zch);
   int* i0l = (int*)(slot + hl.i0);
+  const bool hp = p.hql_partial != 0;                 // partly known contexts (see hql_layout)
+  uint8_t* ot = slot + hl.ot;
+  int* cnl = (int*)(slot + hl.cn);
+  int* gn = (int*)(slot + hl.gn);
+  int* gs = (int*)(slot + hl.gs);
+  int* gsx = (int*)(slot + hl.gsx);
+  double* cyy0 = (double*)(slot + hl.cyy0);
   const int ldm = hl.ldm, ldz = hl.ldz, NRs = hl.ny;      // NRs: row stride of Ny rows
 
   // LDS reuse once the window has been gathered
@@ -304,10 +379,11 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
     // -- candidates: the estimation kernel's phases, then the complete ones.
     //    Staging ORs the window's availability into rowbits, so a workgroup
     //    that takes several blocks clears it for each one.
-    if (h != (int)blockIdx.x) {
+    if (!first) {
       for (int k = tid; k < 2 * Wd; k += kThreads) L.rowbits[k] = 0ull;
       __syncthreads();
     }
+    first = false;
     phase_stage(a, p, L, x0 - r - W, y0 - r - W);
     // context units: the ring, then the block's own pixel pairs if it holds
     // received pixels
@@ -324,8 +400,11 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
       for (int j = j0; j < j1; ++j) {
         int d, n;
         cand_distance(L, cand_off(L.cand[j]), NUe, d, n);
-        const bool comp = n == n0 && n >= nmin;
+        // HQL's candidates: complete contexts, or (hql_partial) every
+        // admissible one, its overlap count kept for the I0 order
+        const bool comp = (hp || n == n0) && n >= nmin;
         L.ell[j] = comp ? (double)d : -1.0;
+        if (hp) L.cand[j] = (L.cand[j] & 0x3ffffu) | ((uint32_t)n << 18);
         cnt += comp;
       }
       int tot = 0;
@@ -334,6 +413,7 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
         if (L.ell[j] >= 0.0) {
           compo[pos] = (uint16_t)cand_off(L.cand[j]);
           compd[pos] = (int)L.ell[j];
+          if (hp) cnl[pos] = cand_n(L.cand[j]);
           ++pos;
         }
       }
@@ -365,11 +445,16 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
     __syncthreads();
     const int Mc = sh.M, Ny = n0;
 
-    // -- gather Y (Ny x Mc), X (B2 x Mc) as bytes, zero padded to ldm; y0
+    // -- gather Y (Ny x Mc), X (B2 x Mc) as bytes, zero padded to ldm; y0.
+    //    Unknown context pixels of a candidate (hql_partial) read 0, with
+    //    availability 0 in ot.
     for (int aa = wave; aa < Ny; aa += kThreads / 64) {
       const int off = m0off[aa];
-      for (int k = lane; k < ldm; k += 64)
-        yt[(size_t)aa * ldm + k] = k < Mc ? (uint8_t)(L.winp[compo[k] + off] & 0xffu) : (uint8_t)0;
+      for (int k = lane; k < ldm; k += 64) {
+        const int v = k < Mc ? (int)(int16_t)(L.winp[compo[k] + off] & 0xffffu) : -1;
+        yt[(size_t)aa * ldm + k] = v >= 0 ? (uint8_t)v : (uint8_t)0;
+        if (hp) ot[(size_t)aa * ldm + k] = v >= 0 ? (uint8_t)1 : (uint8_t)0;
+      }
     }
     for (int q = wave; q < B2; q += kThreads / 64) {
       const int off = (r + q / B) * Wd + r + (q % B);
@@ -379,59 +464,115 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
     for (int aa = tid; aa < Ny; aa += kThreads)
       y0v[aa] = (double)(int)(int16_t)(L.winp[qbase + m0off[aa]] & 0xffffu);
     __syncthreads();
-    // column means: a wave per row, exact integer sums
-    for (int aa = wave; aa < Ny; aa += kThreads / 64) {
-      int s = 0;
-      for (int k = lane; k < Mc; k += 64) s += yt[(size_t)aa * ldm + k];
-      s = wave_sum(s);
-      if (lane == 0) meany[aa] = (double)s / (double)Mc;
-    }
-    for (int q = wave; q < B2; q += kThreads / 64) {
-      int s = 0;
-      for (int k = lane; k < Mc; k += 64) s += xt[(size_t)q * ldm + k];
-      s = wave_sum(s);
-      if (lane == 0) meanx[q] = (double)s / (double)Mc;
-    }
-    __syncthreads();
+    if (!hp) {
+      // column means: a wave per row, exact integer sums
+      for (int aa = wave; aa < Ny; aa += kThreads / 64) {
+        int s = 0;
+        for (int k = lane; k < Mc; k += 64) s += yt[(size_t)aa * ldm + k];
+        s = wave_sum(s);
+        if (lane == 0) meany[aa] = (double)s / (double)Mc;
+      }
+      for (int q = wave; q < B2; q += kThreads / 64) {
+        int s = 0;
+        for (int k = lane; k < Mc; k += 64) s += xt[(size_t)q * ldm + k];
+        s = wave_sum(s);
+        if (lane == 0) meanx[q] = (double)s / (double)Mc;
+      }
+      __syncthreads();
 
-    // -- covariance blocks C_YY (Ny x Ny) and C_XY (B2 x Ny), 1/M normalised
-    gram_cov(yt, yt, Ny, Ny, ldm, Mc, cyy, NRs, meany, meany, true, ta, tb);
-    gram_cov(xt, yt, B2, Ny, ldm, Mc, axy, NRs, meanx, meany, false, ta, tb);
+      // -- covariance blocks C_YY (Ny x Ny) and C_XY (B2 x Ny), 1/M normalised
+      gram_cov(yt, yt, Ny, Ny, ldm, Mc, cyy, NRs, meany, meany, true, ta, tb);
+      gram_cov(xt, yt, B2, Ny, ldm, Mc, axy, NRs, meanx, meany, false, ta, tb);
+    } else {
+      // -- pairwise-complete covariance: for coordinates a, b the candidates
+      //    knowing both (N_ab of them); exact integer Grams of the values
+      //    (unknown = 0) and of the availability, then
+      //    C_ab = G_ab / N_ab - S_a(b) S_b(a) / N_ab^2 with S_a(b) the sum of
+      //    coordinate a over those candidates (0 where N_ab = 0).  The x
+      //    coordinates are always known: N_qb = N_bb.
+      gram_raw(yt, yt, Ny, Ny, ldm, cyy, NRs, true, ta, tb);
+      gram_raw(ot, ot, Ny, Ny, ldm, gn, Ny, true, ta, tb);
+      gram_raw(yt, ot, Ny, Ny, ldm, gs, Ny, false, ta, tb);
+      gram_raw(xt, yt, B2, Ny, ldm, axy, NRs, false, ta, tb);
+      gram_raw(xt, ot, B2, Ny, ldm, gsx, Ny, false, ta, tb);
+      for (int e = tid; e < Ny * Ny; e += kThreads) {
+        const int aa = e / Ny, bb = e - aa * Ny;
+        const double n = (double)gn[e];
+        double* c = cyy + (size_t)aa * NRs + bb;
+        const double v = n > 0.0 ? *c / n - ((double)gs[e] * (double)gs[bb * Ny + aa]) / (n * n)
+                                 : 0.0;
+        *c = v;
+        cyy0[e] = v;
+      }
+      for (int e = tid; e < B2 * Ny; e += kThreads) {
+        const int q = e / Ny, bb = e - q * Ny;
+        const double n = (double)gn[bb * Ny + bb];
+        double* c = axy + (size_t)q * NRs + bb;
+        *c = n > 0.0 ? *c / n - ((double)gsx[e] / n) * ((double)gs[bb * Ny + bb] / n) : 0.0;
+      }
+      __syncthreads();
+      // -- unknown context pixels of a candidate: the coordinate's mean over
+      //    the candidates knowing it, rounded half up (y0's pixel if none)
+      for (int aa = wave; aa < Ny; aa += kThreads / 64) {
+        const int n = gn[aa * Ny + aa], sm = gs[aa * Ny + aa];
+        const int fill = n > 0 ? (2 * sm + n) / (2 * n) : (int)y0v[aa];
+        for (int k = lane; k < Mc; k += 64)
+          if (!ot[(size_t)aa * ldm + k]) yt[(size_t)aa * ldm + k] = (uint8_t)fill;
+      }
+      __syncthreads();
+    }
 
-    // -- ridge and Cholesky C_YY = L L^T (left-looking, in place, lower)
+    // -- ridge and Cholesky C_YY = L L^T (left-looking, in place, lower).
+    //    A pairwise-complete C_YY (hql_partial) need not be positive
+    //    semi-definite: while a pivot is <= 0 the factorisation restarts
+    //    from the saved C_YY with lambda ten times larger, at most
+    //    kPsdRepair times.
+    double lam0;
     {
       double tr = 0.0;
       for (int aa = tid; aa < Ny; aa += kThreads) tr += cyy[(size_t)aa * NRs + aa];
       tr = block_sum_d(tr, hs.red);
-      const double lam = p.ridge_rel * tr / (double)Ny + 1e-12;
+      lam0 = p.ridge_rel * tr / (double)Ny + 1e-12;
+    }
+    for (int rep = 0; rep <= (hp ? kPsdRepair : 0); ++rep) {
+      if (rep > 0) {
+        __syncthreads();
+        for (int e = tid; e < Ny * Ny; e += kThreads) {
+          const int aa = e / Ny, bb = e - aa * Ny;
+          cyy[(size_t)aa * NRs + bb] = cyy0[e];
+        }
+        __syncthreads();
+      }
+      const double lam = lam0 * kPow10[rep];
       for (int aa = tid; aa < Ny; aa += kThreads) cyy[(size_t)aa * NRs + aa] += lam;
       if (tid == 0) hs.fail = 0;
       __syncthreads();
-    }
-    for (int k = 0; k < Ny; ++k) {
-      const double* rowk = cyy + (size_t)k * NRs;
-      for (int m = tid; m < k; m += kThreads) piv[m] = rowk[m];
-      if (wave == 0) {
-        double s = 0.0;
-        for (int m = lane; m < k; m += 64) s += rowk[m] * rowk[m];
-        s = wave_sum(s);
-        if (lane == 0) {
-          const double dd = rowk[k] - s;
-          if (!(dd > 0.0)) hs.fail = 1;
-          hs.dk = dd > 0.0 ? sqrt(dd) : 1.0;
-          cyy[(size_t)k * NRs + k] = hs.dk;
+      for (int k = 0; k < Ny; ++k) {
+        const double* rowk = cyy + (size_t)k * NRs;
+        for (int m = tid; m < k; m += kThreads) piv[m] = rowk[m];
+        if (wave == 0) {
+          double s = 0.0;
+          for (int m = lane; m < k; m += 64) s += rowk[m] * rowk[m];
+          s = wave_sum(s);
+          if (lane == 0) {
+            const double dd = rowk[k] - s;
+            if (!(dd > 0.0)) hs.fail = 1;
+            hs.dk = dd > 0.0 ? sqrt(dd) : 1.0;
+            cyy[(size_t)k * NRs + k] = hs.dk;
+          }
         }
+        __syncthreads();
+        if (hs.fail) break;                 // uniform: written before the barrier
+        const double dk = hs.dk;
+        for (int ii = k + 1 + tid; ii < Ny; ii += kThreads) {
+          double* rowi = cyy + (size_t)ii * NRs;
+          double s = rowi[k];
+          for (int m = 0; m < k; ++m) s -= rowi[m] * piv[m];
+          rowi[k] = s / dk;
+        }
+        __syncthreads();
       }
-      __syncthreads();
-      if (hs.fail) break;                 // uniform: written before the barrier
-      const double dk = hs.dk;
-      for (int ii = k + 1 + tid; ii < Ny; ii += kThreads) {
-        double* rowi = cyy + (size_t)ii * NRs;
-        double s = rowi[k];
-        for (int m = 0; m < k; ++m) s -= rowi[m] * piv[m];
-        rowi[k] = s / dk;
-      }
-      __syncthreads();
+      if (!hs.fail) break;
     }
     if (hs.fail) {
       // C_YY + lambda I is not positive definite in FP64 (a pivot <= 0): the
@@ -541,24 +682,30 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
 
     // -- I0: the min(Ny + 1, Mc) candidates of smallest (distance, index),
     //    found by bisection on the packed key; listed in candidate order
+    //    (hql_partial: of smallest d / n, as floor(d 2^20 / n), which keeps
+    //    the order of the fractions: distinct ones differ by >= 2^20 / n^2 > 3)
     const int k0 = min(Ny + 1, Mc);
     {
-      long long lo = 0, hi = (1ll << 40) - 1;
+      auto key = [&](int j) -> long long {
+        const long long d = compd[j];
+        return (hp ? (d << 20) / cnl[j] : d) << 13 | j;
+      };
+      long long lo = 0, hi = hp ? (1ll << 60) - 1 : (1ll << 40) - 1;
       while (lo < hi) {
         const long long mid = lo + ((hi - lo) >> 1);
         int c = 0;
-        for (int j = tid; j < Mc; j += kThreads) c += ((long long)compd[j] << 13 | j) <= mid;
+        for (int j = tid; j < Mc; j += kThreads) c += key(j) <= mid;
         c = (int)block_sum_d((double)c, hs.red);
         if (c >= k0) hi = mid; else lo = mid + 1;
       }
       const int per = (Mc + kThreads - 1) / kThreads;
       const int j0 = min(Mc, tid * per), j1 = min(Mc, j0 + per);
       int cnt = 0;
-      for (int j = j0; j < j1; ++j) cnt += ((long long)compd[j] << 13 | j) <= lo;
+      for (int j = j0; j < j1; ++j) cnt += key(j) <= lo;
       int tot = 0;
       int pos = block_excl_scan(cnt, sh.scan, &tot);
       for (int j = j0; j < j1; ++j)
-        if (((long long)compd[j] << 13 | j) <= lo) i0l[pos++] = j;
+        if (key(j) <= lo) i0l[pos++] = j;
       __syncthreads();
     }
 
@@ -713,6 +860,45 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
   }
 }
 
+__global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsigned char* ws,
+                                                  size_t slot_bytes) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ BlockShared sh;
+  __shared__ HqlShared hs;
+  const RoundState* st = a.st;
+  if (st->remaining == 0) return;
+  const int n_hql = st->n_hql;
+  if ((int)blockIdx.x >= n_hql) return;
+  bool first = true;
+  hql_frame(a, p, ws, slot_bytes, st->round, n_hql, first, lds_raw, sh, hs);
+}
+
+// Every frame of a batch in turn: the workgroups (one scratch slot each)
+// share each frame's HQL list.
+__global__ __launch_bounds__(kThreads) void k_hql_b(BatchArgs b, DevParams p, unsigned char* ws,
+                                                    size_t slot_bytes) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ BlockShared sh;
+  __shared__ HqlShared hs;
+  if (b.bs->remaining == 0) return;
+  bool first = true;
+  for (int f = 0; f < b.nf; ++f) {
+    const RoundState* st = b.a0.st + f;
+    if (st->remaining == 0) continue;
+    const int n_hql = st->n_hql;
+    if ((int)blockIdx.x >= n_hql) continue;
+    if (!first) __syncthreads();
+    hql_frame(batch_frame(b, f), p, ws, slot_bytes, st->round, n_hql, first, lds_raw, sh, hs);
+  }
+}
+
+hipError_t launch_hql_b(const BatchArgs& b, const DevParams& p, unsigned char* ws,
+                        size_t slot_bytes, int slots, hipStream_t s) {
+  hipLaunchKernelGGL(k_hql_b, dim3(slots), dim3(kThreads), hql_lds_bytes(p), s, b, p, ws,
+                     slot_bytes);
+  return hipGetLastError();
+}
+
 hipError_t launch_hql(const FrameArgs& a, const DevParams& p, unsigned char* ws, size_t slot_bytes,
                       int slots, hipStream_t s) {
   hipLaunchKernelGGL(k_hql, dim3(slots), dim3(kThreads), hql_lds_bytes(p), s, a, p, ws, slot_bytes);
@@ -720,7 +906,10 @@ hipError_t launch_hql(const FrameArgs& a, const DevParams& p, unsigned char* ws,
 }
 
 hipError_t set_hql_lds_limit(size_t bytes) {
-  return hipFuncSetAttribute((const void*)k_hql, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void*)k_hql, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_hql_b, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)bytes);
 }
 

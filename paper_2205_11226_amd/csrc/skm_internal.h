@@ -42,6 +42,7 @@ struct DevParams {
   // first schedule radius >= rho), word rho / 16
   unsigned long long bucket_lut[3];
   int min_pct, min_hql, mode;
+  int hql_partial; // HQL over every admissible candidate (partly known contexts completed)
   int prep_grid;   // workgroups of the round preparation (prep kernel, or the gate in CNN mode)
   int cnn_active;  // CNN mode with a loaded network (else the profile rule)
   int width, height, stride;
@@ -101,6 +102,76 @@ struct FrameArgs {
   int* cnt;
   int cap;                // capacity of info / xhat in blocks
 };
+
+// ------------------------------------------------------------ batching
+// Frames of equal size and parameters are concealed together: every stage of
+// the pipeline is one launch over the (frame, lost block) items of all of
+// them, with per-frame state as in the single-frame pipeline.  The frames'
+// workspaces are equal slices of one allocation, so frame f's FrameArgs are
+// frame 0's plus f strides, with the caller's buffers from a table.
+struct BatchState {
+  int total;               // lost blocks of all frames (items), written by k_init_b
+  int remaining;           // pending blocks of all frames at the start of the next round
+  int err;                 // OR of the frames' error bits
+  unsigned frames_done;    // k_init_b: frames listed so far (zero between launches)
+  unsigned fin_ticket;     // k_round_finalize_b: workgroups done (zero between launches)
+  int pad[3];
+};
+
+struct FrameIO {           // the caller's buffers of one frame
+  const uint8_t* frame;
+  const uint8_t* mask;
+  uint8_t* out;
+  skm_block_info* info;
+  float* xhat;
+  int cap;
+  int pad;
+};
+
+struct BatchArgs {
+  FrameArgs a0;            // frame 0's workspace (its caller buffers unused)
+  size_t val_stride;       // int16 elements between consecutive value planes
+  int cell_stride;         // entries between consecutive block tables
+  int bits_stride;         // words between consecutive cell bit tables
+  int nf;
+  const FrameIO* io;       // [nf]
+  int* cum;                // [nf + 1] lost blocks of the frames before f (k_init_b)
+  BatchState* bs;
+  BatchState* hbs;         // host-visible copy (pinned), written where bs is published
+};
+
+// FrameArgs of frame f of a batch
+__host__ __device__ inline FrameArgs batch_frame(const BatchArgs& b, int f) {
+  FrameArgs a = b.a0;
+  a.val += (size_t)f * b.val_stride;
+  a.cellbits += (size_t)f * b.bits_stride;
+  const size_t c = (size_t)f * b.cell_stride;
+  a.blk += c; a.bstate += c; a.m0cnt += c; a.ring += c; a.hql_list += c;
+  a.gate += c; a.gate_pred += 2 * c;
+  a.st += f;
+  if (a.hstate) a.hstate += f;
+  const FrameIO& io = b.io[f];
+  a.frame = io.frame; a.mask = io.mask; a.work = io.out;
+  a.info = io.info; a.xhat = io.xhat; a.cap = io.cap;
+  return a;
+}
+
+// geometry workgroups of one frame (k_init grid)
+__host__ __device__ inline int init_wg_x(const DevParams& p) { return (p.width + 4 * kThreads - 1) / (4 * kThreads); }
+__host__ __device__ inline int init_wgs(const DevParams& p) { return init_wg_x(p) * ((p.height + p.B - 1) / p.B); }
+
+// batched launchers (every frame has the parameters and size of p)
+hipError_t launch_init_b(const BatchArgs& b, const DevParams& p, hipStream_t s);
+hipError_t launch_prep_b(const BatchArgs& b, const DevParams& p, int grid, hipStream_t s);
+hipError_t launch_est_b(const BatchArgs& b, const DevParams& p, int variant, hipStream_t s);
+hipError_t launch_finalize_b(const BatchArgs& b, const DevParams& p, int grid, hipStream_t s);
+hipError_t launch_cnn_gate_b(const BatchArgs& b, const DevParams& p, const uint4* pk,
+                             const float* wq, float tau1, float tau2, int grid, hipStream_t s);
+hipError_t launch_hql_b(const BatchArgs& b, const DevParams& p, unsigned char* ws,
+                        size_t slot_bytes, int slots, hipStream_t s);
+// estimation kernel variants for p's geometry (candidate slices per thread),
+// the first being the default; returns the count written to out (<= 4)
+int est_variants(const DevParams& p, int* out);
 
 // launchers (skm_kernels.hip)
 hipError_t launch_init(const FrameArgs& a, const DevParams& p, hipStream_t s);

@@ -25,13 +25,14 @@ namespace skm {
 
 // Host-visible copy of the frame state (pinned, coherent host memory): the
 // host reads it after synchronizing the stream instead of a copy node.
-__device__ __forceinline__ void publish_state(const FrameArgs& a) {
-  if (!a.hstate) return;
-  const RoundState* st = a.st;
-  RoundState* h = a.hstate;
+__device__ __forceinline__ void publish_state_to(const RoundState* st, RoundState* h) {
+  if (!h) return;
   h->n_lost = st->n_lost; h->remaining = st->remaining; h->round = st->round;
   h->err = st->err; h->n_hql = st->n_hql;
   h->n_avail = st->n_avail; h->sum_avail = st->sum_avail;
+}
+__device__ __forceinline__ void publish_state(const FrameArgs& a) {
+  publish_state_to(a.st, a.hstate);
 }
 
 // Loss geometry, one pass over the frame.  Grid (ceil(width/1024), bands of
@@ -44,12 +45,14 @@ __device__ __forceinline__ void publish_state(const FrameArgs& a) {
 // Lost cells are ORed into a bit table with device-scope atomics (coherent
 // across XCDs without a cache flush); the workgroup that finishes last lists
 // them in raster order, clears the table and starts the frame state.
-__global__ __launch_bounds__(kThreads) void k_init(FrameArgs a, DevParams p) {
+// Workgroup (wgx, band) of a frame whose geometry pass has nwg workgroups;
+// returns true in the workgroup that finished the frame (it listed the cells).
+static __device__ bool init_body(const FrameArgs& a, const DevParams& p, int wgx, int band,
+                                 unsigned nwg) {
   __shared__ int s_scan[kThreads / 64];
   __shared__ int s_last;
   const int lane = lane_id(), wave = wave_id(), tid = threadIdx.x;
-  const int x = (blockIdx.x * kThreads + tid) * 4;
-  const int band = blockIdx.y;
+  const int x = (wgx * kThreads + tid) * 4;
   const int B = p.B;
   const int y0 = band * B;
   const int rows = min(B, p.height - y0);
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(kThreads) void k_init(FrameArgs a, DevParams p) {
     if (lm | lm_hi) {
       // this wave's cells are consecutive from cell cb: 256 / B of them, bit
       // k of the 128-bit run (lo, hi) for cell cb + k
-      const int cb = band * p.gw + (blockIdx.x * kThreads + wave * 64) * 4 / B;
+      const int cb = band * p.gw + (wgx * kThreads + wave * 64) * 4 / B;
       uint64_t lo = lm, hi = 0;
       if (B == 2) {
         lo = 0;
@@ -150,11 +153,11 @@ __global__ __launch_bounds__(kThreads) void k_init(FrameArgs a, DevParams p) {
   __syncthreads();
   if (tid == 0) {
     const unsigned t = atomicAdd(&st->ticket, 1u);
-    s_last = t + 1 == gridDim.x * gridDim.y;
+    s_last = t + 1 == nwg;
     if (s_last) atomicExch(&st->ticket, 0u);
   }
   __syncthreads();
-  if (!s_last) return;
+  if (!s_last) return false;
 
   // ordered compaction: thread t takes a contiguous run of table words
   const int ncell = p.gh * p.gw, nw = (ncell + 31) >> 5;
@@ -203,9 +206,69 @@ __global__ __launch_bounds__(kThreads) void k_init(FrameArgs a, DevParams p) {
     st->ctx_nq = 0; st->ctx_max = 0;
     publish_state(a);
   }
+  return true;
+}
+
+__global__ __launch_bounds__(kThreads) void k_init(FrameArgs a, DevParams p) {
+  init_body(a, p, blockIdx.x, blockIdx.y, gridDim.x * gridDim.y);
 }
 
 // ------------------------------------------------------------- round prep
+// One wave per pending block: |m0| = known in-frame context pixels, with their
+// sum, minimum and maximum (the context mean and flatness of the BRL gate).
+// Each workgroup adds its (blocks with |m0| >= r B, largest |m0|) to the
+// round state's context rule (integer atomics, so the result is order-free).
+// One wave: context statistics of pending block i over its footprint (the
+// ring and the block's own received pixels; lost ones read -1), written to
+// m0cnt / ring; lane 0 adds the block to (nq, mx).
+static __device__ __forceinline__ void prep_one(const FrameArgs& a, const DevParams& p, int i,
+                                                int lane, int& my_nq, int& my_mx) {
+  const int F = p.F, B = p.B, r = p.r;
+  const int cell = a.blk[i];
+  const int by = cell / p.gw, bx = cell - by * p.gw;
+  const int xr = bx * B - r, yr = by * B - r;
+  int c = 0, sum = 0, vmin = 255, vmax = 0;
+  bool own = false;
+#pragma unroll
+  for (int fy0 = 0; fy0 < 2 * kMaxB; fy0 += 2) {     // two footprint rows per step, F <= 32
+    const int fy = fy0 + (lane >> 5), fx = lane & 31;
+    const int gy = yr + fy, gx = xr + fx;
+    const bool use = fy < F && fx < F && gy >= 0 && gy < p.height && gx >= 0 && gx < p.width;
+    const int cy = min(max(gy, 0), p.height - 1), cx = min(max(gx, 0), p.width - 1);
+    const int v = a.val[(size_t)cy * p.width + cx];
+    if (use && v >= 0) {
+      ++c; sum += v; vmin = min(vmin, v); vmax = max(vmax, v);
+      own = own || (fy >= r && fy < r + B && fx >= r && fx < r + B);
+    }
+  }
+  c = wave_sum(c);
+  sum = wave_sum(sum);
+  vmin = wave_min(vmin);
+  vmax = wave_max(vmax);
+  const bool partial = __ballot(own) != 0ull;
+  if (lane == 0) {
+    a.m0cnt[i] = c | (partial ? kPartialBit : 0);
+    a.ring[i] = make_int2(sum, vmin | (vmax << 16));
+    my_nq += c >= r * B;
+    my_mx = max(my_mx, c);
+  }
+}
+
+// Adds the per-wave (nq, mx) of a workgroup to the context rule of state st
+// (one call per workgroup; every thread of the workgroup calls it).
+static __device__ __forceinline__ void flush_context_rule(RoundState* st, int my_nq, int my_mx,
+                                                          int (*s_nq), int (*s_mx)) {
+  const int lane = lane_id(), wave = wave_id();
+  if (lane == 0) { s_nq[wave] = my_nq; s_mx[wave] = my_mx; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int nq = 0, mx = 0;
+    for (int w = 0; w < kThreads / 64; ++w) { nq += s_nq[w]; mx = max(mx, s_mx[w]); }
+    note_context_rule(st, nq, mx);
+  }
+  __syncthreads();
+}
+
 // One wave per pending block: |m0| = known in-frame context pixels, with their
 // sum, minimum and maximum (the context mean and flatness of the BRL gate).
 // Each workgroup adds its (blocks with |m0| >= r B, largest |m0|) to the
@@ -217,7 +280,6 @@ __global__ __launch_bounds__(kThreads) void k_round_prep(FrameArgs a, DevParams 
   if (blockIdx.x == 0 && threadIdx.x == 0) st->n_hql = 0;
   const int n_lost = st->n_lost;
   const int lane = lane_id(), wave = wave_id();
-  const int F = p.F, B = p.B, r = p.r;
   int my_nq = 0, my_mx = 0;
   // with a grid of whole XCD groups, XCD x takes the x-th contiguous eighth
   // of the blocks, as in the estimation kernel (its L2 then holds the rings)
@@ -231,44 +293,9 @@ __global__ __launch_bounds__(kThreads) void k_round_prep(FrameArgs a, DevParams 
   }
   for (int i = i0; i < i1; i += step) {
     if (a.bstate[i] != 0) continue;
-    const int cell = a.blk[i];
-    const int by = cell / p.gw, bx = cell - by * p.gw;
-    const int xr = bx * B - r, yr = by * B - r;
-    // context statistics over the footprint: the ring and the block's own
-    // received pixels (lost ones read -1)
-    int c = 0, sum = 0, vmin = 255, vmax = 0;
-    bool own = false;
-#pragma unroll
-    for (int fy0 = 0; fy0 < 2 * kMaxB; fy0 += 2) {     // two footprint rows per step, F <= 32
-      const int fy = fy0 + (lane >> 5), fx = lane & 31;
-      const int gy = yr + fy, gx = xr + fx;
-      const bool use = fy < F && fx < F && gy >= 0 && gy < p.height && gx >= 0 && gx < p.width;
-      const int cy = min(max(gy, 0), p.height - 1), cx = min(max(gx, 0), p.width - 1);
-      const int v = a.val[(size_t)cy * p.width + cx];
-      if (use && v >= 0) {
-        ++c; sum += v; vmin = min(vmin, v); vmax = max(vmax, v);
-        own = own || (fy >= r && fy < r + B && fx >= r && fx < r + B);
-      }
-    }
-    c = wave_sum(c);
-    sum = wave_sum(sum);
-    vmin = wave_min(vmin);
-    vmax = wave_max(vmax);
-    const bool partial = __ballot(own) != 0ull;
-    if (lane == 0) {
-      a.m0cnt[i] = c | (partial ? kPartialBit : 0);
-      a.ring[i] = make_int2(sum, vmin | (vmax << 16));
-      my_nq += c >= r * B;
-      my_mx = max(my_mx, c);
-    }
+    prep_one(a, p, i, lane, my_nq, my_mx);
   }
-  if (lane == 0) { s_nq[wave] = my_nq; s_mx[wave] = my_mx; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int nq = 0, mx = 0;
-    for (int w = 0; w < kThreads / 64; ++w) { nq += s_nq[w]; mx = max(mx, s_mx[w]); }
-    note_context_rule(st, nq, mx);
-  }
+  flush_context_rule(st, my_nq, my_mx, s_nq, s_mx);
 }
 
 // ----------------------------------------------------------- main kernel
@@ -308,18 +335,10 @@ __device__ void write_const_block(const FrameArgs& a, const DevParams& p, int i,
 // FG selects the distance loop of the 16 x 16 block, ring 4, radius 24
 // geometry (compile-time unit offsets); launch_main uses it only there.
 template <int KP, int KR, bool FG>
-__global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams p, int dist_only) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  __shared__ BlockShared sh;
+static __device__ __forceinline__ void est_block(const FrameArgs& a, const DevParams& p, int i,
+                                                 int round, int dist_only,
+                                                 unsigned char* lds_raw, BlockShared& sh) {
   RoundState* st = a.st;
-  const int remaining = st->remaining;
-  if (remaining == 0) return;
-  const int n_lost = st->n_lost, round = st->round;
-  // one workgroup per lost block; the grid covers every cell.  Workgroups
-  // go round-robin to the 8 XCDs, so XCD x takes the x-th contiguous eighth
-  // of the (raster ordered) lost blocks: neighbouring windows share its L2.
-  const int i = xcd_block(blockIdx.x, n_lost);
-  if (i < 0) return;
   // the block's values in one round trip, tested afterwards
   const int bst = a.bstate[i], cell = a.blk[i], m0w = a.m0cnt[i];
   const int2 rg = a.ring[i];
@@ -551,7 +570,8 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
       else want_hql = p.mode == SKM_MODE_PROFILE || (p.mode == SKM_MODE_CNN && !cnn);
     }
     if (want_hql) {
-      if (ncom >= max(2, p.min_hql)) layer = SKM_LAYER_HQL;
+      // HQL's candidates: the complete ones, or every admissible one
+      if ((p.hql_partial ? ncand : ncom) >= max(2, p.min_hql)) layer = SKM_LAYER_HQL;
       else flags |= SKM_FLAG_NO_HQL;
     }
     const double lnu_r = readlane_f64(lnu, ridx);      // ridx is uniform in the wave
@@ -697,6 +717,20 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
   if (tid == 0) a.bstate[i] = round;
 }
 
+// one workgroup per lost block; the grid covers every cell.  Workgroups go
+// round-robin to the 8 XCDs, so XCD x takes the x-th contiguous eighth of
+// the (raster ordered) lost blocks: neighbouring windows share its L2.
+template <int KP, int KR, bool FG>
+__global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams p, int dist_only) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ BlockShared sh;
+  const RoundState* st = a.st;
+  if (st->remaining == 0) return;
+  const int i = xcd_block(blockIdx.x, st->n_lost);
+  if (i < 0) return;
+  est_block<KP, KR, FG>(a, p, i, st->round, dist_only, lds_raw, sh);
+}
+
 // -------------------------------------------------------------- finalize
 // Blocks concealed in this round become known: their output pixels enter
 // the value plane.  A workgroup takes kFinPer consecutive lost blocks at a
@@ -840,6 +874,224 @@ __global__ __launch_bounds__(kThreads) void k_fill(FrameArgs a, DevParams p) {
   }
 }
 
+// ------------------------------------------------------------ batched
+// Batched pipeline over the nf frames of a BatchArgs (equal size and
+// parameters p).  Items are the (frame, lost block) pairs in frame order;
+// cum[f] is the index of frame f's first item.  Persistent kernels give XCD x
+// the x-th contiguous eighth of the items, as the single-frame kernels do
+// per frame.
+
+// items of this workgroup's XCD eighth: first, end, stride (grid a multiple
+// of 8); `sub` of `lanes_per_wg` sub-units (waves) of the workgroup
+struct XcdRange { int first, end, step; };
+static __device__ __forceinline__ XcdRange xcd_items(int total, int lanes_per_wg, int sub) {
+  const int per8 = (total + 7) >> 3, xcd = blockIdx.x & 7;
+  const int g0 = min(total, xcd * per8);
+  XcdRange r;
+  r.first = g0 + (int)(blockIdx.x >> 3) * lanes_per_wg + sub;
+  r.end = min(total, g0 + per8);
+  r.step = (int)(gridDim.x >> 3) * lanes_per_wg;
+  return r;
+}
+
+static __device__ __forceinline__ void publish_batch(const BatchArgs& b) {
+  if (!b.hbs) return;
+  b.hbs->total = b.bs->total;
+  b.hbs->remaining = b.bs->remaining;
+  b.hbs->err = b.bs->err;
+}
+
+// Loss geometry of every frame: init_wgs(p) workgroups per frame.  The
+// workgroup that lists the last frame's cells writes the item offsets cum[]
+// and the batch totals.
+__global__ __launch_bounds__(kThreads) void k_init_b(BatchArgs b, DevParams p) {
+  __shared__ int s_lastf;
+  const int wpf = init_wgs(p), gx = init_wg_x(p);
+  const int f = (int)blockIdx.x / wpf, local = (int)blockIdx.x - f * wpf;
+  const FrameArgs a = batch_frame(b, f);
+  if (!init_body(a, p, local % gx, local / gx, (unsigned)wpf)) return;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned t = atomicAdd(&b.bs->frames_done, 1u);
+    s_lastf = t + 1 == (unsigned)b.nf;
+    if (s_lastf) atomicExch(&b.bs->frames_done, 0u);
+  }
+  __syncthreads();
+  if (!s_lastf || threadIdx.x != 0) return;
+  __threadfence();
+  int acc = 0, rem = 0, err = 0;
+  for (int k = 0; k < b.nf; ++k) {
+    RoundState* sk = b.a0.st + k;
+    b.cum[k] = acc;
+    acc += __hip_atomic_load(&sk->n_lost, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int ek = __hip_atomic_load(&sk->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (ek) {
+      // a frame with a geometry error runs no round (its status reports it)
+      sk->remaining = 0;
+      publish_state_to(sk, b.a0.hstate ? b.a0.hstate + k : nullptr);
+    }
+    rem += __hip_atomic_load(&sk->remaining, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    err |= ek;
+  }
+  b.cum[b.nf] = acc;
+  b.bs->total = acc;
+  b.bs->remaining = rem;
+  b.bs->err = err;
+  publish_batch(b);
+}
+
+// Round preparation of every frame: one wave per item; each wave adds its
+// (nq, mx) to a frame's context rule when it moves to another frame.
+__global__ __launch_bounds__(kThreads) void k_round_prep_b(BatchArgs b, DevParams p) {
+  if (b.bs->remaining == 0) return;
+  if (blockIdx.x == 0)
+    for (int f = threadIdx.x; f < b.nf; f += kThreads) b.a0.st[f].n_hql = 0;
+  const int lane = lane_id(), wave = wave_id();
+  const XcdRange R = xcd_items(b.bs->total, kThreads / 64, wave);
+  if (R.first >= R.end) return;
+  int f = frame_of(b.cum, b.nf, R.first);
+  FrameArgs a = batch_frame(b, f);
+  int nq = 0, mx = 0;
+  for (int g = R.first; g < R.end; g += R.step) {
+    if (g >= b.cum[f + 1]) {
+      if (lane == 0) note_context_rule(a.st, nq, mx);
+      nq = 0; mx = 0;
+      while (g >= b.cum[f + 1]) ++f;
+      a = batch_frame(b, f);
+    }
+    const int i = g - b.cum[f];
+    if (a.st->remaining == 0 || a.bstate[i] != 0) continue;
+    prep_one(a, p, i, lane, nq, mx);
+  }
+  if (lane == 0) note_context_rule(a.st, nq, mx);
+}
+
+// Estimation over every frame's items: frame f owns workgroups
+// [f cpad, (f + 1) cpad), cpad = the cell count rounded up to a multiple of
+// 8, and maps them to its lost blocks as the single-frame kernel does (XCD x
+// takes the x-th contiguous eighth).  A persistent loop over the items was
+// measured first: carrying the frame's buffers and parameters across
+// iterations spilled the scalar registers into 250 VGPRs (one wave per SIMD).
+template <int KP, int KR, bool FG>
+__global__ __launch_bounds__(kThreads) void k_round_main_b(BatchArgs b, DevParams p) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ BlockShared sh;
+  const int cpad = (p.gh * p.gw + 7) & ~7;
+  const int f = (int)blockIdx.x / cpad;
+  const FrameArgs a = batch_frame(b, f);
+  const RoundState* st = a.st;
+  if (st->remaining == 0) return;
+  const int i = xcd_block((int)blockIdx.x - f * cpad, st->n_lost);
+  if (i < 0) return;
+  est_block<KP, KR, FG>(a, p, i, st->round, 0, lds_raw, sh);
+}
+
+// Finalize of every frame: the concealed blocks of the round enter the value
+// planes; pending and HQL-waiting blocks are counted per frame (one atomic
+// per run of a frame in a step); the workgroup that finishes last closes the
+// round of every frame that had one and publishes the states.
+__global__ __launch_bounds__(kThreads) void k_round_finalize_b(BatchArgs b, DevParams p) {
+  __shared__ int s_bs[kFinPer], s_round[kFinPer], s_f[kFinPer], s_cnt[kFinPer];
+  __shared__ int s_vo[kFinPer], s_wo[kFinPer];
+  __shared__ int s_last, s_red[2][kThreads / 64];
+  if (b.bs->remaining == 0) return;
+  const int total = b.bs->total;
+  const int tid = threadIdx.x;
+  const int B = p.B, B2 = B * B;
+  const int lb = __ffs(B) - 1;
+  const int py = tid >> lb, px = tid & (B - 1);
+  for (int g0 = blockIdx.x * kFinPer; g0 < total; g0 += gridDim.x * kFinPer) {
+    if (tid < kFinPer) {
+      const int g = g0 + tid;
+      int bs = -1, f = -1, rnd = 0, cnt = 0;
+      if (g < total) {
+        f = frame_of(b.cum, b.nf, g);
+        const FrameArgs a = batch_frame(b, f);
+        if (a.st->remaining != 0) {
+          const int i = g - b.cum[f];
+          bs = a.bstate[i];
+          rnd = a.st->round;
+          const int cell = a.blk[i];
+          const int by = cell / p.gw, bx = cell - by * p.gw;
+          s_vo[tid] = by * B * p.width + bx * B;
+          s_wo[tid] = by * B * p.stride + bx * B;
+          cnt = (bs == 0 ? 1 : 0) | (bs >= kNeedHql ? 1 << 24 : 0);
+        } else {
+          f = -1;
+        }
+      }
+      s_bs[tid] = bs; s_round[tid] = rnd; s_f[tid] = f; s_cnt[tid] = cnt;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      // one atomic per run of equal frames in this step
+      int k = 0;
+      while (k < kFinPer) {
+        const int f = s_f[k];
+        unsigned long long c = 0;
+        int e = k;
+        while (e < kFinPer && s_f[e] == f) c += (unsigned long long)s_cnt[e++];
+        if (f >= 0 && c) atomicAdd(&b.a0.st[f].round_acc, c);
+        k = e;
+      }
+    }
+    uint8_t v[kFinPer];
+#pragma unroll
+    for (int k = 0; k < kFinPer; ++k) {
+      const bool cpy = tid < B2 && s_bs[k] > 0 && s_bs[k] == s_round[k];
+      v[k] = cpy ? b.io[s_f[k]].out[(size_t)s_wo[k] + (size_t)py * p.stride + px] : (uint8_t)0;
+    }
+#pragma unroll
+    for (int k = 0; k < kFinPer; ++k) {
+      const bool cpy = tid < B2 && s_bs[k] > 0 && s_bs[k] == s_round[k];
+      if (cpy)
+        b.a0.val[(size_t)s_f[k] * b.val_stride + (size_t)s_vo[k] + (size_t)py * p.width + px] =
+            (int16_t)v[k];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    __threadfence();
+    const unsigned t = atomicAdd(&b.bs->fin_ticket, 1u);
+    s_last = t + 1 == gridDim.x;
+    if (s_last) atomicExch(&b.bs->fin_ticket, 0u);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  int rem = 0, err = 0;
+  for (int f = tid; f < b.nf; f += kThreads) {
+    const FrameArgs a = batch_frame(b, f);
+    RoundState* st = a.st;
+    if (st->remaining == 0) { err |= st->err; continue; }
+    const unsigned long long tot =
+        __hip_atomic_load(&st->round_acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    st->round_acc = 0ull;
+    st->remaining = (int)(tot & 0xffffffull);
+    st->round = st->round + 1;
+    st->ctx_nq = 0; st->ctx_max = 0;
+    if ((tot >> 24) & 0xffffffull) st->err |= kErrHqlPending;
+    // a frame with an error stops here (its status reports it; the
+    // single-frame pipeline stops at the same point)
+    if (st->err) st->remaining = 0;
+    publish_state(a);
+    rem += st->remaining;
+    err |= st->err;
+  }
+  rem = wave_sum(rem);
+  int e = err;
+  for (int o = 32; o > 0; o >>= 1) e |= __shfl_xor(e, o, 64);
+  if (lane_id() == 0) { s_red[0][wave_id()] = rem; s_red[1][wave_id()] = e; }
+  __syncthreads();
+  if (tid == 0) {
+    int r = 0, ee = 0;
+    for (int w = 0; w < kThreads / 64; ++w) { r += s_red[0][w]; ee |= s_red[1][w]; }
+    b.bs->remaining = r;
+    b.bs->err = ee;
+    publish_batch(b);
+  }
+}
+
 // -------------------------------------------------------------- launchers
 
 static int clamp_grid(long long g, int hi) {
@@ -917,10 +1169,58 @@ hipError_t launch_zero_words(unsigned int* p, size_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Estimation kernel variants: 0 = <6, 8> with the compile-time unit offsets
+// of the 16 x 16 / ring 4 / window 24 geometry, 1 = <6, 8>, 2 = <9, 8>,
+// 3 = <17, 16> (candidate slices per thread, expansion radii).  The first
+// variant written is the one launch_main uses.
+int est_variants(const DevParams& p, int* out) {
+  const int per = (p.MC + kThreads - 1) / kThreads;
+  const bool fg = p.B == Geom16::kB && p.r == Geom16::kR && p.W == Geom16::kW;
+  int n = 0;
+  if (fg && per <= 6 && p.nrad <= 8) out[n++] = 0;
+  if (per <= 6 && p.nrad <= 8) out[n++] = 1;
+  if (per <= 9 && p.nrad <= 8) out[n++] = 2;
+  out[n++] = 3;
+  return n;
+}
+
+hipError_t launch_init_b(const BatchArgs& b, const DevParams& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_b, dim3(b.nf * init_wgs(p)), dim3(kThreads), 0, s, b, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_b(const BatchArgs& b, const DevParams& p, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_round_prep_b, dim3((grid + 7) / 8 * 8), dim3(kThreads), 0, s, b, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_est_b(const BatchArgs& b, const DevParams& p, int variant, hipStream_t s) {
+  const size_t lds = main_lds_bytes(p);
+  const dim3 g(b.nf * ((p.gh * p.gw + 7) & ~7));
+  switch (variant) {
+    case 0: hipLaunchKernelGGL((k_round_main_b<6, 8, true>), g, dim3(kThreads), lds, s, b, p); break;
+    case 1: hipLaunchKernelGGL((k_round_main_b<6, 8, false>), g, dim3(kThreads), lds, s, b, p); break;
+    case 2: hipLaunchKernelGGL((k_round_main_b<9, 8, false>), g, dim3(kThreads), lds, s, b, p); break;
+    default:
+      hipLaunchKernelGGL((k_round_main_b<kMaxPer, kMaxRadii, false>), g, dim3(kThreads), lds, s, b,
+                         p);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_b(const BatchArgs& b, const DevParams& p, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_round_finalize_b, dim3(grid < 1 ? 1 : grid), dim3(kThreads), 0, s, b, p);
+  return hipGetLastError();
+}
+
 hipError_t set_main_lds_limit(size_t bytes) {
-  const void* fns[4] = {(const void*)k_round_main<6, 8, true>, (const void*)k_round_main<6, 8, false>,
+  const void* fns[8] = {(const void*)k_round_main<6, 8, true>, (const void*)k_round_main<6, 8, false>,
                         (const void*)k_round_main<9, 8, false>,
-                        (const void*)k_round_main<kMaxPer, kMaxRadii, false>};
+                        (const void*)k_round_main<kMaxPer, kMaxRadii, false>,
+                        (const void*)k_round_main_b<6, 8, true>,
+                        (const void*)k_round_main_b<6, 8, false>,
+                        (const void*)k_round_main_b<9, 8, false>,
+                        (const void*)k_round_main_b<kMaxPer, kMaxRadii, false>};
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;

@@ -25,7 +25,7 @@ def test_library_exports_every_declared_function():
 def test_struct_layouts():
     import paper_2205_11226_amd as skm
     from paper_2205_11226_amd.api import BlockInfo, Params
-    assert ctypes.sizeof(Params) == 8 * 4 + 4 * 8
+    assert ctypes.sizeof(Params) == 8 * 4 + 4 * 8 + 2 * 4
     assert ctypes.sizeof(BlockInfo) == skm.BLOCK_INFO_DTYPE.itemsize == 48
 
 

@@ -1,0 +1,219 @@
+"""GPU: the batched-kernel mode of skm_conceal_batch (one launch per stage
+over the (frame, block) items of every frame of a group) against single-frame
+runs, bit for bit, and against the frame-pipeline mode; per-frame errors,
+round limits and the tuning cache.  Single-frame runs are compared with the
+float64 oracle in test_gpu_parity."""
+import json
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import synth
+from tests.parity import device_params
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(__file__), "..", "paper_2205_11226_amd", "weights",
+                       "gate_1080p.skm")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2205_11226_amd as skm
+    assert torch.cuda.is_available()
+    c = skm.Context(0)
+    c.cnn_load(WEIGHTS)
+    yield c
+    c.close()
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_single(ctx, f, m, prm):
+    out, info, xh = ctx.conceal_device(to_dev(f), to_dev(m), prm)
+    return out.cpu().numpy(), info, xh.cpu().numpy()
+
+
+def batch_jobs(frames, prms):
+    import torch
+    jobs, outs = [], []
+    for (f, m), prm in zip(frames, prms):
+        fd, md = to_dev(f), to_dev(m)
+        b = prm.block
+        cap = (f.shape[0] // b) * (f.shape[1] // b)
+        info = torch.zeros(max(cap, 1) * 48, dtype=torch.uint8, device="cuda")
+        xh = torch.zeros((max(cap, 1), b, b), dtype=torch.float32, device="cuda")
+        jobs.append((fd, md, torch.empty_like(fd), prm, info, xh, cap))
+        outs.append(jobs[-1][2:3] + (info, xh))
+    return jobs, outs
+
+
+def check_equal(ctx, res, outs, refs, tag):
+    import paper_2205_11226_amd as skm
+    for k, ((out, info, xh), ref) in enumerate(zip(outs, refs)):
+        n, rounds, st = res[k]
+        assert st == 0 and n == len(ref[1]), (tag, k, st, n)
+        # rounds run: the last round of a concealed block (a round-limit
+        # fill reports the round after the limit in its block records)
+        run = ref[1]["round"][ref[1]["layer"] != skm.LAYER_FILL]
+        assert rounds == (int(run.max()) if len(run) else 0), (tag, k)
+        assert np.array_equal(out.cpu().numpy(), ref[0]), (tag, k)
+        gi = info.cpu().numpy().view(skm.BLOCK_INFO_DTYPE)[:n]
+        assert gi.tobytes() == ref[1].tobytes(), (tag, k)
+        assert np.array_equal(xh[:n].cpu().numpy(), ref[2]), (tag, k)
+
+
+def mixed_frames():
+    """Frames of several sizes, block sizes, loss kinds and modes; equal
+    (size, parameters) pairs form groups of several frames."""
+    frames, prms = [], []
+    specs = [((240, 320), 16, "slices", "cnn"), ((240, 320), 16, "random", "cnn"),
+             ((240, 320), 16, "lattice", "cnn"), ((240, 320), 16, "isolated", "profile"),
+             ((240, 320), 16, "isolated", "profile"), ((200, 256), 8, "random", "plain"),
+             ((200, 256), 8, "slices", "plain"), ((176, 208), 16, "partial", "full"),
+             ((176, 208), 16, "isolated", "full"), ((240, 320), 16, "none", "cnn")]
+    for k, ((h, w), b, kind, mode) in enumerate(specs):
+        f = synth.make_luma(h, w, 700 + k, n_bumps=16, n_edges=6)
+        if kind == "slices":
+            m = synth.loss_slices(h, w, b, 0.4, 720 + k)
+        elif kind == "random":
+            m = synth.loss_random(h, w, b, 0.25, 720 + k)
+        elif kind == "lattice":
+            m = synth.loss_dispersed(h, w, b)
+        elif kind == "isolated":
+            m = synth.loss_isolated(h, w, b, 10, 720 + k)
+        elif kind == "partial":
+            m = synth.loss_partial_cells(h, w, b, 0.35, 720 + k, frac=0.6)
+        else:
+            m = np.zeros((h, w), np.uint8)          # nothing lost
+        frames.append((f, m))
+        prms.append(device_params(mode, block=b, min_hql_cands=16))
+    return frames, prms
+
+
+def test_batched_kernels_match_single_frames(ctx):
+    import paper_2205_11226_amd as skm
+    frames, prms = mixed_frames()
+    refs = [run_single(ctx, f, m, prm) for (f, m), prm in zip(frames, prms)]
+    assert max(int(r[1]["round"].max()) for r in refs if len(r[1])) >= 2
+    assert any((r[1]["layer"] == skm.LAYER_HQL).any() for r in refs)
+    ctx.set_option(skm.OPT_BATCH_MODE, 1)
+    try:
+        for graphs, streams in ((0, 4), (1, 4), (1, 4), (1, 1)):
+            ctx.set_option(skm.OPT_GRAPHS, graphs)
+            ctx.set_option(skm.OPT_BATCH_STREAMS, streams)
+            jobs, outs = batch_jobs(frames, prms)
+            res = ctx.conceal_batch(jobs)
+            check_equal(ctx, res, outs, refs, (graphs, streams))
+    finally:
+        ctx.set_option(skm.OPT_GRAPHS, 1)
+        ctx.set_option(skm.OPT_BATCH_STREAMS, 4)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_estimation_variants_agree(ctx, variant):
+    """Every estimation kernel variant (candidate slices per thread) gives
+    the same results on a group of 1080p-lattice-like frames."""
+    import paper_2205_11226_amd as skm
+    frames = [(synth.make_luma(256, 384, 800 + k, n_bumps=20, n_edges=8, texture=True),
+               synth.loss_dispersed(256, 384, 16, k & 1, 0)) for k in range(3)]
+    prms = [device_params("cnn")] * 3
+    refs = [run_single(ctx, f, m, prm) for (f, m), prm in zip(frames, prms)]
+    ctx.set_option(skm.OPT_EST_VARIANT, variant)
+    try:
+        jobs, outs = batch_jobs(frames, prms)
+        res = ctx.conceal_batch(jobs)
+        check_equal(ctx, res, outs, refs, variant)
+    finally:
+        ctx.set_option(skm.OPT_EST_VARIANT, -1)
+
+
+def test_frame_pipeline_mode_still_matches(ctx):
+    import paper_2205_11226_amd as skm
+    frames, prms = mixed_frames()
+    refs = [run_single(ctx, f, m, prm) for (f, m), prm in zip(frames, prms)]
+    ctx.set_option(skm.OPT_BATCH_MODE, 0)
+    try:
+        jobs, outs = batch_jobs(frames, prms)
+        res = ctx.conceal_batch(jobs)
+        check_equal(ctx, res, outs, refs, "pipelines")
+    finally:
+        ctx.set_option(skm.OPT_BATCH_MODE, 1)
+
+
+def test_batched_round_limit_fills_like_single_frames(ctx):
+    import paper_2205_11226_amd as skm
+    frames = [(synth.make_luma(192, 256, 900 + k, n_bumps=12, n_edges=5),
+               synth.loss_slices(192, 256, 16, 0.6, 910 + k)) for k in range(3)]
+    prms = [device_params("profile", max_rounds=1)] * 3
+    refs = [run_single(ctx, f, m, prm) for (f, m), prm in zip(frames, prms)]
+    assert any((r[1]["layer"] == skm.LAYER_FILL).any() for r in refs)
+    jobs, outs = batch_jobs(frames, prms)
+    res = ctx.conceal_batch(jobs)
+    check_equal(ctx, res, outs, refs, "max_rounds")
+
+
+def test_batched_errors_stay_with_their_frame(ctx):
+    """A frame with a lost pixel outside the cells, in a group with good
+    frames of the same size: its status is SKM_EUNSUPPORTED, the others are
+    exact."""
+    import paper_2205_11226_amd as skm
+    f = synth.make_luma(136, 128, 5)
+    good = np.zeros((136, 128), np.uint8)
+    good[:128] = synth.loss_random(128, 128, 16, 0.2, 6)
+    bad = good.copy()
+    bad[130, 5] = 1
+    prm = device_params("plain")
+    refs = [run_single(ctx, f, good, prm)] * 2
+    jobs, outs = batch_jobs([(f, good), (f, bad), (f, good)], [prm] * 3)
+    descs, keep = ctx._frame_descs(jobs)
+    st = skm.api.lib.skm_conceal_batch(ctx._h, descs, 3, None)
+    assert st == -4
+    assert [d.status for d in descs] == [0, -4, 0]
+    res = [(d.n_lost, d.rounds, d.status) for d in descs]
+    check_equal(ctx, [res[0], res[2]], [outs[0], outs[2]], refs, "errors")
+
+
+def test_autotune_cache_roundtrip(ctx):
+    import paper_2205_11226_amd as skm
+    frames = [(synth.make_luma(240, 320, 950 + k, n_bumps=16, n_edges=6),
+               synth.loss_dispersed(240, 320, 16)) for k in range(4)]
+    prms = [device_params("cnn")] * 4
+    refs = [run_single(ctx, f, m, prm) for (f, m), prm in zip(frames, prms)]
+    jobs, outs = batch_jobs(frames, prms)
+    best = ctx.autotune(jobs, reps=1)
+    assert best > 0.0
+    check_equal(ctx, [(r[1].shape[0], int(r[1]["round"].max()), 0) for r in refs], outs, refs,
+                "autotune")
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.json")
+        ctx.autotune_save(path)
+        rec = json.load(open(path))
+        assert rec["version"] == 1 and rec["batch_mode"] in (0, 1)
+        if rec["batch_mode"] == 1:
+            assert [(t["block"], t["ring"], t["window"]) for t in rec["tiles"]] == [(16, 4, 24)]
+        c2 = skm.Context(0)
+        try:
+            c2.autotune_load(path)
+            assert c2.get_option(skm.OPT_BATCH_MODE) == rec["batch_mode"]
+            assert c2.get_option(skm.OPT_GRAPHS) == rec["graphs"]
+            bad = os.path.join(d, "bad.json")
+            rec["tiles"] = [{"block": 16, "ring": 4, "window": 24, "est_variant": 9,
+                             "gate_grid": 768}]
+            json.dump(rec, open(bad, "w"))
+            with pytest.raises(skm.SkmError):
+                c2.autotune_load(bad)
+        finally:
+            c2.close()
+    res = ctx.conceal_batch(jobs)
+    check_equal(ctx, res, outs, refs, "after tuning")
+    ctx.set_option(skm.OPT_BATCH_MODE, 1)
+    ctx.set_option(skm.OPT_BATCH_STREAMS, 4)
+    ctx.set_option(skm.OPT_GRAPHS, 1)
+    ctx.set_option(skm.OPT_GATE_GRID, 768)
