@@ -303,6 +303,7 @@ def main():
     # in the timed region)
     tune_ms = ctx.autotune(jobs_for(p_lay, args.steps), reps=3)
     tuned = {"batch_mode": ctx.get_option(skm.OPT_BATCH_MODE),
+             "group_split": ctx.get_option(skm.OPT_GROUP_SPLIT),
              "batch_streams": ctx.get_option(skm.OPT_BATCH_STREAMS),
              "graphs": ctx.get_option(skm.OPT_GRAPHS),
              "gate_grid": ctx.get_option(skm.OPT_GATE_GRID), "tune_batch_ms": tune_ms}
@@ -510,6 +511,7 @@ def bench_batch(args):
     blocks = sum(r[0] for r in res)
     rounds = [r[1] for r in res]
     tuned = {"batch_mode": ctx.get_option(skm.OPT_BATCH_MODE),
+             "group_split": ctx.get_option(skm.OPT_GROUP_SPLIT),
              "batch_streams": ctx.get_option(skm.OPT_BATCH_STREAMS),
              "graphs": ctx.get_option(skm.OPT_GRAPHS),
              "gate_grid": ctx.get_option(skm.OPT_GATE_GRID), "tune_batch_ms": tune_ms}

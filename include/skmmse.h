@@ -332,20 +332,24 @@ enum {
                                  slot holds, 128..1024 by geometry                */
   SKM_OPT_BATCH_MODE = 5,     /* skm_conceal_batch: 1 (default) batched kernels per
                                  group of equal frames, 0 frame pipelines         */
-  SKM_OPT_EST_VARIANT = 6     /* batched estimation kernel variant: -1 (default)
+  SKM_OPT_EST_VARIANT = 6,    /* batched estimation kernel variant: -1 (default)
                                  the geometry's first; 0: compile-time unit offsets
                                  of B 16 / ring 4 / window 24 (6 candidates per
                                  thread); 1, 2, 3: 6, 9, 17 candidates per thread
                                  (variants too small for the geometry are replaced
                                  by its first).  Setting it, or SKM_OPT_GATE_GRID,
                                  clears the tile table                           */
+  SKM_OPT_GROUP_SPLIT = 7     /* batched mode: a group's frames are split into this
+                                 many sub-groups of contiguous frames, each on its
+                                 own stream, so that their stages overlap, 1..8 (1) */
 };
 skm_status skm_set_option(skm_ctx* ctx, int32_t option, int64_t value);
 skm_status skm_get_option(skm_ctx* ctx, int32_t option, int64_t* value);
 
 /* Autotuner: times skm_conceal_batch on these frames under each launch
  * configuration -- batched mode with every estimation variant of the first
- * frame's geometry and gate grids 512, 768, 1536 and 3072 (CNN mode), and
+ * frame's geometry, gate grids 512, 768, 1536 and 3072 (CNN mode) and group
+ * splits 1, 2 and 4, and
  * frame pipelines on 1, 2, 4 and 8 streams with gate grids 512, 768 and 1536
  * (CNN mode); graphs on and off -- keeping the best of `reps` runs each.  The
  * winner's batch mode, streams and graph use are set on the context; in
@@ -356,7 +360,7 @@ skm_status skm_autotune(skm_ctx* ctx, skm_frame_desc* frames, int32_t n, int32_t
                         double* best_ms);
 
 /* Tuning cache as JSON: {"version": 1, "batch_mode", "batch_streams",
- * "graphs", "gate_grid", "tiles": [{"block", "ring", "window", "est_variant",
+ * "group_split", "graphs", "gate_grid", "tiles": [{"block", "ring", "window", "est_variant",
  * "gate_grid", "batch_ms"}, ...]}.  Save writes the context's options and
  * tile table; load validates every field (SKM_EINVAL on a missing or
  * out-of-range one, the context unchanged) and replaces them. */

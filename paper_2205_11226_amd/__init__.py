@@ -10,4 +10,5 @@ from .api import (  # noqa: F401
     Params,
     default_params, patch_params, Context, lib, exported_symbols, FrameDesc, OPT_GRAPHS, OPT_BATCH_STREAMS,
     OPT_GATE_GRID, OPT_HQL_GRID, OPT_BATCH_MODE, OPT_EST_VARIANT,
+    OPT_GROUP_SPLIT,
 )

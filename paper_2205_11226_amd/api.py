@@ -24,7 +24,7 @@ EXPORTS = ("skm_default_params", "skm_patch_params", "skm_create", "skm_destroy"
            "skm_autotune", "skm_autotune_save", "skm_autotune_load", "skm_profile_enable",
            "skm_profile_read", "skm_last_error")
 OPT_GRAPHS, OPT_BATCH_STREAMS, OPT_GATE_GRID, OPT_HQL_GRID = 1, 2, 3, 4
-OPT_BATCH_MODE, OPT_EST_VARIANT = 5, 6
+OPT_BATCH_MODE, OPT_EST_VARIANT, OPT_GROUP_SPLIT = 5, 6, 7
 CNN_PARAMS = 20898
 
 

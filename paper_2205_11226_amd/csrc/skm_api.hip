@@ -19,6 +19,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <mutex>
 #include <string>
@@ -140,6 +141,7 @@ struct skm_ctx {
   int gate_grid = 768;
   int hql_grid = 0;               // 0: hql_slots(p)
   int est_variant = -1;           // -1: tuned or default
+  int group_split = 1;            // batched mode: a group's frames in this many sub-groups
   // kernel timing (skm_profile_*)
   bool prof = false;
   double prof_ms = 0.0;
@@ -937,6 +939,18 @@ skm_status batch_groups_run(skm_ctx* c, skm_frame_desc* frames, int32_t n, hipSt
     if (gi < 0) { groups.push_back({}); gi = (int)groups.size() - 1; }
     groups[gi].push_back(k);
   }
+  // sub-groups of contiguous frames, so that the stages of one overlap those
+  // of another on the group streams
+  if (c->group_split > 1) {
+    std::vector<std::vector<int>> split;
+    for (const std::vector<int>& gr : groups) {
+      const int parts = (int)gr.size() < c->group_split ? (int)gr.size() : c->group_split;
+      const int per = ((int)gr.size() + parts - 1) / parts;
+      for (size_t k0 = 0; k0 < gr.size(); k0 += per)
+        split.emplace_back(gr.begin() + k0, gr.begin() + std::min(gr.size(), k0 + (size_t)per));
+    }
+    groups.swap(split);
+  }
   const int S = (int)groups.size() < c->batch_streams ? (int)groups.size() : c->batch_streams;
   while ((int)c->groups.size() < S) {
     GroupSlot* g = nullptr;
@@ -1117,6 +1131,11 @@ skm_status skm_set_option(skm_ctx* c, int32_t option, int64_t value) {
       c->est_variant = (int)value;
       c->tiles.clear();
       return SKM_OK;
+    case SKM_OPT_GROUP_SPLIT:
+      if (value < 1 || value > kMaxBatchStreams)
+        return fail(SKM_EINVAL, "SKM_OPT_GROUP_SPLIT takes 1..8");
+      c->group_split = (int)value;
+      return SKM_OK;
     default:
       return fail(SKM_EINVAL, "unknown option");
   }
@@ -1131,6 +1150,7 @@ skm_status skm_get_option(skm_ctx* c, int32_t option, int64_t* value) {
     case SKM_OPT_HQL_GRID: *value = c->hql_grid; return SKM_OK;
     case SKM_OPT_BATCH_MODE: *value = c->batch_mode; return SKM_OK;
     case SKM_OPT_EST_VARIANT: *value = c->est_variant; return SKM_OK;
+    case SKM_OPT_GROUP_SPLIT: *value = c->group_split; return SKM_OK;
     default: return fail(SKM_EINVAL, "unknown option");
   }
 }
@@ -1389,29 +1409,34 @@ skm_status skm_autotune(skm_ctx* c, skm_frame_desc* frames, int32_t n, int32_t r
   const int grids_b[4] = {512, 768, 1536, 3072};
   const int grids_s[3] = {512, 768, 1536};
   const int streams[4] = {1, 2, 4, 8};
-  struct Cfg { int mode, streams, graphs, gate, variant; };
+  const int splits[3] = {1, 2, 4};
+  struct Cfg { int mode, streams, graphs, gate, variant, split; };
   std::vector<Cfg> cfgs;
   for (int graphs = 0; graphs <= 1; ++graphs) {
     for (int vi = 0; vi < nv; ++vi)
       for (int gi = 0; gi < (cnn ? 4 : 1); ++gi)
-        cfgs.push_back({1, 8, graphs, cnn ? grids_b[gi] : c->gate_grid, variants[vi]});
+        for (int sp = 0; sp < 3; ++sp)
+          if (splits[sp] == 1 || splits[sp] <= n)
+            cfgs.push_back({1, 8, graphs, cnn ? grids_b[gi] : c->gate_grid, variants[vi],
+                            splits[sp]});
     for (int si = 0; si < 4; ++si)
       for (int gi = 0; gi < (cnn ? 3 : 1); ++gi)
-        cfgs.push_back({0, streams[si], graphs, cnn ? grids_s[gi] : c->gate_grid, -1});
+        cfgs.push_back({0, streams[si], graphs, cnn ? grids_s[gi] : c->gate_grid, -1, 1});
   }
   const int keep_mode = c->batch_mode, keep_streams = c->batch_streams;
   const bool keep_graphs = c->use_graphs;
-  const int keep_gate = c->gate_grid, keep_var = c->est_variant;
+  const int keep_gate = c->gate_grid, keep_var = c->est_variant, keep_split = c->group_split;
   std::vector<TileConfig> keep_tiles = c->tiles;
   c->tiles.clear();
   double best = 1e300;
-  Cfg win = {keep_mode, keep_streams, keep_graphs ? 1 : 0, keep_gate, keep_var};
+  Cfg win = {keep_mode, keep_streams, keep_graphs ? 1 : 0, keep_gate, keep_var, keep_split};
   for (const Cfg& k : cfgs) {
     c->batch_mode = k.mode;
     c->batch_streams = k.streams;
     c->use_graphs = k.graphs != 0;
     c->gate_grid = k.gate;
     c->est_variant = k.variant;
+    c->group_split = k.split;
     s = skm_conceal_batch(c, frames, n, nullptr);            // warm (captures graphs)
     if (s != SKM_OK) break;
     double t_best = 1e300;
@@ -1428,13 +1453,14 @@ skm_status skm_autotune(skm_ctx* c, skm_frame_desc* frames, int32_t n, int32_t r
   c->tiles = keep_tiles;
   if (s != SKM_OK) {
     c->batch_mode = keep_mode; c->batch_streams = keep_streams; c->use_graphs = keep_graphs;
-    c->gate_grid = keep_gate; c->est_variant = keep_var;
+    c->gate_grid = keep_gate; c->est_variant = keep_var; c->group_split = keep_split;
     return s;
   }
   c->batch_mode = win.mode;
   c->batch_streams = win.mode == 1 ? keep_streams : win.streams;
   c->use_graphs = win.graphs != 0;
   c->est_variant = keep_var;
+  c->group_split = win.mode == 1 ? win.split : keep_split;
   if (win.mode == 1) {
     c->gate_grid = keep_gate;
     TileConfig t = {p0.B, p0.r, p0.W, win.variant, win.gate, best};
@@ -1455,8 +1481,9 @@ skm_status skm_autotune_save(skm_ctx* c, const char* path) {
   FILE* fp = fopen(path, "w");
   if (!fp) return fail(SKM_EINVAL, std::string("cannot write ") + path);
   fprintf(fp, "{\n  \"version\": 1,\n  \"batch_mode\": %d,\n  \"batch_streams\": %d,\n"
-              "  \"graphs\": %d,\n  \"gate_grid\": %d,\n  \"tiles\": [",
-          c->batch_mode, c->batch_streams, c->use_graphs ? 1 : 0, c->gate_grid);
+              "  \"group_split\": %d,\n  \"graphs\": %d,\n  \"gate_grid\": %d,\n"
+              "  \"tiles\": [",
+          c->batch_mode, c->batch_streams, c->group_split, c->use_graphs ? 1 : 0, c->gate_grid);
   for (size_t k = 0; k < c->tiles.size(); ++k) {
     const TileConfig& t = c->tiles[k];
     fprintf(fp, "%s\n    {\"block\": %d, \"ring\": %d, \"window\": %d, \"est_variant\": %d, "
@@ -1479,15 +1506,17 @@ skm_status skm_autotune_load(skm_ctx* c, const char* path) {
   while ((got = fread(buf, 1, sizeof buf, fp)) > 0) t.append(buf, got);
   fclose(fp);
   const size_t tiles_at = t.find("\"tiles\"");
-  int version = 0, mode = 1, streams = 4, graphs = 1, gate = 768;
+  int version = 0, mode = 1, streams = 4, graphs = 1, gate = 768, split = 1;
   const size_t head_end = tiles_at == std::string::npos ? t.size() : tiles_at;
   if (!json_int(t, 0, head_end, "version", &version) || version != 1)
     return fail(SKM_EINVAL, "not a version-1 tuning file");
   if (!json_int(t, 0, head_end, "batch_mode", &mode) ||
       !json_int(t, 0, head_end, "batch_streams", &streams) ||
-      !json_int(t, 0, head_end, "graphs", &graphs) || !json_int(t, 0, head_end, "gate_grid", &gate))
+      !json_int(t, 0, head_end, "graphs", &graphs) || !json_int(t, 0, head_end, "gate_grid", &gate) ||
+      !json_int(t, 0, head_end, "group_split", &split))
     return fail(SKM_EINVAL, "tuning file lacks a launch option");
   if ((mode != 0 && mode != 1) || streams < 1 || streams > kMaxBatchStreams ||
+      split < 1 || split > kMaxBatchStreams ||
       (graphs != 0 && graphs != 1) || gate < 8 || gate > 4096 || gate % 8)
     return fail(SKM_EINVAL, "tuning file holds an out-of-range option");
   std::vector<TileConfig> tiles;
@@ -1511,6 +1540,7 @@ skm_status skm_autotune_load(skm_ctx* c, const char* path) {
   }
   c->batch_mode = mode;
   c->batch_streams = streams;
+  c->group_split = split;
   c->use_graphs = graphs != 0;
   c->gate_grid = gate;
   c->tiles = tiles;

@@ -319,7 +319,7 @@ static __device__ double eval_eps(double beta, int Mc, int Ny, int B2, int ldm, 
 static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevParams& p,
                                                  unsigned char* ws, size_t slot_bytes, int round,
                                                  int n_hql, bool& first, unsigned char* lds_raw,
-                                                 BlockShared& sh, HqlShared& hs) {
+                                                 BlockShared& sh, HqlShared& hs, int* pend) {
   const MainLds L = carve_main_lds(lds_raw, p);
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   const int B = p.B, r = p.r, W = p.W, Wd = p.Wd;
@@ -592,6 +592,7 @@ static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevPa
           a.info[i].flags |= SKM_FLAG_HQL_SINGULAR;
         }
         a.bstate[i] = round;
+        if (pend) atomicSub(pend, 1);
       }
       __syncthreads();
       continue;
@@ -855,7 +856,10 @@ static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevPa
         a.work[(size_t)(y0 + py) * p.stride + x0 + px] = (uint8_t)fmin(fmax(floor(xh + 0.5), 0.0), 255.0);
       if (a.xhat && i < a.cap) a.xhat[(size_t)i * B2 + q] = (float)xh;
     }
-    if (tid == 0) a.bstate[i] = round;
+    if (tid == 0) {
+      a.bstate[i] = round;
+      if (pend) atomicSub(pend, 1);
+    }
     __syncthreads();
   }
 }
@@ -870,7 +874,7 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
   const int n_hql = st->n_hql;
   if ((int)blockIdx.x >= n_hql) return;
   bool first = true;
-  hql_frame(a, p, ws, slot_bytes, st->round, n_hql, first, lds_raw, sh, hs);
+  hql_frame(a, p, ws, slot_bytes, st->round, n_hql, first, lds_raw, sh, hs, nullptr);
 }
 
 // Every frame of a batch in turn: the workgroups (one scratch slot each)
@@ -888,7 +892,8 @@ __global__ __launch_bounds__(kThreads) void k_hql_b(BatchArgs b, DevParams p, un
     const int n_hql = st->n_hql;
     if ((int)blockIdx.x >= n_hql) continue;
     if (!first) __syncthreads();
-    hql_frame(batch_frame(b, f), p, ws, slot_bytes, st->round, n_hql, first, lds_raw, sh, hs);
+    hql_frame(batch_frame(b, f), p, ws, slot_bytes, st->round, n_hql, first, lds_raw, sh, hs,
+              &b.bs->pending);
   }
 }
 

@@ -115,7 +115,10 @@ struct BatchState {
   int err;                 // OR of the frames' error bits
   unsigned frames_done;    // k_init_b: frames listed so far (zero between launches)
   unsigned fin_ticket;     // k_round_finalize_b: workgroups done (zero between launches)
-  int pad[3];
+  int pending;             // blocks of the round left pending by the estimation kernel
+                           // (context rule, or waiting for HQL until the HQL kernel
+                           // takes them); zero between rounds
+  int pad[2];
 };
 
 struct FrameIO {           // the caller's buffers of one frame

@@ -334,10 +334,13 @@ __device__ void write_const_block(const FrameArgs& a, const DevParams& p, int i,
 // fits the geometry.
 // FG selects the distance loop of the 16 x 16 block, ring 4, radius 24
 // geometry (compile-time unit offsets); launch_main uses it only there.
+// pend (batched kernels; nullptr otherwise) counts the blocks this call
+// leaves pending: deferred by the round's context rule, or waiting for HQL.
 template <int KP, int KR, bool FG>
 static __device__ __forceinline__ void est_block(const FrameArgs& a, const DevParams& p, int i,
                                                  int round, int dist_only,
-                                                 unsigned char* lds_raw, BlockShared& sh) {
+                                                 unsigned char* lds_raw, BlockShared& sh,
+                                                 int* pend) {
   RoundState* st = a.st;
   // the block's values in one round trip, tested afterwards
   const int bst = a.bstate[i], cell = a.blk[i], m0w = a.m0cnt[i];
@@ -357,12 +360,18 @@ static __device__ __forceinline__ void est_block(const FrameArgs& a, const DevPa
   StageRegs SR;
   if (!dist_only) stage_issue(a, p, SG, y0 - r - W, SR);
   if (!dist_only && nq == 0 && maxm0 == 0) {
-    if (tid == 0) atomicOr(&st->err, kErrNoContext);
+    if (tid == 0) {
+      atomicOr(&st->err, kErrNoContext);
+      if (pend) atomicAdd(pend, 1);
+    }
     return;
   }
   const int n0 = m0w & (kPartialBit - 1);
   const bool partial = (m0w & kPartialBit) != 0;      // the block holds received pixels
-  if (!dist_only && !(nq > 0 ? (n0 >= p.r * p.B) : (n0 == maxm0))) return;
+  if (!dist_only && !(nq > 0 ? (n0 >= p.r * p.B) : (n0 == maxm0))) {
+    if (pend && tid == 0) atomicAdd(pend, 1);          // deferred to a later round
+    return;
+  }
 
 
   // 1. BRL gate on the prep kernel's ring statistics: context mean for every
@@ -600,6 +609,7 @@ static __device__ __forceinline__ void est_block(const FrameArgs& a, const DevPa
       write_info(a, i, bx, by, SKM_LAYER_HQL, round, sh.n_cand, sh.n_complete, W, sh.flags,
                  phi, n0, sh.lnu);
       a.bstate[i] = kNeedHql + round;
+      if (pend) atomicAdd(pend, 1);                    // until the HQL kernel takes it
       a.hql_list[atomicAdd(&st->n_hql, 1)] = i;
     }
     return;
@@ -728,7 +738,7 @@ __global__ __launch_bounds__(kThreads) void k_round_main(FrameArgs a, DevParams 
   if (st->remaining == 0) return;
   const int i = xcd_block(blockIdx.x, st->n_lost);
   if (i < 0) return;
-  est_block<KP, KR, FG>(a, p, i, st->round, dist_only, lds_raw, sh);
+  est_block<KP, KR, FG>(a, p, i, st->round, dist_only, lds_raw, sh, nullptr);
 }
 
 // -------------------------------------------------------------- finalize
@@ -983,7 +993,7 @@ __global__ __launch_bounds__(kThreads) void k_round_main_b(BatchArgs b, DevParam
   if (st->remaining == 0) return;
   const int i = xcd_block((int)blockIdx.x - f * cpad, st->n_lost);
   if (i < 0) return;
-  est_block<KP, KR, FG>(a, p, i, st->round, 0, lds_raw, sh);
+  est_block<KP, KR, FG>(a, p, i, st->round, 0, lds_raw, sh, &b.bs->pending);
 }
 
 // Finalize of every frame: the concealed blocks of the round enter the value
@@ -995,8 +1005,36 @@ __global__ __launch_bounds__(kThreads) void k_round_finalize_b(BatchArgs b, DevP
   __shared__ int s_vo[kFinPer], s_wo[kFinPer];
   __shared__ int s_last, s_red[2][kThreads / 64];
   if (b.bs->remaining == 0) return;
-  const int total = b.bs->total;
   const int tid = threadIdx.x;
+  if (__hip_atomic_load(&b.bs->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    // no block of any frame is left pending: every frame that had a round
+    // is complete, and no later round reads the value planes
+    if (blockIdx.x != 0) return;
+    int err = 0;
+    for (int f = tid; f < b.nf; f += kThreads) {
+      const FrameArgs a = batch_frame(b, f);
+      RoundState* st = a.st;
+      if (st->remaining != 0) {
+        st->remaining = 0;
+        st->round = st->round + 1;
+        st->ctx_nq = 0; st->ctx_max = 0;
+        publish_state(a);
+      }
+      err |= st->err;
+    }
+    for (int o = 32; o > 0; o >>= 1) err |= __shfl_xor(err, o, 64);
+    if (lane_id() == 0) s_red[1][wave_id()] = err;
+    __syncthreads();
+    if (tid == 0) {
+      int ee = 0;
+      for (int w = 0; w < kThreads / 64; ++w) ee |= s_red[1][w];
+      b.bs->remaining = 0;
+      b.bs->err = ee;
+      publish_batch(b);
+    }
+    return;
+  }
+  const int total = b.bs->total;
   const int B = p.B, B2 = B * B;
   const int lb = __ffs(B) - 1;
   const int py = tid >> lb, px = tid & (B - 1);
@@ -1088,6 +1126,7 @@ __global__ __launch_bounds__(kThreads) void k_round_finalize_b(BatchArgs b, DevP
     for (int w = 0; w < kThreads / 64; ++w) { r += s_red[0][w]; ee |= s_red[1][w]; }
     b.bs->remaining = r;
     b.bs->err = ee;
+    b.bs->pending = 0;                     // counted afresh by the next round
     publish_batch(b);
   }
 }

@@ -105,15 +105,18 @@ def test_batched_kernels_match_single_frames(ctx):
     assert any((r[1]["layer"] == skm.LAYER_HQL).any() for r in refs)
     ctx.set_option(skm.OPT_BATCH_MODE, 1)
     try:
-        for graphs, streams in ((0, 4), (1, 4), (1, 4), (1, 1)):
+        for graphs, streams, split in ((0, 4, 1), (1, 4, 1), (1, 4, 1), (1, 1, 1), (1, 4, 3),
+                                       (0, 2, 2)):
             ctx.set_option(skm.OPT_GRAPHS, graphs)
             ctx.set_option(skm.OPT_BATCH_STREAMS, streams)
+            ctx.set_option(skm.OPT_GROUP_SPLIT, split)
             jobs, outs = batch_jobs(frames, prms)
             res = ctx.conceal_batch(jobs)
-            check_equal(ctx, res, outs, refs, (graphs, streams))
+            check_equal(ctx, res, outs, refs, (graphs, streams, split))
     finally:
         ctx.set_option(skm.OPT_GRAPHS, 1)
         ctx.set_option(skm.OPT_BATCH_STREAMS, 4)
+        ctx.set_option(skm.OPT_GROUP_SPLIT, 1)
 
 
 @pytest.mark.parametrize("variant", [0, 1, 2, 3])
@@ -215,5 +218,6 @@ def test_autotune_cache_roundtrip(ctx):
     check_equal(ctx, res, outs, refs, "after tuning")
     ctx.set_option(skm.OPT_BATCH_MODE, 1)
     ctx.set_option(skm.OPT_BATCH_STREAMS, 4)
+    ctx.set_option(skm.OPT_GROUP_SPLIT, 1)
     ctx.set_option(skm.OPT_GRAPHS, 1)
     ctx.set_option(skm.OPT_GATE_GRID, 768)
