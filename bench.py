@@ -408,14 +408,18 @@ def _line(metric, value, unit, args, ms_per_step, config, higher=True, **extra):
 
 def _timed_batches(ctx, jobs, steps, warmup):
     """`warmup` untimed skm_conceal_batch calls over `jobs`, then `steps` timed
-    ones; returns seconds per call and the last call's results."""
+    ones; returns seconds per call and the last call's results.  Each call
+    prints a progress line (after it returns)."""
     import torch
-    for _ in range(max(warmup, 1)):
+    for k in range(max(warmup, 1)):
+        t = time.perf_counter()
         ctx.conceal_batch(jobs)
+        print(f"# warm-up call {k}: {time.perf_counter() - t:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         res = ctx.conceal_batch(jobs)
+        print(f"# timed call {k} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / max(steps, 1)
     if any(r[2] != 0 for r in res):
@@ -506,7 +510,11 @@ def bench_batch(args):
         jobs.append((fd, md, torch.empty_like(fd), skm.default_params(mode=args.mode,
                                                                       block=w["block"])))
         n_px += w["frame"].size
-    tune_ms = ctx.autotune(jobs, reps=2)
+    # launch configuration tuned on one frame of each size (the batch itself
+    # takes seconds per call in CNN mode with HQL blocks)
+    sub = [jobs[0], jobs[24], jobs[56]]
+    tune_ms = ctx.autotune(sub, reps=1)
+    print(f"# autotuned on 3 frames: {tune_ms:.2f} ms", file=sys.stderr, flush=True)
     sec, res = _timed_batches(ctx, jobs, args.steps, args.warmup)
     blocks = sum(r[0] for r in res)
     rounds = [r[1] for r in res]
@@ -565,7 +573,8 @@ def bench_stream4k(args):
     for k in range(120):
         for c, (fd, md) in enumerate(dev[k % nd]):
             jobs.append((fd, md, torch.empty_like(fd), prm[16 if c == 0 else 8]))
-    tune_ms = ctx.autotune(jobs[:48], reps=2)
+    tune_ms = ctx.autotune(jobs[:6], reps=1)
+    print(f"# autotuned on 2 frames: {tune_ms:.2f} ms", file=sys.stderr, flush=True)
     sec, res = _timed_batches(ctx, jobs, args.steps, args.warmup)
     blocks = sum(r[0] for r in res)
     luma_blocks = sum(r[0] for r in res[0::3])

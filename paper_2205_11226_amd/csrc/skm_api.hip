@@ -655,6 +655,11 @@ PoolLayout pool_layout(const DevParams& p, int nf) {
   return L;
 }
 
+int group_hql_slots(const skm_ctx* c, const DevParams& p) {
+  const int n = hql_slots(p);
+  return c->hql_grid > 0 && c->hql_grid < n ? c->hql_grid : n;
+}
+
 // Workspace and batch arguments of group g for nf frames of p's geometry.
 // The round states and cell tables (the front of the pool) must be zero
 // between launches: they are cleared when the pool is new or its layout
@@ -754,10 +759,6 @@ int group_fin_grid(const DevParams& p, int nf) {
   return (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
 }
 
-int group_hql_slots(const skm_ctx* c, const DevParams& p) {
-  return c->hql_grid > 0 && c->hql_grid < hql_slots(p) ? c->hql_grid : hql_slots(p);
-}
-
 skm_status launch_round_b(skm_ctx* c, GroupSlot* g, hipStream_t s) {
   const DevParams& p = g->p;
   const BatchArgs& b = g->b;
@@ -781,9 +782,14 @@ skm_status launch_round_b(skm_ctx* c, GroupSlot* g, hipStream_t s) {
     SKM_HIP(hipEventRecord(g->ev[2 * k + 1], s), "hipEventRecord");
     g->ev_used = k + 1;
   }
-  if (mode_uses_hql(p.mode))
-    SKM_HIP(launch_hql_b(b, p, g->d_hql_ws, hql_slot_bytes(p), group_hql_slots(c, p), s),
-            "batched HQL kernel");
+  // HQL: the single-frame kernel once per frame, in frame order, on the
+  // group's scratch slots (a frame without HQL blocks returns at once)
+  if (mode_uses_hql(p.mode)) {
+    const int hg = group_hql_slots(c, p);
+    for (int f = 0; f < b.nf; ++f)
+      SKM_HIP(launch_hql(group_frame_host(g, f), p, g->d_hql_ws, hql_slot_bytes(p), hg, s),
+              "HQL kernel");
+  }
   SKM_HIP(launch_finalize_b(b, p, group_fin_grid(p, b.nf), s), "batched finalize kernel");
   return SKM_OK;
 }
@@ -809,8 +815,11 @@ skm_status group_enqueue(skm_ctx* c, GroupSlot* g, int R) {
   // with kernel timing on, launches are eager (events recorded by graph
   // nodes cannot be queried for elapsed time)
   if (!c->use_graphs || c->prof) return group_enqueue_eager(c, g, R, g->stream);
+  // the HQL launches take each frame's caller buffers as arguments, so with
+  // HQL the buffers are part of the key
+  const size_t io_bytes = mode_uses_hql(g->p.mode) ? sizeof(FrameIO) * g->b.nf : 0;
   std::vector<unsigned char> key(sizeof(BatchArgs) + sizeof(DevParams) + 4 * sizeof(int) +
-                                 2 * sizeof(float) + sizeof(void*));
+                                 2 * sizeof(float) + sizeof(void*) + io_bytes);
   unsigned char* kp = key.data();
   memcpy(kp, &g->b, sizeof(BatchArgs)); kp += sizeof(BatchArgs);
   memcpy(kp, &g->p, sizeof(DevParams)); kp += sizeof(DevParams);
@@ -818,7 +827,8 @@ skm_status group_enqueue(skm_ctx* c, GroupSlot* g, int R) {
   memcpy(kp, ints, sizeof(ints)); kp += sizeof(ints);
   memcpy(kp, &c->tau1, sizeof(float)); kp += sizeof(float);
   memcpy(kp, &c->tau2, sizeof(float)); kp += sizeof(float);
-  memcpy(kp, &c->d_cnn, sizeof(void*));
+  memcpy(kp, &c->d_cnn, sizeof(void*)); kp += sizeof(void*);
+  if (io_bytes) memcpy(kp, g->h_io, io_bytes);
   if (!g->gexec || key != g->gkey) {
     if (g->gexec) { (void)hipGraphExecDestroy(g->gexec); g->gexec = nullptr; }
     g->gkey.clear();

@@ -18,6 +18,9 @@
 // The candidate set is every admissible candidate whose ring covers all of
 // the block's known context pixels.  All algebra is FP64; the covariance
 // comes from an exact integer Gram (v_dot4_u32_u8 on the 8-bit pixels).
+// The dense FP64 contractions (blocked Cholesky with the explicit inverse
+// factor L^-1, whitening, A = C_XY C_YY^-1, the leave-one-out distances and
+// sums) run on 64 x 64 output tiles of v_mfma_f64_16x16x4f64.
 // Scratch: one global slot per workgroup (layout in hql_layout).
 #include "skm_device.h"
 
@@ -25,6 +28,8 @@ namespace skm {
 
 struct HqlLayout {
   size_t yt, xt, cyy, axy, v, v0, y0, meany, meanx, dm0, ytil, xtil, vn, dch, zch, i0;
+  size_t li, tmp;   // L^-1 (NY x NY), and a staging block of max(B^2, 64) rows
+  size_t rs;        // exact byte row sums of yt, xt (and ot)
   // partly known contexts (hql_partial): availability bytes, overlap counts,
   // integer Grams of the masks (gn), of values by masks (gs, gsx), and a copy
   // of C_YY for the repair's retries
@@ -60,6 +65,9 @@ __host__ __device__ inline HqlLayout hql_layout(const DevParams& p) {
   h.dch = take(8 * 64 * MC);
   h.zch = take(8 * 64 * (B2 + NY));
   h.i0 = take(4 * MC);
+  h.li = take(8 * NY * NY);
+  h.tmp = take(8 * (B2 > 64 ? B2 : 64) * NY);
+  h.rs = take(4 * (2 * NY + B2));
   const bool pt = p.hql_partial != 0;
   h.ot = take(pt ? NY * h.ldm : 0);
   h.cn = take(pt ? 4 * MC : 0);
@@ -78,17 +86,41 @@ int hql_slots(const DevParams& p) {
   return n < (size_t)kHqlSlots ? kHqlSlots : (n > (size_t)kHqlSlotsMax ? kHqlSlotsMax : (int)n);
 }
 
+// LDS row pitch (doubles) of the MFMA operand tiles: rows k and k + 1 of a
+// tile start 128 bytes apart modulo 256, so the two half-waves of a read hit
+// disjoint banks
+constexpr int kTp = 80;
+constexpr size_t kGemmLds = (size_t)2 * 16 * kTp * 8;
+// LDS row pitch (bytes) of the int8 Gram tiles: 256 bytes of k a row, the
+// 16 row starts of a half-wave's reads on distinct 4-bank groups
+constexpr int kGk = 256;
+constexpr int kGp8 = kGk + 16;
+constexpr size_t kGramLds = (size_t)2 * 64 * kGp8;
+
+// the diagonal block of the blocked Cholesky and its inverse, pitch 65
+constexpr size_t kCholLds = (size_t)2 * 64 * 65 * 8;
+// the eps_y evaluations read the candidates' context bytes from LDS when
+// they fit in this much (NY x ldm bytes)
+constexpr size_t kEpsLds = 96 * 1024;
+
+__host__ __device__ inline bool hql_eps_in_lds(const HqlLayout& h) {
+  return (size_t)h.ny * h.ldm <= kEpsLds;
+}
+
 // the estimation kernel's layout, with the window region large enough for
 // the HQL tiles that reuse it
 size_t hql_lds_bytes(const DevParams& p) {
   size_t offs[10];
   main_lds_layout(p, offs);
+  const HqlLayout h = hql_layout(p);
   size_t need = (size_t)4 * p.Wd * p.Wd;
-  need = need > 16384 ? need : 16384;                      // FP64 GEMM tiles
-  need = need > 2 * 16 * 65 * 8 ? need : 2 * 16 * 65 * 8;   // (pitch 65 for the sums)
-  need = need > (size_t)2 * 64 * 17 * 4 ? need : (size_t)2 * 64 * 17 * 4;   // Gram tiles
-  const size_t ny = (size_t)p.NR + (size_t)p.B * p.B;
-  need = need > 8 * ny ? need : 8 * ny;                     // Cholesky pivot row
+  need = need > kGemmLds ? need : kGemmLds;
+  need = need > kCholLds ? need : kCholLds;
+  need = need > kGramLds ? need : kGramLds;
+  if (hql_eps_in_lds(h)) {
+    const size_t ye = (size_t)h.ny * h.ldm;
+    need = need > ye ? need : ye;
+  }
   return align_up(offs[9] + need, 16);
 }
 
@@ -106,8 +138,7 @@ constexpr double kEpsTieRel = 1e-12;
 struct HqlShared {
   double red[kThreads / 64];
   double eg[33];                 // eps_y on the beta grid g = -8 .. 24
-  double dk, lam, S, eps, dmin;
-  int fail;
+  double S;
   double rowS[64];
 };
 
@@ -129,115 +160,290 @@ static __device__ __forceinline__ double block_min_d(double v, double* red) {
   return fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
 }
 
-// Covariance block from the exact integer Gram of two u8 row sets:
-// out[i*ldo + j] = (sum_k P[i][k] Q[j][k]) / M - mp[i] mq[j].  Rows have
-// leading dimension ld (zero padded beyond M, multiple of 64).  64x64
-// output tiles, K staged 64 bytes at a time in LDS, 4x4 per thread,
-// v_dot4_u32_u8.  With sym (P == Q), only the lower tiles are computed and
-// mirrored.
-static __device__ void gram_cov(const uint8_t* P, const uint8_t* Q, int R1, int R2, int ld, int M,
-                                double* out, int ldo, const double* mp, const double* mq, bool sym,
-                                uint32_t* ta, uint32_t* tb) {
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  const int nt1 = (R1 + 63) / 64, nt2 = (R2 + 63) / 64;
-  const double invM = 1.0 / (double)M;
-  for (int t1 = 0; t1 < nt1; ++t1) {
-    for (int t2 = 0; t2 < nt2; ++t2) {
-      if (sym && t2 > t1) continue;
-      uint32_t acc[4][4];
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// C = A B on FP64 MFMA, one workgroup, 64 x 64 output tiles in raster order.
+// Wave w holds the 32 x 32 quarter (w / 2, w % 2) of a tile as 2 x 2
+// v_mfma_f64_16x16x4f64 accumulators; k advances 16 at a time through LDS
+// (tl: two 16 x kTp tiles), the next step's operands loaded into registers
+// while the current one is multiplied.  Operands are read element-wise by
+// fa(m, k) and fb(k, n); AK (BK) says that consecutive k of A (B) are
+// adjacent in memory, which picks the staging order that keeps each wave's
+// loads contiguous.  tiles(mt, nt, kb, ke) sets the k range of output tile
+// (mt, nt) and returns false for a tile that is not wanted (triangular
+// operands skip their zero blocks this way).  epi(m, n, v) gets every output
+// of a wanted tile once, always from the same lane, in a fixed order.
+template <bool AK, bool BK, class FA, class FB, class FT, class FE>
+static __device__ void gemm_f64(int M, int N, FA fa, FB fb, FT tiles, FE epi, double* tl) {
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  double* As = tl;
+  double* Bs = tl + 16 * kTp;
+  const int ntm = (M + 63) >> 6, ntn = (N + 63) >> 6;
+  const int mw = 32 * (wave >> 1), nw = 32 * (wave & 1);
+  const int li = lane & 15, lk = lane >> 4;
+  const int am = AK ? (tid >> 4) : (tid & 63), ak = AK ? (tid & 15) : (tid >> 6);
+  const int bn = BK ? (tid >> 4) : (tid & 63), bk = BK ? (tid & 15) : (tid >> 6);
+  for (int t = 0; t < ntm * ntn; ++t) {
+    const int mt = t / ntn, nt = t - mt * ntn;
+    int kb = 0, ke = 0;
+    if (!tiles(mt, nt, kb, ke)) continue;
+    const int m0 = mt * 64, n0 = nt * 64;
+    f64x4 acc[2][2];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0u;
-      for (int kk = 0; kk < ld; kk += 64) {
-        // stage 64 rows x 16 words of each operand (row pitch 17 words)
-        for (int e = tid; e < 64 * 16; e += kThreads) {
-          const int row = e >> 4, w = e & 15;
-          const int r1 = t1 * 64 + row, r2 = t2 * 64 + row;
-          ta[row * 17 + w] = r1 < R1 ? *(const uint32_t*)(P + (size_t)r1 * ld + kk + 4 * w) : 0u;
-          tb[row * 17 + w] = r2 < R2 ? *(const uint32_t*)(Q + (size_t)r2 * ld + kk + 4 * w) : 0u;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int w = 0; w < 16; ++w) {
-          uint32_t av[4], bv[4];
+      for (int y = 0; y < 2; ++y) acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+    double ra[4], rb[4];
+    auto load = [&](int k0) {
 #pragma unroll
-          for (int a = 0; a < 4; ++a) av[a] = ta[(ty * 4 + a) * 17 + w];
-#pragma unroll
-          for (int b = 0; b < 4; ++b) bv[b] = tb[(tx * 4 + b) * 17 + w];
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_udot4(av[a], bv[b], acc[a][b], false);
-        }
-        __syncthreads();
+      for (int s = 0; s < 4; ++s) {
+        const int m = m0 + am + (AK ? 16 * s : 0), k = k0 + ak + (AK ? 0 : 4 * s);
+        ra[s] = (m < M && k < ke) ? fa(m, k) : 0.0;
+        const int n = n0 + bn + (BK ? 16 * s : 0), kk = k0 + bk + (BK ? 0 : 4 * s);
+        rb[s] = (n < N && kk < ke) ? fb(kk, n) : 0.0;
       }
+    };
+    load(kb);
+    for (int k0 = kb; k0 < ke; k0 += 16) {
+      __syncthreads();                       // the previous step's reads are done
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
+      for (int s = 0; s < 4; ++s) {
+        As[(ak + (AK ? 0 : 4 * s)) * kTp + am + (AK ? 16 * s : 0)] = ra[s];
+        Bs[(bk + (BK ? 0 : 4 * s)) * kTp + bn + (BK ? 16 * s : 0)] = rb[s];
+      }
+      __syncthreads();
+      if (k0 + 16 < ke) load(k0 + 16);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int i = t1 * 64 + ty * 4 + a, j = t2 * 64 + tx * 4 + b;
-          if (i < R1 && j < R2) {
-            const double c = (double)acc[a][b] * invM - mp[i] * mq[j];
-            out[(size_t)i * ldo + j] = c;
-            if (sym) out[(size_t)j * ldo + i] = c;
-          }
-        }
+      for (int k4 = 0; k4 < 4; ++k4) {
+        const double* ar = As + (4 * k4 + lk) * kTp;
+        const double* br = Bs + (4 * k4 + lk) * kTp;
+        const double a0 = ar[mw + li], a1 = ar[mw + 16 + li];
+        const double b0 = br[nw + li], b1 = br[nw + 16 + li];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
       }
     }
+    // accumulator layout of v_mfma_f64_16x16x4f64: lane l, element r holds
+    // row l / 16 + 4 r, column l % 16 of its 16 x 16 block
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + mw + 16 * x + lk + 4 * r, n = n0 + nw + 16 * y + li;
+          if (m < M && n < N) epi(m, n, acc[x][y][r]);
+        }
   }
   __syncthreads();
 }
 
-// Exact integer Gram P Q^T (rows of P and Q are R1 and R2 byte vectors of
-// length ld, zero padded) stored as Out, without normalisation: the tiles of
-// gram_cov.
-template <typename Out>
-static __device__ void gram_raw(const uint8_t* P, const uint8_t* Q, int R1, int R2, int ld,
-                                Out* out, int ldo, bool sym, uint32_t* ta, uint32_t* tb) {
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+// C (n x n, row stride ld, lower triangle) = L L^T by 64-wide block columns,
+// right-looking: the diagonal block is factored in LDS and inverted there;
+// the panel below it, L_ik = C_ik L_kk^-T, and the trailing update
+// C_ij -= L_ik L_jk^T run on gemm_f64.  Then Li = L^-1 (lower, zeros above
+// the diagonal inside the diagonal blocks) block row by block row:
+// Li_ik = -L_ii^-1 sum_{k <= m < i} L_im Li_mk.  C's strictly lower blocks
+// end up holding L.  Returns false, uniformly, at the first pivot that is
+// not positive.  tmp: 64 x ld doubles; lds: kCholLds bytes.
+static __device__ bool chol_inv(double* C, int ld, int n, double* Li, double* tmp, double* lds) {
+  const int tid = threadIdx.x;
+  double* D = lds;
+  double* Di = lds + 64 * 65;
+  const int nb = (n + 63) >> 6;
+  for (int kb = 0; kb < nb; ++kb) {
+    const int k0 = 64 * kb, kn = min(64, n - k0);
+    for (int e = tid; e < 64 * 64; e += kThreads) {
+      const int i = e >> 6, j = e & 63;
+      D[i * 65 + j] = (i < kn && j <= i) ? C[(size_t)(k0 + i) * ld + k0 + j] : 0.0;
+      Di[i * 65 + j] = 0.0;
+    }
+    __syncthreads();
+    // unblocked right-looking factorisation of the diagonal block; column j
+    // is scaled after the barrier that ends its trailing update (nobody
+    // reads it then)
+    for (int j = 0; j < kn; ++j) {
+      const double dd = D[j * 65 + j];
+      if (!(dd > 0.0)) return false;          // uniform: written before a barrier
+      const double d = sqrt(dd), inv = 1.0 / d;
+      for (int e = tid; e < 64 * 64; e += kThreads) {
+        const int i = e >> 6, l = e & 63;
+        if (l > j && l <= i && i < kn)
+          D[i * 65 + l] -= (D[i * 65 + j] * inv) * (D[l * 65 + j] * inv);
+      }
+      __syncthreads();
+      for (int i = j + tid; i < kn; i += kThreads) D[i * 65 + j] = i == j ? d : D[i * 65 + j] * inv;
+    }
+    __syncthreads();
+    // Di = D^-1 row by row: Di_ic = (delta_ic - sum_{c <= m < i} D_im Di_mc) / D_ii,
+    // four lanes per column c, each over every fourth m
+    {
+      const int c = tid >> 2, part = tid & 3;
+      for (int i = 0; i < kn; ++i) {
+        double s = 0.0;
+        if (c < i)
+          for (int m = c + part; m < i; m += 4) s += D[i * 65 + m] * Di[m * 65 + c];
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (part == 0 && c <= i) Di[i * 65 + c] = ((i == c ? 1.0 : 0.0) - s) / D[i * 65 + i];
+        __syncthreads();
+      }
+    }
+    for (int e = tid; e < kn * 64; e += kThreads) {
+      const int i = e >> 6, c = e & 63;
+      if (c < kn) Li[(size_t)(k0 + i) * ld + k0 + c] = Di[i * 65 + c];
+    }
+    __syncthreads();
+    const int r0 = k0 + 64, nr = n - r0;
+    if (nr <= 0) continue;
+    // panel: L_ik[i][c] = sum_m C_ik[i][m] Di[c][m]  (in place, row tiles disjoint)
+    gemm_f64<true, true>(
+        nr, kn, [&](int i, int m) { return C[(size_t)(r0 + i) * ld + k0 + m]; },
+        [&](int m, int c) { return Li[(size_t)(k0 + c) * ld + k0 + m]; },
+        [&](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = kn; return true; },
+        [&](int i, int c, double v) { C[(size_t)(r0 + i) * ld + k0 + c] = v; }, lds);
+    // trailing update of the lower tiles
+    gemm_f64<true, true>(
+        nr, nr, [&](int i, int m) { return C[(size_t)(r0 + i) * ld + k0 + m]; },
+        [&](int m, int l) { return C[(size_t)(r0 + l) * ld + k0 + m]; },
+        [&](int mt, int nt, int& kb_, int& ke_) { kb_ = 0; ke_ = kn; return nt <= mt; },
+        [&](int i, int l, double v) { C[(size_t)(r0 + i) * ld + r0 + l] -= v; }, lds);
+  }
+  for (int ib = 1; ib < nb; ++ib) {
+    const int i0 = 64 * ib, in = min(64, n - i0);
+    // S = L[i0 .., 0 .. i0) Li[0 .. i0, 0 .. i0), then Li[i0 .., 0 .. i0) = -Di S
+    gemm_f64<true, false>(
+        in, i0, [&](int r, int m) { return C[(size_t)(i0 + r) * ld + m]; },
+        [&](int m, int c) { return Li[(size_t)m * ld + c]; },
+        [&](int, int nt, int& kb_, int& ke_) { kb_ = 64 * nt; ke_ = i0; return true; },
+        [&](int r, int c, double v) { tmp[(size_t)r * ld + c] = v; }, lds);
+    gemm_f64<true, false>(
+        in, i0, [&](int r, int m) { return Li[(size_t)(i0 + r) * ld + i0 + m]; },
+        [&](int m, int c) { return tmp[(size_t)m * ld + c]; },
+        [&](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = in; return true; },
+        [&](int r, int c, double v) { Li[(size_t)(i0 + r) * ld + c] = -v; }, lds);
+  }
+  return true;
+}
+
+// Sums of eight per-lane values over a wave in ten lane exchanges: after
+// halving steps over lane bits 5, 4, 3 each lane carries one of the eight
+// rows, then bits 2..0 finish the sum.  Lane 8 c returns row c's total
+// (c = bits 5..3 of the lane).  The order is fixed.
+static __device__ __forceinline__ double reduce8(const double (&v)[8]) {
+  const int lane = lane_id();
+  const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0;
+  double u[4], w[2];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    u[r] = (h5 ? v[r + 4] : v[r]) + __shfl_xor(h5 ? v[r] : v[r + 4], 32, 64);
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+    w[r] = (h4 ? u[r + 2] : u[r]) + __shfl_xor(h4 ? u[r] : u[r + 2], 16, 64);
+  double x = (h3 ? w[1] : w[0]) + __shfl_xor(h3 ? w[0] : w[1], 8, 64);
+  x += __shfl_xor(x, 4, 64);
+  x += __shfl_xor(x, 2, 64);
+  x += __shfl_xor(x, 1, 64);
+  return x;
+}
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// Exact row sums of a byte matrix (R rows of ld bytes, ld a multiple of 16,
+// rows 16-byte aligned): a wave per row.
+static __device__ void byte_row_sums(const uint8_t* P, int R, int ld, int* out) {
+  const int lane = lane_id(), wave = wave_id();
+  for (int a = wave; a < R; a += kThreads / 64) {
+    const uint4* row = reinterpret_cast<const uint4*>(P + (size_t)a * ld);
+    uint32_t s = 0;
+    for (int c = lane; c < ld / 16; c += 64) {
+      const uint4 v = row[c];
+      s = __builtin_amdgcn_udot4(v.x, 0x01010101u, s, false);
+      s = __builtin_amdgcn_udot4(v.y, 0x01010101u, s, false);
+      s = __builtin_amdgcn_udot4(v.z, 0x01010101u, s, false);
+      s = __builtin_amdgcn_udot4(v.w, 0x01010101u, s, false);
+    }
+    const int t = wave_sum((int)s);
+    if (lane == 0) out[a] = t;
+  }
+}
+
+// Exact integer Gram G = P Q^T of two u8 row sets (R1 and R2 rows of ld
+// bytes, zero padded, ld a multiple of 64) on v_mfma_i32_16x16x64_i8.  The
+// bytes enter the signed product as p - 128, so that
+//   sum_k p_k q_k = sum_k (p_k - 128)(q_k - 128) + 128 (sp + sq) - 128^2 ld
+// with the exact row sums sp[i], sq[j]; every term stays below 2^31 for
+// ld <= 2^16.  64 x 64 output tiles (with sym, P == Q and only tiles on or
+// below the diagonal), k staged kGk bytes at a time through LDS (t8:
+// kGramLds bytes); wave w holds the 32 x 32 quarter (w / 2, w % 2) as 2 x 2
+// accumulators whose element r of lane l is row 4 (l / 16) + r, column
+// l % 16.  epi(i, j, g) gets each entry of a computed tile once.
+template <class FE>
+static __device__ void gram_i8(const uint8_t* P, const uint8_t* Q, int R1, int R2, int ld,
+                               const int* sp, const int* sq, bool sym, FE epi, uint8_t* t8) {
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  uint8_t* ta = t8;
+  uint8_t* tb = t8 + 64 * kGp8;
   const int nt1 = (R1 + 63) / 64, nt2 = (R2 + 63) / 64;
+  const int mw = 32 * (wave >> 1), nw = 32 * (wave & 1);
+  const int li = lane & 15, lk = lane >> 4;
+  const int srow = tid >> 2, sseg = tid & 3;      // staging: 4 x 16 bytes per thread and operand
+  const int corr = 16384 * ld;
   for (int t1 = 0; t1 < nt1; ++t1) {
     for (int t2 = 0; t2 < nt2; ++t2) {
       if (sym && t2 > t1) continue;
-      uint32_t acc[4][4];
+      i32x4 acc[2][2];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0u;
-      for (int kk = 0; kk < ld; kk += 64) {
-        for (int e = tid; e < 64 * 16; e += kThreads) {
-          const int row = e >> 4, w = e & 15;
-          const int r1 = t1 * 64 + row, r2 = t2 * 64 + row;
-          ta[row * 17 + w] = r1 < R1 ? *(const uint32_t*)(P + (size_t)r1 * ld + kk + 4 * w) : 0u;
-          tb[row * 17 + w] = r2 < R2 ? *(const uint32_t*)(Q + (size_t)r2 * ld + kk + 4 * w) : 0u;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int w = 0; w < 16; ++w) {
-          uint32_t av[4], bv[4];
+        for (int y = 0; y < 2; ++y) acc[x][y] = i32x4{0, 0, 0, 0};
+      const int r1 = t1 * 64 + srow, r2 = t2 * 64 + srow;
+      for (int kk = 0; kk < ld; kk += kGk) {
+        uint4 va[4], vb[4];
 #pragma unroll
-          for (int a = 0; a < 4; ++a) av[a] = ta[(ty * 4 + a) * 17 + w];
-#pragma unroll
-          for (int b = 0; b < 4; ++b) bv[b] = tb[(tx * 4 + b) * 17 + w];
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_udot4(av[a], bv[b], acc[a][b], false);
-        }
-        __syncthreads();
-      }
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int i = t1 * 64 + ty * 4 + a, j = t2 * 64 + tx * 4 + b;
-          if (i < R1 && j < R2) {
-            out[(size_t)i * ldo + j] = (Out)acc[a][b];
-            if (sym) out[(size_t)j * ldo + i] = (Out)acc[a][b];
+        for (int s = 0; s < 4; ++s) {
+          const int k = kk + 16 * (sseg + 4 * s);
+          uint4 a = {0u, 0u, 0u, 0u}, b = {0u, 0u, 0u, 0u};
+          if (k < ld) {
+            if (r1 < R1) a = *reinterpret_cast<const uint4*>(P + (size_t)r1 * ld + k);
+            if (r2 < R2) b = *reinterpret_cast<const uint4*>(Q + (size_t)r2 * ld + k);
+            a.x ^= 0x80808080u; a.y ^= 0x80808080u; a.z ^= 0x80808080u; a.w ^= 0x80808080u;
+            b.x ^= 0x80808080u; b.y ^= 0x80808080u; b.z ^= 0x80808080u; b.w ^= 0x80808080u;
           }
+          va[s] = a;
+          vb[s] = b;
+        }
+        __syncthreads();                       // the previous step's reads are done
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          *reinterpret_cast<uint4*>(ta + srow * kGp8 + 16 * (sseg + 4 * s)) = va[s];
+          *reinterpret_cast<uint4*>(tb + srow * kGp8 + 16 * (sseg + 4 * s)) = vb[s];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k64 = 0; k64 < kGk / 64; ++k64) {
+          const int ko = 64 * k64 + 16 * lk;
+          const i32x4 a0 = *reinterpret_cast<const i32x4*>(ta + (mw + li) * kGp8 + ko);
+          const i32x4 a1 = *reinterpret_cast<const i32x4*>(ta + (mw + 16 + li) * kGp8 + ko);
+          const i32x4 b0 = *reinterpret_cast<const i32x4*>(tb + (nw + li) * kGp8 + ko);
+          const i32x4 b1 = *reinterpret_cast<const i32x4*>(tb + (nw + 16 + li) * kGp8 + ko);
+          acc[0][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b1, acc[1][1], 0, 0, 0);
         }
       }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = t1 * 64 + mw + 16 * x + 4 * lk + r, j = t2 * 64 + nw + 16 * y + li;
+            if (i < R1 && j < R2) epi(i, j, acc[x][y][r] + 128 * (sp[i] + sq[j]) - corr);
+          }
     }
   }
   __syncthreads();
@@ -246,10 +452,14 @@ static __device__ void gram_raw(const uint8_t* P, const uint8_t* Q, int R1, int 
 // One evaluation of eps_y(beta) (eq. epsy): weights e_j = exp(-dm0_j/(2 beta)
 // - max), S = sum e_j, y~ = sum e_j y_j / S; returns ||y0 - y~||^2.  Leaves
 // ew, S (in hs.S) and ytil for the caller.  With xt != nullptr also x~.
+// ys: the candidates' context bytes (Ny rows of ldm, zero padded; in LDS or
+// global memory).  A wave takes eight rows at a time; a lane takes four
+// consecutive candidates of four 256-candidate strips per step (32 loads in
+// flight), then reduce8 sums the rows.
 static __device__ double eval_eps(double beta, int Mc, int Ny, int B2, int ldm, const double* dm0,
-                                  double dmin, double* ew, const uint8_t* yt, const uint8_t* xt,
+                                  double dmin, double* ew, const uint8_t* ys, const uint8_t* xt,
                                   const double* y0, double* ytil, double* xtil, HqlShared& hs) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   const double inv2b = 1.0 / (2.0 * beta);      // one division per evaluation
   const double m = -dmin * inv2b;
   double s = 0.0;
@@ -259,53 +469,49 @@ static __device__ double eval_eps(double beta, int Mc, int Ny, int B2, int ldm, 
     s += e;
   }
   const double S = block_sum_d(s, hs.red);     // barrier: ew visible
-  // eight rows per wave at a time; a lane takes four consecutive candidates
-  // per step (one 32-bit load per row: the byte rows are zero-padded to ldm,
-  // a multiple of 64), then fixed-order wave sums
-  const int lane = lane_id(), wave = wave_id();
+  const int R = xt ? Ny + B2 : Ny;
   double part = 0.0;
-  auto rows8 = [&](const uint8_t* base, int a0, int nrow, double* acc) {
+  for (int a0 = 8 * wave; a0 < R; a0 += 8 * (kThreads / 64)) {
+    const uint8_t* rp[8];
+    bool ok[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int a = a0 + r;
+      ok[r] = a < R;
+      rp[r] = a < Ny ? ys + (size_t)a * ldm : xt + (size_t)(a < R ? a - Ny : 0) * ldm;
+    }
+    double acc[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) acc[r] = 0.0;
-    for (int j = 4 * lane; j < Mc; j += 256) {
-      double e[4];
+    for (int j0 = 4 * lane; j0 < Mc; j0 += 1024) {
+      uint32_t w[4][8];
+      double e[4][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) e[q] = j + q < Mc ? ew[j + q] : 0.0;
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + 256 * q;
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        if (a0 + r < nrow) {
-          const uint32_t w = *reinterpret_cast<const uint32_t*>(base + (size_t)(a0 + r) * ldm + j);
-          acc[r] += e[0] * (double)(w & 0xffu) + e[1] * (double)((w >> 8) & 0xffu) +
-                    e[2] * (double)((w >> 16) & 0xffu) + e[3] * (double)(w >> 24);
-        }
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 8; ++r) acc[r] = wave_sum(acc[r]);
-  };
-  for (int a0 = 8 * wave; a0 < Ny; a0 += 8 * (kThreads / 64)) {
-    double acc[8];
-    rows8(yt, a0, Ny, acc);
-    if (lane == 0) {
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        if (a0 + r < Ny) {
-          const double yt_a = acc[r] / S;
-          ytil[a0 + r] = yt_a;
-          const double d = y0[a0 + r] - yt_a;
-          part += d * d;
-        }
-      }
-    }
-  }
-  if (xt) {
-    for (int q0 = 8 * wave; q0 < B2; q0 += 8 * (kThreads / 64)) {
-      double acc[8];
-      rows8(xt, q0, B2, acc);
-      if (lane == 0) {
+        for (int t = 0; t < 4; ++t) e[q][t] = j + t < Mc ? ew[j + t] : 0.0;
 #pragma unroll
         for (int r = 0; r < 8; ++r)
-          if (q0 + r < B2) xtil[q0 + r] = acc[r] / S;
+          w[q][r] = (ok[r] && j < Mc) ? *reinterpret_cast<const uint32_t*>(rp[r] + j) : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+          acc[r] += e[q][0] * (double)(w[q][r] & 0xffu) + e[q][1] * (double)((w[q][r] >> 8) & 0xffu) +
+                    e[q][2] * (double)((w[q][r] >> 16) & 0xffu) + e[q][3] * (double)(w[q][r] >> 24);
+    }
+    const double tot = reduce8(acc);
+    if ((lane & 7) == 0) {
+      const int a = a0 + (lane >> 3);
+      if (a < Ny) {
+        const double yv = tot / S;
+        ytil[a] = yv;
+        const double d = y0[a] - yv;
+        part += d * d;
+      } else if (a < R) {
+        xtil[a - Ny] = tot / S;
       }
     }
   }
@@ -313,19 +519,18 @@ static __device__ double eval_eps(double beta, int Mc, int Ny, int B2, int ldm, 
   return block_sum_d(part, hs.red);
 }
 
-// The HQL blocks h = blockIdx.x, blockIdx.x + gridDim.x, ... of one frame's
-// list (n_hql entries).  `first` is true until the workgroup has taken a
-// block (from any frame).
-static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevParams& p,
+// HQL for entry h of one frame's list, on this workgroup's scratch slot.
+// The caller has run phase_tables; `first` is true for the workgroup's first
+// block of the launch.
+static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevParams& p,
                                                  unsigned char* ws, size_t slot_bytes, int round,
-                                                 int n_hql, bool& first, unsigned char* lds_raw,
+                                                 int h, bool first, unsigned char* lds_raw,
                                                  BlockShared& sh, HqlShared& hs, int* pend) {
   const MainLds L = carve_main_lds(lds_raw, p);
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   const int B = p.B, r = p.r, W = p.W, Wd = p.Wd;
   const int B2 = B * B;
   const int qbase = W * Wd + W;
-  phase_tables(p, L, sh);
   const int NU = sh.NU;
 
   const HqlLayout hl = hql_layout(p);
@@ -356,21 +561,21 @@ static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevPa
   int* gs = (int*)(slot + hl.gs);
   int* gsx = (int*)(slot + hl.gsx);
   double* cyy0 = (double*)(slot + hl.cyy0);
+  double* Li = (double*)(slot + hl.li);
+  double* tmp = (double*)(slot + hl.tmp);
+  int* rsy = (int*)(slot + hl.rs);
+  int* rso = rsy + hl.ny;
+  int* rsx = rso + hl.ny;
   const int ldm = hl.ldm, ldz = hl.ldz, NRs = hl.ny;      // NRs: row stride of Ny rows
 
   // LDS reuse once the window has been gathered
-  uint32_t* ta = (uint32_t*)L.winp;                  // gram tiles, 2 x 64 x 17 words
-  uint32_t* tb = ta + 64 * 17;
-  double* piv = (double*)L.winp;                     // Cholesky pivot row
-  double* ga = (double*)L.winp;                      // FP64 GEMM tiles, 2 x 16 x 64
-  double* gb = ga + 16 * 64;
-  double* ca = ga;                                   // leave-one-out sums: 2 x 16 x 64,
-  double* cb = ga + 16 * 65;                         //   row pitch 65
+  uint8_t* t8 = (uint8_t*)L.winp;                    // int8 Gram tiles
+  double* tl = (double*)L.winp;                      // MFMA operand tiles / Cholesky blocks
   uint16_t* m0off = (uint16_t*)L.qu;                 // known ring pixels (footprint offsets)
   uint16_t* compo = L.selo;                          // complete candidates: window offset
   int* compd = (int*)L.selw;                         //   and exact Euclidean distance
 
-  for (int h = blockIdx.x; h < n_hql; h += gridDim.x) {
+  {
     const int i = a.hql_list[h];
     const int cell = a.blk[i];
     const int by = cell / p.gw, bx = cell - by * p.gw;
@@ -383,7 +588,6 @@ static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevPa
       for (int k = tid; k < 2 * Wd; k += kThreads) L.rowbits[k] = 0ull;
       __syncthreads();
     }
-    first = false;
     phase_stage(a, p, L, x0 - r - W, y0 - r - W);
     // context units: the ring, then the block's own pixel pairs if it holds
     // received pixels
@@ -465,24 +669,26 @@ static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevPa
       y0v[aa] = (double)(int)(int16_t)(L.winp[qbase + m0off[aa]] & 0xffffu);
     __syncthreads();
     if (!hp) {
-      // column means: a wave per row, exact integer sums
-      for (int aa = wave; aa < Ny; aa += kThreads / 64) {
-        int s = 0;
-        for (int k = lane; k < Mc; k += 64) s += yt[(size_t)aa * ldm + k];
-        s = wave_sum(s);
-        if (lane == 0) meany[aa] = (double)s / (double)Mc;
-      }
-      for (int q = wave; q < B2; q += kThreads / 64) {
-        int s = 0;
-        for (int k = lane; k < Mc; k += 64) s += xt[(size_t)q * ldm + k];
-        s = wave_sum(s);
-        if (lane == 0) meanx[q] = (double)s / (double)Mc;
-      }
+      // column means from exact integer row sums
+      byte_row_sums(yt, Ny, ldm, rsy);
+      byte_row_sums(xt, B2, ldm, rsx);
+      __syncthreads();
+      for (int aa = tid; aa < Ny; aa += kThreads) meany[aa] = (double)rsy[aa] / (double)Mc;
+      for (int q = tid; q < B2; q += kThreads) meanx[q] = (double)rsx[q] / (double)Mc;
       __syncthreads();
 
-      // -- covariance blocks C_YY (Ny x Ny) and C_XY (B2 x Ny), 1/M normalised
-      gram_cov(yt, yt, Ny, Ny, ldm, Mc, cyy, NRs, meany, meany, true, ta, tb);
-      gram_cov(xt, yt, B2, Ny, ldm, Mc, axy, NRs, meanx, meany, false, ta, tb);
+      // -- covariance blocks C_YY (Ny x Ny) and C_XY (B2 x Ny), 1/M
+      //    normalised: G / M - mean_i mean_j from the exact integer Grams
+      const double invM = 1.0 / (double)Mc;
+      gram_i8(yt, yt, Ny, Ny, ldm, rsy, rsy, true,
+              [&](int i, int j, int g) {
+                const double c = (double)g * invM - meany[i] * meany[j];
+                cyy[(size_t)i * NRs + j] = c;
+                cyy[(size_t)j * NRs + i] = c;
+              }, t8);
+      gram_i8(xt, yt, B2, Ny, ldm, rsx, rsy, false,
+              [&](int q, int j, int g) { axy[(size_t)q * NRs + j] = (double)g * invM - meanx[q] * meany[j]; },
+              t8);
     } else {
       // -- pairwise-complete covariance: for coordinates a, b the candidates
       //    knowing both (N_ab of them); exact integer Grams of the values
@@ -490,11 +696,23 @@ static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevPa
       //    C_ab = G_ab / N_ab - S_a(b) S_b(a) / N_ab^2 with S_a(b) the sum of
       //    coordinate a over those candidates (0 where N_ab = 0).  The x
       //    coordinates are always known: N_qb = N_bb.
-      gram_raw(yt, yt, Ny, Ny, ldm, cyy, NRs, true, ta, tb);
-      gram_raw(ot, ot, Ny, Ny, ldm, gn, Ny, true, ta, tb);
-      gram_raw(yt, ot, Ny, Ny, ldm, gs, Ny, false, ta, tb);
-      gram_raw(xt, yt, B2, Ny, ldm, axy, NRs, false, ta, tb);
-      gram_raw(xt, ot, B2, Ny, ldm, gsx, Ny, false, ta, tb);
+      byte_row_sums(yt, Ny, ldm, rsy);
+      byte_row_sums(xt, B2, ldm, rsx);
+      byte_row_sums(ot, Ny, ldm, rso);
+      __syncthreads();
+      gram_i8(yt, yt, Ny, Ny, ldm, rsy, rsy, true,
+              [&](int i, int j, int g) {
+                cyy[(size_t)i * NRs + j] = (double)g;
+                cyy[(size_t)j * NRs + i] = (double)g;
+              }, t8);
+      gram_i8(ot, ot, Ny, Ny, ldm, rso, rso, true,
+              [&](int i, int j, int g) { gn[i * Ny + j] = g; gn[j * Ny + i] = g; }, t8);
+      gram_i8(yt, ot, Ny, Ny, ldm, rsy, rso, false,
+              [&](int i, int j, int g) { gs[i * Ny + j] = g; }, t8);
+      gram_i8(xt, yt, B2, Ny, ldm, rsx, rsy, false,
+              [&](int q, int j, int g) { axy[(size_t)q * NRs + j] = (double)g; }, t8);
+      gram_i8(xt, ot, B2, Ny, ldm, rsx, rso, false,
+              [&](int q, int j, int g) { gsx[q * Ny + j] = g; }, t8);
       for (int e = tid; e < Ny * Ny; e += kThreads) {
         const int aa = e / Ny, bb = e - aa * Ny;
         const double n = (double)gn[e];
@@ -522,7 +740,7 @@ static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevPa
       __syncthreads();
     }
 
-    // -- ridge and Cholesky C_YY = L L^T (left-looking, in place, lower).
+    // -- ridge, then C_YY + lambda I = L L^T and Li = L^-1 (chol_inv).
     //    A pairwise-complete C_YY (hql_partial) need not be positive
     //    semi-definite: while a pivot is <= 0 the factorisation restarts
     //    from the saved C_YY with lambda ten times larger, at most
@@ -534,9 +752,9 @@ static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevPa
       tr = block_sum_d(tr, hs.red);
       lam0 = p.ridge_rel * tr / (double)Ny + 1e-12;
     }
+    bool factored = false;
     for (int rep = 0; rep <= (hp ? kPsdRepair : 0); ++rep) {
       if (rep > 0) {
-        __syncthreads();
         for (int e = tid; e < Ny * Ny; e += kThreads) {
           const int aa = e / Ny, bb = e - aa * Ny;
           cyy[(size_t)aa * NRs + bb] = cyy0[e];
@@ -545,36 +763,12 @@ static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevPa
       }
       const double lam = lam0 * kPow10[rep];
       for (int aa = tid; aa < Ny; aa += kThreads) cyy[(size_t)aa * NRs + aa] += lam;
-      if (tid == 0) hs.fail = 0;
       __syncthreads();
-      for (int k = 0; k < Ny; ++k) {
-        const double* rowk = cyy + (size_t)k * NRs;
-        for (int m = tid; m < k; m += kThreads) piv[m] = rowk[m];
-        if (wave == 0) {
-          double s = 0.0;
-          for (int m = lane; m < k; m += 64) s += rowk[m] * rowk[m];
-          s = wave_sum(s);
-          if (lane == 0) {
-            const double dd = rowk[k] - s;
-            if (!(dd > 0.0)) hs.fail = 1;
-            hs.dk = dd > 0.0 ? sqrt(dd) : 1.0;
-            cyy[(size_t)k * NRs + k] = hs.dk;
-          }
-        }
-        __syncthreads();
-        if (hs.fail) break;                 // uniform: written before the barrier
-        const double dk = hs.dk;
-        for (int ii = k + 1 + tid; ii < Ny; ii += kThreads) {
-          double* rowi = cyy + (size_t)ii * NRs;
-          double s = rowi[k];
-          for (int m = 0; m < k; ++m) s -= rowi[m] * piv[m];
-          rowi[k] = s / dk;
-        }
-        __syncthreads();
-      }
-      if (!hs.fail) break;
+      factored = chol_inv(cyy, NRs, Ny, Li, tmp, tl);
+      __syncthreads();
+      if (factored) break;
     }
-    if (hs.fail) {
+    if (!factored) {
       // C_YY + lambda I is not positive definite in FP64 (a pivot <= 0): the
       // covariance model of eq. kmmse does not exist for this block, which
       // takes the context mean of eq. mean, flagged
@@ -595,36 +789,28 @@ static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevPa
         if (pend) atomicSub(pend, 1);
       }
       __syncthreads();
-      continue;
+      return;
     }
-    const double* Lc = cyy;   // lower triangle holds L
 
-    // -- A = C_XY C_YY^-1: row q of C_XY solves L L^T a^T = c^T (in place)
-    for (int q = tid; q < B2; q += kThreads) {
-      double* row = axy + (size_t)q * NRs;
-      for (int k = 0; k < Ny; ++k) {
-        const double* lk = Lc + (size_t)k * NRs;
-        double s = row[k];
-        for (int m = 0; m < k; ++m) s -= lk[m] * row[m];
-        row[k] = s / lk[k];
-      }
-      for (int k = Ny - 1; k >= 0; --k) {
-        double s = row[k];
-        for (int m = k + 1; m < Ny; ++m) s -= Lc[(size_t)m * NRs + k] * row[m];
-        row[k] = s / Lc[(size_t)k * NRs + k];
-      }
-    }
-    // -- whitening: V[j] = L^-1 y_j for every candidate, v0 = L^-1 y0
-    for (int j = tid; j <= Mc; j += kThreads) {
-      double* row = j < Mc ? V + (size_t)j * NRs : v0;
-      for (int k = 0; k < Ny; ++k) {
-        const double* lk = Lc + (size_t)k * NRs;
-        double s = j < Mc ? (double)yt[(size_t)k * ldm + j] : y0v[k];
-        for (int m = 0; m < k; ++m) s -= lk[m] * row[m];
-        row[k] = s / lk[k];
-      }
-    }
-    __syncthreads();
+    // -- whitening: V[j] = L^-1 y_j for every candidate (row j of V), and
+    //    v0 = L^-1 y0 as row Mc; column tile nt of V needs k < 64 (nt + 1)
+    gemm_f64<false, true>(
+        Mc + 1, Ny,
+        [&](int j, int k) { return j < Mc ? (double)yt[(size_t)k * ldm + j] : y0v[k]; },
+        [&](int k, int aa) { return Li[(size_t)aa * NRs + k]; },
+        [&](int, int nt, int& kb_, int& ke_) { kb_ = 0; ke_ = min(Ny, 64 * nt + 64); return true; },
+        [&](int j, int aa, double v) { (j < Mc ? V + (size_t)j * NRs : v0)[aa] = v; }, tl);
+    // -- A = C_XY C_YY^-1 = (C_XY L^-T) L^-1: T in tmp, then A over C_XY
+    gemm_f64<true, true>(
+        B2, Ny, [&](int q, int k) { return axy[(size_t)q * NRs + k]; },
+        [&](int k, int ii) { return Li[(size_t)ii * NRs + k]; },
+        [&](int, int nt, int& kb_, int& ke_) { kb_ = 0; ke_ = min(Ny, 64 * nt + 64); return true; },
+        [&](int q, int ii, double v) { tmp[(size_t)q * NRs + ii] = v; }, tl);
+    gemm_f64<true, false>(
+        B2, Ny, [&](int q, int ii) { return tmp[(size_t)q * NRs + ii]; },
+        [&](int ii, int mm) { return Li[(size_t)ii * NRs + mm]; },
+        [&](int, int nt, int& kb_, int& ke_) { kb_ = 64 * nt; ke_ = Ny; return true; },
+        [&](int q, int mm, double v) { axy[(size_t)q * NRs + mm] = v; }, tl);
     // Mahalanobis distances to y0 and squared norms of the whitened candidates
     double dmin = INFINITY;
     for (int j = tid; j < Mc; j += kThreads) {
@@ -641,12 +827,24 @@ static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevPa
     }
     dmin = block_min_d(dmin, hs.red);
 
+    // -- the candidates' context bytes for the eps_y evaluations: an LDS
+    //    copy when they fit (the operand tiles are idle until the
+    //    leave-one-out sums)
+    const uint8_t* ys = yt;
+    if (hql_eps_in_lds(hl)) {
+      uint4* dst = (uint4*)L.winp;
+      const uint4* srcv = (const uint4*)yt;
+      for (int e = tid; e < Ny * ldm / 16; e += kThreads) dst[e] = srcv[e];
+      __syncthreads();
+      ys = (const uint8_t*)L.winp;
+    }
+
     // -- beta: first grid minimiser, golden-section refinement on log beta
     const double D0 = fmax(dmin, 1e-9);
     double emin = INFINITY;
     for (int g = -8; g <= 24; ++g) {
       const double bt = D0 * exp2((double)g / 2.0);
-      const double e = eval_eps(bt, Mc, Ny, B2, ldm, dm0, dmin, ew, yt, nullptr, y0v, ytil, nullptr, hs);
+      const double e = eval_eps(bt, Mc, Ny, B2, ldm, dm0, dmin, ew, ys, nullptr, y0v, ytil, nullptr, hs);
       if (tid == 0) hs.eg[g + 8] = e;
       emin = fmin(emin, e);
     }
@@ -663,21 +861,21 @@ static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevPa
       const double invphi = (sqrt(5.0) - 1.0) / 2.0;
       double ct = bt - invphi * (bt - at);
       double dt = at + invphi * (bt - at);
-      double fc = eval_eps(exp(ct), Mc, Ny, B2, ldm, dm0, dmin, ew, yt, nullptr, y0v, ytil, nullptr, hs);
-      double fd = eval_eps(exp(dt), Mc, Ny, B2, ldm, dm0, dmin, ew, yt, nullptr, y0v, ytil, nullptr, hs);
+      double fc = eval_eps(exp(ct), Mc, Ny, B2, ldm, dm0, dmin, ew, ys, nullptr, y0v, ytil, nullptr, hs);
+      double fd = eval_eps(exp(dt), Mc, Ny, B2, ldm, dm0, dmin, ew, ys, nullptr, y0v, ytil, nullptr, hs);
       for (int it = 0; it < 40; ++it) {
         if (fc <= fd) {
           bt = dt; dt = ct; fd = fc;
           ct = bt - invphi * (bt - at);
-          fc = eval_eps(exp(ct), Mc, Ny, B2, ldm, dm0, dmin, ew, yt, nullptr, y0v, ytil, nullptr, hs);
+          fc = eval_eps(exp(ct), Mc, Ny, B2, ldm, dm0, dmin, ew, ys, nullptr, y0v, ytil, nullptr, hs);
         } else {
           at = ct; ct = dt; fc = fd;
           dt = at + invphi * (bt - at);
-          fd = eval_eps(exp(dt), Mc, Ny, B2, ldm, dm0, dmin, ew, yt, nullptr, y0v, ytil, nullptr, hs);
+          fd = eval_eps(exp(dt), Mc, Ny, B2, ldm, dm0, dmin, ew, ys, nullptr, y0v, ytil, nullptr, hs);
         }
       }
       beta = exp(0.5 * (at + bt));
-      const double eb = eval_eps(beta, Mc, Ny, B2, ldm, dm0, dmin, ew, yt, nullptr, y0v, ytil, nullptr, hs);
+      const double eb = eval_eps(beta, Mc, Ny, B2, ldm, dm0, dmin, ew, ys, nullptr, y0v, ytil, nullptr, hs);
       if (!(eb < best_eps * (1.0 - kEpsTieRel))) beta = D0 * exp2((double)gstar / 2.0);
     }
 
@@ -712,53 +910,20 @@ static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevPa
 
     // -- leave-one-out predictions of the I0 members, 64 at a time
     double num = 0.0, den = 0.0;
-    const int ty = tid >> 4, tx = tid & 15;
     const double inv2b = 1.0 / (2.0 * beta);
+    const int nd = B2 + Ny;
     for (int c0 = 0; c0 < k0; c0 += 64) {
       const int nc = min(64, k0 - c0);
       // (a) logits -D(y_i, y_j) / (2 beta), D from whitened dot products
-      for (int j0 = 0; j0 < Mc; j0 += 64) {
-        double acc[4][4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-        for (int k0_ = 0; k0_ < Ny; k0_ += 16) {
-          for (int e = tid; e < 16 * 64; e += kThreads) {
-            const int kk = e >> 6, c = e & 63;
-            const int kg = k0_ + kk;
-            ga[kk * 64 + c] = (c < nc && kg < Ny) ? V[(size_t)i0l[c0 + c] * NRs + kg] : 0.0;
-            gb[kk * 64 + c] = (j0 + c < Mc && kg < Ny) ? V[(size_t)(j0 + c) * NRs + kg] : 0.0;
-          }
-          __syncthreads();
-#pragma unroll 4
-          for (int kk = 0; kk < 16; ++kk) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int x = 0; x < 4; ++x) av[x] = ga[kk * 64 + ty * 4 + x];
-#pragma unroll
-            for (int y = 0; y < 4; ++y) bv[y] = gb[kk * 64 + tx * 4 + y];
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-              for (int y = 0; y < 4; ++y) acc[x][y] = fma(av[x], bv[y], acc[x][y]);
-          }
-          __syncthreads();
-        }
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-#pragma unroll
-          for (int y = 0; y < 4; ++y) {
-            const int c = ty * 4 + x, j = j0 + tx * 4 + y;
-            if (c < nc && j < Mc) {
-              const int ii = i0l[c0 + c];
-              const double D = vn[ii] + vn[j] - 2.0 * acc[x][y];
-              dch[(size_t)c * Mc + j] = (j == ii) ? -INFINITY : -D * inv2b;
-            }
-          }
-        }
-      }
-      __syncthreads();
+      gemm_f64<true, true>(
+          nc, Mc, [&](int c, int k) { return V[(size_t)i0l[c0 + c] * NRs + k]; },
+          [&](int k, int j) { return V[(size_t)j * NRs + k]; },
+          [&](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Ny; return true; },
+          [&](int c, int j, double g) {
+            const int ii = i0l[c0 + c];
+            dch[(size_t)c * Mc + j] = (j == ii) ? -INFINITY : -(vn[ii] + vn[j] - 2.0 * g) * inv2b;
+          },
+          tl);
       // (b) row softmax (the member itself excluded): a wave per row, its
       //     lanes striding the candidates (coalesced), fixed-order wave sums
       for (int c = wave; c < nc; c += kThreads / 64) {
@@ -776,68 +941,32 @@ static __device__ __forceinline__ void hql_frame(const FrameArgs& a, const DevPa
         if (lane == 0) hs.rowS[c] = s;
       }
       __syncthreads();
-      // (c) z~_c = sum_j e_cj z_j over the dims of x (B2) and y (Ny)
-      const int nd = B2 + Ny;
-      for (int d0 = 0; d0 < nd; d0 += 64) {
-        double acc[4][4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-        for (int k0_ = 0; k0_ < Mc; k0_ += 16) {
-          // consecutive lanes take consecutive candidates (coalesced reads)
-          for (int e = tid; e < 16 * 64; e += kThreads) {
-            const int kk = e & 15, c = e >> 4;
-            const int kg = k0_ + kk;
-            ca[kk * 65 + c] = (c < nc && kg < Mc) ? dch[(size_t)c * Mc + kg] : 0.0;
-            const int dd = d0 + c;
-            double zv = 0.0;
-            if (dd < nd && kg < Mc)
-              zv = dd < B2 ? (double)xt[(size_t)dd * ldm + kg] : (double)yt[(size_t)(dd - B2) * ldm + kg];
-            cb[kk * 65 + c] = zv;
-          }
-          __syncthreads();
-#pragma unroll 4
-          for (int kk = 0; kk < 16; ++kk) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int x = 0; x < 4; ++x) av[x] = ca[kk * 65 + ty * 4 + x];
-#pragma unroll
-            for (int y = 0; y < 4; ++y) bv[y] = cb[kk * 65 + tx * 4 + y];
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-              for (int y = 0; y < 4; ++y) acc[x][y] = fma(av[x], bv[y], acc[x][y]);
-          }
-          __syncthreads();
-        }
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-#pragma unroll
-          for (int y = 0; y < 4; ++y) {
-            const int c = ty * 4 + x, dd = d0 + tx * 4 + y;
-            if (c < nc && dd < nd) {
-              const int ii = i0l[c0 + c];
-              const double own = dd < B2 ? (double)xt[(size_t)dd * ldm + ii]
-                                         : (double)yt[(size_t)(dd - B2) * ldm + ii];
-              // residual of the leave-one-out prediction: x_i - x~_i, y_i - y~_i
-              zch[(size_t)c * ldz + dd] = own - acc[x][y] / hs.rowS[c];
-            }
-          }
-        }
-      }
-      __syncthreads();
+      // (c) residuals of the leave-one-out predictions, x_i - x~_i and
+      //     y_i - y~_i, with z~_c = sum_j e_cj z_j / S_c over the dims of x
+      //     (B2) and y (Ny)
+      gemm_f64<true, true>(
+          nc, nd, [&](int c, int j) { return dch[(size_t)c * Mc + j]; },
+          [&](int j, int dd) {
+            return dd < B2 ? (double)xt[(size_t)dd * ldm + j] : (double)yt[(size_t)(dd - B2) * ldm + j];
+          },
+          [&](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Mc; return true; },
+          [&](int c, int dd, double v) {
+            const int ii = i0l[c0 + c];
+            const double own = dd < B2 ? (double)xt[(size_t)dd * ldm + ii]
+                                       : (double)yt[(size_t)(dd - B2) * ldm + ii];
+            zch[(size_t)c * ldz + dd] = own - v / hs.rowS[c];
+          },
+          tl);
       // (d) c_i = A r_i; accumulate <c_i, x_i - x~_i> and ||c_i||^2
-      for (int e = tid; e < nc * B2; e += kThreads) {
-        const int c = e / B2, q = e - c * B2;
-        const double* arow = axy + (size_t)q * NRs;
-        const double* rrow = zch + (size_t)c * ldz + B2;
-        double cv = 0.0;
-        for (int k = 0; k < Ny; ++k) cv += arow[k] * rrow[k];
-        num += cv * zch[(size_t)c * ldz + q];
-        den += cv * cv;
-      }
-      __syncthreads();
+      gemm_f64<true, true>(
+          nc, B2, [&](int c, int k) { return zch[(size_t)c * ldz + B2 + k]; },
+          [&](int k, int q) { return axy[(size_t)q * NRs + k]; },
+          [&](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Ny; return true; },
+          [&](int c, int q, double v) {
+            num += v * zch[(size_t)c * ldz + q];
+            den += v * v;
+          },
+          tl);
     }
     num = block_sum_d(num, hs.red);
     den = block_sum_d(den, hs.red);
@@ -873,35 +1002,9 @@ __global__ __launch_bounds__(kThreads) void k_hql(FrameArgs a, DevParams p, unsi
   if (st->remaining == 0) return;
   const int n_hql = st->n_hql;
   if ((int)blockIdx.x >= n_hql) return;
-  bool first = true;
-  hql_frame(a, p, ws, slot_bytes, st->round, n_hql, first, lds_raw, sh, hs, nullptr);
-}
-
-// Every frame of a batch in turn: the workgroups (one scratch slot each)
-// share each frame's HQL list.
-__global__ __launch_bounds__(kThreads) void k_hql_b(BatchArgs b, DevParams p, unsigned char* ws,
-                                                    size_t slot_bytes) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  __shared__ BlockShared sh;
-  __shared__ HqlShared hs;
-  if (b.bs->remaining == 0) return;
-  bool first = true;
-  for (int f = 0; f < b.nf; ++f) {
-    const RoundState* st = b.a0.st + f;
-    if (st->remaining == 0) continue;
-    const int n_hql = st->n_hql;
-    if ((int)blockIdx.x >= n_hql) continue;
-    if (!first) __syncthreads();
-    hql_frame(batch_frame(b, f), p, ws, slot_bytes, st->round, n_hql, first, lds_raw, sh, hs,
-              &b.bs->pending);
-  }
-}
-
-hipError_t launch_hql_b(const BatchArgs& b, const DevParams& p, unsigned char* ws,
-                        size_t slot_bytes, int slots, hipStream_t s) {
-  hipLaunchKernelGGL(k_hql_b, dim3(slots), dim3(kThreads), hql_lds_bytes(p), s, b, p, ws,
-                     slot_bytes);
-  return hipGetLastError();
+  phase_tables(p, carve_main_lds(lds_raw, p), sh);
+  for (int h = blockIdx.x; h < n_hql; h += gridDim.x)
+    hql_block(a, p, ws, slot_bytes, st->round, h, h == (int)blockIdx.x, lds_raw, sh, hs, nullptr);
 }
 
 hipError_t launch_hql(const FrameArgs& a, const DevParams& p, unsigned char* ws, size_t slot_bytes,
@@ -911,10 +1014,7 @@ hipError_t launch_hql(const FrameArgs& a, const DevParams& p, unsigned char* ws,
 }
 
 hipError_t set_hql_lds_limit(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_hql, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_hql_b, hipFuncAttributeMaxDynamicSharedMemorySize,
+  return hipFuncSetAttribute((const void*)k_hql, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)bytes);
 }
 

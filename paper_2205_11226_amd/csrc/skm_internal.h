@@ -170,8 +170,6 @@ hipError_t launch_est_b(const BatchArgs& b, const DevParams& p, int variant, hip
 hipError_t launch_finalize_b(const BatchArgs& b, const DevParams& p, int grid, hipStream_t s);
 hipError_t launch_cnn_gate_b(const BatchArgs& b, const DevParams& p, const uint4* pk,
                              const float* wq, float tau1, float tau2, int grid, hipStream_t s);
-hipError_t launch_hql_b(const BatchArgs& b, const DevParams& p, unsigned char* ws,
-                        size_t slot_bytes, int slots, hipStream_t s);
 // estimation kernel variants for p's geometry (candidate slices per thread),
 // the first being the default; returns the count written to out (<= 4)
 int est_variants(const DevParams& p, int* out);
