@@ -161,6 +161,9 @@ static __device__ __forceinline__ double block_min_d(double v, double* red) {
 }
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+// LDS-qualified views of the tile pointers, so that the tile traffic of
+// functions that the compiler keeps out of line stays on ds_* instructions
+typedef __attribute__((address_space(3))) double lds_f64;
 
 // C = A B on FP64 MFMA, one workgroup, 64 x 64 output tiles in raster order.
 // Wave w holds the 32 x 32 quarter (w / 2, w % 2) of a tile as 2 x 2
@@ -176,8 +179,8 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 template <bool AK, bool BK, class FA, class FB, class FT, class FE>
 static __device__ void gemm_f64(int M, int N, FA fa, FB fb, FT tiles, FE epi, double* tl) {
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
-  double* As = tl;
-  double* Bs = tl + 16 * kTp;
+  lds_f64* As = (lds_f64*)tl;
+  lds_f64* Bs = As + 16 * kTp;
   const int ntm = (M + 63) >> 6, ntn = (N + 63) >> 6;
   const int mw = 32 * (wave >> 1), nw = 32 * (wave & 1);
   const int li = lane & 15, lk = lane >> 4;
@@ -215,8 +218,8 @@ static __device__ void gemm_f64(int M, int N, FA fa, FB fb, FT tiles, FE epi, do
       if (k0 + 16 < ke) load(k0 + 16);
 #pragma unroll
       for (int k4 = 0; k4 < 4; ++k4) {
-        const double* ar = As + (4 * k4 + lk) * kTp;
-        const double* br = Bs + (4 * k4 + lk) * kTp;
+        const lds_f64* ar = As + (4 * k4 + lk) * kTp;
+        const lds_f64* br = Bs + (4 * k4 + lk) * kTp;
         const double a0 = ar[mw + li], a1 = ar[mw + 16 + li];
         const double b0 = br[nw + li], b1 = br[nw + 16 + li];
         acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
@@ -250,8 +253,8 @@ static __device__ void gemm_f64(int M, int N, FA fa, FB fb, FT tiles, FE epi, do
 // not positive.  tmp: 64 x ld doubles; lds: kCholLds bytes.
 static __device__ bool chol_inv(double* C, int ld, int n, double* Li, double* tmp, double* lds) {
   const int tid = threadIdx.x;
-  double* D = lds;
-  double* Di = lds + 64 * 65;
+  lds_f64* D = (lds_f64*)lds;
+  lds_f64* Di = D + 64 * 65;
   const int nb = (n + 63) >> 6;
   for (int kb = 0; kb < nb; ++kb) {
     const int k0 = 64 * kb, kn = min(64, n - k0);
@@ -300,30 +303,30 @@ static __device__ bool chol_inv(double* C, int ld, int n, double* Li, double* tm
     if (nr <= 0) continue;
     // panel: L_ik[i][c] = sum_m C_ik[i][m] Di[c][m]  (in place, row tiles disjoint)
     gemm_f64<true, true>(
-        nr, kn, [&](int i, int m) { return C[(size_t)(r0 + i) * ld + k0 + m]; },
-        [&](int m, int c) { return Li[(size_t)(k0 + c) * ld + k0 + m]; },
-        [&](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = kn; return true; },
-        [&](int i, int c, double v) { C[(size_t)(r0 + i) * ld + k0 + c] = v; }, lds);
+        nr, kn, [=](int i, int m) { return C[(size_t)(r0 + i) * ld + k0 + m]; },
+        [=](int m, int c) { return Li[(size_t)(k0 + c) * ld + k0 + m]; },
+        [=](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = kn; return true; },
+        [=](int i, int c, double v) { C[(size_t)(r0 + i) * ld + k0 + c] = v; }, lds);
     // trailing update of the lower tiles
     gemm_f64<true, true>(
-        nr, nr, [&](int i, int m) { return C[(size_t)(r0 + i) * ld + k0 + m]; },
-        [&](int m, int l) { return C[(size_t)(r0 + l) * ld + k0 + m]; },
-        [&](int mt, int nt, int& kb_, int& ke_) { kb_ = 0; ke_ = kn; return nt <= mt; },
-        [&](int i, int l, double v) { C[(size_t)(r0 + i) * ld + r0 + l] -= v; }, lds);
+        nr, nr, [=](int i, int m) { return C[(size_t)(r0 + i) * ld + k0 + m]; },
+        [=](int m, int l) { return C[(size_t)(r0 + l) * ld + k0 + m]; },
+        [=](int mt, int nt, int& kb_, int& ke_) { kb_ = 0; ke_ = kn; return nt <= mt; },
+        [=](int i, int l, double v) { C[(size_t)(r0 + i) * ld + r0 + l] -= v; }, lds);
   }
   for (int ib = 1; ib < nb; ++ib) {
     const int i0 = 64 * ib, in = min(64, n - i0);
     // S = L[i0 .., 0 .. i0) Li[0 .. i0, 0 .. i0), then Li[i0 .., 0 .. i0) = -Di S
     gemm_f64<true, false>(
-        in, i0, [&](int r, int m) { return C[(size_t)(i0 + r) * ld + m]; },
-        [&](int m, int c) { return Li[(size_t)m * ld + c]; },
-        [&](int, int nt, int& kb_, int& ke_) { kb_ = 64 * nt; ke_ = i0; return true; },
-        [&](int r, int c, double v) { tmp[(size_t)r * ld + c] = v; }, lds);
+        in, i0, [=](int r, int m) { return C[(size_t)(i0 + r) * ld + m]; },
+        [=](int m, int c) { return Li[(size_t)m * ld + c]; },
+        [=](int, int nt, int& kb_, int& ke_) { kb_ = 64 * nt; ke_ = i0; return true; },
+        [=](int r, int c, double v) { tmp[(size_t)r * ld + c] = v; }, lds);
     gemm_f64<true, false>(
-        in, i0, [&](int r, int m) { return Li[(size_t)(i0 + r) * ld + i0 + m]; },
-        [&](int m, int c) { return tmp[(size_t)m * ld + c]; },
-        [&](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = in; return true; },
-        [&](int r, int c, double v) { Li[(size_t)(i0 + r) * ld + c] = -v; }, lds);
+        in, i0, [=](int r, int m) { return Li[(size_t)(i0 + r) * ld + i0 + m]; },
+        [=](int m, int c) { return tmp[(size_t)m * ld + c]; },
+        [=](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = in; return true; },
+        [=](int r, int c, double v) { Li[(size_t)(i0 + r) * ld + c] = -v; }, lds);
   }
   return true;
 }
@@ -681,13 +684,13 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
       //    normalised: G / M - mean_i mean_j from the exact integer Grams
       const double invM = 1.0 / (double)Mc;
       gram_i8(yt, yt, Ny, Ny, ldm, rsy, rsy, true,
-              [&](int i, int j, int g) {
+              [=](int i, int j, int g) {
                 const double c = (double)g * invM - meany[i] * meany[j];
                 cyy[(size_t)i * NRs + j] = c;
                 cyy[(size_t)j * NRs + i] = c;
               }, t8);
       gram_i8(xt, yt, B2, Ny, ldm, rsx, rsy, false,
-              [&](int q, int j, int g) { axy[(size_t)q * NRs + j] = (double)g * invM - meanx[q] * meany[j]; },
+              [=](int q, int j, int g) { axy[(size_t)q * NRs + j] = (double)g * invM - meanx[q] * meany[j]; },
               t8);
     } else {
       // -- pairwise-complete covariance: for coordinates a, b the candidates
@@ -701,18 +704,18 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
       byte_row_sums(ot, Ny, ldm, rso);
       __syncthreads();
       gram_i8(yt, yt, Ny, Ny, ldm, rsy, rsy, true,
-              [&](int i, int j, int g) {
+              [=](int i, int j, int g) {
                 cyy[(size_t)i * NRs + j] = (double)g;
                 cyy[(size_t)j * NRs + i] = (double)g;
               }, t8);
       gram_i8(ot, ot, Ny, Ny, ldm, rso, rso, true,
-              [&](int i, int j, int g) { gn[i * Ny + j] = g; gn[j * Ny + i] = g; }, t8);
+              [=](int i, int j, int g) { gn[i * Ny + j] = g; gn[j * Ny + i] = g; }, t8);
       gram_i8(yt, ot, Ny, Ny, ldm, rsy, rso, false,
-              [&](int i, int j, int g) { gs[i * Ny + j] = g; }, t8);
+              [=](int i, int j, int g) { gs[i * Ny + j] = g; }, t8);
       gram_i8(xt, yt, B2, Ny, ldm, rsx, rsy, false,
-              [&](int q, int j, int g) { axy[(size_t)q * NRs + j] = (double)g; }, t8);
+              [=](int q, int j, int g) { axy[(size_t)q * NRs + j] = (double)g; }, t8);
       gram_i8(xt, ot, B2, Ny, ldm, rsx, rso, false,
-              [&](int q, int j, int g) { gsx[q * Ny + j] = g; }, t8);
+              [=](int q, int j, int g) { gsx[q * Ny + j] = g; }, t8);
       for (int e = tid; e < Ny * Ny; e += kThreads) {
         const int aa = e / Ny, bb = e - aa * Ny;
         const double n = (double)gn[e];
@@ -796,21 +799,21 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
     //    v0 = L^-1 y0 as row Mc; column tile nt of V needs k < 64 (nt + 1)
     gemm_f64<false, true>(
         Mc + 1, Ny,
-        [&](int j, int k) { return j < Mc ? (double)yt[(size_t)k * ldm + j] : y0v[k]; },
-        [&](int k, int aa) { return Li[(size_t)aa * NRs + k]; },
-        [&](int, int nt, int& kb_, int& ke_) { kb_ = 0; ke_ = min(Ny, 64 * nt + 64); return true; },
-        [&](int j, int aa, double v) { (j < Mc ? V + (size_t)j * NRs : v0)[aa] = v; }, tl);
+        [=](int j, int k) { return j < Mc ? (double)yt[(size_t)k * ldm + j] : y0v[k]; },
+        [=](int k, int aa) { return Li[(size_t)aa * NRs + k]; },
+        [=](int, int nt, int& kb_, int& ke_) { kb_ = 0; ke_ = min(Ny, 64 * nt + 64); return true; },
+        [=](int j, int aa, double v) { (j < Mc ? V + (size_t)j * NRs : v0)[aa] = v; }, tl);
     // -- A = C_XY C_YY^-1 = (C_XY L^-T) L^-1: T in tmp, then A over C_XY
     gemm_f64<true, true>(
-        B2, Ny, [&](int q, int k) { return axy[(size_t)q * NRs + k]; },
-        [&](int k, int ii) { return Li[(size_t)ii * NRs + k]; },
-        [&](int, int nt, int& kb_, int& ke_) { kb_ = 0; ke_ = min(Ny, 64 * nt + 64); return true; },
-        [&](int q, int ii, double v) { tmp[(size_t)q * NRs + ii] = v; }, tl);
+        B2, Ny, [=](int q, int k) { return axy[(size_t)q * NRs + k]; },
+        [=](int k, int ii) { return Li[(size_t)ii * NRs + k]; },
+        [=](int, int nt, int& kb_, int& ke_) { kb_ = 0; ke_ = min(Ny, 64 * nt + 64); return true; },
+        [=](int q, int ii, double v) { tmp[(size_t)q * NRs + ii] = v; }, tl);
     gemm_f64<true, false>(
-        B2, Ny, [&](int q, int ii) { return tmp[(size_t)q * NRs + ii]; },
-        [&](int ii, int mm) { return Li[(size_t)ii * NRs + mm]; },
-        [&](int, int nt, int& kb_, int& ke_) { kb_ = 64 * nt; ke_ = Ny; return true; },
-        [&](int q, int mm, double v) { axy[(size_t)q * NRs + mm] = v; }, tl);
+        B2, Ny, [=](int q, int ii) { return tmp[(size_t)q * NRs + ii]; },
+        [=](int ii, int mm) { return Li[(size_t)ii * NRs + mm]; },
+        [=](int, int nt, int& kb_, int& ke_) { kb_ = 64 * nt; ke_ = Ny; return true; },
+        [=](int q, int mm, double v) { axy[(size_t)q * NRs + mm] = v; }, tl);
     // Mahalanobis distances to y0 and squared norms of the whitened candidates
     double dmin = INFINITY;
     for (int j = tid; j < Mc; j += kThreads) {
@@ -916,10 +919,10 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
       const int nc = min(64, k0 - c0);
       // (a) logits -D(y_i, y_j) / (2 beta), D from whitened dot products
       gemm_f64<true, true>(
-          nc, Mc, [&](int c, int k) { return V[(size_t)i0l[c0 + c] * NRs + k]; },
-          [&](int k, int j) { return V[(size_t)j * NRs + k]; },
-          [&](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Ny; return true; },
-          [&](int c, int j, double g) {
+          nc, Mc, [=](int c, int k) { return V[(size_t)i0l[c0 + c] * NRs + k]; },
+          [=](int k, int j) { return V[(size_t)j * NRs + k]; },
+          [=](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Ny; return true; },
+          [=](int c, int j, double g) {
             const int ii = i0l[c0 + c];
             dch[(size_t)c * Mc + j] = (j == ii) ? -INFINITY : -(vn[ii] + vn[j] - 2.0 * g) * inv2b;
           },
@@ -941,28 +944,29 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
         if (lane == 0) hs.rowS[c] = s;
       }
       __syncthreads();
+      const double* rowS = hs.rowS;
       // (c) residuals of the leave-one-out predictions, x_i - x~_i and
       //     y_i - y~_i, with z~_c = sum_j e_cj z_j / S_c over the dims of x
       //     (B2) and y (Ny)
       gemm_f64<true, true>(
-          nc, nd, [&](int c, int j) { return dch[(size_t)c * Mc + j]; },
-          [&](int j, int dd) {
+          nc, nd, [=](int c, int j) { return dch[(size_t)c * Mc + j]; },
+          [=](int j, int dd) {
             return dd < B2 ? (double)xt[(size_t)dd * ldm + j] : (double)yt[(size_t)(dd - B2) * ldm + j];
           },
-          [&](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Mc; return true; },
-          [&](int c, int dd, double v) {
+          [=](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Mc; return true; },
+          [=](int c, int dd, double v) {
             const int ii = i0l[c0 + c];
             const double own = dd < B2 ? (double)xt[(size_t)dd * ldm + ii]
                                        : (double)yt[(size_t)(dd - B2) * ldm + ii];
-            zch[(size_t)c * ldz + dd] = own - v / hs.rowS[c];
+            zch[(size_t)c * ldz + dd] = own - v / rowS[c];
           },
           tl);
       // (d) c_i = A r_i; accumulate <c_i, x_i - x~_i> and ||c_i||^2
       gemm_f64<true, true>(
-          nc, B2, [&](int c, int k) { return zch[(size_t)c * ldz + B2 + k]; },
-          [&](int k, int q) { return axy[(size_t)q * NRs + k]; },
-          [&](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Ny; return true; },
-          [&](int c, int q, double v) {
+          nc, B2, [=](int c, int k) { return zch[(size_t)c * ldz + B2 + k]; },
+          [=](int k, int q) { return axy[(size_t)q * NRs + k]; },
+          [=](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Ny; return true; },
+          [=, &num, &den](int c, int q, double v) {
             num += v * zch[(size_t)c * ldz + q];
             den += v * v;
           },
