@@ -90,7 +90,7 @@ int hql_slots(const DevParams& p) {
 // tile start 128 bytes apart modulo 256, so the two half-waves of a read hit
 // disjoint banks
 constexpr int kTp = 80;
-constexpr size_t kGemmLds = (size_t)2 * 16 * kTp * 8;
+constexpr size_t kGemmLds = (size_t)2 * 32 * kTp * 8;
 // LDS row pitch (bytes) of the int8 Gram tiles: 256 bytes of k a row, the
 // 16 row starts of a half-wave's reads on distinct 4-bank groups
 constexpr int kGk = 256;
@@ -129,6 +129,9 @@ constexpr int kPsdRepair = 6;
 __device__ __constant__ const double kPow10[kPsdRepair + 1] = {1.0, 10.0, 100.0, 1e3, 1e4, 1e5,
                                                                 1e6};
 
+// contexts wider than this evaluate the 33 grid points of beta in one MFMA pass
+constexpr int kGridPassNy = 64;
+
 // eps_y values within this relative margin count as equal: where eps_y is
 // flat (as beta -> 0 the weights become one-hot on the nearest candidate), the
 // argmin of eq. epsy is not unique, so the smallest flat beta is taken and a
@@ -138,6 +141,8 @@ constexpr double kEpsTieRel = 1e-12;
 struct HqlShared {
   double red[kThreads / 64];
   double eg[33];                 // eps_y on the beta grid g = -8 .. 24
+  double ginv[33];               // 1 / (2 beta_g) on that grid
+  double pb[2][kThreads / 64][65];   // eval_eps_narrow: per-wave row partials, S at [64]
   double S;
   double rowS[64];
 };
@@ -164,60 +169,88 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // LDS-qualified views of the tile pointers, so that the tile traffic of
 // functions that the compiler keeps out of line stays on ds_* instructions
 typedef __attribute__((address_space(3))) double lds_f64;
+// and global-qualified views of the scratch operands: flat loads would also
+// count against the LDS wait counter and hold the tile reads behind them
+template <class T>
+static __device__ __forceinline__ __attribute__((address_space(1))) T* glb(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
+// k per staging step of gemm_f64
+constexpr int kKc = 32;
 
 // C = A B on FP64 MFMA, one workgroup, 64 x 64 output tiles in raster order.
 // Wave w holds the 32 x 32 quarter (w / 2, w % 2) of a tile as 2 x 2
-// v_mfma_f64_16x16x4f64 accumulators; k advances 16 at a time through LDS
-// (tl: two 16 x kTp tiles), the next step's operands loaded into registers
-// while the current one is multiplied.  Operands are read element-wise by
-// fa(m, k) and fb(k, n); AK (BK) says that consecutive k of A (B) are
-// adjacent in memory, which picks the staging order that keeps each wave's
-// loads contiguous.  tiles(mt, nt, kb, ke) sets the k range of output tile
-// (mt, nt) and returns false for a tile that is not wanted (triangular
-// operands skip their zero blocks this way).  epi(m, n, v) gets every output
-// of a wanted tile once, always from the same lane, in a fixed order.
+// v_mfma_f64_16x16x4f64 accumulators; k advances kKc at a time through LDS
+// (tl: two kKc x kTp tiles).  The steps of all tiles form one pipeline: the
+// operands of the next step, which may be the first of the next tile, are
+// loaded into registers while the current one is multiplied.  Operands are
+// read element-wise by fa(m, k) and fb(k, n); AK (BK) says that consecutive
+// k of A (B) are adjacent in memory, which picks the staging order that
+// keeps each wave's loads contiguous.  tiles(mt, nt, kb, ke) sets the k
+// range of output tile (mt, nt) and returns false for a tile that is not
+// wanted (triangular operands skip their zero blocks this way).
+// epi(m, n, v) gets every output of a wanted tile once, always from the
+// same lane, in a fixed order.  A tile's loads never read what an earlier
+// tile's epi wrote unless the two touch disjoint rows (in-place panels).
 template <bool AK, bool BK, class FA, class FB, class FT, class FE>
 static __device__ void gemm_f64(int M, int N, FA fa, FB fb, FT tiles, FE epi, double* tl) {
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   lds_f64* As = (lds_f64*)tl;
-  lds_f64* Bs = As + 16 * kTp;
-  const int ntm = (M + 63) >> 6, ntn = (N + 63) >> 6;
+  lds_f64* Bs = As + kKc * kTp;
+  const int ntn = (N + 63) >> 6, nt_all = ((M + 63) >> 6) * ntn;
   const int mw = 32 * (wave >> 1), nw = 32 * (wave & 1);
   const int li = lane & 15, lk = lane >> 4;
-  const int am = AK ? (tid >> 4) : (tid & 63), ak = AK ? (tid & 15) : (tid >> 6);
-  const int bn = BK ? (tid >> 4) : (tid & 63), bk = BK ? (tid & 15) : (tid >> 6);
-  for (int t = 0; t < ntm * ntn; ++t) {
+  // staging: element s (of 8) of A is (am + (AK ? 8 s : 0), ak + (AK ? 0 : 4 s))
+  const int am = AK ? (tid >> 5) : (tid & 63), ak = AK ? (tid & 31) : (tid >> 6);
+  const int bn = BK ? (tid >> 5) : (tid & 63), bk = BK ? (tid & 31) : (tid >> 6);
+  auto next_tile = [&](int t, int& kb, int& ke) {
+    for (; t < nt_all; ++t) {
+      const int mt = t / ntn, nt = t - mt * ntn;
+      if (tiles(mt, nt, kb, ke)) return t;
+    }
+    return nt_all;
+  };
+  double ra[8], rb[8];
+  auto load = [&](int t, int k0, int ke) {
     const int mt = t / ntn, nt = t - mt * ntn;
-    int kb = 0, ke = 0;
-    if (!tiles(mt, nt, kb, ke)) continue;
     const int m0 = mt * 64, n0 = nt * 64;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int m = m0 + am + (AK ? 8 * s : 0), k = k0 + ak + (AK ? 0 : 4 * s);
+      ra[s] = (m < M && k < ke) ? fa(m, k) : 0.0;
+      const int n = n0 + bn + (BK ? 8 * s : 0), kk = k0 + bk + (BK ? 0 : 4 * s);
+      rb[s] = (n < N && kk < ke) ? fb(kk, n) : 0.0;
+    }
+  };
+  int kb = 0, ke = 0;
+  int t = next_tile(0, kb, ke);
+  if (t < nt_all) {
+    int k0 = kb;
+    load(t, k0, ke);
     f64x4 acc[2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
       for (int y = 0; y < 2; ++y) acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
-    double ra[4], rb[4];
-    auto load = [&](int k0) {
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int m = m0 + am + (AK ? 16 * s : 0), k = k0 + ak + (AK ? 0 : 4 * s);
-        ra[s] = (m < M && k < ke) ? fa(m, k) : 0.0;
-        const int n = n0 + bn + (BK ? 16 * s : 0), kk = k0 + bk + (BK ? 0 : 4 * s);
-        rb[s] = (n < N && kk < ke) ? fb(kk, n) : 0.0;
-      }
-    };
-    load(kb);
-    for (int k0 = kb; k0 < ke; k0 += 16) {
+    while (true) {
       __syncthreads();                       // the previous step's reads are done
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        As[(ak + (AK ? 0 : 4 * s)) * kTp + am + (AK ? 16 * s : 0)] = ra[s];
-        Bs[(bk + (BK ? 0 : 4 * s)) * kTp + bn + (BK ? 16 * s : 0)] = rb[s];
+      for (int s = 0; s < 8; ++s) {
+        As[(ak + (AK ? 0 : 4 * s)) * kTp + am + (AK ? 8 * s : 0)] = ra[s];
+        Bs[(bk + (BK ? 0 : 4 * s)) * kTp + bn + (BK ? 8 * s : 0)] = rb[s];
       }
       __syncthreads();
-      if (k0 + 16 < ke) load(k0 + 16);
+      // the next step: the tile's next k range, else the next wanted tile
+      int t2 = t, k2 = k0 + kKc, kb2 = kb, ke2 = ke;
+      const bool last = k2 >= ke;
+      if (last) {
+        t2 = next_tile(t + 1, kb2, ke2);
+        k2 = kb2;
+      }
+      if (t2 < nt_all) load(t2, k2, ke2);
 #pragma unroll
-      for (int k4 = 0; k4 < 4; ++k4) {
+      for (int k4 = 0; k4 < kKc / 4; ++k4) {
         const lds_f64* ar = As + (4 * k4 + lk) * kTp;
         const lds_f64* br = Bs + (4 * k4 + lk) * kTp;
         const double a0 = ar[mw + li], a1 = ar[mw + 16 + li];
@@ -227,18 +260,25 @@ static __device__ void gemm_f64(int M, int N, FA fa, FB fb, FT tiles, FE epi, do
         acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
         acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
       }
+      if (last) {
+        // accumulator layout of v_mfma_f64_16x16x4f64: lane l, element r
+        // holds row l / 16 + 4 r, column l % 16 of its 16 x 16 block
+        const int mt = t / ntn, nt = t - mt * ntn;
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int m = mt * 64 + mw + 16 * x + lk + 4 * r, n = nt * 64 + nw + 16 * y + li;
+              if (m < M && n < N) epi(m, n, acc[x][y][r]);
+            }
+            acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+          }
+        if (t2 >= nt_all) break;
+      }
+      t = t2; k0 = k2; kb = kb2; ke = ke2;
     }
-    // accumulator layout of v_mfma_f64_16x16x4f64: lane l, element r holds
-    // row l / 16 + 4 r, column l % 16 of its 16 x 16 block
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = m0 + mw + 16 * x + lk + 4 * r, n = n0 + nw + 16 * y + li;
-          if (m < M && n < N) epi(m, n, acc[x][y][r]);
-        }
   }
   __syncthreads();
 }
@@ -303,30 +343,30 @@ static __device__ bool chol_inv(double* C, int ld, int n, double* Li, double* tm
     if (nr <= 0) continue;
     // panel: L_ik[i][c] = sum_m C_ik[i][m] Di[c][m]  (in place, row tiles disjoint)
     gemm_f64<true, true>(
-        nr, kn, [=](int i, int m) { return C[(size_t)(r0 + i) * ld + k0 + m]; },
-        [=](int m, int c) { return Li[(size_t)(k0 + c) * ld + k0 + m]; },
+        nr, kn, [=](int i, int m) { return glb(C)[(size_t)(r0 + i) * ld + k0 + m]; },
+        [=](int m, int c) { return glb(Li)[(size_t)(k0 + c) * ld + k0 + m]; },
         [=](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = kn; return true; },
-        [=](int i, int c, double v) { C[(size_t)(r0 + i) * ld + k0 + c] = v; }, lds);
+        [=](int i, int c, double v) { glb(C)[(size_t)(r0 + i) * ld + k0 + c] = v; }, lds);
     // trailing update of the lower tiles
     gemm_f64<true, true>(
-        nr, nr, [=](int i, int m) { return C[(size_t)(r0 + i) * ld + k0 + m]; },
-        [=](int m, int l) { return C[(size_t)(r0 + l) * ld + k0 + m]; },
+        nr, nr, [=](int i, int m) { return glb(C)[(size_t)(r0 + i) * ld + k0 + m]; },
+        [=](int m, int l) { return glb(C)[(size_t)(r0 + l) * ld + k0 + m]; },
         [=](int mt, int nt, int& kb_, int& ke_) { kb_ = 0; ke_ = kn; return nt <= mt; },
-        [=](int i, int l, double v) { C[(size_t)(r0 + i) * ld + r0 + l] -= v; }, lds);
+        [=](int i, int l, double v) { glb(C)[(size_t)(r0 + i) * ld + r0 + l] -= v; }, lds);
   }
   for (int ib = 1; ib < nb; ++ib) {
     const int i0 = 64 * ib, in = min(64, n - i0);
     // S = L[i0 .., 0 .. i0) Li[0 .. i0, 0 .. i0), then Li[i0 .., 0 .. i0) = -Di S
     gemm_f64<true, false>(
-        in, i0, [=](int r, int m) { return C[(size_t)(i0 + r) * ld + m]; },
-        [=](int m, int c) { return Li[(size_t)m * ld + c]; },
+        in, i0, [=](int r, int m) { return glb(C)[(size_t)(i0 + r) * ld + m]; },
+        [=](int m, int c) { return glb(Li)[(size_t)m * ld + c]; },
         [=](int, int nt, int& kb_, int& ke_) { kb_ = 64 * nt; ke_ = i0; return true; },
-        [=](int r, int c, double v) { tmp[(size_t)r * ld + c] = v; }, lds);
+        [=](int r, int c, double v) { glb(tmp)[(size_t)r * ld + c] = v; }, lds);
     gemm_f64<true, false>(
-        in, i0, [=](int r, int m) { return Li[(size_t)(i0 + r) * ld + i0 + m]; },
-        [=](int m, int c) { return tmp[(size_t)m * ld + c]; },
+        in, i0, [=](int r, int m) { return glb(Li)[(size_t)(i0 + r) * ld + i0 + m]; },
+        [=](int m, int c) { return glb(tmp)[(size_t)m * ld + c]; },
         [=](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = in; return true; },
-        [=](int r, int c, double v) { Li[(size_t)(i0 + r) * ld + c] = -v; }, lds);
+        [=](int r, int c, double v) { glb(Li)[(size_t)(i0 + r) * ld + c] = -v; }, lds);
   }
   return true;
 }
@@ -455,19 +495,24 @@ static __device__ void gram_i8(const uint8_t* P, const uint8_t* Q, int R1, int R
 // One evaluation of eps_y(beta) (eq. epsy): weights e_j = exp(-dm0_j/(2 beta)
 // - max), S = sum e_j, y~ = sum e_j y_j / S; returns ||y0 - y~||^2.  Leaves
 // ew, S (in hs.S) and ytil for the caller.  With xt != nullptr also x~.
-// ys: the candidates' context bytes (Ny rows of ldm, zero padded; in LDS or
-// global memory).  A wave takes eight rows at a time; a lane takes four
+// ys: the candidates' context bytes (Ny rows of ldm, zero padded; in LDS
+// with YL, else in global memory, where xt is too).  A wave takes eight rows at a time; a lane takes four
 // consecutive candidates of four 256-candidate strips per step (32 loads in
 // flight), then reduce8 sums the rows.
+typedef __attribute__((address_space(3))) const uint32_t lds_u32c;
+typedef __attribute__((address_space(1))) const uint32_t glb_u32c;
+
+template <bool YL>
 static __device__ double eval_eps(double beta, int Mc, int Ny, int B2, int ldm, const double* dm0,
-                                  double dmin, double* ew, const uint8_t* ys, const uint8_t* xt,
+                                  double dmin, double* ew_, const uint8_t* ys, const uint8_t* xt,
                                   const double* y0, double* ytil, double* xtil, HqlShared& hs) {
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  lds_f64* ew = (lds_f64*)ew_;
   const double inv2b = 1.0 / (2.0 * beta);      // one division per evaluation
   const double m = -dmin * inv2b;
   double s = 0.0;
   for (int j = tid; j < Mc; j += kThreads) {
-    const double e = exp(-dm0[j] * inv2b - m);
+    const double e = exp(-glb(dm0)[j] * inv2b - m);
     ew[j] = e;
     s += e;
   }
@@ -496,7 +541,7 @@ static __device__ double eval_eps(double beta, int Mc, int Ny, int B2, int ldm, 
         for (int t = 0; t < 4; ++t) e[q][t] = j + t < Mc ? ew[j + t] : 0.0;
 #pragma unroll
         for (int r = 0; r < 8; ++r)
-          w[q][r] = (ok[r] && j < Mc) ? *reinterpret_cast<const uint32_t*>(rp[r] + j) : 0u;
+          w[q][r] = (ok[r] && j < Mc) ? (YL ? *(lds_u32c*)(rp[r] + j) : *(glb_u32c*)(rp[r] + j)) : 0u;
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -510,16 +555,85 @@ static __device__ double eval_eps(double beta, int Mc, int Ny, int B2, int ldm, 
       const int a = a0 + (lane >> 3);
       if (a < Ny) {
         const double yv = tot / S;
-        ytil[a] = yv;
-        const double d = y0[a] - yv;
+        glb(ytil)[a] = yv;
+        const double d = glb(y0)[a] - yv;
         part += d * d;
       } else if (a < R) {
-        xtil[a - Ny] = tot / S;
+        glb(xtil)[a - Ny] = tot / S;
       }
     }
   }
   hs.S = S;
   return block_sum_d(part, hs.red);
+}
+
+// eps_y(beta) for contexts of at most 64 pixels (2 x 2 patches): wave w
+// takes the w-th quarter of the candidates for every context row, keeping its
+// weights in registers, and leaves per-row partial sums and its share of S in
+// hs.pb[flip][w]; after one barrier every wave adds the four partials in
+// wave order and returns the same eps_y.  Alternating between the two
+// halves of pb (flip) keeps a wave from overwriting partials that another
+// wave has yet to read.  Same weights and sums as eval_eps, in another
+// order; y~ is not kept.
+template <bool YL>
+static __device__ double eval_eps_narrow(double beta, int Mc, int Ny, int ldm, const double* dm0,
+                                         double dmin, const uint8_t* ys, const double* y0,
+                                         HqlShared& hs, int flip) {
+  const int lane = lane_id(), wave = wave_id();
+  const double inv2b = 1.0 / (2.0 * beta);
+  const double m = -dmin * inv2b;
+  const int Q = ((Mc + 4 * 64 - 1) / (4 * 64)) * 64;        // candidates per wave, multiple of 64
+  const int c0 = wave * Q, c1 = min(Mc, c0 + Q);
+  constexpr int kSteps = (kMaxPer * kThreads + 4 * 256 - 1) / (4 * 256);
+  double e[kSteps][4];
+  double sp = 0.0;
+#pragma unroll
+  for (int st = 0; st < kSteps; ++st) {
+    const int j0 = c0 + 4 * lane + 256 * st;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int j = j0 + t;
+      e[st][t] = j < c1 ? exp(-glb(dm0)[j] * inv2b - m) : 0.0;
+      sp += e[st][t];
+    }
+  }
+  sp = wave_sum(sp);
+  lds_f64* pb = (lds_f64*)&hs.pb[flip][wave][0];
+  for (int a0 = 0; a0 < Ny; a0 += 8) {
+    double acc[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) acc[r] = 0.0;
+#pragma unroll
+    for (int st = 0; st < kSteps; ++st) {
+      const int j0 = c0 + 4 * lane + 256 * st;
+      if (c0 + 256 * st < c1) {                    // wave-uniform
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const uint8_t* row = ys + (size_t)(a0 + r) * ldm + j0;
+          const uint32_t w = (a0 + r < Ny && j0 < c1)
+                                 ? (YL ? *(lds_u32c*)row : *(glb_u32c*)row) : 0u;
+          acc[r] += e[st][0] * (double)(w & 0xffu) + e[st][1] * (double)((w >> 8) & 0xffu) +
+                    e[st][2] * (double)((w >> 16) & 0xffu) + e[st][3] * (double)(w >> 24);
+        }
+      }
+    }
+    const double tot = reduce8(acc);
+    const int a = a0 + (lane >> 3);
+    if ((lane & 7) == 0 && a < Ny) pb[a] = tot;
+  }
+  if (lane == 0) pb[64] = sp;
+  __syncthreads();
+  const lds_f64* q0 = (const lds_f64*)&hs.pb[flip][0][0];
+  const lds_f64* q1 = q0 + 65;
+  const lds_f64* q2 = q1 + 65;
+  const lds_f64* q3 = q2 + 65;
+  const double S = ((q0[64] + q1[64]) + q2[64]) + q3[64];
+  double part = 0.0;
+  if (lane < Ny) {
+    const double d = glb(y0)[lane] - (((q0[lane] + q1[lane]) + q2[lane]) + q3[lane]) / S;
+    part = d * d;
+  }
+  return wave_sum(part);
 }
 
 // HQL for entry h of one frame's list, on this workgroup's scratch slot.
@@ -685,12 +799,12 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
       const double invM = 1.0 / (double)Mc;
       gram_i8(yt, yt, Ny, Ny, ldm, rsy, rsy, true,
               [=](int i, int j, int g) {
-                const double c = (double)g * invM - meany[i] * meany[j];
-                cyy[(size_t)i * NRs + j] = c;
-                cyy[(size_t)j * NRs + i] = c;
+                const double c = (double)g * invM - glb(meany)[i] * glb(meany)[j];
+                glb(cyy)[(size_t)i * NRs + j] = c;
+                glb(cyy)[(size_t)j * NRs + i] = c;
               }, t8);
       gram_i8(xt, yt, B2, Ny, ldm, rsx, rsy, false,
-              [=](int q, int j, int g) { axy[(size_t)q * NRs + j] = (double)g * invM - meanx[q] * meany[j]; },
+              [=](int q, int j, int g) { glb(axy)[(size_t)q * NRs + j] = (double)g * invM - glb(meanx)[q] * glb(meany)[j]; },
               t8);
     } else {
       // -- pairwise-complete covariance: for coordinates a, b the candidates
@@ -705,17 +819,17 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
       __syncthreads();
       gram_i8(yt, yt, Ny, Ny, ldm, rsy, rsy, true,
               [=](int i, int j, int g) {
-                cyy[(size_t)i * NRs + j] = (double)g;
-                cyy[(size_t)j * NRs + i] = (double)g;
+                glb(cyy)[(size_t)i * NRs + j] = (double)g;
+                glb(cyy)[(size_t)j * NRs + i] = (double)g;
               }, t8);
       gram_i8(ot, ot, Ny, Ny, ldm, rso, rso, true,
-              [=](int i, int j, int g) { gn[i * Ny + j] = g; gn[j * Ny + i] = g; }, t8);
+              [=](int i, int j, int g) { glb(gn)[i * Ny + j] = g; glb(gn)[j * Ny + i] = g; }, t8);
       gram_i8(yt, ot, Ny, Ny, ldm, rsy, rso, false,
-              [=](int i, int j, int g) { gs[i * Ny + j] = g; }, t8);
+              [=](int i, int j, int g) { glb(gs)[i * Ny + j] = g; }, t8);
       gram_i8(xt, yt, B2, Ny, ldm, rsx, rsy, false,
-              [=](int q, int j, int g) { axy[(size_t)q * NRs + j] = (double)g; }, t8);
+              [=](int q, int j, int g) { glb(axy)[(size_t)q * NRs + j] = (double)g; }, t8);
       gram_i8(xt, ot, B2, Ny, ldm, rsx, rso, false,
-              [=](int q, int j, int g) { gsx[q * Ny + j] = g; }, t8);
+              [=](int q, int j, int g) { glb(gsx)[q * Ny + j] = g; }, t8);
       for (int e = tid; e < Ny * Ny; e += kThreads) {
         const int aa = e / Ny, bb = e - aa * Ny;
         const double n = (double)gn[e];
@@ -799,21 +913,21 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
     //    v0 = L^-1 y0 as row Mc; column tile nt of V needs k < 64 (nt + 1)
     gemm_f64<false, true>(
         Mc + 1, Ny,
-        [=](int j, int k) { return j < Mc ? (double)yt[(size_t)k * ldm + j] : y0v[k]; },
-        [=](int k, int aa) { return Li[(size_t)aa * NRs + k]; },
+        [=](int j, int k) { return j < Mc ? (double)glb(yt)[(size_t)k * ldm + j] : glb(y0v)[k]; },
+        [=](int k, int aa) { return glb(Li)[(size_t)aa * NRs + k]; },
         [=](int, int nt, int& kb_, int& ke_) { kb_ = 0; ke_ = min(Ny, 64 * nt + 64); return true; },
-        [=](int j, int aa, double v) { (j < Mc ? V + (size_t)j * NRs : v0)[aa] = v; }, tl);
+        [=](int j, int aa, double v) { (j < Mc ? glb(V) + (size_t)j * NRs : glb(v0))[aa] = v; }, tl);
     // -- A = C_XY C_YY^-1 = (C_XY L^-T) L^-1: T in tmp, then A over C_XY
     gemm_f64<true, true>(
-        B2, Ny, [=](int q, int k) { return axy[(size_t)q * NRs + k]; },
-        [=](int k, int ii) { return Li[(size_t)ii * NRs + k]; },
+        B2, Ny, [=](int q, int k) { return glb(axy)[(size_t)q * NRs + k]; },
+        [=](int k, int ii) { return glb(Li)[(size_t)ii * NRs + k]; },
         [=](int, int nt, int& kb_, int& ke_) { kb_ = 0; ke_ = min(Ny, 64 * nt + 64); return true; },
-        [=](int q, int ii, double v) { tmp[(size_t)q * NRs + ii] = v; }, tl);
+        [=](int q, int ii, double v) { glb(tmp)[(size_t)q * NRs + ii] = v; }, tl);
     gemm_f64<true, false>(
-        B2, Ny, [=](int q, int ii) { return tmp[(size_t)q * NRs + ii]; },
-        [=](int ii, int mm) { return Li[(size_t)ii * NRs + mm]; },
+        B2, Ny, [=](int q, int ii) { return glb(tmp)[(size_t)q * NRs + ii]; },
+        [=](int ii, int mm) { return glb(Li)[(size_t)ii * NRs + mm]; },
         [=](int, int nt, int& kb_, int& ke_) { kb_ = 64 * nt; ke_ = Ny; return true; },
-        [=](int q, int mm, double v) { axy[(size_t)q * NRs + mm] = v; }, tl);
+        [=](int q, int mm, double v) { glb(axy)[(size_t)q * NRs + mm] = v; }, tl);
     // Mahalanobis distances to y0 and squared norms of the whitened candidates
     double dmin = INFINITY;
     for (int j = tid; j < Mc; j += kThreads) {
@@ -830,28 +944,76 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
     }
     dmin = block_min_d(dmin, hs.red);
 
+    // -- beta grid D0 2^(g/2), g = -8 .. 24.  With wide contexts the 33
+    //    evaluations of eps_y run in one pass: E[g][j] = exp(-dm0_j / (2 beta_g)
+    //    - max) (the weights of eval_eps) into the leave-one-out logit rows,
+    //    then [T | S] = E [Y^T | 1] on the MFMA tiles, and
+    //    eps_g = ||y0 - T_g / S_g||^2, a wave per g.  Narrow ones (2 x 2
+    //    patches) take 33 eval_eps calls: there the pass costs more than it
+    //    saves.
+    const double D0 = fmax(dmin, 1e-9);
+    if (Ny > kGridPassNy) {
+      if (tid < 33) hs.ginv[tid] = 1.0 / (2.0 * (D0 * exp2((double)(tid - 8) / 2.0)));
+      __syncthreads();
+      for (int g = 0; g < 33; ++g) {
+        const double inv2b = hs.ginv[g];
+        const double m = -dmin * inv2b;
+        for (int j = tid; j < Mc; j += kThreads)
+          glb(dch)[(size_t)g * Mc + j] = exp(-glb(dm0)[j] * inv2b - m);
+      }
+      __syncthreads();
+      gemm_f64<true, true>(
+          33, Ny + 1, [=](int g, int j) { return glb(dch)[(size_t)g * Mc + j]; },
+          [=](int j, int aa) { return aa < Ny ? (double)glb(yt)[(size_t)aa * ldm + j] : 1.0; },
+          [=](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Mc; return true; },
+          [=](int g, int aa, double v) { glb(tmp)[(size_t)g * NRs + aa] = v; }, tl);
+      for (int g = wave; g < 33; g += kThreads / 64) {
+        const double* row = tmp + (size_t)g * NRs;
+        const double S = row[Ny];
+        double part = 0.0;
+        for (int aa = lane; aa < Ny; aa += 64) {
+          const double d = y0v[aa] - row[aa] / S;
+          part += d * d;
+        }
+        part = wave_sum(part);
+        if (lane == 0) hs.eg[g] = part;
+      }
+      __syncthreads();
+    }
     // -- the candidates' context bytes for the eps_y evaluations: an LDS
     //    copy when they fit (the operand tiles are idle until the
     //    leave-one-out sums)
-    const uint8_t* ys = yt;
-    if (hql_eps_in_lds(hl)) {
+    const bool yl = hql_eps_in_lds(hl);
+    if (yl) {
       uint4* dst = (uint4*)L.winp;
       const uint4* srcv = (const uint4*)yt;
       for (int e = tid; e < Ny * ldm / 16; e += kThreads) dst[e] = srcv[e];
       __syncthreads();
-      ys = (const uint8_t*)L.winp;
     }
+    int flip = 0;
+    auto eps_at = [&](double b) {
+      if (Ny <= 64) {
+        flip ^= 1;
+        return yl ? eval_eps_narrow<true>(b, Mc, Ny, ldm, dm0, dmin, (const uint8_t*)L.winp, y0v, hs,
+                                          flip)
+                  : eval_eps_narrow<false>(b, Mc, Ny, ldm, dm0, dmin, yt, y0v, hs, flip);
+      }
+      return yl ? eval_eps<true>(b, Mc, Ny, B2, ldm, dm0, dmin, ew, (const uint8_t*)L.winp, nullptr,
+                                 y0v, ytil, nullptr, hs)
+                : eval_eps<false>(b, Mc, Ny, B2, ldm, dm0, dmin, ew, yt, nullptr, y0v, ytil, nullptr,
+                                  hs);
+    };
+
+    if (Ny <= kGridPassNy)
+      for (int g = 0; g < 33; ++g) {
+        const double e = eps_at(D0 * exp2((double)(g - 8) / 2.0));
+        if (tid == 0) hs.eg[g] = e;
+      }
+    __syncthreads();
+    double emin = INFINITY;
+    for (int g = 0; g < 33; ++g) emin = fmin(emin, hs.eg[g]);
 
     // -- beta: first grid minimiser, golden-section refinement on log beta
-    const double D0 = fmax(dmin, 1e-9);
-    double emin = INFINITY;
-    for (int g = -8; g <= 24; ++g) {
-      const double bt = D0 * exp2((double)g / 2.0);
-      const double e = eval_eps(bt, Mc, Ny, B2, ldm, dm0, dmin, ew, ys, nullptr, y0v, ytil, nullptr, hs);
-      if (tid == 0) hs.eg[g + 8] = e;
-      emin = fmin(emin, e);
-    }
-    __syncthreads();
     int gstar = 24;
     for (int g = 24; g >= -8; --g)
       if (hs.eg[g + 8] <= emin * (1.0 + kEpsTieRel)) gstar = g;
@@ -864,21 +1026,21 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
       const double invphi = (sqrt(5.0) - 1.0) / 2.0;
       double ct = bt - invphi * (bt - at);
       double dt = at + invphi * (bt - at);
-      double fc = eval_eps(exp(ct), Mc, Ny, B2, ldm, dm0, dmin, ew, ys, nullptr, y0v, ytil, nullptr, hs);
-      double fd = eval_eps(exp(dt), Mc, Ny, B2, ldm, dm0, dmin, ew, ys, nullptr, y0v, ytil, nullptr, hs);
+      double fc = eps_at(exp(ct));
+      double fd = eps_at(exp(dt));
       for (int it = 0; it < 40; ++it) {
         if (fc <= fd) {
           bt = dt; dt = ct; fd = fc;
           ct = bt - invphi * (bt - at);
-          fc = eval_eps(exp(ct), Mc, Ny, B2, ldm, dm0, dmin, ew, ys, nullptr, y0v, ytil, nullptr, hs);
+          fc = eps_at(exp(ct));
         } else {
           at = ct; ct = dt; fc = fd;
           dt = at + invphi * (bt - at);
-          fd = eval_eps(exp(dt), Mc, Ny, B2, ldm, dm0, dmin, ew, ys, nullptr, y0v, ytil, nullptr, hs);
+          fd = eps_at(exp(dt));
         }
       }
       beta = exp(0.5 * (at + bt));
-      const double eb = eval_eps(beta, Mc, Ny, B2, ldm, dm0, dmin, ew, ys, nullptr, y0v, ytil, nullptr, hs);
+      const double eb = eps_at(beta);
       if (!(eb < best_eps * (1.0 - kEpsTieRel))) beta = D0 * exp2((double)gstar / 2.0);
     }
 
@@ -919,12 +1081,12 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
       const int nc = min(64, k0 - c0);
       // (a) logits -D(y_i, y_j) / (2 beta), D from whitened dot products
       gemm_f64<true, true>(
-          nc, Mc, [=](int c, int k) { return V[(size_t)i0l[c0 + c] * NRs + k]; },
-          [=](int k, int j) { return V[(size_t)j * NRs + k]; },
+          nc, Mc, [=](int c, int k) { return glb(V)[(size_t)glb(i0l)[c0 + c] * NRs + k]; },
+          [=](int k, int j) { return glb(V)[(size_t)j * NRs + k]; },
           [=](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Ny; return true; },
           [=](int c, int j, double g) {
-            const int ii = i0l[c0 + c];
-            dch[(size_t)c * Mc + j] = (j == ii) ? -INFINITY : -(vn[ii] + vn[j] - 2.0 * g) * inv2b;
+            const int ii = glb(i0l)[c0 + c];
+            glb(dch)[(size_t)c * Mc + j] = (j == ii) ? -INFINITY : -(glb(vn)[ii] + glb(vn)[j] - 2.0 * g) * inv2b;
           },
           tl);
       // (b) row softmax (the member itself excluded): a wave per row, its
@@ -949,25 +1111,25 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
       //     y_i - y~_i, with z~_c = sum_j e_cj z_j / S_c over the dims of x
       //     (B2) and y (Ny)
       gemm_f64<true, true>(
-          nc, nd, [=](int c, int j) { return dch[(size_t)c * Mc + j]; },
+          nc, nd, [=](int c, int j) { return glb(dch)[(size_t)c * Mc + j]; },
           [=](int j, int dd) {
-            return dd < B2 ? (double)xt[(size_t)dd * ldm + j] : (double)yt[(size_t)(dd - B2) * ldm + j];
+            return dd < B2 ? (double)glb(xt)[(size_t)dd * ldm + j] : (double)glb(yt)[(size_t)(dd - B2) * ldm + j];
           },
           [=](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Mc; return true; },
           [=](int c, int dd, double v) {
-            const int ii = i0l[c0 + c];
-            const double own = dd < B2 ? (double)xt[(size_t)dd * ldm + ii]
-                                       : (double)yt[(size_t)(dd - B2) * ldm + ii];
-            zch[(size_t)c * ldz + dd] = own - v / rowS[c];
+            const int ii = glb(i0l)[c0 + c];
+            const double own = dd < B2 ? (double)glb(xt)[(size_t)dd * ldm + ii]
+                                       : (double)glb(yt)[(size_t)(dd - B2) * ldm + ii];
+            glb(zch)[(size_t)c * ldz + dd] = own - v / ((const lds_f64*)rowS)[c];
           },
           tl);
       // (d) c_i = A r_i; accumulate <c_i, x_i - x~_i> and ||c_i||^2
       gemm_f64<true, true>(
-          nc, B2, [=](int c, int k) { return zch[(size_t)c * ldz + B2 + k]; },
-          [=](int k, int q) { return axy[(size_t)q * NRs + k]; },
+          nc, B2, [=](int c, int k) { return glb(zch)[(size_t)c * ldz + B2 + k]; },
+          [=](int k, int q) { return glb(axy)[(size_t)q * NRs + k]; },
           [=](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Ny; return true; },
           [=, &num, &den](int c, int q, double v) {
-            num += v * zch[(size_t)c * ldz + q];
+            num += v * glb(zch)[(size_t)c * ldz + q];
             den += v * v;
           },
           tl);
@@ -977,7 +1139,7 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
     const double alpha = den > 0.0 ? num / den : 0.0;
 
     // -- x0_hat = x~(beta) + alpha A (y0 - y~(beta))
-    eval_eps(beta, Mc, Ny, B2, ldm, dm0, dmin, ew, yt, xt, y0v, ytil, xtil, hs);
+    eval_eps<false>(beta, Mc, Ny, B2, ldm, dm0, dmin, ew, yt, xt, y0v, ytil, xtil, hs);
     for (int q = tid; q < B2; q += kThreads) {
       const double* arow = axy + (size_t)q * NRs;
       double corr = 0.0;
