@@ -131,6 +131,12 @@ __device__ __constant__ const double kPow10[kPsdRepair + 1] = {1.0, 10.0, 100.0,
 
 // contexts wider than this evaluate the 33 grid points of beta in one MFMA pass
 constexpr int kGridPassNy = 64;
+// contexts of at most kNarrowNy pixels (2 x 2 patches) whiten and form the
+// leave-one-out products on VALU, a thread per candidate or per output: for
+// them the 64 x 64 MFMA tiles are mostly padding and per-tile overhead
+constexpr int kNarrowNy = 40;
+constexpr int kNarrowNd = 48;     // and at most this many x and y coordinates
+constexpr int kNarrowOut = (64 * kNarrowNd + kThreads - 1) / kThreads;
 
 // eps_y values within this relative margin count as equal: where eps_y is
 // flat (as beta -> 0 the weights become one-hot on the nearest candidate), the
@@ -909,14 +915,6 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
       return;
     }
 
-    // -- whitening: V[j] = L^-1 y_j for every candidate (row j of V), and
-    //    v0 = L^-1 y0 as row Mc; column tile nt of V needs k < 64 (nt + 1)
-    gemm_f64<false, true>(
-        Mc + 1, Ny,
-        [=](int j, int k) { return j < Mc ? (double)glb(yt)[(size_t)k * ldm + j] : glb(y0v)[k]; },
-        [=](int k, int aa) { return glb(Li)[(size_t)aa * NRs + k]; },
-        [=](int, int nt, int& kb_, int& ke_) { kb_ = 0; ke_ = min(Ny, 64 * nt + 64); return true; },
-        [=](int j, int aa, double v) { (j < Mc ? glb(V) + (size_t)j * NRs : glb(v0))[aa] = v; }, tl);
     // -- A = C_XY C_YY^-1 = (C_XY L^-T) L^-1: T in tmp, then A over C_XY
     gemm_f64<true, true>(
         B2, Ny, [=](int q, int k) { return glb(axy)[(size_t)q * NRs + k]; },
@@ -928,19 +926,64 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
         [=](int ii, int mm) { return glb(Li)[(size_t)ii * NRs + mm]; },
         [=](int, int nt, int& kb_, int& ke_) { kb_ = 64 * nt; ke_ = Ny; return true; },
         [=](int q, int mm, double v) { glb(axy)[(size_t)q * NRs + mm] = v; }, tl);
-    // Mahalanobis distances to y0 and squared norms of the whitened candidates
+    // -- whitening: V[j] = L^-1 y_j for every candidate (row j of V), v0 =
+    //    L^-1 y0, and the Mahalanobis distances to y0 and squared norms of the
+    //    whitened candidates
     double dmin = INFINITY;
-    for (int j = tid; j < Mc; j += kThreads) {
-      const double* row = V + (size_t)j * NRs;
-      double s = 0.0, nn = 0.0;
-      for (int k = 0; k < Ny; ++k) {
-        const double d = row[k] - v0[k];
-        s += d * d;
-        nn += row[k] * row[k];
+    if (Ny <= kNarrowNy) {
+      // a thread per candidate, L^-1 in LDS (every lane reads the same entry)
+      lds_f64* lw = (lds_f64*)tl;
+      lds_f64* lv0 = lw + kNarrowNy * kNarrowNy;
+      for (int e = tid; e < kNarrowNy * kNarrowNy; e += kThreads) {
+        const int aa = e / kNarrowNy, k = e - aa * kNarrowNy;
+        lw[e] = (aa < Ny && k <= aa) ? glb(Li)[(size_t)aa * NRs + k] : 0.0;
       }
-      dm0[j] = s;
-      vn[j] = nn;
-      dmin = fmin(dmin, s);
+      __syncthreads();
+      if (tid < Ny) {
+        double v = 0.0;
+        for (int k = 0; k <= tid; ++k) v = fma(lw[tid * kNarrowNy + k], glb(y0v)[k], v);
+        lv0[tid] = v;
+        glb(v0)[tid] = v;
+      }
+      __syncthreads();
+      for (int j = tid; j < Mc; j += kThreads) {
+        double y[kNarrowNy];
+#pragma unroll
+        for (int k = 0; k < kNarrowNy; ++k) y[k] = k < Ny ? (double)glb(yt)[(size_t)k * ldm + j] : 0.0;
+        double sd = 0.0, nn = 0.0;
+        for (int aa = 0; aa < Ny; ++aa) {
+          double v = 0.0;
+#pragma unroll
+          for (int k = 0; k < kNarrowNy; ++k) v = fma(lw[aa * kNarrowNy + k], y[k], v);
+          glb(V)[(size_t)j * NRs + aa] = v;
+          const double d = v - lv0[aa];
+          sd += d * d;
+          nn += v * v;
+        }
+        glb(dm0)[j] = sd;
+        glb(vn)[j] = nn;
+        dmin = fmin(dmin, sd);
+      }
+    } else {
+      // column tile nt of V needs k < 64 (nt + 1)
+      gemm_f64<false, true>(
+          Mc + 1, Ny,
+          [=](int j, int k) { return j < Mc ? (double)glb(yt)[(size_t)k * ldm + j] : glb(y0v)[k]; },
+          [=](int k, int aa) { return glb(Li)[(size_t)aa * NRs + k]; },
+          [=](int, int nt, int& kb_, int& ke_) { kb_ = 0; ke_ = min(Ny, 64 * nt + 64); return true; },
+          [=](int j, int aa, double v) { (j < Mc ? glb(V) + (size_t)j * NRs : glb(v0))[aa] = v; }, tl);
+      for (int j = tid; j < Mc; j += kThreads) {
+        const double* row = V + (size_t)j * NRs;
+        double sd = 0.0, nn = 0.0;
+        for (int k = 0; k < Ny; ++k) {
+          const double d = row[k] - v0[k];
+          sd += d * d;
+          nn += row[k] * row[k];
+        }
+        dm0[j] = sd;
+        vn[j] = nn;
+        dmin = fmin(dmin, sd);
+      }
     }
     dmin = block_min_d(dmin, hs.red);
 
@@ -1080,15 +1123,46 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
     for (int c0 = 0; c0 < k0; c0 += 64) {
       const int nc = min(64, k0 - c0);
       // (a) logits -D(y_i, y_j) / (2 beta), D from whitened dot products
-      gemm_f64<true, true>(
-          nc, Mc, [=](int c, int k) { return glb(V)[(size_t)glb(i0l)[c0 + c] * NRs + k]; },
-          [=](int k, int j) { return glb(V)[(size_t)j * NRs + k]; },
-          [=](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Ny; return true; },
-          [=](int c, int j, double g) {
-            const int ii = glb(i0l)[c0 + c];
-            glb(dch)[(size_t)c * Mc + j] = (j == ii) ? -INFINITY : -(glb(vn)[ii] + glb(vn)[j] - 2.0 * g) * inv2b;
-          },
-          tl);
+      if (Ny <= kNarrowNy) {
+        // a thread per candidate; the members' whitened rows in LDS
+        lds_f64* vi = (lds_f64*)tl;                          // nc x kNarrowNy
+        lds_f64* vni = vi + 64 * kNarrowNy;                 // their squared norms
+        __attribute__((address_space(3))) int* iic = (__attribute__((address_space(3))) int*)(vni + 64);
+        for (int e = tid; e < nc * kNarrowNy; e += kThreads) {
+          const int c = e / kNarrowNy, k = e - c * kNarrowNy;
+          vi[e] = k < Ny ? glb(V)[(size_t)glb(i0l)[c0 + c] * NRs + k] : 0.0;
+        }
+        if (tid < nc) {
+          const int ii = glb(i0l)[c0 + tid];
+          iic[tid] = ii;
+          vni[tid] = glb(vn)[ii];
+        }
+        __syncthreads();
+        for (int j = tid; j < Mc; j += kThreads) {
+          double vj[kNarrowNy];
+#pragma unroll
+          for (int k = 0; k < kNarrowNy; ++k) vj[k] = k < Ny ? glb(V)[(size_t)j * NRs + k] : 0.0;
+          const double vnj = glb(vn)[j];
+          for (int c = 0; c < nc; ++c) {
+            double g = 0.0;
+#pragma unroll
+            for (int k = 0; k < kNarrowNy; ++k) g = fma(vi[c * kNarrowNy + k], vj[k], g);
+            glb(dch)[(size_t)c * Mc + j] = (j == iic[c]) ? -INFINITY : -(vni[c] + vnj - 2.0 * g) * inv2b;
+          }
+        }
+        __syncthreads();
+      } else {
+        gemm_f64<true, true>(
+            nc, Mc, [=](int c, int k) { return glb(V)[(size_t)glb(i0l)[c0 + c] * NRs + k]; },
+            [=](int k, int j) { return glb(V)[(size_t)j * NRs + k]; },
+            [=](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Ny; return true; },
+            [=](int c, int j, double g) {
+              const int ii = glb(i0l)[c0 + c];
+              glb(dch)[(size_t)c * Mc + j] =
+                  (j == ii) ? -INFINITY : -(glb(vn)[ii] + glb(vn)[j] - 2.0 * g) * inv2b;
+            },
+            tl);
+      }
       // (b) row softmax (the member itself excluded): a wave per row, its
       //     lanes striding the candidates (coalesced), fixed-order wave sums
       for (int c = wave; c < nc; c += kThreads / 64) {
@@ -1110,19 +1184,74 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
       // (c) residuals of the leave-one-out predictions, x_i - x~_i and
       //     y_i - y~_i, with z~_c = sum_j e_cj z_j / S_c over the dims of x
       //     (B2) and y (Ny)
-      gemm_f64<true, true>(
-          nc, nd, [=](int c, int j) { return glb(dch)[(size_t)c * Mc + j]; },
-          [=](int j, int dd) {
-            return dd < B2 ? (double)glb(xt)[(size_t)dd * ldm + j] : (double)glb(yt)[(size_t)(dd - B2) * ldm + j];
-          },
-          [=](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Mc; return true; },
-          [=](int c, int dd, double v) {
+      if (Ny <= kNarrowNy && nd <= kNarrowNd) {
+        // a thread per output (c, dd); candidates staged 64 at a time
+        lds_f64* es = (lds_f64*)tl;                                 // nc x 64 weights
+        __attribute__((address_space(3))) uint8_t* zs =
+            (__attribute__((address_space(3))) uint8_t*)(es + 64 * 64);   // nd x 68 bytes
+        double acc[kNarrowOut];
+#pragma unroll
+        for (int t = 0; t < kNarrowOut; ++t) acc[t] = 0.0;
+        for (int j0 = 0; j0 < Mc; j0 += 64) {
+          for (int e = tid; e < nc * 64; e += kThreads) {
+            const int c = e >> 6, jj = e & 63;
+            es[e] = j0 + jj < Mc ? glb(dch)[(size_t)c * Mc + j0 + jj] : 0.0;
+          }
+          for (int e = tid; e < nd * 64; e += kThreads) {
+            const int dd = e >> 6, jj = e & 63;
+            zs[dd * 68 + jj] = dd < B2 ? glb(xt)[(size_t)dd * ldm + j0 + jj]
+                                       : glb(yt)[(size_t)(dd - B2) * ldm + j0 + jj];
+          }
+          __syncthreads();
+#pragma unroll
+          for (int t = 0; t < kNarrowOut; ++t) {
+            const int o = tid + kThreads * t;
+            if (o < nc * nd) {
+              const int c = o / nd, dd = o - c * nd;
+              const lds_f64* er = es + c * 64;
+              const __attribute__((address_space(3))) uint32_t* zr =
+                  (const __attribute__((address_space(3))) uint32_t*)(zs + dd * 68);
+              double a_ = acc[t];
+              for (int q = 0; q < 16; ++q) {
+                const uint32_t w = zr[q];
+                a_ = fma(er[4 * q], (double)(w & 0xffu), a_);
+                a_ = fma(er[4 * q + 1], (double)((w >> 8) & 0xffu), a_);
+                a_ = fma(er[4 * q + 2], (double)((w >> 16) & 0xffu), a_);
+                a_ = fma(er[4 * q + 3], (double)(w >> 24), a_);
+              }
+              acc[t] = a_;
+            }
+          }
+          __syncthreads();
+        }
+#pragma unroll
+        for (int t = 0; t < kNarrowOut; ++t) {
+          const int o = tid + kThreads * t;
+          if (o < nc * nd) {
+            const int c = o / nd, dd = o - c * nd;
             const int ii = glb(i0l)[c0 + c];
             const double own = dd < B2 ? (double)glb(xt)[(size_t)dd * ldm + ii]
                                        : (double)glb(yt)[(size_t)(dd - B2) * ldm + ii];
-            glb(zch)[(size_t)c * ldz + dd] = own - v / ((const lds_f64*)rowS)[c];
-          },
-          tl);
+            glb(zch)[(size_t)c * ldz + dd] = own - acc[t] / ((const lds_f64*)rowS)[c];
+          }
+        }
+        __syncthreads();
+      } else {
+        gemm_f64<true, true>(
+            nc, nd, [=](int c, int j) { return glb(dch)[(size_t)c * Mc + j]; },
+            [=](int j, int dd) {
+              return dd < B2 ? (double)glb(xt)[(size_t)dd * ldm + j]
+                             : (double)glb(yt)[(size_t)(dd - B2) * ldm + j];
+            },
+            [=](int, int, int& kb_, int& ke_) { kb_ = 0; ke_ = Mc; return true; },
+            [=](int c, int dd, double v) {
+              const int ii = glb(i0l)[c0 + c];
+              const double own = dd < B2 ? (double)glb(xt)[(size_t)dd * ldm + ii]
+                                         : (double)glb(yt)[(size_t)(dd - B2) * ldm + ii];
+              glb(zch)[(size_t)c * ldz + dd] = own - v / ((const lds_f64*)rowS)[c];
+            },
+            tl);
+      }
       // (d) c_i = A r_i; accumulate <c_i, x_i - x~_i> and ||c_i||^2
       gemm_f64<true, true>(
           nc, B2, [=](int c, int k) { return glb(zch)[(size_t)c * ldz + B2 + k]; },
