@@ -149,6 +149,9 @@ struct HqlShared {
   double eg[33];                 // eps_y on the beta grid g = -8 .. 24
   double ginv[33];               // 1 / (2 beta_g) on that grid
   double pb[2][kThreads / 64][65];   // eval_eps_narrow: per-wave row partials, S at [64]
+  int hist[kThreads];            // I0 radix selection: counts of one 8-bit digit
+  long long pref;
+  int rank;
   double S;
   double rowS[64];
 };
@@ -1087,32 +1090,58 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
       if (!(eb < best_eps * (1.0 - kEpsTieRel))) beta = D0 * exp2((double)gstar / 2.0);
     }
 
-    // -- I0: the min(Ny + 1, Mc) candidates of smallest (distance, index),
-    //    found by bisection on the packed key; listed in candidate order
-    //    (hql_partial: of smallest d / n, as floor(d 2^20 / n), which keeps
-    //    the order of the fractions: distinct ones differ by >= 2^20 / n^2 > 3)
+    // -- I0: the min(Ny + 1, Mc) candidates of smallest (distance, index):
+    //    the k0-th smallest packed key by radix selection (8 bits a pass,
+    //    exact integer counts), then the keys up to it listed in candidate
+    //    order (hql_partial: of smallest d / n, as floor(d 2^20 / n), which
+    //    keeps the order of the fractions: distinct ones differ by
+    //    >= 2^20 / n^2 > 3).  The keys live in the weight array, free here.
     const int k0 = min(Ny + 1, Mc);
     {
-      auto key = [&](int j) -> long long {
+      __attribute__((address_space(3))) long long* keys =
+          (__attribute__((address_space(3))) long long*)ew;
+      for (int j = tid; j < Mc; j += kThreads) {
         const long long d = compd[j];
-        return (hp ? (d << 20) / cnl[j] : d) << 13 | j;
-      };
-      long long lo = 0, hi = hp ? (1ll << 60) - 1 : (1ll << 40) - 1;
-      while (lo < hi) {
-        const long long mid = lo + ((hi - lo) >> 1);
-        int c = 0;
-        for (int j = tid; j < Mc; j += kThreads) c += key(j) <= mid;
-        c = (int)block_sum_d((double)c, hs.red);
-        if (c >= k0) hi = mid; else lo = mid + 1;
+        keys[j] = (hp ? (d << 20) / cnl[j] : d) << 13 | j;
       }
+      long long prefix = 0;                 // the key's bits above `shift` found so far
+      int rank = k0;                        // its rank among the keys with that prefix
+      for (int shift = hp ? 56 : 32; shift >= 0; shift -= 8) {
+        hs.hist[tid] = 0;                   // kThreads == 256 bins
+        __syncthreads();
+        const long long hmask = shift + 8 >= 64 ? 0ll : ~((1ll << (shift + 8)) - 1);
+        for (int j = tid; j < Mc; j += kThreads) {
+          const long long k = keys[j];
+          if (((k ^ prefix) & hmask) == 0) atomicAdd(&hs.hist[(int)((k >> shift) & 255)], 1);
+        }
+        __syncthreads();
+        if (wave == 0) {
+          int c4[4], sum4 = 0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sum4 += (c4[q] = hs.hist[4 * lane + q]);
+          int before = wave_incl_scan(sum4) - sum4;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (before < rank && before + c4[q] >= rank) {
+              hs.pref = prefix | ((long long)(4 * lane + q) << shift);
+              hs.rank = rank - before;
+            }
+            before += c4[q];
+          }
+        }
+        __syncthreads();
+        prefix = hs.pref;
+        rank = hs.rank;
+      }
+      const long long lo = prefix;
       const int per = (Mc + kThreads - 1) / kThreads;
       const int j0 = min(Mc, tid * per), j1 = min(Mc, j0 + per);
       int cnt = 0;
-      for (int j = j0; j < j1; ++j) cnt += key(j) <= lo;
+      for (int j = j0; j < j1; ++j) cnt += keys[j] <= lo;
       int tot = 0;
       int pos = block_excl_scan(cnt, sh.scan, &tot);
       for (int j = j0; j < j1; ++j)
-        if (key(j) <= lo) i0l[pos++] = j;
+        if (keys[j] <= lo) i0l[pos++] = j;
       __syncthreads();
     }
 
