@@ -645,6 +645,89 @@ static __device__ double eval_eps_narrow(double beta, int Mc, int Ny, int ldm, c
   return wave_sum(part);
 }
 
+// Narrow-context whitening (Ny <= NYN): a thread per candidate with its NYN
+// context values in registers; L^-1 (NYN x NYN, zeros above the diagonal and
+// beyond Ny) in LDS, read by every lane at once.  Writes V[j], dm0[j], vn[j]
+// and v0; returns the thread's smallest distance to y0.
+template <int NYN>
+static __device__ __forceinline__ double whiten_narrow(const double* Li, int NRs, int Ny,
+                                                       const uint8_t* yt, int ldm, int Mc,
+                                                       const double* y0v, double* V, double* v0,
+                                                       double* dm0, double* vn, double* tl) {
+  const int tid = threadIdx.x;
+  lds_f64* lw = (lds_f64*)tl;
+  lds_f64* lv0 = lw + NYN * NYN;
+  for (int e = tid; e < NYN * NYN; e += kThreads) {
+    const int aa = e / NYN, k = e - aa * NYN;
+    lw[e] = (aa < Ny && k <= aa) ? glb(Li)[(size_t)aa * NRs + k] : 0.0;
+  }
+  __syncthreads();
+  if (tid < Ny) {
+    double v = 0.0;
+    for (int k = 0; k <= tid; ++k) v = fma(lw[tid * NYN + k], glb(y0v)[k], v);
+    lv0[tid] = v;
+    glb(v0)[tid] = v;
+  }
+  __syncthreads();
+  double dmin = INFINITY;
+  for (int j = tid; j < Mc; j += kThreads) {
+    double y[NYN];
+#pragma unroll
+    for (int k = 0; k < NYN; ++k) y[k] = k < Ny ? (double)glb(yt)[(size_t)k * ldm + j] : 0.0;
+    double sd = 0.0, nn = 0.0;
+    for (int aa = 0; aa < Ny; ++aa) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < NYN; ++k) v = fma(lw[aa * NYN + k], y[k], v);
+      glb(V)[(size_t)j * NRs + aa] = v;
+      const double d = v - lv0[aa];
+      sd += d * d;
+      nn += v * v;
+    }
+    glb(dm0)[j] = sd;
+    glb(vn)[j] = nn;
+    dmin = fmin(dmin, sd);
+  }
+  return dmin;
+}
+
+// Narrow-context leave-one-out logits -D(y_i, y_j) / (2 beta) for the nc
+// members from c0 on: a thread per candidate with its whitened row in
+// registers; the members' rows, norms and indices in LDS.
+template <int NYN>
+static __device__ __forceinline__ void logits_narrow(const double* V, const int* i0l, int c0,
+                                                     int nc, int NRs, int Ny, const double* vn,
+                                                     int Mc, double* dch, double inv2b,
+                                                     double* tl) {
+  const int tid = threadIdx.x;
+  lds_f64* vi = (lds_f64*)tl;                          // nc x NYN
+  lds_f64* vni = vi + 64 * NYN;                       // their squared norms
+  __attribute__((address_space(3))) int* iic = (__attribute__((address_space(3))) int*)(vni + 64);
+  for (int e = tid; e < nc * NYN; e += kThreads) {
+    const int c = e / NYN, k = e - c * NYN;
+    vi[e] = k < Ny ? glb(V)[(size_t)glb(i0l)[c0 + c] * NRs + k] : 0.0;
+  }
+  if (tid < nc) {
+    const int ii = glb(i0l)[c0 + tid];
+    iic[tid] = ii;
+    vni[tid] = glb(vn)[ii];
+  }
+  __syncthreads();
+  for (int j = tid; j < Mc; j += kThreads) {
+    double vj[NYN];
+#pragma unroll
+    for (int k = 0; k < NYN; ++k) vj[k] = k < Ny ? glb(V)[(size_t)j * NRs + k] : 0.0;
+    const double vnj = glb(vn)[j];
+    for (int c = 0; c < nc; ++c) {
+      double g = 0.0;
+#pragma unroll
+      for (int k = 0; k < NYN; ++k) g = fma(vi[c * NYN + k], vj[k], g);
+      glb(dch)[(size_t)c * Mc + j] = (j == iic[c]) ? -INFINITY : -(vni[c] + vnj - 2.0 * g) * inv2b;
+    }
+  }
+  __syncthreads();
+}
+
 // HQL for entry h of one frame's list, on this workgroup's scratch slot.
 // The caller has run phase_tables; `first` is true for the workgroup's first
 // block of the launch.
@@ -935,38 +1018,8 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
     double dmin = INFINITY;
     if (Ny <= kNarrowNy) {
       // a thread per candidate, L^-1 in LDS (every lane reads the same entry)
-      lds_f64* lw = (lds_f64*)tl;
-      lds_f64* lv0 = lw + kNarrowNy * kNarrowNy;
-      for (int e = tid; e < kNarrowNy * kNarrowNy; e += kThreads) {
-        const int aa = e / kNarrowNy, k = e - aa * kNarrowNy;
-        lw[e] = (aa < Ny && k <= aa) ? glb(Li)[(size_t)aa * NRs + k] : 0.0;
-      }
-      __syncthreads();
-      if (tid < Ny) {
-        double v = 0.0;
-        for (int k = 0; k <= tid; ++k) v = fma(lw[tid * kNarrowNy + k], glb(y0v)[k], v);
-        lv0[tid] = v;
-        glb(v0)[tid] = v;
-      }
-      __syncthreads();
-      for (int j = tid; j < Mc; j += kThreads) {
-        double y[kNarrowNy];
-#pragma unroll
-        for (int k = 0; k < kNarrowNy; ++k) y[k] = k < Ny ? (double)glb(yt)[(size_t)k * ldm + j] : 0.0;
-        double sd = 0.0, nn = 0.0;
-        for (int aa = 0; aa < Ny; ++aa) {
-          double v = 0.0;
-#pragma unroll
-          for (int k = 0; k < kNarrowNy; ++k) v = fma(lw[aa * kNarrowNy + k], y[k], v);
-          glb(V)[(size_t)j * NRs + aa] = v;
-          const double d = v - lv0[aa];
-          sd += d * d;
-          nn += v * v;
-        }
-        glb(dm0)[j] = sd;
-        glb(vn)[j] = nn;
-        dmin = fmin(dmin, sd);
-      }
+      dmin = Ny <= 32 ? whiten_narrow<32>(Li, NRs, Ny, yt, ldm, Mc, y0v, V, v0, dm0, vn, tl)
+                      : whiten_narrow<kNarrowNy>(Li, NRs, Ny, yt, ldm, Mc, y0v, V, v0, dm0, vn, tl);
     } else {
       // column tile nt of V needs k < 64 (nt + 1)
       gemm_f64<false, true>(
@@ -1154,32 +1207,8 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
       // (a) logits -D(y_i, y_j) / (2 beta), D from whitened dot products
       if (Ny <= kNarrowNy) {
         // a thread per candidate; the members' whitened rows in LDS
-        lds_f64* vi = (lds_f64*)tl;                          // nc x kNarrowNy
-        lds_f64* vni = vi + 64 * kNarrowNy;                 // their squared norms
-        __attribute__((address_space(3))) int* iic = (__attribute__((address_space(3))) int*)(vni + 64);
-        for (int e = tid; e < nc * kNarrowNy; e += kThreads) {
-          const int c = e / kNarrowNy, k = e - c * kNarrowNy;
-          vi[e] = k < Ny ? glb(V)[(size_t)glb(i0l)[c0 + c] * NRs + k] : 0.0;
-        }
-        if (tid < nc) {
-          const int ii = glb(i0l)[c0 + tid];
-          iic[tid] = ii;
-          vni[tid] = glb(vn)[ii];
-        }
-        __syncthreads();
-        for (int j = tid; j < Mc; j += kThreads) {
-          double vj[kNarrowNy];
-#pragma unroll
-          for (int k = 0; k < kNarrowNy; ++k) vj[k] = k < Ny ? glb(V)[(size_t)j * NRs + k] : 0.0;
-          const double vnj = glb(vn)[j];
-          for (int c = 0; c < nc; ++c) {
-            double g = 0.0;
-#pragma unroll
-            for (int k = 0; k < kNarrowNy; ++k) g = fma(vi[c * kNarrowNy + k], vj[k], g);
-            glb(dch)[(size_t)c * Mc + j] = (j == iic[c]) ? -INFINITY : -(vni[c] + vnj - 2.0 * g) * inv2b;
-          }
-        }
-        __syncthreads();
+        if (Ny <= 32) logits_narrow<32>(V, i0l, c0, nc, NRs, Ny, vn, Mc, dch, inv2b, tl);
+        else logits_narrow<kNarrowNy>(V, i0l, c0, nc, NRs, Ny, vn, Mc, dch, inv2b, tl);
       } else {
         gemm_f64<true, true>(
             nc, Mc, [=](int c, int k) { return glb(V)[(size_t)glb(i0l)[c0 + c] * NRs + k]; },
