@@ -288,12 +288,17 @@ __global__ __launch_bounds__(kThreads) void k_cnn_init(float* prm, unsigned long
 // (3x3 taps x input channels) times (taps x channels) by (output positions),
 // run as v_mfma_f32_16x16x32_bf16 tiles with FP32 accumulation: the weights
 // are the A operand (rows = output channels), the im2col activations the B
-// operand (columns = positions).  One workgroup (4 waves) owns one block at a
-// time: its input and both hidden activations stay in LDS in a
-// position-major layout (one 80-byte slot of 32 bf16 channels per pixel,
-// padded against bank conflicts) with a zero row and column in front for the
-// convolutions' padding.  The weight fragments stay in registers for the
-// workgroup's life.
+// operand (columns = positions).
+//
+// A workgroup of two waves owns one block at a time, persistently over a
+// range of blocks.  Wave w computes output channels 16 w .. 16 w + 15 of
+// every layer over all its positions, so that it keeps one half of every
+// layer's weights in registers for the workgroup's life, and a barrier
+// separates the layers.  The block's input and both hidden activations stay
+// in LDS in a position-major layout (one 80-byte slot of 32 bf16 channels per
+// pixel, padded against bank conflicts) with a zero row and column in front
+// for the convolutions' padding.  Small workgroups with 27 KB of LDS put five
+// blocks in flight on every CU.
 //
 // Operand layout of the 16x16x32 MFMA: lane l supplies row (A) or column (B)
 // l % 16 with the eight K values 8 (l / 16) .. 8 (l / 16) + 7; it receives
@@ -308,34 +313,31 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kIn = kS + 1;     // padded side of the space-to-depth input
-constexpr int kS1 = 13;         // padded side of layer-1 output (12 + 1)
-constexpr int kS2 = 7;          // padded side of layer-2 output (6 + 1)
-constexpr int kPix = 40;        // bf16 slots per activation pixel (32 used)
+constexpr int kGateThreads = 128; // two waves per workgroup, one block at a time
+constexpr int kIn = kS + 1;       // padded side of the space-to-depth input
+constexpr int kS1 = 13;           // padded side of layer-1 output (12 + 1)
+constexpr int kS2 = 7;            // padded side of layer-2 output (6 + 1)
+constexpr int kPix = 40;          // bf16 slots per activation pixel (32 used)
 
 struct __align__(16) GateLds {
   u32x4 in[kIn * kIn];                    // the 8 input channels of a pixel (16 B)
   uint16_t a1[kS1 * kS1 * kPix];
   uint16_t a2[kS2 * kS2 * kPix];
-  float p3[4][16][17];                    // layer-3 partial sums: wave, channel row, position
+  float bias[5][kC];                      // per channel: b1, b2, b3 and the head weights wh0, wh1
+  float hp[2][2];                         // head sums of the two waves
+  int red[2][4];                          // ring statistics of the two waves
 };
 static_assert(offsetof(GateLds, a1) % 16 == 0 && offsetof(GateLds, a2) % 16 == 0,
               "activation images must be 16-byte aligned for 128-bit LDS reads");
 
-// Work split of the four waves: wave w owns output-channel tile mt = w & 1 in
-// every layer; layers 1 and 2 split the position tiles between the wave
-// pairs (tiles (w >> 1) + 2 t), layer 3 (one position tile) splits its taps
-// (taps (w >> 1) + 2 u) and sums the two halves in LDS.  A wave thus holds
-// one channel tile of the weights of layers 1 and 2 and about half the taps
-// of layer 3 in registers.
-constexpr int kL3Taps = 5;                // taps of layer 3 per wave (the last pair holds 4)
-
+// A wave's weights: output-channel tile mt = wave index; lane l holds row
+// l % 16 of the A fragments.  The per-channel values (biases, head weights)
+// are in LDS (GateLds::bias), where lane l reads those of its four D rows,
+// channels 16 mt + 4 (l / 16) + j, when a layer needs them.
 struct GateWeights {
   bf16x8 w1[3];                           // layer 1: K steps of 4 taps x 8 channels
   bf16x8 w2[9];                           // layer 2: per tap
-  bf16x8 w3[kL3Taps];                     // layer 3: taps (w >> 1) + 2 u
-  float b1[4], b2[4];                     // biases of this lane's four D rows
-  float b3, wh0, wh1;                     // channel `lane` of layer 3 and the head (lanes < 32)
+  bf16x8 w3[9];                           // layer 3: per tap
   float bh0, bh1;                         // head biases
 };
 
@@ -361,16 +363,15 @@ static __device__ __forceinline__ bf16x8 weight_frag(const float* w, int cin, in
   return __builtin_bit_cast(bf16x8, (u32x4){u[0], u[1], u[2], u[3]});
 }
 
-// The register image of one wave's weights, per lane: 17 bf16x8 MFMA
-// fragments (layer 1: 3, layer 2: 9, layer 3: 5), then b1, b2 and (b3, wh0,
-// wh1, 0) as float4.  Packed once per weight update (k_gate_pack) into
-// [role = wave][item][lane] order, so that a workgroup loads its weights
-// with 16-byte coalesced reads.
-constexpr int kPackItems = 3 + 9 + kL3Taps + 3;
+// The register image of one wave's weights, per lane: 21 bf16x8 MFMA
+// fragments (layer 1: 3, layers 2 and 3: 9 each).  Packed once per weight
+// update (k_gate_pack) into [role = wave][item][lane] order, so that a
+// workgroup loads its weights with 16-byte coalesced reads.
+constexpr int kPackItems = 3 + 9 + 9;
 
-static __device__ __forceinline__ GateWeights gate_weights_from(const float* wq, int wave,
+static __device__ __forceinline__ GateWeights gate_weights_from(const float* wq, int mt,
                                                                 int lane) {
-  const int row = lane & 15, g = lane >> 4, mt = wave & 1;
+  const int row = lane & 15, g = lane >> 4;
   const int n = mt * 16 + row;
   const bf16x8 zero = __builtin_bit_cast(bf16x8, (u32x4){0u, 0u, 0u, 0u});
   GateWeights W;
@@ -382,19 +383,7 @@ static __device__ __forceinline__ GateWeights gate_weights_from(const float* wq,
 #pragma unroll
   for (int tap = 0; tap < 9; ++tap) W.w2[tap] = weight_frag(wq + kOffW2, kC, n, 8 * g, tap);
 #pragma unroll
-  for (int u = 0; u < kL3Taps; ++u) {
-    const int tap = (wave >> 1) + 2 * u;
-    W.w3[u] = tap < 9 ? weight_frag(wq + kOffW3, kC, n, 8 * g, tap) : zero;
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    W.b1[j] = wq[kOffB1 + mt * 16 + 4 * g + j];
-    W.b2[j] = wq[kOffB2 + mt * 16 + 4 * g + j];
-  }
-  const int c = lane & (kC - 1);
-  W.b3 = wq[kOffB3 + c];
-  W.wh0 = wq[kOffWh + c];
-  W.wh1 = wq[kOffWh + kC + c];
+  for (int tap = 0; tap < 9; ++tap) W.w3[tap] = weight_frag(wq + kOffW3, kC, n, 8 * g, tap);
   W.bh0 = wq[kOffBh];
   W.bh1 = wq[kOffBh + 1];
   return W;
@@ -411,13 +400,7 @@ __global__ __launch_bounds__(64) void k_gate_pack(const float* wq, uint4* pk) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) o[64 * f++] = __builtin_bit_cast(uint4, W.w2[k]);
 #pragma unroll
-  for (int k = 0; k < kL3Taps; ++k) o[64 * f++] = __builtin_bit_cast(uint4, W.w3[k]);
-  o[64 * f++] = make_uint4(__float_as_uint(W.b1[0]), __float_as_uint(W.b1[1]),
-                           __float_as_uint(W.b1[2]), __float_as_uint(W.b1[3]));
-  o[64 * f++] = make_uint4(__float_as_uint(W.b2[0]), __float_as_uint(W.b2[1]),
-                           __float_as_uint(W.b2[2]), __float_as_uint(W.b2[3]));
-  o[64 * f++] = make_uint4(__float_as_uint(W.b3), __float_as_uint(W.wh0), __float_as_uint(W.wh1),
-                           0u);
+  for (int k = 0; k < 9; ++k) o[64 * f++] = __builtin_bit_cast(uint4, W.w3[k]);
 }
 
 static __device__ __forceinline__ GateWeights load_gate_weights(const uint4* pk, const float* wq) {
@@ -433,29 +416,29 @@ static __device__ __forceinline__ GateWeights load_gate_weights(const uint4* pk,
 #pragma unroll
   for (int k = 0; k < 9; ++k) W.w2[k] = __builtin_bit_cast(bf16x8, v[f++]);
 #pragma unroll
-  for (int k = 0; k < kL3Taps; ++k) W.w3[k] = __builtin_bit_cast(bf16x8, v[f++]);
-  const uint4 b1 = v[f++], b2 = v[f++], hb = v[f++];
-  W.b1[0] = __uint_as_float(b1.x); W.b1[1] = __uint_as_float(b1.y);
-  W.b1[2] = __uint_as_float(b1.z); W.b1[3] = __uint_as_float(b1.w);
-  W.b2[0] = __uint_as_float(b2.x); W.b2[1] = __uint_as_float(b2.y);
-  W.b2[2] = __uint_as_float(b2.z); W.b2[3] = __uint_as_float(b2.w);
-  W.b3 = __uint_as_float(hb.x); W.wh0 = __uint_as_float(hb.y); W.wh1 = __uint_as_float(hb.z);
+  for (int k = 0; k < 9; ++k) W.w3[k] = __builtin_bit_cast(bf16x8, v[f++]);
   W.bh0 = wq[kOffBh];
   W.bh1 = wq[kOffBh + 1];
   return W;
 }
 
 // zero the padding row and column of every LDS image (never written later)
-static __device__ __forceinline__ void gate_clear_padding(GateLds& G) {
-  for (int e = threadIdx.x; e < 2 * kIn; e += kThreads) {
+// and copy the per-channel values to LDS
+static __device__ __forceinline__ void gate_lds_init(GateLds& G, const float* wq) {
+  for (int e = threadIdx.x; e < 5 * kC; e += kGateThreads) {
+    const int k = e / kC, c = e - k * kC;
+    const int off = k == 0 ? kOffB1 : k == 1 ? kOffB2 : k == 2 ? kOffB3 : k == 3 ? kOffWh : kOffWh + kC;
+    G.bias[k][c] = wq[off + c];
+  }
+  for (int e = threadIdx.x; e < 2 * kIn; e += kGateThreads) {
     const int k = e % kIn;
     G.in[e < kIn ? k : k * kIn] = (u32x4){0u, 0u, 0u, 0u};
   }
-  for (int e = threadIdx.x; e < 2 * kS1 * kPix; e += kThreads) {
+  for (int e = threadIdx.x; e < 2 * kS1 * kPix; e += kGateThreads) {
     const int pix = (e / kPix) % kS1, c = e % kPix;
     G.a1[(e < kS1 * kPix ? pix : pix * kS1) * kPix + c] = 0;
   }
-  for (int e = threadIdx.x; e < 2 * kS2 * kPix; e += kThreads) {
+  for (int e = threadIdx.x; e < 2 * kS2 * kPix; e += kGateThreads) {
     const int pix = (e / kPix) % kS2, c = e % kPix;
     G.a2[(e < kS2 * kPix ? pix : pix * kS2) * kPix + c] = 0;
   }
@@ -465,18 +448,26 @@ static __device__ __forceinline__ bf16x8 lds_frag(const uint16_t* p) {
   return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
 }
 
-// The network on the input staged in G.in; returns (y0, y1) in every lane of
-// wave 0.  Barriers inside; the caller syncs before staging the next input.
+// The network on the input staged in G.in (the caller has synchronised the
+// workgroup after staging); returns (y0, y1) in every thread.  Barriers
+// inside; G.in is free again when it returns.
 static __device__ __forceinline__ void gate_network(GateLds& G, const GateWeights& W, float& y0,
                                                     float& y1) {
-  const int lane = lane_id(), wave = wave_id();
-  const int col = lane & 15, g = lane >> 4, mt = wave & 1;
+  const int lane = lane_id(), mt = wave_id();
+  const int col = lane & 15, g = lane >> 4;
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  const int ch = mt * 16 + 4 * g;        // channel of this lane's first D row
+  auto bias4 = [&](int k, float* b) {
+    const float4 v = *reinterpret_cast<const float4*>(&G.bias[k][ch]);
+    b[0] = v.x; b[1] = v.y; b[2] = v.z; b[3] = v.w;
+  };
 
   // layer 1: 144 positions = 9 column tiles; K = 9 taps x 8 channels in
-  // three steps (lane group g takes tap 4 step + g; tap 9 .. 11 are zero).
+  // three steps (lane group g takes tap 4 step + g; taps 9 .. 11 are zero).
   // The next tile's fragments are read while this tile's products run.
   {
+    float b1[4];
+    bias4(0, b1);
     u32x4 Xn[3];
     auto read_tile = [&](int nt) {
       const int m = nt * 16 + col;
@@ -488,13 +479,13 @@ static __device__ __forceinline__ void gate_network(GateLds& G, const GateWeight
         Xn[ks] = tap < 9 ? G.in[(2 * oy + ky) * kIn + 2 * ox + kx] : (u32x4){0u, 0u, 0u, 0u};
       }
     };
-    read_tile(wave >> 1);
+    read_tile(0);
 #pragma unroll 1
-    for (int nt = wave >> 1; nt < 9; nt += 2) {
+    for (int nt = 0; nt < 9; ++nt) {
       u32x4 X[3];
 #pragma unroll
       for (int ks = 0; ks < 3; ++ks) X[ks] = Xn[ks];
-      if (nt + 2 < 9) read_tile(nt + 2);
+      if (nt + 1 < 9) read_tile(nt + 1);
       f32x4 d = zero;
 #pragma unroll
       for (int ks = 0; ks < 3; ++ks)
@@ -503,69 +494,79 @@ static __device__ __forceinline__ void gate_network(GateLds& G, const GateWeight
       const int m = nt * 16 + col;
       const int oy = m / 12, ox = m - oy * 12;
       *reinterpret_cast<uint2*>(&G.a1[((oy + 1) * kS1 + ox + 1) * kPix + mt * 16 + 4 * g]) =
-          relu_pack4(d, W.b1);
+          relu_pack4(d, b1);
     }
   }
   __syncthreads();
 
-  // layer 2: 36 positions = 3 column tiles (the last 4 columns wide)
-#pragma unroll 1
-  for (int nt = wave >> 1; nt < 3; nt += 2) {
-    const int mv = nt * 16 + col;
-    const int m = min(mv, 35);
-    const int oy = m / 6, ox = m - oy * 6;
-    f32x4 acc = zero;
+  // layer 2: 36 positions = 3 column tiles (the last 4 columns wide), the
+  // three accumulation chains interleaved tap by tap
+  {
+    float b2[4];
+    bias4(1, b2);
+    f32x4 acc[3] = {zero, zero, zero};
+    int base[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int m = min(t * 16 + col, 35);
+      const int oy = m / 6, ox = m - oy * 6;
+      base[t] = (2 * oy * kS1 + 2 * ox) * kPix + 8 * g;
+    }
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
-      const int ky = tap / 3, kx = tap % 3;
-      const bf16x8 X = lds_frag(&G.a1[((2 * oy + ky) * kS1 + 2 * ox + kx) * kPix + 8 * g]);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.w2[tap], X, acc, 0, 0, 0);
-      // at most three fragments in flight: keeps the registers within four
-      // waves per SIMD
-      if (tap % 3 == 2) __builtin_amdgcn_sched_barrier(0);
+      const int off = ((tap / 3) * kS1 + tap % 3) * kPix;
+      bf16x8 X[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) X[t] = lds_frag(&G.a1[base[t] + off]);
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.w2[tap], X[t], acc[t], 0, 0, 0);
     }
-    if (mv < 36)
-      *reinterpret_cast<uint2*>(&G.a2[((oy + 1) * kS2 + ox + 1) * kPix + mt * 16 + 4 * g]) =
-          relu_pack4(acc, W.b2);
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int mv = t * 16 + col;
+      if (mv < 36) {
+        const int oy = mv / 6, ox = mv - oy * 6;
+        *reinterpret_cast<uint2*>(&G.a2[((oy + 1) * kS2 + ox + 1) * kPix + mt * 16 + 4 * g]) =
+            relu_pack4(acc[t], b2);
+      }
+    }
   }
   __syncthreads();
 
   // layer 3: 9 positions = one column tile (columns 9 .. 15 repeat position
-  // 8 and are dropped below); this wave's taps, partial sums to LDS
+  // 8 and are dropped); then the average pool of relu(conv + b3) and the
+  // linear head over this wave's 16 channels
   {
     const int m = min(col, kPool - 1);
     const int oy = m / 3, ox = m - oy * 3;
     f32x4 acc = zero;
 #pragma unroll
-    for (int u = 0; u < kL3Taps; ++u) {
-      const int tap = (wave >> 1) + 2 * u;
-      if (tap < 9) {
-        const int ky = tap / 3, kx = tap % 3;
-        const bf16x8 X = lds_frag(&G.a2[((2 * oy + ky) * kS2 + 2 * ox + kx) * kPix + 8 * g]);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.w3[u], X, acc, 0, 0, 0);
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ky = tap / 3, kx = tap % 3;
+      const bf16x8 X = lds_frag(&G.a2[((2 * oy + ky) * kS2 + 2 * ox + kx) * kPix + 8 * g]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.w3[tap], X, acc, 0, 0, 0);
+    }
+    float b3[4], wh0[4], wh1[4];
+    bias4(2, b3);
+    bias4(3, wh0);
+    bias4(4, wh1);
+    float h0 = 0.0f, h1 = 0.0f;
+    if (col < kPool) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float r = fmaxf(acc[j] + b3[j], 0.0f);
+        h0 += r * wh0[j];
+        h1 += r * wh1[j];
       }
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) G.p3[wave][4 * g + j][col] = acc[j];
+    h0 = wave_sum(h0);
+    h1 = wave_sum(h1);
+    if (lane == 0) { G.hp[mt][0] = h0; G.hp[mt][1] = h1; }
   }
   __syncthreads();
-
-  // pooled relu(conv + b3) per channel, then the two head outputs (wave 0)
-  if (wave == 0) {
-    float h0 = 0.0f, h1 = 0.0f;
-    if (lane < kC) {
-      const int t = lane >> 4, r = lane & 15;
-      float s = 0.0f;
-#pragma unroll
-      for (int mm = 0; mm < kPool; ++mm)
-        s += fmaxf(G.p3[t][r][mm] + G.p3[t + 2][r][mm] + W.b3, 0.0f);
-      const float gv = s * (1.0f / kPool);
-      h0 = gv * W.wh0;
-      h1 = gv * W.wh1;
-    }
-    y0 = wave_sum(h0) + W.bh0;
-    y1 = wave_sum(h1) + W.bh1;
-  }
+  y0 = (G.hp[0][0] + G.hp[1][0]) * (1.0f / kPool) + W.bh0;
+  y1 = (G.hp[0][1] + G.hp[1][1]) * (1.0f / kPool) + W.bh1;
 }
 
 // the 8 space-to-depth channels of input pixel (Y, X) from the four window
@@ -582,6 +583,94 @@ static __device__ __forceinline__ u32x4 s2d_pixel(const int* v) {
                  c1[2] | (c1[3] << 16)};
 }
 
+// Window staging of the gate kernels: thread t owns input pixels
+// t + 128 k (four window pixels each).  The other workgroups on the CU
+// (five are resident) cover the load latency.
+constexpr int kGatePer = (kS * kS + kGateThreads - 1) / kGateThreads;
+
+struct GateWindow {
+  int v[kGatePer][4];
+
+  // the window of the block in frame cell `cell`
+  __device__ __forceinline__ void load(const FrameArgs& a, const DevParams& p, int cell) {
+    // the per-thread index arithmetic is redone for every block rather than
+    // kept live across the network (an empty asm hides that it repeats)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int by = cell / p.gw, bx = cell - by * p.gw;
+    const int gy0 = by * p.B + p.B / 2 - kP / 2, gx0 = bx * p.B + p.B / 2 - kP / 2;
+#pragma unroll
+    for (int t = 0; t < kGatePer; ++t) {
+      const int idx = tid + t * kGateThreads;
+      const int Y = idx / kS, X = idx - Y * kS;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gy = gy0 + 2 * Y + (q >> 1), gx = gx0 + 2 * X + (q & 1);
+        const bool in = idx < kS * kS && gy >= 0 && gy < p.height && gx >= 0 && gx < p.width;
+        const int cy = min(max(gy, 0), p.height - 1), cx = min(max(gx, 0), p.width - 1);
+        // 32-bit byte offsets (a value plane is far below 4 GiB): one register
+        // per address
+        const uint32_t off = 2u * (uint32_t)(cy * p.width + cx);
+        const int val = *(const int16_t*)((const char*)a.val + off);
+        v[t][q] = in ? val : -1;
+      }
+    }
+  }
+
+  // Writes the input image and returns the known context pixels of the
+  // footprint (ring plus the block's own received pixels): count (own ones
+  // again in bits 16..), sum, minimum, maximum, summed over the workgroup
+  // (every thread gets them; one barrier inside).
+  __device__ __forceinline__ void stage(GateLds& G, const DevParams& p, int& c, int& sum,
+                                        int& vmin, int& vmax) const {
+    const int lane = lane_id(), wave = wave_id();
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int b0 = kP / 2 - p.B / 2, b1 = b0 + p.B, f0 = b0 - p.r, f1 = b1 + p.r;
+    c = 0; sum = 0; vmin = 255; vmax = 0;
+#pragma unroll
+    for (int t = 0; t < kGatePer; ++t) {
+      const int idx = tid + t * kGateThreads;
+      if (idx < kS * kS) {
+        const int Y = idx / kS, X = idx - Y * kS;
+        G.in[(Y + 1) * kIn + X + 1] = s2d_pixel(v[t]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int wy = 2 * Y + (q >> 1), wx = 2 * X + (q & 1);
+          const bool ctx = wy >= f0 && wy < f1 && wx >= f0 && wx < f1;
+          const bool own = wy >= b0 && wy < b1 && wx >= b0 && wx < b1;
+          if (ctx && v[t][q] >= 0) {
+            c += own ? 1 + (1 << 16) : 1;
+            sum += v[t][q]; vmin = min(vmin, v[t][q]); vmax = max(vmax, v[t][q]);
+          }
+        }
+      }
+    }
+    c = wave_sum(c); sum = wave_sum(sum); vmin = wave_min(vmin); vmax = wave_max(vmax);
+    if (lane == 0) { G.red[wave][0] = c; G.red[wave][1] = sum; G.red[wave][2] = vmin; G.red[wave][3] = vmax; }
+    __syncthreads();
+    c = G.red[0][0] + G.red[1][0];
+    sum = G.red[0][1] + G.red[1][1];
+    vmin = min(G.red[0][2], G.red[1][2]);
+    vmax = max(G.red[0][3], G.red[1][3]);
+  }
+};
+
+// the statistics and the layer choice of block i (thread 0)
+static __device__ __forceinline__ void gate_record(const FrameArgs& a, const DevParams& p, int i,
+                                                   int c, int sum, int vmin, int vmax, float y0,
+                                                   float y1, float tau1, float tau2, int& nq,
+                                                   int& mx) {
+  const int nown = c >> 16;
+  c &= 0xffff;
+  a.m0cnt[i] = c | (nown > 0 ? kPartialBit : 0);
+  a.ring[i] = make_int2(sum, vmin | (vmax << 16));
+  nq += c >= p.r * p.B;
+  mx = max(mx, c);
+  a.gate[i] = (int8_t)(y0 <= tau1 ? SKM_LAYER_BRL : (y1 > tau2 ? SKM_LAYER_HQL : SKM_LAYER_IDL));
+  if (a.gate_pred) { a.gate_pred[2 * i] = y0; a.gate_pred[2 * i + 1] = y1; }
+}
+
 // In-pipeline gate, which also does the round preparation in CNN mode: one
 // pass over the pending blocks of the round.  For each it records the
 // known in-frame ring pixels (count, sum, minimum, maximum) from the window
@@ -589,18 +678,15 @@ static __device__ __forceinline__ u32x4 s2d_pixel(const int* v) {
 // gate[i] (the predictions to gate_pred).  Each workgroup adds its (blocks
 // with |m0| >= r B, largest |m0|) to the round's context rule, as the prep
 // kernel does.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_gate(
-    FrameArgs a, DevParams p, const uint4* pk, const float* wq, float tau1, float tau2) {
+__global__ __launch_bounds__(kGateThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_gate(FrameArgs a, DevParams p,
+                                                           const uint4* pk, const float* wq,
+                                                           float tau1, float tau2) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  __shared__ int red[kThreads / 64][4];
   GateLds& G = *reinterpret_cast<GateLds*>(lds_raw);
   RoundState* st = a.st;
   if (st->remaining == 0) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) st->n_hql = 0;
   const int n_lost = st->n_lost;
-  gate_clear_padding(G);
-  const GateWeights W = load_gate_weights(pk, wq);
-  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   // XCD x (workgroups x, x + 8, ...) takes the x-th contiguous eighth of the
   // blocks, the same eighth as in the estimation kernel, so that the window
   // pixels read here are still in that XCD's L2 when the block is estimated;
@@ -610,87 +696,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
   const int pw = (per8 + (int)(gridDim.x >> 3) - 1) / (int)(gridDim.x >> 3);
   const int i_begin = min(xend, xcd * per8 + (int)(blockIdx.x >> 3) * pw);
   const int i_end = min(xend, i_begin + pw);
-  // ring of the block in window coordinates: footprint rows/columns
-  // [f0, f1), block [b0, b1)
-  const int b0 = kP / 2 - p.B / 2, b1 = b0 + p.B, f0 = b0 - p.r, f1 = b1 + p.r;
-  // the window pixels of block i + 1 are loaded while block i runs: thread t
-  // owns input pixels t + 256 k, four window pixels each
-  constexpr int kPer = (kS * kS + kThreads - 1) / kThreads;
-  int v[kPer][4];
-  auto load_block = [&](int blk) {
-    const int cell = a.blk[blk];
-    const int by = cell / p.gw, bx = cell - by * p.gw;
-    const int gy0 = by * p.B + p.B / 2 - kP / 2, gx0 = bx * p.B + p.B / 2 - kP / 2;
-#pragma unroll
-    for (int t = 0; t < kPer; ++t) {
-      const int idx = tid + t * kThreads;
-      const int Y = idx / kS, X = idx - Y * kS;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int gy = gy0 + 2 * Y + (q >> 1), gx = gx0 + 2 * X + (q & 1);
-        const bool in = idx < kS * kS && gy >= 0 && gy < p.height && gx >= 0 && gx < p.width;
-        const int cy = min(max(gy, 0), p.height - 1), cx = min(max(gx, 0), p.width - 1);
-        const int val = a.val[(size_t)cy * p.width + cx];
-        v[t][q] = in ? val : -1;
-      }
-    }
-  };
-  int nx_state = 1;                        // state of the next block travels with its pixels
-  if (i_begin < i_end) { load_block(i_begin); nx_state = a.bstate[i_begin]; }
+  if (i_begin >= i_end) return;
+  gate_lds_init(G, wq);
+  const GateWeights W = load_gate_weights(pk, wq);
+  // state and cell of the next block are read one block ahead
+  int nx_state = a.bstate[i_begin], nx_cell = a.blk[i_begin];
   int wg_nq = 0, wg_max = 0;
   for (int i = i_begin; i < i_end; ++i) {
-    const bool pending = nx_state == 0;
-    if (pending) {
-      int c = 0, sum = 0, vmin = 255, vmax = 0;
-#pragma unroll
-      for (int t = 0; t < kPer; ++t) {
-        const int idx = tid + t * kThreads;
-        if (idx < kS * kS) {
-          const int Y = idx / kS, X = idx - Y * kS;
-          G.in[(Y + 1) * kIn + X + 1] = s2d_pixel(v[t]);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            // context: the footprint, with the block's own received pixels
-            // (counted again in bits 16.. to flag a partly received block)
-            const int wy = 2 * Y + (q >> 1), wx = 2 * X + (q & 1);
-            const bool ctx = wy >= f0 && wy < f1 && wx >= f0 && wx < f1;
-            const bool own = wy >= b0 && wy < b1 && wx >= b0 && wx < b1;
-            if (ctx && v[t][q] >= 0) {
-              c += own ? 1 + (1 << 16) : 1;
-              sum += v[t][q]; vmin = min(vmin, v[t][q]); vmax = max(vmax, v[t][q]);
-            }
-          }
-        }
-      }
-      c = wave_sum(c); sum = wave_sum(sum); vmin = wave_min(vmin); vmax = wave_max(vmax);
-      if (lane == 0) { red[wave][0] = c; red[wave][1] = sum; red[wave][2] = vmin; red[wave][3] = vmax; }
-    }
-    __syncthreads();
-    if (pending && tid == 0) {
-      int c = 0, sum = 0, vmin = 255, vmax = 0;
-      for (int w = 0; w < kThreads / 64; ++w) {
-        c += red[w][0]; sum += red[w][1]; vmin = min(vmin, red[w][2]); vmax = max(vmax, red[w][3]);
-      }
-      const int nown = c >> 16;
-      c &= 0xffff;
-      a.m0cnt[i] = c | (nown > 0 ? kPartialBit : 0);
-      a.ring[i] = make_int2(sum, vmin | (vmax << 16));
-      wg_nq += c >= p.r * p.B;
-      wg_max = max(wg_max, c);
-    }
-    if (i + 1 < i_end) { load_block(i + 1); nx_state = a.bstate[i + 1]; }
-    if (!pending) continue;
-    float y0 = 0.0f, y1 = 0.0f;
+    const int state = nx_state, cell = nx_cell;
+    if (i + 1 < i_end) { nx_state = a.bstate[i + 1]; nx_cell = a.blk[i + 1]; }
+    if (state != 0) continue;            // not pending (uniform in the workgroup)
+    GateWindow win;
+    win.load(a, p, cell);
+    int c, sum, vmin, vmax;
+    win.stage(G, p, c, sum, vmin, vmax);
+    float y0, y1;
     gate_network(G, W, y0, y1);
-    if (tid == 0) {
-      a.gate[i] = (int8_t)(y0 <= tau1 ? SKM_LAYER_BRL : (y1 > tau2 ? SKM_LAYER_HQL : SKM_LAYER_IDL));
-      if (a.gate_pred) { a.gate_pred[2 * i] = y0; a.gate_pred[2 * i + 1] = y1; }
-    }
-    __syncthreads();
+    if (threadIdx.x == 0) gate_record(a, p, i, c, sum, vmin, vmax, y0, y1, tau1, tau2, wg_nq, wg_max);
   }
-  if (tid == 0) {
-    note_context_rule(st, wg_nq, wg_max);
-  }
+  if (threadIdx.x == 0) note_context_rule(st, wg_nq, wg_max);
 }
 
 // The gate over every frame of a batch (same block size and ring): as
@@ -698,14 +722,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
 // the workgroups by XCD eighths.  The weights are loaded once per workgroup
 // for all its blocks.  Each workgroup adds its blocks to the context rule of
 // their frame when it moves to the next frame.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_gate_b(
-    BatchArgs b, DevParams p, const uint4* pk, const float* wq, float tau1, float tau2) {
+__global__ __launch_bounds__(kGateThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_gate_b(BatchArgs b, DevParams p,
+                                                             const uint4* pk, const float* wq,
+                                                             float tau1, float tau2) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  __shared__ int red[kThreads / 64][4];
   GateLds& G = *reinterpret_cast<GateLds*>(lds_raw);
   if (b.bs->remaining == 0) return;
   if (blockIdx.x == 0)
-    for (int f = threadIdx.x; f < b.nf; f += kThreads) b.a0.st[f].n_hql = 0;
+    for (int f = threadIdx.x; f < b.nf; f += kGateThreads) b.a0.st[f].n_hql = 0;
   const int total = b.bs->total;
   const int per8 = (total + 7) >> 3, xcd = blockIdx.x & 7;
   const int xend = min(total, (xcd + 1) * per8);
@@ -713,120 +737,45 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
   const int g_begin = min(xend, xcd * per8 + (int)(blockIdx.x >> 3) * pw);
   const int g_end = min(xend, g_begin + pw);
   if (g_begin >= g_end) return;
-  gate_clear_padding(G);
+  gate_lds_init(G, wq);
   const GateWeights W = load_gate_weights(pk, wq);
-  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
-  const int b0 = kP / 2 - p.B / 2, b1 = b0 + p.B, f0 = b0 - p.r, f1 = b1 + p.r;
-  const int rB = p.r * p.B;
-  constexpr int kPer = (kS * kS + kThreads - 1) / kThreads;
-  int v[kPer][4];
-  auto load_block = [&](const FrameArgs& a, int blk) {
-    const int cell = a.blk[blk];
-    const int by = cell / p.gw, bx = cell - by * p.gw;
-    const int gy0 = by * p.B + p.B / 2 - kP / 2, gx0 = bx * p.B + p.B / 2 - kP / 2;
-#pragma unroll
-    for (int t = 0; t < kPer; ++t) {
-      const int idx = tid + t * kThreads;
-      const int Y = idx / kS, X = idx - Y * kS;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int gy = gy0 + 2 * Y + (q >> 1), gx = gx0 + 2 * X + (q & 1);
-        const bool in = idx < kS * kS && gy >= 0 && gy < p.height && gx >= 0 && gx < p.width;
-        const int cy = min(max(gy, 0), p.height - 1), cx = min(max(gx, 0), p.width - 1);
-        const int val = a.val[(size_t)cy * p.width + cx];
-        v[t][q] = in ? val : -1;
-      }
-    }
-  };
-  // frame of the prefetched item (fn) and of the current one (fc)
-  int fn = frame_of(b.cum, b.nf, g_begin);
-  FrameArgs an = batch_frame(b, fn);
-  int nx_state = 1;
-  {
-    const int i = g_begin - b.cum[fn];
-    load_block(an, i);
-    nx_state = an.st->remaining ? an.bstate[i] : 1;
-  }
   int fc = -1;
-  FrameArgs ac = an;
+  FrameArgs ac = batch_frame(b, 0);
   int wg_nq = 0, wg_max = 0;
   for (int g = g_begin; g < g_end; ++g) {
-    if (fn != fc) {
-      if (fc >= 0 && tid == 0) note_context_rule(ac.st, wg_nq, wg_max);
+    if (fc < 0 || g >= b.cum[fc + 1]) {
+      if (fc >= 0 && threadIdx.x == 0) note_context_rule(ac.st, wg_nq, wg_max);
       wg_nq = 0; wg_max = 0;
-      fc = fn;
-      ac = an;
+      fc = fc < 0 ? frame_of(b.cum, b.nf, g) : fc + 1;
+      while (g >= b.cum[fc + 1]) ++fc;
+      ac = batch_frame(b, fc);
     }
     const int i = g - b.cum[fc];
-    const bool pending = nx_state == 0;
-    if (pending) {
-      int c = 0, sum = 0, vmin = 255, vmax = 0;
-#pragma unroll
-      for (int t = 0; t < kPer; ++t) {
-        const int idx = tid + t * kThreads;
-        if (idx < kS * kS) {
-          const int Y = idx / kS, X = idx - Y * kS;
-          G.in[(Y + 1) * kIn + X + 1] = s2d_pixel(v[t]);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int wy = 2 * Y + (q >> 1), wx = 2 * X + (q & 1);
-            const bool ctx = wy >= f0 && wy < f1 && wx >= f0 && wx < f1;
-            const bool own = wy >= b0 && wy < b1 && wx >= b0 && wx < b1;
-            if (ctx && v[t][q] >= 0) {
-              c += own ? 1 + (1 << 16) : 1;
-              sum += v[t][q]; vmin = min(vmin, v[t][q]); vmax = max(vmax, v[t][q]);
-            }
-          }
-        }
-      }
-      c = wave_sum(c); sum = wave_sum(sum); vmin = wave_min(vmin); vmax = wave_max(vmax);
-      if (lane == 0) { red[wave][0] = c; red[wave][1] = sum; red[wave][2] = vmin; red[wave][3] = vmax; }
-    }
-    __syncthreads();
-    if (pending && tid == 0) {
-      int c = 0, sum = 0, vmin = 255, vmax = 0;
-      for (int w = 0; w < kThreads / 64; ++w) {
-        c += red[w][0]; sum += red[w][1]; vmin = min(vmin, red[w][2]); vmax = max(vmax, red[w][3]);
-      }
-      const int nown = c >> 16;
-      c &= 0xffff;
-      ac.m0cnt[i] = c | (nown > 0 ? kPartialBit : 0);
-      ac.ring[i] = make_int2(sum, vmin | (vmax << 16));
-      wg_nq += c >= rB;
-      wg_max = max(wg_max, c);
-    }
-    if (g + 1 < g_end) {
-      if (g + 1 >= b.cum[fn + 1]) {
-        while (g + 1 >= b.cum[fn + 1]) ++fn;
-        an = batch_frame(b, fn);
-      }
-      const int in = g + 1 - b.cum[fn];
-      load_block(an, in);
-      nx_state = an.st->remaining ? an.bstate[in] : 1;
-    }
-    if (!pending) continue;
-    float y0 = 0.0f, y1 = 0.0f;
+    if (ac.st->remaining == 0 || ac.bstate[i] != 0) continue;   // uniform in the workgroup
+    GateWindow win;
+    win.load(ac, p, ac.blk[i]);
+    int c, sum, vmin, vmax;
+    win.stage(G, p, c, sum, vmin, vmax);
+    float y0, y1;
     gate_network(G, W, y0, y1);
-    if (tid == 0) {
-      ac.gate[i] = (int8_t)(y0 <= tau1 ? SKM_LAYER_BRL : (y1 > tau2 ? SKM_LAYER_HQL : SKM_LAYER_IDL));
-      if (ac.gate_pred) { ac.gate_pred[2 * i] = y0; ac.gate_pred[2 * i + 1] = y1; }
-    }
-    __syncthreads();
+    if (threadIdx.x == 0)
+      gate_record(ac, p, i, c, sum, vmin, vmax, y0, y1, tau1, tau2, wg_nq, wg_max);
   }
-  if (tid == 0) note_context_rule(ac.st, wg_nq, wg_max);
+  if (threadIdx.x == 0) note_context_rule(ac.st, wg_nq, wg_max);
 }
 
 // Batched inference on prepared inputs x (bf16 bits [n][8][24][24]).
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_infer(
-    const uint16_t* x, int n, const uint4* pk, const float* wq, float* y) {
+__global__ __launch_bounds__(kGateThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_infer(const uint16_t* x, int n,
+                                                            const uint4* pk, const float* wq,
+                                                            float* y) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   GateLds& G = *reinterpret_cast<GateLds*>(lds_raw);
-  gate_clear_padding(G);
+  gate_lds_init(G, wq);
   const GateWeights W = load_gate_weights(pk, wq);
   const int tid = threadIdx.x;
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const uint16_t* xi = x + (size_t)i * kC0 * kS * kS;
-    for (int idx = tid; idx < kS * kS; idx += kThreads) {
+    for (int idx = tid; idx < kS * kS; idx += kGateThreads) {
       uint32_t u[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -835,10 +784,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
       G.in[(Y + 1) * kIn + X + 1] = (u32x4){u[0], u[1], u[2], u[3]};
     }
     __syncthreads();
-    float y0 = 0.0f, y1 = 0.0f;
+    float y0, y1;
     gate_network(G, W, y0, y1);
     if (tid == 0) { y[2 * (size_t)i] = y0; y[2 * (size_t)i + 1] = y1; }
-    __syncthreads();
   }
 }
 
@@ -856,8 +804,8 @@ hipError_t launch_cnn_inputs(const FrameArgs& a, const DevParams& p, uint16_t* o
   return hipGetLastError();
 }
 
-// upper bound of the gate's persistent grid (three workgroups per CU are
-// resident: registers; the caller picks the grid below this)
+// upper bound of the gate's persistent grid (five workgroups per CU are
+// resident: LDS; the caller picks the grid below this)
 constexpr int kGateGrid = 4096;
 constexpr int kInferGrid = 768;
 
@@ -869,31 +817,31 @@ int cnn_gate_grid(int requested) {
 
 hipError_t launch_cnn_gate(const FrameArgs& a, const DevParams& p, const uint4* pk,
                            const float* wq, float tau1, float tau2, int max_blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_cnn_gate, dim3(cnn_gate_grid(max_blocks)), dim3(kThreads), sizeof(GateLds),
+  hipLaunchKernelGGL(k_cnn_gate, dim3(cnn_gate_grid(max_blocks)), dim3(kGateThreads), sizeof(GateLds),
                      s, a, p, pk, wq, tau1, tau2);
   return hipGetLastError();
 }
 
 hipError_t launch_cnn_gate_b(const BatchArgs& b, const DevParams& p, const uint4* pk,
                              const float* wq, float tau1, float tau2, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_cnn_gate_b, dim3(cnn_gate_grid(grid)), dim3(kThreads), sizeof(GateLds), s,
+  hipLaunchKernelGGL(k_cnn_gate_b, dim3(cnn_gate_grid(grid)), dim3(kGateThreads), sizeof(GateLds), s,
                      b, p, pk, wq, tau1, tau2);
   return hipGetLastError();
 }
 
 hipError_t cnn_infer(const uint16_t* x, int n, const uint4* pk, const float* wq, float* y,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_cnn_infer, dim3(n > kInferGrid ? kInferGrid : n), dim3(kThreads),
+  hipLaunchKernelGGL(k_cnn_infer, dim3(n > kInferGrid ? kInferGrid : n), dim3(kGateThreads),
                      sizeof(GateLds), s, x, n, pk, wq, y);
   return hipGetLastError();
 }
 
 hipError_t cnn_pack(const float* wq, uint4* pk, hipStream_t s) {
-  hipLaunchKernelGGL(k_gate_pack, dim3(kThreads / 64), dim3(64), 0, s, wq, pk);
+  hipLaunchKernelGGL(k_gate_pack, dim3(kGateThreads / 64), dim3(64), 0, s, wq, pk);
   return hipGetLastError();
 }
 
-size_t cnn_pack_bytes() { return sizeof(uint4) * (kThreads / 64) * kPackItems * 64; }
+size_t cnn_pack_bytes() { return sizeof(uint4) * (kGateThreads / 64) * kPackItems * 64; }
 
 size_t cnn_gate_lds_bytes() { return sizeof(GateLds); }
 

@@ -645,6 +645,63 @@ static __device__ double eval_eps_narrow(double beta, int Mc, int Ny, int ldm, c
   return wave_sum(part);
 }
 
+// The 33 grid evaluations of eps_y for contexts of at most 32 pixels: a wave
+// per beta_g over all candidates, with no barrier inside (the weights and
+// sums of eval_eps_narrow, one wave instead of four); eps_g to hs.eg[g].
+// 1 / (2 beta_g) comes from hs.ginv.
+template <bool YL>
+static __device__ void grid_eps_narrow(int Mc, int Ny, int ldm, const double* dm0, double dmin,
+                                       const uint8_t* ys, const double* y0, HqlShared& hs) {
+  const int lane = lane_id(), wave = wave_id();
+  for (int g = wave; g < 33; g += kThreads / 64) {
+    const double inv2b = hs.ginv[g];
+    const double m = -dmin * inv2b;
+    double acc[32];
+#pragma unroll
+    for (int a = 0; a < 32; ++a) acc[a] = 0.0;
+    double sp = 0.0;
+    for (int j0 = 4 * lane; j0 < Mc; j0 += 256) {
+      double e[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        e[t] = j0 + t < Mc ? exp(-glb(dm0)[j0 + t] * inv2b - m) : 0.0;
+        sp += e[t];
+      }
+#pragma unroll
+      for (int a = 0; a < 32; ++a) {
+        const uint8_t* row = ys + (size_t)a * ldm + j0;
+        const uint32_t w = a < Ny ? (YL ? *(lds_u32c*)row : *(glb_u32c*)row) : 0u;
+        acc[a] += e[0] * (double)(w & 0xffu) + e[1] * (double)((w >> 8) & 0xffu) +
+                  e[2] * (double)((w >> 16) & 0xffu) + e[3] * (double)(w >> 24);
+      }
+    }
+    // butterfly: lane l ends with the wave's sum of row l >> 1
+    double u[16], v[8], x[4], q[2];
+    const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0,
+               h2 = (lane & 4) != 0, h1 = (lane & 2) != 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      u[r] = (h5 ? acc[r + 16] : acc[r]) + __shfl_xor(h5 ? acc[r] : acc[r + 16], 32, 64);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = (h4 ? u[r + 8] : u[r]) + __shfl_xor(h4 ? u[r] : u[r + 8], 16, 64);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r] = (h3 ? v[r + 4] : v[r]) + __shfl_xor(h3 ? v[r] : v[r + 4], 8, 64);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) q[r] = (h2 ? x[r + 2] : x[r]) + __shfl_xor(h2 ? x[r] : x[r + 2], 4, 64);
+    double t = (h1 ? q[1] : q[0]) + __shfl_xor(h1 ? q[0] : q[1], 2, 64);
+    t += __shfl_xor(t, 1, 64);
+    const double S = wave_sum(sp);
+    const int a = lane >> 1;
+    double part = 0.0;
+    if ((lane & 1) == 0 && a < Ny) {
+      const double d = glb(y0)[a] - t / S;
+      part = d * d;
+    }
+    part = wave_sum(part);
+    if (lane == 0) hs.eg[g] = part;
+  }
+}
+
 // Narrow-context whitening (Ny <= NYN): a thread per candidate with its NYN
 // context values in registers; L^-1 (NYN x NYN, zeros above the diagonal and
 // beyond Ny) in LDS, read by every lane at once.  Writes V[j], dm0[j], vn[j]
@@ -1047,9 +1104,10 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
     //    evaluations of eps_y run in one pass: E[g][j] = exp(-dm0_j / (2 beta_g)
     //    - max) (the weights of eval_eps) into the leave-one-out logit rows,
     //    then [T | S] = E [Y^T | 1] on the MFMA tiles, and
-    //    eps_g = ||y0 - T_g / S_g||^2, a wave per g.  Narrow ones (2 x 2
-    //    patches) take 33 eval_eps calls: there the pass costs more than it
-    //    saves.
+    //    eps_g = ||y0 - T_g / S_g||^2, a wave per g.  Contexts of at most 32
+    //    pixels (2 x 2 patches) take a wave per g over all candidates
+    //    (grid_eps_narrow, after the LDS copy below), the others up to 64
+    //    pixels 33 eval_eps calls.
     const double D0 = fmax(dmin, 1e-9);
     if (Ny > kGridPassNy) {
       if (tid < 33) hs.ginv[tid] = 1.0 / (2.0 * (D0 * exp2((double)(tid - 8) / 2.0)));
@@ -1103,7 +1161,14 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
                                   hs);
     };
 
-    if (Ny <= kGridPassNy)
+    if (Ny <= 32) {
+      if (tid < 33) hs.ginv[tid] = 1.0 / (2.0 * (D0 * exp2((double)(tid - 8) / 2.0)));
+      __syncthreads();
+      if (yl)
+        grid_eps_narrow<true>(Mc, Ny, ldm, dm0, dmin, (const uint8_t*)L.winp, y0v, hs);
+      else
+        grid_eps_narrow<false>(Mc, Ny, ldm, dm0, dmin, yt, y0v, hs);
+    } else if (Ny <= kGridPassNy)
       for (int g = 0; g < 33; ++g) {
         const double e = eps_at(D0 * exp2((double)(g - 8) / 2.0));
         if (tid == 0) hs.eg[g] = e;

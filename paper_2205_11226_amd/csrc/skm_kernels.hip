@@ -521,8 +521,11 @@ static __device__ __forceinline__ void est_block(const FrameArgs& a, const DevPa
     const double bm = b < p.nrad ? __longlong_as_double((long long)sh.bmax[b]) : -INFINITY;
     double m, cs;
     int cc;
-    double fpair = 0.0;   // KR <= 8: exp(bm[lane & 7] - m[lane >> 3]) for lane & 7 <= lane >> 3
-    if (KR <= 8) {
+    // at most 8 radii (every variant of that case sums in this same order,
+    // so that they agree bit for bit)
+    const bool r8 = KR <= 8 || p.nrad <= 8;
+    double fpair = 0.0;   // r8: exp(bm[lane & 7] - m[lane >> 3]) for lane & 7 <= lane >> 3
+    if (r8) {
       // lane (g, h) = (lane >> 3, lane & 7) holds bucket h's term of prefix g:
       // one exponential per lane, then sums over the eight lanes of a group
       const int g = lane >> 3, h = lane & 7;
@@ -588,7 +591,7 @@ static __device__ __forceinline__ void est_block(const FrameArgs& a, const DevPa
     const double m_r = readlane_f64(m, ridx);
     // weight of a candidate of bucket b <= ridx: term * exp(bm[b] - max over
     // buckets <= ridx); sums (cs_r) are relative to the same maximum
-    if (KR <= 8) {
+    if (r8) {
       if ((lane >> 3) == ridx && (lane & 7) < p.nrad) sh.fsc[lane & 7] = fpair;   // 0 past ridx
     } else if (lane < p.nrad) {
       sh.fsc[lane] = (lane <= ridx && bm != -INFINITY) ? (bm == m_r ? 1.0 : exp(bm - m_r)) : 0.0;

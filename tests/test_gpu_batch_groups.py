@@ -121,12 +121,17 @@ def test_batched_kernels_match_single_frames(ctx):
 
 @pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_estimation_variants_agree(ctx, variant):
-    """Every estimation kernel variant (candidate slices per thread) gives
-    the same results on a group of 1080p-lattice-like frames."""
+    """Every estimation kernel variant (candidate slices per thread, radius
+    buckets) gives the same results, bit for bit, on a group of
+    1080p-lattice-like frames.  The last frame has a block whose log nu
+    differed in the last bit when the 16-bucket variant summed the six
+    radii of the default window in another order."""
     import paper_2205_11226_amd as skm
     frames = [(synth.make_luma(256, 384, 800 + k, n_bumps=20, n_edges=8, texture=True),
                synth.loss_dispersed(256, 384, 16, k & 1, 0)) for k in range(3)]
-    prms = [device_params("cnn")] * 3
+    frames.append((synth.make_luma(240, 320, 953, n_bumps=16, n_edges=6),
+                   synth.loss_dispersed(240, 320, 16)))
+    prms = [device_params("cnn")] * 4
     refs = [run_single(ctx, f, m, prm) for (f, m), prm in zip(frames, prms)]
     ctx.set_option(skm.OPT_EST_VARIANT, variant)
     try:
