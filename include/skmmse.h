@@ -326,7 +326,7 @@ enum {
   SKM_OPT_GRAPHS = 1,         /* 1 (default): replay captured hipGraphs; 0: eager */
   SKM_OPT_BATCH_STREAMS = 2,  /* frames in flight in skm_conceal_batch, 1..8 (4)  */
   SKM_OPT_GATE_GRID = 3,      /* workgroups of the CNN gate kernel, multiple of 8
-                                 in 8..4096 (768)                                 */
+                                 in 8..4096 (1280: five per CU are resident)      */
   SKM_OPT_HQL_GRID = 4,       /* most workgroups of the HQL kernel, 1..1024; 0
                                  (default): as many as 1 GiB of scratch per frame
                                  slot holds, 128..1024 by geometry                */
@@ -348,9 +348,9 @@ skm_status skm_get_option(skm_ctx* ctx, int32_t option, int64_t* value);
 
 /* Autotuner: times skm_conceal_batch on these frames under each launch
  * configuration -- batched mode with every estimation variant of the first
- * frame's geometry, gate grids 512, 768, 1536 and 3072 (CNN mode) and group
+ * frame's geometry, gate grids 640, 1280, 2560 and 3840 (CNN mode) and group
  * splits 1, 2 and 4, and
- * frame pipelines on 1, 2, 4 and 8 streams with gate grids 512, 768 and 1536
+ * frame pipelines on 1, 2, 4 and 8 streams with gate grids 640, 1280 and 2560
  * (CNN mode); graphs on and off -- keeping the best of `reps` runs each.  The
  * winner's batch mode, streams and graph use are set on the context; in
  * batched mode its estimation variant and gate grid are kept in the tile

@@ -98,7 +98,7 @@ struct GroupSlot {
   BatchArgs b;
   int max_rounds = 0;
   int rounds_enqueued = 0;
-  int est_variant = 0, gate_grid = 768;
+  int est_variant = 0, gate_grid = 1280;
   // kernel timing: event pairs around the batched estimation kernel
   std::vector<hipEvent_t> ev;
   int ev_used = 0;
@@ -138,7 +138,7 @@ struct skm_ctx {
   bool use_graphs = true;
   int batch_mode = 1;             // 1: batched kernels per group; 0: frame pipelines
   int batch_streams = 4;
-  int gate_grid = 768;
+  int gate_grid = 1280;             // five gate workgroups per CU
   int hql_grid = 0;               // 0: hql_slots(p)
   int est_variant = -1;           // -1: tuned or default
   int group_split = 1;            // batched mode: a group's frames in this many sub-groups
@@ -1416,8 +1416,8 @@ skm_status skm_autotune(skm_ctx* c, skm_frame_desc* frames, int32_t n, int32_t r
   if (s != SKM_OK) return s;
   int variants[4];
   const int nv = est_variants(p0, variants);
-  const int grids_b[4] = {512, 768, 1536, 3072};
-  const int grids_s[3] = {512, 768, 1536};
+  const int grids_b[4] = {640, 1280, 2560, 3840};
+  const int grids_s[3] = {640, 1280, 2560};
   const int streams[4] = {1, 2, 4, 8};
   const int splits[3] = {1, 2, 4};
   struct Cfg { int mode, streams, graphs, gate, variant, split; };

@@ -249,14 +249,14 @@ def test_autotune_keeps_results(ctx):
     assert best > 0.0
     assert ctx.get_option(skm.OPT_BATCH_STREAMS) in (1, 2, 4, 8)
     assert ctx.get_option(skm.OPT_GRAPHS) in (0, 1)
-    assert ctx.get_option(skm.OPT_GATE_GRID) in (512, 768, 1536)
+    assert ctx.get_option(skm.OPT_GATE_GRID) in (640, 1280, 2560)
     for out, info, xh in outs:
         assert np.array_equal(out.cpu().numpy(), ref[0])
     got = run_single(ctx, f, m, prm)
     assert np.array_equal(got[0], ref[0]) and got[1].tobytes() == ref[1].tobytes()
     ctx.set_option(skm.OPT_BATCH_STREAMS, 4)
     ctx.set_option(skm.OPT_GRAPHS, 1)
-    ctx.set_option(skm.OPT_GATE_GRID, 768)
+    ctx.set_option(skm.OPT_GATE_GRID, 1280)
 
 
 def test_batch_patch_geometry_matches_single_frames(ctx):

@@ -225,4 +225,4 @@ def test_autotune_cache_roundtrip(ctx):
     ctx.set_option(skm.OPT_BATCH_STREAMS, 4)
     ctx.set_option(skm.OPT_GROUP_SPLIT, 1)
     ctx.set_option(skm.OPT_GRAPHS, 1)
-    ctx.set_option(skm.OPT_GATE_GRID, 768)
+    ctx.set_option(skm.OPT_GATE_GRID, 1280)
