@@ -355,10 +355,6 @@ static __device__ __forceinline__ void est_block(const FrameArgs& a, const DevPa
   const int B2 = B * B;
   const int by = cell / p.gw, bx = cell - by * p.gw;
   const int x0 = bx * B, y0 = by * B;
-  // the window loads go out first; they land while the decisions below run
-  const StageGeom SG = stage_geom(p, x0 - r - W);
-  StageRegs SR;
-  if (!dist_only) stage_issue(a, p, SG, y0 - r - W, SR);
   if (!dist_only && nq == 0 && maxm0 == 0) {
     if (tid == 0) {
       atomicOr(&st->err, kErrNoContext);
@@ -392,11 +388,15 @@ static __device__ __forceinline__ void est_block(const FrameArgs& a, const DevPa
   }
 
   // 2. stage the search window in LDS; context ring (packed pairs); row
-  //    B-runs
+  //    B-runs.  The window loads go out only now, so that blocks deferred or
+  //    concealed by BRL above read no window; they land while the tables
+  //    are built.
+  const StageGeom SG = stage_geom(p, x0 - r - W);
+  StageRegs SR;
+  stage_issue(a, p, SG, y0 - r - W, SR);
   const EstLds E = carve_est_lds(lds_raw, p);
   phase_tables(p, E.m, sh);
   const int NU = sh.NU;
-  if (dist_only) stage_issue(a, p, SG, y0 - r - W, SR);
   stage_finish(a, p, E.m, SG, y0 - r - W, SR);
   // context units: the ring, then the block's own pixel pairs if it holds
   // received pixels.  Every ring pixel known and no own units: the distance
