@@ -806,29 +806,33 @@ static __device__ __forceinline__ void cand_distance_fixed(const MainLds& L, int
                                                            int& n_out) {
   int d = 0, nbad = 0;
   const uint32_t* wb = L.winp + base;
-  // two 16-unit steps in flight: the reads of step k + 1 are issued before
-  // the arithmetic of step k; scheduling barriers keep the compiler from
-  // hoisting further reads (registers)
+  // The context pairs are the same for every lane: lane t holds those of
+  // units t, t + 64, ... in registers and v_readlane hands each to the
+  // whole wave, so that the only LDS read per unit is the lane's own window
+  // pair.  Two 16-unit steps in flight: the window reads of step k + 1 are
+  // issued before the arithmetic of step k; scheduling barriers keep the
+  // compiler from hoisting further reads (registers)
   constexpr int kSteps = G::NU / 16;
-  uint32_t qv[2][16], pv[2][16];
+  constexpr int kQ = (G::NU + 63) / 64;
+  const int lane = lane_id();
+  uint32_t qreg[kQ];
 #pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    qv[0][t] = L.qu[t].x;
-    pv[0][t] = wb[G::kUnits.off[t]];
-  }
+  for (int c = 0; c < kQ; ++c) qreg[c] = 64 * c + lane < G::NU ? L.qu[64 * c + lane].x : 0u;
+  uint32_t pv[2][16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) pv[0][t] = wb[G::kUnits.off[t]];
 #pragma unroll
   for (int k = 0; k < kSteps; ++k) {
     if (k + 1 < kSteps) {
 #pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        qv[(k + 1) & 1][t] = L.qu[16 * (k + 1) + t].x;
-        pv[(k + 1) & 1][t] = wb[G::kUnits.off[16 * (k + 1) + t]];
-      }
+      for (int t = 0; t < 16; ++t) pv[(k + 1) & 1][t] = wb[G::kUnits.off[16 * (k + 1) + t]];
     }
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
-      if (QKnown) pair_dist5(qv[k & 1][t], pv[k & 1][t], d, nbad);
-      else pair_dist6(qv[k & 1][t], pv[k & 1][t], d, nbad);
+      const int u = 16 * k + t;
+      const uint32_t q = (uint32_t)__builtin_amdgcn_readlane((int)qreg[u / 64], u % 64);
+      if (QKnown) pair_dist5(q, pv[k & 1][t], d, nbad);
+      else pair_dist6(q, pv[k & 1][t], d, nbad);
     }
     // pin the sums here: otherwise the (pure) dot products sink past the
     // loop and every masked difference stays live until the end
