@@ -323,3 +323,30 @@ def test_headline_config_sampled_oracle_parity(ctx):
     print("headline sample: layers", layers, "skipped", skipped, flush=True)
     assert sum(layers.values()) >= 64
     assert layers.get(skm.LAYER_BRL, 0) > 0 and layers.get(skm.LAYER_IDL, 0) > 0
+
+
+def test_gate_grid_does_not_change_results(ctx):
+    """The gate's workgroups split the lost blocks into contiguous runs per
+    XCD; every grid (a workgroup per XCD, fewer workgroups than blocks, more
+    than the resident count) gives the same layers, records and pixels."""
+    import paper_2205_11226_amd as skm
+    weights = os.path.join(os.path.dirname(__file__), "..", "paper_2205_11226_amd", "weights",
+                           "gate_1080p.skm")
+    ctx.cnn_load(weights)
+    f = synth.make_luma(360, 640, 61, n_bumps=20, n_edges=8, texture=True)
+    m = synth.loss_random(360, 640, 16, 0.3, 62)
+    p = device_params("cnn")
+    ref = None
+    try:
+        for grid in (8, 640, 1280, 4096):
+            ctx.set_option(skm.OPT_GATE_GRID, grid)
+            out, info, xh = ctx.conceal_device(to_dev(f), to_dev(m), p)
+            got = (out.cpu().numpy(), info.tobytes(), xh.cpu().numpy())
+            if ref is None:
+                ref = got
+                continue
+            assert np.array_equal(got[0], ref[0]), grid
+            assert got[1] == ref[1], grid
+            assert np.array_equal(got[2], ref[2]), grid
+    finally:
+        ctx.set_option(skm.OPT_GATE_GRID, 1280)
