@@ -62,8 +62,10 @@ typedef enum skm_status {
 enum {
   SKM_MODE_PROFILE = 0, /* paper's layered scheme: BRL / IDL with support-area
                            expansion / HQL chosen by (t_phi, t_nu)            */
-  SKM_MODE_CNN = 1,     /* layer chosen by the learned gate; profile rule when
-                           no network is loaded                               */
+  SKM_MODE_CNN = 1,     /* BRL where the known context is flat (phi <= t_phi,
+                           the profile rule's test), elsewhere the layer
+                           chosen by the learned gate; profile rule when no
+                           network is loaded                                  */
   SKM_MODE_BRL = 2,     /* context mean for every block (eq. mean)            */
   SKM_MODE_IDL = 3,     /* IDL with expansion, never HQL                      */
   SKM_MODE_FULL = 4,    /* full K-MMSE (HQL) where >= min_hql_cands complete

@@ -523,6 +523,10 @@ def estimate_block(u, avail, by, bx, p: Params, cnn_gate=None):
         return brl, info
     cnn_choice = None
     if mode == "cnn":
+        # the profile rule's flatness test first (it needs only the ring):
+        # a flat ring takes BRL without asking the network
+        if phi <= p.t_phi:
+            return brl, info
         # learned gate: BRL, IDL with the support-area expansion (never
         # escalating), or HQL (full-window IDL when HQL is not available)
         if cnn_gate is None:

@@ -656,26 +656,36 @@ struct GateWindow {
   }
 };
 
-// the statistics and the layer choice of block i (thread 0)
+// the statistics and the layer choice of block i (thread 0); a flat ring
+// takes BRL without predictions
 static __device__ __forceinline__ void gate_record(const FrameArgs& a, const DevParams& p, int i,
-                                                   int c, int sum, int vmin, int vmax, float y0,
-                                                   float y1, float tau1, float tau2, int& nq,
-                                                   int& mx) {
+                                                   int c, int sum, int vmin, int vmax, bool flat,
+                                                   float y0, float y1, float tau1, float tau2,
+                                                   int& nq, int& mx) {
   const int nown = c >> 16;
   c &= 0xffff;
   a.m0cnt[i] = c | (nown > 0 ? kPartialBit : 0);
   a.ring[i] = make_int2(sum, vmin | (vmax << 16));
   nq += c >= p.r * p.B;
   mx = max(mx, c);
-  a.gate[i] = (int8_t)(y0 <= tau1 ? SKM_LAYER_BRL : (y1 > tau2 ? SKM_LAYER_HQL : SKM_LAYER_IDL));
+  a.gate[i] = (int8_t)(flat || y0 <= tau1 ? SKM_LAYER_BRL
+                                          : (y1 > tau2 ? SKM_LAYER_HQL : SKM_LAYER_IDL));
   if (a.gate_pred) { a.gate_pred[2 * i] = y0; a.gate_pred[2 * i + 1] = y1; }
+}
+
+// The profile rule's flatness test on the staged ring statistics (phi =
+// max - min of the known context pixels, 0 without any): a flat ring takes
+// BRL, and the network is not run for it.
+static __device__ __forceinline__ bool gate_flat(const DevParams& p, int c, int vmin, int vmax) {
+  return (double)((c & 0xffff) > 0 ? vmax - vmin : 0) <= p.t_phi;
 }
 
 // In-pipeline gate, which also does the round preparation in CNN mode: one
 // pass over the pending blocks of the round.  For each it records the
 // known in-frame ring pixels (count, sum, minimum, maximum) from the window
-// it has loaded anyway, evaluates the network and writes the layer choice to
-// gate[i] (the predictions to gate_pred).  Each workgroup adds its (blocks
+// it has loaded anyway; a flat ring (phi <= t_phi) takes BRL as in the
+// profile rule, any other block the network's choice, written to gate[i]
+// (the predictions to gate_pred, NaN for flat rings).  Each workgroup adds its (blocks
 // with |m0| >= r B, largest |m0|) to the round's context rule, as the prep
 // kernel does.
 __global__ __launch_bounds__(kGateThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_cnn_gate(FrameArgs a, DevParams p,
@@ -710,9 +720,16 @@ __global__ __launch_bounds__(kGateThreads) __attribute__((amdgpu_waves_per_eu(3)
     win.load(a, p, cell);
     int c, sum, vmin, vmax;
     win.stage(G, p, c, sum, vmin, vmax);
+    if (gate_flat(p, c, vmin, vmax)) {    // uniform in the workgroup
+      if (threadIdx.x == 0)
+        gate_record(a, p, i, c, sum, vmin, vmax, true, NAN, NAN, tau1, tau2, wg_nq, wg_max);
+      __syncthreads();                    // both waves have read G.red
+      continue;
+    }
     float y0, y1;
     gate_network(G, W, y0, y1);
-    if (threadIdx.x == 0) gate_record(a, p, i, c, sum, vmin, vmax, y0, y1, tau1, tau2, wg_nq, wg_max);
+    if (threadIdx.x == 0)
+      gate_record(a, p, i, c, sum, vmin, vmax, false, y0, y1, tau1, tau2, wg_nq, wg_max);
   }
   if (threadIdx.x == 0) note_context_rule(st, wg_nq, wg_max);
 }
@@ -756,10 +773,16 @@ __global__ __launch_bounds__(kGateThreads) __attribute__((amdgpu_waves_per_eu(3)
     win.load(ac, p, ac.blk[i]);
     int c, sum, vmin, vmax;
     win.stage(G, p, c, sum, vmin, vmax);
+    if (gate_flat(p, c, vmin, vmax)) {    // uniform in the workgroup
+      if (threadIdx.x == 0)
+        gate_record(ac, p, i, c, sum, vmin, vmax, true, NAN, NAN, tau1, tau2, wg_nq, wg_max);
+      __syncthreads();                    // both waves have read G.red
+      continue;
+    }
     float y0, y1;
     gate_network(G, W, y0, y1);
     if (threadIdx.x == 0)
-      gate_record(ac, p, i, c, sum, vmin, vmax, y0, y1, tau1, tau2, wg_nq, wg_max);
+      gate_record(ac, p, i, c, sum, vmin, vmax, false, y0, y1, tau1, tau2, wg_nq, wg_max);
   }
   if (threadIdx.x == 0) note_context_rule(ac.st, wg_nq, wg_max);
 }

@@ -64,8 +64,10 @@ def block_labels(ctx, frame, mask, b=16, t_nu=0.1):
     hql = info["layer"] == 2
     g1 = ps(sse["plain"]) - ps(sse["brl"])
     g2 = np.where(hql, ps(sse["full"]) - ps(sse["plain"]), 0.0)
+    # blocks that CNN mode sends to BRL by the flatness test, before the gate
+    flat = info["phi"] <= skm.default_params(mode="cnn", block=b).t_phi
     return {"g": np.stack([g1, g2], 1).astype(np.float32), "sse": sse, "hql": hql,
-            "npx": frame.size}
+            "flat": flat, "npx": frame.size}
 
 
 KINDS = ("lattice", "isolated", "smooth")
@@ -158,7 +160,7 @@ def fit_thresholds(pred, recs, max_dpsnr=0.05, margin=0.01):
             dps, cost = [], 0.0
             for (a, b), r, fp in zip(spans, recs, full_ps):
                 p = pred[a:b]
-                brl = p[:, 0] <= t1
+                brl = (p[:, 0] <= t1) | r["flat"]
                 hql = ~brl & (p[:, 1] > t2) & r["hql"]
                 idl = ~brl & ~hql
                 sse = (r["sse"]["brl"] * brl + r["sse"]["full"] * hql + r["sse"]["idl"] * idl).sum()

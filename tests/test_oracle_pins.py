@@ -539,3 +539,41 @@ def test_patch_mode_partial_cells_vectorised_oracle_equals_loop_oracle(seed, mod
         assert i["layer"] == blay[k]
         tol = 1e-5 if i["layer"] == LAYER_HQL else 1e-9
         np.testing.assert_allclose(xh[k].ravel(), np.array(bxh[k]), rtol=0, atol=tol)
+
+
+def test_cnn_mode_takes_the_flatness_test_before_the_gate():
+    """CNN mode: a block whose known context is flat (phi = max - min <=
+    T_phi, the profile rule's BRL test) takes BRL, the context mean, and the
+    gate is never asked; every other block gets exactly the gate's layer.
+    A gate that always answers IDL pins the order: with it, flat blocks must
+    still be BRL and no non-flat block may be BRL."""
+    f = tiny_frame(71, 48, 48)
+    f[:16, :16] = 120                          # a flat corner region
+    f[2:6, 2:6] = 128                          # phi = 8 around the corner cell
+    m = cells_mask(48, 48, 8, [(0, 0), (1, 4), (4, 1), (4, 4)])
+    u = np.where(m == 0, f, 0).astype(np.int64)
+    avail = m == 0
+    p = Params(mode="cnn", t_phi=20.0, **SMALL)
+    asked = []
+
+    def gate_idl(uu, aa, by, bx):
+        asked.append((by, bx))
+        return LAYER_IDL
+
+    flat_seen = 0
+    for by, bx in lost_cells(m, 8):
+        y0, m0 = block_context(u, avail, by, bx, p)
+        known = y0[m0]
+        phi = int(known.max() - known.min()) if m0.any() else 0
+        n_asked = len(asked)
+        xh, info = estimate_block(u, avail, by, bx, p, gate_idl)
+        assert info["phi"] == phi
+        if phi <= p.t_phi:
+            flat_seen += 1
+            assert len(asked) == n_asked, (by, bx)
+            assert info["layer"] == LAYER_BRL
+            assert np.array_equal(xh, np.full(64, known.mean()))
+        else:
+            assert asked[-1] == (by, bx)
+            assert info["layer"] == LAYER_IDL
+    assert flat_seen >= 1 and len(asked) >= 1
