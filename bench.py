@@ -217,6 +217,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-run", action="store_true",
                     help="only conceal --steps frames and copy a known size (counter runs)")
+    ap.add_argument("--kernel-run", action="store_true",
+                    help="only single-frame calls of the 1080p frame for kernel traces and "
+                         "counters: plain and CNN mode, the gate at several grids, the gate "
+                         "network alone, the distance table")
     ap.add_argument("--geometry", choices=("block", "patch"), default="block",
                     help="patch: the paper's 2x2 patches with a 6x6 context on the same frame "
                          "(a line of its own; the default line is the block workload)")
@@ -242,6 +246,8 @@ def main():
     frame, mask = synth.workload_layered_1080p()
     if args.traffic_run:
         return traffic_run(args, frame, mask)
+    if args.kernel_run:
+        return kernel_run(args, frame, mask)
     if args.geometry == "patch":
         return bench_patch(args, frame, mask)
 
@@ -680,6 +686,42 @@ def traffic_run(args, frame, mask):
     ctx.close()
     print(f"# traffic run: one batch of {args.steps} frames, 3 copies of {COPY_BYTES} bytes",
           flush=True)
+
+
+def kernel_run(args, frame, mask):
+    """Single-frame calls in a fixed order, for `rocprofv3 --kernel-trace` or
+    `--pmc` (one dispatch list per phase): 20 plain frames, 20 CNN frames at
+    the default gate grid, 10 CNN frames at each of the gate grids 768, 1280,
+    2560 and 4096, 10 runs of the gate network alone on the frame's lost
+    blocks, 5 distance tables."""
+    import torch
+    import paper_2205_11226_amd as skm
+    fd = torch.from_numpy(frame).cuda()
+    md = torch.from_numpy(mask).cuda()
+    ctx = skm.Context(0)
+    ctx.cnn_load(args.weights)
+    for mode in ("plain", "cnn"):
+        p = skm.default_params(mode=mode)
+        for _ in range(20):
+            ctx.conceal_device(fd, md, p, want_info=False, want_xhat=False)
+        torch.cuda.synchronize()
+    p = skm.default_params(mode="cnn")
+    default_grid = ctx.get_option(skm.OPT_GATE_GRID)
+    for grid in (768, 1280, 2560, 4096):
+        ctx.set_option(skm.OPT_GATE_GRID, grid)
+        for _ in range(10):
+            ctx.conceal_device(fd, md, p, want_info=False, want_xhat=False)
+        torch.cuda.synchronize()
+    ctx.set_option(skm.OPT_GATE_GRID, default_grid)
+    x = ctx.cnn_inputs(fd, md, skm.default_params(mode="profile"))
+    for _ in range(10):
+        ctx.cnn_forward(x)
+    pp = skm.default_params(mode="plain")
+    for _ in range(5):
+        ctx.distances_device(fd, md, pp)
+    torch.cuda.synchronize()
+    ctx.close()
+    print(f"# kernel run: {x.shape[0]} lost blocks", flush=True)
 
 
 def _counter_rows(d):
