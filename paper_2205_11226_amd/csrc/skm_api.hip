@@ -236,6 +236,7 @@ skm_status make_params(const skm_params* in, int width, int height, int stride, 
   memset(p, 0, sizeof(*p));
   p->B = in->block; p->r = in->ring; p->W = in->window;
   p->Wd = p->B + 2 * p->r + 2 * p->W;
+  p->Wp = p->Wd | 1;
   p->F = p->B + 2 * p->r;
   p->ND = (2 * p->W + 1) * (2 * p->W + 1);
   p->NR = p->F * p->F - p->B * p->B;

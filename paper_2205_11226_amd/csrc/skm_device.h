@@ -221,7 +221,7 @@ __host__ __device__ inline size_t main_lds_layout(const DevParams& p, size_t* of
   offs[6] = o; o = align_up(o + sizeof(uint64_t) * 2 * p.Wd, 16);
   offs[7] = o; o = align_up(o + sizeof(uint64_t) * 2 * p.Wd, 16);
   offs[8] = o; o = align_up(o + sizeof(uint64_t) * 2 * (2 * p.W + 1), 16);
-  offs[9] = o; o = align_up(o + sizeof(uint32_t) * p.Wd * p.Wd, 16);
+  offs[9] = o; o = align_up(o + sizeof(uint32_t) * p.Wd * p.Wp, 16);
   return o;
 }
 
@@ -276,7 +276,7 @@ struct EstLds {
 
 __host__ __device__ inline size_t est_lds_layout(const DevParams& p, size_t* offs) {
   size_t o = 0;
-  offs[0] = o; o = align_up(o + sizeof(uint32_t) * p.Wd * p.Wd, 16);
+  offs[0] = o; o = align_up(o + sizeof(uint32_t) * p.Wd * p.Wp, 16);
   offs[1] = o; o = align_up(o + sizeof(uint2) * (p.NR + p.B * p.B / 2 + 32), 16);
   offs[2] = o; o = align_up(o + sizeof(uint32_t) * p.NR, 16);
   const size_t qu_utab = o - offs[1];
@@ -390,12 +390,12 @@ static __device__ __forceinline__ void phase_tables(const DevParams& p, const Ma
     if (fy < F) {
       if (full) {
         for (int c = 0; c < F; c += 2)
-          L.utab[pos++] = (uint32_t)(fy * Wd + c) | ((uint32_t)(c + 1 >= F) << 16);
+          L.utab[pos++] = (uint32_t)(fy * p.Wp + c) | ((uint32_t)(c + 1 >= F) << 16);
       } else {
         for (int c = 0; c < r; c += 2)
-          L.utab[pos++] = (uint32_t)(fy * Wd + c) | ((uint32_t)(c + 1 >= r) << 16);
+          L.utab[pos++] = (uint32_t)(fy * p.Wp + c) | ((uint32_t)(c + 1 >= r) << 16);
         for (int c = r + B; c < F; c += 2)
-          L.utab[pos++] = (uint32_t)(fy * Wd + c) | ((uint32_t)(c + 1 >= F) << 16);
+          L.utab[pos++] = (uint32_t)(fy * p.Wp + c) | ((uint32_t)(c + 1 >= F) << 16);
       }
     }
     if (lane == 63) sh.NU = x;
@@ -489,8 +489,8 @@ static __device__ __forceinline__ void stage_store(const DevParams& p, const Mai
     for (int q = 0; q < 4; ++q) nib |= (uint32_t)((pr[q] & 0x8000u) == 0u) << q;
     if (nib)
       atomicOr(reinterpret_cast<uint32_t*>(L.rowbits) + 4 * wy + (G.c0 >> 5), nib << (G.c0 & 31));
-    uint32_t* dst = L.winp + wy * Wd + G.c0;
-    if ((Wd & 3) == 0) {
+    uint32_t* dst = L.winp + wy * p.Wp + G.c0;
+    if ((Wd & 3) == 0 && (p.Wp & 3) == 0) {
       *reinterpret_cast<uint4*>(dst) = make_uint4(pr[0], pr[1], pr[2], pr[3]);
     } else {
 #pragma unroll
@@ -540,7 +540,7 @@ struct RingStats { int n0, phi, sum; };
 static __device__ __forceinline__ RingStats phase_context(const DevParams& p, const MainLds& L,
                                                           BlockShared& sh, int NU, int NUe) {
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
-  const int qbase = p.W * p.Wd + p.W;
+  const int qbase = p.W * p.Wp + p.W;
   {
     int c = 0, vmin = 255, vmax = 0, vsum = 0;
     for (int u = tid; u < NUe; u += kThreads) {
@@ -553,7 +553,7 @@ static __device__ __forceinline__ RingStats phase_context(const DevParams& p, co
         if (e >> 16) qp |= 0xffff0000u;
       } else {
         const int k2 = 2 * (u - NU), iy = k2 / p.B, ix = k2 - iy * p.B;
-        off = (p.r + iy) * p.Wd + p.r + ix;
+        off = (p.r + iy) * p.Wp + p.r + ix;
         qp = L.winp[qbase + off];
       }
       L.qu[u] = make_uint2(qp, (uint32_t)off);
@@ -598,7 +598,7 @@ static __device__ __forceinline__ RingStats phase_context(const DevParams& p, co
 static __device__ __forceinline__ int phase_candidates(const DevParams& p, const MainLds& L,
                                                        BlockShared& sh) {
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
-  const int B = p.B, r = p.r, W = p.W, Wd = p.Wd, D2 = 2 * W + 1, nw = kThreads / 64;
+  const int B = p.B, r = p.r, W = p.W, Wp = p.Wp, D2 = 2 * W + 1, nw = kThreads / 64;
   int rowcnt = 0;
   uint64_t mlo = 0ull, mhi = 0ull;
   if (tid < D2) {
@@ -657,7 +657,7 @@ static __device__ __forceinline__ int phase_candidates(const DevParams& p, const
         bits &= bits - 1u;
         const int rho = max(ady, abs(dxi - W));
         const uint32_t bk = (uint32_t)((rho < 16 ? lut0 : lut1) >> (4 * (rho & 15))) & 15u;
-        L.cand[pos++] = (uint32_t)(dyi * Wd + dxi) | (bk << 14);
+        L.cand[pos++] = (uint32_t)(dyi * Wp + dxi) | (bk << 14);
       }
     }
   } else {
@@ -687,7 +687,7 @@ static __device__ __forceinline__ int phase_candidates(const DevParams& p, const
             const int rho = max(ady, abs(dxi - W));
             const unsigned long long lw = rho < 16 ? lut0 : (rho < 32 ? lut1 : lut2);
             const uint32_t bk = (uint32_t)(lw >> (4 * (rho & 15))) & 15u;
-            L.cand[rbv[u] + rank] = (uint32_t)(dyi * Wd + dxi) | (bk << 14);
+            L.cand[rbv[u] + rank] = (uint32_t)(dyi * Wp + dxi) | (bk << 14);
           }
         }
       }
@@ -780,6 +780,7 @@ struct FixedGeom {
   static constexpr int kB = B, kR = R, kW = W;
   static constexpr int F = B + 2 * R;
   static constexpr int Wd = B + 2 * R + 2 * W;
+  static constexpr int Wp = Wd | 1;   // LDS row pitch, as DevParams::Wp
   static constexpr int NU = 2 * R * ((F + 1) / 2) + B * 2 * ((R + 1) / 2);
   static_assert(F % 2 == 0 && R % 2 == 0, "units must be whole pixel pairs");
   static_assert(NU % 32 == 0, "unit count must fill the 16-unit steps without padding");
@@ -790,7 +791,7 @@ struct FixedGeom {
     for (int fy = 0; fy < F; ++fy) {
       const bool full = fy < R || fy >= R + B;
       for (int c = 0; c < F; c += 2)
-        if (full || c < R || c >= R + B) t.off[u++] = fy * Wd + c;
+        if (full || c < R || c >= R + B) t.off[u++] = fy * Wp + c;
     }
     return t;
   }

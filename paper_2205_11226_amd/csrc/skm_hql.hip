@@ -113,7 +113,7 @@ size_t hql_lds_bytes(const DevParams& p) {
   size_t offs[10];
   main_lds_layout(p, offs);
   const HqlLayout h = hql_layout(p);
-  size_t need = (size_t)4 * p.Wd * p.Wd;
+  size_t need = (size_t)4 * p.Wd * p.Wp;
   need = need > kGemmLds ? need : kGemmLds;
   need = need > kCholLds ? need : kCholLds;
   need = need > kGramLds ? need : kGramLds;
@@ -794,9 +794,9 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
                                                  BlockShared& sh, HqlShared& hs, int* pend) {
   const MainLds L = carve_main_lds(lds_raw, p);
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
-  const int B = p.B, r = p.r, W = p.W, Wd = p.Wd;
+  const int B = p.B, r = p.r, W = p.W, Wd = p.Wd, Wp = p.Wp;
   const int B2 = B * B;
-  const int qbase = W * Wd + W;
+  const int qbase = W * Wp + W;
   const int NU = sh.NU;
 
   const HqlLayout hl = hql_layout(p);
@@ -927,7 +927,7 @@ static __device__ __forceinline__ void hql_block(const FrameArgs& a, const DevPa
       }
     }
     for (int q = wave; q < B2; q += kThreads / 64) {
-      const int off = (r + q / B) * Wd + r + (q % B);
+      const int off = (r + q / B) * Wp + r + (q % B);
       for (int k = lane; k < ldm; k += 64)
         xt[(size_t)q * ldm + k] = k < Mc ? (uint8_t)(L.winp[compo[k] + off] & 0xffu) : (uint8_t)0;
     }

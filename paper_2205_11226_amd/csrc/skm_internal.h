@@ -32,6 +32,8 @@ constexpr int kErrHqlPending = 4;    // a block needs HQL and no HQL pass ran
 struct DevParams {
   int B, r, W;
   int Wd;          // window side B + 2r + 2W
+  int Wp;          // LDS row pitch of the window, Wd | 1: with an odd pitch the
+                   // candidates of one window column fall into distinct banks
   int F;           // footprint side B + 2r
   int ND;          // (2W+1)^2 displacements
   int NR;          // ring pixels F^2 - B^2

@@ -351,7 +351,7 @@ static __device__ __forceinline__ void est_block(const FrameArgs& a, const DevPa
   const int nq = st->ctx_nq, maxm0 = st->ctx_max;
   if (bst != 0) return;
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
-  const int B = p.B, r = p.r, W = p.W, Wd = p.Wd, D2 = 2 * W + 1;
+  const int B = p.B, r = p.r, W = p.W, Wp = p.Wp, D2 = 2 * W + 1;
   const int B2 = B * B;
   const int by = cell / p.gw, bx = cell - by * p.gw;
   const int x0 = bx * B, y0 = by * B;
@@ -434,7 +434,7 @@ static __device__ __forceinline__ void est_block(const FrameArgs& a, const DevPa
       nc += ok;
       ncomp += ok && n == n0;
       if (dist_only) {
-        const int t = (base / Wd) * D2 + (base % Wd);
+        const int t = (base / Wp) * D2 + (base % Wp);
         a.dist[(size_t)i * p.ND + t] = ok ? d : -1;
         a.cnt[(size_t)i * p.ND + t] = ok ? n : 0;
         continue;
@@ -679,7 +679,7 @@ static __device__ __forceinline__ void est_block(const FrameArgs& a, const DevPa
     const int GG = kThreads / NP;           // candidate groups, at least 2
     const int h = tid / NP, q = tid - h * NP;
     const int py = (2 * q) / B, px = 2 * q - py * B;
-    const uint32_t* wq = E.winp + (r + py) * Wd + (r + px);
+    const uint32_t* wq = E.winp + (r + py) * Wp + (r + px);
     float acc0 = 0.f, acc1 = 0.f, comp0 = 0.f, comp1 = 0.f;
     for (int j0 = 8 * h; j0 < nsel; j0 += 8 * GG) {
       uint2 sv[8];
@@ -715,7 +715,7 @@ static __device__ __forceinline__ void est_block(const FrameArgs& a, const DevPa
       const double x0h = t0 * sh.xs, x1h = t1 * sh.xs;
       uint8_t* o = a.work + (size_t)(y0 + py) * p.stride + x0 + px;
       // the block's own pair in the window: received pixels are kept
-      const uint32_t own = partial ? wq[W * Wd + W] : 0xffffffffu;
+      const uint32_t own = partial ? wq[W * Wp + W] : 0xffffffffu;
       if ((int16_t)(own & 0xffffu) < 0) o[0] = (uint8_t)fmin(fmax(floor(x0h + 0.5), 0.0), 255.0);
       if ((int16_t)(own >> 16) < 0) o[1] = (uint8_t)fmin(fmax(floor(x1h + 0.5), 0.0), 255.0);
       if (a.xhat && i < a.cap) {
