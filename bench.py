@@ -341,7 +341,8 @@ def main():
     o_lay, info_lay, _ = ctx.conceal_device(fd, md, p_lay, want_xhat=False)
     o_prof, info_prof, _ = ctx.conceal_device(fd, md, p_prof, want_xhat=False)
     o_plain, _, _ = ctx.conceal_device(fd, md, p_plain, want_xhat=False)
-    o_full, _, _ = ctx.conceal_device(fd, md, skm.default_params(mode="full"), want_xhat=False)
+    o_full, info_full, _ = ctx.conceal_device(fd, md, skm.default_params(mode="full"),
+                                              want_xhat=False)
     d_tab, n_tab = ctx.distances_device(fd, md, p_plain)
     d_tab, n_tab = d_tab.cpu().numpy(), n_tab.cpu().numpy()
     n_lost = len(info_lay)
@@ -382,6 +383,9 @@ def main():
             "psnr_layered_db": ps_lay,
             "psnr_full_kmmse_db": ps_full,
             "delta_psnr_db": ps_full - ps_lay,
+            # layers of the reference itself: on this lattice no block has an
+            # HQL candidate set, so full K-MMSE conceals every block by IDL
+            "full_kmmse_layers": layer_counts(info_full),
             "layers": layer_counts(info_lay),
             "plain": {"blocks_per_s": n_lost / sec_plain, "ms_per_frame": sec_plain * 1e3,
                       "delta_psnr_db": ps_full - ps_plain},
