@@ -190,8 +190,9 @@ static __device__ __forceinline__ void note_context_rule(RoundState* st, int nq,
 //   runbits u64 [Wd][2]   bit c set iff columns c .. c+B-1 are all available
 //   cmask   u64 [D2][2]   bit dx of displacement row dy set iff the B x B
 //                         prototype at (dy, dx) is admissible
-//   winp    u32 [Wd*Wd]   window pixel pairs: int16 pixel | next pixel << 16,
-//                         -1 = unknown (lost or out of frame)
+//   winp    u32 [Wd*Wp]   window pixel pairs: int16 pixel | next pixel << 16,
+//                         -1 = unknown (lost or out of frame); Wd rows of
+//                         pitch Wp (odd), the padding column never read
 
 struct MainLds {
   double* ell;
@@ -251,7 +252,7 @@ static __device__ __forceinline__ int cand_n(uint32_t c) { return (int)(c >> 18)
 
 // Estimation-kernel LDS (one block per workgroup), smaller than MainLds so
 // that four workgroups fit a CU at the default geometry:
-//   winp    u32 [Wd*Wd]   as in MainLds
+//   winp    u32 [Wd*Wp]   as in MainLds
 //   qu      u32x2 [NR+B*B/2+32] as in MainLds
 //   utab    u32 [NR]      as in MainLds
 //   cand    u32 [MC+16]   candidate words; n added by the distance step
